@@ -1,0 +1,198 @@
+"""Benchmark of the RBSOG per-step force path on one MI355X.
+
+Workload: the 300,000-ion +-1 electrolyte at number density 0.1 (random
+sequential addition, d_min = 1), r_c = 3.5 with Table 1 row 2 scaled to the
+cutoff, P = 200 wave vectors per step, velocity-Verlet dt = 1e-3 from a
+Maxwellian at T = 1.  A step is one whole pass of the path: kick, drift,
+wrap/quantise, cell list, near part, k staging, structure factor, far force,
+energies, kick.
+
+Prints one JSON line: particle-steps/s of the FP32C form (``value``) and of
+the FP64 form, the FP32C force error against FP64, the roofline of the
+dominant kernel measured with HIP events on the library's stream, and the
+CPU oracle timed on the host on one force evaluation.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s, RBSOG forces FP32-comp vs FP64, at <=1e-5 rel RMS force err"
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz = VALU lane-op slots per second
+PEAK_VALU_SLOTS = 256 * 4 * 16 * 2.4e9
+# issue slots of one FP32 transcendental (sin, cos, exp, rsqrt) on the VALU
+TRANS_SLOTS = 4
+# algorithmic VALU slots per unit of work (the method's arithmetic, not the
+# implementation's): see DESIGN.md, "Roofline".
+WORK = {
+    # per (particle, k): phase 3 + accumulate 2 FMA-class, sin + cos
+    "rho": 5 + 2 * TRANS_SLOTS,
+    # per (particle, k): phase 3 + Im 2 + accumulate 3 FMA-class, sin + cos
+    "far": 8 + 2 * TRANS_SLOTS,
+    # per neighbour pair inside r_c (full list, both orders): rsqrt, M+1 = 17 exp, ~40 FMA-class
+    "near": 40 + 18 * TRANS_SLOTS,
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--n", type=int, default=300_000, help=argparse.SUPPRESS)
+    return ap.parse_args()
+
+
+def run_precision(R, torch, wl, prec, args):
+    n = len(wl["q"])
+    P = wl["P"]
+    stream = torch.cuda.Stream()
+    sysm = R.System(wl["pos"], wl["q"], wl["box"], wl["rc"], P, seed=2022, precision=prec,
+                    stream=stream.cuda_stream)
+    batches = 1 + args.warmup + args.steps + args.profile_steps
+    t0 = time.time()
+    sysm.sample_k(batches)
+    log(f"[bench] prec={prec}: sampled {batches * P} wave vectors in {time.time() - t0:.2f} s")
+    F0, E0 = sysm.forces()
+    Fn0, Ff0 = sysm.components()
+    # neighbour pairs inside r_c at step 0 (full list, both orders), for the near roofline
+    row, _ = R.rbsog_debug_neighbors(sysm.ctx, n)
+    near_pairs = int(row[-1])
+    R.rbsog_set_velocities(sysm.ctx, None, T=1.0, seed=7)
+    sysm.step(args.warmup, 1e-3)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    sysm.step(args.steps, 1e-3)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = ev0.elapsed_time(ev1)
+    log(f"[bench] prec={prec}: {args.steps} steps in {ms:.2f} ms (wall {wall * 1e3:.2f} ms)")
+    kernels = {}
+    if args.profile_steps > 0:
+        R.rbsog_profile(sysm.ctx, True)
+        sysm.step(args.profile_steps, 1e-3)
+        prof = R.rbsog_profile_read(sysm.ctx)
+        R.rbsog_profile(sysm.ctx, False)
+        kernels = {k: {"ms_total": v[0], "launches": v[1], "us_per_launch": 1e3 * v[0] / max(v[1], 1)}
+                   for k, v in prof.items() if v[1] > 0}
+    E = R.rbsog_get_energy(sysm.ctx)
+    sysm.close()
+    return dict(ms=ms, wall=wall, F0=F0, Fn0=Fn0, Ff0=Ff0, E0=E0, E_end=E, kernels=kernels, near_pairs=near_pairs,
+                value=n * args.steps / (ms * 1e-3))
+
+
+def roofline(kernels, n, P, near_pairs):
+    units = {"rho": n * P, "far": n * P, "near": near_pairs}
+    cands = {k: v for k, v in kernels.items() if k in units}
+    if not cands:
+        return None
+    dom = max(cands, key=lambda k: cands[k]["us_per_launch"])
+    t = cands[dom]["us_per_launch"] * 1e-6
+    achieved = units[dom] * WORK[dom] / t
+    return {"kernel": dom, "bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_VALU_SLOTS / 1e9,
+            "unit": "Gop/s (VALU lane slots)", "frac": achieved / PEAK_VALU_SLOTS, "traffic": None,
+            "units_per_launch": units[dom], "slots_per_unit": WORK[dom], "us_per_launch": t * 1e6}
+
+
+def cpu_baseline(wl, budget_s=12.0):
+    import oracle
+
+    sog = oracle.sog_row2(wl["rc"])
+    pos, q, box, rc, P = wl["pos"], wl["q"], wl["box"], wl["rc"], wl["P"]
+    S = oracle.S_product(sog, box)
+    m = oracle.mh_sample(sog, box, seed=99, stream=0, n=P)[0]
+    evals = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.near_cells(pos, q, box, rc, sog)
+        oracle.far_rb(pos, q, box, sog, m, P, S)
+        evals += 1
+        if time.perf_counter() - t0 > budget_s or evals >= 20:
+            break
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": len(q) * evals / dt, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{evals} full force evaluation(s) (near part over the cell list + random-batch far part, "
+                      f"P={P}) of the same {len(q)}-ion system, FP64, OpenMP; the VV update is omitted",
+            "seconds": dt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the path would shard "
+              f"by spatial domains with one all-reduce of rho per step, which this build does not run).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2205_13824_amd import rbsog as R
+    from paper_2205_13824_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    t0 = time.time()
+    wl = W.c2_electrolyte(args.n)
+    n, P = len(wl["q"]), wl["P"]
+    log(f"[bench] workload built in {time.time() - t0:.1f} s: n={n} L={wl['box'][0]:.4f} P={P}")
+
+    r32 = run_precision(R, torch, wl, R.RBSOG_FP32C, args)
+    r64 = run_precision(R, torch, wl, R.RBSOG_FP64, args)
+    err = math.sqrt(float(np.sum((r32["F0"] - r64["F0"]) ** 2) / np.sum(r64["F0"] ** 2)))
+    err_near = math.sqrt(float(np.sum((r32["Fn0"] - r64["Fn0"]) ** 2) / np.sum(r64["Fn0"] ** 2)))
+    err_far = math.sqrt(float(np.sum((r32["Ff0"] - r64["Ff0"]) ** 2) / np.sum(r64["Ff0"] ** 2)))
+    log(f"[bench] FP32C vs FP64 force relrms: total {err:.3e} near {err_near:.3e} far {err_far:.3e}")
+
+    roof = roofline(r32["kernels"], n, P, r32["near_pairs"])
+    out = {
+        "metric": METRIC,
+        "value": r32["value"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{n}-ion +-1 electrolyte, density 0.1, RSA d_min=1, r_c=3.5, P={P}, "
+                               f"Table 1 row 2, velocity-Verlet dt=1e-3, T=1",
+                   "n": n, "P": P, "rc": wl["rc"], "box": float(wl["box"][0])},
+        "fp64": {"value": r64["value"], "ms_per_step": r64["ms"] / args.steps, "dtype": "f64"},
+        "fp32c_speedup_vs_fp64": r32["value"] / r64["value"],
+        "fp32c_force_relrms_vs_fp64": {"total": err, "near": err_near, "far": err_far},
+        "energy_step0": {"fp32c": list(map(float, r32["E0"])), "fp64": list(map(float, r64["E0"]))},
+        "roofline": roof,
+        "kernels_fp32c": r32["kernels"],
+        "kernels_fp64": r64["kernels"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,211 @@
+/*
+ * rbsog.h - C ABI of librbsog, an MI355X (gfx950) implementation of the
+ * per-step electrostatic force evaluation of the random batch
+ * sum-of-Gaussians (RBSOG) method (Liang, Xu, Zhou, arXiv 2205.13824).
+ *
+ * Problem (Sec. 2, eqs. "solutionperiodic", "energy"): N point charges q_i at
+ * r_i in a periodic cuboid L_x x L_y x L_z, sum q_i = 0, unit dielectric,
+ * tinfoil boundary.  The kernel 1/r is split (Sec. 2, eqs. "SOGDEcomp",
+ * "SOGField") into a near part N(r) = 1/r - F(r) for r < r_c and a far part
+ * F(r) = sum_{l=0}^{M} omega_l exp(-r^2/s_l^2), omega_l = sqrt(2/pi) ln b /
+ * (sigma b^l) (omega_0 scaled by w0), s_l = sqrt(2) b^l sigma.
+ *
+ * Per force evaluation the library computes
+ *   near force   F_N,i = sum_{j: r_ij < r_c} q_i q_j (1/r^3 - 2 sum_l omega_l/s_l^2
+ *                 e^{-r^2/s_l^2}) r_ij                  (Sec. 3.1, eq. "forcesplit";
+ *                 the printed 1/(2r^3) form is half of -grad U_N)
+ *   far force    F*_i = -q_i sum_{e=1}^{P} w_e k_e Im(e^{-i k_e.r_i} rho(k_e)),
+ *                 rho(k) = sum_j q_j e^{i k.r_j}, k = 2 pi (m_x/L_x, m_y/L_y, m_z/L_z),
+ *                 w_e = S pi^{3/2} / (P V)              (Sec. 3.3, eq. "approximateForce",
+ *                 with the leading minus sign of -grad U*)
+ *   energies     U_N = sum_{pairs, r<r_c} q_i q_j N(r); U* = 1/2 sum_e w_e |rho(k_e)|^2;
+ *                 U_self = 1/2 F(0) sum q_i^2; U = U_N + U* - U_self      (Sec. 3.1)
+ * The wave vectors m_e are a pre-sampled sequence (Algorithm 1, step 2), drawn
+ * by Metropolis-Hastings from P_k = F~(k)/(pi^{3/2} S) (Sec. 3.3) and consumed
+ * P at a time, in order, one batch per force evaluation.
+ *
+ * Conventions.
+ *   - All host arrays are caller-owned, read or written only during the call.
+ *     Positions/velocities/forces are row-major n x 3 (x, y, z per particle),
+ *     returned in the caller's particle order.
+ *   - Every call returns an rbsog_status; nothing throws or aborts across the
+ *     ABI.  After RBSOG_E_ARG, E_NOT_NEUTRAL, E_CUTOFF, E_SOG or E_KSEQ the
+ *     context is unchanged and usable; after E_DEVICE or E_OOM it must only be
+ *     destroyed.  rbsog_last_error() explains the latest failure.
+ *   - One context must not be used from two threads at once.  Work is
+ *     launched on one HIP stream (the caller's, or one the context owns).
+ *   - Fixed-point coordinates: u_d = min(2^32-1, floor(frac(x_d/L_d) 2^32)).
+ *     Cells: n_d = floor(L_d/r_c) if >= 3, else 1; c_d = (u_d n_d) >> 32;
+ *     cell = c_x + n_x (c_y + n_y c_z); particles ordered by (cell, id).
+ *     A pair is a neighbour iff (dx*dx + dy*dy) + dz*dz < r_c*r_c in FP64
+ *     without contraction, dx = (double)(int32)(u_j,x - u_i,x) * (L_x 2^-32).
+ */
+#ifndef RBSOG_H
+#define RBSOG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rbsog_ctx rbsog_ctx;
+
+typedef enum {
+    RBSOG_OK = 0,
+    RBSOG_E_ARG = -1,          /* null pointer, size or value out of range */
+    RBSOG_E_NOT_NEUTRAL = -2,  /* |sum q| > neutral_tol * sum |q| */
+    RBSOG_E_CUTOFF = -3,       /* r_c <= 0 or r_c > min(L)/2 */
+    RBSOG_E_SOG = -4,          /* b <= 1, sigma <= 0, w0 <= 0 or M < 0 */
+    RBSOG_E_DEVICE = -5,       /* a HIP call failed; the context is poisoned */
+    RBSOG_E_OOM = -6,          /* device allocation failed */
+    RBSOG_E_NONFINITE = -7,    /* non-finite input, or non-finite force/energy produced */
+    RBSOG_E_KSEQ = -8,         /* the wave-vector sequence has fewer than P unused entries */
+    RBSOG_E_STATE = -9         /* call not valid in the context's current state */
+} rbsog_status;
+
+typedef enum {
+    RBSOG_FP64 = 0,   /* every step in FP64 */
+    RBSOG_FP32C = 1   /* FP32 phases and pair arithmetic on fixed-point coordinates,
+                         FP64 accumulation of rho(k) partial sums and energies */
+} rbsog_precision;
+
+/* Sum-of-Gaussians parameters with Table 1 semantics (Sec. 4.1): sigma for the
+ * cutoff in use, w0 the factor applied to the nominal omega_0. */
+typedef struct {
+    double b;
+    double sigma;
+    double w0;
+    int32_t M;
+} rbsog_sog;
+
+typedef struct {
+    int32_t precision;    /* rbsog_precision; default RBSOG_FP64 */
+    int32_t device;       /* HIP device ordinal; default 0 */
+    void *stream;         /* hipStream_t to launch on; NULL = the context creates one */
+    double neutral_tol;   /* default 1e-10 */
+    double mass;          /* mass of every particle; default 1 */
+} rbsog_opts;
+
+/* Fills *o with the defaults above. */
+void rbsog_default_opts(rbsog_opts *o);
+
+/* Table 1 row `row` (1..5) scaled to cutoff rc: b and w0 as printed, sigma
+ * multiplied by rc / 10 (the table is quoted at r_c = 10 Angstrom; the split
+ * is scale covariant).  E_ARG for a row outside 1..5 or rc <= 0. */
+rbsog_status rbsog_sog_table1(int32_t row, double rc, rbsog_sog *out);
+
+/* Creates a context for one periodic system (Sec. 2 problem statement;
+ * Algorithm 1, step 1).
+ *   n     number of particles, >= 2
+ *   pos   host, n x 3, any finite values (wrapped into the box)
+ *   q     host, n charges, finite, neutral within opts->neutral_tol
+ *   box   host, 3 side lengths > 0
+ *   sog   split parameters (b > 1, sigma > 0, w0 > 0, M >= 0)
+ *   rc    cutoff, 0 < rc <= min(box)/2
+ *   P     wave vectors per force evaluation, >= 1
+ *   seed  key of the Metropolis-Hastings sampler's Philox4x32-10 stream
+ *   opts  NULL for defaults
+ * Computes S (Sec. 3.3, eq. "S"), uploads the system and allocates all device
+ * memory; velocities start at zero.  *out is NULL on failure. */
+rbsog_status rbsog_init(rbsog_ctx **out, int64_t n, const double *pos, const double *q,
+                        const double *box, const rbsog_sog *sog, double rc, int32_t P,
+                        uint64_t seed, const rbsog_opts *opts);
+
+/* Extends the wave-vector sequence by n_batches * P states of the
+ * Metropolis-Hastings independence chain of Sec. 3.3 (Algorithm 1, step 2):
+ * proposal m*_d = round(N(0, (L_d/(pi s_0))^2 / 2)), m* = 0 redrawn, accepted
+ * with probability min(1, p(m*) q(m)/(p(m) q(m*))), p ~ F~(2 pi m/L), q the
+ * proposal pmf (1/2)[erf((m+1/2) pi s_0/L_d) - erf((m-1/2) pi s_0/L_d)].  The
+ * chain starts at its first nonzero proposal and discards 100 transitions.
+ * Attempt t uses Philox4x32-10 with counter (t_lo, t_hi, 0, lane) and key
+ * (seed_lo, seed_hi): lanes 0 and 1 give two Box-Muller pairs from 53-bit
+ * uniforms, lane 2 the acceptance uniform.
+ *   m_out  NULL, or host n_batches * P * 3 int32 receiving the new states.
+ * E_ARG if n_batches < 1. */
+rbsog_status rbsog_sample_k(rbsog_ctx *ctx, int64_t n_batches, int32_t *m_out);
+
+/* Replaces the sequence with n_k caller-given nonzero vectors (host, n_k x 3)
+ * and rewinds it.  w: NULL for the random-batch weight S pi^{3/2}/(P V), or
+ * host n_k per-vector weights (w = F~(k)/V with every k of the lattice and
+ * P = n_k turns the far part into the full Fourier sum of eq. "forcesplit").
+ * E_ARG if n_k < 1 or a vector is zero. */
+rbsog_status rbsog_set_k(rbsog_ctx *ctx, int64_t n_k, const int32_t *m, const double *w);
+
+/* One force evaluation at the current positions with the next P vectors of
+ * the sequence (Algorithm 1, step 4): wrap and quantise, cell list, near
+ * part, structure factors, far force, energies.
+ *   F_out  NULL, or host n x 3 total force F_N + F*
+ *   E_out  NULL, or host 4 doubles: U_N, U*, U_self, U
+ * E_KSEQ if fewer than P vectors remain (nothing is computed). */
+rbsog_status rbsog_forces(rbsog_ctx *ctx, double *F_out, double *E_out);
+
+/* n_steps velocity-Verlet steps of size dt (kick dt/2, drift, wrap, forces
+ * with the next batch, kick dt/2; Algorithm 1 with NVE integration).  If the
+ * forces of the current positions are not known yet, one evaluation is made
+ * first.  E_KSEQ (before any work) if the sequence cannot serve every
+ * evaluation; E_NONFINITE if a non-finite force appeared. */
+rbsog_status rbsog_step(rbsog_ctx *ctx, int64_t n_steps, double dt);
+
+/* Sets velocities: v host n x 3, or NULL to draw v ~ N(0, T/m) per component
+ * (Philox4x32-10 keyed by seed, Box-Muller) and remove the centre-of-mass
+ * velocity.  E_ARG if v is NULL and T < 0. */
+rbsog_status rbsog_set_velocities(rbsog_ctx *ctx, const double *v, double T, uint64_t seed);
+
+/* Replaces the positions (host n x 3, finite); forces become unknown. */
+rbsog_status rbsog_set_positions(rbsog_ctx *ctx, const double *pos);
+
+/* Copies the state: pos (wrapped into [0, L)) and vel, host n x 3 each, either may be NULL. */
+rbsog_status rbsog_get_state(rbsog_ctx *ctx, double *pos, double *vel);
+
+/* Copies the near and far parts of the latest force evaluation (host n x 3
+ * each, either may be NULL).  E_STATE if no evaluation has been made. */
+rbsog_status rbsog_get_forces(rbsog_ctx *ctx, double *F_near, double *F_far);
+
+/* Copies the latest energies (U_N, U*, U_self, U) and structure factors
+ * (host P doubles each for rho_re, rho_im; either may be NULL). */
+rbsog_status rbsog_get_energy(rbsog_ctx *ctx, double *E4);
+rbsog_status rbsog_get_rho(rbsog_ctx *ctx, double *rho_re, double *rho_im);
+
+/* Scalars of the context: S, V, number of cells, wave vectors left in the
+ * sequence, evaluations made. */
+typedef struct {
+    double S;
+    double volume;
+    int32_t ncell[3];
+    int64_t k_remaining;
+    int64_t evaluations;
+} rbsog_info_t;
+rbsog_status rbsog_info(rbsog_ctx *ctx, rbsog_info_t *info);
+
+/* Debug exports of the latest cell list and a full neighbour list built on the
+ * device with the pair rule above (rows ascending i, columns ascending j).
+ *   cell_start  host ncell+1 int32;  order  host n int32 (ids by (cell, id))
+ *   row_ptr     host n+1 int64;  cols  host cap int32
+ * rbsog_debug_neighbors returns E_ARG if cap is smaller than the entry count
+ * (row_ptr is still filled, so the call can be repeated). */
+rbsog_status rbsog_debug_cells(rbsog_ctx *ctx, int32_t *cell_start, int32_t *order);
+rbsog_status rbsog_debug_neighbors(rbsog_ctx *ctx, int64_t *row_ptr, int32_t *cols, int64_t cap);
+
+/* Per-kernel timing with HIP events on the context's stream.  enable != 0
+ * starts recording (and clears the totals).  rbsog_profile_read returns the
+ * name, summed milliseconds and launch count of kernel idx (E_ARG past the
+ * last one). */
+rbsog_status rbsog_profile(rbsog_ctx *ctx, int32_t enable);
+rbsog_status rbsog_profile_read(rbsog_ctx *ctx, int32_t idx, const char **name, double *ms,
+                                int64_t *launches);
+
+/* Blocks until all work of the context has finished. */
+rbsog_status rbsog_sync(rbsog_ctx *ctx);
+
+const char *rbsog_last_error(const rbsog_ctx *ctx);
+const char *rbsog_status_string(rbsog_status s);
+
+/* Frees every resource of the context; NULL is ignored. */
+void rbsog_destroy(rbsog_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBSOG_H */

@@ -1,0 +1,282 @@
+"""Thin ctypes binding of librbsog (include/rbsog.h).
+
+Argument marshalling only: every step of the force path runs in the HIP
+library.  Importing this module does not need a GPU; calling anything that
+creates a context does.  If librbsog.so is missing the functions raise
+``RbsogError`` -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librbsog.so")
+
+RBSOG_FP64 = 0
+RBSOG_FP32C = 1
+
+STATUS = {0: "RBSOG_OK", -1: "RBSOG_E_ARG", -2: "RBSOG_E_NOT_NEUTRAL", -3: "RBSOG_E_CUTOFF", -4: "RBSOG_E_SOG",
+          -5: "RBSOG_E_DEVICE", -6: "RBSOG_E_OOM", -7: "RBSOG_E_NONFINITE", -8: "RBSOG_E_KSEQ", -9: "RBSOG_E_STATE"}
+
+# every symbol the header declares
+EXPORTS = ("rbsog_default_opts", "rbsog_sog_table1", "rbsog_init", "rbsog_sample_k", "rbsog_set_k", "rbsog_forces",
+           "rbsog_step", "rbsog_set_velocities", "rbsog_set_positions", "rbsog_get_state", "rbsog_get_forces",
+           "rbsog_get_energy", "rbsog_get_rho", "rbsog_info", "rbsog_debug_cells", "rbsog_debug_neighbors",
+           "rbsog_profile", "rbsog_profile_read", "rbsog_sync", "rbsog_last_error", "rbsog_status_string",
+           "rbsog_destroy")
+
+
+class RbsogError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class rbsog_sog(ctypes.Structure):
+    _fields_ = [("b", ctypes.c_double), ("sigma", ctypes.c_double), ("w0", ctypes.c_double), ("M", ctypes.c_int32)]
+
+
+class rbsog_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("neutral_tol", ctypes.c_double), ("mass", ctypes.c_double)]
+
+
+class rbsog_info_t(ctypes.Structure):
+    _fields_ = [("S", ctypes.c_double), ("volume", ctypes.c_double), ("ncell", ctypes.c_int32 * 3),
+                ("k_remaining", ctypes.c_int64), ("evaluations", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load librbsog.so (raises RbsogError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RbsogError(-5, f"{LIB_PATH} is not built; run paper_2205_13824_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, u64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+        P = ctypes.POINTER
+        sig = {
+            "rbsog_default_opts": (None, [P(rbsog_opts)]),
+            "rbsog_sog_table1": (i32, [i32, dbl, P(rbsog_sog)]),
+            "rbsog_init": (i32, [P(vp), i64, vp, vp, vp, P(rbsog_sog), dbl, i32, u64, P(rbsog_opts)]),
+            "rbsog_sample_k": (i32, [vp, i64, vp]),
+            "rbsog_set_k": (i32, [vp, i64, vp, vp]),
+            "rbsog_forces": (i32, [vp, vp, vp]),
+            "rbsog_step": (i32, [vp, i64, dbl]),
+            "rbsog_set_velocities": (i32, [vp, vp, dbl, u64]),
+            "rbsog_set_positions": (i32, [vp, vp]),
+            "rbsog_get_state": (i32, [vp, vp, vp]),
+            "rbsog_get_forces": (i32, [vp, vp, vp]),
+            "rbsog_get_energy": (i32, [vp, vp]),
+            "rbsog_get_rho": (i32, [vp, vp, vp]),
+            "rbsog_info": (i32, [vp, P(rbsog_info_t)]),
+            "rbsog_debug_cells": (i32, [vp, vp, vp]),
+            "rbsog_debug_neighbors": (i32, [vp, vp, vp, i64]),
+            "rbsog_profile": (i32, [vp, i32]),
+            "rbsog_profile_read": (i32, [vp, i32, P(ctypes.c_char_p), P(dbl), P(i64)]),
+            "rbsog_sync": (i32, [vp]),
+            "rbsog_last_error": (ctypes.c_char_p, [vp]),
+            "rbsog_status_string": (ctypes.c_char_p, [i32]),
+            "rbsog_destroy": (None, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(st: int, ctx=None):
+    if st != 0:
+        msg = lib().rbsog_last_error(ctx)
+        raise RbsogError(st, msg.decode() if msg else "")
+
+
+def _f64(a, shape):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(shape))
+
+
+def rbsog_sog_table1(row: int, rc: float) -> rbsog_sog:
+    out = rbsog_sog()
+    _check(lib().rbsog_sog_table1(int(row), float(rc), ctypes.byref(out)))
+    return out
+
+
+def rbsog_default_opts() -> rbsog_opts:
+    o = rbsog_opts()
+    lib().rbsog_default_opts(ctypes.byref(o))
+    return o
+
+
+def rbsog_init(pos, q, box, sog: rbsog_sog, rc: float, P: int, seed: int, precision: int = RBSOG_FP64,
+               device: int = 0, stream: int | None = None, neutral_tol: float = 1e-10, mass: float = 1.0):
+    q = _f64(q, (-1,))
+    n = q.size
+    pos = _f64(pos, (n, 3))
+    box = _f64(box, (3,))
+    o = rbsog_default_opts()
+    o.precision, o.device, o.neutral_tol, o.mass = precision, device, neutral_tol, mass
+    o.stream = stream
+    ctx = ctypes.c_void_p()
+    _check(lib().rbsog_init(ctypes.byref(ctx), n, _ptr(pos), _ptr(q), _ptr(box), ctypes.byref(sog), float(rc),
+                            int(P), int(seed), ctypes.byref(o)))
+    return ctx
+
+
+def rbsog_sample_k(ctx, n_batches: int, P: int):
+    out = np.zeros((n_batches * P, 3), dtype=np.int32)
+    _check(lib().rbsog_sample_k(ctx, int(n_batches), _ptr(out)), ctx)
+    return out
+
+
+def rbsog_set_k(ctx, m, w=None):
+    m = np.ascontiguousarray(np.asarray(m, dtype=np.int32).reshape(-1, 3))
+    wv = None if w is None else _f64(w, (m.shape[0],))
+    _check(lib().rbsog_set_k(ctx, m.shape[0], _ptr(m), _ptr(wv)), ctx)
+
+
+def rbsog_forces(ctx, n: int, want_forces: bool = True, want_energy: bool = True):
+    F = np.zeros((n, 3)) if want_forces else None
+    E = np.zeros(4) if want_energy else None
+    _check(lib().rbsog_forces(ctx, _ptr(F), _ptr(E)), ctx)
+    return F, E
+
+
+def rbsog_step(ctx, n_steps: int, dt: float):
+    _check(lib().rbsog_step(ctx, int(n_steps), float(dt)), ctx)
+
+
+def rbsog_set_velocities(ctx, v=None, T: float = 1.0, seed: int = 0, n: int | None = None):
+    vv = None if v is None else _f64(v, (-1, 3))
+    _check(lib().rbsog_set_velocities(ctx, _ptr(vv), float(T), int(seed)), ctx)
+
+
+def rbsog_set_positions(ctx, pos):
+    _check(lib().rbsog_set_positions(ctx, _ptr(_f64(pos, (-1, 3)))), ctx)
+
+
+def rbsog_get_state(ctx, n: int):
+    pos = np.zeros((n, 3))
+    vel = np.zeros((n, 3))
+    _check(lib().rbsog_get_state(ctx, _ptr(pos), _ptr(vel)), ctx)
+    return pos, vel
+
+
+def rbsog_get_forces(ctx, n: int):
+    Fn = np.zeros((n, 3))
+    Ff = np.zeros((n, 3))
+    _check(lib().rbsog_get_forces(ctx, _ptr(Fn), _ptr(Ff)), ctx)
+    return Fn, Ff
+
+
+def rbsog_get_energy(ctx):
+    E = np.zeros(4)
+    _check(lib().rbsog_get_energy(ctx, _ptr(E)), ctx)
+    return E
+
+
+def rbsog_get_rho(ctx, P: int):
+    re = np.zeros(P)
+    im = np.zeros(P)
+    _check(lib().rbsog_get_rho(ctx, _ptr(re), _ptr(im)), ctx)
+    return re, im
+
+
+def rbsog_info(ctx) -> dict:
+    info = rbsog_info_t()
+    _check(lib().rbsog_info(ctx, ctypes.byref(info)), ctx)
+    return dict(S=info.S, volume=info.volume, ncell=tuple(info.ncell), k_remaining=info.k_remaining,
+                evaluations=info.evaluations)
+
+
+def rbsog_debug_cells(ctx, n: int):
+    nc = rbsog_info(ctx)["ncell"]
+    start = np.zeros(nc[0] * nc[1] * nc[2] + 1, dtype=np.int32)
+    order = np.zeros(n, dtype=np.int32)
+    _check(lib().rbsog_debug_cells(ctx, _ptr(start), _ptr(order)), ctx)
+    return start, order
+
+
+def rbsog_debug_neighbors(ctx, n: int):
+    row = np.zeros(n + 1, dtype=np.int64)
+    st = lib().rbsog_debug_neighbors(ctx, _ptr(row), None, 0)
+    if st not in (0, -1):
+        _check(st, ctx)
+    cols = np.zeros(max(int(row[-1]), 1), dtype=np.int32)
+    _check(lib().rbsog_debug_neighbors(ctx, _ptr(row), _ptr(cols), cols.size), ctx)
+    return row, cols[:int(row[-1])]
+
+
+def rbsog_profile(ctx, enable: bool):
+    _check(lib().rbsog_profile(ctx, 1 if enable else 0), ctx)
+
+
+def rbsog_profile_read(ctx) -> dict:
+    out = {}
+    i = 0
+    while True:
+        name = ctypes.c_char_p()
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        st = lib().rbsog_profile_read(ctx, i, ctypes.byref(name), ctypes.byref(ms), ctypes.byref(cnt))
+        if st != 0:
+            break
+        out[name.value.decode()] = (ms.value, cnt.value)
+        i += 1
+    return out
+
+
+def rbsog_sync(ctx):
+    _check(lib().rbsog_sync(ctx), ctx)
+
+
+def rbsog_destroy(ctx):
+    if ctx:
+        lib().rbsog_destroy(ctx)
+
+
+class System:
+    """Owning wrapper: one context, destroyed with the object."""
+
+    def __init__(self, pos, q, box, rc, P, seed=0, sog: rbsog_sog | None = None, precision=RBSOG_FP64, **kw):
+        self.n = int(np.asarray(q).size)
+        self.P = int(P)
+        self.sog = sog if sog is not None else rbsog_sog_table1(2, rc)
+        self.ctx = rbsog_init(pos, q, box, self.sog, rc, P, seed, precision=precision, **kw)
+
+    def sample_k(self, n_batches):
+        return rbsog_sample_k(self.ctx, n_batches, self.P)
+
+    def set_k(self, m, w=None):
+        rbsog_set_k(self.ctx, m, w)
+
+    def forces(self):
+        return rbsog_forces(self.ctx, self.n)
+
+    def components(self):
+        return rbsog_get_forces(self.ctx, self.n)
+
+    def step(self, n_steps, dt):
+        rbsog_step(self.ctx, n_steps, dt)
+
+    def close(self):
+        if self.ctx:
+            rbsog_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,244 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: integer work (cells, neighbour lists, sampled wave vectors) bit-exact;
+FP64 forces within 1e-11 relative RMS (per part: near, far, total) and
+FP64 energies within 1e-11 relative; FP32C forces within 1e-5 relative RMS
+of the FP64 oracle.  Random-batch forces are compared on the identical k
+list.  Full-size checks compare sampled particles computed one by one by the
+oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2205_13824_amd import rbsog as R
+from paper_2205_13824_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-11
+F32C_TOL = 1e-5
+
+
+def relrms(a, b):
+    return math.sqrt(float(np.sum((a - b) ** 2)) / float(np.sum(b ** 2)))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def make(pos, q, box, rc, P, seed=11, prec=R.RBSOG_FP64, sog=None):
+    say(f"[gpu] init n={len(q)} box={tuple(np.round(box, 3))} rc={rc} P={P} prec={prec}")
+    return R.System(pos, q, box, rc, P, seed=seed, precision=prec, sog=sog)
+
+
+def oracle_sog(orc, s: R.rbsog_sog):
+    return orc.SOG(s.b, s.sigma, s.w0, s.M)
+
+
+def check_eval(orc, sysm, pos, q, box, rc, m, tol, label):
+    """One evaluation on the GPU vs the oracle's near (brute force) + RB far on list m."""
+    sog = oracle_sog(orc, sysm.sog)
+    F, E = sysm.forces()
+    Fn, Ff = sysm.components()
+    Fn_o, Un_o = orc.near_brute(pos, q, box, rc, sog)
+    Ff_o, Us_o, _, _ = orc.far_rb(pos, q, box, sog, m, sysm.P)
+    e_near, e_far, e_tot = relrms(Fn, Fn_o), relrms(Ff, Ff_o), relrms(F, Fn_o + Ff_o)
+    say(f"[{label}] relrms near {e_near:.3e} far {e_far:.3e} total {e_tot:.3e}")
+    assert e_near < tol and e_far < tol and e_tot < tol
+    Uself = orc.self_energy(sog, q)
+    for got, want, name in ((E[0], Un_o, "U_N"), (E[1], Us_o, "U*"), (E[2], Uself, "U_self"),
+                            (E[3], Un_o + Us_o - Uself, "U")):
+        err = abs(got - want) / max(abs(want), 1.0)
+        say(f"[{label}] {name} gpu {got:.15g} oracle {want:.15g} rel {err:.2e}")
+        assert err < tol * 10
+    return F, E
+
+
+def test_sampler_sequence_bit_exact(orc):
+    c = W.c1_small()
+    sysm = make(c["pos"], c["q"], c["box"], c["rc"], c["P"], seed=101)
+    got = sysm.sample_k(5)
+    want, _ = orc.mh_sample(oracle_sog(orc, sysm.sog), c["box"], seed=101, stream=0, n=5 * c["P"])
+    assert got.shape == want.shape and (got == want).all()
+    # the chain continues across calls
+    more = sysm.sample_k(2)
+    want2, _ = orc.mh_sample(oracle_sog(orc, sysm.sog), c["box"], seed=101, stream=0, n=7 * c["P"])
+    assert (more == want2[5 * c["P"]:]).all()
+
+
+@pytest.mark.parametrize("prec,tol", [(R.RBSOG_FP64, F64_TOL), (R.RBSOG_FP32C, F32C_TOL)])
+def test_c1_one_evaluation(orc, prec, tol):
+    c = W.c1_small()
+    sysm = make(c["pos"], c["q"], c["box"], c["rc"], c["P"], seed=101, prec=prec)
+    m = sysm.sample_k(1)
+    check_eval(orc, sysm, c["pos"], c["q"], c["box"], c["rc"], m, tol, f"C1 prec={prec}")
+    info = R.rbsog_info(sysm.ctx)
+    S_o = orc.S_product(oracle_sog(orc, sysm.sog), c["box"])
+    assert abs(info["S"] / S_o - 1) < 1e-13
+
+
+@pytest.mark.parametrize("prec", [R.RBSOG_FP64, R.RBSOG_FP32C])
+@pytest.mark.parametrize("case", ["c1", "skew", "tiny"])
+def test_cell_and_neighbour_lists_bit_exact(orc, prec, case):
+    if case == "c1":
+        c = W.c1_small()
+        pos, q, box, rc = c["pos"], c["q"], c["box"], c["rc"]
+    elif case == "skew":
+        rng = np.random.default_rng(3)
+        box = np.array([11.3, 9.7, 14.1])
+        pos = rng.random((777, 3)) * box - 5.0  # unwrapped input
+        q = np.where(np.arange(777) < 388, 1.0, -1.0)
+        q[-1] = 0.0
+        rc = 3.1
+    else:
+        rng = np.random.default_rng(4)
+        box = np.array([6.0, 6.0, 6.0])  # floor(L/rc) = 2 -> single cell per dimension
+        pos = rng.random((64, 3)) * box
+        q = np.where(np.arange(64) % 2 == 0, 1.0, -1.0)
+        rc = 2.9
+    sysm = make(pos, q, box, rc, 8, prec=prec)
+    sysm.sample_k(1)
+    sysm.forces()
+    start, order = R.rbsog_debug_cells(sysm.ctx, len(q))
+    nc, _, start_o, order_o = orc.cell_list(pos, box, rc)
+    assert tuple(R.rbsog_info(sysm.ctx)["ncell"]) == tuple(int(v) for v in nc)
+    assert (start == start_o).all() and (order == order_o).all()
+    row, cols = R.rbsog_debug_neighbors(sysm.ctx, len(q))
+    row_o, cols_o = orc.neighbors_brute(pos, box, rc)
+    assert (row == row_o).all() and (cols == cols_o).all()
+
+
+@pytest.mark.parametrize("prec,tol", [(R.RBSOG_FP64, F64_TOL), (R.RBSOG_FP32C, F32C_TOL)])
+@pytest.mark.parametrize("n,box,rc,P", [
+    (777, (11.3, 9.7, 14.1), 3.1, 37),     # ragged n, non-cubic box, odd P
+    (64, (6.0, 6.0, 6.0), 2.9, 130),       # single-cell fallback, P spans 3 k tiles
+    (5000, (20.0, 20.0, 20.0), 3.5, 1500),  # P above one block of k tiles
+    (2, (10.0, 10.0, 10.0), 3.0, 1),       # smallest system
+])
+def test_ragged_shapes(orc, prec, tol, n, box, rc, P):
+    rng = np.random.default_rng(n + P)
+    box = np.array(box)
+    pos = rng.random((n, 3)) * box
+    q = np.where(np.arange(n) < n // 2, 1.0, -1.0)
+    if n % 2:
+        q[-1] = 0.0
+    if n == 2:
+        pos = np.array([[1.0, 1.0, 1.0], [2.2, 1.5, 0.4]])
+    sysm = make(pos, q, box, rc, P, seed=n, prec=prec)
+    m = sysm.sample_k(1)
+    check_eval(orc, sysm, pos, q, box, rc, m, tol, f"ragged n={n} P={P} prec={prec}")
+
+
+@pytest.mark.parametrize("prec,tol", [(R.RBSOG_FP64, F64_TOL), (R.RBSOG_FP32C, F32C_TOL)])
+def test_full_fourier_sum_mode(orc, prec, tol):
+    # every k of the lattice with weight F~(k)/V: the deterministic far part
+    rng = np.random.default_rng(7)
+    L = 8.0
+    box = np.array([L, L, L])
+    n = 300
+    pos = rng.random((n, 3)) * L
+    q = np.where(np.arange(n) < n // 2, 1.0, -1.0)
+    rc = 3.0
+    sog_c = R.rbsog_sog_table1(2, rc)
+    sog = oracle_sog(orc, sog_c)
+    mk = orc.kvectors_full(sog, box)
+    w = orc.full_weights(sog, box, mk)
+    sysm = make(pos, q, box, rc, len(mk), prec=prec, sog=sog_c)
+    sysm.set_k(mk, w)
+    F, E = sysm.forces()
+    _, Ff = sysm.components()
+    Ff_o, Us_o, _, _ = orc.far_full(pos, q, box, sog)
+    err = relrms(Ff, Ff_o)
+    say(f"[full-sum prec={prec}] P={len(mk)} far relrms {err:.3e} U* {E[1]:.15g} vs {Us_o:.15g}")
+    assert err < tol
+    assert abs(E[1] - Us_o) / abs(Us_o) < tol * 10
+
+
+def test_repeat_evaluation_is_bitwise_identical(orc):
+    c = W.c1_small()
+    sysm = make(c["pos"], c["q"], c["box"], c["rc"], c["P"], seed=5)
+    m = sysm.sample_k(1)
+    sysm.set_k(np.concatenate([m, m]))
+    F1, E1 = sysm.forces()
+    F2, E2 = sysm.forces()
+    assert (F1 == F2).all() and (E1 == E2).all()
+
+
+def test_sequence_exhaustion_is_reported_and_recoverable(orc):
+    c = W.c1_small()
+    sysm = make(c["pos"], c["q"], c["box"], c["rc"], c["P"], seed=5)
+    with pytest.raises(R.RbsogError) as e:
+        sysm.forces()
+    assert e.value.status == -8
+    sysm.sample_k(1)
+    sysm.forces()
+    with pytest.raises(R.RbsogError) as e:
+        R.rbsog_step(sysm.ctx, 1, 1e-3)
+    assert e.value.status == -8
+
+
+@pytest.mark.parametrize("prec,tol", [(R.RBSOG_FP64, 1e-10), (R.RBSOG_FP32C, 1e-5)])
+def test_velocity_verlet_matches_oracle(orc, prec, tol):
+    n, L = 200, 10.0
+    pos, q, box = W.ions_rsa(n, n / L ** 3, 1.0, 21)
+    v0 = W.maxwellian(n, 1.0, 22)
+    rc, P, steps, dt = 3.0, 40, 5, 1e-3
+    sysm = make(pos, q, box, rc, P, seed=9, prec=prec)
+    m = sysm.sample_k(steps + 1)
+    R.rbsog_set_velocities(sysm.ctx, v0)
+    sysm.step(steps, dt)
+    x_g, v_g = R.rbsog_get_state(sysm.ctx, n)
+    x_o, v_o, F_o, _ = orc.vv_run(pos, v0, q, box, rc, oracle_sog(orc, sysm.sog), P, m, steps, dt)
+    dx = x_g - x_o
+    dx -= box * np.round(dx / box)
+    ex = float(np.abs(dx).max())
+    ev = relrms(v_g - v0, v_o - v0)
+    say(f"[vv prec={prec}] max|dx| {ex:.3e} velocity-change relrms {ev:.3e}")
+    assert ex < tol * 10
+    assert ev < tol * 10
+    # total momentum: FP64 forces cancel to rounding; FP32C near/far sums cancel to ~1e-7 of |F|
+    assert np.abs(v_g.sum(0) - v0.sum(0)).max() < (1e-9 if prec == R.RBSOG_FP64 else 1e-7)
+
+
+def test_maxwellian_velocities_have_zero_momentum_and_temperature(orc):
+    c = W.c1_small()
+    sysm = make(c["pos"], c["q"], c["box"], c["rc"], c["P"])
+    R.rbsog_set_velocities(sysm.ctx, None, T=2.0, seed=3)
+    _, v = R.rbsog_get_state(sysm.ctx, 1000)
+    assert np.abs(v.sum(0)).max() < 1e-10
+    assert abs(float((v * v).mean()) / 2.0 - 1) < 0.1
+
+
+@pytest.fixture(scope="module")
+def c2():
+    say("[gpu] building the 300,000-ion electrolyte")
+    return W.c2_electrolyte()
+
+
+@pytest.mark.parametrize("prec,tol", [(R.RBSOG_FP64, F64_TOL), (R.RBSOG_FP32C, F32C_TOL)])
+def test_c2_full_size_sampled(orc, c2, prec, tol):
+    pos, q, box, rc, P = c2["pos"], c2["q"], c2["box"], c2["rc"], c2["P"]
+    n = len(q)
+    sysm = make(pos, q, box, rc, P, seed=202, prec=prec)
+    m = sysm.sample_k(1)
+    F, E = sysm.forces()
+    Fn, Ff = sysm.components()
+    re, im = R.rbsog_get_rho(sysm.ctx, P)
+    sog = oracle_sog(orc, sysm.sog)
+    targets = np.random.default_rng(55).choice(n, 400, replace=False)
+    Fn_o = orc.near_targets(pos, q, box, rc, sog, targets)
+    S = orc.S_product(sog, box)
+    Ff_o, Us_o, re_o, im_o = orc.far_rb(pos, q, box, sog, m, P, S, targets=targets)
+    e_rho = math.sqrt(float(np.sum((re - re_o) ** 2 + (im - im_o) ** 2) / np.sum(re_o ** 2 + im_o ** 2)))
+    e_near, e_far = relrms(Fn[targets], Fn_o), relrms(Ff[targets], Ff_o)
+    say(f"[C2 prec={prec}] rho {e_rho:.3e} near {e_near:.3e} far {e_far:.3e} U* rel "
+        f"{abs(E[1] - Us_o) / abs(Us_o):.3e}")
+    assert e_rho < tol and e_near < tol and e_far < tol
+    assert abs(E[1] - Us_o) / abs(Us_o) < 10 * tol
+    # properties at full size: Newton's third law and zero total far force
+    assert np.abs(Fn.sum(0)).max() < (1e-9 if prec == R.RBSOG_FP64 else 1e-3) * np.abs(Fn).max() * math.sqrt(n)
+    assert np.abs(Ff.sum(0)).max() < (1e-9 if prec == R.RBSOG_FP64 else 1e-3) * np.abs(Ff).max() * math.sqrt(n)
