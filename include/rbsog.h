@@ -85,6 +85,7 @@ typedef struct {
     void *stream;         /* hipStream_t to launch on; NULL = the context creates one */
     double neutral_tol;   /* default 1e-10 */
     double mass;          /* mass of every particle; default 1 */
+    int32_t graphs;       /* nonzero: rbsog_step replays one captured HIP graph per step; default 1 */
 } rbsog_opts;
 
 /* Fills *o with the defaults above. */

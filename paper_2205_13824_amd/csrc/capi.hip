@@ -68,12 +68,9 @@ struct ProfEntry {
     int64_t launches = 0;
 };
 
-enum Kid { K_FILL, K_QUANT, K_SCAN, K_SCATTER, K_CSORT, K_GATHER, K_NEAR, K_STAGE, K_RHO, K_RHORED, K_FAR,
-           K_FINAL, K_KICK, K_DRIFT, K_COUNT };
-const char *kKernelNames[K_COUNT] = {"fill_cell_count", "quantise_histogram", "scan_cell_counts", "cell_scatter",
-                                     "cell_sort",       "gather_sorted",      "near",             "stage_k",
-                                     "rho",             "rho_reduce",         "far",              "finalize",
-                                     "kick",            "drift"};
+enum Kid { K_KDQ, K_SCAN, K_SCATTER, K_SORTG, K_NEAR, K_RHO, K_RHORED, K_FAR, K_COUNT };
+const char *kKernelNames[K_COUNT] = {"kick_drift_quantise", "scan_cell_counts", "cell_scatter", "sort_gather",
+                                     "near",                "rho",              "rho_reduce",   "far"};
 
 }  // namespace
 
@@ -94,6 +91,7 @@ struct rbsog_ctx {
     Geom geom{};
     int64_t ncell = 0;
     FarPlan fplan{};
+    NearPlan nplan{};
     // sequence
     MHChain chain;
     std::vector<int32_t> kseq;
@@ -124,9 +122,16 @@ struct rbsog_ctx {
     KRec32 *kb32 = nullptr;
     double *wk = nullptr, *rho = nullptr, *ek = nullptr, *partial = nullptr, *epart = nullptr, *E = nullptr;
     int32_t *flag = nullptr;
+    uint32_t *counter = nullptr;
     double *sog64 = nullptr;
     float *sog32 = nullptr;
     SogDev sogdev{};
+    // graph of one velocity-Verlet step
+    bool use_graphs = true;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    double graph_dt = 0.0;
+    const void *graph_key[3] = {nullptr, nullptr, nullptr};
     // profiling
     bool prof_on = false;
     ProfEntry prof[K_COUNT];
@@ -363,37 +368,74 @@ rbsog_status upload_k(rbsog_ctx *c, int64_t from) {
     return RBSOG_OK;
 }
 
-rbsog_status enqueue_forces(rbsog_ctx *c) {
+// Enqueue one force evaluation (with the velocity-Verlet kick-drift before
+// and the closing kick after it when dt != 0).  Pure launches: no host state
+// changes, so it can be captured into a graph.
+rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt) {
     hipStream_t s = c->stream;
     const Geom &g = c->geom;
     const bool f64 = c->prec == RBSOG_FP64;
-    TRY(timed(c, K_FILL, [&] { launch_fill_i32(c->cell_count, c->ncell, 0, s); }));
-    TRY(timed(c, K_QUANT, [&] { launch_quantise(g, c->x, c->u, c->cell_of, c->cell_count, s); }));
+    KickArgs kick{stepping ? 1 : 0, 0.5 * dt / c->mass, dt, c->v, c->Fn, c->Ff, c->flag};
+    StageArgs stage{c->P, c->dkseq, c->custom_w ? c->dkw : nullptr, c->w_rb, c->dcursor, c->kb64, c->kb32, c->wk};
+    TRY(timed(c, K_KDQ, [&] { launch_kdq(g, kick, stage, c->x, c->u, c->cell_of, c->cell_count, s); }));
     TRY(timed(c, K_SCAN, [&] { launch_scan(c->cell_count, c->cell_start, c->cell_fill, c->ncell, c->blocksums, s); }));
     TRY(timed(c, K_SCATTER, [&] { launch_cell_scatter(g, c->cell_of, c->cell_fill, c->order, s); }));
-    TRY(timed(c, K_CSORT, [&] { launch_cell_sort(c->ncell, c->cell_start, c->order, s); }));
-    TRY(timed(c, K_GATHER, [&] { launch_gather(g, c->order, c->u, c->x, c->q, c->su, c->sx, c->sq, c->sqf, f64, s); }));
-    TRY(timed(c, K_NEAR, [&] {
-        launch_near(g, c->sogdev, f64, c->cell_start, c->order, c->su, c->sx, c->sq, c->sqf, c->Fn, c->epart, s);
+    TRY(timed(c, K_SORTG, [&] {
+        launch_sort_gather(g, c->ncell, c->cell_start, c->order, c->cell_count, c->u, c->x, c->q, c->su, c->sx, c->sq,
+                           c->sqf, f64, s);
     }));
-    TRY(timed(c, K_STAGE, [&] {
-        launch_stage_k(g, c->P, c->dkseq, c->custom_w ? c->dkw : nullptr, c->w_rb, c->dcursor, c->kb64, c->kb32, c->wk,
-                       s);
+    TRY(timed(c, K_NEAR, [&] {
+        launch_near(g, c->sogdev, f64, c->nplan, c->ncell, c->cell_start, c->order, c->su, c->sx, c->sq, c->sqf, c->Fn,
+                    c->epart, s);
     }));
     TRY(timed(c, K_RHO, [&] {
         launch_rho(g, c->fplan, c->P, f64, c->x, c->u, c->q, c->qf, c->kb64, c->kb32, c->partial, s);
     }));
     TRY(timed(c, K_RHORED, [&] {
-        launch_rho_reduce(c->P, c->fplan.nblk, c->partial, c->wk, c->kb64, c->kb32, c->rho, c->ek, s);
+        launch_rho_reduce(c->P, c->fplan.nblk, c->partial, c->wk, c->kb64, c->kb32, c->rho, c->ek, c->nplan.nblk,
+                          c->epart, c->uself, c->E, c->flag, c->counter, s);
     }));
-    TRY(timed(c, K_FAR, [&] { launch_far(g, c->P, f64, c->x, c->u, c->q, c->qf, c->kb64, c->kb32, c->Ff, s); }));
-    TRY(timed(c, K_FINAL, [&] {
-        launch_finalize(near_blocks(c->n), c->epart, c->P, c->ek, c->uself, c->E, c->flag, s);
-    }));
+    TRY(timed(c, K_FAR, [&] { launch_far(g, c->P, f64, c->x, c->u, c->q, c->qf, c->kb64, c->kb32, c->Ff, kick, s); }));
     HIPCHK(c, hipGetLastError());
+    return RBSOG_OK;
+}
+
+void account_eval(rbsog_ctx *c) {
     c->cursor += c->P;
     c->evals += 1;
     c->forces_valid = true;
+}
+
+void drop_graph(rbsog_ctx *c) {
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+}
+
+// The graph of one step captures the kernel arguments: it is rebuilt when dt
+// or a buffer it reads (the sequence and its weights) changes.
+rbsog_status ensure_step_graph(rbsog_ctx *c, double dt) {
+    const void *key[3] = {c->dkseq, c->custom_w ? (const void *)c->dkw : nullptr, (const void *)c->x};
+    if (c->graph_exec && c->graph_dt == dt && std::equal(key, key + 3, c->graph_key)) return RBSOG_OK;
+    drop_graph(c);
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+    rbsog_status st = enqueue_eval(c, true, dt);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (st != RBSOG_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(c, RBSOG_E_DEVICE, "stream capture: %s", hipGetErrorString(e));
+    c->graph = g;
+    e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        drop_graph(c);
+        return fail(c, RBSOG_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+    }
+    c->graph_dt = dt;
+    std::copy(key, key + 3, c->graph_key);
     return RBSOG_OK;
 }
 
@@ -440,6 +482,7 @@ void rbsog_default_opts(rbsog_opts *o) {
     o->stream = nullptr;
     o->neutral_tol = 1e-10;
     o->mass = 1.0;
+    o->graphs = 1;
 }
 
 rbsog_status rbsog_sog_table1(int32_t row, double rc, rbsog_sog *out) {
@@ -502,6 +545,7 @@ rbsog_status rbsog_init(rbsog_ctx **out, int64_t n, const double *pos, const dou
     c->prec = o.precision;
     c->device = o.device;
     c->mass = o.mass;
+    c->use_graphs = o.graphs != 0;
     c->M = sog->M;
     sog_coefficients(*sog, c->omega, c->s);
     c->V = box[0] * box[1] * box[2];
@@ -532,13 +576,23 @@ rbsog_status rbsog_init(rbsog_ctx **out, int64_t n, const double *pos, const dou
     g.band_hi = g.rc2 * (1.0 + d64);
     g.band_lo_f = (float)(g.rc2 * (1.0 - d32));
     g.band_hi_f = (float)(g.rc2 * (1.0 + d32));
-    g.ngauss = c->M + 1;
+    // Gaussians wide enough that exp(-x/s_l^2) is a short Taylor series over
+    // x = r^2 <= rc^2 form the tail; s_l grows with l, so they are l >= nexp.
+    g.nexp = c->M + 1;
+    for (int l = 0; l <= c->M; ++l)
+        if (rc * rc / (c->s[l] * c->s[l]) <= kTailTau) {
+            g.nexp = l;
+            break;
+        }
+    g.ntail64 = g.nexp <= c->M ? kTailDeg64 + 1 : 0;
+    g.ntail32 = g.nexp <= c->M ? kTailDeg32 + 1 : 0;
     c->ncell = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
     if (c->ncell >= (int64_t)INT32_MAX) {
         delete c;
         return fail(nullptr, RBSOG_E_ARG, "too many cells");
     }
     c->fplan = far_plan(n, P);
+    c->nplan = near_plan(c->ncell);
 
     auto bail = [&](rbsog_status st) {
         g_init_error = c->err;
@@ -587,16 +641,17 @@ rbsog_status rbsog_init(rbsog_ctx **out, int64_t n, const double *pos, const dou
     ALLOC(rho, 2 * (int64_t)P);
     ALLOC(ek, P);
     ALLOC(partial, 2 * c->fplan.nblk * (int64_t)P);
-    ALLOC(epart, near_blocks(n));
+    ALLOC(epart, c->nplan.nblk);
     ALLOC(E, 4);
     ALLOC(flag, 1);
-    ALLOC(sog64, 3 * (int64_t)(c->M + 1));
-    ALLOC(sog32, 3 * (int64_t)(c->M + 1));
+    ALLOC(counter, 1);
+    const int G = c->M + 1, T64 = kTailDeg64 + 1, T32 = kTailDeg32 + 1;
+    ALLOC(sog64, 3 * (int64_t)G + 2 * T64);
+    ALLOC(sog32, 3 * (int64_t)G + 2 * T32);
 #undef ALLOC
     {
-        const int G = c->M + 1;
-        std::vector<double> h64(3 * G);
-        std::vector<float> h32(3 * G);
+        std::vector<double> h64(3 * G + 2 * T64, 0.0);
+        std::vector<float> h32(3 * G + 2 * T32, 0.f);
         for (int l = 0; l < G; ++l) {
             const double is2 = 1.0 / (c->s[l] * c->s[l]);
             h64[l] = c->omega[l];
@@ -606,12 +661,34 @@ rbsog_status rbsog_init(rbsog_ctx **out, int64_t n, const double *pos, const dou
             h32[G + l] = (float)(is2 / std::log(2.0));
             h32[2 * G + l] = (float)(2.0 * c->omega[l] * is2);
         }
+        // tail polynomials: sum_{l >= nexp} omega_l e^{-x a_l} = sum_k (-1)^k/k! (sum_l omega_l a_l^k) x^k
+        // and the force weights 2 omega_l a_l e^{-x a_l} likewise (a_l = 1/s_l^2)
+        double fact = 1.0;
+        for (int k = 0; k < T64; ++k) {
+            if (k > 0) fact *= k;
+            double sp = 0.0, sf = 0.0;
+            for (int l = g.nexp; l < G; ++l) {
+                const double a = 1.0 / (c->s[l] * c->s[l]);
+                sp += c->omega[l] * std::pow(a, k);
+                sf += 2.0 * c->omega[l] * std::pow(a, k + 1);
+            }
+            const double sgn = (k & 1) ? -1.0 : 1.0;
+            h64[3 * G + k] = sgn * sp / fact;
+            h64[3 * G + T64 + k] = sgn * sf / fact;
+            if (k < T32) {
+                h32[3 * G + k] = (float)(sgn * sp / fact);
+                h32[3 * G + T32 + k] = (float)(sgn * sf / fact);
+            }
+        }
         if (hipMemcpy(c->sog64, h64.data(), h64.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(c->sog32, h32.data(), h32.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
             fail(c, RBSOG_E_DEVICE, "coefficient upload failed");
             return bail(RBSOG_E_DEVICE);
         }
-        c->sogdev = SogDev{c->sog64, c->sog64 + G, c->sog64 + 2 * G, c->sog32, c->sog32 + G, c->sog32 + 2 * G};
+        c->sogdev = SogDev{c->sog64,          c->sog64 + G,          c->sog64 + 2 * G,
+                           c->sog64 + 3 * G,  c->sog64 + 3 * G + T64, c->sog32,
+                           c->sog32 + G,      c->sog32 + 2 * G,      c->sog32 + 3 * G,
+                           c->sog32 + 3 * G + T32};
     }
     {
         std::vector<double> qd(q, q + n);
@@ -626,7 +703,9 @@ rbsog_status rbsog_init(rbsog_ctx **out, int64_t n, const double *pos, const dou
             hipMemcpy(c->Fn, zero.data(), zero.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(c->Ff, zero.data(), zero.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
             hipMemcpy(c->dcursor, &zc, sizeof zc, hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(c->flag, &zf, sizeof zf, hipMemcpyHostToDevice) != hipSuccess) {
+            hipMemcpy(c->flag, &zf, sizeof zf, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemset(c->counter, 0, sizeof(uint32_t)) != hipSuccess ||
+            hipMemset(c->cell_count, 0, (size_t)c->ncell * sizeof(int32_t)) != hipSuccess) {
             fail(c, RBSOG_E_DEVICE, "initial upload failed");
             return bail(RBSOG_E_DEVICE);
         }
@@ -685,7 +764,8 @@ rbsog_status rbsog_forces(rbsog_ctx *c, double *F_out, double *E_out) {
     const int64_t nvec = (int64_t)c->kseq.size() / 3;
     if (c->cursor + c->P > nvec)
         return fail(c, RBSOG_E_KSEQ, "sequence has %lld unused vectors, P = %d", (long long)(nvec - c->cursor), c->P);
-    TRY(enqueue_forces(c));
+    TRY(enqueue_eval(c, false, 0.0));
+    account_eval(c);
     if (F_out) {
         std::vector<double> a((size_t)3 * c->n), b((size_t)3 * c->n);
         TRY(soa_to_host(c, c->Fn, a.data()));
@@ -707,13 +787,16 @@ rbsog_status rbsog_step(rbsog_ctx *c, int64_t n_steps, double dt) {
     if (c->cursor + need > nvec)
         return fail(c, RBSOG_E_KSEQ, "%lld steps need %lld vectors, %lld remain", (long long)n_steps, (long long)need,
                     (long long)(nvec - c->cursor));
-    if (!c->forces_valid) TRY(enqueue_forces(c));
-    const double hdm = 0.5 * dt / c->mass;
+    if (!c->forces_valid) {
+        TRY(enqueue_eval(c, false, 0.0));
+        account_eval(c);
+    }
+    const bool graphs = c->use_graphs && !c->prof_on && n_steps > 1;
+    if (graphs) TRY(ensure_step_graph(c, dt));
     for (int64_t k = 0; k < n_steps; ++k) {
-        TRY(timed(c, K_KICK, [&] { launch_kick(c->n, hdm, c->v, c->Fn, c->Ff, c->flag, c->stream); }));
-        TRY(timed(c, K_DRIFT, [&] { launch_drift(c->n, dt, c->x, c->v, c->stream); }));
-        TRY(enqueue_forces(c));
-        TRY(timed(c, K_KICK, [&] { launch_kick(c->n, hdm, c->v, c->Fn, c->Ff, c->flag, c->stream); }));
+        if (graphs) HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+        else TRY(enqueue_eval(c, true, dt));
+        account_eval(c);
     }
     int32_t flag = 0;
     HIPCHK(c, hipMemcpyAsync(&flag, c->flag, sizeof flag, hipMemcpyDeviceToHost, c->stream));
@@ -833,10 +916,9 @@ rbsog_status rbsog_debug_neighbors(rbsog_ctx *c, int64_t *row_ptr, int32_t *cols
     TRY(check_ctx(c));
     if (c->evals == 0) return fail(c, RBSOG_E_STATE, "no force evaluation yet");
     if (!row_ptr) return fail(c, RBSOG_E_ARG, "row_ptr is null");
-    const bool f64 = c->prec == RBSOG_FP64;
     int64_t *dcount = nullptr;
     HIPCHK(c, hipMalloc((void **)&dcount, (size_t)(c->n + 1) * sizeof(int64_t)));
-    launch_neighbor_count(c->geom, f64, c->cell_start, c->order, c->su, c->sx, dcount, c->stream);
+    launch_neighbor_count(c->geom, c->cell_start, c->order, c->su, dcount, c->stream);
     std::vector<int64_t> cnt(c->n);
     hipError_t e = hipMemcpyAsync(cnt.data(), dcount, (size_t)c->n * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -855,7 +937,7 @@ rbsog_status rbsog_debug_neighbors(rbsog_ctx *c, int64_t *row_ptr, int32_t *cols
     e = hipMemcpy(dcount, row_ptr, (size_t)(c->n + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc((void **)&dcols, (size_t)std::max<int64_t>(total, 1) * sizeof(int32_t));
     if (e == hipSuccess) {
-        launch_neighbor_fill(c->geom, f64, c->cell_start, c->order, c->su, c->sx, dcount, dcols, c->stream);
+        launch_neighbor_fill(c->geom, c->cell_start, c->order, c->su, dcount, dcols, c->stream);
         e = hipMemcpyAsync(cols, dcols, (size_t)total * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     }
@@ -920,6 +1002,7 @@ void rbsog_destroy(rbsog_ctx *c) {
         (void)hipEventDestroy(p.b);
     }
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    drop_graph(c);
     for (void *p : c->allocs) (void)hipFree(p);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;

@@ -71,33 +71,6 @@ __device__ __forceinline__ void sincos2pi(double f, double *s, double *c) {
     *c = ((q + 1) & 2) ? -b : b;
 }
 
-// Stage the current batch (cursor .. cursor + P) of the sequence: per-k
-// records for both precisions and the weights; then advance the cursor.
-__global__ void k_stage(Geom g, int32_t P, const int32_t *__restrict__ kseq, const double *__restrict__ kw,
-                        double w_rb, int64_t *__restrict__ cursor, KRec64 *__restrict__ kb64,
-                        KRec32 *__restrict__ kb32, double *__restrict__ wk) {
-    const int64_t base = *cursor;
-    for (int32_t k = threadIdx.x; k < P; k += blockDim.x) {
-        const int64_t e = base + k;
-        const int32_t mx = kseq[3 * e], my = kseq[3 * e + 1], mz = kseq[3 * e + 2];
-        const double w = kw ? kw[e] : w_rb;
-        const double kx = kTwoPi * g.invL[0] * mx, ky = kTwoPi * g.invL[1] * my, kz = kTwoPi * g.invL[2] * mz;
-        KRec64 r;
-        r.mx = mx; r.my = my; r.mz = mz;
-        r.ckx = w * kx; r.cky = w * ky; r.ckz = w * kz;
-        r.re = 0.0; r.im = 0.0;
-        kb64[k] = r;
-        KRec32 h;
-        h.mx = mx; h.my = my; h.mz = mz;
-        h.ckx = (float)r.ckx; h.cky = (float)r.cky; h.ckz = (float)r.ckz;
-        h.re = 0.f; h.im = 0.f;
-        kb32[k] = h;
-        wk[k] = w;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) *cursor = base + P;
-}
-
 // Structure factor partial sums.  Block (bx, by): particles
 // [bx*chunk, (bx+1)*chunk), wave vectors [by*kt*64, (by+1)*kt*64).
 // Wave w handles k tile (w % kt) for particle stream (w / kt).
@@ -123,31 +96,67 @@ __global__ __launch_bounds__(1024) void k_rho(Geom g, int32_t P, int kt, int str
     const int64_t a = j0 + st * per;
     const int64_t b = a + per < j1 ? a + per : j1;
     double re = 0.0, im = 0.0;
+    // particles are consumed in groups of G so that the uniform loads of a
+    // group are issued together and their latency is paid once per group
+    constexpr int G = 8;
     if constexpr (F64) {
         const double mx = kb64[kk].mx, my = kb64[kk].my, mz = kb64[kk].mz;
         const double ix = g.invL[0], iy = g.invL[1], iz = g.invL[2];
-        for (int64_t j = a; j < b; ++j) {
+        int64_t j = a;
+        for (; j + G <= b; j += G) {
+            double px[G], py[G], pz[G], pq[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                px[k] = x[j + k]; py[k] = x[n + j + k]; pz[k] = x[2 * n + j + k]; pq[k] = q[j + k];
+            }
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const double t = mx * (px[k] * ix) + my * (py[k] * iy) + mz * (pz[k] * iz);
+                double sn, cs;
+                sincos2pi(t - rint(t), &sn, &cs);
+                re = fma(pq[k], cs, re);
+                im = fma(pq[k], sn, im);
+            }
+        }
+        for (; j < b; ++j) {
             const double t = mx * (x[j] * ix) + my * (x[n + j] * iy) + mz * (x[2 * n + j] * iz);
             double sn, cs;
             sincos2pi(t - rint(t), &sn, &cs);
-            const double qj = q[j];
-            re = fma(qj, cs, re);
-            im = fma(qj, sn, im);
+            re = fma(q[j], cs, re);
+            im = fma(q[j], sn, im);
         }
     } else {
         const uint32_t mx = (uint32_t)kb32[kk].mx, my = (uint32_t)kb32[kk].my, mz = (uint32_t)kb32[kk].mz;
+        int64_t j = a;
+        // FP32 partial sums over 32 particles, then accumulated in FP64
+        for (; j + 4 * G <= b; j += 4 * G) {
+            float rf = 0.f, fi = 0.f;
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                uint32_t px[G], py[G], pz[G];
+                float pq[G];
+#pragma unroll
+                for (int k = 0; k < G; ++k) {
+                    const int64_t jj = j + h * G + k;
+                    px[k] = u[jj]; py[k] = u[n + jj]; pz[k] = u[2 * n + jj]; pq[k] = qf[jj];
+                }
+#pragma unroll
+                for (int k = 0; k < G; ++k) {
+                    const uint32_t t = mx * px[k] + my * py[k] + mz * pz[k];
+                    const float f = (float)(int32_t)t * 0x1.0p-32f;
+                    rf = fmaf(pq[k], __builtin_amdgcn_cosf(f), rf);
+                    fi = fmaf(pq[k], __builtin_amdgcn_sinf(f), fi);
+                }
+            }
+            re += rf;
+            im += fi;
+        }
         float rf = 0.f, fi = 0.f;
-        int cnt = 0;
-        for (int64_t j = a; j < b; ++j) {
+        for (; j < b; ++j) {
             const uint32_t t = mx * u[j] + my * u[n + j] + mz * u[2 * n + j];
             const float f = (float)(int32_t)t * 0x1.0p-32f;
-            const float qj = qf[j];
-            rf = fmaf(qj, __builtin_amdgcn_cosf(f), rf);
-            fi = fmaf(qj, __builtin_amdgcn_sinf(f), fi);
-            if (++cnt == 32) {
-                re += rf; im += fi;
-                rf = 0.f; fi = 0.f; cnt = 0;
-            }
+            rf = fmaf(qf[j], __builtin_amdgcn_cosf(f), rf);
+            fi = fmaf(qf[j], __builtin_amdgcn_sinf(f), fi);
         }
         re += rf;
         im += fi;
@@ -167,12 +176,19 @@ __global__ __launch_bounds__(1024) void k_rho(Geom g, int32_t P, int kt, int str
 }
 
 // rho_e = sum over particle blocks of the partials (fixed order), the
-// per-k energy 1/2 w_e |rho_e|^2, and rho written into the k records.
+// per-k energy 1/2 w_e |rho_e|^2, and rho written into the k records.  The
+// last block to finish (counter) sums the energies in a fixed order:
+// U_N from the near kernel's block partials, U*, U_self, U; and re-arms the
+// counter for the next launch.
 __global__ __launch_bounds__(256) void k_rho_reduce(int32_t P, int64_t nblk, const double *__restrict__ partial,
                                                     const double *__restrict__ wk, KRec64 *__restrict__ kb64,
                                                     KRec32 *__restrict__ kb32, double *__restrict__ rho,
-                                                    double *__restrict__ ek) {
+                                                    double *__restrict__ ek, int64_t nnear,
+                                                    const double *__restrict__ epart, double uself,
+                                                    double *__restrict__ E, int32_t *__restrict__ flag,
+                                                    uint32_t *__restrict__ counter) {
     __shared__ double sr[256], si[256];
+    __shared__ bool last;
     const int32_t k = blockIdx.x;
     double a = 0.0, b = 0.0;
     for (int64_t c = threadIdx.x; c < nblk; c += 256) {
@@ -198,6 +214,33 @@ __global__ __launch_bounds__(256) void k_rho_reduce(int32_t P, int64_t nblk, con
         kb32[k].re = (float)re;
         kb32[k].im = (float)im;
         ek[k] = 0.5 * wk[k] * (re * re + im * im);
+        __threadfence();
+        last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double un = 0.0, us = 0.0;
+    for (int64_t i = threadIdx.x; i < nnear; i += 256) un += epart[i];
+    for (int64_t i = threadIdx.x; i < P; i += 256) us += ek[i];
+    sr[threadIdx.x] = un;
+    si[threadIdx.x] = us;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            sr[threadIdx.x] += sr[threadIdx.x + o];
+            si[threadIdx.x] += si[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double tot = sr[0] + si[0] - uself;
+        E[0] = sr[0];
+        E[1] = si[0];
+        E[2] = uself;
+        E[3] = tot;
+        if (!isfinite(tot)) atomicOr(flag, 2);
+        *counter = 0u;
     }
 }
 
@@ -206,15 +249,33 @@ template <bool F64>
 __global__ __launch_bounds__(256) void k_far(Geom g, int32_t P, const double *__restrict__ x,
                                              const uint32_t *__restrict__ u, const double *__restrict__ q,
                                              const float *__restrict__ qf, const KRec64 *__restrict__ kb64,
-                                             const KRec32 *__restrict__ kb32, double *__restrict__ Ff) {
+                                             const KRec32 *__restrict__ kb32, double *__restrict__ Ff, KickArgs kick) {
     const int64_t n = g.n;
     const int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool valid = i0 < n;
     const int64_t i = valid ? i0 : 0;
     double Fx = 0.0, Fy = 0.0, Fz = 0.0;
+    // records are consumed in groups so that their uniform loads overlap
     if constexpr (F64) {
         const double sx = x[i] * g.invL[0], sy = x[n + i] * g.invL[1], sz = x[2 * n + i] * g.invL[2];
-        for (int32_t e = 0; e < P; ++e) {
+        constexpr int G = 2;
+        int32_t e = 0;
+        for (; e + G <= P; e += G) {
+            KRec64 r[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) r[k] = kb64[e + k];
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const double t = r[k].mx * sx + r[k].my * sy + r[k].mz * sz;
+                double sn, cs;
+                sincos2pi(t - rint(t), &sn, &cs);
+                const double v = cs * r[k].im - sn * r[k].re;
+                Fx = fma(r[k].ckx, v, Fx);
+                Fy = fma(r[k].cky, v, Fy);
+                Fz = fma(r[k].ckz, v, Fz);
+            }
+        }
+        for (; e < P; ++e) {
             const KRec64 r = kb64[e];
             const double t = r.mx * sx + r.my * sy + r.mz * sz;
             double sn, cs;
@@ -228,9 +289,30 @@ __global__ __launch_bounds__(256) void k_far(Geom g, int32_t P, const double *__
         Fx *= -qi; Fy *= -qi; Fz *= -qi;
     } else {
         const uint32_t ux = u[i], uy = u[n + i], uz = u[2 * n + i];
+        constexpr int G = 4;
+        int32_t e = 0;
+        // FP32 partial sums over 64 records, then accumulated in FP64
+        for (; e + 16 * G <= P; e += 16 * G) {
+            float fx = 0.f, fy = 0.f, fz = 0.f;
+#pragma unroll
+            for (int h = 0; h < 16; ++h) {
+                KRec32 r[G];
+#pragma unroll
+                for (int k = 0; k < G; ++k) r[k] = kb32[e + h * G + k];
+#pragma unroll
+                for (int k = 0; k < G; ++k) {
+                    const uint32_t t = (uint32_t)r[k].mx * ux + (uint32_t)r[k].my * uy + (uint32_t)r[k].mz * uz;
+                    const float f = (float)(int32_t)t * 0x1.0p-32f;
+                    const float v = __builtin_amdgcn_cosf(f) * r[k].im - __builtin_amdgcn_sinf(f) * r[k].re;
+                    fx = fmaf(r[k].ckx, v, fx);
+                    fy = fmaf(r[k].cky, v, fy);
+                    fz = fmaf(r[k].ckz, v, fz);
+                }
+            }
+            Fx += fx; Fy += fy; Fz += fz;
+        }
         float fx = 0.f, fy = 0.f, fz = 0.f;
-        int cnt = 0;
-        for (int32_t e = 0; e < P; ++e) {
+        for (; e < P; ++e) {
             const KRec32 r = kb32[e];
             const uint32_t t = (uint32_t)r.mx * ux + (uint32_t)r.my * uy + (uint32_t)r.mz * uz;
             const float f = (float)(int32_t)t * 0x1.0p-32f;
@@ -238,10 +320,6 @@ __global__ __launch_bounds__(256) void k_far(Geom g, int32_t P, const double *__
             fx = fmaf(r.ckx, v, fx);
             fy = fmaf(r.cky, v, fy);
             fz = fmaf(r.ckz, v, fz);
-            if (++cnt == 64) {
-                Fx += fx; Fy += fy; Fz += fz;
-                fx = fy = fz = 0.f; cnt = 0;
-            }
         }
         const double qi = -(double)qf[i];
         Fx = qi * (Fx + fx); Fy = qi * (Fy + fy); Fz = qi * (Fz + fz);
@@ -250,34 +328,16 @@ __global__ __launch_bounds__(256) void k_far(Geom g, int32_t P, const double *__
         Ff[i] = Fx;
         Ff[n + i] = Fy;
         Ff[2 * n + i] = Fz;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_finalize(int64_t nnear, const double *__restrict__ epart, int32_t P,
-                                                  const double *__restrict__ ek, double uself, double *__restrict__ E,
-                                                  int32_t *__restrict__ flag) {
-    __shared__ double s1[256], s2[256];
-    double a = 0.0, b = 0.0;
-    for (int64_t i = threadIdx.x; i < nnear; i += 256) a += epart[i];
-    for (int64_t i = threadIdx.x; i < P; i += 256) b += ek[i];
-    s1[threadIdx.x] = a;
-    s2[threadIdx.x] = b;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
-            s1[threadIdx.x] += s1[threadIdx.x + o];
-            s2[threadIdx.x] += s2[threadIdx.x + o];
+        if (kick.on) {
+            // closing half kick of the velocity-Verlet step
+            const double f[3] = {kick.Fn[i] + Fx, kick.Fn[n + i] + Fy, kick.Fn[2 * n + i] + Fz};
+            bool bad = false;
+            for (int d = 0; d < 3; ++d) {
+                bad |= !isfinite(f[d]);
+                kick.v[d * n + i] += kick.hdm * f[d];
+            }
+            if (bad) atomicOr(kick.flag, 1);
         }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const double un = s1[0], us = s2[0];
-        const double tot = un + us - uself;
-        E[0] = un;
-        E[1] = us;
-        E[2] = uself;
-        E[3] = tot;
-        if (!isfinite(tot)) atomicOr(flag, 2);
     }
 }
 
@@ -300,11 +360,6 @@ FarPlan far_plan(int64_t n, int32_t P) {
     return p;
 }
 
-void launch_stage_k(const Geom &g, int32_t P, const int32_t *kseq, const double *kw, double w_rb, int64_t *cursor,
-                    KRec64 *kb64, KRec32 *kb32, double *wk, hipStream_t s) {
-    hipLaunchKernelGGL(k_stage, dim3(1), dim3(256), 0, s, g, P, kseq, kw, w_rb, cursor, kb64, kb32, wk);
-}
-
 void launch_rho(const Geom &g, const FarPlan &fp, int32_t P, bool f64, const double *x, const uint32_t *u,
                 const double *q, const float *qf, const KRec64 *kb64, const KRec32 *kb32, double *partial,
                 hipStream_t s) {
@@ -318,22 +373,20 @@ void launch_rho(const Geom &g, const FarPlan &fp, int32_t P, bool f64, const dou
 }
 
 void launch_rho_reduce(int32_t P, int64_t nblk, const double *partial, const double *wk, KRec64 *kb64,
-                       KRec32 *kb32, double *rho, double *ek, hipStream_t s) {
-    hipLaunchKernelGGL(k_rho_reduce, dim3((unsigned)P), dim3(256), 0, s, P, nblk, partial, wk, kb64, kb32, rho, ek);
+                       KRec32 *kb32, double *rho, double *ek, int64_t nnear, const double *epart, double uself,
+                       double *E, int32_t *flag, uint32_t *counter, hipStream_t s) {
+    hipLaunchKernelGGL(k_rho_reduce, dim3((unsigned)P), dim3(256), 0, s, P, nblk, partial, wk, kb64, kb32, rho, ek,
+                       nnear, epart, uself, E, flag, counter);
 }
 
 void launch_far(const Geom &g, int32_t P, bool f64, const double *x, const uint32_t *u, const double *q,
-                const float *qf, const KRec64 *kb64, const KRec32 *kb32, double *Ff, hipStream_t s) {
+                const float *qf, const KRec64 *kb64, const KRec32 *kb32, double *Ff, const KickArgs &kick,
+                hipStream_t s) {
     dim3 grid(grid_for(g.n, 256)), block(256);
     if (f64)
-        hipLaunchKernelGGL(k_far<true>, grid, block, 0, s, g, P, x, u, q, qf, kb64, kb32, Ff);
+        hipLaunchKernelGGL(k_far<true>, grid, block, 0, s, g, P, x, u, q, qf, kb64, kb32, Ff, kick);
     else
-        hipLaunchKernelGGL(k_far<false>, grid, block, 0, s, g, P, x, u, q, qf, kb64, kb32, Ff);
-}
-
-void launch_finalize(int64_t nnear, const double *epart, int32_t P, const double *ek, double uself, double *E,
-                     int32_t *flag, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, nnear, epart, P, ek, uself, E, flag);
+        hipLaunchKernelGGL(k_far<false>, grid, block, 0, s, g, P, x, u, q, qf, kb64, kb32, Ff, kick);
 }
 
 }  // namespace rbsog

@@ -21,22 +21,39 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
-// Wrap x into [0, L) (x_w = frac(x/L) L), fixed-point coordinate
-// u = min(2^32-1, floor(frac(x/L) 2^32)), cell c_d = (u n_d) >> 32 and the
-// cell histogram.
-__global__ void k_quantise(Geom g, double *__restrict__ x, uint32_t *__restrict__ u,
-                           int32_t *__restrict__ cell_of, int32_t *__restrict__ count) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Optional kick dt/2 and drift (velocity Verlet), then wrap x into [0, L)
+// (x_w = frac(x/L) L), fixed-point coordinate u = min(2^32-1,
+// floor(frac(x/L) 2^32)), cell c_d = (u n_d) >> 32 and the cell histogram.
+// The extra last block stages the k batch of this evaluation.
+__global__ void k_kdq(Geom g, KickArgs kick, StageArgs stage, double *__restrict__ x, uint32_t *__restrict__ u,
+                      int32_t *__restrict__ cell_of, int32_t *__restrict__ count) {
+    if (blockIdx.x == gridDim.x - 1) {
+        stage_batch(g, stage);
+        return;
+    }
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.n) return;
+    const int64_t n = g.n;
+    if (kick.on) {
+        bool bad = false;
+        for (int d = 0; d < 3; ++d) {
+            const double f = kick.Fn[d * n + i] + kick.Ff[d * n + i];
+            bad |= !isfinite(f);
+            const double vd = kick.v[d * n + i] + kick.hdm * f;
+            kick.v[d * n + i] = vd;
+            x[d * n + i] += kick.dt * vd;
+        }
+        if (bad) atomicOr(kick.flag, 1);
+    }
     int64_t c[3];
     for (int d = 0; d < 3; ++d) {
-        double t = x[d * g.n + i] / g.L[d];
+        double t = x[d * n + i] / g.L[d];
         double f = t - floor(t);
         double v = floor(f * kTwo32);
         v = v > kTwo32 - 1.0 ? kTwo32 - 1.0 : v;
         uint32_t ud = (uint32_t)v;
-        u[d * g.n + i] = ud;
-        x[d * g.n + i] = f * g.L[d];
+        u[d * n + i] = ud;
+        x[d * n + i] = f * g.L[d];
         c[d] = (int64_t)(((uint64_t)ud * (uint64_t)g.nc[d]) >> 32);
     }
     int32_t cell = (int32_t)(c[0] + (int64_t)g.nc[0] * (c[1] + (int64_t)g.nc[1] * c[2]));
@@ -122,14 +139,16 @@ __global__ void k_cell_scatter(int64_t n, const int32_t *__restrict__ cell_of, i
     order[t] = (int32_t)i;
 }
 
-// Insertion sort of each cell's ids: makes the order (cell, id) and
-// independent of the scatter's atomic order.
-__global__ void k_cell_sort(int64_t ncell, const int32_t *__restrict__ start, int32_t *__restrict__ order) {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Per cell: insertion sort of its ids (the order becomes (cell, id),
+// independent of the scatter's atomic order) and reset of its histogram
+// count for the next evaluation.
+__global__ void k_cell_sort(int64_t ncell, const int32_t *__restrict__ start, int32_t *__restrict__ order,
+                            int32_t *__restrict__ count) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
-    int32_t lo = start[c], hi = start[c + 1];
+    const int32_t lo = start[c], hi = start[c + 1];
     for (int32_t a = lo + 1; a < hi; ++a) {
-        int32_t v = order[a];
+        const int32_t v = order[a];
         int32_t b = a - 1;
         while (b >= lo && order[b] > v) {
             order[b + 1] = order[b];
@@ -137,40 +156,24 @@ __global__ void k_cell_sort(int64_t ncell, const int32_t *__restrict__ start, in
         }
         order[b + 1] = v;
     }
+    count[c] = 0;
 }
 
+// Gather into cell order: one thread per sorted slot.
 __global__ void k_gather(Geom g, const int32_t *__restrict__ order, const uint32_t *__restrict__ u,
                          const double *__restrict__ x, const double *__restrict__ q, uint32_t *__restrict__ su,
                          double *__restrict__ sx, double *__restrict__ sq, float *__restrict__ sqf, int f64) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= g.n) return;
-    int64_t id = order[t];
-    for (int d = 0; d < 3; ++d) su[d * g.n + t] = u[d * g.n + id];
-    double qi = q[id];
+    const int64_t n = g.n;
+    const int64_t id = order[t];
+    for (int d = 0; d < 3; ++d) su[d * n + t] = u[d * n + id];
+    const double qi = q[id];
     sqf[t] = (float)qi;
     if (f64) {
-        for (int d = 0; d < 3; ++d) sx[d * g.n + t] = x[d * g.n + id];
+        for (int d = 0; d < 3; ++d) sx[d * n + t] = x[d * n + id];
         sq[t] = qi;
     }
-}
-
-__global__ void k_kick(int64_t n, double hdm, double *__restrict__ v, const double *__restrict__ Fn,
-                       const double *__restrict__ Ff, int32_t *__restrict__ flag) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    bool bad = false;
-    for (int d = 0; d < 3; ++d) {
-        double f = Fn[d * n + i] + Ff[d * n + i];
-        bad |= !isfinite(f);
-        v[d * n + i] += hdm * f;
-    }
-    if (bad) atomicOr(flag, 1);
-}
-
-__global__ void k_drift(int64_t n, double dt, double *__restrict__ x, const double *__restrict__ v) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    for (int d = 0; d < 3; ++d) x[d * n + i] += dt * v[d * n + i];
 }
 
 }  // namespace
@@ -179,9 +182,10 @@ void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, p, n, v);
 }
 
-void launch_quantise(const Geom &g, double *x, uint32_t *u, int32_t *cell_of, int32_t *cell_count,
-                     hipStream_t s) {
-    hipLaunchKernelGGL(k_quantise, dim3(grid_for(g.n, kBlock)), dim3(kBlock), 0, s, g, x, u, cell_of, cell_count);
+void launch_kdq(const Geom &g, const KickArgs &kick, const StageArgs &stage, double *x, uint32_t *u,
+                int32_t *cell_of, int32_t *cell_count, hipStream_t s) {
+    hipLaunchKernelGGL(k_kdq, dim3(grid_for(g.n, kBlock) + 1), dim3(kBlock), 0, s, g, kick, stage, x, u, cell_of,
+                       cell_count);
 }
 
 int64_t scan_blocksums_size(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
@@ -199,23 +203,12 @@ void launch_cell_scatter(const Geom &g, const int32_t *cell_of, int32_t *fill, i
     hipLaunchKernelGGL(k_cell_scatter, dim3(grid_for(g.n, kBlock)), dim3(kBlock), 0, s, g.n, cell_of, fill, order);
 }
 
-void launch_cell_sort(int64_t ncell, const int32_t *start, int32_t *order, hipStream_t s) {
-    hipLaunchKernelGGL(k_cell_sort, dim3(grid_for(ncell, kBlock)), dim3(kBlock), 0, s, ncell, start, order);
-}
-
-void launch_gather(const Geom &g, const int32_t *order, const uint32_t *u, const double *x, const double *q,
-                   uint32_t *su, double *sx, double *sq, float *sqf, bool f64, hipStream_t s) {
-    hipLaunchKernelGGL(k_gather, dim3(grid_for(g.n, kBlock)), dim3(kBlock), 0, s, g, order, u, x, q, su, sx, sq,
-                       sqf, (int)f64);
-}
-
-void launch_kick(int64_t n, double hdm, double *v, const double *Fn, const double *Ff, int32_t *flag,
-                 hipStream_t s) {
-    hipLaunchKernelGGL(k_kick, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, n, hdm, v, Fn, Ff, flag);
-}
-
-void launch_drift(int64_t n, double dt, double *x, const double *v, hipStream_t s) {
-    hipLaunchKernelGGL(k_drift, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, n, dt, x, v);
+void launch_sort_gather(const Geom &g, int64_t ncell, const int32_t *start, int32_t *order, int32_t *cell_count,
+                        const uint32_t *u, const double *x, const double *q, uint32_t *su, double *sx, double *sq,
+                        float *sqf, bool f64, hipStream_t s) {
+    hipLaunchKernelGGL(k_cell_sort, dim3(grid_for(ncell, kBlock)), dim3(kBlock), 0, s, ncell, start, order, cell_count);
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(g.n, kBlock)), dim3(kBlock), 0, s, g, order, u, x, q, su, sx, sq, sqf,
+                       (int)f64);
 }
 
 }  // namespace rbsog

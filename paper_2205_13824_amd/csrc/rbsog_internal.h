@@ -38,44 +38,106 @@ struct Geom {
     float band_lo_f, band_hi_f;  // same for the FP32 fast test
     int32_t nc[3];
     int32_t reach[3];            // 1 if the stencil spans -1..1 in that dimension, 0 otherwise
-    int32_t ngauss;              // M + 1
+    int32_t nexp;                // Gaussians l < nexp are evaluated with an exponential each
+    int32_t ntail64, ntail32;    // coefficients of the tail polynomials in r^2 (0: no tail)
 };
+
+// Degrees of the polynomials in x = r^2 that replace the Gaussians with
+// r_c^2 / s_l^2 <= kTailTau (Taylor series of exp(-x/s_l^2) summed over
+// those l): truncation below 6e-18 (FP64) and 3e-9 (FP32) of the tail.
+constexpr double kTailTau = 0.05;
+constexpr int kTailDeg64 = 8;
+constexpr int kTailDeg32 = 4;
 
 // Device-resident coefficients of the split.
 struct SogDev {
-    const double *w64;    // omega_l
+    const double *w64;    // omega_l, l < nexp
     const double *a64;    // 1 / s_l^2
     const double *c64;    // 2 omega_l / s_l^2
+    const double *pt64;   // potential tail: sum_l omega_l exp(-x/s_l^2) = sum_n pt64[n] x^n
+    const double *ft64;   // force tail: sum_l 2 omega_l/s_l^2 exp(-x/s_l^2) = sum_n ft64[n] x^n
     const float *w32;     // omega_l
     const float *a32;     // log2(e) / s_l^2
     const float *c32;     // 2 omega_l / s_l^2
+    const float *pt32;    // tails in FP32
+    const float *ft32;
 };
+
+// Arguments of the k-batch staging (Algorithm 1: the next P frequencies of the
+// pre-sampled sequence, in order) and of the velocity-Verlet half kicks.
+struct StageArgs {
+    int32_t P;
+    const int32_t *kseq;  // sequence, 3 int32 per vector
+    const double *kw;     // per-vector weights, or null for the random-batch weight
+    double w_rb;          // S pi^{3/2} / (P V)
+    int64_t *cursor;      // device cursor (vectors consumed)
+    KRec64 *kb64;
+    KRec32 *kb32;
+    double *wk;
+};
+struct KickArgs {
+    int32_t on;      // 0: no kick
+    double hdm;      // dt / (2 m)
+    double dt;       // drift step (kick-drift kernel only)
+    double *v;
+    const double *Fn, *Ff;
+    int32_t *flag;   // bit 0: non-finite force
+};
+
+// Stage the current batch: per-k records for both precisions and the weights,
+// then advance the cursor.  Called by one whole block.
+__device__ inline void stage_batch(const Geom &g, const StageArgs &a) {
+    constexpr double kTwoPi = 6.283185307179586476925286766559;
+    const int64_t base = *a.cursor;
+    for (int32_t k = threadIdx.x; k < a.P; k += blockDim.x) {
+        const int64_t e = base + k;
+        const int32_t mx = a.kseq[3 * e], my = a.kseq[3 * e + 1], mz = a.kseq[3 * e + 2];
+        const double w = a.kw ? a.kw[e] : a.w_rb;
+        const double kx = kTwoPi * g.invL[0] * mx, ky = kTwoPi * g.invL[1] * my, kz = kTwoPi * g.invL[2] * mz;
+        KRec64 r;
+        r.mx = mx; r.my = my; r.mz = mz;
+        r.ckx = w * kx; r.cky = w * ky; r.ckz = w * kz;
+        r.re = 0.0; r.im = 0.0;
+        a.kb64[k] = r;
+        KRec32 h;
+        h.mx = mx; h.my = my; h.mz = mz;
+        h.ckx = (float)r.ckx; h.cky = (float)r.cky; h.ckz = (float)r.ckz;
+        h.re = 0.f; h.im = 0.f;
+        a.kb32[k] = h;
+        a.wk[k] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *a.cursor = base + a.P;
+}
 
 // ---- kernel launchers (kernels_md.hip) --------------------------------------
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
-void launch_quantise(const Geom &g, double *x, uint32_t *u, int32_t *cell_of, int32_t *cell_count,
-                     hipStream_t s);
+// kick dt/2 + drift (if kick.on), wrap, quantise, cell histogram; the last
+// block stages the k batch
+void launch_kdq(const Geom &g, const KickArgs &kick, const StageArgs &stage, double *x, uint32_t *u,
+                int32_t *cell_of, int32_t *cell_count, hipStream_t s);
 void launch_scan(const int32_t *in, int32_t *out_excl, int32_t *fill_copy, int64_t n, int32_t *blocksums,
                  hipStream_t s);
 int64_t scan_blocksums_size(int64_t n);
 void launch_cell_scatter(const Geom &g, const int32_t *cell_of, int32_t *fill, int32_t *order, hipStream_t s);
-void launch_cell_sort(int64_t ncell, const int32_t *start, int32_t *order, hipStream_t s);
-void launch_gather(const Geom &g, const int32_t *order, const uint32_t *u, const double *x, const double *q,
-                   uint32_t *su, double *sx, double *sq, float *sqf, bool f64, hipStream_t s);
-void launch_kick(int64_t n, double half_dt_over_m, double *v, const double *Fn, const double *Ff, int32_t *flag,
-                 hipStream_t s);
-void launch_drift(int64_t n, double dt, double *x, const double *v, hipStream_t s);
+// per cell: id sort of its segment and reset of its histogram count; then gather into cell order
+void launch_sort_gather(const Geom &g, int64_t ncell, const int32_t *start, int32_t *order, int32_t *cell_count,
+                        const uint32_t *u, const double *x, const double *q, uint32_t *su, double *sx, double *sq,
+                        float *sqf, bool f64, hipStream_t s);
 
 // ---- near part (kernels_near.hip) ------------------------------------------
-int64_t near_blocks(int64_t n);
-void launch_near(const Geom &g, const SogDev &c, bool f64, const int32_t *start, const int32_t *order,
-                 const uint32_t *su, const double *sx, const double *sq, const float *sqf, double *Fn,
-                 double *epart, hipStream_t s);
-void launch_neighbor_count(const Geom &g, bool f64, const int32_t *start, const int32_t *order,
-                           const uint32_t *su, const double *sx, int64_t *counts, hipStream_t s);
-void launch_neighbor_fill(const Geom &g, bool f64, const int32_t *start, const int32_t *order,
-                          const uint32_t *su, const double *sx, const int64_t *row_ptr, int32_t *cols,
-                          hipStream_t s);
+struct NearPlan {
+    int32_t nblk;             // blocks (a multiple of 8)
+    int64_t cells_per_block;  // contiguous cells per block
+};
+NearPlan near_plan(int64_t ncell);
+void launch_near(const Geom &g, const SogDev &c, bool f64, const NearPlan &np, int64_t ncell, const int32_t *start,
+                 const int32_t *order, const uint32_t *su, const double *sx, const double *sq, const float *sqf,
+                 double *Fn, double *epart, hipStream_t s);
+void launch_neighbor_count(const Geom &g, const int32_t *start, const int32_t *order, const uint32_t *su,
+                           int64_t *counts, hipStream_t s);
+void launch_neighbor_fill(const Geom &g, const int32_t *start, const int32_t *order, const uint32_t *su,
+                          const int64_t *row_ptr, int32_t *cols, hipStream_t s);
 
 // ---- far part (kernels_far.hip) --------------------------------------------
 struct FarPlan {
@@ -86,16 +148,17 @@ struct FarPlan {
     int64_t kblk;  // blocks along the k axis
 };
 FarPlan far_plan(int64_t n, int32_t P);
-void launch_stage_k(const Geom &g, int32_t P, const int32_t *kseq, const double *kw, double w_rb,
-                    int64_t *cursor, KRec64 *kb64, KRec32 *kb32, double *wk, hipStream_t s);
 void launch_rho(const Geom &g, const FarPlan &fp, int32_t P, bool f64, const double *x, const uint32_t *u,
                 const double *q, const float *qf, const KRec64 *kb64, const KRec32 *kb32, double *partial,
                 hipStream_t s);
+// rho_e, its records and per-k energies; the last block to finish also sums
+// the energies (U_N from the near partials, U*, U_self, U) and re-arms counter
 void launch_rho_reduce(int32_t P, int64_t nblk, const double *partial, const double *wk, KRec64 *kb64,
-                       KRec32 *kb32, double *rho, double *ek, hipStream_t s);
+                       KRec32 *kb32, double *rho, double *ek, int64_t nnear, const double *epart, double uself,
+                       double *E, int32_t *flag, uint32_t *counter, hipStream_t s);
+// far force; with kick.on the closing half kick v += dt/(2m) (F_N + F*) follows
 void launch_far(const Geom &g, int32_t P, bool f64, const double *x, const uint32_t *u, const double *q,
-                const float *qf, const KRec64 *kb64, const KRec32 *kb32, double *Ff, hipStream_t s);
-void launch_finalize(int64_t nnear, const double *epart, int32_t P, const double *ek, double uself, double *E,
-                     int32_t *flag, hipStream_t s);
+                const float *qf, const KRec64 *kb64, const KRec32 *kb32, double *Ff, const KickArgs &kick,
+                hipStream_t s);
 
 }  // namespace rbsog

@@ -41,7 +41,7 @@ class rbsog_sog(ctypes.Structure):
 
 class rbsog_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
-                ("neutral_tol", ctypes.c_double), ("mass", ctypes.c_double)]
+                ("neutral_tol", ctypes.c_double), ("mass", ctypes.c_double), ("graphs", ctypes.c_int32)]
 
 
 class rbsog_info_t(ctypes.Structure):
@@ -120,13 +120,14 @@ def rbsog_default_opts() -> rbsog_opts:
 
 
 def rbsog_init(pos, q, box, sog: rbsog_sog, rc: float, P: int, seed: int, precision: int = RBSOG_FP64,
-               device: int = 0, stream: int | None = None, neutral_tol: float = 1e-10, mass: float = 1.0):
+               device: int = 0, stream: int | None = None, neutral_tol: float = 1e-10, mass: float = 1.0,
+               graphs: bool = True):
     q = _f64(q, (-1,))
     n = q.size
     pos = _f64(pos, (n, 3))
     box = _f64(box, (3,))
     o = rbsog_default_opts()
-    o.precision, o.device, o.neutral_tol, o.mass = precision, device, neutral_tol, mass
+    o.precision, o.device, o.neutral_tol, o.mass, o.graphs = precision, device, neutral_tol, mass, int(graphs)
     o.stream = stream
     ctx = ctypes.c_void_p()
     _check(lib().rbsog_init(ctypes.byref(ctx), n, _ptr(pos), _ptr(q), _ptr(box), ctypes.byref(sog), float(rc),

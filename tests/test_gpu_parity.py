@@ -242,3 +242,29 @@ def test_c2_full_size_sampled(orc, c2, prec, tol):
     # properties at full size: Newton's third law and zero total far force
     assert np.abs(Fn.sum(0)).max() < (1e-9 if prec == R.RBSOG_FP64 else 1e-3) * np.abs(Fn).max() * math.sqrt(n)
     assert np.abs(Ff.sum(0)).max() < (1e-9 if prec == R.RBSOG_FP64 else 1e-3) * np.abs(Ff).max() * math.sqrt(n)
+
+
+@pytest.mark.parametrize("prec", [R.RBSOG_FP64, R.RBSOG_FP32C])
+def test_graph_replay_equals_eager(orc, prec):
+    # rbsog_step replays one captured graph per step; interleave replays with
+    # host reads (synchronisations) and compare with eager launches bit for bit
+    n, L = 500, 12.0
+    pos, q, box = W.ions_rsa(n, n / L ** 3, 1.0, 31)
+    v0 = W.maxwellian(n, 1.0, 32)
+    out = []
+    for graphs in (False, True):
+        say(f"[gpu] graph replay check prec={prec} graphs={graphs}")
+        sysm = R.System(pos, q, box, 3.0, 50, seed=3, precision=prec, graphs=graphs)
+        sysm.sample_k(40)
+        R.rbsog_set_velocities(sysm.ctx, v0)
+        states = []
+        for chunk in (5, 7, 3, 9):
+            sysm.step(chunk, 1e-3)
+            states.append(R.rbsog_get_state(sysm.ctx, n))
+        states.append(tuple(sysm.components()))
+        states.append((R.rbsog_get_energy(sysm.ctx),))
+        out.append(states)
+        sysm.close()
+    for a, b in zip(*out):
+        for x, y in zip(a, b):
+            assert (x == y).all()
