@@ -123,9 +123,8 @@ struct rbsog_ctx {
     double *wk = nullptr, *rho = nullptr, *ek = nullptr, *partial = nullptr, *epart = nullptr, *E = nullptr;
     int32_t *flag = nullptr;
     uint32_t *counter = nullptr;
-    double *sog64 = nullptr;
-    float *sog32 = nullptr;
-    SogDev sogdev{};
+    SplitCoef64 co64{};
+    SplitCoef32 co32{};
     // graph of one velocity-Verlet step
     bool use_graphs = true;
     hipGraph_t graph = nullptr;
@@ -385,7 +384,7 @@ rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt) {
                            c->sqf, f64, s);
     }));
     TRY(timed(c, K_NEAR, [&] {
-        launch_near(g, c->sogdev, f64, c->nplan, c->ncell, c->cell_start, c->order, c->su, c->sx, c->sq, c->sqf, c->Fn,
+        launch_near(g, c->co64, c->co32, f64, c->nplan, c->ncell, c->cell_start, c->order, c->su, c->sx, c->sq, c->sqf, c->Fn,
                     c->epart, s);
     }));
     TRY(timed(c, K_RHO, [&] {
@@ -571,21 +570,25 @@ rbsog_status rbsog_init(rbsog_ctx **out, int64_t n, const double *pos, const dou
     }
     g.rc2 = rc * rc;
     const double d64 = 32.0 * hmax / rc + 1e-12;
-    const double d32 = d64 + 4e-6;
+    // the FP32 test runs on cell-relative float coordinates (cells up to 3 r_c
+    // wide): its r^2 is within 2e-5 relative of the exact value
+    const double d32 = d64 + 3e-5;
     g.band_lo = g.rc2 * (1.0 - d64);
     g.band_hi = g.rc2 * (1.0 + d64);
     g.band_lo_f = (float)(g.rc2 * (1.0 - d32));
     g.band_hi_f = (float)(g.rc2 * (1.0 + d32));
     // Gaussians wide enough that exp(-x/s_l^2) is a short Taylor series over
     // x = r^2 <= rc^2 form the tail; s_l grows with l, so they are l >= nexp.
-    g.nexp = c->M + 1;
-    for (int l = 0; l <= c->M; ++l)
-        if (rc * rc / (c->s[l] * c->s[l]) <= kTailTau) {
-            g.nexp = l;
-            break;
-        }
-    g.ntail64 = g.nexp <= c->M ? kTailDeg64 + 1 : 0;
-    g.ntail32 = g.nexp <= c->M ? kTailDeg32 + 1 : 0;
+    auto first_wide = [&](double tau) {
+        for (int l = 0; l <= c->M; ++l)
+            if (rc * rc / (c->s[l] * c->s[l]) <= tau) return l;
+        return c->M + 1;
+    };
+    const int nexp64 = first_wide(kTailTau64), nexp32 = first_wide(kTailTau32);
+    if (nexp64 > kMaxExp) {
+        delete c;
+        return fail(nullptr, RBSOG_E_SOG, "more than 24 Gaussians narrower than r_c / sqrt(0.05)");
+    }
     c->ncell = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
     if (c->ncell >= (int64_t)INT32_MAX) {
         delete c;
@@ -645,50 +648,49 @@ rbsog_status rbsog_init(rbsog_ctx **out, int64_t n, const double *pos, const dou
     ALLOC(E, 4);
     ALLOC(flag, 1);
     ALLOC(counter, 1);
-    const int G = c->M + 1, T64 = kTailDeg64 + 1, T32 = kTailDeg32 + 1;
-    ALLOC(sog64, 3 * (int64_t)G + 2 * T64);
-    ALLOC(sog32, 3 * (int64_t)G + 2 * T32);
 #undef ALLOC
     {
-        std::vector<double> h64(3 * G + 2 * T64, 0.0);
-        std::vector<float> h32(3 * G + 2 * T32, 0.f);
-        for (int l = 0; l < G; ++l) {
-            const double is2 = 1.0 / (c->s[l] * c->s[l]);
-            h64[l] = c->omega[l];
-            h64[G + l] = is2;
-            h64[2 * G + l] = 2.0 * c->omega[l] * is2;
-            h32[l] = (float)c->omega[l];
-            h32[G + l] = (float)(is2 / std::log(2.0));
-            h32[2 * G + l] = (float)(2.0 * c->omega[l] * is2);
-        }
-        // tail polynomials: sum_{l >= nexp} omega_l e^{-x a_l} = sum_k (-1)^k/k! (sum_l omega_l a_l^k) x^k
+        // explicit Gaussians and the tail polynomials:
+        // sum_{l >= nexp} omega_l e^{-x a_l} = sum_k (-1)^k/k! (sum_l omega_l a_l^k) x^k
         // and the force weights 2 omega_l a_l e^{-x a_l} likewise (a_l = 1/s_l^2)
-        double fact = 1.0;
-        for (int k = 0; k < T64; ++k) {
-            if (k > 0) fact *= k;
-            double sp = 0.0, sf = 0.0;
-            for (int l = g.nexp; l < G; ++l) {
+        const int G = c->M + 1;
+        auto tail = [&](int l0, int k) {
+            double sp = 0.0, sf = 0.0, fact = 1.0;
+            for (int i = 2; i <= k; ++i) fact *= i;
+            for (int l = l0; l < G; ++l) {
                 const double a = 1.0 / (c->s[l] * c->s[l]);
                 sp += c->omega[l] * std::pow(a, k);
                 sf += 2.0 * c->omega[l] * std::pow(a, k + 1);
             }
             const double sgn = (k & 1) ? -1.0 : 1.0;
-            h64[3 * G + k] = sgn * sp / fact;
-            h64[3 * G + T64 + k] = sgn * sf / fact;
-            if (k < T32) {
-                h32[3 * G + k] = (float)(sgn * sp / fact);
-                h32[3 * G + T32 + k] = (float)(sgn * sf / fact);
-            }
+            return std::make_pair(sgn * sp / fact, sgn * sf / fact);
+        };
+        SplitCoef64 &h64 = c->co64;
+        SplitCoef32 &h32 = c->co32;
+        h64.nexp = nexp64;
+        h32.nexp = nexp32;
+        for (int l = 0; l < nexp64; ++l) {
+            const double is2 = 1.0 / (c->s[l] * c->s[l]);
+            h64.a[l] = is2;
+            h64.cw[l] = 2.0 * c->omega[l] * is2;
+            h64.w[l] = c->omega[l];
         }
-        if (hipMemcpy(c->sog64, h64.data(), h64.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(c->sog32, h32.data(), h32.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
-            fail(c, RBSOG_E_DEVICE, "coefficient upload failed");
-            return bail(RBSOG_E_DEVICE);
+        for (int l = 0; l < nexp32; ++l) {
+            const double is2 = 1.0 / (c->s[l] * c->s[l]);
+            h32.a[l] = (float)(is2 / std::log(2.0));
+            h32.cw[l] = (float)(2.0 * c->omega[l] * is2);
+            h32.w[l] = (float)c->omega[l];
         }
-        c->sogdev = SogDev{c->sog64,          c->sog64 + G,          c->sog64 + 2 * G,
-                           c->sog64 + 3 * G,  c->sog64 + 3 * G + T64, c->sog32,
-                           c->sog32 + G,      c->sog32 + 2 * G,      c->sog32 + 3 * G,
-                           c->sog32 + 3 * G + T32};
+        for (int k = 0; k <= kTailDeg64; ++k) {
+            const auto pf = tail(nexp64, k);
+            h64.pt[k] = pf.first;
+            h64.ft[k] = pf.second;
+        }
+        for (int k = 0; k <= kTailDeg32; ++k) {
+            const auto pf = tail(nexp32, k);
+            h32.pt[k] = (float)pf.first;
+            h32.ft[k] = (float)pf.second;
+        }
     }
     {
         std::vector<double> qd(q, q + n);

@@ -102,6 +102,9 @@ __device__ double block_sum(double v) {
     return s;
 }
 
+// Values the wave holds in common (loaded or broadcast): keep them scalar.
+__device__ __forceinline__ int32_t rfl(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -118,111 +121,89 @@ __device__ __forceinline__ double bcast64(double v, int src) {
 
 constexpr int kNW = 4;        // waves per block
 constexpr int kQueue = 128;   // pair queue entries per wave (>= 2 x 64)
-constexpr int kExpMax = 12;   // explicit Gaussians held in registers
+constexpr uint32_t kNoCand = 0xfffffffeu;  // candidate slot past the end of the list
 
 template <bool F64>
 struct NearLds {
     using R = typename std::conditional<F64, double, float>::type;
     static constexpr int HC = F64 ? 64 : 128;   // home particles staged per batch
-    static constexpr int CAP = 128;             // candidates staged per pass
     static constexpr int XH = F64 ? HC : 1;
-    static constexpr int XC = F64 ? CAP : 1;
     uint4 hu[HC];          // home u_x, u_y, u_z, global sorted index
     R hq[HC];
     double hx[3][XH];
     R hf[3][HC];           // force accumulators of the home batch
-    uint4 cu[CAP];         // candidate u_x, u_y, u_z, global sorted index
-    R cq[CAP];
-    double cx[3][XC];
-    typename std::conditional<F64, double4, float4>::type qd[kQueue];  // queued pairs: x_j - x_i, q_i q_j
-    uint32_t qs[kQueue];   // home slot of the queued pair
-};
-
-// Split coefficients held in registers (uniform): explicit Gaussians l < nexp
-// and the tail polynomials.
-template <bool F64>
-struct NearCoef {
-    using R = typename std::conditional<F64, double, float>::type;
-    static constexpr int NT = (F64 ? kTailDeg64 : kTailDeg32) + 1;
-    R a[kExpMax], cw[kExpMax], w[kExpMax];
-    R pt[NT], ft[NT];
-    int nexp, ntail;
+    uint2 q[kQueue];       // queued pairs: (home slot, candidate sorted index)
 };
 
 template <bool F64>
-__device__ __forceinline__ void load_coef(const Geom &g, const SogDev &c, NearCoef<F64> &k) {
-    k.nexp = g.nexp < kExpMax ? g.nexp : kExpMax;
-    k.ntail = F64 ? g.ntail64 : g.ntail32;
-#pragma unroll
-    for (int l = 0; l < kExpMax; ++l) {
-        const bool on = l < k.nexp;
-        if constexpr (F64) {
-            k.a[l] = on ? c.a64[l] : 0.0; k.cw[l] = on ? c.c64[l] : 0.0; k.w[l] = on ? c.w64[l] : 0.0;
-        } else {
-            k.a[l] = on ? c.a32[l] : 0.f; k.cw[l] = on ? c.c32[l] : 0.f; k.w[l] = on ? c.w32[l] : 0.f;
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < NearCoef<F64>::NT; ++t) {
-        const bool on = t < k.ntail;
-        if constexpr (F64) {
-            k.pt[t] = on ? c.pt64[t] : 0.0; k.ft[t] = on ? c.ft64[t] : 0.0;
-        } else {
-            k.pt[t] = on ? c.pt32[t] : 0.f; k.ft[t] = on ? c.ft32[t] : 0.f;
-        }
-    }
-}
+struct CoefOf { using type = SplitCoef32; };
+template <>
+struct CoefOf<true> { using type = SplitCoef64; };
 
-// Evaluate the first `count` queued pairs, one per lane, and add their forces
-// to the home accumulators.  Entries of one home are mostly contiguous in the
-// queue (homes are tested one after another), so the forces are summed by a
-// segmented scan across the wave and the last lane of each segment adds the
-// total.
+// Evaluate the first `count` queued pairs, one per lane.  The test admitted
+// every pair with an approximate r^2 below the upper band edge; here the pair
+// rule is applied: the fixed-point r^2 in FP32 decides below the lower band
+// edge, the exact FP64 rule inside the band (rare).  Then the exact
+// displacement (fixed point for FP32C, wrapped FP64 coordinates for FP64), the
+// pair force and energy.  Entries of one home are contiguous within one
+// candidate pass, so forces are summed by a segmented scan across the wave
+// and the last lane of each segment adds the total to the home accumulator.
 template <bool F64>
-__device__ __forceinline__ void eval_batch(const Geom &g, const SogDev &c, const NearCoef<F64> &k, NearLds<F64> &L,
-                                           int lane, int count, double &e) {
+__device__ __forceinline__ void eval_batch(const Geom &g, const typename CoefOf<F64>::type &co, NearLds<F64> &L,
+                                           const uint32_t *__restrict__ su, const double *__restrict__ sx,
+                                           const double *__restrict__ sq, const float *__restrict__ sqf, int lane,
+                                           int count, double &e) {
     using R = typename NearLds<F64>::R;
-    const bool act = lane < count;
+    constexpr int NT = (F64 ? kTailDeg64 : kTailDeg32) + 1;
+    const int64_t n = g.n;
     R fx = 0, fy = 0, fz = 0;
     int slot = -1;
-    if (act) {
-        const auto qe = L.qd[lane];
-        const R dx = qe.x, dy = qe.y, dz = qe.z, qq = qe.w;
-        slot = (int)L.qs[lane];
-        const R r2 = dx * dx + dy * dy + dz * dz;
-        R rinv, gs = 0, ph = 0;
-        if constexpr (F64) rinv = rsqrt(r2);
-        else rinv = __builtin_amdgcn_rsqf(r2);
-#pragma unroll
-        for (int t = NearCoef<F64>::NT - 1; t >= 0; --t) {
-            if constexpr (F64) { gs = fma(gs, r2, k.ft[t]); ph = fma(ph, r2, k.pt[t]); }
-            else { gs = fmaf(gs, r2, k.ft[t]); ph = fmaf(ph, r2, k.pt[t]); }
-        }
-#pragma unroll
-        for (int l = 0; l < kExpMax; ++l) {
-            if (l < k.nexp) {
-                R ex;
-                if constexpr (F64) ex = exp(-r2 * k.a[l]);
-                else ex = __builtin_amdgcn_exp2f(-r2 * k.a[l]);
-                gs += k.cw[l] * ex;
-                ph += k.w[l] * ex;
-            }
-        }
-        for (int l = kExpMax; l < g.nexp; ++l) {
+    if (lane < count) {
+        const uint2 qe = L.q[lane];
+        slot = (int)qe.x;
+        const uint32_t j = qe.y;
+        const uint4 h = L.hu[slot];
+        const uint32_t dux = su[j] - h.x, duy = su[n + j] - h.y, duz = su[2 * n + j] - h.z;
+        const float ex_ = (float)(int32_t)dux * g.hf[0];
+        const float ey_ = (float)(int32_t)duy * g.hf[1];
+        const float ez_ = (float)(int32_t)duz * g.hf[2];
+        const float r2f = ex_ * ex_ + ey_ * ey_ + ez_ * ez_;
+        bool in = r2f <= g.band_lo_f;
+        if (!in) in = exact_in(g, dux, duy, duz);
+        if (in) {
+            R dx, dy, dz, qq;
             if constexpr (F64) {
-                const double ex = exp(-r2 * c.a64[l]);
-                gs += c.c64[l] * ex; ph += c.w64[l] * ex;
+                dx = mi64(sx[j] - L.hx[0][slot], g.L[0], g.invL[0]);
+                dy = mi64(sx[n + j] - L.hx[1][slot], g.L[1], g.invL[1]);
+                dz = mi64(sx[2 * n + j] - L.hx[2][slot], g.L[2], g.invL[2]);
+                qq = L.hq[slot] * sq[j];
             } else {
-                const float ex = __builtin_amdgcn_exp2f(-r2 * c.a32[l]);
-                gs += c.c32[l] * ex; ph += c.w32[l] * ex;
+                dx = ex_; dy = ey_; dz = ez_;
+                qq = L.hq[slot] * sqf[j];
             }
+            const R r2 = F64 ? dx * dx + dy * dy + dz * dz : r2f;
+            R rinv, gs = 0, ph = 0;
+            if constexpr (F64) rinv = rsqrt(r2);
+            else rinv = __builtin_amdgcn_rsqf(r2);
+#pragma unroll
+            for (int t = NT - 1; t >= 0; --t) {
+                if constexpr (F64) { gs = fma(gs, r2, co.ft[t]); ph = fma(ph, r2, co.pt[t]); }
+                else { gs = fmaf(gs, r2, co.ft[t]); ph = fmaf(ph, r2, co.pt[t]); }
+            }
+            for (int l = 0; l < co.nexp; ++l) {
+                R ex;
+                if constexpr (F64) ex = exp(-r2 * co.a[l]);
+                else ex = __builtin_amdgcn_exp2f(-r2 * co.a[l]);
+                gs += co.cw[l] * ex;
+                ph += co.w[l] * ex;
+            }
+            const R coef = qq * (rinv * rinv * rinv - gs);
+            // force on the home along r_i - r_j = -(dx, dy, dz)
+            fx = -coef * dx;
+            fy = -coef * dy;
+            fz = -coef * dz;
+            e += 0.5 * (double)(qq * (rinv - ph));
         }
-        const R coef = qq * (rinv * rinv * rinv - gs);
-        // force on the home along r_i - r_j = -(dx, dy, dz)
-        fx = -coef * dx;
-        fy = -coef * dy;
-        fz = -coef * dz;
-        e += 0.5 * (double)(qq * (rinv - ph));
     }
     const int prev = __shfl_up(slot, 1, 64);
     const bool head = lane == 0 || slot != prev;
@@ -233,10 +214,9 @@ __device__ __forceinline__ void eval_batch(const Geom &g, const SogDev &c, const
         const R ux = __shfl_up(fx, off, 64), uy = __shfl_up(fy, off, 64), uz = __shfl_up(fz, off, 64);
         if (lane - off >= sstart) { fx += ux; fy += uy; fz += uz; }
     }
-    const bool tail = act && (lane == count - 1 || (lane < 63 && ((H >> (lane + 1)) & 1ull)));
-    // a home's entries are contiguous within one candidate pass, but a batch
-    // can span two passes, so segment totals are still added atomically
-    // (almost always one lane per home)
+    // a batch can span two candidate passes of one home, so segment totals
+    // are added atomically (almost always one lane per home)
+    const bool tail = lane < count && (lane == count - 1 || (lane < 63 && ((H >> (lane + 1)) & 1ull)));
     if (tail) {
         atomicAdd(&L.hf[0][slot], fx);
         atomicAdd(&L.hf[1][slot], fy);
@@ -245,7 +225,7 @@ __device__ __forceinline__ void eval_batch(const Geom &g, const SogDev &c, const
 }
 
 template <bool F64>
-__global__ __launch_bounds__(64 * kNW) void k_near(Geom g, SogDev c, int64_t ncell, int64_t cells_per_block,
+__global__ __launch_bounds__(64 * kNW) void k_near(Geom g, typename CoefOf<F64>::type co, int64_t ncell, int64_t cells_per_block,
                                                    int32_t nblk, const int32_t *__restrict__ start,
                                                    const int32_t *__restrict__ order, const uint32_t *__restrict__ su,
                                                    const double *__restrict__ sx, const double *__restrict__ sq,
@@ -253,13 +233,12 @@ __global__ __launch_bounds__(64 * kNW) void k_near(Geom g, SogDev c, int64_t nce
                                                    double *__restrict__ epart) {
     using Lds = NearLds<F64>;
     using R = typename Lds::R;
+    constexpr int S = 2;  // candidate slots per lane and pass
     __shared__ Lds lds[kNW];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     Lds &L = lds[wave];
     const int64_t n = g.n;
-    NearCoef<F64> K;
-    load_coef<F64>(g, c, K);
     // blocks are dealt to the 8 XCDs round robin: block b (on XCD b % 8) takes
     // chunk (b % 8) * (nblk / 8) + b / 8, so each XCD sweeps one slab of cells;
     // within the chunk each wave owns a contiguous run of cells
@@ -272,20 +251,21 @@ __global__ __launch_bounds__(64 * kNW) void k_near(Geom g, SogDev c, int64_t nce
     const int64_t rb = ra + per < c1 ? ra + per : c1;
     double e = 0.0;
     int qn = 0;
-    int32_t t = ra < rb ? start[ra] : 0;
-    const int32_t t_hi = ra < rb ? start[rb] : 0;
+    int32_t t = ra < rb ? rfl(start[ra]) : 0;
+    const int32_t t_hi = ra < rb ? rfl(start[rb]) : 0;
     int64_t cur = ra;  // cell containing home t
+    const bool rel = g.nc[0] >= 4 && g.nc[1] >= 4 && g.nc[2] >= 4;
     while (t < t_hi) {
+        // stage a batch of up to HC consecutive homes (all loads first)
         const int32_t t_end = t + Lds::HC < t_hi ? t + Lds::HC : t_hi;
         const int H = t_end - t;
         {
-            // all loads of the batch first, then the LDS stores (one round trip)
-            constexpr int S = Lds::HC / 64;
-            uint32_t vx[S], vy[S], vz[S];
-            R vq[S];
-            double wx[S], wy[S], wz[S];
+            constexpr int SH = Lds::HC / 64;
+            uint32_t vx[SH], vy[SH], vz[SH];
+            R vq[SH];
+            double wx[SH], wy[SH], wz[SH];
 #pragma unroll
-            for (int s2 = 0; s2 < S; ++s2) {
+            for (int s2 = 0; s2 < SH; ++s2) {
                 const int k = s2 * 64 + lane;
                 if (k < H) {
                     const int64_t tt = t + k;
@@ -299,7 +279,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near(Geom g, SogDev c, int64_t nce
                 }
             }
 #pragma unroll
-            for (int s2 = 0; s2 < S; ++s2) {
+            for (int s2 = 0; s2 < SH; ++s2) {
                 const int k = s2 * 64 + lane;
                 if (k < H) {
                     L.hu[k] = make_uint4(vx[s2], vy[s2], vz[s2], (uint32_t)(t + k));
@@ -309,10 +289,14 @@ __global__ __launch_bounds__(64 * kNW) void k_near(Geom g, SogDev c, int64_t nce
                 }
             }
         }
-        while (start[cur + 1] <= t) ++cur;
-        for (int64_t cell = cur; cell < rb && start[cell] < t_end; ++cell) {
-            const int32_t hs = start[cell] > t ? start[cell] : t;
-            const int32_t he = start[cell + 1] < t_end ? start[cell + 1] : t_end;
+        wave_sync();
+        while (rfl(start[cur + 1]) <= t) ++cur;
+        for (int64_t cell = cur; cell < rb; ++cell) {
+            const int32_t cs = rfl(start[cell]);
+            if (cs >= t_end) break;
+            const int32_t ce = rfl(start[cell + 1]);
+            const int32_t hs = cs > t ? cs : t;
+            const int32_t he = ce < t_end ? ce : t_end;
             if (hs >= he) continue;
             const int i0 = hs - t, i1 = he - t;
             const uint32_t cu32 = (uint32_t)cell;
@@ -332,141 +316,117 @@ __global__ __launch_bounds__(64 * kNW) void k_near(Geom g, SogDev c, int64_t nce
                 if (lane >= o) incl += v;
             }
             const int32_t excl = incl - len;
-            const int32_t C = __shfl(incl, kRanges - 1, 64);
-            for (int32_t cb = 0; cb < C; cb += Lds::CAP) {
-                const int Cc = C - cb < Lds::CAP ? C - cb : Lds::CAP;
-                // stage: each lane finds the range of its slots by counting range
-                // ends (broadcast with readlane), then every load of the pass is
-                // in flight at once, then the LDS stores
-                wave_sync();
-                {
-                    constexpr int S = Lds::CAP / 64;
-                    int rr[S];
+            const int32_t C = __builtin_amdgcn_readlane(incl, kRanges - 1);
+            // origin of the cell-relative float coordinates used by the test:
+            // the first home of the cell
+            const uint4 o4 = L.hu[i0];
+            const uint32_t ox = (uint32_t)rfl((int)o4.x), oy = (uint32_t)rfl((int)o4.y),
+                           oz = (uint32_t)rfl((int)o4.z);
+            for (int32_t cb = 0; cb < C; cb += 64 * S) {
+                // candidates of this pass in registers: each lane finds the range
+                // of its slots by counting range ends (broadcast with readlane)
+                int rr[S];
 #pragma unroll
-                    for (int s2 = 0; s2 < S; ++s2) rr[s2] = 0;
-                    for (int r = 0; r < kRanges - 1; ++r) {
-                        const int32_t end = __builtin_amdgcn_readlane(incl, r);
+                for (int s2 = 0; s2 < S; ++s2) rr[s2] = 0;
+                for (int r = 0; r < kRanges - 1; ++r) {
+                    const int32_t end = __builtin_amdgcn_readlane(incl, r);
 #pragma unroll
-                        for (int s2 = 0; s2 < S; ++s2) rr[s2] += (cb + s2 * 64 + lane >= end) ? 1 : 0;
-                    }
-                    uint32_t vj[S], vx[S], vy[S], vz[S];
-                    R vq[S];
-                    double wx[S], wy[S], wz[S];
-                    // the permutes read other lanes' registers: run them with the
-                    // whole wave active, before any predication
-                    uint32_t jj[S];
+                    for (int s2 = 0; s2 < S; ++s2) rr[s2] += (cb + s2 * 64 + lane >= end) ? 1 : 0;
+                }
+                // the permutes read other lanes' registers: the whole wave is active
+                uint32_t cj[S];
 #pragma unroll
-                    for (int s2 = 0; s2 < S; ++s2)
-                        jj[s2] = (uint32_t)(__shfl(lo, rr[s2], 64) + (cb + s2 * 64 + lane - __shfl(excl, rr[s2], 64)));
+                for (int s2 = 0; s2 < S; ++s2)
+                    cj[s2] = (uint32_t)(__shfl(lo, rr[s2], 64) + (cb + s2 * 64 + lane - __shfl(excl, rr[s2], 64)));
+                uint32_t cux[S], cuy[S], cuz[S];
 #pragma unroll
-                    for (int s2 = 0; s2 < S; ++s2) {
-                        const int k = s2 * 64 + lane;
-                        if (k < Cc) {
-                            const uint32_t j = jj[s2];
-                            vj[s2] = j;
-                            vx[s2] = su[j]; vy[s2] = su[n + j]; vz[s2] = su[2 * n + j];
-                            if constexpr (F64) {
-                                vq[s2] = sq[j];
-                                wx[s2] = sx[j]; wy[s2] = sx[n + j]; wz[s2] = sx[2 * n + j];
-                            } else {
-                                vq[s2] = sqf[j];
-                            }
-                        }
-                    }
-#pragma unroll
-                    for (int s2 = 0; s2 < S; ++s2) {
-                        const int k = s2 * 64 + lane;
-                        if (k < Cc) {
-                            L.cu[k] = make_uint4(vx[s2], vy[s2], vz[s2], vj[s2]);
-                            L.cq[k] = vq[s2];
-                            if constexpr (F64) { L.cx[0][k] = wx[s2]; L.cx[1][k] = wy[s2]; L.cx[2][k] = wz[s2]; }
-                        }
+                for (int s2 = 0; s2 < S; ++s2) {
+                    if (cb + s2 * 64 + lane < C) {
+                        cux[s2] = su[cj[s2]]; cuy[s2] = su[n + cj[s2]]; cuz[s2] = su[2 * n + cj[s2]];
+                    } else {
+                        cux[s2] = ox; cuy[s2] = oy; cuz[s2] = oz;
+                        cj[s2] = kNoCand;
                     }
                 }
-                wave_sync();
+                // relative coordinates: with at least 4 cells per side every
+                // candidate lies within 2 cell widths (< L/2) of the origin, so
+                // the wrapped difference to the origin is its true offset and
+                // differences of relative coordinates are minimum images;
+                // smaller grids take the difference of the fixed-point values
+                // per pair instead.  Empty slots sit far away.
+                float cfx[S], cfy[S], cfz[S];
+#pragma unroll
+                for (int s2 = 0; s2 < S; ++s2) {
+                    const bool ok = cj[s2] != kNoCand;
+                    cfx[s2] = ok ? (float)(int32_t)(cux[s2] - ox) * g.hf[0] : 1e18f;
+                    cfy[s2] = ok ? (float)(int32_t)(cuy[s2] - oy) * g.hf[1] : 1e18f;
+                    cfz[s2] = ok ? (float)(int32_t)(cuz[s2] - oz) * g.hf[2] : 1e18f;
+                }
+                const int nslot = (C - cb + 63) / 64 < S ? (C - cb + 63) / 64 : S;
                 // homes of this cell in groups of 64: lane l holds home g0 + l in
-                // registers and home i is broadcast with readlane, so the test
-                // loop touches LDS only to append accepted pairs
+                // registers and home i is broadcast with readlane.  The test
+                // admits every pair below the upper band edge (the pair rule is
+                // applied when the pair is evaluated); accepted pairs are
+                // appended to the queue, home after home.
                 for (int g0 = i0; g0 < i1; g0 += 64) {
                     const int gn = i1 - g0 < 64 ? i1 - g0 : 64;
                     const int gi = g0 + lane;
-                    const bool hv = gi < i1;
-                    const uint4 hme = hv ? L.hu[gi] : make_uint4(0u, 0u, 0u, 0xffffffffu);
-                    const R hqv = hv ? L.hq[gi] : R(0);
-                    double hxv = 0, hyv = 0, hzv = 0;
-                    if constexpr (F64) {
-                        if (hv) { hxv = L.hx[0][gi]; hyv = L.hx[1][gi]; hzv = L.hx[2][gi]; }
-                    }
-                    // candidates of this pass in registers, S slots per lane
-                    constexpr int S = Lds::CAP / 64;
-                    uint4 cj[S];
-                    R qj[S];
-                    double xj[S], yj[S], zj[S];
-#pragma unroll
-                    for (int s2 = 0; s2 < S; ++s2) {
-                        const int k = s2 * 64 + lane;
-                        const bool kv = k < Cc;
-                        cj[s2] = kv ? L.cu[k] : make_uint4(0u, 0u, 0u, 0xfffffffeu);
-                        qj[s2] = kv ? L.cq[k] : R(0);
-                        xj[s2] = yj[s2] = zj[s2] = 0;
-                        if constexpr (F64) {
-                            if (kv) { xj[s2] = L.cx[0][k]; yj[s2] = L.cx[1][k]; zj[s2] = L.cx[2][k]; }
-                        }
-                    }
+                    const uint4 hme = gi < i1 ? L.hu[gi] : make_uint4(ox, oy, oz, 0u);
+                    const float hfx = (float)(int32_t)(hme.x - ox) * g.hf[0];
+                    const float hfy = (float)(int32_t)(hme.y - oy) * g.hf[1];
+                    const float hfz = (float)(int32_t)(hme.z - oz) * g.hf[2];
+                    const uint32_t hbase = (uint32_t)(t + g0);  // sorted index of home g0
                     for (int ii = 0; ii < gn; ++ii) {
-                        const uint32_t hx_ = (uint32_t)__builtin_amdgcn_readlane((int)hme.x, ii);
-                        const uint32_t hy_ = (uint32_t)__builtin_amdgcn_readlane((int)hme.y, ii);
-                        const uint32_t hz_ = (uint32_t)__builtin_amdgcn_readlane((int)hme.z, ii);
-                        const uint32_t hw_ = (uint32_t)__builtin_amdgcn_readlane((int)hme.w, ii);
+                        float hx_, hy_, hz_;
+                        uint32_t hux = 0, huy = 0, huz = 0;
+                        if (rel) {
+                            hx_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfx), ii));
+                            hy_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfy), ii));
+                            hz_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfz), ii));
+                        } else {
+                            hux = (uint32_t)__builtin_amdgcn_readlane((int)hme.x, ii);
+                            huy = (uint32_t)__builtin_amdgcn_readlane((int)hme.y, ii);
+                            huz = (uint32_t)__builtin_amdgcn_readlane((int)hme.z, ii);
+                        }
+                        const uint32_t self = hbase + (uint32_t)ii;
 #pragma unroll
                         for (int s2 = 0; s2 < S; ++s2) {
-                            if (s2 * 64 >= Cc) break;
-                            const uint32_t dux = cj[s2].x - hx_, duy = cj[s2].y - hy_, duz = cj[s2].z - hz_;
-                            const float fx = (float)(int32_t)dux * g.hf[0];
-                            const float fy = (float)(int32_t)duy * g.hf[1];
-                            const float fz = (float)(int32_t)duz * g.hf[2];
-                            const float r2 = fx * fx + fy * fy + fz * fz;
-                            bool acc = cj[s2].w != hw_ && r2 < g.band_hi_f;
-                            if (acc && r2 > g.band_lo_f) acc = exact_in(g, dux, duy, duz);
-                            const uint64_t m = __ballot(acc);
-                            if (acc) {
-                                const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi(
-                                                         (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
-                                if constexpr (F64) {
-                                    L.qd[pos] = make_double4(mi64(xj[s2] - bcast64(hxv, ii), g.L[0], g.invL[0]),
-                                                             mi64(yj[s2] - bcast64(hyv, ii), g.L[1], g.invL[1]),
-                                                             mi64(zj[s2] - bcast64(hzv, ii), g.L[2], g.invL[2]),
-                                                             bcast64(hqv, ii) * qj[s2]);
+                            if (s2 < nslot) {
+                                float r2;
+                                if (rel) {
+                                    const float dx = cfx[s2] - hx_, dy = cfy[s2] - hy_, dz = cfz[s2] - hz_;
+                                    r2 = dx * dx + dy * dy + dz * dz;
                                 } else {
-                                    const float hq_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hqv), ii));
-                                    L.qd[pos] = make_float4(fx, fy, fz, hq_ * qj[s2]);
+                                    r2 = cj[s2] == kNoCand ? 1e36f
+                                                           : fixed_r2(g, cux[s2] - hux, cuy[s2] - huy, cuz[s2] - huz);
                                 }
-                                L.qs[pos] = (uint32_t)(g0 + ii);
-                            }
-                            qn = __builtin_amdgcn_readfirstlane(qn + (int)__popcll(m));
-                            if (qn >= 64) {
-                                wave_sync();
-                                eval_batch<F64>(g, c, K, L, lane, 64, e);
-                                const bool mv = lane + 64 < qn;
-                                const auto rest = L.qd[mv ? lane + 64 : lane];
-                                const uint32_t rs = L.qs[mv ? lane + 64 : lane];
-                                wave_sync();
-                                if (mv) {
-                                    L.qd[lane] = rest;
-                                    L.qs[lane] = rs;
+                                const bool acc = r2 < g.band_hi_f && cj[s2] != self;
+                                const uint64_t m = __ballot(acc);
+                                if (acc) {
+                                    const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi(
+                                                             (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+                                    L.q[pos] = make_uint2((uint32_t)(g0 + ii), cj[s2]);
                                 }
-                                qn -= 64;
-                                wave_sync();
+                                qn += (int)__popcll(m);
+                                if (qn >= 64) {
+                                    wave_sync();
+                                    eval_batch<F64>(g, co, L, su, sx, sq, sqf, lane, 64, e);
+                                    const bool mv = lane + 64 < qn;
+                                    const uint2 rest = L.q[mv ? lane + 64 : lane];
+                                    wave_sync();
+                                    if (mv) L.q[lane] = rest;
+                                    qn -= 64;
+                                    wave_sync();
+                                }
                             }
                         }
                     }
                 }
-                wave_sync();
             }
         }
         // the queue refers to this batch's home slots: drain it, then write
         wave_sync();
-        if (qn > 0) eval_batch<F64>(g, c, K, L, lane, qn, e);
+        if (qn > 0) eval_batch<F64>(g, co, L, su, sx, sq, sqf, lane, qn, e);
         qn = 0;
         wave_sync();
         for (int k = lane; k < H; k += 64) {
@@ -534,15 +494,15 @@ NearPlan near_plan(int64_t ncell) {
     return p;
 }
 
-void launch_near(const Geom &g, const SogDev &c, bool f64, const NearPlan &np, int64_t ncell, const int32_t *start,
+void launch_near(const Geom &g, const SplitCoef64 &c64, const SplitCoef32 &c32, bool f64, const NearPlan &np, int64_t ncell, const int32_t *start,
                  const int32_t *order, const uint32_t *su, const double *sx, const double *sq, const float *sqf,
                  double *Fn, double *epart, hipStream_t s) {
     dim3 grid((unsigned)np.nblk), block(64 * kNW);
     if (f64)
-        hipLaunchKernelGGL(k_near<true>, grid, block, 0, s, g, c, ncell, np.cells_per_block, np.nblk, start, order,
+        hipLaunchKernelGGL(k_near<true>, grid, block, 0, s, g, c64, ncell, np.cells_per_block, np.nblk, start, order,
                            su, sx, sq, sqf, Fn, epart);
     else
-        hipLaunchKernelGGL(k_near<false>, grid, block, 0, s, g, c, ncell, np.cells_per_block, np.nblk, start, order,
+        hipLaunchKernelGGL(k_near<false>, grid, block, 0, s, g, c32, ncell, np.cells_per_block, np.nblk, start, order,
                            su, sx, sq, sqf, Fn, epart);
 }
 

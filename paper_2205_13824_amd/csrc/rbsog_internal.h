@@ -38,30 +38,31 @@ struct Geom {
     float band_lo_f, band_hi_f;  // same for the FP32 fast test
     int32_t nc[3];
     int32_t reach[3];            // 1 if the stencil spans -1..1 in that dimension, 0 otherwise
-    int32_t nexp;                // Gaussians l < nexp are evaluated with an exponential each
-    int32_t ntail64, ntail32;    // coefficients of the tail polynomials in r^2 (0: no tail)
 };
 
-// Degrees of the polynomials in x = r^2 that replace the Gaussians with
-// r_c^2 / s_l^2 <= kTailTau (Taylor series of exp(-x/s_l^2) summed over
-// those l): truncation below 6e-18 (FP64) and 3e-9 (FP32) of the tail.
-constexpr double kTailTau = 0.05;
+// The near kernel evaluates the narrow Gaussians (r_c^2 / s_l^2 > tau) with an
+// exponential each and replaces the wide ones (s_l grows with l, so they are
+// l >= nexp) by the Taylor polynomial of their sum in x = r^2.  Truncation per
+// Gaussian: tau^(deg+1)/(deg+1)! of its weight, 5e-18 (FP64) and 1.2e-8 (FP32).
+constexpr double kTailTau64 = 0.05;
+constexpr double kTailTau32 = 0.25;
 constexpr int kTailDeg64 = 8;
-constexpr int kTailDeg32 = 4;
+constexpr int kTailDeg32 = 6;
+constexpr int kMaxExp = 24;  // narrow Gaussians per split (more is rejected)
 
-// Device-resident coefficients of the split.
-struct SogDev {
-    const double *w64;    // omega_l, l < nexp
-    const double *a64;    // 1 / s_l^2
-    const double *c64;    // 2 omega_l / s_l^2
-    const double *pt64;   // potential tail: sum_l omega_l exp(-x/s_l^2) = sum_n pt64[n] x^n
-    const double *ft64;   // force tail: sum_l 2 omega_l/s_l^2 exp(-x/s_l^2) = sum_n ft64[n] x^n
-    const float *w32;     // omega_l
-    const float *a32;     // log2(e) / s_l^2
-    const float *c32;     // 2 omega_l / s_l^2
-    const float *pt32;    // tails in FP32
-    const float *ft32;
+// Split coefficients, passed by value in the near kernel's arguments so that
+// every lane reads them through the scalar unit.
+template <typename R, int NT>
+struct SplitCoef {
+    R a[kMaxExp];   // 1/s_l^2 (FP32: log2(e)/s_l^2, for exp2)
+    R cw[kMaxExp];  // 2 omega_l / s_l^2
+    R w[kMaxExp];   // omega_l
+    R pt[NT];       // sum_{l>=nexp} omega_l e^{-x/s_l^2} = sum_k pt[k] x^k
+    R ft[NT];       // sum_{l>=nexp} 2 omega_l/s_l^2 e^{-x/s_l^2} = sum_k ft[k] x^k
+    int32_t nexp;
 };
+using SplitCoef64 = SplitCoef<double, kTailDeg64 + 1>;
+using SplitCoef32 = SplitCoef<float, kTailDeg32 + 1>;
 
 // Arguments of the k-batch staging (Algorithm 1: the next P frequencies of the
 // pre-sampled sequence, in order) and of the velocity-Verlet half kicks.
@@ -131,7 +132,7 @@ struct NearPlan {
     int64_t cells_per_block;  // contiguous cells per block
 };
 NearPlan near_plan(int64_t ncell);
-void launch_near(const Geom &g, const SogDev &c, bool f64, const NearPlan &np, int64_t ncell, const int32_t *start,
+void launch_near(const Geom &g, const SplitCoef64 &c64, const SplitCoef32 &c32, bool f64, const NearPlan &np, int64_t ncell, const int32_t *start,
                  const int32_t *order, const uint32_t *su, const double *sx, const double *sq, const float *sqf,
                  double *Fn, double *epart, hipStream_t s);
 void launch_neighbor_count(const Geom &g, const int32_t *start, const int32_t *order, const uint32_t *su,
