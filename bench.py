@@ -28,18 +28,20 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-steps/s, RBSOG forces FP32-comp vs FP64, at <=1e-5 rel RMS force err"
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz = VALU lane-op slots per second
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz = VALU lane-op slots per
+# second for non-packed instructions (FP32 FMA counts one slot)
 PEAK_VALU_SLOTS = 256 * 4 * 16 * 2.4e9
-# issue slots of one FP32 transcendental (sin, cos, exp, rsqrt) on the VALU
-TRANS_SLOTS = 4
+# issue slots of one FP32 transcendental (sin, cos, exp, rsqrt): gfx950 issues
+# them at half the FMA rate (measured: 16.5 vs 31.9 T lane-ops/s)
+TRANS_SLOTS = 2
 # algorithmic VALU slots per unit of work (the method's arithmetic, not the
-# implementation's): see DESIGN.md, "Roofline".
+# implementation's: candidate rejects and the full-list doubling are overhead)
 WORK = {
-    # per (particle, k): phase 3 + accumulate 2 FMA-class, sin + cos
+    # per (particle, k): phase 3 + accumulate 2, sin + cos
     "rho": 5 + 2 * TRANS_SLOTS,
-    # per (particle, k): phase 3 + Im 2 + accumulate 3 FMA-class, sin + cos
+    # per (particle, k): phase 3 + Im 2 + accumulate 3, sin + cos
     "far": 8 + 2 * TRANS_SLOTS,
-    # per neighbour pair inside r_c (full list, both orders): rsqrt, M+1 = 17 exp, ~40 FMA-class
+    # per unique pair inside r_c: rsqrt, M+1 = 17 exp, ~40 FMA-class (direct Gaussian sum)
     "near": 40 + 18 * TRANS_SLOTS,
 }
 
@@ -56,6 +58,9 @@ def parse():
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=300_000, help=argparse.SUPPRESS)
+    # after the bench: device-to-device copies of this many MiB, the reference
+    # kernel against which rocprofv3's FETCH_SIZE / WRITE_SIZE are scaled
+    ap.add_argument("--copy-probe-mib", type=int, default=0)
     return ap.parse_args()
 
 
@@ -101,17 +106,24 @@ def run_precision(R, torch, wl, prec, args):
                 value=n * args.steps / (ms * 1e-3))
 
 
-def roofline(kernels, n, P, near_pairs):
-    units = {"rho": n * P, "far": n * P, "near": near_pairs}
+def roofline(kernels, n, P, near_pairs, nexp32=3, ntail32=7):
+    # near: units are unique pairs (the list holds both orders)
+    units = {"rho": n * P, "far": n * P, "near": near_pairs // 2}
     cands = {k: v for k, v in kernels.items() if k in units}
     if not cands:
         return None
     dom = max(cands, key=lambda k: cands[k]["us_per_launch"])
     t = cands[dom]["us_per_launch"] * 1e-6
     achieved = units[dom] * WORK[dom] / t
-    return {"kernel": dom, "bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_VALU_SLOTS / 1e9,
-            "unit": "Gop/s (VALU lane slots)", "frac": achieved / PEAK_VALU_SLOTS, "traffic": None,
-            "units_per_launch": units[dom], "slots_per_unit": WORK[dom], "us_per_launch": t * 1e6}
+    out = {"kernel": dom, "bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_VALU_SLOTS / 1e9,
+           "unit": "Gop/s (VALU lane slots)", "frac": achieved / PEAK_VALU_SLOTS, "traffic": None,
+           "units_per_launch": units[dom], "slots_per_unit": WORK[dom], "us_per_launch": t * 1e6}
+    if dom == "near":
+        # the same pairs priced as this library evaluates them (both orders;
+        # rsqrt, nexp exponentials, two tail polynomials, ~15 FMA-class)
+        ev = 2 * (TRANS_SLOTS * (1 + nexp32) + 3 * nexp32 + 2 * ntail32 + 15)
+        out["as_evaluated"] = {"slots_per_unit": ev, "frac": units[dom] * ev / t / PEAK_VALU_SLOTS}
+    return out
 
 
 def cpu_baseline(wl, budget_s=12.0):
@@ -192,6 +204,14 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
+    if args.copy_probe_mib > 0:
+        nb = args.copy_probe_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: 3 x {args.copy_probe_mib} MiB device-to-device")
 
 
 if __name__ == "__main__":

@@ -24,6 +24,12 @@
  * by Metropolis-Hastings from P_k = F~(k)/(pi^{3/2} S) (Sec. 3.3) and consumed
  * P at a time, in order, one batch per force evaluation.
  *
+ * A context holds one system (rbsog_init) or a batch of independent systems
+ * (rbsog_init_batch, e.g. an ensemble of replicas): every call acts on all of
+ * them at once, each system with its own box, charges, cutoff, split, P and
+ * sampler; "n" below is the total particle count and particle arrays
+ * concatenate the systems in the order of the offsets.
+ *
  * Conventions.
  *   - All host arrays are caller-owned, read or written only during the call.
  *     Positions/velocities/forces are row-major n x 3 (x, y, z per particle),
@@ -97,7 +103,7 @@ void rbsog_default_opts(rbsog_opts *o);
 rbsog_status rbsog_sog_table1(int32_t row, double rc, rbsog_sog *out);
 
 /* Creates a context for one periodic system (Sec. 2 problem statement;
- * Algorithm 1, step 1).
+ * Algorithm 1, step 1): a batch of one.
  *   n     number of particles, >= 2
  *   pos   host, n x 3, any finite values (wrapped into the box)
  *   q     host, n charges, finite, neutral within opts->neutral_tol
@@ -113,6 +119,18 @@ rbsog_status rbsog_init(rbsog_ctx **out, int64_t n, const double *pos, const dou
                         const double *box, const rbsog_sog *sog, double rc, int32_t P,
                         uint64_t seed, const rbsog_opts *opts);
 
+/* Creates a context for n_sys independent systems evaluated together (one
+ * launch per kernel for the whole batch).  System s owns particles
+ * [offsets[s], offsets[s+1]) of pos (n x 3) and q, box boxes[3s..3s+2], split
+ * sog[s], cutoff rc[s], P[s] wave vectors per evaluation and sampler key
+ * seeds[s]; each is validated as by rbsog_init (errors name the system).
+ *   offsets  host n_sys+1 int64, offsets[0] = 0, at least 2 particles each
+ * Precision, device, stream, mass and graphs of opts apply to all systems. */
+rbsog_status rbsog_init_batch(rbsog_ctx **out, int32_t n_sys, const int64_t *offsets,
+                              const double *pos, const double *q, const double *boxes,
+                              const rbsog_sog *sog, const double *rc, const int32_t *P,
+                              const uint64_t *seeds, const rbsog_opts *opts);
+
 /* Extends the wave-vector sequence by n_batches * P states of the
  * Metropolis-Hastings independence chain of Sec. 3.3 (Algorithm 1, step 2):
  * proposal m*_d = round(N(0, (L_d/(pi s_0))^2 / 2)), m* = 0 redrawn, accepted
@@ -122,23 +140,26 @@ rbsog_status rbsog_init(rbsog_ctx **out, int64_t n, const double *pos, const dou
  * Attempt t uses Philox4x32-10 with counter (t_lo, t_hi, 0, lane) and key
  * (seed_lo, seed_hi): lanes 0 and 1 give two Box-Muller pairs from 53-bit
  * uniforms, lane 2 the acceptance uniform.
- *   m_out  NULL, or host n_batches * P * 3 int32 receiving the new states.
+ * Every system extends its own chain (key seeds[s]).
+ *   m_out  NULL, or host sum_s n_batches * P_s * 3 int32 receiving the new
+ *          states, system after system.
  * E_ARG if n_batches < 1. */
 rbsog_status rbsog_sample_k(rbsog_ctx *ctx, int64_t n_batches, int32_t *m_out);
 
-/* Replaces the sequence with n_k caller-given nonzero vectors (host, n_k x 3)
- * and rewinds it.  w: NULL for the random-batch weight S pi^{3/2}/(P V), or
+/* Replaces the sequence of system sys with n_k caller-given nonzero vectors
+ * (host, n_k x 3) and rewinds it.  w: NULL for the random-batch weight S pi^{3/2}/(P V), or
  * host n_k per-vector weights (w = F~(k)/V with every k of the lattice and
  * P = n_k turns the far part into the full Fourier sum of eq. "forcesplit").
- * E_ARG if n_k < 1 or a vector is zero. */
-rbsog_status rbsog_set_k(rbsog_ctx *ctx, int64_t n_k, const int32_t *m, const double *w);
+ * E_ARG if sys is out of range, n_k < 1 or a vector is zero. */
+rbsog_status rbsog_set_k(rbsog_ctx *ctx, int32_t sys, int64_t n_k, const int32_t *m,
+                         const double *w);
 
 /* One force evaluation at the current positions with the next P vectors of
  * the sequence (Algorithm 1, step 4): wrap and quantise, cell list, near
  * part, structure factors, far force, energies.
  *   F_out  NULL, or host n x 3 total force F_N + F*
- *   E_out  NULL, or host 4 doubles: U_N, U*, U_self, U
- * E_KSEQ if fewer than P vectors remain (nothing is computed). */
+ *   E_out  NULL, or host 4 * n_sys doubles: U_N, U*, U_self, U of each system
+ * E_KSEQ if a system has fewer than P vectors left (nothing is computed). */
 rbsog_status rbsog_forces(rbsog_ctx *ctx, double *F_out, double *E_out);
 
 /* n_steps velocity-Verlet steps of size dt (kick dt/2, drift, wrap, forces
@@ -149,8 +170,9 @@ rbsog_status rbsog_forces(rbsog_ctx *ctx, double *F_out, double *E_out);
 rbsog_status rbsog_step(rbsog_ctx *ctx, int64_t n_steps, double dt);
 
 /* Sets velocities: v host n x 3, or NULL to draw v ~ N(0, T/m) per component
- * (Philox4x32-10 keyed by seed, Box-Muller) and remove the centre-of-mass
- * velocity.  E_ARG if v is NULL and T < 0. */
+ * (Philox4x32-10 keyed by seed, counter (i, 0, 1, lane) for particle i,
+ * Box-Muller) and remove each system's centre-of-mass velocity.  E_ARG if v
+ * is NULL and T < 0. */
 rbsog_status rbsog_set_velocities(rbsog_ctx *ctx, const double *v, double T, uint64_t seed);
 
 /* Replaces the positions (host n x 3, finite); forces become unknown. */
@@ -163,30 +185,35 @@ rbsog_status rbsog_get_state(rbsog_ctx *ctx, double *pos, double *vel);
  * each, either may be NULL).  E_STATE if no evaluation has been made. */
 rbsog_status rbsog_get_forces(rbsog_ctx *ctx, double *F_near, double *F_far);
 
-/* Copies the latest energies (U_N, U*, U_self, U) and structure factors
- * (host P doubles each for rho_re, rho_im; either may be NULL). */
-rbsog_status rbsog_get_energy(rbsog_ctx *ctx, double *E4);
-rbsog_status rbsog_get_rho(rbsog_ctx *ctx, double *rho_re, double *rho_im);
+/* Copies the latest energies (host 4 * n_sys doubles: U_N, U*, U_self, U of
+ * each system) and the structure factors of system sys (host P doubles each
+ * for rho_re, rho_im; either may be NULL). */
+rbsog_status rbsog_get_energy(rbsog_ctx *ctx, double *E);
+rbsog_status rbsog_get_rho(rbsog_ctx *ctx, int32_t sys, double *rho_re, double *rho_im);
 
-/* Scalars of the context: S, V, number of cells, wave vectors left in the
- * sequence, evaluations made. */
+/* Scalars of system sys: S, V, number of cells, wave vectors left in its
+ * sequence, evaluations made, its particle count and the number of systems. */
 typedef struct {
     double S;
     double volume;
     int32_t ncell[3];
     int64_t k_remaining;
     int64_t evaluations;
+    int64_t n;
+    int32_t n_sys;
 } rbsog_info_t;
-rbsog_status rbsog_info(rbsog_ctx *ctx, rbsog_info_t *info);
+rbsog_status rbsog_info(rbsog_ctx *ctx, int32_t sys, rbsog_info_t *info);
 
-/* Debug exports of the latest cell list and a full neighbour list built on the
- * device with the pair rule above (rows ascending i, columns ascending j).
- *   cell_start  host ncell+1 int32;  order  host n int32 (ids by (cell, id))
- *   row_ptr     host n+1 int64;  cols  host cap int32
+/* Debug exports of system sys: the latest cell list and a full neighbour
+ * list built on the device with the pair rule above (rows ascending i,
+ * columns ascending j).  Indices are local to the system (0 .. n_s - 1).
+ *   cell_start  host ncell+1 int32;  order  host n_s int32 (ids by (cell, id))
+ *   row_ptr     host n_s+1 int64;  cols  host cap int32
  * rbsog_debug_neighbors returns E_ARG if cap is smaller than the entry count
  * (row_ptr is still filled, so the call can be repeated). */
-rbsog_status rbsog_debug_cells(rbsog_ctx *ctx, int32_t *cell_start, int32_t *order);
-rbsog_status rbsog_debug_neighbors(rbsog_ctx *ctx, int64_t *row_ptr, int32_t *cols, int64_t cap);
+rbsog_status rbsog_debug_cells(rbsog_ctx *ctx, int32_t sys, int32_t *cell_start, int32_t *order);
+rbsog_status rbsog_debug_neighbors(rbsog_ctx *ctx, int32_t sys, int64_t *row_ptr, int32_t *cols,
+                                   int64_t cap);
 
 /* Per-kernel timing with HIP events on the context's stream.  enable != 0
  * starts recording (and clears the totals).  rbsog_profile_read returns the

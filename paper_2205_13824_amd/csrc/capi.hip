@@ -1,7 +1,8 @@
 // Host side of librbsog: the C ABI of include/rbsog.h.  Validates inputs,
-// builds the split coefficients and the normaliser S, runs the wave-vector
-// sampler, owns the device memory and enqueues the kernels of one force
-// evaluation / one velocity-Verlet step on a single HIP stream.
+// builds the split coefficients and the normaliser S of every system, runs
+// the wave-vector samplers, builds the work lists of the batch, owns the
+// device memory and enqueues the kernels of one force evaluation / one
+// velocity-Verlet step of all systems on a single HIP stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -72,26 +73,25 @@ enum Kid { K_KDQ, K_SCAN, K_SCATTER, K_SORTG, K_NEAR, K_RHO, K_RHORED, K_FAR, K_
 const char *kKernelNames[K_COUNT] = {"kick_drift_quantise", "scan_cell_counts", "cell_scatter", "sort_gather",
                                      "near",                "rho",              "rho_reduce",   "far"};
 
-}  // namespace
 
-struct rbsog_ctx {
-    // system
-    int64_t n = 0;
+// One system of the batch: host-side parameters, sampler and sequence.
+struct SysHost {
+    int64_t n = 0, p0 = 0;
     double box[3] = {0, 0, 0};
     double rc = 0;
     int32_t P = 0;
     uint64_t seed = 0;
-    int prec = RBSOG_FP64;
-    int device = 0;
-    double mass = 1.0;
-    // split
     int M = 0;
     std::vector<double> omega, s;
     double S = 0, V = 0, uself = 0, w_rb = 0;
-    Geom geom{};
-    int64_t ncell = 0;
-    FarPlan fplan{};
-    NearPlan nplan{};
+    Geom g{};
+    int64_t ncell = 0, c0 = 0;
+    int32_t k0 = 0;
+    SplitCoef64 co64{};
+    SplitCoef32 co32{};
+    // work lists
+    int32_t it0 = 0, it1 = 0, nch = 0, kt = 1, streams = 1;
+    int64_t pofs = 0;
     // sequence
     MHChain chain;
     std::vector<int32_t> kseq;
@@ -99,38 +99,54 @@ struct rbsog_ctx {
     bool custom_w = false;
     int64_t cursor = 0;
     int64_t kcap = 0;
+    int32_t *dkseq = nullptr;
+    double *dkw = nullptr;
+};
+
+}  // namespace
+
+struct rbsog_ctx {
+    int32_t nsys = 0;
+    std::vector<SysHost> sys;
+    int64_t N = 0, C = 0;
+    int32_t K = 0;
+    int prec = RBSOG_FP64;
+    int device = 0;
+    double mass = 1.0;
+    std::vector<double> q_host;  // charges in the caller's order
     // state
     bool forces_valid = false;
     int64_t evals = 0;
     bool poisoned = false;
     std::string err;
+    int parity = 0;  // buf[parity] holds the current cell order
     // stream
     hipStream_t stream = nullptr;
     bool own_stream = false;
     // device memory
     std::vector<void *> allocs;
-    double *x = nullptr, *v = nullptr, *q = nullptr, *Fn = nullptr, *Ff = nullptr;
-    float *qf = nullptr, *sqf = nullptr;
-    uint32_t *u = nullptr, *su = nullptr;
-    double *sx = nullptr, *sq = nullptr;
-    int32_t *cell_of = nullptr, *cell_count = nullptr, *cell_start = nullptr, *cell_fill = nullptr,
-            *order = nullptr, *blocksums = nullptr;
-    int32_t *dkseq = nullptr;
-    double *dkw = nullptr;
-    int64_t *dcursor = nullptr;
+    SysDev *dsys = nullptr;
+    int32_t *sys_of = nullptr, *ksys = nullptr;
+    StateBufs buf[2] = {};
+    uint32_t *u_tmp = nullptr, *u = nullptr;
+    int32_t *cell_of = nullptr, *cell_count = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *src = nullptr,
+            *blocksums = nullptr;
+    double *Fn = nullptr, *Ff = nullptr;
+    int64_t *kcur = nullptr;
     KRec64 *kb64 = nullptr;
     KRec32 *kb32 = nullptr;
     double *wk = nullptr, *rho = nullptr, *ek = nullptr, *partial = nullptr, *epart = nullptr, *E = nullptr;
     int32_t *flag = nullptr;
-    uint32_t *counter = nullptr;
-    SplitCoef64 co64{};
-    SplitCoef32 co32{};
-    // graph of one velocity-Verlet step
+    uint32_t *sys_done = nullptr;
+    NearItem *near_items = nullptr;
+    RhoItem *rho_items = nullptr;
+    FarItem *far_items = nullptr;
+    int32_t n_near = 0, n_rho = 0, n_far = 0;
+    // graphs of one velocity-Verlet step, one per buffer parity
     bool use_graphs = true;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
     double graph_dt = 0.0;
-    const void *graph_key[3] = {nullptr, nullptr, nullptr};
     // profiling
     bool prof_on = false;
     ProfEntry prof[K_COUNT];
@@ -220,7 +236,7 @@ double normaliser_S(const std::vector<double> &omega, const std::vector<double> 
 }
 
 // ---- sampler -------------------------------------------------------------------
-double target_weight(const rbsog_ctx *c, const int32_t m[3]) {
+double target_weight(const SysHost *c, const int32_t m[3]) {
     const double t = (double)m[0] * m[0] / (c->box[0] * c->box[0]) + (double)m[1] * m[1] / (c->box[1] * c->box[1]) +
                      (double)m[2] * m[2] / (c->box[2] * c->box[2]);
     double acc = 0.0;
@@ -235,7 +251,7 @@ double proposal_1d(int32_t m, double a) {
     return 0.5 * (std::erfc((am - 0.5) * a) - std::erfc((am + 0.5) * a));
 }
 
-void mh_extend(rbsog_ctx *c, int64_t count, std::vector<int32_t> &out) {
+void mh_extend(SysHost *c, int64_t count, std::vector<int32_t> &out) {
     MHChain &ch = c->chain;
     const double s0 = c->s[0];
     double sd[3], a[3];
@@ -326,9 +342,43 @@ rbsog_status timed(rbsog_ctx *c, int kid, F &&launch) {
 }
 
 // ---- device orchestration --------------------------------------------------------
-rbsog_status ensure_kcap(rbsog_ctx *c, int64_t nvec) {
-    if (nvec <= c->kcap) return RBSOG_OK;
-    int64_t cap = std::max<int64_t>(nvec, 2 * c->kcap);
+SysDev sysdev_of(const SysHost &h) {
+    SysDev d{};
+    d.g = h.g;
+    d.co64 = h.co64;
+    d.co32 = h.co32;
+    d.p0 = h.p0;
+    d.c0 = h.c0;
+    d.P = h.P;
+    d.k0 = h.k0;
+    d.kseq = h.dkseq;
+    d.kw = h.custom_w ? h.dkw : nullptr;
+    d.w_rb = h.w_rb;
+    d.uself = h.uself;
+    d.it0 = h.it0;
+    d.it1 = h.it1;
+    d.pofs = h.pofs;
+    d.nch = h.nch;
+    d.kt = h.kt;
+    d.streams = h.streams;
+    return d;
+}
+
+rbsog_status upload_sysdev(rbsog_ctx *c, int32_t s) {
+    const SysDev d = sysdev_of(c->sys[s]);
+    HIPCHK(c, hipMemcpy(c->dsys + s, &d, sizeof d, hipMemcpyHostToDevice));
+    return RBSOG_OK;
+}
+
+rbsog_status upload_cursor(rbsog_ctx *c, int32_t s) {
+    HIPCHK(c, hipMemcpy(c->kcur + s, &c->sys[s].cursor, sizeof(int64_t), hipMemcpyHostToDevice));
+    return RBSOG_OK;
+}
+
+rbsog_status ensure_kcap(rbsog_ctx *c, int32_t s, int64_t nvec) {
+    SysHost &h = c->sys[s];
+    if (nvec <= h.kcap) return RBSOG_OK;
+    int64_t cap = std::max<int64_t>(nvec, 2 * h.kcap);
     int32_t *nk = nullptr;
     double *nw = nullptr;
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -338,107 +388,143 @@ rbsog_status ensure_kcap(rbsog_ctx *c, int64_t nvec) {
         (void)hipFree(nk);
         return fail(c, RBSOG_E_OOM, "weight buffer of %lld vectors", (long long)cap);
     }
-    if (c->dkseq) {
-        HIPCHK(c, hipMemcpy(nk, c->dkseq, (size_t)c->kcap * 3 * sizeof(int32_t), hipMemcpyDeviceToDevice));
-        HIPCHK(c, hipMemcpy(nw, c->dkw, (size_t)c->kcap * sizeof(double), hipMemcpyDeviceToDevice));
-        c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), (void *)c->dkseq), c->allocs.end());
-        c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), (void *)c->dkw), c->allocs.end());
-        (void)hipFree(c->dkseq);
-        (void)hipFree(c->dkw);
+    if (h.dkseq) {
+        HIPCHK(c, hipMemcpy(nk, h.dkseq, (size_t)h.kcap * 3 * sizeof(int32_t), hipMemcpyDeviceToDevice));
+        HIPCHK(c, hipMemcpy(nw, h.dkw, (size_t)h.kcap * sizeof(double), hipMemcpyDeviceToDevice));
+        c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), (void *)h.dkseq), c->allocs.end());
+        c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), (void *)h.dkw), c->allocs.end());
+        (void)hipFree(h.dkseq);
+        (void)hipFree(h.dkw);
     }
-    c->dkseq = nk;
-    c->dkw = nw;
+    h.dkseq = nk;
+    h.dkw = nw;
     c->allocs.push_back(nk);
     c->allocs.push_back(nw);
-    c->kcap = cap;
-    return RBSOG_OK;
+    h.kcap = cap;
+    return upload_sysdev(c, s);
 }
 
-rbsog_status upload_k(rbsog_ctx *c, int64_t from) {
-    const int64_t nvec = (int64_t)c->kseq.size() / 3;
-    TRY(ensure_kcap(c, nvec));
+rbsog_status upload_k(rbsog_ctx *c, int32_t s, int64_t from) {
+    SysHost &h = c->sys[s];
+    const int64_t nvec = (int64_t)h.kseq.size() / 3;
+    TRY(ensure_kcap(c, s, nvec));
     if (nvec > from) {
-        HIPCHK(c, hipMemcpy(c->dkseq + 3 * from, c->kseq.data() + 3 * from, (size_t)(nvec - from) * 3 * sizeof(int32_t),
+        HIPCHK(c, hipMemcpy(h.dkseq + 3 * from, h.kseq.data() + 3 * from, (size_t)(nvec - from) * 3 * sizeof(int32_t),
                             hipMemcpyHostToDevice));
-        if (c->custom_w)
-            HIPCHK(c, hipMemcpy(c->dkw + from, c->kw.data() + from, (size_t)(nvec - from) * sizeof(double),
+        if (h.custom_w)
+            HIPCHK(c, hipMemcpy(h.dkw + from, h.kw.data() + from, (size_t)(nvec - from) * sizeof(double),
                                 hipMemcpyHostToDevice));
     }
     return RBSOG_OK;
 }
 
+EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
+    EvalArgs a{};
+    a.N = c->N;
+    a.C = c->C;
+    a.nsys = c->nsys;
+    a.K = c->K;
+    a.sys = c->dsys;
+    a.sys_of = c->sys_of;
+    a.ksys = c->ksys;
+    a.cur = c->buf[c->parity];
+    a.nxt = c->buf[1 - c->parity];
+    a.u_tmp = c->u_tmp;
+    a.u = c->u;
+    a.cell_of = c->cell_of;
+    a.cell_count = c->cell_count;
+    a.cell_start = c->cell_start;
+    a.cell_fill = c->cell_fill;
+    a.src = c->src;
+    a.blocksums = c->blocksums;
+    a.Fn = c->Fn;
+    a.Ff = c->Ff;
+    a.kcur = c->kcur;
+    a.kb64 = c->kb64;
+    a.kb32 = c->kb32;
+    a.wk = c->wk;
+    a.rho = c->rho;
+    a.ek = c->ek;
+    a.partial = c->partial;
+    a.epart = c->epart;
+    a.E = c->E;
+    a.flag = c->flag;
+    a.sys_done = c->sys_done;
+    a.kick = stepping ? 1 : 0;
+    a.hdm = 0.5 * dt / c->mass;
+    a.dt = dt;
+    return a;
+}
+
 // Enqueue one force evaluation (with the velocity-Verlet kick-drift before
-// and the closing kick after it when dt != 0).  Pure launches: no host state
+// and the closing kick after it when stepping).  Pure launches: no host state
 // changes, so it can be captured into a graph.
 rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt) {
     hipStream_t s = c->stream;
-    const Geom &g = c->geom;
     const bool f64 = c->prec == RBSOG_FP64;
-    KickArgs kick{stepping ? 1 : 0, 0.5 * dt / c->mass, dt, c->v, c->Fn, c->Ff, c->flag};
-    StageArgs stage{c->P, c->dkseq, c->custom_w ? c->dkw : nullptr, c->w_rb, c->dcursor, c->kb64, c->kb32, c->wk};
-    TRY(timed(c, K_KDQ, [&] { launch_kdq(g, kick, stage, c->x, c->u, c->cell_of, c->cell_count, s); }));
-    TRY(timed(c, K_SCAN, [&] { launch_scan(c->cell_count, c->cell_start, c->cell_fill, c->ncell, c->blocksums, s); }));
-    TRY(timed(c, K_SCATTER, [&] { launch_cell_scatter(g, c->cell_of, c->cell_fill, c->order, s); }));
-    TRY(timed(c, K_SORTG, [&] {
-        launch_sort_gather(g, c->ncell, c->cell_start, c->order, c->cell_count, c->u, c->x, c->q, c->su, c->sx, c->sq,
-                           c->sqf, f64, s);
-    }));
-    TRY(timed(c, K_NEAR, [&] {
-        launch_near(g, c->co64, c->co32, f64, c->nplan, c->ncell, c->cell_start, c->order, c->su, c->sx, c->sq, c->sqf, c->Fn,
-                    c->epart, s);
-    }));
-    TRY(timed(c, K_RHO, [&] {
-        launch_rho(g, c->fplan, c->P, f64, c->x, c->u, c->q, c->qf, c->kb64, c->kb32, c->partial, s);
-    }));
-    TRY(timed(c, K_RHORED, [&] {
-        launch_rho_reduce(c->P, c->fplan.nblk, c->partial, c->wk, c->kb64, c->kb32, c->rho, c->ek, c->nplan.nblk,
-                          c->epart, c->uself, c->E, c->flag, c->counter, s);
-    }));
-    TRY(timed(c, K_FAR, [&] { launch_far(g, c->P, f64, c->x, c->u, c->q, c->qf, c->kb64, c->kb32, c->Ff, kick, s); }));
+    const EvalArgs a = make_args(c, stepping, dt);
+    TRY(timed(c, K_KDQ, [&] { launch_kdq(a, s); }));
+    TRY(timed(c, K_SCAN, [&] { launch_scan(a, s); }));
+    TRY(timed(c, K_SCATTER, [&] { launch_cell_scatter(a, s); }));
+    TRY(timed(c, K_SORTG, [&] { launch_sort_gather(a, s); }));
+    TRY(timed(c, K_NEAR, [&] { launch_near(a, f64, c->near_items, c->n_near, s); }));
+    TRY(timed(c, K_RHO, [&] { launch_rho(a, f64, c->rho_items, c->n_rho, s); }));
+    TRY(timed(c, K_RHORED, [&] { launch_rho_reduce(a, s); }));
+    TRY(timed(c, K_FAR, [&] { launch_far(a, f64, c->far_items, c->n_far, s); }));
     HIPCHK(c, hipGetLastError());
     return RBSOG_OK;
 }
 
 void account_eval(rbsog_ctx *c) {
-    c->cursor += c->P;
+    for (auto &h : c->sys) h.cursor += h.P;
     c->evals += 1;
     c->forces_valid = true;
+    c->parity = 1 - c->parity;
 }
 
-void drop_graph(rbsog_ctx *c) {
-    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
-    c->graph_exec = nullptr;
-    c->graph = nullptr;
+void drop_graphs(rbsog_ctx *c) {
+    for (int p = 0; p < 2; ++p) {
+        if (c->graph_exec[p]) (void)hipGraphExecDestroy(c->graph_exec[p]);
+        if (c->graph[p]) (void)hipGraphDestroy(c->graph[p]);
+        c->graph_exec[p] = nullptr;
+        c->graph[p] = nullptr;
+    }
 }
 
-// The graph of one step captures the kernel arguments: it is rebuilt when dt
-// or a buffer it reads (the sequence and its weights) changes.
-rbsog_status ensure_step_graph(rbsog_ctx *c, double dt) {
-    const void *key[3] = {c->dkseq, c->custom_w ? (const void *)c->dkw : nullptr, (const void *)c->x};
-    if (c->graph_exec && c->graph_dt == dt && std::equal(key, key + 3, c->graph_key)) return RBSOG_OK;
-    drop_graph(c);
-    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
-    rbsog_status st = enqueue_eval(c, true, dt);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(c->stream, &g);
-    if (st != RBSOG_OK) {
-        if (g) (void)hipGraphDestroy(g);
-        return st;
+// The graph of one step captures the kernel arguments: one graph per buffer
+// parity, rebuilt when dt changes.  Sequence buffers are reached through the
+// per-system table, so re-sampling does not invalidate them.
+rbsog_status ensure_step_graphs(rbsog_ctx *c, double dt) {
+    if (c->graph_exec[0] && c->graph_exec[1] && c->graph_dt == dt) return RBSOG_OK;
+    drop_graphs(c);
+    const int keep = c->parity;
+    for (int p = 0; p < 2; ++p) {
+        c->parity = p;
+        HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+        rbsog_status st = enqueue_eval(c, true, dt);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->stream, &g);
+        c->parity = keep;
+        if (st != RBSOG_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            drop_graphs(c);
+            return st;
+        }
+        if (e != hipSuccess) {
+            drop_graphs(c);
+            return fail(c, RBSOG_E_DEVICE, "stream capture: %s", hipGetErrorString(e));
+        }
+        c->graph[p] = g;
+        e = hipGraphInstantiate(&c->graph_exec[p], g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graphs(c);
+            return fail(c, RBSOG_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+        }
     }
-    if (e != hipSuccess) return fail(c, RBSOG_E_DEVICE, "stream capture: %s", hipGetErrorString(e));
-    c->graph = g;
-    e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-        drop_graph(c);
-        return fail(c, RBSOG_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
-    }
+    c->parity = keep;
     c->graph_dt = dt;
-    std::copy(key, key + 3, c->graph_key);
     return RBSOG_OK;
 }
-
-bool usable(rbsog_ctx *c) { return c && !c->poisoned; }
 
 rbsog_status check_ctx(rbsog_ctx *c) {
     if (!c) return fail(nullptr, RBSOG_E_ARG, "null context");
@@ -447,25 +533,369 @@ rbsog_status check_ctx(rbsog_ctx *c) {
     return RBSOG_OK;
 }
 
-rbsog_status upload_positions(rbsog_ctx *c, const double *pos) {
-    std::vector<double> soa((size_t)c->n * 3);
-    for (int64_t i = 0; i < c->n; ++i)
-        for (int d = 0; d < 3; ++d) {
-            const double v = pos[3 * i + d];
-            if (!std::isfinite(v)) return fail(c, RBSOG_E_NONFINITE, "position %lld is not finite", (long long)i);
-            soa[(size_t)d * c->n + i] = v;
-        }
-    HIPCHK(c, hipMemcpy(c->x, soa.data(), soa.size() * sizeof(double), hipMemcpyHostToDevice));
-    c->forces_valid = false;
+rbsog_status check_sys(rbsog_ctx *c, int32_t s) {
+    if (s < 0 || s >= c->nsys) return fail(c, RBSOG_E_ARG, "system %d out of range [0, %d)", s, c->nsys);
     return RBSOG_OK;
 }
 
-rbsog_status soa_to_host(rbsog_ctx *c, const double *dev, double *host) {
-    std::vector<double> soa((size_t)c->n * 3);
+// ids of the current cell order (slot -> caller index)
+rbsog_status current_ids(rbsog_ctx *c, std::vector<int32_t> &id) {
+    id.resize((size_t)c->N);
+    HIPCHK(c, hipMemcpyAsync(id.data(), c->buf[c->parity].id, (size_t)c->N * sizeof(int32_t), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RBSOG_OK;
+}
+
+// host n x 3 in caller order -> device SoA in the current cell order
+rbsog_status upload_by_id(rbsog_ctx *c, const double *host, double *dev, const char *what) {
+    std::vector<int32_t> id;
+    TRY(current_ids(c, id));
+    std::vector<double> soa((size_t)c->N * 3);
+    for (int64_t t = 0; t < c->N; ++t)
+        for (int d = 0; d < 3; ++d) {
+            const double v = host[3 * (int64_t)id[t] + d];
+            if (!std::isfinite(v)) return fail(c, RBSOG_E_NONFINITE, "%s of particle %d is not finite", what, id[t]);
+            soa[(size_t)d * c->N + t] = v;
+        }
+    HIPCHK(c, hipMemcpy(dev, soa.data(), soa.size() * sizeof(double), hipMemcpyHostToDevice));
+    return RBSOG_OK;
+}
+
+// device SoA in the current cell order -> host n x 3 in caller order
+rbsog_status download_by_id(rbsog_ctx *c, const double *dev, double *host) {
+    std::vector<int32_t> id;
+    TRY(current_ids(c, id));
+    std::vector<double> soa((size_t)c->N * 3);
     HIPCHK(c, hipMemcpyAsync(soa.data(), dev, soa.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (int64_t i = 0; i < c->n; ++i)
-        for (int d = 0; d < 3; ++d) host[3 * i + d] = soa[(size_t)d * c->n + i];
+    for (int64_t t = 0; t < c->N; ++t)
+        for (int d = 0; d < 3; ++d) host[3 * (int64_t)id[t] + d] = soa[(size_t)d * c->N + t];
+    return RBSOG_OK;
+}
+
+// Split coefficients of the near kernel for one system.
+void build_split(SysHost &h, int nexp64, int nexp32) {
+    // explicit Gaussians and the tail polynomials:
+    // sum_{l >= nexp} omega_l e^{-x a_l} = sum_k (-1)^k/k! (sum_l omega_l a_l^k) x^k
+    // and the force weights 2 omega_l a_l e^{-x a_l} likewise (a_l = 1/s_l^2)
+    const int G = h.M + 1;
+    auto tail = [&](int l0, int k) {
+        double sp = 0.0, sf = 0.0, fact = 1.0;
+        for (int i = 2; i <= k; ++i) fact *= i;
+        for (int l = l0; l < G; ++l) {
+            const double a = 1.0 / (h.s[l] * h.s[l]);
+            sp += h.omega[l] * std::pow(a, k);
+            sf += 2.0 * h.omega[l] * std::pow(a, k + 1);
+        }
+        const double sgn = (k & 1) ? -1.0 : 1.0;
+        return std::make_pair(sgn * sp / fact, sgn * sf / fact);
+    };
+    h.co64 = SplitCoef64{};
+    h.co32 = SplitCoef32{};
+    h.co64.nexp = nexp64;
+    h.co32.nexp = nexp32;
+    for (int l = 0; l < nexp64; ++l) {
+        const double is2 = 1.0 / (h.s[l] * h.s[l]);
+        h.co64.a[l] = is2;
+        h.co64.cw[l] = 2.0 * h.omega[l] * is2;
+        h.co64.w[l] = h.omega[l];
+    }
+    for (int l = 0; l < nexp32; ++l) {
+        const double is2 = 1.0 / (h.s[l] * h.s[l]);
+        h.co32.a[l] = (float)(is2 / std::log(2.0));
+        h.co32.cw[l] = (float)(2.0 * h.omega[l] * is2);
+        h.co32.w[l] = (float)h.omega[l];
+    }
+    for (int k = 0; k <= kTailDeg64; ++k) {
+        const auto pf = tail(nexp64, k);
+        h.co64.pt[k] = pf.first;
+        h.co64.ft[k] = pf.second;
+    }
+    for (int k = 0; k <= kTailDeg32; ++k) {
+        const auto pf = tail(nexp32, k);
+        h.co32.pt[k] = (float)pf.first;
+        h.co32.ft[k] = (float)pf.second;
+    }
+}
+
+// Validates one system and fills its host record (everything but offsets
+// and work lists).
+rbsog_status setup_system(SysHost &h, int64_t n, const double *pos, const double *q, const double *box,
+                          const rbsog_sog *sog, double rc, int32_t P, uint64_t seed, double neutral_tol, int32_t idx) {
+    if (n < 2) return fail(nullptr, RBSOG_E_ARG, "system %d: n must be >= 2", idx);
+    if (P < 1) return fail(nullptr, RBSOG_E_ARG, "system %d: P must be >= 1", idx);
+    for (int d = 0; d < 3; ++d)
+        if (!(box[d] > 0.0) || !std::isfinite(box[d]))
+            return fail(nullptr, RBSOG_E_ARG, "system %d: box sides must be > 0", idx);
+    if (!(sog->b > 1.0) || !std::isfinite(sog->b) || !(sog->sigma > 0.0) || !std::isfinite(sog->sigma) ||
+        !(sog->w0 > 0.0) || !std::isfinite(sog->w0) || sog->M < 0 || sog->M + 1 > kMaxGauss)
+        return fail(nullptr, RBSOG_E_SOG, "system %d: split parameters need b > 1, sigma > 0, w0 > 0, 0 <= M < %d",
+                    idx, kMaxGauss);
+    const double lmin = std::min(box[0], std::min(box[1], box[2]));
+    if (!(rc > 0.0) || !(rc <= 0.5 * lmin))
+        return fail(nullptr, RBSOG_E_CUTOFF, "system %d: need 0 < rc <= min(L)/2", idx);
+    double qs = 0.0, qa = 0.0, q2 = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!std::isfinite(q[i]))
+            return fail(nullptr, RBSOG_E_NONFINITE, "system %d: charge %lld is not finite", idx, (long long)i);
+        qs += q[i];
+        qa += std::fabs(q[i]);
+        q2 += q[i] * q[i];
+    }
+    if (std::fabs(qs) > neutral_tol * qa)
+        return fail(nullptr, RBSOG_E_NOT_NEUTRAL, "system %d: sum q = %.17g exceeds %.3g * sum|q|", idx, qs,
+                    neutral_tol);
+    for (int64_t i = 0; i < 3 * n; ++i)
+        if (!std::isfinite(pos[i]))
+            return fail(nullptr, RBSOG_E_NONFINITE, "system %d: position entry %lld is not finite", idx, (long long)i);
+    h.n = n;
+    std::copy(box, box + 3, h.box);
+    h.rc = rc;
+    h.P = P;
+    h.seed = seed;
+    h.M = sog->M;
+    sog_coefficients(*sog, h.omega, h.s);
+    h.V = box[0] * box[1] * box[2];
+    h.S = normaliser_S(h.omega, h.s, box);
+    h.w_rb = h.S * std::pow(kPi, 1.5) / ((double)P * h.V);
+    double f0 = 0.0;
+    for (double w : h.omega) f0 += w;
+    h.uself = 0.5 * f0 * q2;
+    Geom &g = h.g;
+    g.n = n;
+    double hmax = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        g.L[d] = box[d];
+        g.invL[d] = 1.0 / box[d];
+        g.h[d] = box[d] / kTwo32;
+        g.hf[d] = (float)g.h[d];
+        hmax = std::max(hmax, g.h[d]);
+        const int64_t k = (int64_t)std::floor(box[d] / rc);
+        g.nc[d] = (int32_t)(k >= 3 ? k : 1);
+        g.reach[d] = g.nc[d] >= 3 ? 1 : 0;
+    }
+    g.rc2 = rc * rc;
+    const double d64 = 32.0 * hmax / rc + 1e-12;
+    // the FP32 test runs on cell-relative float coordinates (cells up to 3 r_c
+    // wide): its r^2 is within 2e-5 relative of the exact value
+    const double d32 = d64 + 3e-5;
+    g.band_lo = g.rc2 * (1.0 - d64);
+    g.band_hi = g.rc2 * (1.0 + d64);
+    g.band_lo_f = (float)(g.rc2 * (1.0 - d32));
+    g.band_hi_f = (float)(g.rc2 * (1.0 + d32));
+    // Gaussians wide enough that exp(-x/s_l^2) is a short Taylor series over
+    // x = r^2 <= rc^2 form the tail; s_l grows with l, so they are l >= nexp.
+    auto first_wide = [&](double tau) {
+        for (int l = 0; l <= h.M; ++l)
+            if (rc * rc / (h.s[l] * h.s[l]) <= tau) return l;
+        return h.M + 1;
+    };
+    const int nexp64 = first_wide(kTailTau64), nexp32 = first_wide(kTailTau32);
+    if (nexp64 > kMaxExp)
+        return fail(nullptr, RBSOG_E_SOG, "system %d: more than %d Gaussians narrower than r_c / sqrt(%g)", idx,
+                    kMaxExp, kTailTau64);
+    build_split(h, nexp64, nexp32);
+    h.ncell = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
+    return RBSOG_OK;
+}
+
+// Work lists of the batch.  Near: runs of about `cells_per_item` cells of one
+// system; rho: particle chunks of about `chunk` slots x k-tile groups; far:
+// runs of 256 slots.
+void build_work(rbsog_ctx *c, std::vector<NearItem> &near, std::vector<RhoItem> &rho, std::vector<FarItem> &far) {
+    const int64_t cpi = std::max<int64_t>(1, std::min<int64_t>(64, (c->C + 8191) / 8192));
+    const int64_t chunk = std::max<int64_t>(256, (c->N + 511) / 512);
+    int64_t pofs = 0;
+    for (int32_t s = 0; s < c->nsys; ++s) {
+        SysHost &h = c->sys[s];
+        h.it0 = (int32_t)near.size();
+        for (int64_t cb = 0; cb < h.ncell; cb += cpi)
+            near.push_back(NearItem{s, 0, h.c0 + cb, h.c0 + std::min(h.ncell, cb + cpi)});
+        h.it1 = (int32_t)near.size();
+        const int32_t ktiles = (h.P + 63) / 64;
+        h.kt = std::min(ktiles, 16);
+        h.streams = std::max(1, 16 / h.kt);
+        const int32_t kgroups = (ktiles + h.kt - 1) / h.kt;
+        h.nch = (int32_t)std::max<int64_t>(1, (h.n + chunk - 1) / chunk);
+        const int64_t per = (h.n + h.nch - 1) / h.nch;
+        for (int32_t kg = 0; kg < kgroups; ++kg)
+            for (int32_t ch = 0; ch < h.nch; ++ch) {
+                const int64_t j0 = h.p0 + std::min(h.n, ch * per), j1 = h.p0 + std::min(h.n, (ch + 1) * per);
+                rho.push_back(RhoItem{s, kg, ch, 0, j0, j1});
+            }
+        h.pofs = pofs;
+        pofs += (int64_t)h.nch * h.P;
+        for (int64_t t = 0; t < h.n; t += 256)
+            far.push_back(FarItem{s, 0, h.p0 + t, h.p0 + std::min(h.n, t + 256)});
+    }
+}
+
+rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, const double *pos, const double *q,
+                        const double *boxes, const rbsog_sog *sog, const double *rc, const int32_t *P,
+                        const uint64_t *seeds, const rbsog_opts *opts) {
+    if (!out) return fail(nullptr, RBSOG_E_ARG, "out is null");
+    *out = nullptr;
+    if (nsys < 1) return fail(nullptr, RBSOG_E_ARG, "need at least one system");
+    if (!offsets || !pos || !q || !boxes || !sog || !rc || !P || !seeds)
+        return fail(nullptr, RBSOG_E_ARG, "null input pointer");
+    if (offsets[0] != 0) return fail(nullptr, RBSOG_E_ARG, "offsets[0] must be 0");
+    for (int32_t s = 0; s < nsys; ++s)
+        if (offsets[s + 1] < offsets[s] + 2) return fail(nullptr, RBSOG_E_ARG, "system %d has fewer than 2 particles", s);
+    if (offsets[nsys] > (int64_t)INT32_MAX) return fail(nullptr, RBSOG_E_ARG, "more than 2^31-1 particles");
+    rbsog_opts o;
+    rbsog_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.precision != RBSOG_FP64 && o.precision != RBSOG_FP32C)
+        return fail(nullptr, RBSOG_E_ARG, "unknown precision %d", o.precision);
+    if (!(o.mass > 0.0) || !std::isfinite(o.mass)) return fail(nullptr, RBSOG_E_ARG, "mass must be > 0");
+    if (!(o.neutral_tol >= 0.0)) return fail(nullptr, RBSOG_E_ARG, "neutral_tol must be >= 0");
+
+    rbsog_ctx *c = new rbsog_ctx();
+    c->nsys = nsys;
+    c->sys.resize(nsys);
+    c->prec = o.precision;
+    c->device = o.device;
+    c->mass = o.mass;
+    c->use_graphs = o.graphs != 0;
+    for (int k = 0; k < K_COUNT; ++k) c->prof[k].name = kKernelNames[k];
+    for (int32_t s = 0; s < nsys; ++s) {
+        SysHost &h = c->sys[s];
+        const int64_t p0 = offsets[s], n = offsets[s + 1] - offsets[s];
+        rbsog_status st = setup_system(h, n, pos + 3 * p0, q + p0, boxes + 3 * s, sog + s, rc[s], P[s], seeds[s],
+                                       o.neutral_tol, s);
+        if (st != RBSOG_OK) {
+            delete c;
+            return st;
+        }
+        h.p0 = p0;
+        h.c0 = c->C;
+        h.k0 = c->K;
+        c->C += h.ncell;
+        if (c->C >= (int64_t)INT32_MAX || (int64_t)c->K + P[s] >= (int64_t)INT32_MAX) {
+            delete c;
+            return fail(nullptr, RBSOG_E_ARG, "too many cells or wave vectors");
+        }
+        c->K += P[s];
+    }
+    c->N = offsets[nsys];
+    c->q_host.assign(q, q + c->N);
+    std::vector<NearItem> near;
+    std::vector<RhoItem> rho;
+    std::vector<FarItem> far;
+    build_work(c, near, rho, far);
+    c->n_near = (int32_t)near.size();
+    c->n_rho = (int32_t)rho.size();
+    c->n_far = (int32_t)far.size();
+    int64_t npart = 0;
+    for (auto &h : c->sys) npart += (int64_t)h.nch * h.P;
+
+    auto bail = [&](rbsog_status st) {
+        g_init_error = c->err;
+        rbsog_destroy(c);
+        return st;
+    };
+    if (hipSetDevice(o.device) != hipSuccess) {
+        fail(c, RBSOG_E_DEVICE, "hipSetDevice(%d) failed", o.device);
+        return bail(RBSOG_E_DEVICE);
+    }
+    if (o.stream) {
+        c->stream = (hipStream_t)o.stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            fail(c, RBSOG_E_DEVICE, "hipStreamCreate failed");
+            return bail(RBSOG_E_DEVICE);
+        }
+        c->own_stream = true;
+    }
+    const int64_t N = c->N, C = c->C, K = c->K;
+    rbsog_status st = RBSOG_OK;
+#define ALLOC(ptr, cnt)                                   \
+    if ((st = dalloc(c, &c->ptr, (cnt))) != RBSOG_OK) return bail(st);
+    for (int p = 0; p < 2; ++p) {
+        ALLOC(buf[p].x, 3 * N);
+        ALLOC(buf[p].v, 3 * N);
+        ALLOC(buf[p].q, N);
+        ALLOC(buf[p].qf, N);
+        ALLOC(buf[p].id, N);
+    }
+    ALLOC(dsys, nsys);
+    ALLOC(sys_of, N);
+    ALLOC(ksys, K);
+    ALLOC(u_tmp, 3 * N);
+    ALLOC(u, 3 * N);
+    ALLOC(cell_of, N);
+    ALLOC(src, N);
+    ALLOC(cell_count, C);
+    ALLOC(cell_start, C + 1);
+    ALLOC(cell_fill, C);
+    ALLOC(blocksums, scan_blocksums_size(C));
+    ALLOC(Fn, 3 * N);
+    ALLOC(Ff, 3 * N);
+    ALLOC(kcur, nsys);
+    ALLOC(kb64, K);
+    ALLOC(kb32, K);
+    ALLOC(wk, K);
+    ALLOC(rho, 2 * K);
+    ALLOC(ek, K);
+    ALLOC(partial, 2 * npart);
+    ALLOC(epart, c->n_near);
+    ALLOC(E, 4 * (int64_t)nsys);
+    ALLOC(flag, 1);
+    ALLOC(sys_done, nsys);
+    ALLOC(near_items, c->n_near);
+    ALLOC(rho_items, c->n_rho);
+    ALLOC(far_items, c->n_far);
+#undef ALLOC
+    {
+        // initial state in the caller's order (slot t holds particle t)
+        std::vector<double> soa((size_t)3 * N), zero((size_t)3 * N, 0.0);
+        for (int64_t i = 0; i < N; ++i)
+            for (int d = 0; d < 3; ++d) soa[(size_t)d * N + i] = pos[3 * i + d];
+        std::vector<float> qff(N);
+        std::vector<int32_t> ids(N), sof(N), ks(K);
+        for (int64_t i = 0; i < N; ++i) {
+            qff[i] = (float)q[i];
+            ids[i] = (int32_t)i;
+        }
+        for (int32_t s = 0; s < nsys; ++s) {
+            const SysHost &h = c->sys[s];
+            for (int64_t i = 0; i < h.n; ++i) sof[h.p0 + i] = s;
+            for (int32_t k = 0; k < h.P; ++k) ks[h.k0 + k] = s;
+        }
+        std::vector<SysDev> sd(nsys);
+        for (int32_t s = 0; s < nsys; ++s) sd[s] = sysdev_of(c->sys[s]);
+        std::vector<int64_t> zc(nsys, 0);
+        std::vector<uint32_t> zu(nsys, 0u);
+        const int32_t zf = 0;
+        const StateBufs &b = c->buf[0];
+        bool ok = hipMemcpy(b.x, soa.data(), soa.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(b.v, zero.data(), zero.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(b.q, q, N * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(b.qf, qff.data(), N * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(b.id, ids.data(), N * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(c->Fn, zero.data(), zero.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(c->Ff, zero.data(), zero.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(c->sys_of, sof.data(), N * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(c->ksys, ks.data(), K * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(c->dsys, sd.data(), nsys * sizeof(SysDev), hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(c->kcur, zc.data(), nsys * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(c->sys_done, zu.data(), nsys * sizeof(uint32_t), hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(c->flag, &zf, sizeof zf, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemset(c->cell_count, 0, (size_t)C * sizeof(int32_t)) == hipSuccess &&
+                  hipMemcpy(c->near_items, near.data(), near.size() * sizeof(NearItem), hipMemcpyHostToDevice) ==
+                      hipSuccess &&
+                  hipMemcpy(c->rho_items, rho.data(), rho.size() * sizeof(RhoItem), hipMemcpyHostToDevice) ==
+                      hipSuccess &&
+                  hipMemcpy(c->far_items, far.data(), far.size() * sizeof(FarItem), hipMemcpyHostToDevice) == hipSuccess;
+        if (!ok) {
+            fail(c, RBSOG_E_DEVICE, "initial upload failed");
+            return bail(RBSOG_E_DEVICE);
+        }
+    }
+    for (int32_t s = 0; s < nsys; ++s)
+        if ((st = ensure_kcap(c, s, 4 * (int64_t)c->sys[s].P)) != RBSOG_OK) return bail(st);
+    *out = c;
     return RBSOG_OK;
 }
 
@@ -505,245 +935,48 @@ rbsog_status rbsog_init(rbsog_ctx **out, int64_t n, const double *pos, const dou
                         const rbsog_sog *sog, double rc, int32_t P, uint64_t seed, const rbsog_opts *opts) {
     if (!out) return fail(nullptr, RBSOG_E_ARG, "out is null");
     *out = nullptr;
-    if (!pos || !q || !box || !sog) return fail(nullptr, RBSOG_E_ARG, "null input pointer");
     if (n < 2 || n > (int64_t)INT32_MAX) return fail(nullptr, RBSOG_E_ARG, "n must be in [2, 2^31-1]");
-    if (P < 1) return fail(nullptr, RBSOG_E_ARG, "P must be >= 1");
-    rbsog_opts o;
-    rbsog_default_opts(&o);
-    if (opts) o = *opts;
-    if (o.precision != RBSOG_FP64 && o.precision != RBSOG_FP32C)
-        return fail(nullptr, RBSOG_E_ARG, "unknown precision %d", o.precision);
-    if (!(o.mass > 0.0) || !std::isfinite(o.mass)) return fail(nullptr, RBSOG_E_ARG, "mass must be > 0");
-    if (!(o.neutral_tol >= 0.0)) return fail(nullptr, RBSOG_E_ARG, "neutral_tol must be >= 0");
-    for (int d = 0; d < 3; ++d)
-        if (!(box[d] > 0.0) || !std::isfinite(box[d])) return fail(nullptr, RBSOG_E_ARG, "box sides must be > 0");
-    if (!(sog->b > 1.0) || !std::isfinite(sog->b) || !(sog->sigma > 0.0) || !std::isfinite(sog->sigma) ||
-        !(sog->w0 > 0.0) || !std::isfinite(sog->w0) || sog->M < 0 || sog->M + 1 > kMaxGauss)
-        return fail(nullptr, RBSOG_E_SOG, "split parameters need b > 1, sigma > 0, w0 > 0, 0 <= M < %d", kMaxGauss);
-    const double lmin = std::min(box[0], std::min(box[1], box[2]));
-    if (!(rc > 0.0) || !(rc <= 0.5 * lmin)) return fail(nullptr, RBSOG_E_CUTOFF, "need 0 < rc <= min(L)/2");
-    double qs = 0.0, qa = 0.0, q2 = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-        if (!std::isfinite(q[i])) return fail(nullptr, RBSOG_E_NONFINITE, "charge %lld is not finite", (long long)i);
-        qs += q[i];
-        qa += std::fabs(q[i]);
-        q2 += q[i] * q[i];
-    }
-    if (std::fabs(qs) > o.neutral_tol * qa)
-        return fail(nullptr, RBSOG_E_NOT_NEUTRAL, "sum q = %.17g exceeds %.3g * sum|q|", qs, o.neutral_tol);
-    for (int64_t i = 0; i < 3 * n; ++i)
-        if (!std::isfinite(pos[i])) return fail(nullptr, RBSOG_E_NONFINITE, "position entry %lld is not finite",
-                                                (long long)i);
+    const int64_t offsets[2] = {0, n};
+    return init_batch(out, 1, offsets, pos, q, box, sog, &rc, &P, &seed, opts);
+}
 
-    rbsog_ctx *c = new rbsog_ctx();
-    c->n = n;
-    std::copy(box, box + 3, c->box);
-    c->rc = rc;
-    c->P = P;
-    c->seed = seed;
-    c->prec = o.precision;
-    c->device = o.device;
-    c->mass = o.mass;
-    c->use_graphs = o.graphs != 0;
-    c->M = sog->M;
-    sog_coefficients(*sog, c->omega, c->s);
-    c->V = box[0] * box[1] * box[2];
-    c->S = normaliser_S(c->omega, c->s, box);
-    c->w_rb = c->S * std::pow(kPi, 1.5) / ((double)P * c->V);
-    double f0 = 0.0;
-    for (double w : c->omega) f0 += w;
-    c->uself = 0.5 * f0 * q2;
-    for (int k = 0; k < K_COUNT; ++k) c->prof[k].name = kKernelNames[k];
-
-    Geom &g = c->geom;
-    g.n = n;
-    double hmax = 0.0;
-    for (int d = 0; d < 3; ++d) {
-        g.L[d] = box[d];
-        g.invL[d] = 1.0 / box[d];
-        g.h[d] = box[d] / kTwo32;
-        g.hf[d] = (float)g.h[d];
-        hmax = std::max(hmax, g.h[d]);
-        const int64_t k = (int64_t)std::floor(box[d] / rc);
-        g.nc[d] = (int32_t)(k >= 3 ? k : 1);
-        g.reach[d] = g.nc[d] >= 3 ? 1 : 0;
-    }
-    g.rc2 = rc * rc;
-    const double d64 = 32.0 * hmax / rc + 1e-12;
-    // the FP32 test runs on cell-relative float coordinates (cells up to 3 r_c
-    // wide): its r^2 is within 2e-5 relative of the exact value
-    const double d32 = d64 + 3e-5;
-    g.band_lo = g.rc2 * (1.0 - d64);
-    g.band_hi = g.rc2 * (1.0 + d64);
-    g.band_lo_f = (float)(g.rc2 * (1.0 - d32));
-    g.band_hi_f = (float)(g.rc2 * (1.0 + d32));
-    // Gaussians wide enough that exp(-x/s_l^2) is a short Taylor series over
-    // x = r^2 <= rc^2 form the tail; s_l grows with l, so they are l >= nexp.
-    auto first_wide = [&](double tau) {
-        for (int l = 0; l <= c->M; ++l)
-            if (rc * rc / (c->s[l] * c->s[l]) <= tau) return l;
-        return c->M + 1;
-    };
-    const int nexp64 = first_wide(kTailTau64), nexp32 = first_wide(kTailTau32);
-    if (nexp64 > kMaxExp) {
-        delete c;
-        return fail(nullptr, RBSOG_E_SOG, "more than 24 Gaussians narrower than r_c / sqrt(0.05)");
-    }
-    c->ncell = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
-    if (c->ncell >= (int64_t)INT32_MAX) {
-        delete c;
-        return fail(nullptr, RBSOG_E_ARG, "too many cells");
-    }
-    c->fplan = far_plan(n, P);
-    c->nplan = near_plan(c->ncell);
-
-    auto bail = [&](rbsog_status st) {
-        g_init_error = c->err;
-        rbsog_destroy(c);
-        return st;
-    };
-    if (hipSetDevice(o.device) != hipSuccess) {
-        fail(c, RBSOG_E_DEVICE, "hipSetDevice(%d) failed", o.device);
-        return bail(RBSOG_E_DEVICE);
-    }
-    if (o.stream) {
-        c->stream = (hipStream_t)o.stream;
-    } else {
-        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
-            fail(c, RBSOG_E_DEVICE, "hipStreamCreate failed");
-            return bail(RBSOG_E_DEVICE);
-        }
-        c->own_stream = true;
-    }
-    rbsog_status st = RBSOG_OK;
-#define ALLOC(ptr, cnt)                                   \
-    if ((st = dalloc(c, &c->ptr, (cnt))) != RBSOG_OK) return bail(st);
-    ALLOC(x, 3 * n);
-    ALLOC(v, 3 * n);
-    ALLOC(q, n);
-    ALLOC(qf, n);
-    ALLOC(Fn, 3 * n);
-    ALLOC(Ff, 3 * n);
-    ALLOC(u, 3 * n);
-    ALLOC(su, 3 * n);
-    ALLOC(sqf, n);
-    if (c->prec == RBSOG_FP64) {
-        ALLOC(sx, 3 * n);
-        ALLOC(sq, n);
-    }
-    ALLOC(cell_of, n);
-    ALLOC(order, n);
-    ALLOC(cell_count, c->ncell);
-    ALLOC(cell_start, c->ncell + 1);
-    ALLOC(cell_fill, c->ncell);
-    ALLOC(blocksums, scan_blocksums_size(c->ncell));
-    ALLOC(dcursor, 1);
-    ALLOC(kb64, P);
-    ALLOC(kb32, P);
-    ALLOC(wk, P);
-    ALLOC(rho, 2 * (int64_t)P);
-    ALLOC(ek, P);
-    ALLOC(partial, 2 * c->fplan.nblk * (int64_t)P);
-    ALLOC(epart, c->nplan.nblk);
-    ALLOC(E, 4);
-    ALLOC(flag, 1);
-    ALLOC(counter, 1);
-#undef ALLOC
-    {
-        // explicit Gaussians and the tail polynomials:
-        // sum_{l >= nexp} omega_l e^{-x a_l} = sum_k (-1)^k/k! (sum_l omega_l a_l^k) x^k
-        // and the force weights 2 omega_l a_l e^{-x a_l} likewise (a_l = 1/s_l^2)
-        const int G = c->M + 1;
-        auto tail = [&](int l0, int k) {
-            double sp = 0.0, sf = 0.0, fact = 1.0;
-            for (int i = 2; i <= k; ++i) fact *= i;
-            for (int l = l0; l < G; ++l) {
-                const double a = 1.0 / (c->s[l] * c->s[l]);
-                sp += c->omega[l] * std::pow(a, k);
-                sf += 2.0 * c->omega[l] * std::pow(a, k + 1);
-            }
-            const double sgn = (k & 1) ? -1.0 : 1.0;
-            return std::make_pair(sgn * sp / fact, sgn * sf / fact);
-        };
-        SplitCoef64 &h64 = c->co64;
-        SplitCoef32 &h32 = c->co32;
-        h64.nexp = nexp64;
-        h32.nexp = nexp32;
-        for (int l = 0; l < nexp64; ++l) {
-            const double is2 = 1.0 / (c->s[l] * c->s[l]);
-            h64.a[l] = is2;
-            h64.cw[l] = 2.0 * c->omega[l] * is2;
-            h64.w[l] = c->omega[l];
-        }
-        for (int l = 0; l < nexp32; ++l) {
-            const double is2 = 1.0 / (c->s[l] * c->s[l]);
-            h32.a[l] = (float)(is2 / std::log(2.0));
-            h32.cw[l] = (float)(2.0 * c->omega[l] * is2);
-            h32.w[l] = (float)c->omega[l];
-        }
-        for (int k = 0; k <= kTailDeg64; ++k) {
-            const auto pf = tail(nexp64, k);
-            h64.pt[k] = pf.first;
-            h64.ft[k] = pf.second;
-        }
-        for (int k = 0; k <= kTailDeg32; ++k) {
-            const auto pf = tail(nexp32, k);
-            h32.pt[k] = (float)pf.first;
-            h32.ft[k] = (float)pf.second;
-        }
-    }
-    {
-        std::vector<double> qd(q, q + n);
-        std::vector<float> qff(n);
-        for (int64_t i = 0; i < n; ++i) qff[i] = (float)q[i];
-        std::vector<double> zero((size_t)3 * n, 0.0);
-        const int64_t zc = 0;
-        const int32_t zf = 0;
-        if (hipMemcpy(c->q, qd.data(), n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(c->qf, qff.data(), n * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(c->v, zero.data(), zero.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(c->Fn, zero.data(), zero.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(c->Ff, zero.data(), zero.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(c->dcursor, &zc, sizeof zc, hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(c->flag, &zf, sizeof zf, hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemset(c->counter, 0, sizeof(uint32_t)) != hipSuccess ||
-            hipMemset(c->cell_count, 0, (size_t)c->ncell * sizeof(int32_t)) != hipSuccess) {
-            fail(c, RBSOG_E_DEVICE, "initial upload failed");
-            return bail(RBSOG_E_DEVICE);
-        }
-    }
-    if ((st = upload_positions(c, pos)) != RBSOG_OK) return bail(st);
-    if ((st = ensure_kcap(c, 4 * (int64_t)P)) != RBSOG_OK) return bail(st);
-    *out = c;
-    return RBSOG_OK;
+rbsog_status rbsog_init_batch(rbsog_ctx **out, int32_t n_sys, const int64_t *offsets, const double *pos,
+                              const double *q, const double *boxes, const rbsog_sog *sog, const double *rc,
+                              const int32_t *P, const uint64_t *seeds, const rbsog_opts *opts) {
+    return init_batch(out, n_sys, offsets, pos, q, boxes, sog, rc, P, seeds, opts);
 }
 
 rbsog_status rbsog_sample_k(rbsog_ctx *c, int64_t n_batches, int32_t *m_out) {
     TRY(check_ctx(c));
     if (n_batches < 1) return fail(c, RBSOG_E_ARG, "n_batches must be >= 1");
-    const int64_t from = (int64_t)c->kseq.size() / 3;
-    if (c->custom_w) {
-        // a caller-given weighted list is replaced by the sampled sequence
-        c->kseq.clear();
-        c->kw.clear();
-        c->custom_w = false;
-        c->cursor = 0;
-        const int64_t zc = 0;
-        HIPCHK(c, hipMemcpy(c->dcursor, &zc, sizeof zc, hipMemcpyHostToDevice));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int64_t written = 0;
+    for (int32_t s = 0; s < c->nsys; ++s) {
+        SysHost &h = c->sys[s];
+        if (h.custom_w) {
+            // a caller-given weighted list is replaced by the sampled sequence
+            h.kseq.clear();
+            h.kw.clear();
+            h.custom_w = false;
+            h.cursor = 0;
+            TRY(upload_cursor(c, s));
+            TRY(upload_sysdev(c, s));
+        }
+        const int64_t start = (int64_t)h.kseq.size() / 3;
+        std::vector<int32_t> fresh;
+        fresh.reserve((size_t)(n_batches * h.P * 3));
+        mh_extend(&h, n_batches * h.P, fresh);
+        h.kseq.insert(h.kseq.end(), fresh.begin(), fresh.end());
+        TRY(upload_k(c, s, start));
+        if (m_out) std::copy(fresh.begin(), fresh.end(), m_out + written);
+        written += (int64_t)fresh.size();
     }
-    const int64_t start = (int64_t)c->kseq.size() / 3;
-    std::vector<int32_t> fresh;
-    fresh.reserve((size_t)(n_batches * c->P * 3));
-    mh_extend(c, n_batches * c->P, fresh);
-    c->kseq.insert(c->kseq.end(), fresh.begin(), fresh.end());
-    TRY(upload_k(c, start));
-    if (m_out) std::copy(fresh.begin(), fresh.end(), m_out);
-    (void)from;
     return RBSOG_OK;
 }
 
-rbsog_status rbsog_set_k(rbsog_ctx *c, int64_t n_k, const int32_t *m, const double *w) {
+rbsog_status rbsog_set_k(rbsog_ctx *c, int32_t sys, int64_t n_k, const int32_t *m, const double *w) {
     TRY(check_ctx(c));
+    TRY(check_sys(c, sys));
     if (n_k < 1 || !m) return fail(c, RBSOG_E_ARG, "need n_k >= 1 vectors");
     for (int64_t e = 0; e < n_k; ++e) {
         if (m[3 * e] == 0 && m[3 * e + 1] == 0 && m[3 * e + 2] == 0)
@@ -751,31 +984,41 @@ rbsog_status rbsog_set_k(rbsog_ctx *c, int64_t n_k, const int32_t *m, const doub
         if (w && !std::isfinite(w[e])) return fail(c, RBSOG_E_NONFINITE, "weight %lld is not finite", (long long)e);
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->kseq.assign(m, m + 3 * n_k);
-    c->custom_w = w != nullptr;
-    if (w) c->kw.assign(w, w + n_k);
-    else c->kw.clear();
-    c->cursor = 0;
-    const int64_t zc = 0;
-    HIPCHK(c, hipMemcpy(c->dcursor, &zc, sizeof zc, hipMemcpyHostToDevice));
-    return upload_k(c, 0);
+    SysHost &h = c->sys[sys];
+    h.kseq.assign(m, m + 3 * n_k);
+    h.custom_w = w != nullptr;
+    if (w) h.kw.assign(w, w + n_k);
+    else h.kw.clear();
+    h.cursor = 0;
+    TRY(upload_cursor(c, sys));
+    TRY(upload_k(c, sys, 0));
+    return upload_sysdev(c, sys);
+}
+
+static rbsog_status check_kseq(rbsog_ctx *c, int64_t evals) {
+    for (int32_t s = 0; s < c->nsys; ++s) {
+        const SysHost &h = c->sys[s];
+        const int64_t nvec = (int64_t)h.kseq.size() / 3;
+        if (h.cursor + evals * h.P > nvec)
+            return fail(c, RBSOG_E_KSEQ, "system %d: %lld evaluations need %lld vectors, %lld remain", s,
+                        (long long)evals, (long long)(evals * h.P), (long long)(nvec - h.cursor));
+    }
+    return RBSOG_OK;
 }
 
 rbsog_status rbsog_forces(rbsog_ctx *c, double *F_out, double *E_out) {
     TRY(check_ctx(c));
-    const int64_t nvec = (int64_t)c->kseq.size() / 3;
-    if (c->cursor + c->P > nvec)
-        return fail(c, RBSOG_E_KSEQ, "sequence has %lld unused vectors, P = %d", (long long)(nvec - c->cursor), c->P);
+    TRY(check_kseq(c, 1));
     TRY(enqueue_eval(c, false, 0.0));
     account_eval(c);
     if (F_out) {
-        std::vector<double> a((size_t)3 * c->n), b((size_t)3 * c->n);
-        TRY(soa_to_host(c, c->Fn, a.data()));
-        TRY(soa_to_host(c, c->Ff, b.data()));
-        for (size_t i = 0; i < a.size(); ++i) F_out[i] = a[i] + b[i];
+        std::vector<double> b((size_t)3 * c->N);
+        TRY(download_by_id(c, c->Fn, F_out));
+        TRY(download_by_id(c, c->Ff, b.data()));
+        for (size_t i = 0; i < b.size(); ++i) F_out[i] += b[i];
     }
     if (E_out) {
-        HIPCHK(c, hipMemcpyAsync(E_out, c->E, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(E_out, c->E, 4 * (size_t)c->nsys * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     return RBSOG_OK;
@@ -784,19 +1027,15 @@ rbsog_status rbsog_forces(rbsog_ctx *c, double *F_out, double *E_out) {
 rbsog_status rbsog_step(rbsog_ctx *c, int64_t n_steps, double dt) {
     TRY(check_ctx(c));
     if (n_steps < 0 || !std::isfinite(dt)) return fail(c, RBSOG_E_ARG, "need n_steps >= 0 and finite dt");
-    const int64_t need = (n_steps + (c->forces_valid ? 0 : 1)) * (int64_t)c->P;
-    const int64_t nvec = (int64_t)c->kseq.size() / 3;
-    if (c->cursor + need > nvec)
-        return fail(c, RBSOG_E_KSEQ, "%lld steps need %lld vectors, %lld remain", (long long)n_steps, (long long)need,
-                    (long long)(nvec - c->cursor));
+    TRY(check_kseq(c, n_steps + (c->forces_valid ? 0 : 1)));
     if (!c->forces_valid) {
         TRY(enqueue_eval(c, false, 0.0));
         account_eval(c);
     }
     const bool graphs = c->use_graphs && !c->prof_on && n_steps > 1;
-    if (graphs) TRY(ensure_step_graph(c, dt));
+    if (graphs) TRY(ensure_step_graphs(c, dt));
     for (int64_t k = 0; k < n_steps; ++k) {
-        if (graphs) HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+        if (graphs) HIPCHK(c, hipGraphLaunch(c->graph_exec[c->parity], c->stream));
         else TRY(enqueue_eval(c, true, dt));
         account_eval(c);
     }
@@ -809,137 +1048,153 @@ rbsog_status rbsog_step(rbsog_ctx *c, int64_t n_steps, double dt) {
 
 rbsog_status rbsog_set_velocities(rbsog_ctx *c, const double *v, double T, uint64_t seed) {
     TRY(check_ctx(c));
-    std::vector<double> soa((size_t)3 * c->n);
     if (v) {
-        for (int64_t i = 0; i < c->n; ++i)
-            for (int d = 0; d < 3; ++d) {
-                if (!std::isfinite(v[3 * i + d])) return fail(c, RBSOG_E_NONFINITE, "velocity %lld", (long long)i);
-                soa[(size_t)d * c->n + i] = v[3 * i + d];
-            }
-    } else {
-        if (!(T >= 0.0) || !std::isfinite(T)) return fail(c, RBSOG_E_ARG, "temperature must be >= 0");
-        const double sd = std::sqrt(T / c->mass);
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return upload_by_id(c, v, c->buf[c->parity].v, "velocity");
+    }
+    if (!(T >= 0.0) || !std::isfinite(T)) return fail(c, RBSOG_E_ARG, "temperature must be >= 0");
+    const double sd = std::sqrt(T / c->mass);
+    std::vector<double> vv((size_t)3 * c->N);
+    for (const SysHost &h : c->sys) {
         double mean[3] = {0, 0, 0};
-        for (int64_t i = 0; i < c->n; ++i) {
+        for (int64_t i = h.p0; i < h.p0 + h.n; ++i) {
             double u1, u2, u3, u4;
             Philox::uniform2(seed, 1, (uint64_t)i, 0, u1, u2);
             Philox::uniform2(seed, 1, (uint64_t)i, 1, u3, u4);
             const double r1 = std::sqrt(-2.0 * std::log(1.0 - u1)), r2 = std::sqrt(-2.0 * std::log(1.0 - u3));
             const double z[3] = {r1 * std::cos(2 * kPi * u2), r1 * std::sin(2 * kPi * u2), r2 * std::cos(2 * kPi * u4)};
             for (int d = 0; d < 3; ++d) {
-                soa[(size_t)d * c->n + i] = sd * z[d];
+                vv[3 * i + d] = sd * z[d];
                 mean[d] += sd * z[d];
             }
         }
         for (int d = 0; d < 3; ++d) {
-            mean[d] /= (double)c->n;
-            for (int64_t i = 0; i < c->n; ++i) soa[(size_t)d * c->n + i] -= mean[d];
+            mean[d] /= (double)h.n;
+            for (int64_t i = h.p0; i < h.p0 + h.n; ++i) vv[3 * i + d] -= mean[d];
         }
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, hipMemcpy(c->v, soa.data(), soa.size() * sizeof(double), hipMemcpyHostToDevice));
-    return RBSOG_OK;
+    return upload_by_id(c, vv.data(), c->buf[c->parity].v, "velocity");
 }
 
 rbsog_status rbsog_set_positions(rbsog_ctx *c, const double *pos) {
     TRY(check_ctx(c));
     if (!pos) return fail(c, RBSOG_E_ARG, "pos is null");
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    return upload_positions(c, pos);
+    TRY(upload_by_id(c, pos, c->buf[c->parity].x, "position"));
+    c->forces_valid = false;
+    return RBSOG_OK;
 }
 
 rbsog_status rbsog_get_state(rbsog_ctx *c, double *pos, double *vel) {
     TRY(check_ctx(c));
     if (pos) {
-        TRY(soa_to_host(c, c->x, pos));
+        TRY(download_by_id(c, c->buf[c->parity].x, pos));
         // the stored coordinates are wrapped at each evaluation; wrap here too
-        for (int64_t i = 0; i < c->n; ++i)
-            for (int d = 0; d < 3; ++d) {
-                const double t = pos[3 * i + d] / c->box[d];
-                pos[3 * i + d] = (t - std::floor(t)) * c->box[d];
-            }
+        for (const SysHost &h : c->sys)
+            for (int64_t i = h.p0; i < h.p0 + h.n; ++i)
+                for (int d = 0; d < 3; ++d) {
+                    const double t = pos[3 * i + d] / h.box[d];
+                    pos[3 * i + d] = (t - std::floor(t)) * h.box[d];
+                }
     }
-    if (vel) TRY(soa_to_host(c, c->v, vel));
+    if (vel) TRY(download_by_id(c, c->buf[c->parity].v, vel));
     return RBSOG_OK;
 }
 
 rbsog_status rbsog_get_forces(rbsog_ctx *c, double *F_near, double *F_far) {
     TRY(check_ctx(c));
     if (c->evals == 0) return fail(c, RBSOG_E_STATE, "no force evaluation yet");
-    if (F_near) TRY(soa_to_host(c, c->Fn, F_near));
-    if (F_far) TRY(soa_to_host(c, c->Ff, F_far));
+    if (F_near) TRY(download_by_id(c, c->Fn, F_near));
+    if (F_far) TRY(download_by_id(c, c->Ff, F_far));
     return RBSOG_OK;
 }
 
-rbsog_status rbsog_get_energy(rbsog_ctx *c, double *E4) {
+rbsog_status rbsog_get_energy(rbsog_ctx *c, double *E) {
     TRY(check_ctx(c));
     if (c->evals == 0) return fail(c, RBSOG_E_STATE, "no force evaluation yet");
-    if (!E4) return fail(c, RBSOG_E_ARG, "E4 is null");
-    HIPCHK(c, hipMemcpyAsync(E4, c->E, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (!E) return fail(c, RBSOG_E_ARG, "E is null");
+    HIPCHK(c, hipMemcpyAsync(E, c->E, 4 * (size_t)c->nsys * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return RBSOG_OK;
 }
 
-rbsog_status rbsog_get_rho(rbsog_ctx *c, double *re, double *im) {
+rbsog_status rbsog_get_rho(rbsog_ctx *c, int32_t sys, double *re, double *im) {
     TRY(check_ctx(c));
+    TRY(check_sys(c, sys));
     if (c->evals == 0) return fail(c, RBSOG_E_STATE, "no force evaluation yet");
-    std::vector<double> r(2 * (size_t)c->P);
-    HIPCHK(c, hipMemcpyAsync(r.data(), c->rho, r.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    const SysHost &h = c->sys[sys];
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (re) std::copy(r.begin(), r.begin() + c->P, re);
-    if (im) std::copy(r.begin() + c->P, r.end(), im);
+    if (re) HIPCHK(c, hipMemcpy(re, c->rho + h.k0, (size_t)h.P * sizeof(double), hipMemcpyDeviceToHost));
+    if (im) HIPCHK(c, hipMemcpy(im, c->rho + c->K + h.k0, (size_t)h.P * sizeof(double), hipMemcpyDeviceToHost));
     return RBSOG_OK;
 }
 
-rbsog_status rbsog_info(rbsog_ctx *c, rbsog_info_t *info) {
+rbsog_status rbsog_info(rbsog_ctx *c, int32_t sys, rbsog_info_t *info) {
     TRY(check_ctx(c));
+    TRY(check_sys(c, sys));
     if (!info) return fail(c, RBSOG_E_ARG, "info is null");
-    info->S = c->S;
-    info->volume = c->V;
-    for (int d = 0; d < 3; ++d) info->ncell[d] = c->geom.nc[d];
-    info->k_remaining = (int64_t)c->kseq.size() / 3 - c->cursor;
+    const SysHost &h = c->sys[sys];
+    info->S = h.S;
+    info->volume = h.V;
+    for (int d = 0; d < 3; ++d) info->ncell[d] = h.g.nc[d];
+    info->k_remaining = (int64_t)h.kseq.size() / 3 - h.cursor;
     info->evaluations = c->evals;
+    info->n = h.n;
+    info->n_sys = c->nsys;
     return RBSOG_OK;
 }
 
-rbsog_status rbsog_debug_cells(rbsog_ctx *c, int32_t *cell_start, int32_t *order) {
+rbsog_status rbsog_debug_cells(rbsog_ctx *c, int32_t sys, int32_t *cell_start, int32_t *order) {
     TRY(check_ctx(c));
+    TRY(check_sys(c, sys));
     if (c->evals == 0) return fail(c, RBSOG_E_STATE, "no force evaluation yet");
-    if (cell_start)
-        HIPCHK(c, hipMemcpyAsync(cell_start, c->cell_start, (size_t)(c->ncell + 1) * sizeof(int32_t),
-                                 hipMemcpyDeviceToHost, c->stream));
-    if (order)
-        HIPCHK(c, hipMemcpyAsync(order, c->order, (size_t)c->n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    const SysHost &h = c->sys[sys];
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (cell_start) {
+        HIPCHK(c, hipMemcpy(cell_start, c->cell_start + h.c0, (size_t)(h.ncell + 1) * sizeof(int32_t),
+                            hipMemcpyDeviceToHost));
+        for (int64_t k = 0; k <= h.ncell; ++k) cell_start[k] -= (int32_t)h.p0;
+    }
+    if (order) {
+        HIPCHK(c, hipMemcpy(order, c->buf[c->parity].id + h.p0, (size_t)h.n * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int64_t k = 0; k < h.n; ++k) order[k] -= (int32_t)h.p0;
+    }
     return RBSOG_OK;
 }
 
-rbsog_status rbsog_debug_neighbors(rbsog_ctx *c, int64_t *row_ptr, int32_t *cols, int64_t cap) {
+rbsog_status rbsog_debug_neighbors(rbsog_ctx *c, int32_t sys, int64_t *row_ptr, int32_t *cols, int64_t cap) {
     TRY(check_ctx(c));
+    TRY(check_sys(c, sys));
     if (c->evals == 0) return fail(c, RBSOG_E_STATE, "no force evaluation yet");
     if (!row_ptr) return fail(c, RBSOG_E_ARG, "row_ptr is null");
+    const SysHost &h = c->sys[sys];
+    const int64_t n = h.n;
+    // the latest evaluation's arrays: its cell order is the current one
+    EvalArgs a = make_args(c, false, 0.0);
+    const int32_t *idc = c->buf[c->parity].id;
     int64_t *dcount = nullptr;
-    HIPCHK(c, hipMalloc((void **)&dcount, (size_t)(c->n + 1) * sizeof(int64_t)));
-    launch_neighbor_count(c->geom, c->cell_start, c->order, c->su, dcount, c->stream);
-    std::vector<int64_t> cnt(c->n);
-    hipError_t e = hipMemcpyAsync(cnt.data(), dcount, (size_t)c->n * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream);
+    HIPCHK(c, hipMalloc((void **)&dcount, (size_t)(n + 1) * sizeof(int64_t)));
+    launch_neighbor_count(a, sys, n, h.p0, idc, dcount, c->stream);
+    std::vector<int64_t> cnt(n);
+    hipError_t e = hipMemcpyAsync(cnt.data(), dcount, (size_t)n * sizeof(int64_t), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         (void)hipFree(dcount);
         return fail(c, RBSOG_E_DEVICE, "neighbour count: %s", hipGetErrorString(e));
     }
     row_ptr[0] = 0;
-    for (int64_t i = 0; i < c->n; ++i) row_ptr[i + 1] = row_ptr[i] + cnt[i];
-    const int64_t total = row_ptr[c->n];
+    for (int64_t i = 0; i < n; ++i) row_ptr[i + 1] = row_ptr[i] + cnt[i];
+    const int64_t total = row_ptr[n];
     if (!cols || cap < total) {
         (void)hipFree(dcount);
         return fail(c, RBSOG_E_ARG, "cols needs %lld entries", (long long)total);
     }
     int32_t *dcols = nullptr;
-    e = hipMemcpy(dcount, row_ptr, (size_t)(c->n + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
+    e = hipMemcpy(dcount, row_ptr, (size_t)(n + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc((void **)&dcols, (size_t)std::max<int64_t>(total, 1) * sizeof(int32_t));
     if (e == hipSuccess) {
-        launch_neighbor_fill(c->geom, c->cell_start, c->order, c->su, dcount, dcols, c->stream);
+        launch_neighbor_fill(a, sys, n, h.p0, idc, dcount, dcols, c->stream);
         e = hipMemcpyAsync(cols, dcols, (size_t)total * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     }
@@ -1004,7 +1259,7 @@ void rbsog_destroy(rbsog_ctx *c) {
         (void)hipEventDestroy(p.b);
     }
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-    drop_graph(c);
+    drop_graphs(c);
     for (void *p : c->allocs) (void)hipFree(p);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;

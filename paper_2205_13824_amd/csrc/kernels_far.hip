@@ -11,7 +11,8 @@
 // Work split: the structure factor puts one wave vector on each lane and
 // streams particles uniformly through the wave (no cross-lane reduction in
 // the inner loop); the force puts one particle on each lane and streams the
-// P wave-vector records uniformly.  Partial sums of rho are reduced in a
+// P wave-vector records uniformly.  Both walk lists of work items, each item
+// within one system of the batch.  Partial sums of rho are reduced in a
 // fixed order, so the result is identical from run to run.
 #include "rbsog_internal.h"
 
@@ -20,8 +21,6 @@ namespace rbsog {
 namespace {
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
-
-inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 // sin(2 pi f), cos(2 pi f) for |f| <= 1/2 in FP64: quadrant q = rint(4f),
 // r = f - q/4 in [-1/8, 1/8], Taylor series of sin/cos(2 pi r) through
@@ -71,322 +70,353 @@ __device__ __forceinline__ void sincos2pi(double f, double *s, double *c) {
     *c = ((q + 1) & 2) ? -b : b;
 }
 
-// Structure factor partial sums.  Block (bx, by): particles
-// [bx*chunk, (bx+1)*chunk), wave vectors [by*kt*64, (by+1)*kt*64).
-// Wave w handles k tile (w % kt) for particle stream (w / kt).
+typedef const SysDev __attribute__((address_space(4))) CSys;
+// k records are read-only within the kernels that stream them: reading them
+// through the constant address space makes the uniform reads scalar loads
+typedef const KRec64 __attribute__((address_space(4))) CRec64;
+typedef const KRec32 __attribute__((address_space(4))) CRec32;
+__device__ __forceinline__ KRec64 ld(CRec64 *p) {
+    KRec64 r;
+    r.mx = p->mx; r.my = p->my; r.mz = p->mz;
+    r.ckx = p->ckx; r.cky = p->cky; r.ckz = p->ckz;
+    r.re = p->re; r.im = p->im;
+    return r;
+}
+__device__ __forceinline__ KRec32 ld(CRec32 *p) {
+    KRec32 r;
+    r.mx = p->mx; r.my = p->my; r.mz = p->mz;
+    r.ckx = p->ckx; r.cky = p->cky; r.ckz = p->ckz;
+    r.re = p->re; r.im = p->im;
+    return r;
+}
+
+// Uniform values loaded from memory: keep them scalar.
+__device__ __forceinline__ int32_t rfl(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t rfl64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Structure factor partial sums over the work items (grid-stride).  Item
+// (s, kg, chunk, [j0, j1)): wave w handles k tile (w % kt) of group kg for
+// particle stream (w / kt) of the slot range; the streams' sums are added in
+// a fixed order.  Blocks have 16 waves; kt * streams <= 16 per system.
 template <bool F64>
-__global__ __launch_bounds__(1024) void k_rho(Geom g, int32_t P, int kt, int streams, int64_t chunk,
-                                              const double *__restrict__ x, const uint32_t *__restrict__ u,
-                                              const double *__restrict__ q, const float *__restrict__ qf,
-                                              const KRec64 *__restrict__ kb64, const KRec32 *__restrict__ kb32,
-                                              double *__restrict__ partial) {
+__global__ __launch_bounds__(1024) void k_rho(EvalArgs a, const RhoItem *__restrict__ items, int32_t nitems) {
     __shared__ double2 red[1024];
-    const int64_t n = g.n;
+    const int64_t n = a.N;
+    const double *__restrict__ x = a.nxt.x;
+    const double *__restrict__ q = a.nxt.q;
+    const float *__restrict__ qf = a.nxt.qf;
+    const uint32_t *__restrict__ u = a.u;
     // the wave index is uniform: readfirstlane lets the particle loads below
     // be scalar loads shared by the whole wave
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    const int kti = wave % kt, st = wave / kt;
-    const int32_t k = ((int32_t)blockIdx.y * kt + kti) * 64 + lane;
-    const bool active = k < P;
-    const int32_t kk = active ? k : 0;
-    const int64_t j0 = (int64_t)blockIdx.x * chunk;
-    const int64_t j1 = j0 + chunk < n ? j0 + chunk : n;
-    const int64_t per = (chunk + streams - 1) / streams;
-    const int64_t a = j0 + st * per;
-    const int64_t b = a + per < j1 ? a + per : j1;
-    double re = 0.0, im = 0.0;
-    // particles are consumed in groups of G so that the uniform loads of a
-    // group are issued together and their latency is paid once per group
-    constexpr int G = 8;
-    if constexpr (F64) {
-        const double mx = kb64[kk].mx, my = kb64[kk].my, mz = kb64[kk].mz;
-        const double ix = g.invL[0], iy = g.invL[1], iz = g.invL[2];
-        int64_t j = a;
-        for (; j + G <= b; j += G) {
-            double px[G], py[G], pz[G], pq[G];
+    for (int32_t itx = blockIdx.x; itx < nitems; itx += gridDim.x) {
+        const RhoItem item = items[itx];
+        const int32_t sys = rfl(item.sys), kg = rfl(item.kg), chunk = rfl(item.chunk);
+        CSys *sp = (CSys *)(a.sys + sys);
+        const int32_t P = sp->P, kt = sp->kt, streams = sp->streams, k0 = sp->k0;
+        const int kti = wave % kt, st = wave / kt;
+        const int32_t k = (kg * kt + kti) * 64 + lane;
+        const bool active = k < P && st < streams;
+        const int32_t kk = k0 + (k < P ? k : 0);
+        const int64_t j0 = rfl64(item.j0), j1 = rfl64(item.j1);
+        const int64_t per = (j1 - j0 + streams - 1) / streams;
+        const int64_t ja = st < streams ? (j0 + st * per < j1 ? j0 + st * per : j1) : j1;
+        const int64_t jb = ja + per < j1 ? ja + per : j1;
+        double re = 0.0, im = 0.0;
+        // particles are consumed in groups of G so that the uniform loads of
+        // a group are issued together and their latency is paid once per group
+        constexpr int G = 8;
+        if constexpr (F64) {
+            const double mx = a.kb64[kk].mx, my = a.kb64[kk].my, mz = a.kb64[kk].mz;
+            const double ix = sp->g.invL[0], iy = sp->g.invL[1], iz = sp->g.invL[2];
+            int64_t j = ja;
+            for (; j + G <= jb; j += G) {
+                double px[G], py[G], pz[G], pq[G];
 #pragma unroll
-            for (int k = 0; k < G; ++k) {
-                px[k] = x[j + k]; py[k] = x[n + j + k]; pz[k] = x[2 * n + j + k]; pq[k] = q[j + k];
+                for (int h = 0; h < G; ++h) {
+                    px[h] = x[j + h]; py[h] = x[n + j + h]; pz[h] = x[2 * n + j + h]; pq[h] = q[j + h];
+                }
+#pragma unroll
+                for (int h = 0; h < G; ++h) {
+                    const double t = mx * (px[h] * ix) + my * (py[h] * iy) + mz * (pz[h] * iz);
+                    double sn, cs;
+                    sincos2pi(t - rint(t), &sn, &cs);
+                    re = fma(pq[h], cs, re);
+                    im = fma(pq[h], sn, im);
+                }
             }
-#pragma unroll
-            for (int k = 0; k < G; ++k) {
-                const double t = mx * (px[k] * ix) + my * (py[k] * iy) + mz * (pz[k] * iz);
+            for (; j < jb; ++j) {
+                const double t = mx * (x[j] * ix) + my * (x[n + j] * iy) + mz * (x[2 * n + j] * iz);
                 double sn, cs;
                 sincos2pi(t - rint(t), &sn, &cs);
-                re = fma(pq[k], cs, re);
-                im = fma(pq[k], sn, im);
+                re = fma(q[j], cs, re);
+                im = fma(q[j], sn, im);
             }
-        }
-        for (; j < b; ++j) {
-            const double t = mx * (x[j] * ix) + my * (x[n + j] * iy) + mz * (x[2 * n + j] * iz);
-            double sn, cs;
-            sincos2pi(t - rint(t), &sn, &cs);
-            re = fma(q[j], cs, re);
-            im = fma(q[j], sn, im);
-        }
-    } else {
-        const uint32_t mx = (uint32_t)kb32[kk].mx, my = (uint32_t)kb32[kk].my, mz = (uint32_t)kb32[kk].mz;
-        int64_t j = a;
-        // FP32 partial sums over 32 particles, then accumulated in FP64
-        for (; j + 4 * G <= b; j += 4 * G) {
+        } else {
+            const uint32_t mx = (uint32_t)a.kb32[kk].mx, my = (uint32_t)a.kb32[kk].my, mz = (uint32_t)a.kb32[kk].mz;
+            int64_t j = ja;
+            // FP32 partial sums over 32 particles, then accumulated in FP64
+            for (; j + 4 * G <= jb; j += 4 * G) {
+                float rf = 0.f, fi = 0.f;
+#pragma unroll
+                for (int h4 = 0; h4 < 4; ++h4) {
+                    uint32_t px[G], py[G], pz[G];
+                    float pq[G];
+#pragma unroll
+                    for (int h = 0; h < G; ++h) {
+                        const int64_t jj = j + h4 * G + h;
+                        px[h] = u[jj]; py[h] = u[n + jj]; pz[h] = u[2 * n + jj]; pq[h] = qf[jj];
+                    }
+#pragma unroll
+                    for (int h = 0; h < G; ++h) {
+                        const uint32_t t = mx * px[h] + my * py[h] + mz * pz[h];
+                        const float f = (float)(int32_t)t * 0x1.0p-32f;
+                        rf = fmaf(pq[h], __builtin_amdgcn_cosf(f), rf);
+                        fi = fmaf(pq[h], __builtin_amdgcn_sinf(f), fi);
+                    }
+                }
+                re += rf;
+                im += fi;
+            }
             float rf = 0.f, fi = 0.f;
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                uint32_t px[G], py[G], pz[G];
-                float pq[G];
-#pragma unroll
-                for (int k = 0; k < G; ++k) {
-                    const int64_t jj = j + h * G + k;
-                    px[k] = u[jj]; py[k] = u[n + jj]; pz[k] = u[2 * n + jj]; pq[k] = qf[jj];
-                }
-#pragma unroll
-                for (int k = 0; k < G; ++k) {
-                    const uint32_t t = mx * px[k] + my * py[k] + mz * pz[k];
-                    const float f = (float)(int32_t)t * 0x1.0p-32f;
-                    rf = fmaf(pq[k], __builtin_amdgcn_cosf(f), rf);
-                    fi = fmaf(pq[k], __builtin_amdgcn_sinf(f), fi);
-                }
+            for (; j < jb; ++j) {
+                const uint32_t t = mx * u[j] + my * u[n + j] + mz * u[2 * n + j];
+                const float f = (float)(int32_t)t * 0x1.0p-32f;
+                rf = fmaf(qf[j], __builtin_amdgcn_cosf(f), rf);
+                fi = fmaf(qf[j], __builtin_amdgcn_sinf(f), fi);
             }
             re += rf;
             im += fi;
         }
-        float rf = 0.f, fi = 0.f;
-        for (; j < b; ++j) {
-            const uint32_t t = mx * u[j] + my * u[n + j] + mz * u[2 * n + j];
-            const float f = (float)(int32_t)t * 0x1.0p-32f;
-            rf = fmaf(qf[j], __builtin_amdgcn_cosf(f), rf);
-            fi = fmaf(qf[j], __builtin_amdgcn_sinf(f), fi);
-        }
-        re += rf;
-        im += fi;
-    }
-    red[threadIdx.x] = make_double2(re, im);
-    __syncthreads();
-    if (st == 0 && active) {
-        double sr = 0.0, si = 0.0;
-        for (int s2 = 0; s2 < streams; ++s2) {
-            const double2 v = red[(s2 * kt + kti) * 64 + lane];
-            sr += v.x;
-            si += v.y;
-        }
-        partial[2 * ((int64_t)blockIdx.x * P + k)] = sr;
-        partial[2 * ((int64_t)blockIdx.x * P + k) + 1] = si;
-    }
-}
-
-// rho_e = sum over particle blocks of the partials (fixed order), the
-// per-k energy 1/2 w_e |rho_e|^2, and rho written into the k records.  The
-// last block to finish (counter) sums the energies in a fixed order:
-// U_N from the near kernel's block partials, U*, U_self, U; and re-arms the
-// counter for the next launch.
-__global__ __launch_bounds__(256) void k_rho_reduce(int32_t P, int64_t nblk, const double *__restrict__ partial,
-                                                    const double *__restrict__ wk, KRec64 *__restrict__ kb64,
-                                                    KRec32 *__restrict__ kb32, double *__restrict__ rho,
-                                                    double *__restrict__ ek, int64_t nnear,
-                                                    const double *__restrict__ epart, double uself,
-                                                    double *__restrict__ E, int32_t *__restrict__ flag,
-                                                    uint32_t *__restrict__ counter) {
-    __shared__ double sr[256], si[256];
-    __shared__ bool last;
-    const int32_t k = blockIdx.x;
-    double a = 0.0, b = 0.0;
-    for (int64_t c = threadIdx.x; c < nblk; c += 256) {
-        a += partial[2 * (c * P + k)];
-        b += partial[2 * (c * P + k) + 1];
-    }
-    sr[threadIdx.x] = a;
-    si[threadIdx.x] = b;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
-            sr[threadIdx.x] += sr[threadIdx.x + o];
-            si[threadIdx.x] += si[threadIdx.x + o];
-        }
+        red[threadIdx.x] = make_double2(re, im);
         __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const double re = sr[0], im = si[0];
-        rho[k] = re;
-        rho[P + k] = im;
-        kb64[k].re = re;
-        kb64[k].im = im;
-        kb32[k].re = (float)re;
-        kb32[k].im = (float)im;
-        ek[k] = 0.5 * wk[k] * (re * re + im * im);
-        __threadfence();
-        last = atomicAdd(counter, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    double un = 0.0, us = 0.0;
-    for (int64_t i = threadIdx.x; i < nnear; i += 256) un += epart[i];
-    for (int64_t i = threadIdx.x; i < P; i += 256) us += ek[i];
-    sr[threadIdx.x] = un;
-    si[threadIdx.x] = us;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
-            sr[threadIdx.x] += sr[threadIdx.x + o];
-            si[threadIdx.x] += si[threadIdx.x + o];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const double tot = sr[0] + si[0] - uself;
-        E[0] = sr[0];
-        E[1] = si[0];
-        E[2] = uself;
-        E[3] = tot;
-        if (!isfinite(tot)) atomicOr(flag, 2);
-        *counter = 0u;
-    }
-}
-
-// Far force, one particle per lane, the P records streamed uniformly.
-template <bool F64>
-__global__ __launch_bounds__(256) void k_far(Geom g, int32_t P, const double *__restrict__ x,
-                                             const uint32_t *__restrict__ u, const double *__restrict__ q,
-                                             const float *__restrict__ qf, const KRec64 *__restrict__ kb64,
-                                             const KRec32 *__restrict__ kb32, double *__restrict__ Ff, KickArgs kick) {
-    const int64_t n = g.n;
-    const int64_t i0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool valid = i0 < n;
-    const int64_t i = valid ? i0 : 0;
-    double Fx = 0.0, Fy = 0.0, Fz = 0.0;
-    // records are consumed in groups so that their uniform loads overlap
-    if constexpr (F64) {
-        const double sx = x[i] * g.invL[0], sy = x[n + i] * g.invL[1], sz = x[2 * n + i] * g.invL[2];
-        constexpr int G = 2;
-        int32_t e = 0;
-        for (; e + G <= P; e += G) {
-            KRec64 r[G];
-#pragma unroll
-            for (int k = 0; k < G; ++k) r[k] = kb64[e + k];
-#pragma unroll
-            for (int k = 0; k < G; ++k) {
-                const double t = r[k].mx * sx + r[k].my * sy + r[k].mz * sz;
-                double sn, cs;
-                sincos2pi(t - rint(t), &sn, &cs);
-                const double v = cs * r[k].im - sn * r[k].re;
-                Fx = fma(r[k].ckx, v, Fx);
-                Fy = fma(r[k].cky, v, Fy);
-                Fz = fma(r[k].ckz, v, Fz);
+        if (st == 0 && active) {
+            double sr = 0.0, si = 0.0;
+            for (int s2 = 0; s2 < streams; ++s2) {
+                const double2 v = red[(s2 * kt + kti) * 64 + lane];
+                sr += v.x;
+                si += v.y;
             }
+            const int64_t o = sp->pofs + (int64_t)chunk * P + k;
+            a.partial[2 * o] = sr;
+            a.partial[2 * o + 1] = si;
         }
-        for (; e < P; ++e) {
-            const KRec64 r = kb64[e];
-            const double t = r.mx * sx + r.my * sy + r.mz * sz;
-            double sn, cs;
-            sincos2pi(t - rint(t), &sn, &cs);
-            const double v = cs * r.im - sn * r.re;
-            Fx = fma(r.ckx, v, Fx);
-            Fy = fma(r.cky, v, Fy);
-            Fz = fma(r.ckz, v, Fz);
+        __syncthreads();
+    }
+}
+
+// Sum over the wave in a fixed order (the same on every run).
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// One wave per k record r: rho = sum over the system's chunks of the
+// partials (fixed order), the per-k energy 1/2 w |rho|^2, and rho written
+// into the records.  The block that reduces the last record of a system
+// (per-system counter) sums that system's energies in a fixed order: U_N
+// from the near items' partials, U*, U_self, U; advances its sequence cursor
+// by P and re-arms the counter.
+__global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
+    __shared__ double sr[256], si[256];
+    __shared__ int32_t fin[4];
+    __shared__ int32_t nfin;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + wave;
+    int32_t sys = -1;
+    if (r < a.K) {
+        sys = a.ksys[r];
+        const SysDev &sd = a.sys[sys];
+        const int32_t P = sd.P, k = (int32_t)(r - sd.k0);
+        double re = 0.0, im = 0.0;
+        for (int64_t c = lane; c < sd.nch; c += 64) {
+            const int64_t o = sd.pofs + c * P + k;
+            re += a.partial[2 * o];
+            im += a.partial[2 * o + 1];
         }
-        const double qi = q[i];
-        Fx *= -qi; Fy *= -qi; Fz *= -qi;
-    } else {
-        const uint32_t ux = u[i], uy = u[n + i], uz = u[2 * n + i];
-        constexpr int G = 4;
-        int32_t e = 0;
-        // FP32 partial sums over 64 records, then accumulated in FP64
-        for (; e + 16 * G <= P; e += 16 * G) {
-            float fx = 0.f, fy = 0.f, fz = 0.f;
+        re = wave_sum(re);
+        im = wave_sum(im);
+        if (lane == 0) {
+            a.rho[r] = re;
+            a.rho[a.K + r] = im;
+            a.kb64[r].re = re;
+            a.kb64[r].im = im;
+            a.kb32[r].re = (float)re;
+            a.kb32[r].im = (float)im;
+            a.ek[r] = 0.5 * a.wk[r] * (re * re + im * im);
+        }
+    }
+    if (threadIdx.x == 0) nfin = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        for (int w = 0; w < 4; ++w) {
+            const int64_t rw = (int64_t)blockIdx.x * 4 + w;
+            if (rw >= a.K) break;
+            const int32_t s = a.ksys[rw];
+            if (atomicAdd(&a.sys_done[s], 1u) == (uint32_t)a.sys[s].P - 1u) fin[nfin++] = s;
+        }
+    }
+    __syncthreads();
+    const int32_t nf = nfin;
+    for (int f = 0; f < nf; ++f) {
+        __threadfence();
+        const int32_t s = fin[f];
+        const SysDev &sd = a.sys[s];
+        double un = 0.0, us = 0.0;
+        for (int64_t i = sd.it0 + threadIdx.x; i < sd.it1; i += 256) un += a.epart[i];
+        for (int64_t i = threadIdx.x; i < sd.P; i += 256) us += a.ek[sd.k0 + i];
+        sr[threadIdx.x] = un;
+        si[threadIdx.x] = us;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (threadIdx.x < o) {
+                sr[threadIdx.x] += sr[threadIdx.x + o];
+                si[threadIdx.x] += si[threadIdx.x + o];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const double tot = sr[0] + si[0] - sd.uself;
+            a.E[4 * s] = sr[0];
+            a.E[4 * s + 1] = si[0];
+            a.E[4 * s + 2] = sd.uself;
+            a.E[4 * s + 3] = tot;
+            if (!isfinite(tot)) atomicOr(a.flag, 2);
+            a.kcur[s] += sd.P;
+            a.sys_done[s] = 0u;
+        }
+        __syncthreads();
+    }
+}
+
+// Far force, one particle per lane, the P records of its system streamed
+// uniformly; items are runs of up to 256 slots of one system (grid-stride).
+template <bool F64>
+__global__ __launch_bounds__(256) void k_far(EvalArgs a, const FarItem *__restrict__ items, int32_t nitems) {
+    const int64_t n = a.N;
+    for (int32_t itx = blockIdx.x; itx < nitems; itx += gridDim.x) {
+        const FarItem item = items[itx];
+        const int32_t sys = rfl(item.sys);
+        CSys *sp = (CSys *)(a.sys + sys);
+        const int32_t P = sp->P;
+        CRec64 *kb64 = (CRec64 *)(a.kb64 + sp->k0);
+        CRec32 *kb32 = (CRec32 *)(a.kb32 + sp->k0);
+        const int64_t t0 = rfl64(item.t0), t1 = rfl64(item.t1);
+        const int64_t i0 = t0 + threadIdx.x;
+        const bool valid = i0 < t1;
+        const int64_t i = valid ? i0 : t0;
+        double Fx = 0.0, Fy = 0.0, Fz = 0.0;
+        // records are consumed in groups so that their uniform loads overlap
+        if constexpr (F64) {
+            const double *__restrict__ x = a.nxt.x;
+            const double sx = x[i] * sp->g.invL[0], sy = x[n + i] * sp->g.invL[1], sz = x[2 * n + i] * sp->g.invL[2];
+            constexpr int G = 2;
+            int32_t e = 0;
+            for (; e + G <= P; e += G) {
+                KRec64 r[G];
 #pragma unroll
-            for (int h = 0; h < 16; ++h) {
-                KRec32 r[G];
+                for (int h = 0; h < G; ++h) r[h] = ld(kb64 + e + h);
 #pragma unroll
-                for (int k = 0; k < G; ++k) r[k] = kb32[e + h * G + k];
-#pragma unroll
-                for (int k = 0; k < G; ++k) {
-                    const uint32_t t = (uint32_t)r[k].mx * ux + (uint32_t)r[k].my * uy + (uint32_t)r[k].mz * uz;
-                    const float f = (float)(int32_t)t * 0x1.0p-32f;
-                    const float v = __builtin_amdgcn_cosf(f) * r[k].im - __builtin_amdgcn_sinf(f) * r[k].re;
-                    fx = fmaf(r[k].ckx, v, fx);
-                    fy = fmaf(r[k].cky, v, fy);
-                    fz = fmaf(r[k].ckz, v, fz);
+                for (int h = 0; h < G; ++h) {
+                    const double t = r[h].mx * sx + r[h].my * sy + r[h].mz * sz;
+                    double sn, cs;
+                    sincos2pi(t - rint(t), &sn, &cs);
+                    const double v = cs * r[h].im - sn * r[h].re;
+                    Fx = fma(r[h].ckx, v, Fx);
+                    Fy = fma(r[h].cky, v, Fy);
+                    Fz = fma(r[h].ckz, v, Fz);
                 }
             }
-            Fx += fx; Fy += fy; Fz += fz;
-        }
-        float fx = 0.f, fy = 0.f, fz = 0.f;
-        for (; e < P; ++e) {
-            const KRec32 r = kb32[e];
-            const uint32_t t = (uint32_t)r.mx * ux + (uint32_t)r.my * uy + (uint32_t)r.mz * uz;
-            const float f = (float)(int32_t)t * 0x1.0p-32f;
-            const float v = __builtin_amdgcn_cosf(f) * r.im - __builtin_amdgcn_sinf(f) * r.re;
-            fx = fmaf(r.ckx, v, fx);
-            fy = fmaf(r.cky, v, fy);
-            fz = fmaf(r.ckz, v, fz);
-        }
-        const double qi = -(double)qf[i];
-        Fx = qi * (Fx + fx); Fy = qi * (Fy + fy); Fz = qi * (Fz + fz);
-    }
-    if (valid) {
-        Ff[i] = Fx;
-        Ff[n + i] = Fy;
-        Ff[2 * n + i] = Fz;
-        if (kick.on) {
-            // closing half kick of the velocity-Verlet step
-            const double f[3] = {kick.Fn[i] + Fx, kick.Fn[n + i] + Fy, kick.Fn[2 * n + i] + Fz};
-            bool bad = false;
-            for (int d = 0; d < 3; ++d) {
-                bad |= !isfinite(f[d]);
-                kick.v[d * n + i] += kick.hdm * f[d];
+            for (; e < P; ++e) {
+                const KRec64 r = ld(kb64 + e);
+                const double t = r.mx * sx + r.my * sy + r.mz * sz;
+                double sn, cs;
+                sincos2pi(t - rint(t), &sn, &cs);
+                const double v = cs * r.im - sn * r.re;
+                Fx = fma(r.ckx, v, Fx);
+                Fy = fma(r.cky, v, Fy);
+                Fz = fma(r.ckz, v, Fz);
             }
-            if (bad) atomicOr(kick.flag, 1);
+            const double qi = a.nxt.q[i];
+            Fx *= -qi; Fy *= -qi; Fz *= -qi;
+        } else {
+            const uint32_t *__restrict__ u = a.u;
+            const uint32_t ux = u[i], uy = u[n + i], uz = u[2 * n + i];
+            constexpr int G = 4;
+            int32_t e = 0;
+            // FP32 partial sums over 64 records, then accumulated in FP64
+            for (; e + 16 * G <= P; e += 16 * G) {
+                float fx = 0.f, fy = 0.f, fz = 0.f;
+#pragma unroll
+                for (int h4 = 0; h4 < 16; ++h4) {
+                    KRec32 r[G];
+#pragma unroll
+                    for (int h = 0; h < G; ++h) r[h] = ld(kb32 + e + h4 * G + h);
+#pragma unroll
+                    for (int h = 0; h < G; ++h) {
+                        const uint32_t t = (uint32_t)r[h].mx * ux + (uint32_t)r[h].my * uy + (uint32_t)r[h].mz * uz;
+                        const float f = (float)(int32_t)t * 0x1.0p-32f;
+                        const float v = __builtin_amdgcn_cosf(f) * r[h].im - __builtin_amdgcn_sinf(f) * r[h].re;
+                        fx = fmaf(r[h].ckx, v, fx);
+                        fy = fmaf(r[h].cky, v, fy);
+                        fz = fmaf(r[h].ckz, v, fz);
+                    }
+                }
+                Fx += fx; Fy += fy; Fz += fz;
+            }
+            float fx = 0.f, fy = 0.f, fz = 0.f;
+            for (; e < P; ++e) {
+                const KRec32 r = ld(kb32 + e);
+                const uint32_t t = (uint32_t)r.mx * ux + (uint32_t)r.my * uy + (uint32_t)r.mz * uz;
+                const float f = (float)(int32_t)t * 0x1.0p-32f;
+                const float v = __builtin_amdgcn_cosf(f) * r.im - __builtin_amdgcn_sinf(f) * r.re;
+                fx = fmaf(r.ckx, v, fx);
+                fy = fmaf(r.cky, v, fy);
+                fz = fmaf(r.ckz, v, fz);
+            }
+            const double qi = -(double)a.nxt.qf[i];
+            Fx = qi * (Fx + fx); Fy = qi * (Fy + fy); Fz = qi * (Fz + fz);
+        }
+        if (valid) {
+            a.Ff[i] = Fx;
+            a.Ff[n + i] = Fy;
+            a.Ff[2 * n + i] = Fz;
+            if (a.kick) {
+                // closing half kick of the velocity-Verlet step
+                const double f[3] = {a.Fn[i] + Fx, a.Fn[n + i] + Fy, a.Fn[2 * n + i] + Fz};
+                bool bad = false;
+                for (int d = 0; d < 3; ++d) {
+                    bad |= !isfinite(f[d]);
+                    a.nxt.v[d * n + i] += a.hdm * f[d];
+                }
+                if (bad) atomicOr(a.flag, 1);
+            }
         }
     }
 }
 
 }  // namespace
 
-FarPlan far_plan(int64_t n, int32_t P) {
-    FarPlan p;
-    const int64_t ktiles = (P + 63) / 64;
-    p.kt = (int)(ktiles < 16 ? ktiles : 16);
-    p.kblk = (ktiles + p.kt - 1) / p.kt;
-    p.streams = 16 / p.kt;
-    if (p.streams < 1) p.streams = 1;
-    // aim for ~2 blocks of 16 waves per CU over 256 CUs
-    const int64_t want_blocks = 512 / (p.kblk > 0 ? p.kblk : 1);
-    int64_t chunk = (n + want_blocks - 1) / (want_blocks > 0 ? want_blocks : 1);
-    const int64_t min_chunk = 64 * p.streams;
-    if (chunk < min_chunk) chunk = min_chunk;
-    p.chunk = chunk;
-    p.nblk = (n + chunk - 1) / chunk;
-    return p;
+void launch_rho(const EvalArgs &a, bool f64, const RhoItem *items, int32_t nitems, hipStream_t s) {
+    dim3 grid((unsigned)nitems), block(1024);
+    if (f64) hipLaunchKernelGGL(k_rho<true>, grid, block, 0, s, a, items, nitems);
+    else hipLaunchKernelGGL(k_rho<false>, grid, block, 0, s, a, items, nitems);
 }
 
-void launch_rho(const Geom &g, const FarPlan &fp, int32_t P, bool f64, const double *x, const uint32_t *u,
-                const double *q, const float *qf, const KRec64 *kb64, const KRec32 *kb32, double *partial,
-                hipStream_t s) {
-    dim3 grid((unsigned)fp.nblk, (unsigned)fp.kblk), block(64 * fp.kt * fp.streams);
-    if (f64)
-        hipLaunchKernelGGL(k_rho<true>, grid, block, 0, s, g, P, fp.kt, fp.streams, fp.chunk, x, u, q, qf, kb64,
-                           kb32, partial);
-    else
-        hipLaunchKernelGGL(k_rho<false>, grid, block, 0, s, g, P, fp.kt, fp.streams, fp.chunk, x, u, q, qf, kb64,
-                           kb32, partial);
+void launch_rho_reduce(const EvalArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_rho_reduce, dim3((unsigned)((a.K + 3) / 4)), dim3(256), 0, s, a);
 }
 
-void launch_rho_reduce(int32_t P, int64_t nblk, const double *partial, const double *wk, KRec64 *kb64,
-                       KRec32 *kb32, double *rho, double *ek, int64_t nnear, const double *epart, double uself,
-                       double *E, int32_t *flag, uint32_t *counter, hipStream_t s) {
-    hipLaunchKernelGGL(k_rho_reduce, dim3((unsigned)P), dim3(256), 0, s, P, nblk, partial, wk, kb64, kb32, rho, ek,
-                       nnear, epart, uself, E, flag, counter);
-}
-
-void launch_far(const Geom &g, int32_t P, bool f64, const double *x, const uint32_t *u, const double *q,
-                const float *qf, const KRec64 *kb64, const KRec32 *kb32, double *Ff, const KickArgs &kick,
-                hipStream_t s) {
-    dim3 grid(grid_for(g.n, 256)), block(256);
-    if (f64)
-        hipLaunchKernelGGL(k_far<true>, grid, block, 0, s, g, P, x, u, q, qf, kb64, kb32, Ff, kick);
-    else
-        hipLaunchKernelGGL(k_far<false>, grid, block, 0, s, g, P, x, u, q, qf, kb64, kb32, Ff, kick);
+void launch_far(const EvalArgs &a, bool f64, const FarItem *items, int32_t nitems, hipStream_t s) {
+    dim3 grid((unsigned)nitems), block(256);
+    if (f64) hipLaunchKernelGGL(k_far<true>, grid, block, 0, s, a, items, nitems);
+    else hipLaunchKernelGGL(k_far<false>, grid, block, 0, s, a, items, nitems);
 }
 
 }  // namespace rbsog

@@ -1,10 +1,12 @@
 // Particle bookkeeping kernels of librbsog for gfx950: wrap and quantise,
-// the cell list (histogram, exclusive scan, scatter, per-cell id sort,
-// gather into cell order) and the velocity-Verlet kick/drift.
+// the cell list (histogram, exclusive scan, scatter, per-cell id sort and
+// gather of the state into cell order), the velocity-Verlet kick/drift and the
+// staging of each evaluation's wave vectors.
 //
-// Arrays are structure-of-arrays: component d of particle i is at [d*n + i].
-// These passes are HBM-bound streams; each thread owns one particle (or one
-// cell) and global accesses are coalesced except the cell scatter/gather.
+// Arrays are structure-of-arrays over all systems of the batch: component d
+// of slot t is at [d*N + t].  The state stays in cell order between
+// evaluations, so these passes stream it coalesced and the re-sort moves
+// particles only as far as they drifted.
 #include "rbsog_internal.h"
 
 namespace rbsog {
@@ -13,6 +15,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr double kTwo32 = 4294967296.0;
+constexpr double kTwoPi = 6.283185307179586476925286766559;
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
@@ -21,44 +24,69 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
+// Stage the next P_s wave vectors of every system (Algorithm 1: the sequence
+// is consumed in order, one batch per evaluation): per-k records for both
+// precisions and the weights.  The cursors advance once the batch is reduced.
+__device__ void stage_records(const EvalArgs &a, int64_t r) {
+    if (r >= a.K) return;
+    const int32_t s = a.ksys[r];
+    const SysDev &sd = a.sys[s];
+    const int64_t e = a.kcur[s] + (r - sd.k0);
+    const int32_t mx = sd.kseq[3 * e], my = sd.kseq[3 * e + 1], mz = sd.kseq[3 * e + 2];
+    const double w = sd.kw ? sd.kw[e] : sd.w_rb;
+    const double kx = kTwoPi * sd.g.invL[0] * mx, ky = kTwoPi * sd.g.invL[1] * my, kz = kTwoPi * sd.g.invL[2] * mz;
+    KRec64 h;
+    h.mx = mx; h.my = my; h.mz = mz;
+    h.ckx = w * kx; h.cky = w * ky; h.ckz = w * kz;
+    h.re = 0.0; h.im = 0.0;
+    a.kb64[r] = h;
+    KRec32 f;
+    f.mx = mx; f.my = my; f.mz = mz;
+    f.ckx = (float)h.ckx; f.cky = (float)h.cky; f.ckz = (float)h.ckz;
+    f.re = 0.f; f.im = 0.f;
+    a.kb32[r] = f;
+    a.wk[r] = w;
+}
+
 // Optional kick dt/2 and drift (velocity Verlet), then wrap x into [0, L)
 // (x_w = frac(x/L) L), fixed-point coordinate u = min(2^32-1,
 // floor(frac(x/L) 2^32)), cell c_d = (u n_d) >> 32 and the cell histogram.
-// The extra last block stages the k batch of this evaluation.
-__global__ void k_kdq(Geom g, KickArgs kick, StageArgs stage, double *__restrict__ x, uint32_t *__restrict__ u,
-                      int32_t *__restrict__ cell_of, int32_t *__restrict__ count) {
-    if (blockIdx.x == gridDim.x - 1) {
-        stage_batch(g, stage);
+// Blocks past the particles stage the k records.
+__global__ __launch_bounds__(kBlock) void k_kdq(EvalArgs a, int32_t pblocks) {
+    if ((int32_t)blockIdx.x >= pblocks) {
+        stage_records(a, (int64_t)(blockIdx.x - pblocks) * kBlock + threadIdx.x);
         return;
     }
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.n) return;
-    const int64_t n = g.n;
-    if (kick.on) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= a.N) return;
+    const int64_t N = a.N;
+    double *x = a.cur.x;
+    if (a.kick) {
         bool bad = false;
         for (int d = 0; d < 3; ++d) {
-            const double f = kick.Fn[d * n + i] + kick.Ff[d * n + i];
+            const double f = a.Fn[d * N + t] + a.Ff[d * N + t];
             bad |= !isfinite(f);
-            const double vd = kick.v[d * n + i] + kick.hdm * f;
-            kick.v[d * n + i] = vd;
-            x[d * n + i] += kick.dt * vd;
+            const double vd = a.cur.v[d * N + t] + a.hdm * f;
+            a.cur.v[d * N + t] = vd;
+            x[d * N + t] += a.dt * vd;
         }
-        if (bad) atomicOr(kick.flag, 1);
+        if (bad) atomicOr(a.flag, 1);
     }
+    const SysDev &sd = a.sys[a.sys_of[t]];
     int64_t c[3];
     for (int d = 0; d < 3; ++d) {
-        double t = x[d * n + i] / g.L[d];
-        double f = t - floor(t);
+        double r = x[d * N + t] / sd.g.L[d];
+        double f = r - floor(r);
         double v = floor(f * kTwo32);
         v = v > kTwo32 - 1.0 ? kTwo32 - 1.0 : v;
-        uint32_t ud = (uint32_t)v;
-        u[d * n + i] = ud;
-        x[d * n + i] = f * g.L[d];
-        c[d] = (int64_t)(((uint64_t)ud * (uint64_t)g.nc[d]) >> 32);
+        const uint32_t ud = (uint32_t)v;
+        a.u_tmp[d * N + t] = ud;
+        x[d * N + t] = f * sd.g.L[d];
+        c[d] = (int64_t)(((uint64_t)ud * (uint64_t)sd.g.nc[d]) >> 32);
     }
-    int32_t cell = (int32_t)(c[0] + (int64_t)g.nc[0] * (c[1] + (int64_t)g.nc[1] * c[2]));
-    cell_of[i] = cell;
-    atomicAdd(&count[cell], 1);
+    const int64_t cell = sd.c0 + c[0] + (int64_t)sd.g.nc[0] * (c[1] + (int64_t)sd.g.nc[1] * c[2]);
+    a.cell_of[t] = (int32_t)cell;
+    atomicAdd(&a.cell_count[cell], 1);
 }
 
 // ---- exclusive scan of int32 counts: 1024 elements per block --------------
@@ -131,49 +159,51 @@ __global__ void k_scan_apply(const int32_t *__restrict__ in, int64_t n, const in
     }
 }
 
-__global__ void k_cell_scatter(int64_t n, const int32_t *__restrict__ cell_of, int32_t *__restrict__ fill,
-                               int32_t *__restrict__ order) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int32_t t = atomicAdd(&fill[cell_of[i]], 1);
-    order[t] = (int32_t)i;
+__global__ void k_cell_scatter(int64_t N, const int32_t *__restrict__ cell_of, int32_t *__restrict__ fill,
+                               int32_t *__restrict__ src) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    const int32_t dst = atomicAdd(&fill[cell_of[t]], 1);
+    src[dst] = (int32_t)t;
 }
 
-// Per cell: insertion sort of its ids (the order becomes (cell, id),
-// independent of the scatter's atomic order) and reset of its histogram
-// count for the next evaluation.
-__global__ void k_cell_sort(int64_t ncell, const int32_t *__restrict__ start, int32_t *__restrict__ order,
-                            int32_t *__restrict__ count) {
+// Per cell: insertion sort of its slots by particle id (the order becomes
+// (cell, id), independent of the scatter's atomic order) and reset of its
+// histogram count for the next evaluation.
+__global__ __launch_bounds__(kBlock) void k_cell_sort(EvalArgs a) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell) return;
-    const int32_t lo = start[c], hi = start[c + 1];
-    for (int32_t a = lo + 1; a < hi; ++a) {
-        const int32_t v = order[a];
-        int32_t b = a - 1;
-        while (b >= lo && order[b] > v) {
-            order[b + 1] = order[b];
-            --b;
+    if (c >= a.C) return;
+    const int32_t lo = a.cell_start[c], hi = a.cell_start[c + 1];
+    int32_t *src = a.src;
+    const int32_t *idc = a.cur.id;
+    for (int32_t i = lo + 1; i < hi; ++i) {
+        const int32_t v = src[i];
+        const int32_t key = idc[v];
+        int32_t j = i - 1;
+        while (j >= lo && idc[src[j]] > key) {
+            src[j + 1] = src[j];
+            --j;
         }
-        order[b + 1] = v;
+        src[j + 1] = v;
     }
-    count[c] = 0;
+    a.cell_count[c] = 0;
 }
 
-// Gather into cell order: one thread per sorted slot.
-__global__ void k_gather(Geom g, const int32_t *__restrict__ order, const uint32_t *__restrict__ u,
-                         const double *__restrict__ x, const double *__restrict__ q, uint32_t *__restrict__ su,
-                         double *__restrict__ sx, double *__restrict__ sq, float *__restrict__ sqf, int f64) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= g.n) return;
-    const int64_t n = g.n;
-    const int64_t id = order[t];
-    for (int d = 0; d < 3; ++d) su[d * n + t] = u[d * n + id];
-    const double qi = q[id];
-    sqf[t] = (float)qi;
-    if (f64) {
-        for (int d = 0; d < 3; ++d) sx[d * n + t] = x[d * n + id];
-        sq[t] = qi;
+// Gather of the state into the new order, one thread per new slot: writes
+// are coalesced and the reads stay close (particles move little per step).
+__global__ __launch_bounds__(kBlock) void k_gather(EvalArgs a) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.N) return;
+    const int64_t N = a.N;
+    const int64_t t = a.src[k];
+    for (int d = 0; d < 3; ++d) {
+        a.nxt.x[d * N + k] = a.cur.x[d * N + t];
+        a.nxt.v[d * N + k] = a.cur.v[d * N + t];
+        a.u[d * N + k] = a.u_tmp[d * N + t];
     }
+    a.nxt.q[k] = a.cur.q[t];
+    a.nxt.qf[k] = a.cur.qf[t];
+    a.nxt.id[k] = a.cur.id[t];
 }
 
 }  // namespace
@@ -182,33 +212,31 @@ void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, p, n, v);
 }
 
-void launch_kdq(const Geom &g, const KickArgs &kick, const StageArgs &stage, double *x, uint32_t *u,
-                int32_t *cell_of, int32_t *cell_count, hipStream_t s) {
-    hipLaunchKernelGGL(k_kdq, dim3(grid_for(g.n, kBlock) + 1), dim3(kBlock), 0, s, g, kick, stage, x, u, cell_of,
-                       cell_count);
+void launch_kdq(const EvalArgs &a, hipStream_t s) {
+    const int32_t pb = (int32_t)grid_for(a.N, kBlock);
+    const int32_t kb = (int32_t)grid_for(a.K, kBlock);
+    hipLaunchKernelGGL(k_kdq, dim3((unsigned)(pb + kb)), dim3(kBlock), 0, s, a, pb);
 }
 
 int64_t scan_blocksums_size(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
-void launch_scan(const int32_t *in, int32_t *out_excl, int32_t *fill_copy, int64_t n, int32_t *blocksums,
-                 hipStream_t s) {
+void launch_scan(const EvalArgs &a, hipStream_t s) {
+    const int64_t n = a.C;
     int64_t nb = (n + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, blocksums);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, blocksums, nb);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, blocksums, out_excl,
-                       fill_copy);
+    hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(kBlock), 0, s, a.cell_count, n, a.blocksums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, a.blocksums, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kBlock), 0, s, a.cell_count, n, a.blocksums,
+                       a.cell_start, a.cell_fill);
 }
 
-void launch_cell_scatter(const Geom &g, const int32_t *cell_of, int32_t *fill, int32_t *order, hipStream_t s) {
-    hipLaunchKernelGGL(k_cell_scatter, dim3(grid_for(g.n, kBlock)), dim3(kBlock), 0, s, g.n, cell_of, fill, order);
+void launch_cell_scatter(const EvalArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_cell_scatter, dim3(grid_for(a.N, kBlock)), dim3(kBlock), 0, s, a.N, a.cell_of, a.cell_fill,
+                       a.src);
 }
 
-void launch_sort_gather(const Geom &g, int64_t ncell, const int32_t *start, int32_t *order, int32_t *cell_count,
-                        const uint32_t *u, const double *x, const double *q, uint32_t *su, double *sx, double *sq,
-                        float *sqf, bool f64, hipStream_t s) {
-    hipLaunchKernelGGL(k_cell_sort, dim3(grid_for(ncell, kBlock)), dim3(kBlock), 0, s, ncell, start, order, cell_count);
-    hipLaunchKernelGGL(k_gather, dim3(grid_for(g.n, kBlock)), dim3(kBlock), 0, s, g, order, u, x, q, su, sx, sq, sqf,
-                       (int)f64);
+void launch_sort_gather(const EvalArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_cell_sort, dim3(grid_for(a.C, kBlock)), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(a.N, kBlock)), dim3(kBlock), 0, s, a);
 }
 
 }  // namespace rbsog

@@ -3,7 +3,8 @@
 //   F_N,i = sum_{j: r_ij < r_c} q_i q_j (1/r^3 - 2 sum_l omega_l/s_l^2 e^{-r^2/s_l^2}) r_ij
 //   U_N   = 1/2 sum_i sum_j q_i q_j (1/r - sum_l omega_l e^{-r^2/s_l^2})
 //
-// One wave per home cell.  The candidates of a cell are the particles of its
+// Work items are runs of consecutive cells of one system; one wave per item,
+// one home cell at a time.  The candidates of a cell are the particles of its
 // 27 (or fewer) neighbouring cells; the three cells of a row are contiguous
 // in cell order, so they are up to 18 contiguous ranges of the sorted arrays.
 // The wave stages them in LDS with coalesced loads, then tests every (home i,
@@ -11,9 +12,10 @@
 // one candidate in six lies inside r_c: accepted pairs are compacted with a
 // ballot into an LDS queue and evaluated 64 at a time, so the pair arithmetic
 // runs on full waves; forces accumulate into per-home LDS slots.  Blocks take
-// contiguous chunks of cells, and chunks are assigned so that each XCD (blocks
-// are dealt to the 8 XCDs round robin) works on one contiguous slab of the
-// box and keeps it in its own L2.
+// contiguous runs of items, assigned so that each XCD (blocks are dealt to the
+// 8 XCDs round robin) works on one contiguous slab of cells and keeps it in
+// its own L2.  The state is in cell order, so homes and forces are read and
+// written coalesced.
 //
 // Gaussians with r_c^2/s_l^2 <= kTailTau are summed as one polynomial in r^2
 // (their Taylor series, truncated below rounding), the narrow ones with an
@@ -90,16 +92,10 @@ __device__ __forceinline__ bool row_range(const Geom &g, const int32_t *__restri
 
 __device__ __forceinline__ double mi64(double d, double L, double invL) { return d - L * rint(d * invL); }
 
-__device__ double block_sum(double v) {
-    __shared__ double ws[kBlock / 64];
+// Sum over the wave in a fixed order (the same on every run).
+__device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) ws[wid] = v;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < kBlock / 64; ++w) s += ws[w];
-    return s;
+    return v;
 }
 
 // Values the wave holds in common (loaded or broadcast): keep them scalar.
@@ -128,17 +124,42 @@ struct NearLds {
     using R = typename std::conditional<F64, double, float>::type;
     static constexpr int HC = F64 ? 64 : 128;   // home particles staged per batch
     static constexpr int XH = F64 ? HC : 1;
-    uint4 hu[HC];          // home u_x, u_y, u_z, global sorted index
+    uint4 hu[HC];          // home u_x, u_y, u_z, slot
     R hq[HC];
     double hx[3][XH];
     R hf[3][HC];           // force accumulators of the home batch
-    uint2 q[kQueue];       // queued pairs: (home slot, candidate sorted index)
+    uint2 q[kQueue];       // queued pairs: (home index in the batch, candidate slot)
 };
 
+// Per-system constants are read through the constant address space, so that
+// uniform reads become scalar loads.
+typedef const SysDev __attribute__((address_space(4))) CSys;
+typedef const SplitCoef64 __attribute__((address_space(4))) CCoef64;
+typedef const SplitCoef32 __attribute__((address_space(4))) CCoef32;
 template <bool F64>
-struct CoefOf { using type = SplitCoef32; };
+struct CoefOf { using type = CCoef32; };
+
+// Field-wise copy of a system's geometry out of the constant address space.
+__device__ __forceinline__ Geom load_geom(CSys *sp) {
+    Geom g;
+    g.n = sp->g.n;
+    for (int d = 0; d < 3; ++d) {
+        g.L[d] = sp->g.L[d];
+        g.invL[d] = sp->g.invL[d];
+        g.h[d] = sp->g.h[d];
+        g.hf[d] = sp->g.hf[d];
+        g.nc[d] = sp->g.nc[d];
+        g.reach[d] = sp->g.reach[d];
+    }
+    g.rc2 = sp->g.rc2;
+    g.band_lo = sp->g.band_lo;
+    g.band_hi = sp->g.band_hi;
+    g.band_lo_f = sp->g.band_lo_f;
+    g.band_hi_f = sp->g.band_hi_f;
+    return g;
+}
 template <>
-struct CoefOf<true> { using type = SplitCoef64; };
+struct CoefOf<true> { using type = CCoef64; };
 
 // Evaluate the first `count` queued pairs, one per lane.  The test admitted
 // every pair with an approximate r^2 below the upper band edge; here the pair
@@ -149,13 +170,12 @@ struct CoefOf<true> { using type = SplitCoef64; };
 // candidate pass, so forces are summed by a segmented scan across the wave
 // and the last lane of each segment adds the total to the home accumulator.
 template <bool F64>
-__device__ __forceinline__ void eval_batch(const Geom &g, const typename CoefOf<F64>::type &co, NearLds<F64> &L,
+__device__ __forceinline__ void eval_batch(const Geom &g, typename CoefOf<F64>::type *co, NearLds<F64> &L,
                                            const uint32_t *__restrict__ su, const double *__restrict__ sx,
-                                           const double *__restrict__ sq, const float *__restrict__ sqf, int lane,
-                                           int count, double &e) {
+                                           const double *__restrict__ sq, const float *__restrict__ sqf, int64_t n,
+                                           int lane, int count, double &e) {
     using R = typename NearLds<F64>::R;
     constexpr int NT = (F64 ? kTailDeg64 : kTailDeg32) + 1;
-    const int64_t n = g.n;
     R fx = 0, fy = 0, fz = 0;
     int slot = -1;
     if (lane < count) {
@@ -187,15 +207,15 @@ __device__ __forceinline__ void eval_batch(const Geom &g, const typename CoefOf<
             else rinv = __builtin_amdgcn_rsqf(r2);
 #pragma unroll
             for (int t = NT - 1; t >= 0; --t) {
-                if constexpr (F64) { gs = fma(gs, r2, co.ft[t]); ph = fma(ph, r2, co.pt[t]); }
-                else { gs = fmaf(gs, r2, co.ft[t]); ph = fmaf(ph, r2, co.pt[t]); }
+                if constexpr (F64) { gs = fma(gs, r2, co->ft[t]); ph = fma(ph, r2, co->pt[t]); }
+                else { gs = fmaf(gs, r2, co->ft[t]); ph = fmaf(ph, r2, co->pt[t]); }
             }
-            for (int l = 0; l < co.nexp; ++l) {
+            for (int l = 0; l < co->nexp; ++l) {
                 R ex;
-                if constexpr (F64) ex = exp(-r2 * co.a[l]);
-                else ex = __builtin_amdgcn_exp2f(-r2 * co.a[l]);
-                gs += co.cw[l] * ex;
-                ph += co.w[l] * ex;
+                if constexpr (F64) ex = exp(-r2 * co->a[l]);
+                else ex = __builtin_amdgcn_exp2f(-r2 * co->a[l]);
+                gs += co->cw[l] * ex;
+                ph += co->w[l] * ex;
             }
             const R coef = qq * (rinv * rinv * rinv - gs);
             // force on the home along r_i - r_j = -(dx, dy, dz)
@@ -225,12 +245,8 @@ __device__ __forceinline__ void eval_batch(const Geom &g, const typename CoefOf<
 }
 
 template <bool F64>
-__global__ __launch_bounds__(64 * kNW) void k_near(Geom g, typename CoefOf<F64>::type co, int64_t ncell, int64_t cells_per_block,
-                                                   int32_t nblk, const int32_t *__restrict__ start,
-                                                   const int32_t *__restrict__ order, const uint32_t *__restrict__ su,
-                                                   const double *__restrict__ sx, const double *__restrict__ sq,
-                                                   const float *__restrict__ sqf, double *__restrict__ Fn,
-                                                   double *__restrict__ epart) {
+__global__ __launch_bounds__(64 * kNW) void k_near(EvalArgs a, const NearItem *__restrict__ items, int32_t nitems,
+                                                   int32_t nblk) {
     using Lds = NearLds<F64>;
     using R = typename Lds::R;
     constexpr int S = 2;  // candidate slots per lane and pass
@@ -238,17 +254,28 @@ __global__ __launch_bounds__(64 * kNW) void k_near(Geom g, typename CoefOf<F64>:
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     Lds &L = lds[wave];
-    const int64_t n = g.n;
+    const int64_t n = a.N;  // stride of the structure-of-arrays
+    const int32_t *__restrict__ start = a.cell_start;
+    const uint32_t *__restrict__ su = a.u;
+    const double *__restrict__ sx = a.nxt.x;
+    const double *__restrict__ sq = a.nxt.q;
+    const float *__restrict__ sqf = a.nxt.qf;
+    double *__restrict__ Fn = a.Fn;
     // blocks are dealt to the 8 XCDs round robin: block b (on XCD b % 8) takes
-    // chunk (b % 8) * (nblk / 8) + b / 8, so each XCD sweeps one slab of cells;
-    // within the chunk each wave owns a contiguous run of cells
+    // chunk (b % 8) * (nblk / 8) + b / 8 of the item list, so each XCD sweeps
+    // one slab of cells
     const int32_t b = blockIdx.x;
     const int32_t chunk = (b % 8) * (nblk / 8) + b / 8;
-    const int64_t c0 = (int64_t)chunk * cells_per_block;
-    const int64_t c1 = c0 + cells_per_block < ncell ? c0 + cells_per_block : ncell;
-    const int64_t per = (cells_per_block + kNW - 1) / kNW;
-    const int64_t ra = c0 + wave * per < c1 ? c0 + wave * per : c1;
-    const int64_t rb = ra + per < c1 ? ra + per : c1;
+    for (int32_t it = chunk * kNW + wave; it < nitems; it += nblk * kNW) {
+    const NearItem item = items[it];
+    const int32_t sys = rfl(item.sys);
+    CSys *sp = (CSys *)(a.sys + sys);
+    const Geom g = load_geom(sp);
+    typename CoefOf<F64>::type *co;
+    if constexpr (F64) co = &sp->co64;
+    else co = &sp->co32;
+    const int64_t c0s = sp->c0;
+    const int64_t ra = item.c_begin, rb = item.c_end;
     double e = 0.0;
     int qn = 0;
     int32_t t = ra < rb ? rfl(start[ra]) : 0;
@@ -299,7 +326,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near(Geom g, typename CoefOf<F64>:
             const int32_t he = ce < t_end ? ce : t_end;
             if (hs >= he) continue;
             const int i0 = hs - t, i1 = he - t;
-            const uint32_t cu32 = (uint32_t)cell;
+            const uint32_t cu32 = (uint32_t)(cell - c0s);
             const int cx = (int)(cu32 % (uint32_t)g.nc[0]);
             const int cy = (int)((cu32 / (uint32_t)g.nc[0]) % (uint32_t)g.nc[1]);
             const int cz = (int)(cu32 / ((uint32_t)g.nc[0] * (uint32_t)g.nc[1]));
@@ -308,7 +335,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near(Geom g, typename CoefOf<F64>:
             int32_t lo = 0, len = 0;
             if (lane < kRanges) {
                 int32_t ra_, rb_;
-                if (row_range(g, start, lane, cx, cy, cz, ra_, rb_)) { lo = ra_; len = rb_ - ra_; }
+                if (row_range(g, start + c0s, lane, cx, cy, cz, ra_, rb_)) { lo = ra_; len = rb_ - ra_; }
             }
             int32_t incl = len;
             for (int o = 1; o < 32; o <<= 1) {
@@ -410,7 +437,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near(Geom g, typename CoefOf<F64>:
                                 qn += (int)__popcll(m);
                                 if (qn >= 64) {
                                     wave_sync();
-                                    eval_batch<F64>(g, co, L, su, sx, sq, sqf, lane, 64, e);
+                                    eval_batch<F64>(g, co, L, su, sx, sq, sqf, n, lane, 64, e);
                                     const bool mv = lane + 64 < qn;
                                     const uint2 rest = L.q[mv ? lane + 64 : lane];
                                     wave_sync();
@@ -426,33 +453,40 @@ __global__ __launch_bounds__(64 * kNW) void k_near(Geom g, typename CoefOf<F64>:
         }
         // the queue refers to this batch's home slots: drain it, then write
         wave_sync();
-        if (qn > 0) eval_batch<F64>(g, co, L, su, sx, sq, sqf, lane, qn, e);
+        if (qn > 0) eval_batch<F64>(g, co, L, su, sx, sq, sqf, n, lane, qn, e);
         qn = 0;
         wave_sync();
         for (int k = lane; k < H; k += 64) {
-            const int64_t id = order[t + k];
-            Fn[id] = (double)L.hf[0][k]; Fn[n + id] = (double)L.hf[1][k]; Fn[2 * n + id] = (double)L.hf[2][k];
+            const int64_t tt = t + k;
+            Fn[tt] = (double)L.hf[0][k]; Fn[n + tt] = (double)L.hf[1][k]; Fn[2 * n + tt] = (double)L.hf[2][k];
         }
         wave_sync();
         t = t_end;
     }
-    const double s = block_sum(e);
-    if (threadIdx.x == 0) epart[blockIdx.x] = s;
+    const double es = wave_sum(e);
+    if (lane == 0) a.epart[it] = es;
+    }
 }
 
-// Debug export of the neighbour list with exactly the decision of k_near.
+// Debug export of the neighbour list of one system with exactly the pair rule
+// of k_near.  Rows and columns are local ids (id - first id of the system).
 template <bool FILL>
-__global__ void k_neighbors(Geom g, const int32_t *__restrict__ start, const int32_t *__restrict__ order,
-                            const uint32_t *__restrict__ su, int64_t *__restrict__ counts,
-                            const int64_t *__restrict__ row_ptr, int32_t *__restrict__ cols) {
-    const int64_t n = g.n;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const uint32_t ux = su[t], uy = su[n + t], uz = su[2 * n + t];
+__global__ void k_neighbors(EvalArgs a, int32_t sys, int64_t nloc, int64_t p0, const int32_t *__restrict__ idc,
+                            int64_t *__restrict__ counts, const int64_t *__restrict__ row_ptr,
+                            int32_t *__restrict__ cols) {
+    const int64_t N = a.N;
+    const int64_t tl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tl >= nloc) return;
+    const SysDev &sd = a.sys[sys];
+    const Geom &g = sd.g;
+    const int32_t *start = a.cell_start + sd.c0;
+    const uint32_t *su = a.u;
+    const int64_t t = p0 + tl;
+    const uint32_t ux = su[t], uy = su[N + t], uz = su[2 * N + t];
     const int cx = (int)(((uint64_t)ux * (uint32_t)g.nc[0]) >> 32);
     const int cy = (int)(((uint64_t)uy * (uint32_t)g.nc[1]) >> 32);
     const int cz = (int)(((uint64_t)uz * (uint32_t)g.nc[2]) >> 32);
-    const int64_t id = order[t];
+    const int64_t id = idc[t] - p0;
     int64_t cnt = 0;
     const int64_t base = FILL ? row_ptr[id] : 0;
     for (int r = 0; r < kRanges; ++r) {
@@ -460,61 +494,48 @@ __global__ void k_neighbors(Geom g, const int32_t *__restrict__ start, const int
         if (!row_range(g, start, r, cx, cy, cz, lo, hi)) continue;
         for (int32_t j = lo; j < hi; ++j) {
             if (j == t) continue;
-            if (!decide(g, su[j] - ux, su[n + j] - uy, su[2 * n + j] - uz)) continue;
-            if (FILL) cols[base + cnt] = order[j];
+            if (!decide(g, su[j] - ux, su[N + j] - uy, su[2 * N + j] - uz)) continue;
+            if (FILL) cols[base + cnt] = (int32_t)(idc[j] - p0);
             ++cnt;
         }
     }
     if (!FILL) {
         counts[id] = cnt;
     } else {
-        for (int64_t a = base + 1; a < base + cnt; ++a) {
-            const int32_t v = cols[a];
-            int64_t b = a - 1;
-            while (b >= base && cols[b] > v) {
-                cols[b + 1] = cols[b];
-                --b;
+        for (int64_t x = base + 1; x < base + cnt; ++x) {
+            const int32_t v = cols[x];
+            int64_t y = x - 1;
+            while (y >= base && cols[y] > v) {
+                cols[y + 1] = cols[y];
+                --y;
             }
-            cols[b + 1] = v;
+            cols[y + 1] = v;
         }
     }
 }
 
 }  // namespace
 
-NearPlan near_plan(int64_t ncell) {
-    // a multiple of 8 blocks (one contiguous slab per XCD); each wave owns a
-    // run of about 8 cells, capped at 2048 blocks
-    NearPlan p;
-    int64_t nb = (ncell + 8 * kNW * 8 - 1) / (8 * kNW * 8);
-    if (nb > 256) nb = 256;
-    if (nb < 1) nb = 1;
-    p.nblk = (int32_t)(8 * nb);
-    p.cells_per_block = (ncell + p.nblk - 1) / p.nblk;
-    return p;
+void launch_near(const EvalArgs &a, bool f64, const NearItem *items, int32_t nitems, hipStream_t s) {
+    // one item per wave; a multiple of 8 blocks so that the XCD mapping is a
+    // permutation of the blocks
+    int32_t nblk = (nitems + kNW - 1) / kNW;
+    nblk = (nblk + 7) / 8 * 8;
+    if (nblk < 8) nblk = 8;
+    dim3 grid((unsigned)nblk), block(64 * kNW);
+    if (f64) hipLaunchKernelGGL(k_near<true>, grid, block, 0, s, a, items, nitems, nblk);
+    else hipLaunchKernelGGL(k_near<false>, grid, block, 0, s, a, items, nitems, nblk);
 }
 
-void launch_near(const Geom &g, const SplitCoef64 &c64, const SplitCoef32 &c32, bool f64, const NearPlan &np, int64_t ncell, const int32_t *start,
-                 const int32_t *order, const uint32_t *su, const double *sx, const double *sq, const float *sqf,
-                 double *Fn, double *epart, hipStream_t s) {
-    dim3 grid((unsigned)np.nblk), block(64 * kNW);
-    if (f64)
-        hipLaunchKernelGGL(k_near<true>, grid, block, 0, s, g, c64, ncell, np.cells_per_block, np.nblk, start, order,
-                           su, sx, sq, sqf, Fn, epart);
-    else
-        hipLaunchKernelGGL(k_near<false>, grid, block, 0, s, g, c32, ncell, np.cells_per_block, np.nblk, start, order,
-                           su, sx, sq, sqf, Fn, epart);
-}
-
-void launch_neighbor_count(const Geom &g, const int32_t *start, const int32_t *order, const uint32_t *su,
+void launch_neighbor_count(const EvalArgs &a, int32_t sys, int64_t n, int64_t p0, const int32_t *id_cur,
                            int64_t *counts, hipStream_t s) {
-    hipLaunchKernelGGL(k_neighbors<false>, dim3(grid_for(g.n, kBlock)), dim3(kBlock), 0, s, g, start, order, su,
+    hipLaunchKernelGGL(k_neighbors<false>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, a, sys, n, p0, id_cur,
                        counts, (const int64_t *)nullptr, (int32_t *)nullptr);
 }
 
-void launch_neighbor_fill(const Geom &g, const int32_t *start, const int32_t *order, const uint32_t *su,
+void launch_neighbor_fill(const EvalArgs &a, int32_t sys, int64_t n, int64_t p0, const int32_t *id_cur,
                           const int64_t *row_ptr, int32_t *cols, hipStream_t s) {
-    hipLaunchKernelGGL(k_neighbors<true>, dim3(grid_for(g.n, kBlock)), dim3(kBlock), 0, s, g, start, order, su,
+    hipLaunchKernelGGL(k_neighbors<true>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, a, sys, n, p0, id_cur,
                        (int64_t *)nullptr, row_ptr, cols);
 }
 

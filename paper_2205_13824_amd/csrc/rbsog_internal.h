@@ -1,12 +1,17 @@
 // Internal declarations shared by the host side (capi.hip) and the kernels
 // (kernels_*.hip) of librbsog.  Not part of the public ABI.
+//
+// A context holds a batch of S >= 1 independent periodic systems.  Device
+// arrays concatenate the systems: the particles of system s occupy slots
+// [p0_s, p0_s + n_s), its cells [c0_s, c0_s + ncell_s) and its wave-vector
+// records [k0_s, k0_s + P_s).  Particle state is kept in cell order: each
+// force evaluation re-sorts it by (cell, id), id being the particle's index in
+// the caller's arrays, so slots of one system stay in that system's range.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
-#include <string>
-#include <vector>
 
 #include "rbsog.h"
 
@@ -28,7 +33,7 @@ struct KRec32 {
     float re, im;
 };
 
-// Geometry and split constants passed by value to the kernels.
+// Geometry of one system.
 struct Geom {
     int64_t n;
     double L[3], invL[3], h[3];  // h = L * 2^-32
@@ -50,8 +55,6 @@ constexpr int kTailDeg64 = 8;
 constexpr int kTailDeg32 = 6;
 constexpr int kMaxExp = 24;  // narrow Gaussians per split (more is rejected)
 
-// Split coefficients, passed by value in the near kernel's arguments so that
-// every lane reads them through the scalar unit.
 template <typename R, int NT>
 struct SplitCoef {
     R a[kMaxExp];   // 1/s_l^2 (FP32: log2(e)/s_l^2, for exp2)
@@ -64,102 +67,101 @@ struct SplitCoef {
 using SplitCoef64 = SplitCoef<double, kTailDeg64 + 1>;
 using SplitCoef32 = SplitCoef<float, kTailDeg32 + 1>;
 
-// Arguments of the k-batch staging (Algorithm 1: the next P frequencies of the
-// pre-sampled sequence, in order) and of the velocity-Verlet half kicks.
-struct StageArgs {
-    int32_t P;
-    const int32_t *kseq;  // sequence, 3 int32 per vector
+// Per-system constants, one entry per system in a device array.
+struct SysDev {
+    Geom g;
+    SplitCoef64 co64;
+    SplitCoef32 co32;
+    int64_t p0;           // first particle slot
+    int64_t c0;           // first cell
+    int32_t P;            // wave vectors per evaluation
+    int32_t k0;           // first k record
+    const int32_t *kseq;  // the system's wave-vector sequence, 3 int32 per vector
     const double *kw;     // per-vector weights, or null for the random-batch weight
     double w_rb;          // S pi^{3/2} / (P V)
-    int64_t *cursor;      // device cursor (vectors consumed)
-    KRec64 *kb64;
-    KRec32 *kb32;
-    double *wk;
-};
-struct KickArgs {
-    int32_t on;      // 0: no kick
-    double hdm;      // dt / (2 m)
-    double dt;       // drift step (kick-drift kernel only)
-    double *v;
-    const double *Fn, *Ff;
-    int32_t *flag;   // bit 0: non-finite force
+    double uself;         // U_self
+    int32_t it0, it1;     // near work items [it0, it1)
+    int64_t pofs;         // first rho partial (complex entries) of the system
+    int32_t nch;          // rho particle chunks of the system
+    int32_t kt, streams;  // rho block shape: k tiles of 64 lanes x particle streams
 };
 
-// Stage the current batch: per-k records for both precisions and the weights,
-// then advance the cursor.  Called by one whole block.
-__device__ inline void stage_batch(const Geom &g, const StageArgs &a) {
-    constexpr double kTwoPi = 6.283185307179586476925286766559;
-    const int64_t base = *a.cursor;
-    for (int32_t k = threadIdx.x; k < a.P; k += blockDim.x) {
-        const int64_t e = base + k;
-        const int32_t mx = a.kseq[3 * e], my = a.kseq[3 * e + 1], mz = a.kseq[3 * e + 2];
-        const double w = a.kw ? a.kw[e] : a.w_rb;
-        const double kx = kTwoPi * g.invL[0] * mx, ky = kTwoPi * g.invL[1] * my, kz = kTwoPi * g.invL[2] * mz;
-        KRec64 r;
-        r.mx = mx; r.my = my; r.mz = mz;
-        r.ckx = w * kx; r.cky = w * ky; r.ckz = w * kz;
-        r.re = 0.0; r.im = 0.0;
-        a.kb64[k] = r;
-        KRec32 h;
-        h.mx = mx; h.my = my; h.mz = mz;
-        h.ckx = (float)r.ckx; h.cky = (float)r.cky; h.ckz = (float)r.ckz;
-        h.re = 0.f; h.im = 0.f;
-        a.kb32[k] = h;
-        a.wk[k] = w;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) *a.cursor = base + a.P;
-}
+// Near work item: a run of cells of one system.
+struct NearItem {
+    int32_t sys;
+    int32_t pad;
+    int64_t c_begin, c_end;
+};
+// Structure-factor work item: particle slots [j0, j1) of one system against
+// the k tiles of group kg; its partials go to chunk `chunk` of the system.
+struct RhoItem {
+    int32_t sys, kg, chunk, pad;
+    int64_t j0, j1;
+};
+// Far-force work item: particle slots [t0, t1) of one system (<= 256).
+struct FarItem {
+    int32_t sys, pad;
+    int64_t t0, t1;
+};
+
+// Buffers of one evaluation.  State arrays come in two copies; `cur` is the
+// order the evaluation starts from, `nxt` receives the new cell order.
+struct StateBufs {
+    double *x, *v, *q;
+    float *qf;
+    int32_t *id;
+};
+struct EvalArgs {
+    int64_t N;             // particles over all systems
+    int64_t C;             // cells over all systems
+    int32_t nsys;
+    int32_t K;             // k records over all systems
+    const SysDev *sys;
+    const int32_t *sys_of;  // system of each slot (static)
+    const int32_t *ksys;    // system of each k record (static)
+    StateBufs cur, nxt;
+    uint32_t *u_tmp;       // fixed-point coordinates in `cur` order
+    uint32_t *u;           // fixed-point coordinates in cell order
+    int32_t *cell_of, *cell_count, *cell_start, *cell_fill, *src, *blocksums;
+    double *Fn, *Ff;       // forces in cell order
+    int64_t *kcur;         // per-system sequence cursor
+    KRec64 *kb64;
+    KRec32 *kb32;
+    double *wk, *rho, *ek, *partial, *epart, *E;
+    int32_t *flag;         // bit 0: non-finite force, bit 1: non-finite energy
+    uint32_t *sys_done;    // per-system counters of reduced k records
+    // velocity-Verlet
+    int32_t kick;          // nonzero: kick + drift before, kick after
+    double hdm, dt;
+};
 
 // ---- kernel launchers (kernels_md.hip) --------------------------------------
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
-// kick dt/2 + drift (if kick.on), wrap, quantise, cell histogram; the last
-// block stages the k batch
-void launch_kdq(const Geom &g, const KickArgs &kick, const StageArgs &stage, double *x, uint32_t *u,
-                int32_t *cell_of, int32_t *cell_count, hipStream_t s);
-void launch_scan(const int32_t *in, int32_t *out_excl, int32_t *fill_copy, int64_t n, int32_t *blocksums,
-                 hipStream_t s);
+// kick dt/2 + drift (if a.kick), wrap, quantise, cell histogram; extra blocks
+// stage the k batch of every system
+void launch_kdq(const EvalArgs &a, hipStream_t s);
+void launch_scan(const EvalArgs &a, hipStream_t s);
 int64_t scan_blocksums_size(int64_t n);
-void launch_cell_scatter(const Geom &g, const int32_t *cell_of, int32_t *fill, int32_t *order, hipStream_t s);
-// per cell: id sort of its segment and reset of its histogram count; then gather into cell order
-void launch_sort_gather(const Geom &g, int64_t ncell, const int32_t *start, int32_t *order, int32_t *cell_count,
-                        const uint32_t *u, const double *x, const double *q, uint32_t *su, double *sx, double *sq,
-                        float *sqf, bool f64, hipStream_t s);
+void launch_cell_scatter(const EvalArgs &a, hipStream_t s);
+// per cell: id sort of its segment, reset of its histogram count, gather of
+// the state into the new order
+void launch_sort_gather(const EvalArgs &a, hipStream_t s);
 
 // ---- near part (kernels_near.hip) ------------------------------------------
-struct NearPlan {
-    int32_t nblk;             // blocks (a multiple of 8)
-    int64_t cells_per_block;  // contiguous cells per block
-};
-NearPlan near_plan(int64_t ncell);
-void launch_near(const Geom &g, const SplitCoef64 &c64, const SplitCoef32 &c32, bool f64, const NearPlan &np, int64_t ncell, const int32_t *start,
-                 const int32_t *order, const uint32_t *su, const double *sx, const double *sq, const float *sqf,
-                 double *Fn, double *epart, hipStream_t s);
-void launch_neighbor_count(const Geom &g, const int32_t *start, const int32_t *order, const uint32_t *su,
+void launch_near(const EvalArgs &a, bool f64, const NearItem *items, int32_t nitems, hipStream_t s);
+// neighbour list of one system (debug export): counts per local id, then fill
+void launch_neighbor_count(const EvalArgs &a, int32_t sys, int64_t n, int64_t p0, const int32_t *id_cur,
                            int64_t *counts, hipStream_t s);
-void launch_neighbor_fill(const Geom &g, const int32_t *start, const int32_t *order, const uint32_t *su,
+void launch_neighbor_fill(const EvalArgs &a, int32_t sys, int64_t n, int64_t p0, const int32_t *id_cur,
                           const int64_t *row_ptr, int32_t *cols, hipStream_t s);
 
 // ---- far part (kernels_far.hip) --------------------------------------------
-struct FarPlan {
-    int kt;        // k tiles of 64 lanes per block
-    int streams;   // particle streams (waves per k tile) per block
-    int64_t chunk; // particles per block
-    int64_t nblk;  // blocks along the particle axis
-    int64_t kblk;  // blocks along the k axis
-};
-FarPlan far_plan(int64_t n, int32_t P);
-void launch_rho(const Geom &g, const FarPlan &fp, int32_t P, bool f64, const double *x, const uint32_t *u,
-                const double *q, const float *qf, const KRec64 *kb64, const KRec32 *kb32, double *partial,
-                hipStream_t s);
-// rho_e, its records and per-k energies; the last block to finish also sums
-// the energies (U_N from the near partials, U*, U_self, U) and re-arms counter
-void launch_rho_reduce(int32_t P, int64_t nblk, const double *partial, const double *wk, KRec64 *kb64,
-                       KRec32 *kb32, double *rho, double *ek, int64_t nnear, const double *epart, double uself,
-                       double *E, int32_t *flag, uint32_t *counter, hipStream_t s);
-// far force; with kick.on the closing half kick v += dt/(2m) (F_N + F*) follows
-void launch_far(const Geom &g, int32_t P, bool f64, const double *x, const uint32_t *u, const double *q,
-                const float *qf, const KRec64 *kb64, const KRec32 *kb32, double *Ff, const KickArgs &kick,
-                hipStream_t s);
+void launch_rho(const EvalArgs &a, bool f64, const RhoItem *items, int32_t nitems, hipStream_t s);
+// rho_e per record from the partials (fixed order), its records and per-k
+// energies; the block that completes a system's records also sums that
+// system's energies and advances its sequence cursor
+void launch_rho_reduce(const EvalArgs &a, hipStream_t s);
+// far force; with a.kick the closing half kick v += dt/(2m) (F_N + F*) follows
+void launch_far(const EvalArgs &a, bool f64, const FarItem *items, int32_t nitems, hipStream_t s);
 
 }  // namespace rbsog

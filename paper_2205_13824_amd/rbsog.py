@@ -22,7 +22,8 @@ STATUS = {0: "RBSOG_OK", -1: "RBSOG_E_ARG", -2: "RBSOG_E_NOT_NEUTRAL", -3: "RBSO
           -5: "RBSOG_E_DEVICE", -6: "RBSOG_E_OOM", -7: "RBSOG_E_NONFINITE", -8: "RBSOG_E_KSEQ", -9: "RBSOG_E_STATE"}
 
 # every symbol the header declares
-EXPORTS = ("rbsog_default_opts", "rbsog_sog_table1", "rbsog_init", "rbsog_sample_k", "rbsog_set_k", "rbsog_forces",
+EXPORTS = ("rbsog_default_opts", "rbsog_sog_table1", "rbsog_init", "rbsog_init_batch", "rbsog_sample_k",
+           "rbsog_set_k", "rbsog_forces",
            "rbsog_step", "rbsog_set_velocities", "rbsog_set_positions", "rbsog_get_state", "rbsog_get_forces",
            "rbsog_get_energy", "rbsog_get_rho", "rbsog_info", "rbsog_debug_cells", "rbsog_debug_neighbors",
            "rbsog_profile", "rbsog_profile_read", "rbsog_sync", "rbsog_last_error", "rbsog_status_string",
@@ -46,7 +47,8 @@ class rbsog_opts(ctypes.Structure):
 
 class rbsog_info_t(ctypes.Structure):
     _fields_ = [("S", ctypes.c_double), ("volume", ctypes.c_double), ("ncell", ctypes.c_int32 * 3),
-                ("k_remaining", ctypes.c_int64), ("evaluations", ctypes.c_int64)]
+                ("k_remaining", ctypes.c_int64), ("evaluations", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("n_sys", ctypes.c_int32)]
 
 
 _lib = None
@@ -65,8 +67,9 @@ def lib():
             "rbsog_default_opts": (None, [P(rbsog_opts)]),
             "rbsog_sog_table1": (i32, [i32, dbl, P(rbsog_sog)]),
             "rbsog_init": (i32, [P(vp), i64, vp, vp, vp, P(rbsog_sog), dbl, i32, u64, P(rbsog_opts)]),
+            "rbsog_init_batch": (i32, [P(vp), i32, vp, vp, vp, vp, vp, vp, vp, vp, P(rbsog_opts)]),
             "rbsog_sample_k": (i32, [vp, i64, vp]),
-            "rbsog_set_k": (i32, [vp, i64, vp, vp]),
+            "rbsog_set_k": (i32, [vp, i32, i64, vp, vp]),
             "rbsog_forces": (i32, [vp, vp, vp]),
             "rbsog_step": (i32, [vp, i64, dbl]),
             "rbsog_set_velocities": (i32, [vp, vp, dbl, u64]),
@@ -74,10 +77,10 @@ def lib():
             "rbsog_get_state": (i32, [vp, vp, vp]),
             "rbsog_get_forces": (i32, [vp, vp, vp]),
             "rbsog_get_energy": (i32, [vp, vp]),
-            "rbsog_get_rho": (i32, [vp, vp, vp]),
-            "rbsog_info": (i32, [vp, P(rbsog_info_t)]),
-            "rbsog_debug_cells": (i32, [vp, vp, vp]),
-            "rbsog_debug_neighbors": (i32, [vp, vp, vp, i64]),
+            "rbsog_get_rho": (i32, [vp, i32, vp, vp]),
+            "rbsog_info": (i32, [vp, i32, P(rbsog_info_t)]),
+            "rbsog_debug_cells": (i32, [vp, i32, vp, vp]),
+            "rbsog_debug_neighbors": (i32, [vp, i32, vp, vp, i64]),
             "rbsog_profile": (i32, [vp, i32]),
             "rbsog_profile_read": (i32, [vp, i32, P(ctypes.c_char_p), P(dbl), P(i64)]),
             "rbsog_sync": (i32, [vp]),
@@ -119,6 +122,13 @@ def rbsog_default_opts() -> rbsog_opts:
     return o
 
 
+def _opts(precision, device, stream, neutral_tol, mass, graphs):
+    o = rbsog_default_opts()
+    o.precision, o.device, o.neutral_tol, o.mass, o.graphs = precision, device, neutral_tol, mass, int(graphs)
+    o.stream = stream
+    return o
+
+
 def rbsog_init(pos, q, box, sog: rbsog_sog, rc: float, P: int, seed: int, precision: int = RBSOG_FP64,
                device: int = 0, stream: int | None = None, neutral_tol: float = 1e-10, mass: float = 1.0,
                graphs: bool = True):
@@ -126,30 +136,55 @@ def rbsog_init(pos, q, box, sog: rbsog_sog, rc: float, P: int, seed: int, precis
     n = q.size
     pos = _f64(pos, (n, 3))
     box = _f64(box, (3,))
-    o = rbsog_default_opts()
-    o.precision, o.device, o.neutral_tol, o.mass, o.graphs = precision, device, neutral_tol, mass, int(graphs)
-    o.stream = stream
+    o = _opts(precision, device, stream, neutral_tol, mass, graphs)
     ctx = ctypes.c_void_p()
     _check(lib().rbsog_init(ctypes.byref(ctx), n, _ptr(pos), _ptr(q), _ptr(box), ctypes.byref(sog), float(rc),
                             int(P), int(seed), ctypes.byref(o)))
     return ctx
 
 
+def rbsog_init_batch(pos_list, q_list, boxes, sogs, rcs, Ps, seeds, precision: int = RBSOG_FP64, device: int = 0,
+                     stream: int | None = None, neutral_tol: float = 1e-10, mass: float = 1.0, graphs: bool = True):
+    """One context over len(q_list) systems; particle arrays are concatenated."""
+    ns = len(q_list)
+    sizes = [int(np.asarray(qq).size) for qq in q_list]
+    offsets = np.zeros(ns + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(sizes)
+    pos = np.ascontiguousarray(np.concatenate([_f64(p_, (n_, 3)) for p_, n_ in zip(pos_list, sizes)]))
+    q = np.ascontiguousarray(np.concatenate([_f64(qq, (-1,)) for qq in q_list]))
+    box = _f64(boxes, (ns, 3))
+    sog_arr = (rbsog_sog * ns)(*sogs)
+    rc = _f64(rcs, (ns,))
+    Pa = np.ascontiguousarray(np.asarray(Ps, dtype=np.int32).reshape(ns))
+    sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64).reshape(ns))
+    o = _opts(precision, device, stream, neutral_tol, mass, graphs)
+    ctx = ctypes.c_void_p()
+    _check(lib().rbsog_init_batch(ctypes.byref(ctx), ns, _ptr(offsets), _ptr(pos), _ptr(q), _ptr(box),
+                                  ctypes.cast(sog_arr, ctypes.c_void_p), _ptr(rc), _ptr(Pa), _ptr(sd),
+                                  ctypes.byref(o)))
+    return ctx
+
+
 def rbsog_sample_k(ctx, n_batches: int, P: int):
+    """New states of every system, system after system (P: the sum of P_s)."""
     out = np.zeros((n_batches * P, 3), dtype=np.int32)
     _check(lib().rbsog_sample_k(ctx, int(n_batches), _ptr(out)), ctx)
     return out
 
 
-def rbsog_set_k(ctx, m, w=None):
+def rbsog_set_k(ctx, m, w=None, sys: int = 0):
     m = np.ascontiguousarray(np.asarray(m, dtype=np.int32).reshape(-1, 3))
     wv = None if w is None else _f64(w, (m.shape[0],))
-    _check(lib().rbsog_set_k(ctx, m.shape[0], _ptr(m), _ptr(wv)), ctx)
+    _check(lib().rbsog_set_k(ctx, int(sys), m.shape[0], _ptr(m), _ptr(wv)), ctx)
+
+
+def n_systems(ctx) -> int:
+    return rbsog_info(ctx, 0)["n_sys"]
 
 
 def rbsog_forces(ctx, n: int, want_forces: bool = True, want_energy: bool = True):
     F = np.zeros((n, 3)) if want_forces else None
-    E = np.zeros(4) if want_energy else None
+    E = np.zeros(4 * n_systems(ctx)) if want_energy else None
     _check(lib().rbsog_forces(ctx, _ptr(F), _ptr(E)), ctx)
     return F, E
 
@@ -182,40 +217,42 @@ def rbsog_get_forces(ctx, n: int):
 
 
 def rbsog_get_energy(ctx):
-    E = np.zeros(4)
+    E = np.zeros(4 * n_systems(ctx))
     _check(lib().rbsog_get_energy(ctx, _ptr(E)), ctx)
     return E
 
 
-def rbsog_get_rho(ctx, P: int):
+def rbsog_get_rho(ctx, P: int, sys: int = 0):
     re = np.zeros(P)
     im = np.zeros(P)
-    _check(lib().rbsog_get_rho(ctx, _ptr(re), _ptr(im)), ctx)
+    _check(lib().rbsog_get_rho(ctx, int(sys), _ptr(re), _ptr(im)), ctx)
     return re, im
 
 
-def rbsog_info(ctx) -> dict:
+def rbsog_info(ctx, sys: int = 0) -> dict:
     info = rbsog_info_t()
-    _check(lib().rbsog_info(ctx, ctypes.byref(info)), ctx)
+    _check(lib().rbsog_info(ctx, int(sys), ctypes.byref(info)), ctx)
     return dict(S=info.S, volume=info.volume, ncell=tuple(info.ncell), k_remaining=info.k_remaining,
-                evaluations=info.evaluations)
+                evaluations=info.evaluations, n=info.n, n_sys=info.n_sys)
 
 
-def rbsog_debug_cells(ctx, n: int):
-    nc = rbsog_info(ctx)["ncell"]
+def rbsog_debug_cells(ctx, n: int | None = None, sys: int = 0):
+    info = rbsog_info(ctx, sys)
+    nc = info["ncell"]
     start = np.zeros(nc[0] * nc[1] * nc[2] + 1, dtype=np.int32)
-    order = np.zeros(n, dtype=np.int32)
-    _check(lib().rbsog_debug_cells(ctx, _ptr(start), _ptr(order)), ctx)
+    order = np.zeros(info["n"], dtype=np.int32)
+    _check(lib().rbsog_debug_cells(ctx, int(sys), _ptr(start), _ptr(order)), ctx)
     return start, order
 
 
-def rbsog_debug_neighbors(ctx, n: int):
+def rbsog_debug_neighbors(ctx, n: int | None = None, sys: int = 0):
+    n = rbsog_info(ctx, sys)["n"]
     row = np.zeros(n + 1, dtype=np.int64)
-    st = lib().rbsog_debug_neighbors(ctx, _ptr(row), None, 0)
+    st = lib().rbsog_debug_neighbors(ctx, int(sys), _ptr(row), None, 0)
     if st not in (0, -1):
         _check(st, ctx)
     cols = np.zeros(max(int(row[-1]), 1), dtype=np.int32)
-    _check(lib().rbsog_debug_neighbors(ctx, _ptr(row), _ptr(cols), cols.size), ctx)
+    _check(lib().rbsog_debug_neighbors(ctx, int(sys), _ptr(row), _ptr(cols), cols.size), ctx)
     return row, cols[:int(row[-1])]
 
 
@@ -260,10 +297,49 @@ class System:
         return rbsog_sample_k(self.ctx, n_batches, self.P)
 
     def set_k(self, m, w=None):
-        rbsog_set_k(self.ctx, m, w)
+        rbsog_set_k(self.ctx, m, w, 0)
 
     def forces(self):
         return rbsog_forces(self.ctx, self.n)
+
+    def components(self):
+        return rbsog_get_forces(self.ctx, self.n)
+
+    def step(self, n_steps, dt):
+        rbsog_step(self.ctx, n_steps, dt)
+
+    def close(self):
+        if self.ctx:
+            rbsog_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Owning wrapper of a batch context: systems given as lists."""
+
+    def __init__(self, pos_list, q_list, boxes, rc, P, seeds, sogs=None, precision=RBSOG_FP64, **kw):
+        ns = len(q_list)
+        self.sizes = [int(np.asarray(qq).size) for qq in q_list]
+        self.n = int(sum(self.sizes))
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
+        rcs = np.broadcast_to(np.asarray(rc, dtype=np.float64), (ns,))
+        self.Ps = np.broadcast_to(np.asarray(P, dtype=np.int32), (ns,)).copy()
+        self.sogs = sogs if sogs is not None else [rbsog_sog_table1(2, float(r)) for r in rcs]
+        self.ctx = rbsog_init_batch(pos_list, q_list, boxes, self.sogs, rcs, self.Ps, seeds, precision=precision,
+                                    **kw)
+
+    def sample_k(self, n_batches):
+        return rbsog_sample_k(self.ctx, n_batches, int(self.Ps.sum()))
+
+    def forces(self):
+        F, E = rbsog_forces(self.ctx, self.n)
+        return F, E.reshape(-1, 4)
 
     def components(self):
         return rbsog_get_forces(self.ctx, self.n)

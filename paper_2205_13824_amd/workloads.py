@@ -179,3 +179,14 @@ def c3_water(n_side: int = 100):
     """n_side^3 water-shaped molecules at 0.0334 / A^3, r_c = 10 A, P = 500."""
     pos, q, box = water(n_side, 0.0334, seed=3)
     return dict(pos=pos, q=q, box=box, rc=10.0, P=500)
+
+
+def c4_ensemble(n_sys: int = 256, nmin: int = 500, nmax: int = 50_000, seed: int = 4):
+    """Replica ensemble: n_sys +-1 electrolytes at density 0.1 (RSA, d_min = 1)
+    with log-uniform sizes in [nmin, nmax], r_c = 3.5, P = 100, seeds 1000 + r."""
+    sizes = ensemble_sizes(n_sys, nmin, nmax, seed)
+    systems = []
+    for r, n in enumerate(sizes):
+        pos, q, box = ions_rsa(int(n), 0.1, 1.0, seed=1000 + r)
+        systems.append(dict(pos=pos, q=q, box=box))
+    return dict(systems=systems, rc=3.5, P=100, seeds=[1000 + r for r in range(n_sys)])
