@@ -130,7 +130,7 @@ struct rbsog_ctx {
     StateBufs buf[2] = {};
     uint32_t *u_tmp = nullptr, *u = nullptr;
     int32_t *cell_of = nullptr, *cell_count = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *src = nullptr,
-            *blocksums = nullptr;
+            *sorted = nullptr, *blocksums = nullptr;
     double *Fn = nullptr, *Ff = nullptr;
     int64_t *kcur = nullptr;
     KRec64 *kb64 = nullptr;
@@ -436,6 +436,7 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
     a.cell_start = c->cell_start;
     a.cell_fill = c->cell_fill;
     a.src = c->src;
+    a.sorted = c->sorted;
     a.blocksums = c->blocksums;
     a.Fn = c->Fn;
     a.Ff = c->Ff;
@@ -826,6 +827,7 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     ALLOC(u, 3 * N);
     ALLOC(cell_of, N);
     ALLOC(src, N);
+    ALLOC(sorted, N);
     ALLOC(cell_count, C);
     ALLOC(cell_start, C + 1);
     ALLOC(cell_fill, C);

@@ -202,7 +202,8 @@ __global__ __launch_bounds__(1024) void k_rho(EvalArgs a, const RhoItem *__restr
                 sr += v.x;
                 si += v.y;
             }
-            const int64_t o = sp->pofs + (int64_t)chunk * P + k;
+            // layout [k][chunk]: the reduction reads each k's partials contiguously
+            const int64_t o = sp->pofs + (int64_t)k * sp->nch + chunk;
             a.partial[2 * o] = sr;
             a.partial[2 * o + 1] = si;
         }
@@ -232,13 +233,22 @@ __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
     if (r < a.K) {
         sys = a.ksys[r];
         const SysDev &sd = a.sys[sys];
-        const int32_t P = sd.P, k = (int32_t)(r - sd.k0);
-        double re = 0.0, im = 0.0;
-        for (int64_t c = lane; c < sd.nch; c += 64) {
-            const int64_t o = sd.pofs + c * P + k;
-            re += a.partial[2 * o];
-            im += a.partial[2 * o + 1];
+        const int32_t k = (int32_t)(r - sd.k0);
+        const double2 *pk = reinterpret_cast<const double2 *>(a.partial) + sd.pofs + (int64_t)k * sd.nch;
+        const int32_t nch = sd.nch;
+        // four independent loads in flight per lane, summed in a fixed order
+        double2 v0 = make_double2(0.0, 0.0), v1 = v0, v2 = v0, v3 = v0;
+        int32_t c = lane;
+        for (; c + 192 < nch; c += 256) {
+            const double2 a0 = pk[c], a1 = pk[c + 64], a2 = pk[c + 128], a3 = pk[c + 192];
+            v0.x += a0.x; v0.y += a0.y; v1.x += a1.x; v1.y += a1.y;
+            v2.x += a2.x; v2.y += a2.y; v3.x += a3.x; v3.y += a3.y;
         }
+        for (; c < nch; c += 64) {
+            const double2 a0 = pk[c];
+            v0.x += a0.x; v0.y += a0.y;
+        }
+        double re = (v0.x + v1.x) + (v2.x + v3.x), im = (v0.y + v1.y) + (v2.y + v3.y);
         re = wave_sum(re);
         im = wave_sum(im);
         if (lane == 0) {
@@ -268,9 +278,17 @@ __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
         __threadfence();
         const int32_t s = fin[f];
         const SysDev &sd = a.sys[s];
-        double un = 0.0, us = 0.0;
-        for (int64_t i = sd.it0 + threadIdx.x; i < sd.it1; i += 256) un += a.epart[i];
-        for (int64_t i = threadIdx.x; i < sd.P; i += 256) us += a.ek[sd.k0 + i];
+        // eight independent loads in flight per thread, summed in a fixed order
+        double u8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int64_t i = sd.it0 + threadIdx.x;
+        for (; i + 7 * 256 < sd.it1; i += 8 * 256) {
+#pragma unroll
+            for (int h = 0; h < 8; ++h) u8[h] += a.epart[i + h * 256];
+        }
+        for (; i < sd.it1; i += 256) u8[0] += a.epart[i];
+        const double un = ((u8[0] + u8[1]) + (u8[2] + u8[3])) + ((u8[4] + u8[5]) + (u8[6] + u8[7]));
+        double us = 0.0;
+        for (int64_t k = threadIdx.x; k < sd.P; k += 256) us += a.ek[sd.k0 + k];
         sr[threadIdx.x] = un;
         si[threadIdx.x] = us;
         __syncthreads();

@@ -167,24 +167,46 @@ __global__ void k_cell_scatter(int64_t N, const int32_t *__restrict__ cell_of, i
     src[dst] = (int32_t)t;
 }
 
-// Per cell: insertion sort of its slots by particle id (the order becomes
-// (cell, id), independent of the scatter's atomic order) and reset of its
-// histogram count for the next evaluation.
+// Per cell: order of its slots by particle id (the order becomes (cell, id),
+// independent of the scatter's atomic order), written to `sorted`, and reset
+// of its histogram count for the next evaluation.  Cells of up to kRankMax
+// particles load their keys at once and rank them in registers; larger cells
+// take an insertion sort in memory.
+constexpr int kRankMax = 16;
+
 __global__ __launch_bounds__(kBlock) void k_cell_sort(EvalArgs a) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.C) return;
     const int32_t lo = a.cell_start[c], hi = a.cell_start[c + 1];
-    int32_t *src = a.src;
+    const int32_t cnt = hi - lo;
+    const int32_t *src = a.src;
+    int32_t *out = a.sorted;
     const int32_t *idc = a.cur.id;
-    for (int32_t i = lo + 1; i < hi; ++i) {
-        const int32_t v = src[i];
-        const int32_t key = idc[v];
-        int32_t j = i - 1;
-        while (j >= lo && idc[src[j]] > key) {
-            src[j + 1] = src[j];
-            --j;
+    if (cnt <= kRankMax) {
+        int32_t sv[kRankMax], key[kRankMax];
+#pragma unroll
+        for (int i = 0; i < kRankMax; ++i) sv[i] = i < cnt ? src[lo + i] : 0;
+#pragma unroll
+        for (int i = 0; i < kRankMax; ++i) key[i] = i < cnt ? idc[sv[i]] : INT32_MAX;
+#pragma unroll
+        for (int i = 0; i < kRankMax; ++i) {
+            int32_t rank = 0;
+#pragma unroll
+            for (int j = 0; j < kRankMax; ++j) rank += key[j] < key[i] ? 1 : 0;
+            if (i < cnt) out[lo + rank] = sv[i];
         }
-        src[j + 1] = v;
+    } else {
+        for (int32_t i = lo; i < hi; ++i) out[i] = src[i];
+        for (int32_t i = lo + 1; i < hi; ++i) {
+            const int32_t v = out[i];
+            const int32_t kv = idc[v];
+            int32_t j = i - 1;
+            while (j >= lo && idc[out[j]] > kv) {
+                out[j + 1] = out[j];
+                --j;
+            }
+            out[j + 1] = v;
+        }
     }
     a.cell_count[c] = 0;
 }
@@ -195,7 +217,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(EvalArgs a) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.N) return;
     const int64_t N = a.N;
-    const int64_t t = a.src[k];
+    const int64_t t = a.sorted[k];
     for (int d = 0; d < 3; ++d) {
         a.nxt.x[d * N + k] = a.cur.x[d * N + t];
         a.nxt.v[d * N + k] = a.cur.v[d * N + t];
@@ -222,6 +244,7 @@ int64_t scan_blocksums_size(int64_t n) { return (n + kScanTile - 1) / kScanTile 
 
 void launch_scan(const EvalArgs &a, hipStream_t s) {
     const int64_t n = a.C;
+
     int64_t nb = (n + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(kBlock), 0, s, a.cell_count, n, a.blocksums);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, a.blocksums, nb);

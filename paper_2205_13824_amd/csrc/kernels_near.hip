@@ -116,7 +116,8 @@ __device__ __forceinline__ double bcast64(double v, int src) {
 }
 
 constexpr int kNW = 4;        // waves per block
-constexpr int kQueue = 128;   // pair queue entries per wave (>= 2 x 64)
+constexpr int kU = 2;         // homes tested together
+constexpr int kQueue = 512;   // pair queue entries per wave: a ring (power of two)
 constexpr uint32_t kNoCand = 0xfffffffeu;  // candidate slot past the end of the list
 
 template <bool F64>
@@ -128,7 +129,7 @@ struct NearLds {
     R hq[HC];
     double hx[3][XH];
     R hf[3][HC];           // force accumulators of the home batch
-    uint2 q[kQueue];       // queued pairs: (home index in the batch, candidate slot)
+    uint2 q[kQueue];       // ring of queued pairs: (home index in the batch, candidate slot)
 };
 
 // Per-system constants are read through the constant address space, so that
@@ -161,7 +162,7 @@ __device__ __forceinline__ Geom load_geom(CSys *sp) {
 template <>
 struct CoefOf<true> { using type = CCoef64; };
 
-// Evaluate the first `count` queued pairs, one per lane.  The test admitted
+// Evaluate `count` queued pairs from the ring position `head`, one per lane.  The test admitted
 // every pair with an approximate r^2 below the upper band edge; here the pair
 // rule is applied: the fixed-point r^2 in FP32 decides below the lower band
 // edge, the exact FP64 rule inside the band (rare).  Then the exact
@@ -173,13 +174,13 @@ template <bool F64>
 __device__ __forceinline__ void eval_batch(const Geom &g, typename CoefOf<F64>::type *co, NearLds<F64> &L,
                                            const uint32_t *__restrict__ su, const double *__restrict__ sx,
                                            const double *__restrict__ sq, const float *__restrict__ sqf, int64_t n,
-                                           int lane, int count, double &e) {
+                                           int lane, int head, int count, double &e) {
     using R = typename NearLds<F64>::R;
     constexpr int NT = (F64 ? kTailDeg64 : kTailDeg32) + 1;
     R fx = 0, fy = 0, fz = 0;
     int slot = -1;
     if (lane < count) {
-        const uint2 qe = L.q[lane];
+        const uint2 qe = L.q[(head + lane) & (kQueue - 1)];
         slot = (int)qe.x;
         const uint32_t j = qe.y;
         const uint4 h = L.hu[slot];
@@ -188,8 +189,9 @@ __device__ __forceinline__ void eval_batch(const Geom &g, typename CoefOf<F64>::
         const float ey_ = (float)(int32_t)duy * g.hf[1];
         const float ez_ = (float)(int32_t)duz * g.hf[2];
         const float r2f = ex_ * ex_ + ey_ * ey_ + ez_ * ez_;
-        bool in = r2f <= g.band_lo_f;
-        if (!in) in = exact_in(g, dux, duy, duz);
+        // the test admits the home itself (r^2 = 0); it is dropped here
+        bool in = r2f <= g.band_lo_f && j != h.w;
+        if (!in && j != h.w) in = exact_in(g, dux, duy, duz);
         if (in) {
             R dx, dy, dz, qq;
             if constexpr (F64) {
@@ -226,8 +228,8 @@ __device__ __forceinline__ void eval_batch(const Geom &g, typename CoefOf<F64>::
         }
     }
     const int prev = __shfl_up(slot, 1, 64);
-    const bool head = lane == 0 || slot != prev;
-    const uint64_t H = __ballot(head);
+    const bool seg = lane == 0 || slot != prev;
+    const uint64_t H = __ballot(seg);
     const uint64_t upto = H & ((2ull << lane) - 1ull);
     const int sstart = 63 - __clzll((long long)upto);
     for (int off = 1; off < 64; off <<= 1) {
@@ -277,7 +279,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near(EvalArgs a, const NearItem *_
     const int64_t c0s = sp->c0;
     const int64_t ra = item.c_begin, rb = item.c_end;
     double e = 0.0;
-    int qn = 0;
+    int qn = 0, qh = 0;  // ring tail (pairs queued) and head (pairs evaluated)
     int32_t t = ra < rb ? rfl(start[ra]) : 0;
     const int32_t t_hi = ra < rb ? rfl(start[rb]) : 0;
     int64_t cur = ra;  // cell containing home t
@@ -391,10 +393,11 @@ __global__ __launch_bounds__(64 * kNW) void k_near(EvalArgs a, const NearItem *_
                 }
                 const int nslot = (C - cb + 63) / 64 < S ? (C - cb + 63) / 64 : S;
                 // homes of this cell in groups of 64: lane l holds home g0 + l in
-                // registers and home i is broadcast with readlane.  The test
-                // admits every pair below the upper band edge (the pair rule is
-                // applied when the pair is evaluated); accepted pairs are
-                // appended to the queue, home after home.
+                // registers, homes are broadcast with readlane.  The test admits
+                // every pair below the upper band edge (the pair rule, and the
+                // exclusion of the home itself, are applied when the pair is
+                // evaluated).  kU homes x S slots are tested independently, then
+                // their accepted pairs are appended to the ring, home after home.
                 for (int g0 = i0; g0 < i1; g0 += 64) {
                     const int gn = i1 - g0 < 64 ? i1 - g0 : 64;
                     const int gi = g0 + lane;
@@ -402,50 +405,52 @@ __global__ __launch_bounds__(64 * kNW) void k_near(EvalArgs a, const NearItem *_
                     const float hfx = (float)(int32_t)(hme.x - ox) * g.hf[0];
                     const float hfy = (float)(int32_t)(hme.y - oy) * g.hf[1];
                     const float hfz = (float)(int32_t)(hme.z - oz) * g.hf[2];
-                    const uint32_t hbase = (uint32_t)(t + g0);  // sorted index of home g0
-                    for (int ii = 0; ii < gn; ++ii) {
-                        float hx_, hy_, hz_;
-                        uint32_t hux = 0, huy = 0, huz = 0;
-                        if (rel) {
-                            hx_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfx), ii));
-                            hy_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfy), ii));
-                            hz_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfz), ii));
-                        } else {
-                            hux = (uint32_t)__builtin_amdgcn_readlane((int)hme.x, ii);
-                            huy = (uint32_t)__builtin_amdgcn_readlane((int)hme.y, ii);
-                            huz = (uint32_t)__builtin_amdgcn_readlane((int)hme.z, ii);
-                        }
-                        const uint32_t self = hbase + (uint32_t)ii;
+                    for (int ii = 0; ii < gn; ii += kU) {
+                        bool acc[kU][S];
 #pragma unroll
-                        for (int s2 = 0; s2 < S; ++s2) {
-                            if (s2 < nslot) {
-                                float r2;
-                                if (rel) {
+                        for (int uu = 0; uu < kU; ++uu) {
+                            const int h = ii + uu < gn ? ii + uu : ii;
+                            const bool hv = ii + uu < gn;
+                            if (rel) {
+                                const float hx_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfx), h));
+                                const float hy_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfy), h));
+                                const float hz_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfz), h));
+#pragma unroll
+                                for (int s2 = 0; s2 < S; ++s2) {
                                     const float dx = cfx[s2] - hx_, dy = cfy[s2] - hy_, dz = cfz[s2] - hz_;
-                                    r2 = dx * dx + dy * dy + dz * dz;
-                                } else {
-                                    r2 = cj[s2] == kNoCand ? 1e36f
-                                                           : fixed_r2(g, cux[s2] - hux, cuy[s2] - huy, cuz[s2] - huz);
+                                    const float r2 = dx * dx + dy * dy + dz * dz;
+                                    acc[uu][s2] = hv && r2 < g.band_hi_f;
                                 }
-                                const bool acc = r2 < g.band_hi_f && cj[s2] != self;
-                                const uint64_t m = __ballot(acc);
-                                if (acc) {
-                                    const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi(
-                                                             (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
-                                    L.q[pos] = make_uint2((uint32_t)(g0 + ii), cj[s2]);
-                                }
-                                qn += (int)__popcll(m);
-                                if (qn >= 64) {
-                                    wave_sync();
-                                    eval_batch<F64>(g, co, L, su, sx, sq, sqf, n, lane, 64, e);
-                                    const bool mv = lane + 64 < qn;
-                                    const uint2 rest = L.q[mv ? lane + 64 : lane];
-                                    wave_sync();
-                                    if (mv) L.q[lane] = rest;
-                                    qn -= 64;
-                                    wave_sync();
+                            } else {
+                                const uint32_t hux = (uint32_t)__builtin_amdgcn_readlane((int)hme.x, h);
+                                const uint32_t huy = (uint32_t)__builtin_amdgcn_readlane((int)hme.y, h);
+                                const uint32_t huz = (uint32_t)__builtin_amdgcn_readlane((int)hme.z, h);
+#pragma unroll
+                                for (int s2 = 0; s2 < S; ++s2) {
+                                    const float r2 = fixed_r2(g, cux[s2] - hux, cuy[s2] - huy, cuz[s2] - huz);
+                                    acc[uu][s2] = hv && cj[s2] != kNoCand && r2 < g.band_hi_f;
                                 }
                             }
+                        }
+#pragma unroll
+                        for (int uu = 0; uu < kU; ++uu) {
+#pragma unroll
+                            for (int s2 = 0; s2 < S; ++s2) {
+                                const uint64_t mm = __ballot(acc[uu][s2]);
+                                if (acc[uu][s2]) {
+                                    const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi(
+                                                             (uint32_t)(mm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0));
+                                    L.q[pos & (kQueue - 1)] = make_uint2((uint32_t)(g0 + ii + uu), cj[s2]);
+                                }
+                                qn += (int)__popcll(mm);
+                            }
+                        }
+                        // at most 63 + kU * S * 64 entries are pending: the ring holds them
+                        static_assert(63 + kU * S * 64 < kQueue, "ring too small");
+                        while (qn - qh >= 64) {
+                            wave_sync();
+                            eval_batch<F64>(g, co, L, su, sx, sq, sqf, n, lane, qh, 64, e);
+                            qh += 64;
                         }
                     }
                 }
@@ -453,8 +458,9 @@ __global__ __launch_bounds__(64 * kNW) void k_near(EvalArgs a, const NearItem *_
         }
         // the queue refers to this batch's home slots: drain it, then write
         wave_sync();
-        if (qn > 0) eval_batch<F64>(g, co, L, su, sx, sq, sqf, n, lane, qn, e);
+        if (qn > qh) eval_batch<F64>(g, co, L, su, sx, sq, sqf, n, lane, qh, qn - qh, e);
         qn = 0;
+        qh = 0;
         wave_sync();
         for (int k = lane; k < H; k += 64) {
             const int64_t tt = t + k;

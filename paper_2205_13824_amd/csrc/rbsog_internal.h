@@ -122,7 +122,7 @@ struct EvalArgs {
     StateBufs cur, nxt;
     uint32_t *u_tmp;       // fixed-point coordinates in `cur` order
     uint32_t *u;           // fixed-point coordinates in cell order
-    int32_t *cell_of, *cell_count, *cell_start, *cell_fill, *src, *blocksums;
+    int32_t *cell_of, *cell_count, *cell_start, *cell_fill, *src, *sorted, *blocksums;
     double *Fn, *Ff;       // forces in cell order
     int64_t *kcur;         // per-system sequence cursor
     KRec64 *kb64;

@@ -82,7 +82,7 @@ def test_c1_one_evaluation(orc, prec, tol):
 
 
 @pytest.mark.parametrize("prec", [R.RBSOG_FP64, R.RBSOG_FP32C])
-@pytest.mark.parametrize("case", ["c1", "skew", "tiny"])
+@pytest.mark.parametrize("case", ["c1", "skew", "tiny", "manycells"])
 def test_cell_and_neighbour_lists_bit_exact(orc, prec, case):
     if case == "c1":
         c = W.c1_small()
@@ -94,6 +94,13 @@ def test_cell_and_neighbour_lists_bit_exact(orc, prec, case):
         q = np.where(np.arange(777) < 388, 1.0, -1.0)
         q[-1] = 0.0
         rc = 3.1
+    elif case == "manycells":
+        # 66^3 = 287,496 cells: the cell-count scan takes its multi-block path
+        rng = np.random.default_rng(5)
+        box = np.array([66.5, 66.5, 66.5])
+        pos = rng.random((20000, 3)) * box
+        q = np.where(np.arange(20000) % 2 == 0, 1.0, -1.0)
+        rc = 1.0
     else:
         rng = np.random.default_rng(4)
         box = np.array([6.0, 6.0, 6.0])  # floor(L/rc) = 2 -> single cell per dimension
