@@ -48,6 +48,25 @@ __device__ void stage_records(const EvalArgs &a, int64_t r) {
     a.wk[r] = w;
 }
 
+// Lanes holding the same cell in a run of consecutive lanes (the state is in
+// cell order, so runs are the rule) share one atomic: the run's first lane
+// adds the run length and the others take their offset in the run.  Returns
+// the old counter value plus the lane's offset (all lanes must be active).
+__device__ __forceinline__ int32_t run_atomic_add(int32_t *ctr, int64_t cell, bool valid) {
+    const int lane = threadIdx.x & 63;
+    const int64_t key = valid ? cell : -1;
+    const int64_t prev = __shfl_up(key, 1, 64);
+    const bool head = lane == 0 || key != prev;
+    const uint64_t H = __ballot(head);
+    const uint64_t after = lane == 63 ? 0ull : (H >> (lane + 1)) << (lane + 1);
+    const int nxt = after ? __builtin_ctzll(after) : 64;
+    const int first = 63 - __clzll((long long)(H & ((2ull << lane) - 1ull)));
+    int32_t base = 0;
+    if (head && valid) base = atomicAdd(&ctr[cell], nxt - lane);
+    base = __shfl(base, first, 64);
+    return base + (lane - first);
+}
+
 // Optional kick dt/2 and drift (velocity Verlet), then wrap x into [0, L)
 // (x_w = frac(x/L) L), fixed-point coordinate u = min(2^32-1,
 // floor(frac(x/L) 2^32)), cell c_d = (u n_d) >> 32 and the cell histogram.
@@ -57,36 +76,53 @@ __global__ __launch_bounds__(kBlock) void k_kdq(EvalArgs a, int32_t pblocks) {
         stage_records(a, (int64_t)(blockIdx.x - pblocks) * kBlock + threadIdx.x);
         return;
     }
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= a.N) return;
+    const int64_t t0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = t0 < a.N;
+    const int64_t t = valid ? t0 : a.N - 1;
     const int64_t N = a.N;
-    double *x = a.cur.x;
+    double *__restrict__ x = a.cur.x;
+    double *__restrict__ v = a.cur.v;
+    // every load first: the system's constants and the particle's state
+    const SysDev &sd = a.sys[a.sys_of[t]];
+    double L[3], xs[3];
+    int32_t nc[3];
+    for (int d = 0; d < 3; ++d) {
+        L[d] = sd.g.L[d];
+        nc[d] = sd.g.nc[d];
+        xs[d] = x[d * N + t];
+    }
+    const int64_t c0 = sd.c0;
     if (a.kick) {
+        double f[3], vs[3];
+        for (int d = 0; d < 3; ++d) {
+            f[d] = a.Fn[d * N + t] + a.Ff[d * N + t];
+            vs[d] = v[d * N + t];
+        }
         bool bad = false;
         for (int d = 0; d < 3; ++d) {
-            const double f = a.Fn[d * N + t] + a.Ff[d * N + t];
-            bad |= !isfinite(f);
-            const double vd = a.cur.v[d * N + t] + a.hdm * f;
-            a.cur.v[d * N + t] = vd;
-            x[d * N + t] += a.dt * vd;
+            bad |= !isfinite(f[d]);
+            vs[d] += a.hdm * f[d];
+            xs[d] += a.dt * vs[d];
+            if (valid) v[d * N + t] = vs[d];
         }
-        if (bad) atomicOr(a.flag, 1);
+        if (bad && valid) atomicOr(a.flag, 1);
     }
-    const SysDev &sd = a.sys[a.sys_of[t]];
     int64_t c[3];
     for (int d = 0; d < 3; ++d) {
-        double r = x[d * N + t] / sd.g.L[d];
-        double f = r - floor(r);
-        double v = floor(f * kTwo32);
-        v = v > kTwo32 - 1.0 ? kTwo32 - 1.0 : v;
-        const uint32_t ud = (uint32_t)v;
-        a.u_tmp[d * N + t] = ud;
-        x[d * N + t] = f * sd.g.L[d];
-        c[d] = (int64_t)(((uint64_t)ud * (uint64_t)sd.g.nc[d]) >> 32);
+        const double r = xs[d] / L[d];
+        const double f = r - floor(r);
+        double w = floor(f * kTwo32);
+        w = w > kTwo32 - 1.0 ? kTwo32 - 1.0 : w;
+        const uint32_t ud = (uint32_t)w;
+        if (valid) {
+            a.u_tmp[d * N + t] = ud;
+            x[d * N + t] = f * L[d];
+        }
+        c[d] = (int64_t)(((uint64_t)ud * (uint64_t)nc[d]) >> 32);
     }
-    const int64_t cell = sd.c0 + c[0] + (int64_t)sd.g.nc[0] * (c[1] + (int64_t)sd.g.nc[1] * c[2]);
-    a.cell_of[t] = (int32_t)cell;
-    atomicAdd(&a.cell_count[cell], 1);
+    const int64_t cell = c0 + c[0] + (int64_t)nc[0] * (c[1] + (int64_t)nc[1] * c[2]);
+    if (valid) a.cell_of[t] = (int32_t)cell;
+    run_atomic_add(a.cell_count, cell, valid);
 }
 
 // ---- exclusive scan of int32 counts: 1024 elements per block --------------
@@ -159,12 +195,13 @@ __global__ void k_scan_apply(const int32_t *__restrict__ in, int64_t n, const in
     }
 }
 
-__global__ void k_cell_scatter(int64_t N, const int32_t *__restrict__ cell_of, int32_t *__restrict__ fill,
-                               int32_t *__restrict__ src) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= N) return;
-    const int32_t dst = atomicAdd(&fill[cell_of[t]], 1);
-    src[dst] = (int32_t)t;
+__global__ __launch_bounds__(kBlock) void k_cell_scatter(int64_t N, const int32_t *__restrict__ cell_of,
+                                                         int32_t *__restrict__ fill, int32_t *__restrict__ src) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = t < N;
+    const int32_t cell = valid ? cell_of[t] : 0;
+    const int32_t dst = run_atomic_add(fill, cell, valid);
+    if (valid) src[dst] = (int32_t)t;
 }
 
 // Per cell: order of its slots by particle id (the order becomes (cell, id),
