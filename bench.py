@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    # launch shapes are tuned during the warm-up steps unless this is given
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--n", type=int, default=300_000, help=argparse.SUPPRESS)
     # after the bench: device-to-device copies of this many MiB, the reference
     # kernel against which rocprofv3's FETCH_SIZE / WRITE_SIZE are scaled
@@ -69,7 +71,7 @@ def run_precision(R, torch, wl, prec, args):
     P = wl["P"]
     stream = torch.cuda.Stream()
     sysm = R.System(wl["pos"], wl["q"], wl["box"], wl["rc"], P, seed=2022, precision=prec,
-                    stream=stream.cuda_stream)
+                    stream=stream.cuda_stream, autotune=not args.no_autotune)
     batches = 1 + args.warmup + args.steps + args.profile_steps
     t0 = time.time()
     sysm.sample_k(batches)
@@ -101,9 +103,11 @@ def run_precision(R, torch, wl, prec, args):
         kernels = {k: {"ms_total": v[0], "launches": v[1], "us_per_launch": 1e3 * v[0] / max(v[1], 1)}
                    for k, v in prof.items() if v[1] > 0}
     E = R.rbsog_get_energy(sysm.ctx)
+    info = R.rbsog_info(sysm.ctx)
+    shapes = {k: info[k] for k in ("near_cells_per_item", "rho_chunk", "far_block", "tuned")}
     sysm.close()
     return dict(ms=ms, wall=wall, F0=F0, Fn0=Fn0, Ff0=Ff0, E0=E0, E_end=E, kernels=kernels, near_pairs=near_pairs,
-                value=n * args.steps / (ms * 1e-3))
+                value=n * args.steps / (ms * 1e-3), shapes=shapes)
 
 
 def roofline(kernels, n, P, near_pairs, nexp32=3, ntail32=7):
@@ -200,6 +204,7 @@ def main():
         "roofline": roof,
         "kernels_fp32c": r32["kernels"],
         "kernels_fp64": r64["kernels"],
+        "launch_shapes": {"fp32c": r32["shapes"], "fp64": r64["shapes"]},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -92,6 +92,8 @@ typedef struct {
     double neutral_tol;   /* default 1e-10 */
     double mass;          /* mass of every particle; default 1 */
     int32_t graphs;       /* nonzero: rbsog_step replays one captured HIP graph per step; default 1 */
+    int32_t autotune;     /* nonzero: the first rbsog_step tunes the launch shapes (rbsog_autotune
+                             with 5 repetitions) unless a cached tuning applies; default 0 */
 } rbsog_opts;
 
 /* Fills *o with the defaults above. */
@@ -201,8 +203,25 @@ typedef struct {
     int64_t evaluations;
     int64_t n;
     int32_t n_sys;
+    int32_t near_cells_per_item;  /* launch shapes in use (see rbsog_autotune) */
+    int32_t rho_chunk;
+    int32_t far_block;
+    int32_t tuned;                /* 1 if the shapes come from tuning (now or cached) */
 } rbsog_info_t;
 rbsog_status rbsog_info(rbsog_ctx *ctx, int32_t sys, rbsog_info_t *info);
+
+/* Tunes the launch shapes of the batch on the data of the latest evaluation:
+ * cells per near work item (1..64), particles per structure-factor chunk
+ * (256..8192) and particles per far block (64, 128, 256), one phase after the
+ * other, each candidate timed over `reps` launches of its kernel with HIP
+ * events; the fastest are kept.  Only the near, structure-factor and far
+ * kernels run (the sequence is not consumed; forces are recomputed for the
+ * same positions).  The choice is cached for the process under (GPU
+ * architecture, precision, batch size, log2 n, P, log2 cells) and, if the
+ * environment variable RBSOG_TUNE_CACHE names a file, appended to it; new
+ * contexts of the same kind start from the cached shapes.
+ * E_STATE before the first evaluation. */
+rbsog_status rbsog_autotune(rbsog_ctx *ctx, int32_t reps);
 
 /* Debug exports of system sys: the latest cell list and a full neighbour
  * list built on the device with the pair rule above (rows ascending i,

@@ -7,6 +7,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <map>
+#include <mutex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -73,6 +76,13 @@ enum Kid { K_KDQ, K_SCAN, K_SCATTER, K_SORTG, K_NEAR, K_RHO, K_RHORED, K_FAR, K_
 const char *kKernelNames[K_COUNT] = {"kick_drift_quantise", "scan_cell_counts", "cell_scatter", "sort_gather",
                                      "near",                "rho",              "rho_reduce",   "far"};
 
+
+// Launch shapes of the work lists (the tunable part of the plan).
+struct Tune {
+    int32_t near_cpi = 0;   // cells per near item
+    int32_t rho_chunk = 0;  // particles per structure-factor chunk
+    int32_t far_block = 0;  // particles per far item (= block size)
+};
 
 // One system of the batch: host-side parameters, sampler and sequence.
 struct SysHost {
@@ -142,6 +152,11 @@ struct rbsog_ctx {
     RhoItem *rho_items = nullptr;
     FarItem *far_items = nullptr;
     int32_t n_near = 0, n_rho = 0, n_far = 0;
+    // work-list shapes: the current ones, whether they were tuned, and
+    // whether tuning runs at the first step
+    Tune tune;
+    bool tuned = false, autotune = false;
+    std::string tune_key;
     // graphs of one velocity-Verlet step, one per buffer parity
     bool use_graphs = true;
     hipGraph_t graph[2] = {nullptr, nullptr};
@@ -471,7 +486,7 @@ rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt) {
     TRY(timed(c, K_NEAR, [&] { launch_near(a, f64, c->near_items, c->n_near, s); }));
     TRY(timed(c, K_RHO, [&] { launch_rho(a, f64, c->rho_items, c->n_rho, s); }));
     TRY(timed(c, K_RHORED, [&] { launch_rho_reduce(a, s); }));
-    TRY(timed(c, K_FAR, [&] { launch_far(a, f64, c->far_items, c->n_far, s); }));
+    TRY(timed(c, K_FAR, [&] { launch_far(a, f64, c->far_items, c->n_far, c->tune.far_block, s); }));
     HIPCHK(c, hipGetLastError());
     return RBSOG_OK;
 }
@@ -701,12 +716,78 @@ rbsog_status setup_system(SysHost &h, int64_t n, const double *pos, const double
     return RBSOG_OK;
 }
 
-// Work lists of the batch.  Near: runs of about `cells_per_item` cells of one
-// system; rho: particle chunks of about `chunk` slots x k-tile groups; far:
-// runs of 256 slots.
-void build_work(rbsog_ctx *c, std::vector<NearItem> &near, std::vector<RhoItem> &rho, std::vector<FarItem> &far) {
-    const int64_t cpi = std::max<int64_t>(1, std::min<int64_t>(64, (c->C + 8191) / 8192));
-    const int64_t chunk = std::max<int64_t>(256, (c->N + 511) / 512);
+// ---- shape cache: tuned shapes by (architecture, precision, batch size,
+// log2 N, P per system, log2 cells), kept for the process and optionally in
+// the text file named by RBSOG_TUNE_CACHE (one "key cpi chunk block" line per
+// entry, later lines win).
+std::mutex g_tune_mu;
+std::map<std::string, Tune> g_tune_cache;
+bool g_tune_loaded = false;
+
+int ilog2(int64_t v) {
+    int l = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++l;
+    }
+    return l;
+}
+
+std::string tune_key(const std::string &arch, const rbsog_ctx *c) {
+    int64_t psum = 0;
+    for (const SysHost &h : c->sys) psum += h.P;
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s|prec%d|sys%d|n%d|P%lld|c%d", arch.c_str(), c->prec, ilog2(c->nsys), ilog2(c->N),
+             (long long)(psum / c->nsys), ilog2(c->C));
+    return buf;
+}
+
+void tune_cache_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("RBSOG_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char key[256];
+    int a, b, d;
+    while (std::fscanf(f, "%255s %d %d %d", key, &a, &b, &d) == 4) {
+        Tune t;
+        t.near_cpi = a;
+        t.rho_chunk = b;
+        t.far_block = d;
+        g_tune_cache[key] = t;
+    }
+    std::fclose(f);
+}
+
+bool tune_cache_lookup(const std::string &key, Tune &t) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache_load_locked();
+    auto it = g_tune_cache.find(key);
+    if (it == g_tune_cache.end()) return false;
+    t = it->second;
+    return true;
+}
+
+void tune_cache_store(const std::string &key, const Tune &t) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache_load_locked();
+    g_tune_cache[key] = t;
+    const char *path = std::getenv("RBSOG_TUNE_CACHE");
+    if (!path || !*path) return;
+    if (FILE *f = std::fopen(path, "a")) {
+        std::fprintf(f, "%s %d %d %d\n", key.c_str(), t.near_cpi, t.rho_chunk, t.far_block);
+        std::fclose(f);
+    }
+}
+
+// Work lists of the batch.  Near: runs of t.near_cpi cells of one system;
+// rho: particle chunks of about t.rho_chunk slots x k-tile groups; far: runs
+// of t.far_block slots.
+void build_work(rbsog_ctx *c, const Tune &t, std::vector<NearItem> &near, std::vector<RhoItem> &rho,
+                std::vector<FarItem> &far) {
+    const int64_t cpi = t.near_cpi, chunk = t.rho_chunk, fb = t.far_block;
     int64_t pofs = 0;
     for (int32_t s = 0; s < c->nsys; ++s) {
         SysHost &h = c->sys[s];
@@ -727,9 +808,127 @@ void build_work(rbsog_ctx *c, std::vector<NearItem> &near, std::vector<RhoItem> 
             }
         h.pofs = pofs;
         pofs += (int64_t)h.nch * h.P;
-        for (int64_t t = 0; t < h.n; t += 256)
-            far.push_back(FarItem{s, 0, h.p0 + t, h.p0 + std::min(h.n, t + 256)});
+        for (int64_t i = 0; i < h.n; i += fb)
+            far.push_back(FarItem{s, 0, h.p0 + i, h.p0 + std::min(h.n, i + fb)});
     }
+}
+
+// Default shapes: about 8192 near items (one per wave), 512 structure-factor
+// chunks and 256-particle far blocks over the batch.
+Tune default_tune(const rbsog_ctx *c) {
+    Tune t;
+    t.near_cpi = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, (c->C + 8191) / 8192));
+    t.rho_chunk = (int32_t)std::max<int64_t>(256, (c->N + 511) / 512);
+    t.far_block = 256;
+    return t;
+}
+
+// Capacities of the work lists and partial buffers: the largest any shape
+// below may need (1 cell per near item, 256-particle chunks, 64-particle
+// far items).
+void work_caps(const rbsog_ctx *c, int64_t &near_cap, int64_t &rho_cap, int64_t &far_cap, int64_t &part_cap) {
+    near_cap = c->C;
+    rho_cap = far_cap = part_cap = 0;
+    for (const SysHost &h : c->sys) {
+        const int64_t ktiles = (h.P + 63) / 64, kt = std::min<int64_t>(ktiles, 16);
+        const int64_t nch = std::max<int64_t>(1, (h.n + 255) / 256);
+        rho_cap += ((ktiles + kt - 1) / kt) * nch;
+        part_cap += nch * h.P;
+        far_cap += (h.n + 63) / 64;
+    }
+}
+
+bool valid_tune(const Tune &t) {
+    return t.near_cpi >= 1 && t.near_cpi <= 1024 && t.rho_chunk >= 256 && (t.far_block == 64 || t.far_block == 128 ||
+                                                                         t.far_block == 256);
+}
+
+// Installs a set of shapes: builds and uploads the work lists and the
+// per-system table; captured graphs are dropped (their launch sizes change).
+rbsog_status apply_tune(rbsog_ctx *c, const Tune &t) {
+    std::vector<NearItem> near;
+    std::vector<RhoItem> rho;
+    std::vector<FarItem> far;
+    build_work(c, t, near, rho, far);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->near_items, near.data(), near.size() * sizeof(NearItem), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->rho_items, rho.data(), rho.size() * sizeof(RhoItem), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->far_items, far.data(), far.size() * sizeof(FarItem), hipMemcpyHostToDevice));
+    c->n_near = (int32_t)near.size();
+    c->n_rho = (int32_t)rho.size();
+    c->n_far = (int32_t)far.size();
+    for (int32_t s = 0; s < c->nsys; ++s) TRY(upload_sysdev(c, s));
+    c->tune = t;
+    drop_graphs(c);
+    return RBSOG_OK;
+}
+
+// Times each phase's candidate shapes on the latest evaluation's data (the
+// near, structure-factor and far kernels only: no cursor moves, no state
+// changes beyond recomputing the same forces) and keeps the fastest.
+rbsog_status autotune_now(rbsog_ctx *c, int32_t reps) {
+    if (c->evals == 0) return fail(c, RBSOG_E_STATE, "autotuning needs one force evaluation first");
+    if (reps < 1) reps = 1;
+    const bool f64 = c->prec == RBSOG_FP64;
+    // the kernels after the re-sort read the `nxt` buffers: those of the latest order
+    c->parity = 1 - c->parity;
+    const EvalArgs a = make_args(c, false, 0.0);
+    c->parity = 1 - c->parity;
+    hipEvent_t e0 = get_event(c), e1 = get_event(c);
+    if (!e0 || !e1) return fail(c, RBSOG_E_DEVICE, "hipEventCreate failed");
+    auto time_of = [&](int phase, double &ms) -> rbsog_status {
+        auto launch = [&] {
+            if (phase == 0) launch_near(a, f64, c->near_items, c->n_near, c->stream);
+            else if (phase == 1) launch_rho(a, f64, c->rho_items, c->n_rho, c->stream);
+            else launch_far(a, f64, c->far_items, c->n_far, c->tune.far_block, c->stream);
+        };
+        launch();
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        for (int r = 0; r < reps; ++r) launch();
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        HIPCHK(c, hipGetLastError());
+        float f = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&f, e0, e1));
+        ms = f / reps;
+        return RBSOG_OK;
+    };
+    Tune best = c->tune;
+    const Tune dflt = default_tune(c);
+    int64_t nmax = 0;
+    for (const SysHost &h : c->sys) nmax = std::max(nmax, h.n);
+    std::vector<int32_t> cpis = {1, 2, 4, 8, 16, 32, 64, dflt.near_cpi};
+    std::vector<int32_t> chunks = {256, 512, 1024, 2048, 4096, 8192, dflt.rho_chunk};
+    std::vector<int32_t> blocks = {64, 128, 256};
+    for (int phase = 0; phase < 3; ++phase) {
+        const std::vector<int32_t> &cand = phase == 0 ? cpis : phase == 1 ? chunks : blocks;
+        double best_ms = 1e30;
+        int32_t best_v = phase == 0 ? best.near_cpi : phase == 1 ? best.rho_chunk : best.far_block;
+        for (int32_t v : cand) {
+            if (phase == 1 && v > std::max<int64_t>(256, nmax)) continue;
+            Tune t = best;
+            (phase == 0 ? t.near_cpi : phase == 1 ? t.rho_chunk : t.far_block) = v;
+            TRY(apply_tune(c, t));
+            double ms = 0.0;
+            TRY(time_of(phase, ms));
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_v = v;
+            }
+        }
+        (phase == 0 ? best.near_cpi : phase == 1 ? best.rho_chunk : best.far_block) = best_v;
+    }
+    c->ev_pool.push_back(e0);
+    c->ev_pool.push_back(e1);
+    TRY(apply_tune(c, best));
+    // the last trial's far pass left the forces of another shape: recompute
+    // them with the chosen shapes (same data, same arithmetic per particle)
+    launch_near(a, f64, c->near_items, c->n_near, c->stream);
+    launch_far(a, f64, c->far_items, c->n_far, c->tune.far_block, c->stream);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->tuned = true;
+    tune_cache_store(c->tune_key, best);
+    return RBSOG_OK;
 }
 
 rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, const double *pos, const double *q,
@@ -781,15 +980,9 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     }
     c->N = offsets[nsys];
     c->q_host.assign(q, q + c->N);
-    std::vector<NearItem> near;
-    std::vector<RhoItem> rho;
-    std::vector<FarItem> far;
-    build_work(c, near, rho, far);
-    c->n_near = (int32_t)near.size();
-    c->n_rho = (int32_t)rho.size();
-    c->n_far = (int32_t)far.size();
-    int64_t npart = 0;
-    for (auto &h : c->sys) npart += (int64_t)h.nch * h.P;
+    c->autotune = o.autotune != 0;
+    int64_t near_cap, rho_cap, far_cap, part_cap;
+    work_caps(c, near_cap, rho_cap, far_cap, part_cap);
 
     auto bail = [&](rbsog_status st) {
         g_init_error = c->err;
@@ -840,14 +1033,14 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     ALLOC(wk, K);
     ALLOC(rho, 2 * K);
     ALLOC(ek, K);
-    ALLOC(partial, 2 * npart);
-    ALLOC(epart, c->n_near);
+    ALLOC(partial, 2 * part_cap);
+    ALLOC(epart, near_cap);
     ALLOC(E, 4 * (int64_t)nsys);
     ALLOC(flag, 1);
     ALLOC(sys_done, nsys);
-    ALLOC(near_items, c->n_near);
-    ALLOC(rho_items, c->n_rho);
-    ALLOC(far_items, c->n_far);
+    ALLOC(near_items, near_cap);
+    ALLOC(rho_items, rho_cap);
+    ALLOC(far_items, far_cap);
 #undef ALLOC
     {
         // initial state in the caller's order (slot t holds particle t)
@@ -884,12 +1077,7 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
                   hipMemcpy(c->kcur, zc.data(), nsys * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->sys_done, zu.data(), nsys * sizeof(uint32_t), hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->flag, &zf, sizeof zf, hipMemcpyHostToDevice) == hipSuccess &&
-                  hipMemset(c->cell_count, 0, (size_t)C * sizeof(int32_t)) == hipSuccess &&
-                  hipMemcpy(c->near_items, near.data(), near.size() * sizeof(NearItem), hipMemcpyHostToDevice) ==
-                      hipSuccess &&
-                  hipMemcpy(c->rho_items, rho.data(), rho.size() * sizeof(RhoItem), hipMemcpyHostToDevice) ==
-                      hipSuccess &&
-                  hipMemcpy(c->far_items, far.data(), far.size() * sizeof(FarItem), hipMemcpyHostToDevice) == hipSuccess;
+                  hipMemset(c->cell_count, 0, (size_t)C * sizeof(int32_t)) == hipSuccess;
         if (!ok) {
             fail(c, RBSOG_E_DEVICE, "initial upload failed");
             return bail(RBSOG_E_DEVICE);
@@ -897,6 +1085,17 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     }
     for (int32_t s = 0; s < nsys; ++s)
         if ((st = ensure_kcap(c, s, 4 * (int64_t)c->sys[s].P)) != RBSOG_OK) return bail(st);
+    {
+        // shapes: a tuned entry of the cache for this kind of batch, else defaults
+        hipDeviceProp_t prop;
+        std::string arch = hipGetDeviceProperties(&prop, o.device) == hipSuccess ? std::string(prop.gcnArchName) : "?";
+        arch = arch.substr(0, arch.find(':'));
+        c->tune_key = tune_key(arch, c);
+        Tune t = default_tune(c);
+        if (tune_cache_lookup(c->tune_key, t) && valid_tune(t)) c->tuned = true;
+        else t = default_tune(c);
+        if ((st = apply_tune(c, t)) != RBSOG_OK) return bail(st);
+    }
     *out = c;
     return RBSOG_OK;
 }
@@ -914,6 +1113,7 @@ void rbsog_default_opts(rbsog_opts *o) {
     o->neutral_tol = 1e-10;
     o->mass = 1.0;
     o->graphs = 1;
+    o->autotune = 0;
 }
 
 rbsog_status rbsog_sog_table1(int32_t row, double rc, rbsog_sog *out) {
@@ -1034,6 +1234,7 @@ rbsog_status rbsog_step(rbsog_ctx *c, int64_t n_steps, double dt) {
         TRY(enqueue_eval(c, false, 0.0));
         account_eval(c);
     }
+    if (c->autotune && !c->tuned && !c->prof_on) TRY(autotune_now(c, 5));
     const bool graphs = c->use_graphs && !c->prof_on && n_steps > 1;
     if (graphs) TRY(ensure_step_graphs(c, dt));
     for (int64_t k = 0; k < n_steps; ++k) {
@@ -1144,7 +1345,17 @@ rbsog_status rbsog_info(rbsog_ctx *c, int32_t sys, rbsog_info_t *info) {
     info->evaluations = c->evals;
     info->n = h.n;
     info->n_sys = c->nsys;
+    info->near_cells_per_item = c->tune.near_cpi;
+    info->rho_chunk = c->tune.rho_chunk;
+    info->far_block = c->tune.far_block;
+    info->tuned = c->tuned ? 1 : 0;
     return RBSOG_OK;
+}
+
+rbsog_status rbsog_autotune(rbsog_ctx *c, int32_t reps) {
+    TRY(check_ctx(c));
+    if (c->prof_on) return fail(c, RBSOG_E_STATE, "autotuning is not available while profiling");
+    return autotune_now(c, reps);
 }
 
 rbsog_status rbsog_debug_cells(rbsog_ctx *c, int32_t sys, int32_t *cell_start, int32_t *order) {

@@ -431,8 +431,9 @@ void launch_rho_reduce(const EvalArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_rho_reduce, dim3((unsigned)((a.K + 3) / 4)), dim3(256), 0, s, a);
 }
 
-void launch_far(const EvalArgs &a, bool f64, const FarItem *items, int32_t nitems, hipStream_t s) {
-    dim3 grid((unsigned)nitems), block(256);
+void launch_far(const EvalArgs &a, bool f64, const FarItem *items, int32_t nitems, int32_t block_size,
+                hipStream_t s) {
+    dim3 grid((unsigned)nitems), block((unsigned)block_size);
     if (f64) hipLaunchKernelGGL(k_far<true>, grid, block, 0, s, a, items, nitems);
     else hipLaunchKernelGGL(k_far<false>, grid, block, 0, s, a, items, nitems);
 }

@@ -391,7 +391,6 @@ __global__ __launch_bounds__(64 * kNW) void k_near(EvalArgs a, const NearItem *_
                     cfy[s2] = ok ? (float)(int32_t)(cuy[s2] - oy) * g.hf[1] : 1e18f;
                     cfz[s2] = ok ? (float)(int32_t)(cuz[s2] - oz) * g.hf[2] : 1e18f;
                 }
-                const int nslot = (C - cb + 63) / 64 < S ? (C - cb + 63) / 64 : S;
                 // homes of this cell in groups of 64: lane l holds home g0 + l in
                 // registers, homes are broadcast with readlane.  The test admits
                 // every pair below the upper band edge (the pair rule, and the

@@ -162,6 +162,8 @@ void launch_rho(const EvalArgs &a, bool f64, const RhoItem *items, int32_t nitem
 // system's energies and advances its sequence cursor
 void launch_rho_reduce(const EvalArgs &a, hipStream_t s);
 // far force; with a.kick the closing half kick v += dt/(2m) (F_N + F*) follows
-void launch_far(const EvalArgs &a, bool f64, const FarItem *items, int32_t nitems, hipStream_t s);
+// (items of at most block_size particles, block_size in {64, 128, 256})
+void launch_far(const EvalArgs &a, bool f64, const FarItem *items, int32_t nitems, int32_t block_size,
+                hipStream_t s);
 
 }  // namespace rbsog

@@ -27,7 +27,7 @@ EXPORTS = ("rbsog_default_opts", "rbsog_sog_table1", "rbsog_init", "rbsog_init_b
            "rbsog_step", "rbsog_set_velocities", "rbsog_set_positions", "rbsog_get_state", "rbsog_get_forces",
            "rbsog_get_energy", "rbsog_get_rho", "rbsog_info", "rbsog_debug_cells", "rbsog_debug_neighbors",
            "rbsog_profile", "rbsog_profile_read", "rbsog_sync", "rbsog_last_error", "rbsog_status_string",
-           "rbsog_destroy")
+           "rbsog_destroy", "rbsog_autotune")
 
 
 class RbsogError(RuntimeError):
@@ -42,13 +42,15 @@ class rbsog_sog(ctypes.Structure):
 
 class rbsog_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
-                ("neutral_tol", ctypes.c_double), ("mass", ctypes.c_double), ("graphs", ctypes.c_int32)]
+                ("neutral_tol", ctypes.c_double), ("mass", ctypes.c_double), ("graphs", ctypes.c_int32),
+                ("autotune", ctypes.c_int32)]
 
 
 class rbsog_info_t(ctypes.Structure):
     _fields_ = [("S", ctypes.c_double), ("volume", ctypes.c_double), ("ncell", ctypes.c_int32 * 3),
                 ("k_remaining", ctypes.c_int64), ("evaluations", ctypes.c_int64), ("n", ctypes.c_int64),
-                ("n_sys", ctypes.c_int32)]
+                ("n_sys", ctypes.c_int32), ("near_cells_per_item", ctypes.c_int32), ("rho_chunk", ctypes.c_int32),
+                ("far_block", ctypes.c_int32), ("tuned", ctypes.c_int32)]
 
 
 _lib = None
@@ -87,6 +89,7 @@ def lib():
             "rbsog_last_error": (ctypes.c_char_p, [vp]),
             "rbsog_status_string": (ctypes.c_char_p, [i32]),
             "rbsog_destroy": (None, [vp]),
+            "rbsog_autotune": (i32, [vp, i32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -122,21 +125,22 @@ def rbsog_default_opts() -> rbsog_opts:
     return o
 
 
-def _opts(precision, device, stream, neutral_tol, mass, graphs):
+def _opts(precision, device, stream, neutral_tol, mass, graphs, autotune=False):
     o = rbsog_default_opts()
     o.precision, o.device, o.neutral_tol, o.mass, o.graphs = precision, device, neutral_tol, mass, int(graphs)
+    o.autotune = int(autotune)
     o.stream = stream
     return o
 
 
 def rbsog_init(pos, q, box, sog: rbsog_sog, rc: float, P: int, seed: int, precision: int = RBSOG_FP64,
                device: int = 0, stream: int | None = None, neutral_tol: float = 1e-10, mass: float = 1.0,
-               graphs: bool = True):
+               graphs: bool = True, autotune: bool = False):
     q = _f64(q, (-1,))
     n = q.size
     pos = _f64(pos, (n, 3))
     box = _f64(box, (3,))
-    o = _opts(precision, device, stream, neutral_tol, mass, graphs)
+    o = _opts(precision, device, stream, neutral_tol, mass, graphs, autotune)
     ctx = ctypes.c_void_p()
     _check(lib().rbsog_init(ctypes.byref(ctx), n, _ptr(pos), _ptr(q), _ptr(box), ctypes.byref(sog), float(rc),
                             int(P), int(seed), ctypes.byref(o)))
@@ -144,7 +148,8 @@ def rbsog_init(pos, q, box, sog: rbsog_sog, rc: float, P: int, seed: int, precis
 
 
 def rbsog_init_batch(pos_list, q_list, boxes, sogs, rcs, Ps, seeds, precision: int = RBSOG_FP64, device: int = 0,
-                     stream: int | None = None, neutral_tol: float = 1e-10, mass: float = 1.0, graphs: bool = True):
+                     stream: int | None = None, neutral_tol: float = 1e-10, mass: float = 1.0, graphs: bool = True,
+                     autotune: bool = False):
     """One context over len(q_list) systems; particle arrays are concatenated."""
     ns = len(q_list)
     sizes = [int(np.asarray(qq).size) for qq in q_list]
@@ -157,7 +162,7 @@ def rbsog_init_batch(pos_list, q_list, boxes, sogs, rcs, Ps, seeds, precision: i
     rc = _f64(rcs, (ns,))
     Pa = np.ascontiguousarray(np.asarray(Ps, dtype=np.int32).reshape(ns))
     sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64).reshape(ns))
-    o = _opts(precision, device, stream, neutral_tol, mass, graphs)
+    o = _opts(precision, device, stream, neutral_tol, mass, graphs, autotune)
     ctx = ctypes.c_void_p()
     _check(lib().rbsog_init_batch(ctypes.byref(ctx), ns, _ptr(offsets), _ptr(pos), _ptr(q), _ptr(box),
                                   ctypes.cast(sog_arr, ctypes.c_void_p), _ptr(rc), _ptr(Pa), _ptr(sd),
@@ -233,7 +238,14 @@ def rbsog_info(ctx, sys: int = 0) -> dict:
     info = rbsog_info_t()
     _check(lib().rbsog_info(ctx, int(sys), ctypes.byref(info)), ctx)
     return dict(S=info.S, volume=info.volume, ncell=tuple(info.ncell), k_remaining=info.k_remaining,
-                evaluations=info.evaluations, n=info.n, n_sys=info.n_sys)
+                evaluations=info.evaluations, n=info.n, n_sys=info.n_sys,
+                near_cells_per_item=info.near_cells_per_item, rho_chunk=info.rho_chunk, far_block=info.far_block,
+                tuned=bool(info.tuned))
+
+
+def rbsog_autotune(ctx, reps: int = 5) -> dict:
+    _check(lib().rbsog_autotune(ctx, int(reps)), ctx)
+    return rbsog_info(ctx, 0)
 
 
 def rbsog_debug_cells(ctx, n: int | None = None, sys: int = 0):

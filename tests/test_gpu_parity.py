@@ -275,3 +275,36 @@ def test_graph_replay_equals_eager(orc, prec):
     for a, b in zip(*out):
         for x, y in zip(a, b):
             assert (x == y).all()
+
+
+@pytest.mark.parametrize("prec,tol", [(R.RBSOG_FP64, F64_TOL), (R.RBSOG_FP32C, F32C_TOL)])
+def test_autotune_keeps_results(orc, prec, tol):
+    c = W.c1_small()
+    sysm = make(c["pos"], c["q"], c["box"], c["rc"], c["P"], seed=101, prec=prec)
+    m = sysm.sample_k(3)
+    F0, E0 = sysm.forces()
+    Fn0, Ff0 = sysm.components()
+    info = R.rbsog_autotune(sysm.ctx, 2)
+    say(f"[autotune prec={prec}] shapes cpi={info['near_cells_per_item']} chunk={info['rho_chunk']} "
+        f"far_block={info['far_block']} tuned={info['tuned']}")
+    assert info["tuned"] and info["k_remaining"] == 2 * c["P"]
+    # the tuning recomputed the forces of the same positions with the chosen shapes
+    Fn1, Ff1 = sysm.components()
+    assert relrms(Fn1, Fn0) < 1e-13 and relrms(Ff1, Ff0) < 1e-13
+    # and later evaluations still match the oracle
+    check_eval(orc, sysm, c["pos"], c["q"], c["box"], c["rc"], m[c["P"]:2 * c["P"]], tol, f"tuned prec={prec}")
+
+
+def test_autotune_option_in_step():
+    c = W.c1_small()
+    runs = []
+    for tune in (False, True):
+        s = R.System(c["pos"], c["q"], c["box"], c["rc"], c["P"], seed=5, precision=R.RBSOG_FP64, autotune=tune)
+        s.sample_k(6)
+        R.rbsog_set_velocities(s.ctx, None, T=1.0, seed=2)
+        s.step(4, 1e-3)
+        runs.append(R.rbsog_get_state(s.ctx, 1000) + (R.rbsog_get_energy(s.ctx),))
+        assert R.rbsog_info(s.ctx)["tuned"] == tune or tune is False
+        s.close()
+    for a, b in zip(*runs):
+        assert np.allclose(a, b, rtol=1e-11, atol=1e-12)
