@@ -87,6 +87,28 @@ def ions_rsa(n: int, density: float, dmin: float, seed: int):
     return pos, np.ascontiguousarray(q), np.array([L, L, L], dtype=np.float64)
 
 
+def ions_lattice(n_side: int, density: float, seed: int, jitter: float = 0.25):
+    """Neutral +-1 electrolyte of n_side^3 ions (even) at the given number density:
+    a simple-cubic lattice of spacing a jittered by U(-jitter a, +jitter a) per
+    axis, so that no two ions are closer than (1 - 2 jitter) a; charges shuffled.
+    Used where random sequential addition of tens of millions of ions would
+    dominate the set-up time."""
+    n = n_side ** 3
+    if n % 2:
+        raise ValueError("n_side^3 must be even for a neutral +-1 system")
+    L = (n / density) ** (1.0 / 3.0)
+    a = L / n_side
+    rng = np.random.default_rng(seed)
+    g = (np.arange(n_side, dtype=np.float64) + 0.5) * a
+    gx, gy, gz = np.meshgrid(g, g, g, indexing="ij")
+    pos = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], axis=1)
+    pos += rng.uniform(-jitter * a, jitter * a, size=pos.shape)
+    pos -= L * np.floor(pos / L)
+    q = np.where(np.arange(n) < n // 2, 1.0, -1.0)
+    rng.shuffle(q)
+    return np.ascontiguousarray(pos), np.ascontiguousarray(q), np.array([L, L, L], dtype=np.float64)
+
+
 def _random_rotations(rng: np.random.Generator, n: int) -> np.ndarray:
     """Uniform random rotation matrices from normalised Gaussian quaternions."""
     qv = rng.standard_normal((n, 4))
@@ -190,3 +212,10 @@ def c4_ensemble(n_sys: int = 256, nmin: int = 500, nmax: int = 50_000, seed: int
         pos, q, box = ions_rsa(int(n), 0.1, 1.0, seed=1000 + r)
         systems.append(dict(pos=pos, q=q, box=box))
     return dict(systems=systems, rc=3.5, P=100, seeds=[1000 + r for r in range(n_sys)])
+
+
+def c5_large(n_side: int = 272):
+    """About 2e7 ions (272^3 = 20,123,648) at density 0.1 on a jittered lattice
+    (minimum separation 0.5 a = 1.08), r_c = 3.5, P = 1000."""
+    pos, q, box = ions_lattice(n_side, 0.1, seed=5)
+    return dict(pos=pos, q=q, box=box, rc=3.5, P=1000)
