@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     # launch shapes are tuned during the warm-up steps unless this is given
     ap.add_argument("--no-autotune", action="store_true")
+    # the ensemble, 2e7-ion and water workloads (reported next to the main line)
+    ap.add_argument("--no-other", action="store_true")
+    ap.add_argument("--other-steps", type=int, default=100)
     ap.add_argument("--n", type=int, default=300_000, help=argparse.SUPPRESS)
     # after the bench: device-to-device copies of this many MiB, the reference
     # kernel against which rocprofv3's FETCH_SIZE / WRITE_SIZE are scaled
@@ -127,6 +130,77 @@ def roofline(kernels, n, P, near_pairs, nexp32=3, ntail32=7):
         # rsqrt, nexp exponentials, two tail polynomials, ~15 FMA-class)
         ev = 2 * (TRANS_SLOTS * (1 + nexp32) + 3 * nexp32 + 2 * ntail32 + 15)
         out["as_evaluated"] = {"slots_per_unit": ev, "frac": units[dom] * ev / t / PEAK_VALU_SLOTS}
+    return out
+
+
+def timed_steps(R, torch, obj, stream, steps, dt):
+    """HIP-event time of `steps` velocity-Verlet steps on the library's stream (ms)."""
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    obj.step(steps, dt)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def other_workloads(R, W, torch, args):
+    """The other workloads the path is built for, each in the launch shapes the
+    autotuner picks: the 256-replica ensemble, about 2e7 ions, 3e6 water sites."""
+    out = {}
+    # replica ensemble: 256 systems, log-uniform sizes 500..50000, P = 100, FP32C
+    t0 = time.time()
+    ens = W.c4_ensemble()
+    sysl = ens["systems"]
+    stream = torch.cuda.Stream()
+    b = R.Batch([x["pos"] for x in sysl], [x["q"] for x in sysl], [x["box"] for x in sysl], ens["rc"], ens["P"],
+                ens["seeds"], precision=R.RBSOG_FP32C, stream=stream.cuda_stream, autotune=True)
+    steps = args.other_steps
+    b.sample_k(2 + args.warmup + steps)
+    b.forces()
+    R.rbsog_set_velocities(b.ctx, None, T=1.0, seed=7)
+    b.step(args.warmup, 1e-3)
+    ms = timed_steps(R, torch, b, stream, steps, 1e-3)
+    out["ensemble_256"] = {"workload": f"256 replicas, {b.n} ions in all (500..50000 each, log-uniform), density "
+                                       f"0.1, r_c=3.5, P=100, FP32C, velocity-Verlet",
+                           "value": b.n * steps / (ms * 1e-3), "unit": "particle-steps/s", "steps": steps,
+                           "ms_per_step": ms / steps, "setup_s": time.time() - t0}
+    b.close()
+    log(f"[bench] ensemble: {out['ensemble_256']['value']:.3e} particle-steps/s")
+    # about 2e7 ions, P = 1000, both precisions
+    c5 = W.c5_large()
+    for prec, name in ((R.RBSOG_FP32C, "fp32c"), (R.RBSOG_FP64, "fp64")):
+        stream = torch.cuda.Stream()
+        sm = R.System(c5["pos"], c5["q"], c5["box"], c5["rc"], c5["P"], seed=5, precision=prec,
+                      stream=stream.cuda_stream, autotune=True)
+        steps5 = max(5, steps // 10)
+        sm.sample_k(2 + 2 + steps5)
+        sm.forces()
+        R.rbsog_set_velocities(sm.ctx, None, T=1.0, seed=7)
+        sm.step(2, 1e-3)
+        ms = timed_steps(R, torch, sm, stream, steps5, 1e-3)
+        out[f"ions_20M_{name}"] = {"workload": f"{len(c5['q'])} ions, density 0.1, jittered lattice, r_c=3.5, "
+                                               f"P=1000, velocity-Verlet",
+                                   "value": len(c5["q"]) * steps5 / (ms * 1e-3), "unit": "particle-steps/s",
+                                   "steps": steps5, "ms_per_step": ms / steps5}
+        sm.close()
+        log(f"[bench] 2e7 ions {name}: {out[f'ions_20M_{name}']['value']:.3e} particle-steps/s")
+    del c5
+    # 3e6 water sites (10^6 rigid 3-site molecules as point charges), r_c = 10, P = 500
+    pos, q, box = W.water(100, 0.0334, seed=3)
+    for prec, name in ((R.RBSOG_FP32C, "fp32c"), (R.RBSOG_FP64, "fp64")):
+        stream = torch.cuda.Stream()
+        sm = R.System(pos, q, box, 10.0, 500, seed=3, precision=prec, stream=stream.cuda_stream, autotune=True)
+        sm.sample_k(2 + 1 + 5)
+        sm.forces()
+        sm.step(1, 1e-4)
+        ms = timed_steps(R, torch, sm, stream, 5, 1e-4)
+        out[f"water_3M_{name}"] = {"workload": "3,000,000 water sites (SPC/E-shaped charges), r_c=10, P=500",
+                                   "value": len(q) * 5 / (ms * 1e-3), "unit": "particle-steps/s", "steps": 5,
+                                   "ms_per_step": ms / 5}
+        sm.close()
+        log(f"[bench] water {name}: {out[f'water_3M_{name}']['value']:.3e} particle-steps/s")
     return out
 
 
@@ -206,6 +280,8 @@ def main():
         "kernels_fp64": r64["kernels"],
         "launch_shapes": {"fp32c": r32["shapes"], "fp64": r64["shapes"]},
     }
+    if not args.no_other:
+        out["other_workloads"] = other_workloads(R, W, torch, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
