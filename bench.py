@@ -57,8 +57,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    # launch shapes are tuned during the warm-up steps unless this is given
-    ap.add_argument("--no-autotune", action="store_true")
+    # tune the main workload's launch shapes during its warm-up (the other
+    # workloads are always tuned); off by default so that a kernel trace of the
+    # run holds only the timed shapes
+    ap.add_argument("--autotune", action="store_true")
     # the ensemble, 2e7-ion and water workloads (reported next to the main line)
     ap.add_argument("--no-other", action="store_true")
     ap.add_argument("--other-steps", type=int, default=100)
@@ -74,7 +76,7 @@ def run_precision(R, torch, wl, prec, args):
     P = wl["P"]
     stream = torch.cuda.Stream()
     sysm = R.System(wl["pos"], wl["q"], wl["box"], wl["rc"], P, seed=2022, precision=prec,
-                    stream=stream.cuda_stream, autotune=not args.no_autotune)
+                    stream=stream.cuda_stream, autotune=args.autotune)
     batches = 1 + args.warmup + args.steps + args.profile_steps
     t0 = time.time()
     sysm.sample_k(batches)
@@ -113,6 +115,30 @@ def run_precision(R, torch, wl, prec, args):
                 value=n * args.steps / (ms * 1e-3), shapes=shapes)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_electrolyte300k.md")
+NEAR_SOURCES = ("paper_2205_13824_amd/csrc/kernels_near.hip", "paper_2205_13824_amd/csrc/rbsog_internal.h")
+
+
+def near_traffic():
+    """HBM bytes per launch of the FP32C near kernel from the committed
+    rocprofv3 counters (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or
+    None when the kernel's sources changed since the counters were taken."""
+    import hashlib
+
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = dict(line.split(": ", 1) for line in text.splitlines() if line.startswith(("near-", "copy-")))
+    h = hashlib.sha256()
+    for rel in NEAR_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    if vals.get("near-source-sha256", "").strip() != h.hexdigest():
+        return None
+    return int(vals["near-fp32c-traffic-bytes-per-launch"])
+
+
 def roofline(kernels, n, P, near_pairs, nexp32=3, ntail32=7):
     # near: units are unique pairs (the list holds both orders)
     units = {"rho": n * P, "far": n * P, "near": near_pairs // 2}
@@ -126,6 +152,7 @@ def roofline(kernels, n, P, near_pairs, nexp32=3, ntail32=7):
            "unit": "Gop/s (VALU lane slots)", "frac": achieved / PEAK_VALU_SLOTS, "traffic": None,
            "units_per_launch": units[dom], "slots_per_unit": WORK[dom], "us_per_launch": t * 1e6}
     if dom == "near":
+        out["traffic"] = near_traffic()
         # the same pairs priced as this library evaluates them (both orders;
         # rsqrt, nexp exponentials, two tail polynomials, ~15 FMA-class)
         ev = 2 * (TRANS_SLOTS * (1 + nexp32) + 3 * nexp32 + 2 * ntail32 + 15)
@@ -217,7 +244,7 @@ def cpu_baseline(wl, budget_s=12.0):
         oracle.near_cells(pos, q, box, rc, sog)
         oracle.far_rb(pos, q, box, sog, m, P, S)
         evals += 1
-        if time.perf_counter() - t0 > budget_s or evals >= 20:
+        if time.perf_counter() - t0 > budget_s or evals >= 60:
             break
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
