@@ -130,6 +130,8 @@ struct NearLds {
     double hx[3][XH];
     R hf[3][HC];           // force accumulators of the home batch
     uint2 q[kQueue];       // ring of queued pairs: (home index in the batch, candidate slot)
+    int32_t rlo[32], rex[32];  // non-empty candidate ranges of the cell: first slot, offset in the list
+    int32_t flag[64];          // range starts inside the current 64-slot window
 };
 
 // Per-system constants are read through the constant address space, so that
@@ -346,27 +348,48 @@ __global__ __launch_bounds__(64 * kNW) void k_near(EvalArgs a, const NearItem *_
             }
             const int32_t excl = incl - len;
             const int32_t C = __builtin_amdgcn_readlane(incl, kRanges - 1);
+            // the non-empty ranges, compacted: lane k < nne holds the k-th one's
+            // first slot and its offset in the flattened list (offsets strictly
+            // increase, the first is 0)
+            const bool ne = lane < kRanges && len > 0;
+            const uint64_t NE = __ballot(ne);
+            const int nne = (int)__popcll(NE);
+            if (ne) {
+                const int k = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(NE >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)NE, 0));
+                L.rlo[k] = lo;
+                L.rex[k] = excl;
+            }
+            wave_sync();
+            const int32_t clo = lane < nne ? L.rlo[lane < 32 ? lane : 0] : 0;
+            const int32_t cex = lane < nne ? L.rex[lane < 32 ? lane : 0] : 0x7fffffff;
             // origin of the cell-relative float coordinates used by the test:
             // the first home of the cell
             const uint4 o4 = L.hu[i0];
             const uint32_t ox = (uint32_t)rfl((int)o4.x), oy = (uint32_t)rfl((int)o4.y),
                            oz = (uint32_t)rfl((int)o4.z);
             for (int32_t cb = 0; cb < C; cb += 64 * S) {
-                // candidates of this pass in registers: each lane finds the range
-                // of its slots by counting range ends (broadcast with readlane)
-                int rr[S];
-#pragma unroll
-                for (int s2 = 0; s2 < S; ++s2) rr[s2] = 0;
-                for (int r = 0; r < kRanges - 1; ++r) {
-                    const int32_t end = __builtin_amdgcn_readlane(incl, r);
-#pragma unroll
-                    for (int s2 = 0; s2 < S; ++s2) rr[s2] += (cb + s2 * 64 + lane >= end) ? 1 : 0;
-                }
-                // the permutes read other lanes' registers: the whole wave is active
+                // candidates of this pass in registers.  For each 64-slot window,
+                // the starts of ranges inside it are flagged in LDS; a slot's
+                // range is the number of range starts at or before it (those
+                // before the window, plus the flagged ones up to its lane) - 1.
                 uint32_t cj[S];
 #pragma unroll
-                for (int s2 = 0; s2 < S; ++s2)
-                    cj[s2] = (uint32_t)(__shfl(lo, rr[s2], 64) + (cb + s2 * 64 + lane - __shfl(excl, rr[s2], 64)));
+                for (int s2 = 0; s2 < S; ++s2) {
+                    const int32_t base = cb + s2 * 64;
+                    L.flag[lane] = 0;
+                    wave_sync();
+                    if (lane < nne && cex >= base && cex < base + 64) L.flag[cex - base] = 1;
+                    wave_sync();
+                    const uint64_t B = __ballot(L.flag[lane] != 0);
+                    const int before = (int)__popcll(__ballot(lane < nne && cex < base));
+                    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+                    int k = before + (int)__popcll(B & upto) - 1;
+                    k = k < 0 ? 0 : k;
+                    // the permutes read other lanes' registers: the whole wave is active
+                    cj[s2] = (uint32_t)(__shfl(clo, k, 64) + (base + lane - __shfl(cex, k, 64)));
+                    wave_sync();
+                }
                 uint32_t cux[S], cuy[S], cuz[S];
 #pragma unroll
                 for (int s2 = 0; s2 < S; ++s2) {
