@@ -123,7 +123,7 @@ constexpr uint32_t kNoCand = 0xfffffffeu;  // candidate slot past the end of the
 template <bool F64>
 struct NearLds {
     using R = typename std::conditional<F64, double, float>::type;
-    static constexpr int HC = F64 ? 64 : 128;   // home particles staged per batch
+    static constexpr int HC = 64;                // home particles staged per batch
     static constexpr int XH = F64 ? HC : 1;
     uint4 hu[HC];          // home u_x, u_y, u_z, slot
     R hq[HC];
