@@ -139,6 +139,54 @@ struct NearLds {
 typedef const SysDev __attribute__((address_space(4))) CSys;
 typedef const SplitCoef64 __attribute__((address_space(4))) CCoef64;
 typedef const SplitCoef32 __attribute__((address_space(4))) CCoef32;
+// DPP lane moves (row = 16 lanes): row_shr:n, and row_bcast:15 / row_bcast:31.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, true));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROWS, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (uint32_t)lo);
+}
+template <int CTRL, int ROWS, typename R>
+__device__ __forceinline__ R dpp(R v) {
+    if constexpr (sizeof(R) == 8) return dpp_d<CTRL, ROWS>(v);
+    else return dpp_f<CTRL, ROWS>(v);
+}
+
+// Segmented inclusive sum across the wave: lane l ends with the sum of lanes
+// [max(sstart, .), l] of its segment (segments are runs of lanes; sstart is
+// the first lane of l's segment).  In-row shifts 1, 2, 4, 8, then the row
+// totals: lane 15 into rows 1 and 3, lane 31 into rows 2 and 3.
+template <typename R>
+__device__ __forceinline__ void seg_scan3(R &x, R &y, R &z, int lane, int sstart) {
+    const int pos = lane & 15;
+#define RBSOG_SHR(N)                                                                     \
+    {                                                                                    \
+        const R tx = dpp<0x110 + N, 0xf>(x), ty = dpp<0x110 + N, 0xf>(y), tz = dpp<0x110 + N, 0xf>(z); \
+        if (pos >= N && lane - N >= sstart) { x += tx; y += ty; z += tz; }              \
+    }
+    RBSOG_SHR(1)
+    RBSOG_SHR(2)
+    RBSOG_SHR(4)
+    RBSOG_SHR(8)
+#undef RBSOG_SHR
+    {
+        // row_bcast:15 to rows 1 and 3 (row mask 0xa)
+        const R tx = dpp<0x142, 0xa>(x), ty = dpp<0x142, 0xa>(y), tz = dpp<0x142, 0xa>(z);
+        const int row = lane >> 4;
+        if ((row == 1 || row == 3) && row * 16 - 1 >= sstart) { x += tx; y += ty; z += tz; }
+    }
+    {
+        // row_bcast:31 to rows 2 and 3 (row mask 0xc)
+        const R tx = dpp<0x143, 0xc>(x), ty = dpp<0x143, 0xc>(y), tz = dpp<0x143, 0xc>(z);
+        if (lane >= 32 && 31 >= sstart) { x += tx; y += ty; z += tz; }
+    }
+}
+
 template <bool F64>
 struct CoefOf { using type = CCoef32; };
 
@@ -234,10 +282,7 @@ __device__ __forceinline__ void eval_batch(const Geom &g, typename CoefOf<F64>::
     const uint64_t H = __ballot(seg);
     const uint64_t upto = H & ((2ull << lane) - 1ull);
     const int sstart = 63 - __clzll((long long)upto);
-    for (int off = 1; off < 64; off <<= 1) {
-        const R ux = __shfl_up(fx, off, 64), uy = __shfl_up(fy, off, 64), uz = __shfl_up(fz, off, 64);
-        if (lane - off >= sstart) { fx += ux; fy += uy; fz += uz; }
-    }
+    seg_scan3<R>(fx, fy, fz, lane, sstart);
     // a batch can span two candidate passes of one home, so segment totals
     // are added atomically (almost always one lane per home)
     const bool tail = lane < count && (lane == count - 1 || (lane < 63 && ((H >> (lane + 1)) & 1ull)));
