@@ -71,12 +71,12 @@ def parse():
     return ap.parse_args()
 
 
-def run_precision(R, torch, wl, prec, args):
+def run_precision(R, torch, wl, prec, args, near_table=False):
     n = len(wl["q"])
     P = wl["P"]
     stream = torch.cuda.Stream()
     sysm = R.System(wl["pos"], wl["q"], wl["box"], wl["rc"], P, seed=2022, precision=prec,
-                    stream=stream.cuda_stream, autotune=args.autotune)
+                    stream=stream.cuda_stream, autotune=args.autotune, near_table=near_table)
     batches = 1 + args.warmup + args.steps + args.profile_steps
     t0 = time.time()
     sysm.sample_k(batches)
@@ -98,7 +98,8 @@ def run_precision(R, torch, wl, prec, args):
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     ms = ev0.elapsed_time(ev1)
-    log(f"[bench] prec={prec}: {args.steps} steps in {ms:.2f} ms (wall {wall * 1e3:.2f} ms)")
+    log(f"[bench] prec={prec}{' core-shell' if near_table else ''}: {args.steps} steps in {ms:.2f} ms "
+        f"(wall {wall * 1e3:.2f} ms)")
     kernels = {}
     if args.profile_steps > 0:
         R.rbsog_profile(sysm.ctx, True)
@@ -276,10 +277,13 @@ def main():
 
     r32 = run_precision(R, torch, wl, R.RBSOG_FP32C, args)
     r64 = run_precision(R, torch, wl, R.RBSOG_FP64, args)
+    r32t = run_precision(R, torch, wl, R.RBSOG_FP32C, args, near_table=True)
     err = math.sqrt(float(np.sum((r32["F0"] - r64["F0"]) ** 2) / np.sum(r64["F0"] ** 2)))
     err_near = math.sqrt(float(np.sum((r32["Fn0"] - r64["Fn0"]) ** 2) / np.sum(r64["Fn0"] ** 2)))
     err_far = math.sqrt(float(np.sum((r32["Ff0"] - r64["Ff0"]) ** 2) / np.sum(r64["Ff0"] ** 2)))
     log(f"[bench] FP32C vs FP64 force relrms: total {err:.3e} near {err_near:.3e} far {err_far:.3e}")
+    err_t = math.sqrt(float(np.sum((r32t["F0"] - r64["F0"]) ** 2) / np.sum(r64["F0"] ** 2)))
+    log(f"[bench] FP32C core-shell vs FP64 force relrms: total {err_t:.3e}")
 
     roof = roofline(r32["kernels"], n, P, r32["near_pairs"])
     out = {
@@ -300,6 +304,10 @@ def main():
                    "n": n, "P": P, "rc": wl["rc"], "box": float(wl["box"][0])},
         "fp64": {"value": r64["value"], "ms_per_step": r64["ms"] / args.steps, "dtype": "f64"},
         "fp32c_speedup_vs_fp64": r32["value"] / r64["value"],
+        "fp32c_coreshell": {"value": r32t["value"], "ms_per_step": r32t["ms"] / args.steps, "dtype": "f32",
+                            "force_relrms_vs_fp64": err_t,
+                            "near_us_per_launch": r32t["kernels"].get("near", {}).get("us_per_launch"),
+                            "note": "near part by the core-shell table of Sec. 3.4 (opts.near_table)"},
         "fp32c_force_relrms_vs_fp64": {"total": err, "near": err_near, "far": err_far},
         "energy_step0": {"fp32c": list(map(float, r32["E0"])), "fp64": list(map(float, r64["E0"]))},
         "roofline": roof,

@@ -94,6 +94,14 @@ typedef struct {
     int32_t graphs;       /* nonzero: rbsog_step replays one captured HIP graph per step; default 1 */
     int32_t autotune;     /* nonzero: the first rbsog_step tunes the launch shapes (rbsog_autotune
                              with 5 repetitions) unless a cached tuning applies; default 0 */
+    int32_t near_table;   /* FP32C only, nonzero: core-shell near kernel (Sec. 3.4): pairs with
+                             r < r_in = 0.2 r_c take 4 Taylor terms of the Gaussians (the
+                             coefficients with the series' alternating sign), pairs with
+                             r_in <= r < r_c a 4096-point table indexed by the low 3 exponent
+                             bits and high 9 mantissa bits of r^2 in FP32, linearly
+                             interpolated; relative error of a pair force below 2e-6.
+                             E_ARG with FP64, or if r_c^2/r_in^2 spans more than 6 binades.
+                             Default 0 (direct evaluation). */
 } rbsog_opts;
 
 /* Fills *o with the defaults above. */

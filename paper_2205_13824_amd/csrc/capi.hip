@@ -99,6 +99,10 @@ struct SysHost {
     int32_t k0 = 0;
     SplitCoef64 co64{};
     SplitCoef32 co32{};
+    // core-shell near kernel (FP32C option)
+    const float4 *tbl = nullptr;
+    float rin2 = 0.f;
+    float ta[kTabQ] = {0, 0, 0, 0}, tb[kTabQ] = {0, 0, 0, 0};
     // work lists
     int32_t it0 = 0, it1 = 0, nch = 0, kt = 1, streams = 1;
     int64_t pofs = 0;
@@ -376,6 +380,12 @@ SysDev sysdev_of(const SysHost &h) {
     d.nch = h.nch;
     d.kt = h.kt;
     d.streams = h.streams;
+    d.tbl = h.tbl;
+    d.rin2 = h.rin2;
+    for (int i = 0; i < kTabQ; ++i) {
+        d.ta[i] = h.ta[i];
+        d.tb[i] = h.tb[i];
+    }
     return d;
 }
 
@@ -716,6 +726,63 @@ rbsog_status setup_system(SysHost &h, int64_t n, const double *pos, const double
     return RBSOG_OK;
 }
 
+// ---- core-shell near kernel (Sec. 3.4) -------------------------------------
+// Exact split kernels at x = r^2: force coefficient g and pair potential h.
+void split_kernels(const SysHost &h, double x, double &g, double &hv) {
+    g = std::pow(x, -1.5);
+    hv = 1.0 / std::sqrt(x);
+    for (size_t l = 0; l < h.s.size(); ++l) {
+        const double a = 1.0 / (h.s[l] * h.s[l]);
+        const double e = std::exp(-x * a);
+        g -= 2.0 * h.omega[l] * a * e;
+        hv -= h.omega[l] * e;
+    }
+}
+
+// Table of the shell and Taylor coefficients of the core for one system.  The
+// table's 2^kTabBexp binades start at the one holding r_in^2 (as an FP32
+// value); index i stands for the point whose FP32 bits are (e << 23) |
+// ((i mod 2^kTabBman) << (23 - kTabBman)) with e the binade whose low
+// kTabBexp exponent bits are i >> kTabBman.
+rbsog_status build_coreshell(SysHost &h, std::vector<float4> &table, int32_t idx) {
+    const float rin = (float)(kTabRin * h.rc);
+    const float rin2 = rin * rin, rc2 = (float)(h.rc * h.rc);
+    uint32_t b0, bt;
+    std::memcpy(&b0, &rin2, 4);
+    std::memcpy(&bt, &rc2, 4);
+    const int e0 = (int)((b0 >> 23) & 0xff), etop = (int)((bt >> 23) & 0xff);
+    const int nb = 1 << kTabBexp, sh = 23 - kTabBman;
+    if (etop - e0 > nb - 2) return fail(nullptr, RBSOG_E_ARG, "system %d: r_c / r_in spans too many binades", idx);
+    table.resize(kTabSize);
+    for (int i = 0; i < kTabSize; ++i) {
+        const int blk = i >> kTabBman, mant = i & ((1 << kTabBman) - 1);
+        const int e = e0 + (((blk - e0) % nb) + nb) % nb;
+        const uint32_t bits = ((uint32_t)e << 23) | ((uint32_t)mant << sh);
+        const uint32_t nbits = bits + (1u << sh);
+        float x, xn;
+        std::memcpy(&x, &bits, 4);
+        std::memcpy(&xn, &nbits, 4);
+        double g, hv, gn, hn;
+        split_kernels(h, x, g, hv);
+        split_kernels(h, xn, gn, hn);
+        table[i] = make_float4((float)g, (float)(gn - g), (float)hv, (float)(hn - hv));
+    }
+    h.rin2 = rin2;
+    for (int i = 0; i < kTabQ; ++i) {
+        double a_i = 0.0, b_i = 0.0, fact = 1.0;
+        for (int k = 2; k < i + 1; ++k) fact *= k;
+        for (size_t l = 0; l < h.s.size(); ++l) {
+            const double a = 1.0 / (h.s[l] * h.s[l]);
+            const double c = ((i & 1) ? -1.0 : 1.0) / fact * std::pow(a, i);
+            a_i += h.omega[l] * a * c;
+            b_i += h.omega[l] * c;
+        }
+        h.ta[i] = (float)a_i;
+        h.tb[i] = (float)b_i;
+    }
+    return RBSOG_OK;
+}
+
 // ---- shape cache: tuned shapes by (architecture, precision, batch size,
 // log2 N, P per system, log2 cells), kept for the process and optionally in
 // the text file named by RBSOG_TUNE_CACHE (one "key cpi chunk block" line per
@@ -948,6 +1015,8 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     if (opts) o = *opts;
     if (o.precision != RBSOG_FP64 && o.precision != RBSOG_FP32C)
         return fail(nullptr, RBSOG_E_ARG, "unknown precision %d", o.precision);
+    if (o.near_table && o.precision != RBSOG_FP32C)
+        return fail(nullptr, RBSOG_E_ARG, "the core-shell near table is an option of the FP32C form");
     if (!(o.mass > 0.0) || !std::isfinite(o.mass)) return fail(nullptr, RBSOG_E_ARG, "mass must be > 0");
     if (!(o.neutral_tol >= 0.0)) return fail(nullptr, RBSOG_E_ARG, "neutral_tol must be >= 0");
 
@@ -980,6 +1049,17 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     }
     c->N = offsets[nsys];
     c->q_host.assign(q, q + c->N);
+    std::vector<std::vector<float4>> tables;
+    if (o.near_table) {
+        tables.resize(nsys);
+        for (int32_t s = 0; s < nsys; ++s) {
+            rbsog_status st = build_coreshell(c->sys[s], tables[s], s);
+            if (st != RBSOG_OK) {
+                delete c;
+                return st;
+            }
+        }
+    }
     c->autotune = o.autotune != 0;
     int64_t near_cap, rho_cap, far_cap, part_cap;
     work_caps(c, near_cap, rho_cap, far_cap, part_cap);
@@ -1038,6 +1118,18 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     ALLOC(E, 4 * (int64_t)nsys);
     ALLOC(flag, 1);
     ALLOC(sys_done, nsys);
+    float4 *dtab = nullptr;
+    if (o.near_table) {
+        if ((st = dalloc(c, &dtab, (int64_t)nsys * kTabSize)) != RBSOG_OK) return bail(st);
+        for (int32_t s = 0; s < nsys; ++s) {
+            if (hipMemcpy(dtab + (int64_t)s * kTabSize, tables[s].data(), kTabSize * sizeof(float4),
+                          hipMemcpyHostToDevice) != hipSuccess) {
+                fail(c, RBSOG_E_DEVICE, "table upload failed");
+                return bail(RBSOG_E_DEVICE);
+            }
+            c->sys[s].tbl = dtab + (int64_t)s * kTabSize;
+        }
+    }
     ALLOC(near_items, near_cap);
     ALLOC(rho_items, rho_cap);
     ALLOC(far_items, far_cap);
@@ -1114,6 +1206,7 @@ void rbsog_default_opts(rbsog_opts *o) {
     o->mass = 1.0;
     o->graphs = 1;
     o->autotune = 0;
+    o->near_table = 0;
 }
 
 rbsog_status rbsog_sog_table1(int32_t row, double rc, rbsog_sog *out) {

@@ -224,7 +224,8 @@ template <bool F64>
 __device__ __forceinline__ void eval_batch(const Geom &g, typename CoefOf<F64>::type *co, NearLds<F64> &L,
                                            const uint32_t *__restrict__ su, const double *__restrict__ sx,
                                            const double *__restrict__ sq, const float *__restrict__ sqf, int64_t n,
-                                           int lane, int head, int count, double &e) {
+                                           const float4 *__restrict__ tbl, float rin2, const float *ta,
+                                           const float *tb, int lane, int head, int count, double &e) {
     using R = typename NearLds<F64>::R;
     constexpr int NT = (F64 ? kTailDeg64 : kTailDeg32) + 1;
     R fx = 0, fy = 0, fz = 0;
@@ -254,27 +255,52 @@ __device__ __forceinline__ void eval_batch(const Geom &g, typename CoefOf<F64>::
                 qq = L.hq[slot] * sqf[j];
             }
             const R r2 = F64 ? dx * dx + dy * dy + dz * dz : r2f;
-            R rinv, gs = 0, ph = 0;
-            if constexpr (F64) rinv = rsqrt(r2);
-            else rinv = __builtin_amdgcn_rsqf(r2);
+            R gk, hk;  // force coefficient g and pair potential h of the split
+            if (!F64 && tbl) {
+                if (r2 >= rin2) {
+                    // shell: table point from the FP32 bits of r^2, linear in r^2
+                    const uint32_t bits = __float_as_uint(r2f);
+                    const float4 tv = tbl[(bits >> (23 - kTabBman)) & (kTabSize - 1)];
+                    const float fr = (float)(bits & ((1u << (23 - kTabBman)) - 1u)) * (1.0f / (1 << (23 - kTabBman)));
+                    gk = fmaf(fr, tv.y, tv.x);
+                    hk = fmaf(fr, tv.w, tv.z);
+                } else {
+                    // core: Taylor terms of the Gaussians, 1/r and 1/r^3 computed
+                    const float ri = __builtin_amdgcn_rsqf(r2f);
+                    float pa = ta[kTabQ - 1], pb = tb[kTabQ - 1];
 #pragma unroll
-            for (int t = NT - 1; t >= 0; --t) {
-                if constexpr (F64) { gs = fma(gs, r2, co->ft[t]); ph = fma(ph, r2, co->pt[t]); }
-                else { gs = fmaf(gs, r2, co->ft[t]); ph = fmaf(ph, r2, co->pt[t]); }
+                    for (int t = kTabQ - 2; t >= 0; --t) {
+                        pa = fmaf(pa, r2f, ta[t]);
+                        pb = fmaf(pb, r2f, tb[t]);
+                    }
+                    gk = ri * ri * ri - 2.0f * pa;
+                    hk = ri - pb;
+                }
+            } else {
+                R rinv, gs = 0, ph = 0;
+                if constexpr (F64) rinv = rsqrt(r2);
+                else rinv = __builtin_amdgcn_rsqf(r2);
+#pragma unroll
+                for (int t = NT - 1; t >= 0; --t) {
+                    if constexpr (F64) { gs = fma(gs, r2, co->ft[t]); ph = fma(ph, r2, co->pt[t]); }
+                    else { gs = fmaf(gs, r2, co->ft[t]); ph = fmaf(ph, r2, co->pt[t]); }
+                }
+                for (int l = 0; l < co->nexp; ++l) {
+                    R ex;
+                    if constexpr (F64) ex = exp(-r2 * co->a[l]);
+                    else ex = __builtin_amdgcn_exp2f(-r2 * co->a[l]);
+                    gs += co->cw[l] * ex;
+                    ph += co->w[l] * ex;
+                }
+                gk = rinv * rinv * rinv - gs;
+                hk = rinv - ph;
             }
-            for (int l = 0; l < co->nexp; ++l) {
-                R ex;
-                if constexpr (F64) ex = exp(-r2 * co->a[l]);
-                else ex = __builtin_amdgcn_exp2f(-r2 * co->a[l]);
-                gs += co->cw[l] * ex;
-                ph += co->w[l] * ex;
-            }
-            const R coef = qq * (rinv * rinv * rinv - gs);
+            const R coef = qq * gk;
             // force on the home along r_i - r_j = -(dx, dy, dz)
             fx = -coef * dx;
             fy = -coef * dy;
             fz = -coef * dz;
-            e += 0.5 * (double)(qq * (rinv - ph));
+            e += 0.5 * (double)(qq * hk);
         }
     }
     const int prev = __shfl_up(slot, 1, 64);
@@ -324,6 +350,13 @@ __global__ __launch_bounds__(64 * kNW) void k_near(EvalArgs a, const NearItem *_
     if constexpr (F64) co = &sp->co64;
     else co = &sp->co32;
     const int64_t c0s = sp->c0;
+    const float4 *tbl = F64 ? nullptr : sp->tbl;
+    const float rin2 = sp->rin2;
+    float ta[kTabQ], tb[kTabQ];
+    for (int t = 0; t < kTabQ; ++t) {
+        ta[t] = sp->ta[t];
+        tb[t] = sp->tb[t];
+    }
     const int64_t ra = item.c_begin, rb = item.c_end;
     double e = 0.0;
     int qn = 0, qh = 0;  // ring tail (pairs queued) and head (pairs evaluated)
@@ -516,7 +549,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near(EvalArgs a, const NearItem *_
                         static_assert(63 + kU * S * 64 < kQueue, "ring too small");
                         while (qn - qh >= 64) {
                             wave_sync();
-                            eval_batch<F64>(g, co, L, su, sx, sq, sqf, n, lane, qh, 64, e);
+                            eval_batch<F64>(g, co, L, su, sx, sq, sqf, n, tbl, rin2, ta, tb, lane, qh, 64, e);
                             qh += 64;
                         }
                     }
@@ -525,7 +558,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near(EvalArgs a, const NearItem *_
         }
         // the queue refers to this batch's home slots: drain it, then write
         wave_sync();
-        if (qn > qh) eval_batch<F64>(g, co, L, su, sx, sq, sqf, n, lane, qh, qn - qh, e);
+        if (qn > qh) eval_batch<F64>(g, co, L, su, sx, sq, sqf, n, tbl, rin2, ta, tb, lane, qh, qn - qh, e);
         qn = 0;
         qh = 0;
         wave_sync();

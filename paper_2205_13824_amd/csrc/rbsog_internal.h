@@ -67,6 +67,18 @@ struct SplitCoef {
 using SplitCoef64 = SplitCoef<double, kTailDeg64 + 1>;
 using SplitCoef32 = SplitCoef<float, kTailDeg32 + 1>;
 
+// Core-shell near kernel (Sec. 3.4), an option of the FP32C form: pairs with
+// r < r_in take Q Taylor terms of the Gaussians with 1/r and 1/r^3 computed;
+// r_in <= r < r_c take a table indexed by the FP32 bits of r^2 (the low
+// kTabBexp exponent bits and the high kTabBman mantissa bits) with linear
+// interpolation.  Entry: (g, g_next - g, h, h_next - h) at the table point,
+// g = 1/r^3 - 2 sum_l omega_l/s_l^2 e^{-r^2/s_l^2}, h = 1/r - sum_l omega_l e^{-r^2/s_l^2}.
+constexpr int kTabQ = 4;
+constexpr int kTabBexp = 3;
+constexpr int kTabBman = 9;
+constexpr int kTabSize = 1 << (kTabBexp + kTabBman);
+constexpr double kTabRin = 0.2;  // r_in / r_c
+
 // Per-system constants, one entry per system in a device array.
 struct SysDev {
     Geom g;
@@ -84,6 +96,11 @@ struct SysDev {
     int64_t pofs;         // first rho partial (complex entries) of the system
     int32_t nch;          // rho particle chunks of the system
     int32_t kt, streams;  // rho block shape: k tiles of 64 lanes x particle streams
+    // core-shell near kernel (FP32C option): table, r_in^2, Taylor coefficients
+    const float4 *tbl;    // null: direct evaluation
+    float rin2;
+    float ta[kTabQ];      // sum_l omega_l/s_l^2 (-1)^(i-1)/(i-1)! s_l^(-2(i-1)), i = 1..Q
+    float tb[kTabQ];      // sum_l omega_l (-1)^(i-1)/(i-1)! s_l^(-2(i-1))
 };
 
 // Near work item: a run of cells of one system.

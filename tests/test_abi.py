@@ -81,3 +81,20 @@ def test_null_context_calls_fail_cleanly(lib):
     assert lib.rbsog_forces(None, None, None) == -1
     assert lib.rbsog_step(None, 1, 0.1) == -1
     lib.rbsog_destroy(None)
+
+
+def test_option_and_batch_validation(lib):
+    pos, q, box = _system()
+    sog = R.rbsog_sog_table1(2, 3.0)
+    # the core-shell table is an option of the FP32C form only
+    with pytest.raises(R.RbsogError) as e:
+        R.rbsog_init(pos, q, box, sog, 3.0, 10, 1, precision=R.RBSOG_FP64, near_table=True)
+    assert e.value.status == -1
+    # a batch names the system that fails validation
+    q_bad = np.array([1, -1] * 3 + [1, 0.5])
+    with pytest.raises(R.RbsogError) as e:
+        R.rbsog_init_batch([pos, pos], [q, q_bad], [box, box], [sog, sog], [3.0, 3.0], [10, 10], [1, 2])
+    assert e.value.status == -2 and "system 1" in str(e.value)
+    with pytest.raises(R.RbsogError) as e:
+        R.rbsog_init_batch([pos, pos[:1]], [q, q[:1]], [box, box], [sog, sog], [3.0, 3.0], [10, 10], [1, 2])
+    assert e.value.status == -1

@@ -308,3 +308,35 @@ def test_autotune_option_in_step():
         s.close()
     for a, b in zip(*runs):
         assert np.allclose(a, b, rtol=1e-11, atol=1e-12)
+
+
+@pytest.mark.parametrize("case", ["c1", "ions5000", "water"])
+def test_coreshell_table_near(orc, case):
+    # core-shell near kernel (Sec. 3.4) in the FP32C form: against the oracle's
+    # core-shell kernel (same table construction and Taylor core) and against
+    # the direct Gaussian sum, both to the FP32C bar
+    from oracle import coreshell as cs
+    if case == "c1":
+        c = W.c1_small()
+        pos, q, box, rc, P = c["pos"], c["q"], c["box"], c["rc"], c["P"]
+    elif case == "ions5000":
+        pos, q, box = W.ions_rsa(5000, 0.1, 1.0, seed=21)
+        rc, P = 3.5, 64
+    else:
+        pos, q, box = W.water(10, 0.0334, seed=22)
+        rc, P = 10.0, 50
+    say(f"[gpu] core-shell near, case {case}: n={len(q)} rc={rc}")
+    sysm = R.System(pos, q, box, rc, P, seed=9, precision=R.RBSOG_FP32C, near_table=True)
+    m = sysm.sample_k(1)
+    F, E = sysm.forces()
+    Fn, Ff = sysm.components()
+    sog = oracle_sog(orc, sysm.sog)
+    nb = orc.neighbors_brute(pos, box, rc)
+    Fcs, Ucs = cs.near_coreshell(pos, q, box, rc, sog, nb)
+    Fo, Uo = orc.near_brute(pos, q, box, rc, sog)
+    Ffo, _, _, _ = orc.far_rb(pos, q, box, sog, m, P)
+    e_cs, e_ex, e_far = relrms(Fn, Fcs), relrms(Fn, Fo), relrms(Ff, Ffo)
+    e_u = abs(E[0] - Ucs) / abs(Ucs)
+    say(f"[core-shell {case}] near vs oracle core-shell {e_cs:.3e}, vs direct sum {e_ex:.3e}; far {e_far:.3e}; "
+        f"U_N rel {e_u:.2e}")
+    assert e_cs < F32C_TOL and e_ex < F32C_TOL and e_far < F32C_TOL and e_u < F32C_TOL
