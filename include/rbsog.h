@@ -102,6 +102,11 @@ typedef struct {
                              interpolated; relative error of a pair force below 2e-6.
                              E_ARG with FP64, or if r_c^2/r_in^2 spans more than 6 binades.
                              Default 0 (direct evaluation). */
+    int32_t zero_mode;    /* zero-frequency mode term (Sec. 3.2, eqs. "sperical", "planar"),
+                             M = sum_i q_i r_i over the wrapped positions:
+                             0 tinfoil (none; default), 1 spherical U^0 = (2 pi/3V)|M|^2,
+                             2 slab along z U^0 = (2 pi/V) M_z^2; its force -grad U^0 is
+                             added to the far force and U^0 to U* and U. */
 } rbsog_opts;
 
 /* Fills *o with the defaults above. */

@@ -103,9 +103,12 @@ struct SysHost {
     const float4 *tbl = nullptr;
     float rin2 = 0.f;
     float ta[kTabQ] = {0, 0, 0, 0}, tb[kTabQ] = {0, 0, 0, 0};
+    // zero-frequency mode
+    int32_t zmode = 0;
+    double zu = 0.0, zf = 0.0;
     // work lists
     int32_t it0 = 0, it1 = 0, nch = 0, kt = 1, streams = 1;
-    int64_t pofs = 0;
+    int64_t pofs = 0, choff = 0;
     // sequence
     MHChain chain;
     std::vector<int32_t> kseq;
@@ -150,6 +153,7 @@ struct rbsog_ctx {
     KRec64 *kb64 = nullptr;
     KRec32 *kb32 = nullptr;
     double *wk = nullptr, *rho = nullptr, *ek = nullptr, *partial = nullptr, *epart = nullptr, *E = nullptr;
+    double *dip_part = nullptr, *dipole = nullptr;
     int32_t *flag = nullptr;
     uint32_t *sys_done = nullptr;
     NearItem *near_items = nullptr;
@@ -382,6 +386,10 @@ SysDev sysdev_of(const SysHost &h) {
     d.streams = h.streams;
     d.tbl = h.tbl;
     d.rin2 = h.rin2;
+    d.zmode = h.zmode;
+    d.zu = h.zu;
+    d.zf = h.zf;
+    d.choff = h.choff;
     for (int i = 0; i < kTabQ; ++i) {
         d.ta[i] = h.ta[i];
         d.tb[i] = h.tb[i];
@@ -474,6 +482,8 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
     a.partial = c->partial;
     a.epart = c->epart;
     a.E = c->E;
+    a.dip_part = c->dip_part;
+    a.dipole = c->dipole;
     a.flag = c->flag;
     a.sys_done = c->sys_done;
     a.kick = stepping ? 1 : 0;
@@ -855,7 +865,7 @@ void tune_cache_store(const std::string &key, const Tune &t) {
 void build_work(rbsog_ctx *c, const Tune &t, std::vector<NearItem> &near, std::vector<RhoItem> &rho,
                 std::vector<FarItem> &far) {
     const int64_t cpi = t.near_cpi, chunk = t.rho_chunk, fb = t.far_block;
-    int64_t pofs = 0;
+    int64_t pofs = 0, choff = 0;
     for (int32_t s = 0; s < c->nsys; ++s) {
         SysHost &h = c->sys[s];
         h.it0 = (int32_t)near.size();
@@ -875,6 +885,8 @@ void build_work(rbsog_ctx *c, const Tune &t, std::vector<NearItem> &near, std::v
             }
         h.pofs = pofs;
         pofs += (int64_t)h.nch * h.P;
+        h.choff = choff;
+        choff += h.nch;
         for (int64_t i = 0; i < h.n; i += fb)
             far.push_back(FarItem{s, 0, h.p0 + i, h.p0 + std::min(h.n, i + fb)});
     }
@@ -893,14 +905,16 @@ Tune default_tune(const rbsog_ctx *c) {
 // Capacities of the work lists and partial buffers: the largest any shape
 // below may need (1 cell per near item, 256-particle chunks, 64-particle
 // far items).
-void work_caps(const rbsog_ctx *c, int64_t &near_cap, int64_t &rho_cap, int64_t &far_cap, int64_t &part_cap) {
+void work_caps(const rbsog_ctx *c, int64_t &near_cap, int64_t &rho_cap, int64_t &far_cap, int64_t &part_cap,
+               int64_t &chunk_cap) {
     near_cap = c->C;
-    rho_cap = far_cap = part_cap = 0;
+    rho_cap = far_cap = part_cap = chunk_cap = 0;
     for (const SysHost &h : c->sys) {
         const int64_t ktiles = (h.P + 63) / 64, kt = std::min<int64_t>(ktiles, 16);
         const int64_t nch = std::max<int64_t>(1, (h.n + 255) / 256);
         rho_cap += ((ktiles + kt - 1) / kt) * nch;
         part_cap += nch * h.P;
+        chunk_cap += nch;
         far_cap += (h.n + 63) / 64;
     }
 }
@@ -1017,6 +1031,7 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
         return fail(nullptr, RBSOG_E_ARG, "unknown precision %d", o.precision);
     if (o.near_table && o.precision != RBSOG_FP32C)
         return fail(nullptr, RBSOG_E_ARG, "the core-shell near table is an option of the FP32C form");
+    if (o.zero_mode < 0 || o.zero_mode > 2) return fail(nullptr, RBSOG_E_ARG, "zero_mode must be 0, 1 or 2");
     if (!(o.mass > 0.0) || !std::isfinite(o.mass)) return fail(nullptr, RBSOG_E_ARG, "mass must be > 0");
     if (!(o.neutral_tol >= 0.0)) return fail(nullptr, RBSOG_E_ARG, "neutral_tol must be >= 0");
 
@@ -1040,6 +1055,15 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
         h.p0 = p0;
         h.c0 = c->C;
         h.k0 = c->K;
+        // zero-frequency mode (Sec. 3.2): spherical (2 pi/3V)|M|^2, slab (2 pi/V) M_z^2
+        h.zmode = o.zero_mode;
+        if (o.zero_mode == 1) {
+            h.zu = 2.0 * kPi / (3.0 * h.V);
+            h.zf = -4.0 * kPi / (3.0 * h.V);
+        } else if (o.zero_mode == 2) {
+            h.zu = 2.0 * kPi / h.V;
+            h.zf = -4.0 * kPi / h.V;
+        }
         c->C += h.ncell;
         if (c->C >= (int64_t)INT32_MAX || (int64_t)c->K + P[s] >= (int64_t)INT32_MAX) {
             delete c;
@@ -1061,8 +1085,8 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
         }
     }
     c->autotune = o.autotune != 0;
-    int64_t near_cap, rho_cap, far_cap, part_cap;
-    work_caps(c, near_cap, rho_cap, far_cap, part_cap);
+    int64_t near_cap, rho_cap, far_cap, part_cap, chunk_cap;
+    work_caps(c, near_cap, rho_cap, far_cap, part_cap, chunk_cap);
 
     auto bail = [&](rbsog_status st) {
         g_init_error = c->err;
@@ -1116,6 +1140,8 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     ALLOC(partial, 2 * part_cap);
     ALLOC(epart, near_cap);
     ALLOC(E, 4 * (int64_t)nsys);
+    ALLOC(dip_part, 3 * chunk_cap);
+    ALLOC(dipole, 3 * (int64_t)nsys);
     ALLOC(flag, 1);
     ALLOC(sys_done, nsys);
     float4 *dtab = nullptr;
@@ -1207,6 +1233,7 @@ void rbsog_default_opts(rbsog_opts *o) {
     o->graphs = 1;
     o->autotune = 0;
     o->near_table = 0;
+    o->zero_mode = 0;
 }
 
 rbsog_status rbsog_sog_table1(int32_t row, double rc, rbsog_sog *out) {

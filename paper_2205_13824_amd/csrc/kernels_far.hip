@@ -208,6 +208,41 @@ __global__ __launch_bounds__(1024) void k_rho(EvalArgs a, const RhoItem *__restr
             a.partial[2 * o + 1] = si;
         }
         __syncthreads();
+        if (sp->zmode != 0 && kg == 0) {
+            // dipole moment of the chunk, sum_j q_j x_j over the wrapped
+            // positions, for the zero-frequency mode term (fixed order)
+            double mx = 0.0, my = 0.0, mz = 0.0;
+            for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+                const double qj = q[j];
+                mx = fma(qj, x[j], mx);
+                my = fma(qj, x[n + j], my);
+                mz = fma(qj, x[2 * n + j], mz);
+            }
+            red[threadIdx.x] = make_double2(mx, my);
+            __syncthreads();
+            for (int w = 512; w > 0; w >>= 1) {
+                if ((int)threadIdx.x < w) {
+                    red[threadIdx.x].x += red[threadIdx.x + w].x;
+                    red[threadIdx.x].y += red[threadIdx.x + w].y;
+                }
+                __syncthreads();
+            }
+            const double2 mxy = red[0];
+            __syncthreads();
+            red[threadIdx.x] = make_double2(mz, 0.0);
+            __syncthreads();
+            for (int w = 512; w > 0; w >>= 1) {
+                if ((int)threadIdx.x < w) red[threadIdx.x].x += red[threadIdx.x + w].x;
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) {
+                const int64_t c = 3 * (sp->choff + chunk);
+                a.dip_part[c] = mxy.x;
+                a.dip_part[c + 1] = mxy.y;
+                a.dip_part[c + 2] = red[0].x;
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -300,9 +335,18 @@ __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
             __syncthreads();
         }
         if (threadIdx.x == 0) {
-            const double tot = sr[0] + si[0] - sd.uself;
+            double u0 = 0.0;
+            if (sd.zmode != 0) {
+                double m[3] = {0.0, 0.0, 0.0};
+                for (int32_t ch = 0; ch < sd.nch; ++ch)
+                    for (int d = 0; d < 3; ++d) m[d] += a.dip_part[3 * (sd.choff + ch) + d];
+                for (int d = 0; d < 3; ++d) a.dipole[3 * s + d] = m[d];
+                u0 = sd.zmode == 1 ? sd.zu * (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) : sd.zu * m[2] * m[2];
+            }
+            // U* holds the far part with the zero-frequency mode term
+            const double tot = sr[0] + si[0] + u0 - sd.uself;
             a.E[4 * s] = sr[0];
-            a.E[4 * s + 1] = si[0];
+            a.E[4 * s + 1] = si[0] + u0;
             a.E[4 * s + 2] = sd.uself;
             a.E[4 * s + 3] = tot;
             if (!isfinite(tot)) atomicOr(a.flag, 2);
@@ -402,6 +446,15 @@ __global__ __launch_bounds__(256) void k_far(EvalArgs a, const FarItem *__restri
             Fx = qi * (Fx + fx); Fy = qi * (Fy + fy); Fz = qi * (Fz + fz);
         }
         if (valid) {
+            if (sp->zmode != 0) {
+                const double qi = a.nxt.q[i], c = sp->zf * qi;
+                const double *M = a.dipole + 3 * sys;
+                if (sp->zmode == 1) {
+                    Fx += c * M[0];
+                    Fy += c * M[1];
+                }
+                Fz += c * M[2];
+            }
             a.Ff[i] = Fx;
             a.Ff[n + i] = Fy;
             a.Ff[2 * n + i] = Fz;

@@ -101,6 +101,11 @@ struct SysDev {
     float rin2;
     float ta[kTabQ];      // sum_l omega_l/s_l^2 (-1)^(i-1)/(i-1)! s_l^(-2(i-1)), i = 1..Q
     float tb[kTabQ];      // sum_l omega_l (-1)^(i-1)/(i-1)! s_l^(-2(i-1))
+    // zero-frequency mode (Sec. 3.2): 0 tinfoil, 1 spherical, 2 slab along z;
+    // U^0 = zu * |M|^2 (or M_z^2), F_i = zf * q_i M (or M_z e_z)
+    int32_t zmode;
+    double zu, zf;
+    int64_t choff;        // first structure-factor chunk of the system over the batch
 };
 
 // Near work item: a run of cells of one system.
@@ -145,6 +150,8 @@ struct EvalArgs {
     KRec64 *kb64;
     KRec32 *kb32;
     double *wk, *rho, *ek, *partial, *epart, *E;
+    double *dip_part;      // dipole partials per structure-factor chunk (3 per chunk)
+    double *dipole;        // dipole moment M per system (3 per system)
     int32_t *flag;         // bit 0: non-finite force, bit 1: non-finite energy
     uint32_t *sys_done;    // per-system counters of reduced k records
     // velocity-Verlet

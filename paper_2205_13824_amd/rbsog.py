@@ -18,6 +18,10 @@ LIB_PATH = os.path.join(_HERE, "librbsog.so")
 RBSOG_FP64 = 0
 RBSOG_FP32C = 1
 
+ZERO_MODE_TINFOIL = 0
+ZERO_MODE_SPHERICAL = 1
+ZERO_MODE_SLAB = 2
+
 STATUS = {0: "RBSOG_OK", -1: "RBSOG_E_ARG", -2: "RBSOG_E_NOT_NEUTRAL", -3: "RBSOG_E_CUTOFF", -4: "RBSOG_E_SOG",
           -5: "RBSOG_E_DEVICE", -6: "RBSOG_E_OOM", -7: "RBSOG_E_NONFINITE", -8: "RBSOG_E_KSEQ", -9: "RBSOG_E_STATE"}
 
@@ -43,7 +47,7 @@ class rbsog_sog(ctypes.Structure):
 class rbsog_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("neutral_tol", ctypes.c_double), ("mass", ctypes.c_double), ("graphs", ctypes.c_int32),
-                ("autotune", ctypes.c_int32), ("near_table", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32), ("near_table", ctypes.c_int32), ("zero_mode", ctypes.c_int32)]
 
 
 class rbsog_info_t(ctypes.Structure):
@@ -125,23 +129,24 @@ def rbsog_default_opts() -> rbsog_opts:
     return o
 
 
-def _opts(precision, device, stream, neutral_tol, mass, graphs, autotune=False, near_table=False):
+def _opts(precision, device, stream, neutral_tol, mass, graphs, autotune=False, near_table=False, zero_mode=0):
     o = rbsog_default_opts()
     o.precision, o.device, o.neutral_tol, o.mass, o.graphs = precision, device, neutral_tol, mass, int(graphs)
     o.autotune = int(autotune)
     o.near_table = int(near_table)
+    o.zero_mode = int(zero_mode)
     o.stream = stream
     return o
 
 
 def rbsog_init(pos, q, box, sog: rbsog_sog, rc: float, P: int, seed: int, precision: int = RBSOG_FP64,
                device: int = 0, stream: int | None = None, neutral_tol: float = 1e-10, mass: float = 1.0,
-               graphs: bool = True, autotune: bool = False, near_table: bool = False):
+               graphs: bool = True, autotune: bool = False, near_table: bool = False, zero_mode: int = 0):
     q = _f64(q, (-1,))
     n = q.size
     pos = _f64(pos, (n, 3))
     box = _f64(box, (3,))
-    o = _opts(precision, device, stream, neutral_tol, mass, graphs, autotune, near_table)
+    o = _opts(precision, device, stream, neutral_tol, mass, graphs, autotune, near_table, zero_mode)
     ctx = ctypes.c_void_p()
     _check(lib().rbsog_init(ctypes.byref(ctx), n, _ptr(pos), _ptr(q), _ptr(box), ctypes.byref(sog), float(rc),
                             int(P), int(seed), ctypes.byref(o)))
@@ -150,7 +155,7 @@ def rbsog_init(pos, q, box, sog: rbsog_sog, rc: float, P: int, seed: int, precis
 
 def rbsog_init_batch(pos_list, q_list, boxes, sogs, rcs, Ps, seeds, precision: int = RBSOG_FP64, device: int = 0,
                      stream: int | None = None, neutral_tol: float = 1e-10, mass: float = 1.0, graphs: bool = True,
-                     autotune: bool = False, near_table: bool = False):
+                     autotune: bool = False, near_table: bool = False, zero_mode: int = 0):
     """One context over len(q_list) systems; particle arrays are concatenated."""
     ns = len(q_list)
     sizes = [int(np.asarray(qq).size) for qq in q_list]
@@ -163,7 +168,7 @@ def rbsog_init_batch(pos_list, q_list, boxes, sogs, rcs, Ps, seeds, precision: i
     rc = _f64(rcs, (ns,))
     Pa = np.ascontiguousarray(np.asarray(Ps, dtype=np.int32).reshape(ns))
     sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64).reshape(ns))
-    o = _opts(precision, device, stream, neutral_tol, mass, graphs, autotune, near_table)
+    o = _opts(precision, device, stream, neutral_tol, mass, graphs, autotune, near_table, zero_mode)
     ctx = ctypes.c_void_p()
     _check(lib().rbsog_init_batch(ctypes.byref(ctx), ns, _ptr(offsets), _ptr(pos), _ptr(q), _ptr(box),
                                   ctypes.cast(sog_arr, ctypes.c_void_p), _ptr(rc), _ptr(Pa), _ptr(sd),

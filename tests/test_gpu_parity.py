@@ -340,3 +340,38 @@ def test_coreshell_table_near(orc, case):
     say(f"[core-shell {case}] near vs oracle core-shell {e_cs:.3e}, vs direct sum {e_ex:.3e}; far {e_far:.3e}; "
         f"U_N rel {e_u:.2e}")
     assert e_cs < F32C_TOL and e_ex < F32C_TOL and e_far < F32C_TOL and e_u < F32C_TOL
+
+
+@pytest.mark.parametrize("prec,tol", [(R.RBSOG_FP64, F64_TOL), (R.RBSOG_FP32C, F32C_TOL)])
+@pytest.mark.parametrize("mode", [1, 2])
+def test_zero_mode_terms(orc, prec, tol, mode):
+    # spherical (1) and slab (2) zero-frequency mode terms of Sec. 3.2 on top of
+    # the random-batch far force, in a 2-system batch (unwrapped input positions)
+    from oracle import zeromode as zm
+    systems = []
+    for i, (n, L, rc, P) in enumerate(((777, 11.3, 3.1, 37), (1000, 10.0, 3.0, 100))):
+        rng = np.random.default_rng(40 + i)
+        box = np.array([L, L * 0.9, L * 1.1])
+        pos = rng.random((n, 3)) * box * 1.5 - 2.0
+        q = np.where(np.arange(n) < n // 2, 1.0, -1.0)
+        if n % 2:
+            q[-1] = 0.0
+        systems.append(dict(pos=pos, q=q, box=box, rc=rc, P=P))
+    b = R.Batch([s["pos"] for s in systems], [s["q"] for s in systems], [s["box"] for s in systems],
+                [s["rc"] for s in systems], [s["P"] for s in systems], [61, 62], precision=prec, zero_mode=mode)
+    m_all = b.sample_k(1)
+    F, E = b.forces()
+    Fn, Ff = b.components()
+    off = np.cumsum([0] + [len(s["q"]) for s in systems])
+    ms = np.split(m_all, np.cumsum([s["P"] for s in systems])[:-1])
+    for i, s in enumerate(systems):
+        sl = slice(off[i], off[i + 1])
+        sog = oracle_sog(orc, b.sogs[i])
+        Ffo, Uso, _, _ = orc.far_rb(s["pos"], s["q"], s["box"], sog, ms[i], s["P"])
+        Fz, Uz, _ = zm.zero_mode(s["pos"], s["q"], s["box"], mode)
+        e_f = relrms(Ff[sl], Ffo + Fz)
+        e_u = abs(E[i][1] - (Uso + Uz)) / abs(Uso + Uz)
+        say(f"[zero mode {mode} prec={prec} sys {i}] far+zero-mode relrms {e_f:.3e}, U* rel {e_u:.2e}, "
+            f"U0/U* {Uz / Uso:.3f}")
+        assert e_f < tol and e_u < 10 * tol
+    b.close()
