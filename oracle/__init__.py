@@ -17,7 +17,8 @@ garbled formulas (checked by finite differences or quadrature):
     C0/C1 for the untruncated series (l = 0..infinity);
   * self energy: (1/2) F_M(0) sum q_i^2 with the retuned omega_0 (Sec. 3.1).
 The core-shell near kernel of Sec. 3.4 is in ``oracle/coreshell.py``, the
-zero-frequency mode terms of Sec. 3.2 in ``oracle/zeromode.py``.
+zero-frequency mode terms of Sec. 3.2 in ``oracle/zeromode.py``, the Langevin
+(BAOAB) thermostat in ``oracle/thermostat.py``.
 """
 from __future__ import annotations
 
