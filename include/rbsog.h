@@ -178,7 +178,8 @@ rbsog_status rbsog_set_k(rbsog_ctx *ctx, int32_t sys, int64_t n_k, const int32_t
 rbsog_status rbsog_forces(rbsog_ctx *ctx, double *F_out, double *E_out);
 
 /* n_steps velocity-Verlet steps of size dt (kick dt/2, drift, wrap, forces
- * with the next batch, kick dt/2; Algorithm 1 with NVE integration).  If the
+ * with the next batch, kick dt/2; Algorithm 1 with NVE integration, or the
+ * Langevin BAOAB step of rbsog_set_thermostat).  If the
  * forces of the current positions are not known yet, one evaluation is made
  * first.  E_KSEQ (before any work) if the sequence cannot serve every
  * evaluation; E_NONFINITE if a non-finite force appeared. */
@@ -189,6 +190,17 @@ rbsog_status rbsog_step(rbsog_ctx *ctx, int64_t n_steps, double dt);
  * Box-Muller) and remove each system's centre-of-mass velocity.  E_ARG if v
  * is NULL and T < 0. */
 rbsog_status rbsog_set_velocities(rbsog_ctx *ctx, const double *v, double T, uint64_t seed);
+
+/* Langevin thermostat for rbsog_step (Algorithm 1 leaves the thermostat open;
+ * Theorem 3 is stated for Langevin dynamics).  gamma > 0: each step is BAOAB:
+ * kick dt/2, drift dt/2, v <- c1 v + c2 xi with c1 = exp(-gamma dt),
+ * c2 = sqrt((1 - c1^2) T/m), drift dt/2, forces, kick dt/2; xi are standard
+ * normals, for particle i (caller index) at thermostatted step s (counted from
+ * this call, from 0) drawn with Philox4x32-10, key (seed_lo, seed_hi), counter
+ * (i, s, 2, lane), lanes 0 and 1 giving two 53-bit uniforms each (u1, u2),
+ * (u3, u4), xi = (r1 cos 2pi u2, r1 sin 2pi u2, r2 cos 2pi u4), r = sqrt(-2 ln(1-u)).
+ * gamma = 0 restores NVE velocity Verlet.  E_ARG for gamma < 0 or T < 0. */
+rbsog_status rbsog_set_thermostat(rbsog_ctx *ctx, double gamma, double T, uint64_t seed);
 
 /* Replaces the positions (host n x 3, finite); forces become unknown. */
 rbsog_status rbsog_set_positions(rbsog_ctx *ctx, const double *pos);

@@ -154,6 +154,10 @@ struct rbsog_ctx {
     KRec32 *kb32 = nullptr;
     double *wk = nullptr, *rho = nullptr, *ek = nullptr, *partial = nullptr, *epart = nullptr, *E = nullptr;
     double *dip_part = nullptr, *dipole = nullptr;
+    // Langevin thermostat
+    double gamma = 0.0, temp = 0.0;
+    uint64_t tseed = 0;
+    int64_t *tstep = nullptr;
     int32_t *flag = nullptr;
     uint32_t *sys_done = nullptr;
     NearItem *near_items = nullptr;
@@ -489,6 +493,11 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
     a.kick = stepping ? 1 : 0;
     a.hdm = 0.5 * dt / c->mass;
     a.dt = dt;
+    a.thermo = c->gamma > 0.0 ? 1 : 0;
+    a.c1 = std::exp(-c->gamma * dt);
+    a.c2 = std::sqrt((1.0 - a.c1 * a.c1) * c->temp / c->mass);
+    a.tseed = c->tseed;
+    a.tstep = c->tstep;
     return a;
 }
 
@@ -1141,6 +1150,7 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     ALLOC(epart, near_cap);
     ALLOC(E, 4 * (int64_t)nsys);
     ALLOC(dip_part, 3 * chunk_cap);
+    ALLOC(tstep, 1);
     ALLOC(dipole, 3 * (int64_t)nsys);
     ALLOC(flag, 1);
     ALLOC(sys_done, nsys);
@@ -1193,6 +1203,7 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
                   hipMemcpy(c->ksys, ks.data(), K * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->dsys, sd.data(), nsys * sizeof(SysDev), hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->kcur, zc.data(), nsys * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(c->tstep, zc.data(), sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->sys_done, zu.data(), nsys * sizeof(uint32_t), hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->flag, &zf, sizeof zf, hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemset(c->cell_count, 0, (size_t)C * sizeof(int32_t)) == hipSuccess;
@@ -1398,6 +1409,20 @@ rbsog_status rbsog_set_velocities(rbsog_ctx *c, const double *v, double T, uint6
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return upload_by_id(c, vv.data(), c->buf[c->parity].v, "velocity");
+}
+
+rbsog_status rbsog_set_thermostat(rbsog_ctx *c, double gamma, double T, uint64_t seed) {
+    TRY(check_ctx(c));
+    if (!(gamma >= 0.0) || !std::isfinite(gamma) || !(T >= 0.0) || !std::isfinite(T))
+        return fail(c, RBSOG_E_ARG, "need gamma >= 0 and T >= 0");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->gamma = gamma;
+    c->temp = T;
+    c->tseed = seed;
+    const int64_t z = 0;
+    HIPCHK(c, hipMemcpy(c->tstep, &z, sizeof z, hipMemcpyHostToDevice));
+    drop_graphs(c);  // the graphs hold the step's constants
+    return RBSOG_OK;
 }
 
 rbsog_status rbsog_set_positions(rbsog_ctx *c, const double *pos) {

@@ -352,6 +352,7 @@ __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
             if (!isfinite(tot)) atomicOr(a.flag, 2);
             a.kcur[s] += sd.P;
             a.sys_done[s] = 0u;
+            if (s == 0 && a.kick && a.thermo) *a.tstep += 1;
         }
         __syncthreads();
     }

@@ -157,6 +157,11 @@ struct EvalArgs {
     // velocity-Verlet
     int32_t kick;          // nonzero: kick + drift before, kick after
     double hdm, dt;
+    // Langevin thermostat (BAOAB): half drift, v <- c1 v + c2 xi, half drift
+    int32_t thermo;
+    double c1, c2;
+    uint64_t tseed;
+    int64_t *tstep;        // thermostatted steps taken (noise counter)
 };
 
 // ---- kernel launchers (kernels_md.hip) --------------------------------------

@@ -31,7 +31,7 @@ EXPORTS = ("rbsog_default_opts", "rbsog_sog_table1", "rbsog_init", "rbsog_init_b
            "rbsog_step", "rbsog_set_velocities", "rbsog_set_positions", "rbsog_get_state", "rbsog_get_forces",
            "rbsog_get_energy", "rbsog_get_rho", "rbsog_info", "rbsog_debug_cells", "rbsog_debug_neighbors",
            "rbsog_profile", "rbsog_profile_read", "rbsog_sync", "rbsog_last_error", "rbsog_status_string",
-           "rbsog_destroy", "rbsog_autotune")
+           "rbsog_destroy", "rbsog_autotune", "rbsog_set_thermostat")
 
 
 class RbsogError(RuntimeError):
@@ -94,6 +94,7 @@ def lib():
             "rbsog_status_string": (ctypes.c_char_p, [i32]),
             "rbsog_destroy": (None, [vp]),
             "rbsog_autotune": (i32, [vp, i32]),
+            "rbsog_set_thermostat": (i32, [vp, dbl, dbl, u64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -207,6 +208,10 @@ def rbsog_step(ctx, n_steps: int, dt: float):
 def rbsog_set_velocities(ctx, v=None, T: float = 1.0, seed: int = 0, n: int | None = None):
     vv = None if v is None else _f64(v, (-1, 3))
     _check(lib().rbsog_set_velocities(ctx, _ptr(vv), float(T), int(seed)), ctx)
+
+
+def rbsog_set_thermostat(ctx, gamma: float, T: float, seed: int = 0):
+    _check(lib().rbsog_set_thermostat(ctx, float(gamma), float(T), int(seed)), ctx)
 
 
 def rbsog_set_positions(ctx, pos):

@@ -375,3 +375,49 @@ def test_zero_mode_terms(orc, prec, tol, mode):
             f"U0/U* {Uz / Uso:.3f}")
         assert e_f < tol and e_u < 10 * tol
     b.close()
+
+
+def test_langevin_baoab_steps_match_oracle(orc):
+    # three BAOAB steps in FP64 against the oracle's own Philox noise
+    from oracle import thermostat as th
+    n, L = 400, 16.0
+    pos, q, box = W.ions_rsa(n, n / L ** 3, 1.0, 71)
+    v0 = W.maxwellian(n, 1.0, 72)
+    rc, P, dt, gamma, T, seed = 3.5, 40, 2e-3, 3.0, 1.7, 1234
+    out = []
+    for graphs in (False, True):
+        sysm = R.System(pos, q, box, rc, P, seed=8, precision=R.RBSOG_FP64, graphs=graphs)
+        ks = sysm.sample_k(4)
+        R.rbsog_set_velocities(sysm.ctx, v0)
+        R.rbsog_set_thermostat(sysm.ctx, gamma, T, seed)
+        sysm.step(3, dt)
+        out.append(R.rbsog_get_state(sysm.ctx, n))
+        sysm.close()
+    assert (out[0][0] == out[1][0]).all() and (out[0][1] == out[1][1]).all()
+    xo, vo = th.baoab_run(orc, pos, v0, q, box, rc, oracle_sog(orc, R.rbsog_sog_table1(2, rc)), P, ks, 3, dt,
+                          gamma, T, seed)
+    ex = float(np.abs(out[0][0] - xo).max())
+    ev = relrms(out[0][1], vo)
+    say(f"[baoab] max |x - x_oracle| {ex:.2e}, velocity relrms {ev:.2e}")
+    assert ex < 1e-10 and ev < 1e-10
+
+
+def test_langevin_thermostat_holds_temperature():
+    # weak charges (+-0.1, Coulomb energy at contact well below kT): point ions
+    # without a repulsive core would otherwise pair up and heat the system
+    n = 512
+    pos, q, box = W.ions_rsa(n, 0.1, 1.0, 73)
+    q = 0.1 * q
+    T, gamma = 1.5, 2.0
+    sysm = R.System(pos, q, box, 3.5, 50, seed=9, precision=R.RBSOG_FP32C)
+    sysm.sample_k(2 + 3000)
+    R.rbsog_set_thermostat(sysm.ctx, gamma, T, 77)
+    sysm.step(1000, 2e-3)
+    temps = []
+    for _ in range(40):
+        sysm.step(50, 2e-3)
+        _, v = R.rbsog_get_state(sysm.ctx, n)
+        temps.append(float((v * v).sum()) / (3 * n))
+    Tm = float(np.mean(temps))
+    say(f"[thermostat] kinetic temperature {Tm:.4f} (target {T})")
+    assert abs(Tm / T - 1.0) < 0.05
