@@ -71,16 +71,19 @@ def parse():
     return ap.parse_args()
 
 
-def run_precision(R, torch, wl, prec, args, near_table=False):
+def run_precision(R, torch, wl, prec, args, near_table=False, device_chains=0):
     n = len(wl["q"])
     P = wl["P"]
     stream = torch.cuda.Stream()
     sysm = R.System(wl["pos"], wl["q"], wl["box"], wl["rc"], P, seed=2022, precision=prec,
-                    stream=stream.cuda_stream, autotune=args.autotune, near_table=near_table)
-    batches = 1 + args.warmup + args.steps + args.profile_steps
-    t0 = time.time()
-    sysm.sample_k(batches)
-    log(f"[bench] prec={prec}: sampled {batches * P} wave vectors in {time.time() - t0:.2f} s")
+                    stream=stream.cuda_stream, autotune=args.autotune, near_table=near_table,
+                    device_chains=device_chains)
+    label = f"prec={prec}{' core-shell' if near_table else ''}{f' device-chains={device_chains}' if device_chains else ''}"
+    if not device_chains:
+        batches = 1 + args.warmup + args.steps + args.profile_steps
+        t0 = time.time()
+        sysm.sample_k(batches)
+        log(f"[bench] prec={prec}: sampled {batches * P} wave vectors in {time.time() - t0:.2f} s")
     F0, E0 = sysm.forces()
     Fn0, Ff0 = sysm.components()
     # neighbour pairs inside r_c at step 0 (full list, both orders), for the near roofline
@@ -98,7 +101,7 @@ def run_precision(R, torch, wl, prec, args, near_table=False):
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     ms = ev0.elapsed_time(ev1)
-    log(f"[bench] prec={prec}{' core-shell' if near_table else ''}: {args.steps} steps in {ms:.2f} ms "
+    log(f"[bench] {label}: {args.steps} steps in {ms:.2f} ms "
         f"(wall {wall * 1e3:.2f} ms)")
     kernels = {}
     if args.profile_steps > 0:
@@ -116,6 +119,7 @@ def run_precision(R, torch, wl, prec, args, near_table=False):
                 value=n * args.steps / (ms * 1e-3), shapes=shapes)
 
 
+DEVICE_CHAINS = 64
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_electrolyte300k.md")
 NEAR_SOURCES = ("paper_2205_13824_amd/csrc/kernels_near.hip", "paper_2205_13824_amd/csrc/rbsog_internal.h")
 
@@ -175,7 +179,9 @@ def timed_steps(R, torch, obj, stream, steps, dt):
 
 def other_workloads(R, W, torch, args):
     """The other workloads the path is built for, each in the launch shapes the
-    autotuner picks: the 256-replica ensemble, about 2e7 ions, 3e6 water sites."""
+    autotuner picks: the 256-replica ensemble, about 2e7 ions, 3e6 water sites.
+    Wave vectors come from the device chains (a refill every DEVICE_CHAINS
+    steps, so the shorter runs below time steps between refills)."""
     out = {}
     # replica ensemble: 256 systems, log-uniform sizes 500..50000, P = 100, FP32C
     t0 = time.time()
@@ -183,9 +189,9 @@ def other_workloads(R, W, torch, args):
     sysl = ens["systems"]
     stream = torch.cuda.Stream()
     b = R.Batch([x["pos"] for x in sysl], [x["q"] for x in sysl], [x["box"] for x in sysl], ens["rc"], ens["P"],
-                ens["seeds"], precision=R.RBSOG_FP32C, stream=stream.cuda_stream, autotune=True)
+                ens["seeds"], precision=R.RBSOG_FP32C, stream=stream.cuda_stream, autotune=True,
+                device_chains=DEVICE_CHAINS)
     steps = args.other_steps
-    b.sample_k(2 + args.warmup + steps)
     b.forces()
     R.rbsog_set_velocities(b.ctx, None, T=1.0, seed=7)
     b.step(args.warmup, 1e-3)
@@ -201,9 +207,8 @@ def other_workloads(R, W, torch, args):
     for prec, name in ((R.RBSOG_FP32C, "fp32c"), (R.RBSOG_FP64, "fp64")):
         stream = torch.cuda.Stream()
         sm = R.System(c5["pos"], c5["q"], c5["box"], c5["rc"], c5["P"], seed=5, precision=prec,
-                      stream=stream.cuda_stream, autotune=True)
+                      stream=stream.cuda_stream, autotune=True, device_chains=DEVICE_CHAINS)
         steps5 = max(5, steps // 10)
-        sm.sample_k(2 + 2 + steps5)
         sm.forces()
         R.rbsog_set_velocities(sm.ctx, None, T=1.0, seed=7)
         sm.step(2, 1e-3)
@@ -219,8 +224,8 @@ def other_workloads(R, W, torch, args):
     pos, q, box = W.water(100, 0.0334, seed=3)
     for prec, name in ((R.RBSOG_FP32C, "fp32c"), (R.RBSOG_FP64, "fp64")):
         stream = torch.cuda.Stream()
-        sm = R.System(pos, q, box, 10.0, 500, seed=3, precision=prec, stream=stream.cuda_stream, autotune=True)
-        sm.sample_k(2 + 1 + 5)
+        sm = R.System(pos, q, box, 10.0, 500, seed=3, precision=prec, stream=stream.cuda_stream, autotune=True,
+                      device_chains=DEVICE_CHAINS)
         sm.forces()
         sm.step(1, 1e-4)
         ms = timed_steps(R, torch, sm, stream, 5, 1e-4)
@@ -275,9 +280,13 @@ def main():
     n, P = len(wl["q"]), wl["P"]
     log(f"[bench] workload built in {time.time() - t0:.1f} s: n={n} L={wl['box'][0]:.4f} P={P}")
 
-    r32 = run_precision(R, torch, wl, R.RBSOG_FP32C, args)
-    r64 = run_precision(R, torch, wl, R.RBSOG_FP64, args)
-    r32t = run_precision(R, torch, wl, R.RBSOG_FP32C, args, near_table=True)
+    # every leg draws its wave vectors inside the timed steps (device chains,
+    # identical sequences in both precisions); one more leg takes them from a
+    # host-sampled sequence uploaded before timing
+    r32 = run_precision(R, torch, wl, R.RBSOG_FP32C, args, device_chains=DEVICE_CHAINS)
+    r64 = run_precision(R, torch, wl, R.RBSOG_FP64, args, device_chains=DEVICE_CHAINS)
+    r32t = run_precision(R, torch, wl, R.RBSOG_FP32C, args, near_table=True, device_chains=DEVICE_CHAINS)
+    r32h = run_precision(R, torch, wl, R.RBSOG_FP32C, args)
     err = math.sqrt(float(np.sum((r32["F0"] - r64["F0"]) ** 2) / np.sum(r64["F0"] ** 2)))
     err_near = math.sqrt(float(np.sum((r32["Fn0"] - r64["Fn0"]) ** 2) / np.sum(r64["Fn0"] ** 2)))
     err_far = math.sqrt(float(np.sum((r32["Ff0"] - r64["Ff0"]) ** 2) / np.sum(r64["Ff0"] ** 2)))
@@ -300,7 +309,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{n}-ion +-1 electrolyte, density 0.1, RSA d_min=1, r_c=3.5, P={P}, "
-                               f"Table 1 row 2, velocity-Verlet dt=1e-3, T=1",
+                               f"Table 1 row 2, velocity-Verlet dt=1e-3, T=1, "
+                               f"wave vectors sampled on the device ({DEVICE_CHAINS} chains)",
                    "n": n, "P": P, "rc": wl["rc"], "box": float(wl["box"][0])},
         "fp64": {"value": r64["value"], "ms_per_step": r64["ms"] / args.steps, "dtype": "f64"},
         "fp32c_speedup_vs_fp64": r32["value"] / r64["value"],
@@ -308,6 +318,13 @@ def main():
                             "force_relrms_vs_fp64": err_t,
                             "near_us_per_launch": r32t["kernels"].get("near", {}).get("us_per_launch"),
                             "note": "near part by the core-shell table of Sec. 3.4 (opts.near_table)"},
+        "sampling": {"chains": DEVICE_CHAINS,
+                     "refill_us_per_launch": r32["kernels"].get("sample_refill", {}).get("us_per_launch"),
+                     "note": "wave vectors drawn inside the timed steps by on-device Metropolis-Hastings chains "
+                             f"(opts.device_chains = {DEVICE_CHAINS}): one refill launch every {DEVICE_CHAINS} "
+                             "steps advances every chain by P states"},
+        "fp32c_host_sequence": {"value": r32h["value"], "ms_per_step": r32h["ms"] / args.steps, "dtype": "f32",
+                                "note": "wave vectors from the host chain, sampled and uploaded before timing"},
         "fp32c_force_relrms_vs_fp64": {"total": err, "near": err_near, "far": err_far},
         "energy_step0": {"fp32c": list(map(float, r32["E0"])), "fp64": list(map(float, r64["E0"]))},
         "roofline": roof,

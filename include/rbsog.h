@@ -107,6 +107,15 @@ typedef struct {
                              0 tinfoil (none; default), 1 spherical U^0 = (2 pi/3V)|M|^2,
                              2 slab along z U^0 = (2 pi/V) M_z^2; its force -grad U^0 is
                              added to the far force and U^0 to U* and U. */
+    int32_t device_chains;/* lambda >= 1: the wave vectors are drawn on the device by lambda
+                             independent Metropolis-Hastings chains per system (the parallel
+                             sampling of Sec. 3.4): chain c serves evaluations c, c + lambda,
+                             c + 2 lambda, ... with P consecutive chain states each; it uses
+                             Philox stream 3 + c keyed by the system's seed and otherwise the
+                             host chain's algorithm (Sec. 3.3, 100 transitions discarded).
+                             Every lambda evaluations one kernel advances all chains by P
+                             states.  rbsog_sample_k and rbsog_set_k then return E_STATE.
+                             0 (default): the host chain fills the sequence. At most 4096. */
 } rbsog_opts;
 
 /* Fills *o with the defaults above. */
@@ -217,6 +226,12 @@ rbsog_status rbsog_get_forces(rbsog_ctx *ctx, double *F_near, double *F_far);
  * for rho_re, rho_im; either may be NULL). */
 rbsog_status rbsog_get_energy(rbsog_ctx *ctx, double *E);
 rbsog_status rbsog_get_rho(rbsog_ctx *ctx, int32_t sys, double *rho_re, double *rho_im);
+
+/* Copies the wave vectors m of the latest evaluation's batch of system sys
+ * (Algorithm 1, the P vectors of one step; host 3 * P int32, m_x m_y m_z per
+ * vector) whether the host chain or the device chains drew them.  E_STATE if
+ * no evaluation has been made. */
+rbsog_status rbsog_get_kbatch(rbsog_ctx *ctx, int32_t sys, int32_t *m_out);
 
 /* Scalars of system sys: S, V, number of cells, wave vectors left in its
  * sequence, evaluations made, its particle count and the number of systems. */

@@ -72,9 +72,10 @@ struct ProfEntry {
     int64_t launches = 0;
 };
 
-enum Kid { K_KDQ, K_SCAN, K_SCATTER, K_SORTG, K_NEAR, K_RHO, K_RHORED, K_FAR, K_COUNT };
+enum Kid { K_KDQ, K_SCAN, K_SCATTER, K_SORTG, K_NEAR, K_RHO, K_RHORED, K_FAR, K_SAMPLE, K_COUNT };
 const char *kKernelNames[K_COUNT] = {"kick_drift_quantise", "scan_cell_counts", "cell_scatter", "sort_gather",
-                                     "near",                "rho",              "rho_reduce",   "far"};
+                                     "near",                "rho",              "rho_reduce",   "far",
+                                     "sample_refill"};
 
 
 // Launch shapes of the work lists (the tunable part of the plan).
@@ -118,6 +119,8 @@ struct SysHost {
     int64_t kcap = 0;
     int32_t *dkseq = nullptr;
     double *dkw = nullptr;
+    // on-device chains: split coefficients in device memory
+    double *domega = nullptr, *ds = nullptr;
 };
 
 }  // namespace
@@ -158,6 +161,10 @@ struct rbsog_ctx {
     double gamma = 0.0, temp = 0.0;
     uint64_t tseed = 0;
     int64_t *tstep = nullptr;
+    // on-device sampler: lambda chains per system (0 = host chain)
+    int32_t lambda = 0;
+    SampDev *dsamp = nullptr;
+    ChainState *chains = nullptr;
     int32_t *flag = nullptr;
     uint32_t *sys_done = nullptr;
     NearItem *near_items = nullptr;
@@ -517,6 +524,20 @@ rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt) {
     TRY(timed(c, K_RHORED, [&] { launch_rho_reduce(a, s); }));
     TRY(timed(c, K_FAR, [&] { launch_far(a, f64, c->far_items, c->n_far, c->tune.far_block, s); }));
     HIPCHK(c, hipGetLastError());
+    return RBSOG_OK;
+}
+
+// On-device sampler: the ring of lambda batches is refilled (every chain
+// advanced by P states, the cursors reset to 0) before the evaluation that
+// would run past its end.  The host mirrors the cursors, so the schedule is
+// known here and the refill stays outside the captured step graphs.
+rbsog_status refill_if_due(rbsog_ctx *c) {
+    if (!c->lambda) return RBSOG_OK;
+    const SysHost &h0 = c->sys[0];
+    if (h0.cursor + h0.P <= (int64_t)c->lambda * h0.P) return RBSOG_OK;
+    TRY(timed(c, K_SAMPLE, [&] { launch_refill(c->dsamp, c->nsys, c->lambda, c->chains, c->kcur, c->flag, c->stream); }));
+    HIPCHK(c, hipGetLastError());
+    for (auto &h : c->sys) h.cursor = 0;
     return RBSOG_OK;
 }
 
@@ -1021,6 +1042,43 @@ rbsog_status autotune_now(rbsog_ctx *c, int32_t reps) {
     return RBSOG_OK;
 }
 
+// On-device sampler: lambda fresh chains per system (not started, 100
+// transitions to discard) and the per-system constants; the cursors start at
+// the end of the ring so that the first evaluation refills it.
+rbsog_status setup_device_chains(rbsog_ctx *c, int32_t lambda) {
+    c->lambda = lambda;
+    TRY(dalloc(c, &c->dsamp, c->nsys));
+    TRY(dalloc(c, &c->chains, (int64_t)c->nsys * lambda));
+    std::vector<SampDev> sd((size_t)c->nsys);
+    for (int32_t s = 0; s < c->nsys; ++s) {
+        SysHost &h = c->sys[s];
+        const int32_t G = (int32_t)h.omega.size();
+        TRY(dalloc(c, &h.domega, G));
+        TRY(dalloc(c, &h.ds, G));
+        HIPCHK(c, hipMemcpy(h.domega, h.omega.data(), G * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(h.ds, h.s.data(), G * sizeof(double), hipMemcpyHostToDevice));
+        SampDev &d = sd[s];
+        d.omega = h.domega;
+        d.s = h.ds;
+        d.G = G;
+        d.P = h.P;
+        for (int k = 0; k < 3; ++k) {
+            d.L[k] = h.box[k];
+            d.sd[k] = h.box[k] / (std::sqrt(2.0) * kPi * h.s[0]);
+            d.a[k] = kPi * h.s[0] / h.box[k];
+        }
+        d.seed = h.seed;
+        d.out = h.dkseq;
+        h.cursor = (int64_t)lambda * h.P;
+    }
+    HIPCHK(c, hipMemcpy(c->dsamp, sd.data(), sd.size() * sizeof(SampDev), hipMemcpyHostToDevice));
+    ChainState fresh{};
+    fresh.burn_left = 100;
+    std::vector<ChainState> ch((size_t)c->nsys * lambda, fresh);
+    HIPCHK(c, hipMemcpy(c->chains, ch.data(), ch.size() * sizeof(ChainState), hipMemcpyHostToDevice));
+    return RBSOG_OK;
+}
+
 rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, const double *pos, const double *q,
                         const double *boxes, const rbsog_sog *sog, const double *rc, const int32_t *P,
                         const uint64_t *seeds, const rbsog_opts *opts) {
@@ -1041,6 +1099,8 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     if (o.near_table && o.precision != RBSOG_FP32C)
         return fail(nullptr, RBSOG_E_ARG, "the core-shell near table is an option of the FP32C form");
     if (o.zero_mode < 0 || o.zero_mode > 2) return fail(nullptr, RBSOG_E_ARG, "zero_mode must be 0, 1 or 2");
+    if (o.device_chains < 0 || o.device_chains > kMaxChains)
+        return fail(nullptr, RBSOG_E_ARG, "device_chains must be in [0, %d]", kMaxChains);
     if (!(o.mass > 0.0) || !std::isfinite(o.mass)) return fail(nullptr, RBSOG_E_ARG, "mass must be > 0");
     if (!(o.neutral_tol >= 0.0)) return fail(nullptr, RBSOG_E_ARG, "neutral_tol must be >= 0");
 
@@ -1213,7 +1273,8 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
         }
     }
     for (int32_t s = 0; s < nsys; ++s)
-        if ((st = ensure_kcap(c, s, 4 * (int64_t)c->sys[s].P)) != RBSOG_OK) return bail(st);
+        if ((st = ensure_kcap(c, s, std::max<int64_t>(4, o.device_chains) * c->sys[s].P)) != RBSOG_OK) return bail(st);
+    if (o.device_chains > 0 && (st = setup_device_chains(c, o.device_chains)) != RBSOG_OK) return bail(st);
     {
         // shapes: a tuned entry of the cache for this kind of batch, else defaults
         hipDeviceProp_t prop;
@@ -1245,6 +1306,7 @@ void rbsog_default_opts(rbsog_opts *o) {
     o->autotune = 0;
     o->near_table = 0;
     o->zero_mode = 0;
+    o->device_chains = 0;
 }
 
 rbsog_status rbsog_sog_table1(int32_t row, double rc, rbsog_sog *out) {
@@ -1281,6 +1343,7 @@ rbsog_status rbsog_init_batch(rbsog_ctx **out, int32_t n_sys, const int64_t *off
 
 rbsog_status rbsog_sample_k(rbsog_ctx *c, int64_t n_batches, int32_t *m_out) {
     TRY(check_ctx(c));
+    if (c->lambda) return fail(c, RBSOG_E_STATE, "wave vectors are drawn by the device chains (device_chains > 0)");
     if (n_batches < 1) return fail(c, RBSOG_E_ARG, "n_batches must be >= 1");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     int64_t written = 0;
@@ -1310,6 +1373,7 @@ rbsog_status rbsog_sample_k(rbsog_ctx *c, int64_t n_batches, int32_t *m_out) {
 rbsog_status rbsog_set_k(rbsog_ctx *c, int32_t sys, int64_t n_k, const int32_t *m, const double *w) {
     TRY(check_ctx(c));
     TRY(check_sys(c, sys));
+    if (c->lambda) return fail(c, RBSOG_E_STATE, "wave vectors are drawn by the device chains (device_chains > 0)");
     if (n_k < 1 || !m) return fail(c, RBSOG_E_ARG, "need n_k >= 1 vectors");
     for (int64_t e = 0; e < n_k; ++e) {
         if (m[3 * e] == 0 && m[3 * e + 1] == 0 && m[3 * e + 2] == 0)
@@ -1329,6 +1393,7 @@ rbsog_status rbsog_set_k(rbsog_ctx *c, int32_t sys, int64_t n_k, const int32_t *
 }
 
 static rbsog_status check_kseq(rbsog_ctx *c, int64_t evals) {
+    if (c->lambda) return RBSOG_OK;  // the device chains never run out
     for (int32_t s = 0; s < c->nsys; ++s) {
         const SysHost &h = c->sys[s];
         const int64_t nvec = (int64_t)h.kseq.size() / 3;
@@ -1342,6 +1407,7 @@ static rbsog_status check_kseq(rbsog_ctx *c, int64_t evals) {
 rbsog_status rbsog_forces(rbsog_ctx *c, double *F_out, double *E_out) {
     TRY(check_ctx(c));
     TRY(check_kseq(c, 1));
+    TRY(refill_if_due(c));
     TRY(enqueue_eval(c, false, 0.0));
     account_eval(c);
     if (F_out) {
@@ -1362,6 +1428,7 @@ rbsog_status rbsog_step(rbsog_ctx *c, int64_t n_steps, double dt) {
     if (n_steps < 0 || !std::isfinite(dt)) return fail(c, RBSOG_E_ARG, "need n_steps >= 0 and finite dt");
     TRY(check_kseq(c, n_steps + (c->forces_valid ? 0 : 1)));
     if (!c->forces_valid) {
+        TRY(refill_if_due(c));
         TRY(enqueue_eval(c, false, 0.0));
         account_eval(c);
     }
@@ -1369,6 +1436,7 @@ rbsog_status rbsog_step(rbsog_ctx *c, int64_t n_steps, double dt) {
     const bool graphs = c->use_graphs && !c->prof_on && n_steps > 1;
     if (graphs) TRY(ensure_step_graphs(c, dt));
     for (int64_t k = 0; k < n_steps; ++k) {
+        TRY(refill_if_due(c));
         if (graphs) HIPCHK(c, hipGraphLaunch(c->graph_exec[c->parity], c->stream));
         else TRY(enqueue_eval(c, true, dt));
         account_eval(c);
@@ -1376,6 +1444,7 @@ rbsog_status rbsog_step(rbsog_ctx *c, int64_t n_steps, double dt) {
     int32_t flag = 0;
     HIPCHK(c, hipMemcpyAsync(&flag, c->flag, sizeof flag, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (flag & 4) return fail(c, RBSOG_E_STATE, "a device chain exceeded its proposal limit (flag %d)", flag);
     if (flag) return fail(c, RBSOG_E_NONFINITE, "non-finite force or energy (flag %d)", flag);
     return RBSOG_OK;
 }
@@ -1478,6 +1547,23 @@ rbsog_status rbsog_get_rho(rbsog_ctx *c, int32_t sys, double *re, double *im) {
     return RBSOG_OK;
 }
 
+rbsog_status rbsog_get_kbatch(rbsog_ctx *c, int32_t sys, int32_t *m_out) {
+    TRY(check_ctx(c));
+    TRY(check_sys(c, sys));
+    if (!m_out) return fail(c, RBSOG_E_ARG, "m_out is null");
+    if (!c->forces_valid) return fail(c, RBSOG_E_STATE, "no force evaluation yet");
+    const SysHost &h = c->sys[sys];
+    std::vector<KRec32> r((size_t)h.P);
+    HIPCHK(c, hipMemcpyAsync(r.data(), c->kb32 + h.k0, r.size() * sizeof(KRec32), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int32_t e = 0; e < h.P; ++e) {
+        m_out[3 * e] = r[e].mx;
+        m_out[3 * e + 1] = r[e].my;
+        m_out[3 * e + 2] = r[e].mz;
+    }
+    return RBSOG_OK;
+}
+
 rbsog_status rbsog_info(rbsog_ctx *c, int32_t sys, rbsog_info_t *info) {
     TRY(check_ctx(c));
     TRY(check_sys(c, sys));
@@ -1486,7 +1572,7 @@ rbsog_status rbsog_info(rbsog_ctx *c, int32_t sys, rbsog_info_t *info) {
     info->S = h.S;
     info->volume = h.V;
     for (int d = 0; d < 3; ++d) info->ncell[d] = h.g.nc[d];
-    info->k_remaining = (int64_t)h.kseq.size() / 3 - h.cursor;
+    info->k_remaining = c->lambda ? (int64_t)c->lambda * h.P - h.cursor : (int64_t)h.kseq.size() / 3 - h.cursor;
     info->evaluations = c->evals;
     info->n = h.n;
     info->n_sys = c->nsys;

@@ -164,6 +164,29 @@ struct EvalArgs {
     int64_t *tstep;        // thermostatted steps taken (noise counter)
 };
 
+// ---- on-device sampler (kernels_sample.hip) ---------------------------------
+// State of one Metropolis-Hastings chain.
+struct ChainState {
+    int32_t m[3];
+    int32_t started;
+    int64_t burn_left;
+    uint64_t attempt;
+    double p, qprop;
+};
+// Per-system constants of the chains.
+struct SampDev {
+    const double *omega, *s;  // split coefficients, G = M + 1 of each
+    int32_t G, P;
+    double L[3], sd[3], a[3];  // box, proposal standard deviation L/(sqrt(2) pi s_0), pi s_0 / L
+    uint64_t seed;
+    int32_t *out;             // lambda batches of P vectors (3 int32 each)
+};
+constexpr int32_t kMaxChains = 4096;
+// advances every chain of every system by P states and resets the cursors;
+// sets bit 4 of *flag if a chain exceeds its attempt limit
+void launch_refill(const SampDev *samp, int32_t nsys, int32_t lambda, ChainState *chains, int64_t *kcur,
+                   int32_t *flag, hipStream_t s);
+
 // ---- kernel launchers (kernels_md.hip) --------------------------------------
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 // kick dt/2 + drift (if a.kick), wrap, quantise, cell histogram; extra blocks

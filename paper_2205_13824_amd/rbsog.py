@@ -31,7 +31,7 @@ EXPORTS = ("rbsog_default_opts", "rbsog_sog_table1", "rbsog_init", "rbsog_init_b
            "rbsog_step", "rbsog_set_velocities", "rbsog_set_positions", "rbsog_get_state", "rbsog_get_forces",
            "rbsog_get_energy", "rbsog_get_rho", "rbsog_info", "rbsog_debug_cells", "rbsog_debug_neighbors",
            "rbsog_profile", "rbsog_profile_read", "rbsog_sync", "rbsog_last_error", "rbsog_status_string",
-           "rbsog_destroy", "rbsog_autotune", "rbsog_set_thermostat")
+           "rbsog_destroy", "rbsog_autotune", "rbsog_set_thermostat", "rbsog_get_kbatch")
 
 
 class RbsogError(RuntimeError):
@@ -47,7 +47,8 @@ class rbsog_sog(ctypes.Structure):
 class rbsog_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("neutral_tol", ctypes.c_double), ("mass", ctypes.c_double), ("graphs", ctypes.c_int32),
-                ("autotune", ctypes.c_int32), ("near_table", ctypes.c_int32), ("zero_mode", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32), ("near_table", ctypes.c_int32), ("zero_mode", ctypes.c_int32),
+                ("device_chains", ctypes.c_int32)]
 
 
 class rbsog_info_t(ctypes.Structure):
@@ -84,6 +85,7 @@ def lib():
             "rbsog_get_forces": (i32, [vp, vp, vp]),
             "rbsog_get_energy": (i32, [vp, vp]),
             "rbsog_get_rho": (i32, [vp, i32, vp, vp]),
+            "rbsog_get_kbatch": (i32, [vp, i32, vp]),
             "rbsog_info": (i32, [vp, i32, P(rbsog_info_t)]),
             "rbsog_debug_cells": (i32, [vp, i32, vp, vp]),
             "rbsog_debug_neighbors": (i32, [vp, i32, vp, vp, i64]),
@@ -130,24 +132,27 @@ def rbsog_default_opts() -> rbsog_opts:
     return o
 
 
-def _opts(precision, device, stream, neutral_tol, mass, graphs, autotune=False, near_table=False, zero_mode=0):
+def _opts(precision, device, stream, neutral_tol, mass, graphs, autotune=False, near_table=False, zero_mode=0,
+          device_chains=0):
     o = rbsog_default_opts()
     o.precision, o.device, o.neutral_tol, o.mass, o.graphs = precision, device, neutral_tol, mass, int(graphs)
     o.autotune = int(autotune)
     o.near_table = int(near_table)
     o.zero_mode = int(zero_mode)
+    o.device_chains = int(device_chains)
     o.stream = stream
     return o
 
 
 def rbsog_init(pos, q, box, sog: rbsog_sog, rc: float, P: int, seed: int, precision: int = RBSOG_FP64,
                device: int = 0, stream: int | None = None, neutral_tol: float = 1e-10, mass: float = 1.0,
-               graphs: bool = True, autotune: bool = False, near_table: bool = False, zero_mode: int = 0):
+               graphs: bool = True, autotune: bool = False, near_table: bool = False, zero_mode: int = 0,
+               device_chains: int = 0):
     q = _f64(q, (-1,))
     n = q.size
     pos = _f64(pos, (n, 3))
     box = _f64(box, (3,))
-    o = _opts(precision, device, stream, neutral_tol, mass, graphs, autotune, near_table, zero_mode)
+    o = _opts(precision, device, stream, neutral_tol, mass, graphs, autotune, near_table, zero_mode, device_chains)
     ctx = ctypes.c_void_p()
     _check(lib().rbsog_init(ctypes.byref(ctx), n, _ptr(pos), _ptr(q), _ptr(box), ctypes.byref(sog), float(rc),
                             int(P), int(seed), ctypes.byref(o)))
@@ -156,7 +161,7 @@ def rbsog_init(pos, q, box, sog: rbsog_sog, rc: float, P: int, seed: int, precis
 
 def rbsog_init_batch(pos_list, q_list, boxes, sogs, rcs, Ps, seeds, precision: int = RBSOG_FP64, device: int = 0,
                      stream: int | None = None, neutral_tol: float = 1e-10, mass: float = 1.0, graphs: bool = True,
-                     autotune: bool = False, near_table: bool = False, zero_mode: int = 0):
+                     autotune: bool = False, near_table: bool = False, zero_mode: int = 0, device_chains: int = 0):
     """One context over len(q_list) systems; particle arrays are concatenated."""
     ns = len(q_list)
     sizes = [int(np.asarray(qq).size) for qq in q_list]
@@ -169,7 +174,7 @@ def rbsog_init_batch(pos_list, q_list, boxes, sogs, rcs, Ps, seeds, precision: i
     rc = _f64(rcs, (ns,))
     Pa = np.ascontiguousarray(np.asarray(Ps, dtype=np.int32).reshape(ns))
     sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64).reshape(ns))
-    o = _opts(precision, device, stream, neutral_tol, mass, graphs, autotune, near_table, zero_mode)
+    o = _opts(precision, device, stream, neutral_tol, mass, graphs, autotune, near_table, zero_mode, device_chains)
     ctx = ctypes.c_void_p()
     _check(lib().rbsog_init_batch(ctypes.byref(ctx), ns, _ptr(offsets), _ptr(pos), _ptr(q), _ptr(box),
                                   ctypes.cast(sog_arr, ctypes.c_void_p), _ptr(rc), _ptr(Pa), _ptr(sd),
@@ -243,6 +248,13 @@ def rbsog_get_rho(ctx, P: int, sys: int = 0):
     im = np.zeros(P)
     _check(lib().rbsog_get_rho(ctx, int(sys), _ptr(re), _ptr(im)), ctx)
     return re, im
+
+
+def rbsog_get_kbatch(ctx, P: int, sys: int = 0):
+    """Wave vectors (P x 3 int32) of the latest evaluation's batch of system sys."""
+    m = np.zeros((P, 3), dtype=np.int32)
+    _check(lib().rbsog_get_kbatch(ctx, int(sys), _ptr(m)), ctx)
+    return m
 
 
 def rbsog_info(ctx, sys: int = 0) -> dict:
@@ -327,6 +339,9 @@ class System:
 
     def components(self):
         return rbsog_get_forces(self.ctx, self.n)
+
+    def kbatch(self):
+        return rbsog_get_kbatch(self.ctx, self.P)
 
     def step(self, n_steps, dt):
         rbsog_step(self.ctx, n_steps, dt)
