@@ -113,7 +113,7 @@ def run_precision(R, torch, wl, prec, args, near_table=False, device_chains=0):
                    for k, v in prof.items() if v[1] > 0}
     E = R.rbsog_get_energy(sysm.ctx)
     info = R.rbsog_info(sysm.ctx)
-    shapes = {k: info[k] for k in ("near_cells_per_item", "rho_chunk", "far_block", "tuned")}
+    shapes = {k: info[k] for k in ("rho_chunk", "far_block", "tuned", "list_capacity", "list_builds")}
     sysm.close()
     return dict(ms=ms, wall=wall, F0=F0, Fn0=Fn0, Ff0=Ff0, E0=E0, E_end=E, kernels=kernels, near_pairs=near_pairs,
                 value=n * args.steps / (ms * 1e-3), shapes=shapes)

@@ -41,10 +41,21 @@
  *   - One context must not be used from two threads at once.  Work is
  *     launched on one HIP stream (the caller's, or one the context owns).
  *   - Fixed-point coordinates: u_d = min(2^32-1, floor(frac(x_d/L_d) 2^32)).
- *     Cells: n_d = floor(L_d/r_c) if >= 3, else 1; c_d = (u_d n_d) >> 32;
- *     cell = c_x + n_x (c_y + n_y c_z); particles ordered by (cell, id).
+ *     Cells: n_d = floor(L_d/(r_c (1 + skin))) if >= 3, else 1;
+ *     c_d = (u_d n_d) >> 32; cell = c_x + n_x (c_y + n_y c_z); particles
+ *     ordered by (cell, id) at each near-list build.
  *     A pair is a neighbour iff (dx*dx + dy*dy) + dz*dz < r_c*r_c in FP64
  *     without contraction, dx = (double)(int32)(u_j,x - u_i,x) * (L_x 2^-32).
+ *   - Near list: a build lists the pairs within r_c (1 + skin) (cell
+ *     stencil, FP32 test widened beyond its rounding); every evaluation
+ *     applies the pair rule above to the listed pairs at the current
+ *     positions.  An evaluation builds first if some particle has moved
+ *     farther than skin r_c / 2 (minimum image of the fixed-point
+ *     difference) since the latest build, or after rbsog_set_positions, so
+ *     the pairs evaluated are exactly the neighbours.  The list holds up to
+ *     twice the largest per-item count seen (grown between calls when a
+ *     build passes 3/4 of it); a build that overflows fails the call with
+ *     E_STATE and poisons the context.
  */
 #ifndef RBSOG_H
 #define RBSOG_H
@@ -116,6 +127,8 @@ typedef struct {
                              Every lambda evaluations one kernel advances all chains by P
                              states.  rbsog_sample_k and rbsog_set_k then return E_STATE.
                              0 (default): the host chain fills the sequence. At most 4096. */
+    double skin;          /* near-list skin as a fraction of r_c, in [0, 1]; default 0.1.
+                             0 builds the list at every evaluation whose positions moved. */
 } rbsog_opts;
 
 /* Fills *o with the defaults above. */
@@ -179,8 +192,9 @@ rbsog_status rbsog_set_k(rbsog_ctx *ctx, int32_t sys, int64_t n_k, const int32_t
                          const double *w);
 
 /* One force evaluation at the current positions with the next P vectors of
- * the sequence (Algorithm 1, step 4): wrap and quantise, cell list, near
- * part, structure factors, far force, energies.
+ * the sequence (Algorithm 1, step 4): wrap and quantise, near-list check
+ * (and build: cell list, re-sort, list), near part, structure factors, far
+ * force, energies.
  *   F_out  NULL, or host n x 3 total force F_N + F*
  *   E_out  NULL, or host 4 * n_sys doubles: U_N, U*, U_self, U of each system
  * E_KSEQ if a system has fewer than P vectors left (nothing is computed). */
@@ -243,29 +257,33 @@ typedef struct {
     int64_t evaluations;
     int64_t n;
     int32_t n_sys;
-    int32_t near_cells_per_item;  /* launch shapes in use (see rbsog_autotune) */
-    int32_t rho_chunk;
+    int32_t rho_chunk;            /* launch shapes in use (see rbsog_autotune) */
     int32_t far_block;
     int32_t tuned;                /* 1 if the shapes come from tuning (now or cached) */
+    int64_t list_capacity;        /* near-list pairs per 64-particle item */
+    int64_t list_builds;          /* near-list builds made by evaluations so far */
+    double skin;                  /* skin in use: the caller's, or 0 while the steps build every time
+                                     (rbsog_step checks every 32 steps: when lists last under two
+                                     steps it builds at every step, with r_c-wide cells and no list,
+                                     and tries the caller's skin again after 4 to 32 checks) */
 } rbsog_info_t;
 rbsog_status rbsog_info(rbsog_ctx *ctx, int32_t sys, rbsog_info_t *info);
 
 /* Tunes the launch shapes of the batch on the data of the latest evaluation:
- * cells per near work item (1..64), particles per structure-factor chunk
- * (256..8192) and particles per far block (64, 128, 256), one phase after the
- * other, each candidate timed over `reps` launches of its kernel with HIP
- * events; the fastest are kept.  Only the near, structure-factor and far
- * kernels run (the sequence is not consumed; forces are recomputed for the
- * same positions).  The choice is cached for the process under (GPU
+ * particles per structure-factor chunk (256..8192) and particles per far
+ * block (64, 128, 256), one phase after the other, each candidate timed over
+ * `reps` launches of its kernel with HIP events; the fastest are kept.  Only
+ * the structure-factor and far kernels run (the sequence is not consumed;
+ * forces are recomputed for the same positions).  The choice is cached for the process under (GPU
  * architecture, precision, batch size, log2 n, P, log2 cells) and, if the
  * environment variable RBSOG_TUNE_CACHE names a file, appended to it; new
  * contexts of the same kind start from the cached shapes.
  * E_STATE before the first evaluation. */
 rbsog_status rbsog_autotune(rbsog_ctx *ctx, int32_t reps);
 
-/* Debug exports of system sys: the latest cell list and a full neighbour
- * list built on the device with the pair rule above (rows ascending i,
- * columns ascending j).  Indices are local to the system (0 .. n_s - 1).
+/* Debug exports of system sys: the cell list of the latest near-list build
+ * and a full neighbour list at the current positions built on the device
+ * with the pair rule above (rows ascending i, columns ascending j).  Indices are local to the system (0 .. n_s - 1).
  *   cell_start  host ncell+1 int32;  order  host n_s int32 (ids by (cell, id))
  *   row_ptr     host n_s+1 int64;  cols  host cap int32
  * rbsog_debug_neighbors returns E_ARG if cap is smaller than the entry count

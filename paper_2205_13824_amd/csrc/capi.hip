@@ -72,15 +72,15 @@ struct ProfEntry {
     int64_t launches = 0;
 };
 
-enum Kid { K_KDQ, K_SCAN, K_SCATTER, K_SORTG, K_NEAR, K_RHO, K_RHORED, K_FAR, K_SAMPLE, K_COUNT };
-const char *kKernelNames[K_COUNT] = {"kick_drift_quantise", "scan_cell_counts", "cell_scatter", "sort_gather",
-                                     "near",                "rho",              "rho_reduce",   "far",
-                                     "sample_refill"};
+constexpr int64_t kAdaptSteps = 32;  // steps between checks of the near-list build rate
+
+enum Kid { K_KDQ, K_BIN, K_SCAN, K_SCATTER, K_SORTG, K_LIST, K_NEAR, K_RHO, K_RHORED, K_FAR, K_SAMPLE, K_COUNT };
+const char *kKernelNames[K_COUNT] = {"kick_drift_quantise", "bin", "scan_cell_counts", "cell_scatter", "sort_gather",
+                                     "list_build", "near", "rho", "rho_reduce", "far", "sample_refill"};
 
 
 // Launch shapes of the work lists (the tunable part of the plan).
 struct Tune {
-    int32_t near_cpi = 0;   // cells per near item
     int32_t rho_chunk = 0;  // particles per structure-factor chunk
     int32_t far_block = 0;  // particles per far item (= block size)
 };
@@ -96,7 +96,7 @@ struct SysHost {
     std::vector<double> omega, s;
     double S = 0, V = 0, uself = 0, w_rb = 0;
     Geom g{};
-    int64_t ncell = 0, c0 = 0;
+    int64_t ncell = 0, ncell_max = 0, c0 = 0;
     int32_t k0 = 0;
     SplitCoef64 co64{};
     SplitCoef32 co32{};
@@ -108,7 +108,7 @@ struct SysHost {
     int32_t zmode = 0;
     double zu = 0.0, zf = 0.0;
     // work lists
-    int32_t it0 = 0, it1 = 0, nch = 0, kt = 1, streams = 1;
+    int32_t it0 = 0, it1 = 0, jt0 = 0, jt1 = 0, nch = 0, kt = 1, streams = 1;
     int64_t pofs = 0, choff = 0;
     // sequence
     MHChain chain;
@@ -139,7 +139,6 @@ struct rbsog_ctx {
     int64_t evals = 0;
     bool poisoned = false;
     std::string err;
-    int parity = 0;  // buf[parity] holds the current cell order
     // stream
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -150,7 +149,20 @@ struct rbsog_ctx {
     StateBufs buf[2] = {};
     uint32_t *u_tmp = nullptr, *u = nullptr;
     int32_t *cell_of = nullptr, *cell_count = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *src = nullptr,
-            *sorted = nullptr, *blocksums = nullptr;
+            *sorted = nullptr, *blocksums = nullptr, *cell_sorted = nullptr;
+    // Verlet list: skin (fraction of r_c), pairs, per-item counts and
+    // capacity, rebuild flag, largest count of the latest build, builds made
+    double skin = 0.1;      // the caller's
+    double skin_cur = 0.1;  // in use: the caller's, or 0 while builds come every step
+    // adaptive skin: steps and builds since the last check, checks left in
+    // the build-every-step mode, and the length of the next such period
+    int64_t adapt_steps = 0, adapt_nb0 = 0;
+    int32_t hold = 0, hold_len = 4;
+    uint2 *pairs = nullptr;
+    int32_t *pcnt = nullptr, *rebuild = nullptr, *pmax = nullptr;
+    int64_t icap = 0;
+    int64_t *nbuild = nullptr;
+    int32_t build_slots = 2;  // candidates per lane and test pass of the build
     double *Fn = nullptr, *Ff = nullptr;
     int64_t *kcur = nullptr;
     KRec64 *kb64 = nullptr;
@@ -167,19 +179,22 @@ struct rbsog_ctx {
     ChainState *chains = nullptr;
     int32_t *flag = nullptr;
     uint32_t *sys_done = nullptr;
-    NearItem *near_items = nullptr;
+    ListItem *list_items = nullptr;
+    NearItem *near_items = nullptr;  // cell runs of the build-every-evaluation mode
+    int32_t n_near = 0;
+    double *epart_cells = nullptr;
     RhoItem *rho_items = nullptr;
     FarItem *far_items = nullptr;
-    int32_t n_near = 0, n_rho = 0, n_far = 0;
+    int32_t n_list = 0, n_rho = 0, n_far = 0;
     // work-list shapes: the current ones, whether they were tuned, and
     // whether tuning runs at the first step
     Tune tune;
     bool tuned = false, autotune = false;
     std::string tune_key;
-    // graphs of one velocity-Verlet step, one per buffer parity
+    // graph of one velocity-Verlet step
     bool use_graphs = true;
-    hipGraph_t graph[2] = {nullptr, nullptr};
-    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
     double graph_dt = 0.0;
     // profiling
     bool prof_on = false;
@@ -391,6 +406,8 @@ SysDev sysdev_of(const SysHost &h) {
     d.uself = h.uself;
     d.it0 = h.it0;
     d.it1 = h.it1;
+    d.jt0 = h.jt0;
+    d.jt1 = h.jt1;
     d.pofs = h.pofs;
     d.nch = h.nch;
     d.kt = h.kt;
@@ -471,8 +488,8 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
     a.sys = c->dsys;
     a.sys_of = c->sys_of;
     a.ksys = c->ksys;
-    a.cur = c->buf[c->parity];
-    a.nxt = c->buf[1 - c->parity];
+    a.cur = c->buf[0];
+    a.nxt = c->buf[1];
     a.u_tmp = c->u_tmp;
     a.u = c->u;
     a.cell_of = c->cell_of;
@@ -482,6 +499,14 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
     a.src = c->src;
     a.sorted = c->sorted;
     a.blocksums = c->blocksums;
+    a.cell_sorted = c->cell_sorted;
+    a.rebuild = c->rebuild;
+    a.pairs = c->skin_cur > 0.0 ? c->pairs : nullptr;
+    a.always_build = c->skin_cur > 0.0 ? 0 : 1;
+    a.pcnt = c->pcnt;
+    a.icap = c->icap;
+    a.pmax = c->pmax;
+    a.nbuild = c->nbuild;
     a.Fn = c->Fn;
     a.Ff = c->Ff;
     a.kcur = c->kcur;
@@ -492,6 +517,7 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
     a.ek = c->ek;
     a.partial = c->partial;
     a.epart = c->epart;
+    a.epart_cells = c->epart_cells;
     a.E = c->E;
     a.dip_part = c->dip_part;
     a.dipole = c->dipole;
@@ -509,17 +535,25 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
 }
 
 // Enqueue one force evaluation (with the velocity-Verlet kick-drift before
-// and the closing kick after it when stepping).  Pure launches: no host state
-// changes, so it can be captured into a graph.
+// and the closing kick after it when stepping).  The list-build kernels run
+// every time and return at once unless the displacement check (or the host)
+// asked for a build.  Pure launches: no host state changes, so it can be
+// captured into a graph.
 rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt) {
     hipStream_t s = c->stream;
     const bool f64 = c->prec == RBSOG_FP64;
     const EvalArgs a = make_args(c, stepping, dt);
     TRY(timed(c, K_KDQ, [&] { launch_kdq(a, s); }));
+    TRY(timed(c, K_BIN, [&] { launch_bin(a, s); }));
     TRY(timed(c, K_SCAN, [&] { launch_scan(a, s); }));
     TRY(timed(c, K_SCATTER, [&] { launch_cell_scatter(a, s); }));
     TRY(timed(c, K_SORTG, [&] { launch_sort_gather(a, s); }));
-    TRY(timed(c, K_NEAR, [&] { launch_near(a, f64, c->near_items, c->n_near, s); }));
+    if (a.always_build) {
+        TRY(timed(c, K_NEAR, [&] { launch_near_cells(a, f64, c->near_items, c->n_near, s); }));
+    } else {
+        TRY(timed(c, K_LIST, [&] { launch_list_build(a, f64, c->list_items, c->n_list, c->build_slots, s); }));
+        TRY(timed(c, K_NEAR, [&] { launch_near(a, f64, c->list_items, c->n_list, s); }));
+    }
     TRY(timed(c, K_RHO, [&] { launch_rho(a, f64, c->rho_items, c->n_rho, s); }));
     TRY(timed(c, K_RHORED, [&] { launch_rho_reduce(a, s); }));
     TRY(timed(c, K_FAR, [&] { launch_far(a, f64, c->far_items, c->n_far, c->tune.far_block, s); }));
@@ -545,50 +579,133 @@ void account_eval(rbsog_ctx *c) {
     for (auto &h : c->sys) h.cursor += h.P;
     c->evals += 1;
     c->forces_valid = true;
-    c->parity = 1 - c->parity;
 }
 
 void drop_graphs(rbsog_ctx *c) {
-    for (int p = 0; p < 2; ++p) {
-        if (c->graph_exec[p]) (void)hipGraphExecDestroy(c->graph_exec[p]);
-        if (c->graph[p]) (void)hipGraphDestroy(c->graph[p]);
-        c->graph_exec[p] = nullptr;
-        c->graph[p] = nullptr;
-    }
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
 }
 
-// The graph of one step captures the kernel arguments: one graph per buffer
-// parity, rebuilt when dt changes.  Sequence buffers are reached through the
-// per-system table, so re-sampling does not invalidate them.
+// The graph of one step captures the kernel arguments; it is rebuilt when dt
+// or a buffer changes.  Sequence buffers are reached through the per-system
+// table, so re-sampling does not invalidate it.
 rbsog_status ensure_step_graphs(rbsog_ctx *c, double dt) {
-    if (c->graph_exec[0] && c->graph_exec[1] && c->graph_dt == dt) return RBSOG_OK;
+    if (c->graph_exec && c->graph_dt == dt) return RBSOG_OK;
     drop_graphs(c);
-    const int keep = c->parity;
-    for (int p = 0; p < 2; ++p) {
-        c->parity = p;
-        HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
-        rbsog_status st = enqueue_eval(c, true, dt);
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(c->stream, &g);
-        c->parity = keep;
-        if (st != RBSOG_OK) {
-            if (g) (void)hipGraphDestroy(g);
-            drop_graphs(c);
-            return st;
-        }
-        if (e != hipSuccess) {
-            drop_graphs(c);
-            return fail(c, RBSOG_E_DEVICE, "stream capture: %s", hipGetErrorString(e));
-        }
-        c->graph[p] = g;
-        e = hipGraphInstantiate(&c->graph_exec[p], g, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            drop_graphs(c);
-            return fail(c, RBSOG_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
-        }
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+    rbsog_status st = enqueue_eval(c, true, dt);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (st != RBSOG_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
     }
-    c->parity = keep;
+    if (e != hipSuccess) return fail(c, RBSOG_E_DEVICE, "stream capture: %s", hipGetErrorString(e));
+    c->graph = g;
+    e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        drop_graphs(c);
+        return fail(c, RBSOG_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+    }
     c->graph_dt = dt;
+    return RBSOG_OK;
+}
+
+rbsog_status request_build(rbsog_ctx *c);
+rbsog_status upload_cell_items(rbsog_ctx *c);
+int32_t build_slots_for(const rbsog_ctx *c);
+void set_geometry(SysHost &h, double skin);
+
+// Installs the cell grid and list thresholds of a skin on every system (the
+// next evaluation builds).
+rbsog_status apply_skin(rbsog_ctx *c, double skin) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (SysHost &h : c->sys) set_geometry(h, skin);
+    for (int32_t s = 0; s < c->nsys; ++s) TRY(upload_sysdev(c, s));
+    c->skin_cur = skin;
+    c->build_slots = build_slots_for(c);
+    TRY(upload_cell_items(c));
+    drop_graphs(c);
+    return request_build(c);
+}
+
+// Adaptive skin, checked every kAdaptSteps steps: when lists last less than
+// two steps (particles far faster than the skin allows for, as when
+// oppositely charged ions without a repulsive core fall onto each other),
+// keeping a list costs more than it saves, so the steps build every time at
+// skin 0 (cells r_c wide, no list written); after a hold of a few checks the
+// caller's skin is tried again, and the hold doubles (up to 32 checks) each
+// time that try fails.  The pairs evaluated are the same in either mode.
+rbsog_status adapt_skin(rbsog_ctx *c) {
+    c->adapt_steps = 0;
+    if (!(c->skin > 0.0)) return RBSOG_OK;
+    int64_t nb = 0;
+    HIPCHK(c, hipMemcpyAsync(&nb, c->nbuild, sizeof nb, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int64_t builds = nb - c->adapt_nb0;
+    c->adapt_nb0 = nb;
+    const bool busy = 2 * builds >= kAdaptSteps;
+    if (c->skin_cur > 0.0) {
+        if (busy) {
+            c->hold = c->hold_len;
+            c->hold_len = std::min(2 * c->hold_len, 32);
+            TRY(apply_skin(c, 0.0));
+        } else {
+            c->hold_len = 4;
+        }
+    } else if (--c->hold <= 0) {
+        TRY(apply_skin(c, c->skin));
+    }
+    return RBSOG_OK;
+}
+
+// Asks for a list build at the next evaluation (positions set from the host,
+// a larger list, or a new cell grid).
+rbsog_status request_build(rbsog_ctx *c) {
+    const int32_t one = 1;
+    HIPCHK(c, hipMemcpyAsync(c->rebuild, &one, sizeof one, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RBSOG_OK;
+}
+
+// Capacity of the pair list: every item holds kListWaves segments (one per
+// quarter of its homes) of icap / kListWaves pairs.  Sized from the largest
+// segment count of a build with room to spare; a build whose largest count
+// passes 3/4 of the capacity makes the next call grow it (and build again),
+// and one that overflows fails the call.
+rbsog_status size_list(rbsog_ctx *c, int64_t largest) {
+    const int64_t want = kListWaves * ((2 * std::max<int64_t>(largest, 64) + 63) / 64 * 64);
+    if (c->pairs && want <= c->icap) return RBSOG_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    uint2 *np = nullptr;
+    if (hipMalloc((void **)&np, (size_t)c->n_list * (size_t)want * sizeof(uint2)) != hipSuccess)
+        return fail(c, RBSOG_E_OOM, "pair list of %lld x %lld entries", (long long)c->n_list, (long long)want);
+    if (c->pairs) {
+        c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), (void *)c->pairs), c->allocs.end());
+        (void)hipFree(c->pairs);
+    }
+    c->pairs = np;
+    c->allocs.push_back(np);
+    c->icap = want;
+    // no item of the new buffer holds pairs until the next build
+    HIPCHK(c, hipMemset(c->pcnt, 0, (size_t)kListWaves * c->n_list * sizeof(int32_t)));
+    drop_graphs(c);
+    return request_build(c);
+}
+
+// After a call's evaluations: overflow fails it (the forces after it were
+// incomplete); a list close to full is grown for the next call.
+rbsog_status check_list(rbsog_ctx *c, int32_t flag) {
+    if (flag & 8) {
+        c->poisoned = true;
+        return fail(c, RBSOG_E_STATE, "a near-list segment exceeded its capacity of %lld pairs",
+                    (long long)(c->icap / kListWaves));
+    }
+    int32_t pm = 0;
+    HIPCHK(c, hipMemcpy(&pm, c->pmax, sizeof pm, hipMemcpyDeviceToHost));
+    if (4 * (int64_t)pm > 3 * (c->icap / kListWaves)) TRY(size_list(c, pm));
     return RBSOG_OK;
 }
 
@@ -607,7 +724,7 @@ rbsog_status check_sys(rbsog_ctx *c, int32_t s) {
 // ids of the current cell order (slot -> caller index)
 rbsog_status current_ids(rbsog_ctx *c, std::vector<int32_t> &id) {
     id.resize((size_t)c->N);
-    HIPCHK(c, hipMemcpyAsync(id.data(), c->buf[c->parity].id, (size_t)c->N * sizeof(int32_t), hipMemcpyDeviceToHost,
+    HIPCHK(c, hipMemcpyAsync(id.data(), c->buf[0].id, (size_t)c->N * sizeof(int32_t), hipMemcpyDeviceToHost,
                              c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return RBSOG_OK;
@@ -685,10 +802,33 @@ void build_split(SysHost &h, int nexp64, int nexp32) {
     }
 }
 
+// Cell grid and near-list thresholds of one system for a skin.  skin > 0:
+// the list holds the pairs within r_l = r_c (1 + skin) at the build and stays
+// valid while no particle has moved farther than skin r_c / 2 (cells at least
+// r_l wide hold every pair of the list).  The FP32 list test is widened and
+// the FP32 displacement test narrowed by far more than their rounding (2e-5
+// relative), so the list holds every pair the exact rule can accept before
+// the check asks for a build.  skin = 0: every evaluation builds (the
+// displacement threshold is negative) and no list is kept.
+void set_geometry(SysHost &h, double skin) {
+    Geom &g = h.g;
+    for (int d = 0; d < 3; ++d) {
+        const int64_t k = (int64_t)std::floor(h.box[d] / (h.rc * (1.0 + skin)));
+        g.nc[d] = (int32_t)(k >= 3 ? k : 1);
+        g.reach[d] = g.nc[d] >= 3 ? 1 : 0;
+    }
+    const double rl = h.rc * (1.0 + skin);
+    g.rl2_f = (float)(rl * rl * (1.0 + 1e-4) + 1e-30);
+    const double dmax = 0.5 * skin * h.rc;
+    g.dthr2_f = skin > 0.0 ? (float)(dmax * dmax * (1.0 - 1e-4)) : -1.0f;
+    h.ncell = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
+}
+
 // Validates one system and fills its host record (everything but offsets
 // and work lists).
 rbsog_status setup_system(SysHost &h, int64_t n, const double *pos, const double *q, const double *box,
-                          const rbsog_sog *sog, double rc, int32_t P, uint64_t seed, double neutral_tol, int32_t idx) {
+                          const rbsog_sog *sog, double rc, int32_t P, uint64_t seed, double neutral_tol, double skin,
+                          int32_t idx) {
     if (n < 2) return fail(nullptr, RBSOG_E_ARG, "system %d: n must be >= 2", idx);
     if (P < 1) return fail(nullptr, RBSOG_E_ARG, "system %d: P must be >= 1", idx);
     for (int d = 0; d < 3; ++d)
@@ -737,9 +877,6 @@ rbsog_status setup_system(SysHost &h, int64_t n, const double *pos, const double
         g.h[d] = box[d] / kTwo32;
         g.hf[d] = (float)g.h[d];
         hmax = std::max(hmax, g.h[d]);
-        const int64_t k = (int64_t)std::floor(box[d] / rc);
-        g.nc[d] = (int32_t)(k >= 3 ? k : 1);
-        g.reach[d] = g.nc[d] >= 3 ? 1 : 0;
     }
     g.rc2 = rc * rc;
     const double d64 = 32.0 * hmax / rc + 1e-12;
@@ -750,6 +887,14 @@ rbsog_status setup_system(SysHost &h, int64_t n, const double *pos, const double
     g.band_hi = g.rc2 * (1.0 + d64);
     g.band_lo_f = (float)(g.rc2 * (1.0 - d32));
     g.band_hi_f = (float)(g.rc2 * (1.0 + d32));
+    // cells are allocated for the finest grid (skin 0); the grid in use is a
+    // prefix of that range
+    h.ncell_max = 1;
+    for (int d = 0; d < 3; ++d) {
+        const int64_t k = (int64_t)std::floor(box[d] / rc);
+        h.ncell_max *= k >= 3 ? k : 1;
+    }
+    set_geometry(h, skin);
     // Gaussians wide enough that exp(-x/s_l^2) is a short Taylor series over
     // x = r^2 <= rc^2 form the tail; s_l grows with l, so they are l >= nexp.
     auto first_wide = [&](double tau) {
@@ -762,7 +907,6 @@ rbsog_status setup_system(SysHost &h, int64_t n, const double *pos, const double
         return fail(nullptr, RBSOG_E_SOG, "system %d: more than %d Gaussians narrower than r_c / sqrt(%g)", idx,
                     kMaxExp, kTailTau64);
     build_split(h, nexp64, nexp32);
-    h.ncell = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
     return RBSOG_OK;
 }
 
@@ -857,10 +1001,9 @@ void tune_cache_load_locked() {
     FILE *f = std::fopen(path, "r");
     if (!f) return;
     char key[256];
-    int a, b, d;
-    while (std::fscanf(f, "%255s %d %d %d", key, &a, &b, &d) == 4) {
+    int b, d;
+    while (std::fscanf(f, "%255s %d %d", key, &b, &d) == 3) {
         Tune t;
-        t.near_cpi = a;
         t.rho_chunk = b;
         t.far_block = d;
         g_tune_cache[key] = t;
@@ -884,23 +1027,23 @@ void tune_cache_store(const std::string &key, const Tune &t) {
     const char *path = std::getenv("RBSOG_TUNE_CACHE");
     if (!path || !*path) return;
     if (FILE *f = std::fopen(path, "a")) {
-        std::fprintf(f, "%s %d %d %d\n", key.c_str(), t.near_cpi, t.rho_chunk, t.far_block);
+        std::fprintf(f, "%s %d %d\n", key.c_str(), t.rho_chunk, t.far_block);
         std::fclose(f);
     }
 }
 
-// Work lists of the batch.  Near: runs of t.near_cpi cells of one system;
+// Work lists of the batch.  Near: runs of kListHomes slots of one system;
 // rho: particle chunks of about t.rho_chunk slots x k-tile groups; far: runs
 // of t.far_block slots.
-void build_work(rbsog_ctx *c, const Tune &t, std::vector<NearItem> &near, std::vector<RhoItem> &rho,
+void build_work(rbsog_ctx *c, const Tune &t, std::vector<ListItem> &near, std::vector<RhoItem> &rho,
                 std::vector<FarItem> &far) {
-    const int64_t cpi = t.near_cpi, chunk = t.rho_chunk, fb = t.far_block;
+    const int64_t chunk = t.rho_chunk, fb = t.far_block;
     int64_t pofs = 0, choff = 0;
     for (int32_t s = 0; s < c->nsys; ++s) {
         SysHost &h = c->sys[s];
         h.it0 = (int32_t)near.size();
-        for (int64_t cb = 0; cb < h.ncell; cb += cpi)
-            near.push_back(NearItem{s, 0, h.c0 + cb, h.c0 + std::min(h.ncell, cb + cpi)});
+        for (int64_t i = 0; i < h.n; i += kListHomes)
+            near.push_back(ListItem{s, 0, h.p0 + i, h.p0 + std::min<int64_t>(h.n, i + kListHomes)});
         h.it1 = (int32_t)near.size();
         const int32_t ktiles = (h.P + 63) / 64;
         h.kt = std::min(ktiles, 16);
@@ -922,24 +1065,22 @@ void build_work(rbsog_ctx *c, const Tune &t, std::vector<NearItem> &near, std::v
     }
 }
 
-// Default shapes: about 8192 near items (one per wave), 512 structure-factor
-// chunks and 256-particle far blocks over the batch.
+// Default shapes: 512 structure-factor chunks and 256-particle far blocks
+// over the batch.
 Tune default_tune(const rbsog_ctx *c) {
     Tune t;
-    t.near_cpi = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, (c->C + 8191) / 8192));
     t.rho_chunk = (int32_t)std::max<int64_t>(256, (c->N + 511) / 512);
     t.far_block = 256;
     return t;
 }
 
 // Capacities of the work lists and partial buffers: the largest any shape
-// below may need (1 cell per near item, 256-particle chunks, 64-particle
-// far items).
+// below may need (256-particle chunks, 64-particle far items).
 void work_caps(const rbsog_ctx *c, int64_t &near_cap, int64_t &rho_cap, int64_t &far_cap, int64_t &part_cap,
                int64_t &chunk_cap) {
-    near_cap = c->C;
-    rho_cap = far_cap = part_cap = chunk_cap = 0;
+    near_cap = rho_cap = far_cap = part_cap = chunk_cap = 0;
     for (const SysHost &h : c->sys) {
+        near_cap += (h.n + kListHomes - 1) / kListHomes;
         const int64_t ktiles = (h.P + 63) / 64, kt = std::min<int64_t>(ktiles, 16);
         const int64_t nch = std::max<int64_t>(1, (h.n + 255) / 256);
         rho_cap += ((ktiles + kt - 1) / kt) * nch;
@@ -950,22 +1091,21 @@ void work_caps(const rbsog_ctx *c, int64_t &near_cap, int64_t &rho_cap, int64_t 
 }
 
 bool valid_tune(const Tune &t) {
-    return t.near_cpi >= 1 && t.near_cpi <= 1024 && t.rho_chunk >= 256 && (t.far_block == 64 || t.far_block == 128 ||
-                                                                         t.far_block == 256);
+    return t.rho_chunk >= 256 && (t.far_block == 64 || t.far_block == 128 || t.far_block == 256);
 }
 
 // Installs a set of shapes: builds and uploads the work lists and the
 // per-system table; captured graphs are dropped (their launch sizes change).
 rbsog_status apply_tune(rbsog_ctx *c, const Tune &t) {
-    std::vector<NearItem> near;
+    std::vector<ListItem> near;
     std::vector<RhoItem> rho;
     std::vector<FarItem> far;
     build_work(c, t, near, rho, far);
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, hipMemcpy(c->near_items, near.data(), near.size() * sizeof(NearItem), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->list_items, near.data(), near.size() * sizeof(ListItem), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->rho_items, rho.data(), rho.size() * sizeof(RhoItem), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->far_items, far.data(), far.size() * sizeof(FarItem), hipMemcpyHostToDevice));
-    c->n_near = (int32_t)near.size();
+    c->n_list = (int32_t)near.size();
     c->n_rho = (int32_t)rho.size();
     c->n_far = (int32_t)far.size();
     for (int32_t s = 0; s < c->nsys; ++s) TRY(upload_sysdev(c, s));
@@ -974,23 +1114,43 @@ rbsog_status apply_tune(rbsog_ctx *c, const Tune &t) {
     return RBSOG_OK;
 }
 
+// Near items of the build-every-evaluation mode: runs of about C / 8192
+// cells (1..64) of the grid in use, one per wave; per-system ranges in the
+// system table.
+rbsog_status upload_cell_items(rbsog_ctx *c) {
+    int64_t ctot = 0;
+    for (const SysHost &h : c->sys) ctot += h.ncell;
+    const int64_t cpi = std::max<int64_t>(1, std::min<int64_t>(64, (ctot + 8191) / 8192));
+    std::vector<NearItem> items;
+    for (int32_t s = 0; s < c->nsys; ++s) {
+        SysHost &h = c->sys[s];
+        h.jt0 = (int32_t)items.size();
+        for (int64_t cb = 0; cb < h.ncell; cb += cpi)
+            items.push_back(NearItem{s, 0, h.c0 + cb, h.c0 + std::min(h.ncell, cb + cpi)});
+        h.jt1 = (int32_t)items.size();
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->near_items, items.data(), items.size() * sizeof(NearItem), hipMemcpyHostToDevice));
+    c->n_near = (int32_t)items.size();
+    for (int32_t s = 0; s < c->nsys; ++s) TRY(upload_sysdev(c, s));
+    return RBSOG_OK;
+}
+
 // Times each phase's candidate shapes on the latest evaluation's data (the
-// near, structure-factor and far kernels only: no cursor moves, no state
-// changes beyond recomputing the same forces) and keeps the fastest.
+// structure-factor and far kernels only: no cursor moves, no state changes
+// beyond recomputing the same forces) and keeps the fastest.
 rbsog_status autotune_now(rbsog_ctx *c, int32_t reps) {
-    if (c->evals == 0) return fail(c, RBSOG_E_STATE, "autotuning needs one force evaluation first");
+    if (c->evals == 0 || !c->forces_valid)
+        return fail(c, RBSOG_E_STATE, "autotuning needs the forces of the current positions first");
     if (reps < 1) reps = 1;
     const bool f64 = c->prec == RBSOG_FP64;
-    // the kernels after the re-sort read the `nxt` buffers: those of the latest order
-    c->parity = 1 - c->parity;
-    const EvalArgs a = make_args(c, false, 0.0);
-    c->parity = 1 - c->parity;
+    EvalArgs a = make_args(c, false, 0.0);
+    a.rebuild = nullptr;  // the far kernel leaves the near-list flag alone
     hipEvent_t e0 = get_event(c), e1 = get_event(c);
     if (!e0 || !e1) return fail(c, RBSOG_E_DEVICE, "hipEventCreate failed");
     auto time_of = [&](int phase, double &ms) -> rbsog_status {
         auto launch = [&] {
-            if (phase == 0) launch_near(a, f64, c->near_items, c->n_near, c->stream);
-            else if (phase == 1) launch_rho(a, f64, c->rho_items, c->n_rho, c->stream);
+            if (phase == 1) launch_rho(a, f64, c->rho_items, c->n_rho, c->stream);
             else launch_far(a, f64, c->far_items, c->n_far, c->tune.far_block, c->stream);
         };
         launch();
@@ -1008,17 +1168,16 @@ rbsog_status autotune_now(rbsog_ctx *c, int32_t reps) {
     const Tune dflt = default_tune(c);
     int64_t nmax = 0;
     for (const SysHost &h : c->sys) nmax = std::max(nmax, h.n);
-    std::vector<int32_t> cpis = {1, 2, 4, 8, 16, 32, 64, dflt.near_cpi};
     std::vector<int32_t> chunks = {256, 512, 1024, 2048, 4096, 8192, dflt.rho_chunk};
     std::vector<int32_t> blocks = {64, 128, 256};
-    for (int phase = 0; phase < 3; ++phase) {
-        const std::vector<int32_t> &cand = phase == 0 ? cpis : phase == 1 ? chunks : blocks;
+    for (int phase = 1; phase < 3; ++phase) {
+        const std::vector<int32_t> &cand = phase == 1 ? chunks : blocks;
         double best_ms = 1e30;
-        int32_t best_v = phase == 0 ? best.near_cpi : phase == 1 ? best.rho_chunk : best.far_block;
+        int32_t best_v = phase == 1 ? best.rho_chunk : best.far_block;
         for (int32_t v : cand) {
             if (phase == 1 && v > std::max<int64_t>(256, nmax)) continue;
             Tune t = best;
-            (phase == 0 ? t.near_cpi : phase == 1 ? t.rho_chunk : t.far_block) = v;
+            (phase == 1 ? t.rho_chunk : t.far_block) = v;
             TRY(apply_tune(c, t));
             double ms = 0.0;
             TRY(time_of(phase, ms));
@@ -1027,14 +1186,13 @@ rbsog_status autotune_now(rbsog_ctx *c, int32_t reps) {
                 best_v = v;
             }
         }
-        (phase == 0 ? best.near_cpi : phase == 1 ? best.rho_chunk : best.far_block) = best_v;
+        (phase == 1 ? best.rho_chunk : best.far_block) = best_v;
     }
     c->ev_pool.push_back(e0);
     c->ev_pool.push_back(e1);
     TRY(apply_tune(c, best));
     // the last trial's far pass left the forces of another shape: recompute
     // them with the chosen shapes (same data, same arithmetic per particle)
-    launch_near(a, f64, c->near_items, c->n_near, c->stream);
     launch_far(a, f64, c->far_items, c->n_far, c->tune.far_block, c->stream);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->tuned = true;
@@ -1079,6 +1237,67 @@ rbsog_status setup_device_chains(rbsog_ctx *c, int32_t lambda) {
     return RBSOG_OK;
 }
 
+// Candidate slots per lane and test pass of the build (2, 3 or 4: passes of
+// 128, 192 or 256 candidates): the choice with the fewest slots tested per
+// home cell, the candidate count of a cell taken as normal with the mean
+// stencil occupancy of the densest system and its square root as spread.
+int32_t build_slots_for(const rbsog_ctx *c) {
+    double cand = 0.0;
+    for (const SysHost &h : c->sys) {
+        const double reach = (h.g.reach[0] ? 3.0 : 1.0) * (h.g.reach[1] ? 3.0 : 1.0) * (h.g.reach[2] ? 3.0 : 1.0);
+        cand = std::max(cand, reach * (double)h.n / (double)h.ncell);
+    }
+    const double sd = std::sqrt(std::max(cand, 1.0));
+    int32_t best = 2;
+    double best_cost = 1e300;
+    for (int32_t S = 2; S <= 4; ++S) {
+        const double pass = 64.0 * S;
+        double cost = 0.0, wsum = 0.0;
+        for (int k = -40; k <= 40; ++k) {
+            const double x = 0.1 * k, w = std::exp(-0.5 * x * x);
+            const double cnt = std::max(1.0, cand + x * sd);
+            cost += w * pass * std::ceil(cnt / pass);
+            wsum += w;
+        }
+        cost /= wsum;
+        if (cost < best_cost - 1e-9) {
+            best_cost = cost;
+            best = S;
+        }
+    }
+    return best;
+}
+
+// A list build that only counts, at the initial positions: its largest item
+// count sizes the pair list.  It also puts the state in cell order; the
+// first evaluation builds the list itself.
+rbsog_status first_build(rbsog_ctx *c) {
+    TRY(upload_cell_items(c));
+    const int32_t one = 1, zero = 0;
+    const int64_t zero64 = 0;
+    HIPCHK(c, hipMemcpy(c->rebuild, &one, sizeof one, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->pmax, &zero, sizeof zero, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->nbuild, &zero64, sizeof zero64, hipMemcpyHostToDevice));
+    if (!(c->skin_cur > 0.0)) return RBSOG_OK;  // no list is kept at skin 0
+    EvalArgs a = make_args(c, false, 0.0);
+    a.K = 0;
+    a.pairs = nullptr;
+    a.icap = 0;
+    hipStream_t s = c->stream;
+    launch_kdq(a, s);
+    launch_bin(a, s);
+    launch_scan(a, s);
+    launch_cell_scatter(a, s);
+    launch_sort_gather(a, s);
+    launch_list_build(a, c->prec == RBSOG_FP64, c->list_items, c->n_list, c->build_slots, s);
+    HIPCHK(c, hipGetLastError());
+    int32_t pm = 0;
+    HIPCHK(c, hipMemcpyAsync(&pm, c->pmax, sizeof pm, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    HIPCHK(c, hipMemcpy(c->nbuild, &zero64, sizeof zero64, hipMemcpyHostToDevice));
+    return size_list(c, pm);
+}
+
 rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, const double *pos, const double *q,
                         const double *boxes, const rbsog_sog *sog, const double *rc, const int32_t *P,
                         const uint64_t *seeds, const rbsog_opts *opts) {
@@ -1103,6 +1322,7 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
         return fail(nullptr, RBSOG_E_ARG, "device_chains must be in [0, %d]", kMaxChains);
     if (!(o.mass > 0.0) || !std::isfinite(o.mass)) return fail(nullptr, RBSOG_E_ARG, "mass must be > 0");
     if (!(o.neutral_tol >= 0.0)) return fail(nullptr, RBSOG_E_ARG, "neutral_tol must be >= 0");
+    if (!(o.skin >= 0.0 && o.skin <= 1.0)) return fail(nullptr, RBSOG_E_ARG, "skin must be in [0, 1]");
 
     rbsog_ctx *c = new rbsog_ctx();
     c->nsys = nsys;
@@ -1111,12 +1331,14 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     c->device = o.device;
     c->mass = o.mass;
     c->use_graphs = o.graphs != 0;
+    c->skin = o.skin;
+    c->skin_cur = o.skin;
     for (int k = 0; k < K_COUNT; ++k) c->prof[k].name = kKernelNames[k];
     for (int32_t s = 0; s < nsys; ++s) {
         SysHost &h = c->sys[s];
         const int64_t p0 = offsets[s], n = offsets[s + 1] - offsets[s];
         rbsog_status st = setup_system(h, n, pos + 3 * p0, q + p0, boxes + 3 * s, sog + s, rc[s], P[s], seeds[s],
-                                       o.neutral_tol, s);
+                                       o.neutral_tol, o.skin, s);
         if (st != RBSOG_OK) {
             delete c;
             return st;
@@ -1133,7 +1355,7 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
             h.zu = 2.0 * kPi / h.V;
             h.zf = -4.0 * kPi / h.V;
         }
-        c->C += h.ncell;
+        c->C += h.ncell_max;
         if (c->C >= (int64_t)INT32_MAX || (int64_t)c->K + P[s] >= (int64_t)INT32_MAX) {
             delete c;
             return fail(nullptr, RBSOG_E_ARG, "too many cells or wave vectors");
@@ -1142,6 +1364,7 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     }
     c->N = offsets[nsys];
     c->q_host.assign(q, q + c->N);
+    c->build_slots = build_slots_for(c);
     std::vector<std::vector<float4>> tables;
     if (o.near_table) {
         tables.resize(nsys);
@@ -1226,7 +1449,14 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
             c->sys[s].tbl = dtab + (int64_t)s * kTabSize;
         }
     }
-    ALLOC(near_items, near_cap);
+    ALLOC(list_items, near_cap);
+    ALLOC(near_items, C);
+    ALLOC(epart_cells, C);
+    ALLOC(pcnt, kListWaves * near_cap);
+    ALLOC(cell_sorted, N);
+    ALLOC(rebuild, 1);
+    ALLOC(pmax, 1);
+    ALLOC(nbuild, 1);
     ALLOC(rho_items, rho_cap);
     ALLOC(far_items, far_cap);
 #undef ALLOC
@@ -1286,6 +1516,7 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
         else t = default_tune(c);
         if ((st = apply_tune(c, t)) != RBSOG_OK) return bail(st);
     }
+    if ((st = first_build(c)) != RBSOG_OK) return bail(st);
     *out = c;
     return RBSOG_OK;
 }
@@ -1307,6 +1538,7 @@ void rbsog_default_opts(rbsog_opts *o) {
     o->near_table = 0;
     o->zero_mode = 0;
     o->device_chains = 0;
+    o->skin = 0.1;
 }
 
 rbsog_status rbsog_sog_table1(int32_t row, double rc, rbsog_sog *out) {
@@ -1410,6 +1642,12 @@ rbsog_status rbsog_forces(rbsog_ctx *c, double *F_out, double *E_out) {
     TRY(refill_if_due(c));
     TRY(enqueue_eval(c, false, 0.0));
     account_eval(c);
+    {
+        int32_t flag = 0;
+        HIPCHK(c, hipMemcpyAsync(&flag, c->flag, sizeof flag, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        TRY(check_list(c, flag));
+    }
     if (F_out) {
         std::vector<double> b((size_t)3 * c->N);
         TRY(download_by_id(c, c->Fn, F_out));
@@ -1434,16 +1672,24 @@ rbsog_status rbsog_step(rbsog_ctx *c, int64_t n_steps, double dt) {
     }
     if (c->autotune && !c->tuned && !c->prof_on) TRY(autotune_now(c, 5));
     const bool graphs = c->use_graphs && !c->prof_on && n_steps > 1;
-    if (graphs) TRY(ensure_step_graphs(c, dt));
-    for (int64_t k = 0; k < n_steps; ++k) {
-        TRY(refill_if_due(c));
-        if (graphs) HIPCHK(c, hipGraphLaunch(c->graph_exec[c->parity], c->stream));
-        else TRY(enqueue_eval(c, true, dt));
-        account_eval(c);
+    for (int64_t k = 0; k < n_steps;) {
+        // up to the next check of the build rate
+        const int64_t chunk = std::min<int64_t>(n_steps - k, kAdaptSteps - c->adapt_steps);
+        if (graphs) TRY(ensure_step_graphs(c, dt));
+        for (int64_t i = 0; i < chunk; ++i) {
+            TRY(refill_if_due(c));
+            if (graphs) HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+            else TRY(enqueue_eval(c, true, dt));
+            account_eval(c);
+        }
+        k += chunk;
+        c->adapt_steps += chunk;
+        if (c->adapt_steps >= kAdaptSteps) TRY(adapt_skin(c));
     }
     int32_t flag = 0;
     HIPCHK(c, hipMemcpyAsync(&flag, c->flag, sizeof flag, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    TRY(check_list(c, flag));
     if (flag & 4) return fail(c, RBSOG_E_STATE, "a device chain exceeded its proposal limit (flag %d)", flag);
     if (flag) return fail(c, RBSOG_E_NONFINITE, "non-finite force or energy (flag %d)", flag);
     return RBSOG_OK;
@@ -1453,7 +1699,7 @@ rbsog_status rbsog_set_velocities(rbsog_ctx *c, const double *v, double T, uint6
     TRY(check_ctx(c));
     if (v) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        return upload_by_id(c, v, c->buf[c->parity].v, "velocity");
+        return upload_by_id(c, v, c->buf[0].v, "velocity");
     }
     if (!(T >= 0.0) || !std::isfinite(T)) return fail(c, RBSOG_E_ARG, "temperature must be >= 0");
     const double sd = std::sqrt(T / c->mass);
@@ -1477,7 +1723,7 @@ rbsog_status rbsog_set_velocities(rbsog_ctx *c, const double *v, double T, uint6
         }
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    return upload_by_id(c, vv.data(), c->buf[c->parity].v, "velocity");
+    return upload_by_id(c, vv.data(), c->buf[0].v, "velocity");
 }
 
 rbsog_status rbsog_set_thermostat(rbsog_ctx *c, double gamma, double T, uint64_t seed) {
@@ -1498,15 +1744,15 @@ rbsog_status rbsog_set_positions(rbsog_ctx *c, const double *pos) {
     TRY(check_ctx(c));
     if (!pos) return fail(c, RBSOG_E_ARG, "pos is null");
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    TRY(upload_by_id(c, pos, c->buf[c->parity].x, "position"));
+    TRY(upload_by_id(c, pos, c->buf[0].x, "position"));
     c->forces_valid = false;
-    return RBSOG_OK;
+    return request_build(c);
 }
 
 rbsog_status rbsog_get_state(rbsog_ctx *c, double *pos, double *vel) {
     TRY(check_ctx(c));
     if (pos) {
-        TRY(download_by_id(c, c->buf[c->parity].x, pos));
+        TRY(download_by_id(c, c->buf[0].x, pos));
         // the stored coordinates are wrapped at each evaluation; wrap here too
         for (const SysHost &h : c->sys)
             for (int64_t i = h.p0; i < h.p0 + h.n; ++i)
@@ -1515,7 +1761,7 @@ rbsog_status rbsog_get_state(rbsog_ctx *c, double *pos, double *vel) {
                     pos[3 * i + d] = (t - std::floor(t)) * h.box[d];
                 }
     }
-    if (vel) TRY(download_by_id(c, c->buf[c->parity].v, vel));
+    if (vel) TRY(download_by_id(c, c->buf[0].v, vel));
     return RBSOG_OK;
 }
 
@@ -1576,7 +1822,10 @@ rbsog_status rbsog_info(rbsog_ctx *c, int32_t sys, rbsog_info_t *info) {
     info->evaluations = c->evals;
     info->n = h.n;
     info->n_sys = c->nsys;
-    info->near_cells_per_item = c->tune.near_cpi;
+    info->list_capacity = c->icap;
+    info->skin = c->skin_cur;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(&info->list_builds, c->nbuild, sizeof(int64_t), hipMemcpyDeviceToHost));
     info->rho_chunk = c->tune.rho_chunk;
     info->far_block = c->tune.far_block;
     info->tuned = c->tuned ? 1 : 0;
@@ -1601,7 +1850,7 @@ rbsog_status rbsog_debug_cells(rbsog_ctx *c, int32_t sys, int32_t *cell_start, i
         for (int64_t k = 0; k <= h.ncell; ++k) cell_start[k] -= (int32_t)h.p0;
     }
     if (order) {
-        HIPCHK(c, hipMemcpy(order, c->buf[c->parity].id + h.p0, (size_t)h.n * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(order, c->buf[0].id + h.p0, (size_t)h.n * sizeof(int32_t), hipMemcpyDeviceToHost));
         for (int64_t k = 0; k < h.n; ++k) order[k] -= (int32_t)h.p0;
     }
     return RBSOG_OK;
@@ -1610,13 +1859,16 @@ rbsog_status rbsog_debug_cells(rbsog_ctx *c, int32_t sys, int32_t *cell_start, i
 rbsog_status rbsog_debug_neighbors(rbsog_ctx *c, int32_t sys, int64_t *row_ptr, int32_t *cols, int64_t cap) {
     TRY(check_ctx(c));
     TRY(check_sys(c, sys));
-    if (c->evals == 0) return fail(c, RBSOG_E_STATE, "no force evaluation yet");
+    // the candidates come from the cells of the latest build, which cover
+    // the neighbours only while the positions are those of an evaluation
+    if (c->evals == 0 || !c->forces_valid)
+        return fail(c, RBSOG_E_STATE, "needs the forces of the current positions first");
     if (!row_ptr) return fail(c, RBSOG_E_ARG, "row_ptr is null");
     const SysHost &h = c->sys[sys];
     const int64_t n = h.n;
     // the latest evaluation's arrays: its cell order is the current one
     EvalArgs a = make_args(c, false, 0.0);
-    const int32_t *idc = c->buf[c->parity].id;
+    const int32_t *idc = c->buf[0].id;
     int64_t *dcount = nullptr;
     HIPCHK(c, hipMalloc((void **)&dcount, (size_t)(n + 1) * sizeof(int64_t)));
     launch_neighbor_count(a, sys, n, h.p0, idc, dcount, c->stream);

@@ -106,10 +106,10 @@ template <bool F64>
 __global__ __launch_bounds__(1024) void k_rho(EvalArgs a, const RhoItem *__restrict__ items, int32_t nitems) {
     __shared__ double2 red[1024];
     const int64_t n = a.N;
-    const double *__restrict__ x = a.nxt.x;
-    const double *__restrict__ q = a.nxt.q;
-    const float *__restrict__ qf = a.nxt.qf;
-    const uint32_t *__restrict__ u = a.u;
+    const double *__restrict__ x = a.cur.x;
+    const double *__restrict__ q = a.cur.q;
+    const float *__restrict__ qf = a.cur.qf;
+    const uint32_t *__restrict__ u = a.u_tmp;
     // the wave index is uniform: readfirstlane lets the particle loads below
     // be scalar loads shared by the whole wave
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -315,12 +315,15 @@ __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
         const SysDev &sd = a.sys[s];
         // eight independent loads in flight per thread, summed in a fixed order
         double u8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        int64_t i = sd.it0 + threadIdx.x;
-        for (; i + 7 * 256 < sd.it1; i += 8 * 256) {
+        // near energies per item of the mode in use
+        const double *ep = a.always_build ? a.epart_cells : a.epart;
+        const int64_t i0 = a.always_build ? sd.jt0 : sd.it0, i1 = a.always_build ? sd.jt1 : sd.it1;
+        int64_t i = i0 + threadIdx.x;
+        for (; i + 7 * 256 < i1; i += 8 * 256) {
 #pragma unroll
-            for (int h = 0; h < 8; ++h) u8[h] += a.epart[i + h * 256];
+            for (int h = 0; h < 8; ++h) u8[h] += ep[i + h * 256];
         }
-        for (; i < sd.it1; i += 256) u8[0] += a.epart[i];
+        for (; i < i1; i += 256) u8[0] += ep[i];
         const double un = ((u8[0] + u8[1]) + (u8[2] + u8[3])) + ((u8[4] + u8[5]) + (u8[6] + u8[7]));
         double us = 0.0;
         for (int64_t k = threadIdx.x; k < sd.P; k += 256) us += a.ek[sd.k0 + k];
@@ -360,9 +363,12 @@ __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
 
 // Far force, one particle per lane, the P records of its system streamed
 // uniformly; items are runs of up to 256 slots of one system (grid-stride).
+// The near-list rebuild flag is cleared here: every kernel of the
+// evaluation that reads it has run.
 template <bool F64>
 __global__ __launch_bounds__(256) void k_far(EvalArgs a, const FarItem *__restrict__ items, int32_t nitems) {
     const int64_t n = a.N;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.rebuild) *a.rebuild = 0;
     for (int32_t itx = blockIdx.x; itx < nitems; itx += gridDim.x) {
         const FarItem item = items[itx];
         const int32_t sys = rfl(item.sys);
@@ -377,7 +383,7 @@ __global__ __launch_bounds__(256) void k_far(EvalArgs a, const FarItem *__restri
         double Fx = 0.0, Fy = 0.0, Fz = 0.0;
         // records are consumed in groups so that their uniform loads overlap
         if constexpr (F64) {
-            const double *__restrict__ x = a.nxt.x;
+            const double *__restrict__ x = a.cur.x;
             const double sx = x[i] * sp->g.invL[0], sy = x[n + i] * sp->g.invL[1], sz = x[2 * n + i] * sp->g.invL[2];
             constexpr int G = 2;
             int32_t e = 0;
@@ -406,10 +412,10 @@ __global__ __launch_bounds__(256) void k_far(EvalArgs a, const FarItem *__restri
                 Fy = fma(r.cky, v, Fy);
                 Fz = fma(r.ckz, v, Fz);
             }
-            const double qi = a.nxt.q[i];
+            const double qi = a.cur.q[i];
             Fx *= -qi; Fy *= -qi; Fz *= -qi;
         } else {
-            const uint32_t *__restrict__ u = a.u;
+            const uint32_t *__restrict__ u = a.u_tmp;
             const uint32_t ux = u[i], uy = u[n + i], uz = u[2 * n + i];
             constexpr int G = 4;
             int32_t e = 0;
@@ -443,12 +449,12 @@ __global__ __launch_bounds__(256) void k_far(EvalArgs a, const FarItem *__restri
                 fy = fmaf(r.cky, v, fy);
                 fz = fmaf(r.ckz, v, fz);
             }
-            const double qi = -(double)a.nxt.qf[i];
+            const double qi = -(double)a.cur.qf[i];
             Fx = qi * (Fx + fx); Fy = qi * (Fy + fy); Fz = qi * (Fz + fz);
         }
         if (valid) {
             if (sp->zmode != 0) {
-                const double qi = a.nxt.q[i], c = sp->zf * qi;
+                const double qi = a.cur.q[i], c = sp->zf * qi;
                 const double *M = a.dipole + 3 * sys;
                 if (sp->zmode == 1) {
                     Fx += c * M[0];
@@ -465,7 +471,7 @@ __global__ __launch_bounds__(256) void k_far(EvalArgs a, const FarItem *__restri
                 bool bad = false;
                 for (int d = 0; d < 3; ++d) {
                     bad |= !isfinite(f[d]);
-                    a.nxt.v[d * n + i] += a.hdm * f[d];
+                    a.cur.v[d * n + i] += a.hdm * f[d];
                 }
                 if (bad) atomicOr(a.flag, 1);
             }

@@ -1,12 +1,14 @@
-// Particle bookkeeping kernels of librbsog for gfx950: wrap and quantise,
-// the cell list (histogram, exclusive scan, scatter, per-cell id sort and
-// gather of the state into cell order), the velocity-Verlet kick/drift and the
-// staging of each evaluation's wave vectors.
+// Particle bookkeeping kernels of librbsog for gfx950: the velocity-Verlet
+// kick/drift, wrap and quantise with the displacement check of the Verlet
+// list, the cell list of a list build (histogram, exclusive scan, scatter,
+// per-cell id sort and gather of the state into cell order) and the staging
+// of each evaluation's wave vectors.
 //
 // Arrays are structure-of-arrays over all systems of the batch: component d
-// of slot t is at [d*N + t].  The state stays in cell order between
-// evaluations, so these passes stream it coalesced and the re-sort moves
-// particles only as far as they drifted.
+// of slot t is at [d*N + t].  The state is in the cell order of the latest
+// list build, so these passes stream it coalesced and a re-sort moves
+// particles only as far as they drifted.  The list-build kernels read the
+// rebuild flag first and return at once when it is clear.
 #include "rbsog_internal.h"
 
 namespace rbsog {
@@ -103,9 +105,12 @@ __device__ __forceinline__ int32_t run_atomic_add(int32_t *ctr, int64_t cell, bo
 }
 
 // Optional kick dt/2 and drift (velocity Verlet), then wrap x into [0, L)
-// (x_w = frac(x/L) L), fixed-point coordinate u = min(2^32-1,
-// floor(frac(x/L) 2^32)), cell c_d = (u n_d) >> 32 and the cell histogram.
-// Blocks past the particles stage the k records.
+// (x_w = frac(x/L) L) and fixed-point coordinate u = min(2^32-1,
+// floor(frac(x/L) 2^32)).  A particle farther than skin r_c / 2 from its
+// position at the latest list build sets the rebuild flag: the list holds
+// every pair within r_c (1 + skin) at the build, so it holds every pair
+// within r_c while no particle has moved farther.  Blocks past the particles
+// stage the k records.
 __global__ __launch_bounds__(kBlock) void k_kdq(EvalArgs a, int32_t pblocks) {
     if ((int32_t)blockIdx.x >= pblocks) {
         stage_records(a, (int64_t)(blockIdx.x - pblocks) * kBlock + threadIdx.x);
@@ -120,13 +125,15 @@ __global__ __launch_bounds__(kBlock) void k_kdq(EvalArgs a, int32_t pblocks) {
     // every load first: the system's constants and the particle's state
     const SysDev &sd = a.sys[a.sys_of[t]];
     double L[3], xs[3];
-    int32_t nc[3];
+    float hf[3];
+    uint32_t uref[3];
     for (int d = 0; d < 3; ++d) {
         L[d] = sd.g.L[d];
-        nc[d] = sd.g.nc[d];
+        hf[d] = sd.g.hf[d];
         xs[d] = x[d * N + t];
+        uref[d] = a.u[d * N + t];
     }
-    const int64_t c0 = sd.c0;
+    const float dthr2 = sd.g.dthr2_f;
     if (a.kick) {
         double f[3], vs[3];
         for (int d = 0; d < 3; ++d) {
@@ -156,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_kdq(EvalArgs a, int32_t pblocks) {
         }
         if (bad && valid) atomicOr(a.flag, 1);
     }
-    int64_t c[3];
+    float d2 = 0.f;
     for (int d = 0; d < 3; ++d) {
         const double r = xs[d] / L[d];
         const double f = r - floor(r);
@@ -167,9 +174,34 @@ __global__ __launch_bounds__(kBlock) void k_kdq(EvalArgs a, int32_t pblocks) {
             a.u_tmp[d * N + t] = ud;
             x[d * N + t] = f * L[d];
         }
-        c[d] = (int64_t)(((uint64_t)ud * (uint64_t)nc[d]) >> 32);
+        // the wrapped fixed-point difference is the minimum image
+        const float dd = (float)(int32_t)(ud - uref[d]) * hf[d];
+        d2 += dd * dd;
     }
-    const int64_t cell = c0 + c[0] + (int64_t)nc[0] * (c[1] + (int64_t)nc[1] * c[2]);
+    if (a.always_build) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *a.rebuild = 1;
+    } else {
+        // one atomic per wave that found a particle past the threshold
+        const bool far_ = valid && !(d2 <= dthr2);
+        if (__ballot(far_) != 0ull && (threadIdx.x & 63) == 0) atomicOr(a.rebuild, 1);
+    }
+}
+
+// Cell c_d = (u n_d) >> 32 of each particle and the cell histogram.
+__global__ __launch_bounds__(kBlock) void k_bin(EvalArgs a) {
+    if (!*a.rebuild) return;
+    const int64_t t0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = t0 < a.N;
+    const int64_t t = valid ? t0 : a.N - 1;
+    const int64_t N = a.N;
+    const SysDev &sd = a.sys[a.sys_of[t]];
+    int64_t c[3];
+    int32_t nc[3];
+    for (int d = 0; d < 3; ++d) {
+        nc[d] = sd.g.nc[d];
+        c[d] = (int64_t)(((uint64_t)a.u_tmp[d * N + t] * (uint64_t)nc[d]) >> 32);
+    }
+    const int64_t cell = sd.c0 + c[0] + (int64_t)nc[0] * (c[1] + (int64_t)nc[1] * c[2]);
     if (valid) a.cell_of[t] = (int32_t)cell;
     run_atomic_add(a.cell_count, cell, valid);
 }
@@ -198,7 +230,9 @@ __device__ int32_t block_exclusive_scan(int32_t v, int32_t *total) {
     return base + incl - v;
 }
 
-__global__ void k_scan_blocks(const int32_t *__restrict__ in, int64_t n, int32_t *__restrict__ bsum) {
+__global__ void k_scan_blocks(const int32_t *__restrict__ in, int64_t n, int32_t *__restrict__ bsum,
+                              const int32_t *__restrict__ cond) {
+    if (!*cond) return;
     int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int32_t s = 0;
     for (int k = 0; k < kScanItems; ++k)
@@ -208,7 +242,8 @@ __global__ void k_scan_blocks(const int32_t *__restrict__ in, int64_t n, int32_t
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-__global__ void k_scan_sums(int32_t *bsum, int64_t nb) {
+__global__ void k_scan_sums(int32_t *bsum, int64_t nb, const int32_t *__restrict__ cond) {
+    if (!*cond) return;
     // one block: exclusive scan of the block totals in place
     int64_t per = (nb + kBlock - 1) / kBlock;
     int64_t lo = threadIdx.x * per, hi = lo + per < nb ? lo + per : nb;
@@ -224,7 +259,8 @@ __global__ void k_scan_sums(int32_t *bsum, int64_t nb) {
 }
 
 __global__ void k_scan_apply(const int32_t *__restrict__ in, int64_t n, const int32_t *__restrict__ bsum,
-                             int32_t *__restrict__ out, int32_t *__restrict__ fill) {
+                             int32_t *__restrict__ out, int32_t *__restrict__ fill, const int32_t *__restrict__ cond) {
+    if (!*cond) return;
     int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int32_t vals[kScanItems];
     int32_t s = 0;
@@ -245,7 +281,9 @@ __global__ void k_scan_apply(const int32_t *__restrict__ in, int64_t n, const in
 }
 
 __global__ __launch_bounds__(kBlock) void k_cell_scatter(int64_t N, const int32_t *__restrict__ cell_of,
-                                                         int32_t *__restrict__ fill, int32_t *__restrict__ src) {
+                                                         int32_t *__restrict__ fill, int32_t *__restrict__ src,
+                                                         const int32_t *__restrict__ cond) {
+    if (!*cond) return;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = t < N;
     const int32_t cell = valid ? cell_of[t] : 0;
@@ -261,6 +299,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_scatter(int64_t N, const int32_
 constexpr int kRankMax = 16;
 
 __global__ __launch_bounds__(kBlock) void k_cell_sort(EvalArgs a) {
+    if (!*a.rebuild) return;
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= a.C) return;
     const int32_t lo = a.cell_start[c], hi = a.cell_start[c + 1];
@@ -297,9 +336,11 @@ __global__ __launch_bounds__(kBlock) void k_cell_sort(EvalArgs a) {
     a.cell_count[c] = 0;
 }
 
-// Gather of the state into the new order, one thread per new slot: writes
-// are coalesced and the reads stay close (particles move little per step).
+// Gather of the state into `nxt` in the new order, one thread per new slot:
+// writes are coalesced and the reads stay close (particles move little
+// between builds).  The positions become the new list reference `u`.
 __global__ __launch_bounds__(kBlock) void k_gather(EvalArgs a) {
+    if (!*a.rebuild) return;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.N) return;
     const int64_t N = a.N;
@@ -312,6 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(EvalArgs a) {
     a.nxt.q[k] = a.cur.q[t];
     a.nxt.qf[k] = a.cur.qf[t];
     a.nxt.id[k] = a.cur.id[t];
+    a.cell_sorted[k] = a.cell_of[t];
 }
 
 }  // namespace
@@ -328,19 +370,24 @@ void launch_kdq(const EvalArgs &a, hipStream_t s) {
 
 int64_t scan_blocksums_size(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
+void launch_bin(const EvalArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_bin, dim3(grid_for(a.N, kBlock)), dim3(kBlock), 0, s, a);
+}
+
 void launch_scan(const EvalArgs &a, hipStream_t s) {
     const int64_t n = a.C;
 
     int64_t nb = (n + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(kBlock), 0, s, a.cell_count, n, a.blocksums);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, a.blocksums, nb);
+    hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(kBlock), 0, s, a.cell_count, n, a.blocksums,
+                       (const int32_t *)a.rebuild);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, a.blocksums, nb, (const int32_t *)a.rebuild);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kBlock), 0, s, a.cell_count, n, a.blocksums,
-                       a.cell_start, a.cell_fill);
+                       a.cell_start, a.cell_fill, (const int32_t *)a.rebuild);
 }
 
 void launch_cell_scatter(const EvalArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_cell_scatter, dim3(grid_for(a.N, kBlock)), dim3(kBlock), 0, s, a.N, a.cell_of, a.cell_fill,
-                       a.src);
+                       a.src, (const int32_t *)a.rebuild);
 }
 
 void launch_sort_gather(const EvalArgs &a, hipStream_t s) {

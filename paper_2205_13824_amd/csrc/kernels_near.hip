@@ -3,25 +3,36 @@
 //   F_N,i = sum_{j: r_ij < r_c} q_i q_j (1/r^3 - 2 sum_l omega_l/s_l^2 e^{-r^2/s_l^2}) r_ij
 //   U_N   = 1/2 sum_i sum_j q_i q_j (1/r - sum_l omega_l e^{-r^2/s_l^2})
 //
-// Work items are runs of consecutive cells of one system; one wave per item,
-// one home cell at a time.  The candidates of a cell are the particles of its
-// 27 (or fewer) neighbouring cells; the three cells of a row are contiguous
-// in cell order, so they are up to 18 contiguous ranges of the sorted arrays.
-// The wave stages them in LDS with coalesced loads, then tests every (home i,
-// candidate j) pair with i uniform across the wave and j on the lanes.  About
-// one candidate in six lies inside r_c: accepted pairs are compacted with a
-// ballot into an LDS queue and evaluated 64 at a time, so the pair arithmetic
-// runs on full waves; forces accumulate into per-home LDS slots.  Blocks take
-// contiguous runs of items, assigned so that each XCD (blocks are dealt to the
-// 8 XCDs round robin) works on one contiguous slab of cells and keeps it in
-// its own L2.  The state is in cell order, so homes and forces are read and
-// written coalesced.
+// A Verlet list with a skin: a build lists, for every particle, the particles
+// within r_c (1 + skin) of it, and the list serves every evaluation until a
+// particle has moved farther than skin r_c / 2 from its position at the build
+// (checked at every step by the kick/drift kernel).  Every listed pair is
+// still put to the exact pair rule at its current positions, so the pairs
+// evaluated are exactly those within r_c.
+//
+// Build: work items are 64 consecutive particles (homes) of one system in
+// cell order, one wave per item.  The candidates of a home cell are the
+// particles of its 27 (or fewer) neighbouring cells (cells are at least
+// r_c (1 + skin) wide); the three cells of a row are contiguous in cell order,
+// so they are up to 18 contiguous ranges of the sorted arrays.  The wave holds
+// candidates on its lanes and tests every (home, candidate) pair with the
+// home broadcast; accepted pairs are compacted with a ballot into an LDS ring
+// and written out 64 at a time.  The list of item b is the entries
+// [b icap, b icap + count) of the pair array.
+//
+// Evaluation: one block of four waves per item; the waves take turns over the
+// item's pairs, 64 per pass, sum each home's forces with a segmented scan
+// across the wave and keep them in per-wave LDS slots, added in a fixed order
+// at the end, so results are the same on every run.  Blocks are dealt to the
+// 8 XCDs so that each XCD sweeps one contiguous slab of items and keeps its
+// candidates in its own L2.
 //
 // Gaussians with r_c^2/s_l^2 <= kTailTau are summed as one polynomial in r^2
 // (their Taylor series, truncated below rounding), the narrow ones with an
 // exponential each.  Pair inclusion follows the fixed-point rule of rbsog.h:
 // an FP32 test decides every pair outside a narrow band around r_c, the exact
-// FP64 rule decides the rest, so the list is bit-exact in both precisions.
+// FP64 rule decides the rest, so the pairs are bit-exact in both precisions.
+#include <algorithm>
 #include <type_traits>
 
 #include "rbsog_internal.h"
@@ -115,25 +126,6 @@ __device__ __forceinline__ double bcast64(double v, int src) {
     return __longlong_as_double(((long long)hi << 32) | (uint32_t)lo);
 }
 
-constexpr int kNW = 4;        // waves per block
-constexpr int kU = 2;         // homes tested together
-constexpr int kQueue = 512;   // pair queue entries per wave: a ring (power of two)
-constexpr uint32_t kNoCand = 0xfffffffeu;  // candidate slot past the end of the list
-
-template <bool F64>
-struct NearLds {
-    using R = typename std::conditional<F64, double, float>::type;
-    static constexpr int HC = 64;                // home particles staged per batch
-    static constexpr int XH = F64 ? HC : 1;
-    uint4 hu[HC];          // home u_x, u_y, u_z, slot
-    R hq[HC];
-    double hx[3][XH];
-    R hf[3][HC];           // force accumulators of the home batch
-    uint2 q[kQueue];       // ring of queued pairs: (home index in the batch, candidate slot)
-    int32_t rlo[32], rex[32];  // non-empty candidate ranges of the cell: first slot, offset in the list
-    int32_t flag[64];          // range starts inside the current 64-slot window
-};
-
 // Per-system constants are read through the constant address space, so that
 // uniform reads become scalar loads.
 typedef const SysDev __attribute__((address_space(4))) CSys;
@@ -207,32 +199,66 @@ __device__ __forceinline__ Geom load_geom(CSys *sp) {
     g.band_hi = sp->g.band_hi;
     g.band_lo_f = sp->g.band_lo_f;
     g.band_hi_f = sp->g.band_hi_f;
+    g.rl2_f = sp->g.rl2_f;
+    g.dthr2_f = sp->g.dthr2_f;
     return g;
 }
 template <>
 struct CoefOf<true> { using type = CCoef64; };
 
-// Evaluate `count` queued pairs from the ring position `head`, one per lane.  The test admitted
-// every pair with an approximate r^2 below the upper band edge; here the pair
-// rule is applied: the fixed-point r^2 in FP32 decides below the lower band
-// edge, the exact FP64 rule inside the band (rare).  Then the exact
-// displacement (fixed point for FP32C, wrapped FP64 coordinates for FP64), the
-// pair force and energy.  Entries of one home are contiguous within one
-// candidate pass, so forces are summed by a segmented scan across the wave
-// and the last lane of each segment adds the total to the home accumulator.
+constexpr int kNW = 4;        // waves per block
+constexpr int kU = 2;         // homes tested together in the build
+// pair ring entries per wave in the build (a power of two above the
+// 63 + kU * S * 64 entries that can be pending)
+constexpr int ring_size(int S) { return S <= 3 ? 512 : 1024; }
+constexpr uint32_t kNoCand = 0xfffffffeu;  // candidate slot past the end of the list
+
+// Homes per wave: an item's four waves each own a quarter of its homes (and
+// the quarter's segment of the item's list), in the build and in the list
+// pass alike, so a home's pairs are added by one wave in one order.
+constexpr int kQuarter = kListHomes / kNW;
+static_assert(kNW == kListWaves, "one wave per quarter of an item");
+
 template <bool F64>
-__device__ __forceinline__ void eval_batch(const Geom &g, typename CoefOf<F64>::type *co, NearLds<F64> &L,
-                                           const uint32_t *__restrict__ su, const double *__restrict__ sx,
-                                           const double *__restrict__ sq, const float *__restrict__ sqf, int64_t n,
-                                           const float4 *__restrict__ tbl, float rin2, const float *ta,
-                                           const float *tb, int lane, int head, int count, double &e) {
-    using R = typename NearLds<F64>::R;
+struct EvalLds {
+    using R = typename std::conditional<F64, double, float>::type;
+    static constexpr int XH = F64 ? kQuarter : 1;
+    uint4 hu[kQuarter];    // home u_x, u_y, u_z, slot
+    R hq[kQuarter];
+    double hx[3][XH];
+    R hf[3][kQuarter];     // force accumulators
+};
+
+// One listed pair per lane (`have`): the pair rule at the current positions
+// (the fixed-point r^2 in FP32 decides below the lower band edge, the exact
+// FP64 rule above it), then the exact displacement (fixed point for FP32C,
+// wrapped FP64 coordinates for FP64), the pair force and energy.  One home's
+// entries are contiguous within a build pass, so forces are summed by a
+// segmented scan across the wave and the last lane of each segment adds the
+// total to the wave's accumulator of that home.
+// Homes of one item in LDS, as the evaluation reads them; `hf` is the
+// accumulator set the pairs add to.
+template <bool F64>
+struct HomeView {
+    using R = typename std::conditional<F64, double, float>::type;
+    const uint4 *hu;       // u_x, u_y, u_z, slot
+    const R *hq;
+    const double *hx[3];   // FP64 positions (FP64 form only)
+    R *hf[3];
+};
+
+template <bool F64>
+__device__ __forceinline__ void eval_pair(const Geom &g, typename CoefOf<F64>::type *co, const HomeView<F64> &L,
+                                          const uint32_t *__restrict__ su, const double *__restrict__ sx,
+                                          const double *__restrict__ sq, const float *__restrict__ sqf, int64_t n,
+                                          const float4 *__restrict__ tbl, float rin2, const float *ta,
+                                          const float *tb, int lane, uint2 qe, bool have, double &e) {
+    double de = 0.0;
+    using R = typename HomeView<F64>::R;
     constexpr int NT = (F64 ? kTailDeg64 : kTailDeg32) + 1;
     R fx = 0, fy = 0, fz = 0;
-    int slot = -1;
-    if (lane < count) {
-        const uint2 qe = L.q[(head + lane) & (kQueue - 1)];
-        slot = (int)qe.x;
+    const int slot = have ? (int)qe.x : -1;
+    if (have) {
         const uint32_t j = qe.y;
         const uint4 h = L.hu[slot];
         const uint32_t dux = su[j] - h.x, duy = su[n + j] - h.y, duz = su[2 * n + j] - h.z;
@@ -240,9 +266,8 @@ __device__ __forceinline__ void eval_batch(const Geom &g, typename CoefOf<F64>::
         const float ey_ = (float)(int32_t)duy * g.hf[1];
         const float ez_ = (float)(int32_t)duz * g.hf[2];
         const float r2f = ex_ * ex_ + ey_ * ey_ + ez_ * ez_;
-        // the test admits the home itself (r^2 = 0); it is dropped here
-        bool in = r2f <= g.band_lo_f && j != h.w;
-        if (!in && j != h.w) in = exact_in(g, dux, duy, duz);
+        bool in = r2f <= g.band_lo_f;
+        if (!in && r2f < g.band_hi_f) in = exact_in(g, dux, duy, duz);
         if (in) {
             R dx, dy, dz, qq;
             if constexpr (F64) {
@@ -300,18 +325,21 @@ __device__ __forceinline__ void eval_batch(const Geom &g, typename CoefOf<F64>::
             fx = -coef * dx;
             fy = -coef * dy;
             fz = -coef * dz;
-            e += 0.5 * (double)(qq * hk);
+            de = 0.5 * (double)(qq * hk);
         }
     }
+    e += de;
     const int prev = __shfl_up(slot, 1, 64);
     const bool seg = lane == 0 || slot != prev;
     const uint64_t H = __ballot(seg);
     const uint64_t upto = H & ((2ull << lane) - 1ull);
     const int sstart = 63 - __clzll((long long)upto);
     seg_scan3<R>(fx, fy, fz, lane, sstart);
-    // a batch can span two candidate passes of one home, so segment totals
-    // are added atomically (almost always one lane per home)
-    const bool tail = lane < count && (lane == count - 1 || (lane < 63 && ((H >> (lane + 1)) & 1ull)));
+    // a pass can hold two runs of one home (two candidate passes of the
+    // build), so segment totals are added atomically; the adds of one wave
+    // into its own slots happen in a fixed order
+    const int count = (int)__popcll(__ballot(have));  // the lanes holding pairs are a prefix
+    const bool tail = have && (lane == count - 1 || (lane < 63 && ((H >> (lane + 1)) & 1ull)));
     if (tail) {
         atomicAdd(&L.hf[0][slot], fx);
         atomicAdd(&L.hf[1][slot], fy);
@@ -319,12 +347,435 @@ __device__ __forceinline__ void eval_batch(const Geom &g, typename CoefOf<F64>::
     }
 }
 
+template <bool F64, int Q>
+struct BuildLds {
+    using R = typename std::conditional<F64, double, float>::type;
+    static constexpr int XH = F64 ? kQuarter : 1;
+    uint4 hu[kQuarter];        // home u_x, u_y, u_z, slot
+    R hq[kQuarter];
+    double hx[3][XH];
+    R hf[3][kQuarter];         // force accumulators of the wave's homes
+    uint2 q[Q];                // ring of accepted pairs: (home index in the quarter, candidate slot)
+    int32_t rlo[32], rex[32];  // non-empty candidate ranges of the cell: first slot, offset in the list
+    int32_t flag[64];          // range starts inside the current 64-slot window
+};
+
+// Ring entries [head, head + count): written to the item's list (entries at
+// or beyond the capacity are dropped; the caller flags the overflow) and
+// evaluated, one per lane.
+// The state gathered into `nxt` goes back to `cur`; the new reference
+// positions are the current ones (grid-stride from i0).
+__device__ __forceinline__ void copy_back(const EvalArgs &a, int64_t i0, int64_t stride) {
+    const int64_t n = a.N;
+    for (int64_t i = i0; i < n; i += stride) {
+        for (int d = 0; d < 3; ++d) {
+            a.cur.x[d * n + i] = a.nxt.x[d * n + i];
+            a.cur.v[d * n + i] = a.nxt.v[d * n + i];
+            a.u_tmp[d * n + i] = a.u[d * n + i];
+        }
+        a.cur.q[i] = a.nxt.q[i];
+        a.cur.qf[i] = a.nxt.qf[i];
+        a.cur.id[i] = a.nxt.id[i];
+    }
+}
+
+// Ring entries [head, head + count), one per lane.
+template <bool F64, int Q>
+__device__ __forceinline__ void eval_ring(const uint2 *ring, const HomeView<F64> &hv, const Geom &g,
+                                          typename CoefOf<F64>::type *co, const uint32_t *__restrict__ su,
+                                          const double *__restrict__ sx, const double *__restrict__ sq,
+                                          const float *__restrict__ sqf, int64_t n, const float4 *__restrict__ tbl,
+                                          float rin2, const float *ta, const float *tb, int lane, int head, int count,
+                                          double &e) {
+    const bool have = lane < count;
+    const uint2 qe = have ? ring[(head + lane) & (Q - 1)] : make_uint2(0u, 0u);
+    eval_pair<F64>(g, co, hv, su, sx, sq, sqf, n, tbl, rin2, ta, tb, lane, qe, have, e);
+}
+
+// Ring entries [head, head + count): written to the wave's list segment
+// (entries at or beyond its capacity are dropped; the caller flags the
+// overflow) and evaluated, one per lane, in the chunks of 64 in which the
+// list pass reads the segment.
+template <bool F64, int Q>
+__device__ __forceinline__ void drain_ring(const BuildLds<F64, Q> &L, const HomeView<F64> &hv,
+                                           uint2 *__restrict__ out, int64_t cap, const Geom &g,
+                                           typename CoefOf<F64>::type *co, const uint32_t *__restrict__ su,
+                                           const double *__restrict__ sx, const double *__restrict__ sq,
+                                           const float *__restrict__ sqf, int64_t n, const float4 *__restrict__ tbl,
+                                           float rin2, const float *ta, const float *tb, int lane, int head,
+                                           int count, double &e) {
+    const bool have = lane < count;
+    const int idx = head + lane;
+    const uint2 qe = have ? L.q[idx & (Q - 1)] : make_uint2(0u, 0u);
+    if (have && out && idx < cap) out[idx] = qe;
+    eval_pair<F64>(g, co, hv, su, sx, sq, sqf, n, tbl, rin2, ta, tb, lane, qe, have, e);
+}
+
+// The build also evaluates this step's near forces from the same candidate
+// tests (every pair it lists passes through the ring, where the pair rule
+// and the force are applied), so a step with a build needs no list pass.
+// S: candidate slots per lane and pass (64 S candidates tested per pass)
+template <bool F64, int S>
+__global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListItem *__restrict__ items,
+                                                         int32_t nitems, int32_t nblk) {
+    if (!*a.rebuild) return;
+    const int64_t n = a.N;  // stride of the structure-of-arrays
+    if ((int32_t)blockIdx.x >= nblk) {
+        copy_back(a, (int64_t)(blockIdx.x - nblk) * blockDim.x + threadIdx.x, (int64_t)(gridDim.x - nblk) * blockDim.x);
+        return;
+    }
+    constexpr int Q = ring_size(S);
+    using Lds = BuildLds<F64, Q>;
+    using R = typename Lds::R;
+    __shared__ Lds lds[kNW];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    Lds &L = lds[wave];
+    const int32_t *__restrict__ start = a.cell_start;
+    // the build runs on the gathered state (`nxt` and the new reference `u`,
+    // which are the current positions in the new order)
+    const uint32_t *__restrict__ su = a.u;
+    const double *__restrict__ sx = a.nxt.x;
+    const double *__restrict__ sq = a.nxt.q;
+    const float *__restrict__ sqf = a.nxt.qf;
+    __shared__ double es_w[kNW];
+    HomeView<F64> hv;
+    hv.hu = L.hu;
+    hv.hq = L.hq;
+    for (int d = 0; d < 3; ++d) {
+        hv.hx[d] = L.hx[d];
+        hv.hf[d] = L.hf[d];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) ++*a.nbuild;
+    // one item per block; blocks are dealt to the 8 XCDs round robin: block b
+    // (on XCD b % 8) takes item (b % 8) * (nblk / 8) + b / 8
+    const int32_t b = blockIdx.x;
+    const int32_t it = (b % 8) * (nblk / 8) + b / 8;
+    if (it >= nitems) return;
+    {
+    const ListItem item = items[it];
+    const int32_t sys = rfl(item.sys);
+    CSys *sp = (CSys *)(a.sys + sys);
+    const Geom g = load_geom(sp);
+    const int64_t c0s = sp->c0;
+    typename CoefOf<F64>::type *co;
+    if constexpr (F64) co = &sp->co64;
+    else co = &sp->co32;
+    const float4 *tbl = F64 ? nullptr : sp->tbl;
+    const float rin2 = sp->rin2;
+    float ta[kTabQ], tb[kTabQ];
+    for (int k = 0; k < kTabQ; ++k) {
+        ta[k] = sp->ta[k];
+        tb[k] = sp->tb[k];
+    }
+    double e = 0.0;
+    // this wave's quarter of the item's homes and of its list
+    const int32_t t = (int32_t)std::min<int64_t>(item.t0 + wave * kQuarter, item.t1);
+    const int32_t t_end = (int32_t)std::min<int64_t>(item.t0 + (wave + 1) * kQuarter, item.t1);
+    const int64_t cap = a.icap / kNW;
+    uint2 *out = a.pairs ? a.pairs + (int64_t)it * a.icap + wave * cap : nullptr;
+    const bool rel = g.nc[0] >= 4 && g.nc[1] >= 4 && g.nc[2] >= 4;
+    if (lane < t_end - t) {
+        const int64_t tt = t + lane;
+        L.hu[lane] = make_uint4(su[tt], su[n + tt], su[2 * n + tt], (uint32_t)tt);
+        if constexpr (F64) {
+            L.hq[lane] = sq[tt];
+            L.hx[0][lane] = sx[tt]; L.hx[1][lane] = sx[n + tt]; L.hx[2][lane] = sx[2 * n + tt];
+        } else {
+            L.hq[lane] = sqf[tt];
+        }
+    }
+    if (lane < kQuarter) {
+        L.hf[0][lane] = 0; L.hf[1][lane] = 0; L.hf[2][lane] = 0;
+    }
+    wave_sync();
+    int qn = 0, qh = 0;  // ring tail (pairs accepted) and head (pairs written)
+    for (int64_t cell = t < t_end ? rfl(a.cell_sorted[t]) : 0; t < t_end; ++cell) {
+        const int32_t cs = rfl(start[cell]);
+        if (cs >= t_end) break;
+        const int32_t ce = rfl(start[cell + 1]);
+        const int32_t hs = cs > t ? cs : t;
+        const int32_t he = ce < t_end ? ce : t_end;
+        if (hs >= he) continue;
+        const int i0 = hs - t, i1 = he - t;
+        const uint32_t cu32 = (uint32_t)(cell - c0s);
+        const int cx = (int)(cu32 % (uint32_t)g.nc[0]);
+        const int cy = (int)((cu32 / (uint32_t)g.nc[0]) % (uint32_t)g.nc[1]);
+        const int cz = (int)(cu32 / ((uint32_t)g.nc[0] * (uint32_t)g.nc[1]));
+        // lane r < 18 holds candidate range r: first sorted index, and its
+        // offsets in the flattened candidate list
+        int32_t lo = 0, len = 0;
+        if (lane < kRanges) {
+            int32_t ra_, rb_;
+            if (row_range(g, start + c0s, lane, cx, cy, cz, ra_, rb_)) { lo = ra_; len = rb_ - ra_; }
+        }
+        int32_t incl = len;
+        for (int o = 1; o < 32; o <<= 1) {
+            const int32_t v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+        }
+        const int32_t excl = incl - len;
+        const int32_t C = __builtin_amdgcn_readlane(incl, kRanges - 1);
+        // the non-empty ranges, compacted: lane k < nne holds the k-th one's
+        // first slot and its offset in the flattened list (offsets strictly
+        // increase, the first is 0)
+        const bool ne = lane < kRanges && len > 0;
+        const uint64_t NE = __ballot(ne);
+        const int nne = (int)__popcll(NE);
+        if (ne) {
+            const int k = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(NE >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)NE, 0));
+            L.rlo[k] = lo;
+            L.rex[k] = excl;
+        }
+        wave_sync();
+        const int32_t clo = lane < nne ? L.rlo[lane < 32 ? lane : 0] : 0;
+        const int32_t cex = lane < nne ? L.rex[lane < 32 ? lane : 0] : 0x7fffffff;
+        // origin of the cell-relative float coordinates used by the test:
+        // the first home of the cell
+        const uint4 o4 = L.hu[i0];
+        const uint32_t ox = (uint32_t)rfl((int)o4.x), oy = (uint32_t)rfl((int)o4.y), oz = (uint32_t)rfl((int)o4.z);
+        for (int32_t cb = 0; cb < C; cb += 64 * S) {
+            // candidates of this pass in registers.  For each 64-slot window,
+            // the starts of ranges inside it are flagged in LDS; a slot's
+            // range is the number of range starts at or before it (those
+            // before the window, plus the flagged ones up to its lane) - 1.
+            uint32_t cj[S];
+#pragma unroll
+            for (int s2 = 0; s2 < S; ++s2) {
+                const int32_t base = cb + s2 * 64;
+                L.flag[lane] = 0;
+                wave_sync();
+                if (lane < nne && cex >= base && cex < base + 64) L.flag[cex - base] = 1;
+                wave_sync();
+                const uint64_t B = __ballot(L.flag[lane] != 0);
+                const int before = (int)__popcll(__ballot(lane < nne && cex < base));
+                const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+                int k = before + (int)__popcll(B & upto) - 1;
+                k = k < 0 ? 0 : k;
+                // the permutes read other lanes' registers: the whole wave is active
+                cj[s2] = (uint32_t)(__shfl(clo, k, 64) + (base + lane - __shfl(cex, k, 64)));
+                wave_sync();
+            }
+            uint32_t cux[S], cuy[S], cuz[S];
+#pragma unroll
+            for (int s2 = 0; s2 < S; ++s2) {
+                if (cb + s2 * 64 + lane < C) {
+                    cux[s2] = su[cj[s2]]; cuy[s2] = su[n + cj[s2]]; cuz[s2] = su[2 * n + cj[s2]];
+                } else {
+                    cux[s2] = ox; cuy[s2] = oy; cuz[s2] = oz;
+                    cj[s2] = kNoCand;
+                }
+            }
+            // relative coordinates: with at least 4 cells per side every
+            // candidate lies within 2 cell widths (< L/2) of the origin, so
+            // the wrapped difference to the origin is its true offset and
+            // differences of relative coordinates are minimum images;
+            // smaller grids take the difference of the fixed-point values
+            // per pair instead.  Empty slots sit far away.
+            float cfx[S], cfy[S], cfz[S];
+#pragma unroll
+            for (int s2 = 0; s2 < S; ++s2) {
+                const bool ok = cj[s2] != kNoCand;
+                cfx[s2] = ok ? (float)(int32_t)(cux[s2] - ox) * g.hf[0] : 1e18f;
+                cfy[s2] = ok ? (float)(int32_t)(cuy[s2] - oy) * g.hf[1] : 1e18f;
+                cfz[s2] = ok ? (float)(int32_t)(cuz[s2] - oz) * g.hf[2] : 1e18f;
+            }
+            // homes of this cell in groups of 64: lane l holds home g0 + l in
+            // registers, homes are broadcast with readlane.  kU homes x S
+            // slots are tested independently, then their accepted pairs are
+            // appended to the ring, home after home (so one home's pairs of
+            // a pass are contiguous).  The home itself is left out.
+            for (int g0 = i0; g0 < i1; g0 += 64) {
+                const int gn = i1 - g0 < 64 ? i1 - g0 : 64;
+                const int gi = g0 + lane;
+                const uint4 hme = gi < i1 ? L.hu[gi] : make_uint4(ox, oy, oz, 0u);
+                const float hfx = (float)(int32_t)(hme.x - ox) * g.hf[0];
+                const float hfy = (float)(int32_t)(hme.y - oy) * g.hf[1];
+                const float hfz = (float)(int32_t)(hme.z - oz) * g.hf[2];
+                for (int ii = 0; ii < gn; ii += kU) {
+                    bool acc[kU][S];
+#pragma unroll
+                    for (int uu = 0; uu < kU; ++uu) {
+                        const int h = ii + uu < gn ? ii + uu : ii;
+                        const bool hv = ii + uu < gn;
+                        const uint32_t self = (uint32_t)(t + g0 + h);
+                        if (rel) {
+                            const float hx_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfx), h));
+                            const float hy_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfy), h));
+                            const float hz_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfz), h));
+#pragma unroll
+                            for (int s2 = 0; s2 < S; ++s2) {
+                                const float dx = cfx[s2] - hx_, dy = cfy[s2] - hy_, dz = cfz[s2] - hz_;
+                                const float r2 = dx * dx + dy * dy + dz * dz;
+                                acc[uu][s2] = hv && r2 < g.rl2_f && cj[s2] != self;
+                            }
+                        } else {
+                            const uint32_t hux = (uint32_t)__builtin_amdgcn_readlane((int)hme.x, h);
+                            const uint32_t huy = (uint32_t)__builtin_amdgcn_readlane((int)hme.y, h);
+                            const uint32_t huz = (uint32_t)__builtin_amdgcn_readlane((int)hme.z, h);
+#pragma unroll
+                            for (int s2 = 0; s2 < S; ++s2) {
+                                const float r2 = fixed_r2(g, cux[s2] - hux, cuy[s2] - huy, cuz[s2] - huz);
+                                acc[uu][s2] = hv && cj[s2] != kNoCand && r2 < g.rl2_f && cj[s2] != self;
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int uu = 0; uu < kU; ++uu) {
+#pragma unroll
+                        for (int s2 = 0; s2 < S; ++s2) {
+                            const uint64_t mm = __ballot(acc[uu][s2]);
+                            if (acc[uu][s2]) {
+                                const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi(
+                                                         (uint32_t)(mm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0));
+                                L.q[pos & (Q - 1)] = make_uint2((uint32_t)(g0 + ii + uu), cj[s2]);
+                            }
+                            qn += (int)__popcll(mm);
+                        }
+                    }
+                    // at most 63 + kU * S * 64 entries are pending: the ring holds them
+                    static_assert(63 + kU * S * 64 < Q, "ring too small");
+                    while (qn - qh >= 64) {
+                        wave_sync();
+                        drain_ring<F64, Q>(L, hv, out, cap, g, co, su, sx, sq, sqf, n, tbl, rin2, ta, tb, lane, qh, 64,
+                                           e);
+                        qh += 64;
+                    }
+                }
+            }
+        }
+    }
+    wave_sync();
+    if (qn > qh)
+        drain_ring<F64, Q>(L, hv, out, cap, g, co, su, sx, sq, sqf, n, tbl, rin2, ta, tb, lane, qh, qn - qh, e);
+    wave_sync();
+    if (lane < t_end - t) {
+        const int64_t tt = t + lane;
+        a.Fn[tt] = (double)L.hf[0][lane]; a.Fn[n + tt] = (double)L.hf[1][lane]; a.Fn[2 * n + tt] = (double)L.hf[2][lane];
+    }
+    const double es = wave_sum(e);
+    if (lane == 0) {
+        es_w[wave] = es;
+        a.pcnt[(int64_t)it * kNW + wave] = (int64_t)qn < cap || !out ? qn : (int32_t)cap;
+        atomicMax(a.pmax, qn);
+        if (out && (int64_t)qn > cap) atomicOr(a.flag, 8);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) a.epart[it] = ((es_w[0] + es_w[1]) + es_w[2]) + es_w[3];
+    }
+}
+
 template <bool F64>
-__global__ __launch_bounds__(64 * kNW) void k_near(EvalArgs a, const NearItem *__restrict__ items, int32_t nitems,
-                                                   int32_t nblk) {
+__global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListItem *__restrict__ items,
+                                                        int32_t nitems, int32_t nblk) {
+    using Lds = EvalLds<F64>;
+    __shared__ Lds lds[kNW];
+    __shared__ double es_w[kNW];
+    // a build in this evaluation has evaluated the forces already
+    if (*a.rebuild) return;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    Lds &L = lds[w];
+    const int64_t n = a.N;
+    const uint32_t *__restrict__ su = a.u_tmp;
+    const double *__restrict__ sx = a.cur.x;
+    const double *__restrict__ sq = a.cur.q;
+    const float *__restrict__ sqf = a.cur.qf;
+    // one item per block, dealt to the XCDs as in the build
+    const int32_t b = blockIdx.x;
+    const int32_t it = (b % 8) * (nblk / 8) + b / 8;
+    if (it >= nitems) return;
+    const ListItem item = items[it];
+    const int32_t sys = rfl(item.sys);
+    CSys *sp = (CSys *)(a.sys + sys);
+    const Geom g = load_geom(sp);
+    typename CoefOf<F64>::type *co;
+    if constexpr (F64) co = &sp->co64;
+    else co = &sp->co32;
+    const float4 *tbl = F64 ? nullptr : sp->tbl;
+    const float rin2 = sp->rin2;
+    float ta[kTabQ], tb[kTabQ];
+    for (int k = 0; k < kTabQ; ++k) {
+        ta[k] = sp->ta[k];
+        tb[k] = sp->tb[k];
+    }
+    // this wave's quarter of the homes and its segment of the list
+    const int64_t t0 = std::min<int64_t>(item.t0 + w * kQuarter, item.t1);
+    const int H = (int)(std::min<int64_t>(item.t0 + (w + 1) * kQuarter, item.t1) - t0);
+    if (lane < H) {
+        const int64_t tt = t0 + lane;
+        L.hu[lane] = make_uint4(su[tt], su[n + tt], su[2 * n + tt], (uint32_t)tt);
+        if constexpr (F64) {
+            L.hq[lane] = sq[tt];
+            L.hx[0][lane] = sx[tt]; L.hx[1][lane] = sx[n + tt]; L.hx[2][lane] = sx[2 * n + tt];
+        } else {
+            L.hq[lane] = sqf[tt];
+        }
+    }
+    if (lane < kQuarter) {
+        L.hf[0][lane] = 0; L.hf[1][lane] = 0; L.hf[2][lane] = 0;
+    }
+    wave_sync();
+    const int64_t cap = a.icap / kNW;
+    const int32_t cnt = rfl(a.pcnt[(int64_t)it * kNW + w]);
+    const uint2 *__restrict__ pl = a.pairs + (int64_t)it * a.icap + w * cap;
+    HomeView<F64> hv;
+    hv.hu = L.hu;
+    hv.hq = L.hq;
+    for (int d = 0; d < 3; ++d) {
+        hv.hx[d] = L.hx[d];
+        hv.hf[d] = L.hf[d];
+    }
+    double e = 0.0;
+    // the segment in the build's chunks of 64, in order
+    for (int32_t c = 0; c < cnt; c += 64) {
+        const bool have = c + lane < cnt;
+        const uint2 qe = have ? pl[c + lane] : make_uint2(0u, 0u);
+        eval_pair<F64>(g, co, hv, su, sx, sq, sqf, n, tbl, rin2, ta, tb, lane, qe, have, e);
+    }
+    wave_sync();
+    if (lane < H) {
+        const int64_t tt = t0 + lane;
+        a.Fn[tt] = (double)L.hf[0][lane]; a.Fn[n + tt] = (double)L.hf[1][lane]; a.Fn[2 * n + tt] = (double)L.hf[2][lane];
+    }
+    const double es = wave_sum(e);
+    if (lane == 0) es_w[w] = es;
+    __syncthreads();
+    if (threadIdx.x == 0) a.epart[it] = ((es_w[0] + es_w[1]) + es_w[2]) + es_w[3];
+}
+
+template <bool F64>
+struct NearLds {
+    using R = typename std::conditional<F64, double, float>::type;
+    static constexpr int HC = 64;                // home particles staged per batch
+    static constexpr int XH = F64 ? HC : 1;
+    uint4 hu[HC];          // home u_x, u_y, u_z, slot
+    R hq[HC];
+    double hx[3][XH];
+    R hf[3][HC];           // force accumulators of the home batch
+    uint2 q[512];          // ring of queued pairs: (home index in the batch, candidate slot)
+    int32_t rlo[32], rex[32];  // non-empty candidate ranges of the cell: first slot, offset in the list
+    int32_t flag[64];          // range starts inside the current 64-slot window
+};
+
+// Steps that build at every evaluation (skin 0) need no list: this kernel
+// finds the pairs and evaluates them in one pass, one wave per run of cells
+// (cells r_c wide), the pair ring evaluated 64 entries at a time.  Blocks
+// past nblk copy the gathered state back into `cur`.
+template <bool F64>
+__global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearItem *__restrict__ items,
+                                                         int32_t nitems, int32_t nblk) {
+    if (!*a.rebuild) return;
+    if ((int32_t)blockIdx.x >= nblk) {
+        copy_back(a, (int64_t)(blockIdx.x - nblk) * blockDim.x + threadIdx.x, (int64_t)(gridDim.x - nblk) * blockDim.x);
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) ++*a.nbuild;
     using Lds = NearLds<F64>;
     using R = typename Lds::R;
     constexpr int S = 2;  // candidate slots per lane and pass
+    constexpr int Q = 512;
     __shared__ Lds lds[kNW];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
@@ -336,6 +787,13 @@ __global__ __launch_bounds__(64 * kNW) void k_near(EvalArgs a, const NearItem *_
     const double *__restrict__ sq = a.nxt.q;
     const float *__restrict__ sqf = a.nxt.qf;
     double *__restrict__ Fn = a.Fn;
+    HomeView<F64> hv;
+    hv.hu = L.hu;
+    hv.hq = L.hq;
+    for (int d = 0; d < 3; ++d) {
+        hv.hx[d] = L.hx[d];
+        hv.hf[d] = L.hf[d];
+    }
     // blocks are dealt to the 8 XCDs round robin: block b (on XCD b % 8) takes
     // chunk (b % 8) * (nblk / 8) + b / 8 of the item list, so each XCD sweeps
     // one slab of cells
@@ -510,7 +968,8 @@ __global__ __launch_bounds__(64 * kNW) void k_near(EvalArgs a, const NearItem *_
 #pragma unroll
                         for (int uu = 0; uu < kU; ++uu) {
                             const int h = ii + uu < gn ? ii + uu : ii;
-                            const bool hv = ii + uu < gn;
+                            const bool hok = ii + uu < gn;
+                            const uint32_t self = (uint32_t)(t + g0 + h);
                             if (rel) {
                                 const float hx_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfx), h));
                                 const float hy_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfy), h));
@@ -519,7 +978,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near(EvalArgs a, const NearItem *_
                                 for (int s2 = 0; s2 < S; ++s2) {
                                     const float dx = cfx[s2] - hx_, dy = cfy[s2] - hy_, dz = cfz[s2] - hz_;
                                     const float r2 = dx * dx + dy * dy + dz * dz;
-                                    acc[uu][s2] = hv && r2 < g.band_hi_f;
+                                    acc[uu][s2] = hok && r2 < g.band_hi_f && cj[s2] != self;
                                 }
                             } else {
                                 const uint32_t hux = (uint32_t)__builtin_amdgcn_readlane((int)hme.x, h);
@@ -528,7 +987,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near(EvalArgs a, const NearItem *_
 #pragma unroll
                                 for (int s2 = 0; s2 < S; ++s2) {
                                     const float r2 = fixed_r2(g, cux[s2] - hux, cuy[s2] - huy, cuz[s2] - huz);
-                                    acc[uu][s2] = hv && cj[s2] != kNoCand && r2 < g.band_hi_f;
+                                    acc[uu][s2] = hok && cj[s2] != kNoCand && r2 < g.band_hi_f && cj[s2] != self;
                                 }
                             }
                         }
@@ -540,16 +999,16 @@ __global__ __launch_bounds__(64 * kNW) void k_near(EvalArgs a, const NearItem *_
                                 if (acc[uu][s2]) {
                                     const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi(
                                                              (uint32_t)(mm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0));
-                                    L.q[pos & (kQueue - 1)] = make_uint2((uint32_t)(g0 + ii + uu), cj[s2]);
+                                    L.q[pos & (Q - 1)] = make_uint2((uint32_t)(g0 + ii + uu), cj[s2]);
                                 }
                                 qn += (int)__popcll(mm);
                             }
                         }
                         // at most 63 + kU * S * 64 entries are pending: the ring holds them
-                        static_assert(63 + kU * S * 64 < kQueue, "ring too small");
+                        static_assert(63 + kU * S * 64 < Q, "ring too small");
                         while (qn - qh >= 64) {
                             wave_sync();
-                            eval_batch<F64>(g, co, L, su, sx, sq, sqf, n, tbl, rin2, ta, tb, lane, qh, 64, e);
+                            eval_ring<F64, Q>(L.q, hv, g, co, su, sx, sq, sqf, n, tbl, rin2, ta, tb, lane, qh, 64, e);
                             qh += 64;
                         }
                     }
@@ -558,7 +1017,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near(EvalArgs a, const NearItem *_
         }
         // the queue refers to this batch's home slots: drain it, then write
         wave_sync();
-        if (qn > qh) eval_batch<F64>(g, co, L, su, sx, sq, sqf, n, tbl, rin2, ta, tb, lane, qh, qn - qh, e);
+        if (qn > qh) eval_ring<F64, Q>(L.q, hv, g, co, su, sx, sq, sqf, n, tbl, rin2, ta, tb, lane, qh, qn - qh, e);
         qn = 0;
         qh = 0;
         wave_sync();
@@ -570,12 +1029,15 @@ __global__ __launch_bounds__(64 * kNW) void k_near(EvalArgs a, const NearItem *_
         t = t_end;
     }
     const double es = wave_sum(e);
-    if (lane == 0) a.epart[it] = es;
+    if (lane == 0) a.epart_cells[it] = es;
     }
 }
 
 // Debug export of the neighbour list of one system with exactly the pair rule
-// of k_near.  Rows and columns are local ids (id - first id of the system).
+// of the near kernel, at the current positions.  Candidates come from the
+// cells of the latest list build, which hold every particle within r_c of the
+// home while the list is valid.  Rows and columns are local ids (id - first
+// id of the system).
 template <bool FILL>
 __global__ void k_neighbors(EvalArgs a, int32_t sys, int64_t nloc, int64_t p0, const int32_t *__restrict__ idc,
                             int64_t *__restrict__ counts, const int64_t *__restrict__ row_ptr,
@@ -586,12 +1048,13 @@ __global__ void k_neighbors(EvalArgs a, int32_t sys, int64_t nloc, int64_t p0, c
     const SysDev &sd = a.sys[sys];
     const Geom &g = sd.g;
     const int32_t *start = a.cell_start + sd.c0;
-    const uint32_t *su = a.u;
+    const uint32_t *su = a.u_tmp;
     const int64_t t = p0 + tl;
     const uint32_t ux = su[t], uy = su[N + t], uz = su[2 * N + t];
-    const int cx = (int)(((uint64_t)ux * (uint32_t)g.nc[0]) >> 32);
-    const int cy = (int)(((uint64_t)uy * (uint32_t)g.nc[1]) >> 32);
-    const int cz = (int)(((uint64_t)uz * (uint32_t)g.nc[2]) >> 32);
+    const uint32_t cu32 = (uint32_t)(a.cell_sorted[t] - sd.c0);
+    const int cx = (int)(cu32 % (uint32_t)g.nc[0]);
+    const int cy = (int)((cu32 / (uint32_t)g.nc[0]) % (uint32_t)g.nc[1]);
+    const int cz = (int)(cu32 / ((uint32_t)g.nc[0] * (uint32_t)g.nc[1]));
     const int64_t id = idc[t] - p0;
     int64_t cnt = 0;
     const int64_t base = FILL ? row_ptr[id] : 0;
@@ -622,15 +1085,45 @@ __global__ void k_neighbors(EvalArgs a, int32_t sys, int64_t nloc, int64_t p0, c
 
 }  // namespace
 
-void launch_near(const EvalArgs &a, bool f64, const NearItem *items, int32_t nitems, hipStream_t s) {
+void launch_list_build(const EvalArgs &a, bool f64, const ListItem *items, int32_t nitems, int32_t slots,
+                       hipStream_t s) {
+    // one item per block (a wave per quarter); a multiple of 8 blocks so that
+    // the XCD mapping is a permutation of the blocks; then the blocks of the
+    // copy back
+    int32_t nblk = (nitems + 7) / 8 * 8;
+    if (nblk < 8) nblk = 8;
+    const int64_t ncopy = std::min<int64_t>(1024, std::max<int64_t>(1, grid_for(a.N, 64 * kNW)));
+    const dim3 grid((unsigned)(nblk + ncopy)), block(64 * kNW);
+    if (f64) {
+        if (slots <= 2) hipLaunchKernelGGL((k_list_build<true, 2>), grid, block, 0, s, a, items, nitems, nblk);
+        else if (slots == 3) hipLaunchKernelGGL((k_list_build<true, 3>), grid, block, 0, s, a, items, nitems, nblk);
+        else hipLaunchKernelGGL((k_list_build<true, 4>), grid, block, 0, s, a, items, nitems, nblk);
+    } else {
+        if (slots <= 2) hipLaunchKernelGGL((k_list_build<false, 2>), grid, block, 0, s, a, items, nitems, nblk);
+        else if (slots == 3) hipLaunchKernelGGL((k_list_build<false, 3>), grid, block, 0, s, a, items, nitems, nblk);
+        else hipLaunchKernelGGL((k_list_build<false, 4>), grid, block, 0, s, a, items, nitems, nblk);
+    }
+}
+
+void launch_near_cells(const EvalArgs &a, bool f64, const NearItem *items, int32_t nitems, hipStream_t s) {
     // one item per wave; a multiple of 8 blocks so that the XCD mapping is a
-    // permutation of the blocks
+    // permutation of the blocks; then the blocks of the copy back
     int32_t nblk = (nitems + kNW - 1) / kNW;
     nblk = (nblk + 7) / 8 * 8;
     if (nblk < 8) nblk = 8;
+    const int64_t ncopy = std::min<int64_t>(1024, std::max<int64_t>(1, grid_for(a.N, 64 * kNW)));
+    const dim3 grid((unsigned)(nblk + ncopy)), block(64 * kNW);
+    if (f64) hipLaunchKernelGGL(k_near_cells<true>, grid, block, 0, s, a, items, nitems, nblk);
+    else hipLaunchKernelGGL(k_near_cells<false>, grid, block, 0, s, a, items, nitems, nblk);
+}
+
+void launch_near(const EvalArgs &a, bool f64, const ListItem *items, int32_t nitems, hipStream_t s) {
+    // one item per block
+    int32_t nblk = (nitems + 7) / 8 * 8;
+    if (nblk < 8) nblk = 8;
     dim3 grid((unsigned)nblk), block(64 * kNW);
-    if (f64) hipLaunchKernelGGL(k_near<true>, grid, block, 0, s, a, items, nitems, nblk);
-    else hipLaunchKernelGGL(k_near<false>, grid, block, 0, s, a, items, nitems, nblk);
+    if (f64) hipLaunchKernelGGL(k_near_list<true>, grid, block, 0, s, a, items, nitems, nblk);
+    else hipLaunchKernelGGL(k_near_list<false>, grid, block, 0, s, a, items, nitems, nblk);
 }
 
 void launch_neighbor_count(const EvalArgs &a, int32_t sys, int64_t n, int64_t p0, const int32_t *id_cur,

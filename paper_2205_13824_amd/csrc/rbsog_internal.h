@@ -41,8 +41,10 @@ struct Geom {
     double rc2;                  // rc * rc
     double band_lo, band_hi;     // FP64 r^2 thresholds outside which the fast test decides
     float band_lo_f, band_hi_f;  // same for the FP32 fast test
-    int32_t nc[3];
+    int32_t nc[3];               // cells per side: floor(L / (r_c (1 + skin))), or 1 below 3
     int32_t reach[3];            // 1 if the stencil spans -1..1 in that dimension, 0 otherwise
+    float rl2_f;                 // FP32 r^2 below which a pair enters the Verlet list (r_c (1 + skin))^2, widened
+    float dthr2_f;               // FP32 squared displacement beyond which the list is rebuilt (skin r_c / 2)^2, narrowed
 };
 
 // The near kernel evaluates the narrow Gaussians (r_c^2 / s_l^2 > tau) with an
@@ -92,7 +94,8 @@ struct SysDev {
     const double *kw;     // per-vector weights, or null for the random-batch weight
     double w_rb;          // S pi^{3/2} / (P V)
     double uself;         // U_self
-    int32_t it0, it1;     // near work items [it0, it1)
+    int32_t it0, it1;     // near list items [it0, it1)
+    int32_t jt0, jt1;     // near cell-run items [jt0, jt1) (build-every-evaluation mode)
     int64_t pofs;         // first rho partial (complex entries) of the system
     int32_t nch;          // rho particle chunks of the system
     int32_t kt, streams;  // rho block shape: k tiles of 64 lanes x particle streams
@@ -108,11 +111,23 @@ struct SysDev {
     int64_t choff;        // first structure-factor chunk of the system over the batch
 };
 
-// Near work item: a run of cells of one system.
+// Near item of the build-every-evaluation mode: a run of cells of one system.
 struct NearItem {
     int32_t sys;
     int32_t pad;
     int64_t c_begin, c_end;
+};
+// Near list item: up to kListHomes consecutive particle slots [t0, t1) of one
+// system (in the cell order of the latest list build).  Its homes come in
+// kListWaves quarters; the pairs of quarter w are entries
+// [item icap + w icap/kListWaves, ... + pcnt[item kListWaves + w]) of the
+// pair list.
+constexpr int kListHomes = 64;
+constexpr int kListWaves = 4;
+struct ListItem {
+    int32_t sys;
+    int32_t pad;
+    int64_t t0, t1;
 };
 // Structure-factor work item: particle slots [j0, j1) of one system against
 // the k tiles of group kg; its partials go to chunk `chunk` of the system.
@@ -126,8 +141,8 @@ struct FarItem {
     int64_t t0, t1;
 };
 
-// Buffers of one evaluation.  State arrays come in two copies; `cur` is the
-// order the evaluation starts from, `nxt` receives the new cell order.
+// State arrays.  `cur` holds the state; a list build gathers it into `nxt`
+// in the new cell order and copies it back.
 struct StateBufs {
     double *x, *v, *q;
     float *qf;
@@ -142,17 +157,29 @@ struct EvalArgs {
     const int32_t *sys_of;  // system of each slot (static)
     const int32_t *ksys;    // system of each k record (static)
     StateBufs cur, nxt;
-    uint32_t *u_tmp;       // fixed-point coordinates in `cur` order
-    uint32_t *u;           // fixed-point coordinates in cell order
+    uint32_t *u_tmp;       // fixed-point coordinates of the current positions
+    uint32_t *u;           // fixed-point coordinates at the latest list build (its reference)
     int32_t *cell_of, *cell_count, *cell_start, *cell_fill, *src, *sorted, *blocksums;
-    double *Fn, *Ff;       // forces in cell order
+    int32_t *cell_sorted;  // cell of each slot at the latest list build
+    double *Fn, *Ff;       // forces in slot order
+    // Verlet list: rebuild flag (set by the displacement check, cleared by the
+    // near kernel), pairs (home index in the item, candidate slot), counts,
+    // capacity per item, largest count of the latest build, builds made
+    int32_t *rebuild;
+    int32_t always_build;  // nonzero: every evaluation builds (no displacement check, no list kept)
+    uint2 *pairs;
+    int32_t *pcnt;
+    int64_t icap;
+    int32_t *pmax;
+    int64_t *nbuild;
     int64_t *kcur;         // per-system sequence cursor
     KRec64 *kb64;
     KRec32 *kb32;
     double *wk, *rho, *ek, *partial, *epart, *E;
+    double *epart_cells;   // near energies per cell-run item (build-every-evaluation mode)
     double *dip_part;      // dipole partials per structure-factor chunk (3 per chunk)
     double *dipole;        // dipole moment M per system (3 per system)
-    int32_t *flag;         // bit 0: non-finite force, bit 1: non-finite energy
+    int32_t *flag;         // bit 0: non-finite force, bit 1: non-finite energy, bit 3: list overflow
     uint32_t *sys_done;    // per-system counters of reduced k records
     // velocity-Verlet
     int32_t kick;          // nonzero: kick + drift before, kick after
@@ -189,18 +216,34 @@ void launch_refill(const SampDev *samp, int32_t nsys, int32_t lambda, ChainState
 
 // ---- kernel launchers (kernels_md.hip) --------------------------------------
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
-// kick dt/2 + drift (if a.kick), wrap, quantise, cell histogram; extra blocks
-// stage the k batch of every system
+// kick dt/2 + drift (if a.kick), wrap, quantise, displacement check against
+// the list reference (sets *a.rebuild); extra blocks stage the k batch of
+// every system
 void launch_kdq(const EvalArgs &a, hipStream_t s);
+// The list build: each of these returns at once unless *a.rebuild is set.
+// Cell of each particle and the histogram; exclusive scan of the counts;
+// scatter into cells; per cell: id sort of its segment, reset of its count,
+// gather of the state into `nxt` in the new order
+void launch_bin(const EvalArgs &a, hipStream_t s);
 void launch_scan(const EvalArgs &a, hipStream_t s);
 int64_t scan_blocksums_size(int64_t n);
 void launch_cell_scatter(const EvalArgs &a, hipStream_t s);
-// per cell: id sort of its segment, reset of its histogram count, gather of
-// the state into the new order
 void launch_sort_gather(const EvalArgs &a, hipStream_t s);
 
 // ---- near part (kernels_near.hip) ------------------------------------------
-void launch_near(const EvalArgs &a, bool f64, const NearItem *items, int32_t nitems, hipStream_t s);
+// Verlet list of every item (a.pairs null: not written) with this
+// evaluation's near forces and energies, and the copy of the gathered state
+// back into `cur`; returns at once unless *a.rebuild is set.  slots (2..4):
+// candidates per lane and test pass
+void launch_list_build(const EvalArgs &a, bool f64, const ListItem *items, int32_t nitems, int32_t slots,
+                       hipStream_t s);
+// build-every-evaluation mode (a.always_build): near forces and energies in
+// one pass over cell runs (no list), and the copy back; returns at once
+// unless *a.rebuild is set
+void launch_near_cells(const EvalArgs &a, bool f64, const NearItem *items, int32_t nitems, hipStream_t s);
+// near forces and energies from the list; returns at once if *a.rebuild is
+// set (the build has evaluated them)
+void launch_near(const EvalArgs &a, bool f64, const ListItem *items, int32_t nitems, hipStream_t s);
 // neighbour list of one system (debug export): counts per local id, then fill
 void launch_neighbor_count(const EvalArgs &a, int32_t sys, int64_t n, int64_t p0, const int32_t *id_cur,
                            int64_t *counts, hipStream_t s);

@@ -48,14 +48,15 @@ class rbsog_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("device", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("neutral_tol", ctypes.c_double), ("mass", ctypes.c_double), ("graphs", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("near_table", ctypes.c_int32), ("zero_mode", ctypes.c_int32),
-                ("device_chains", ctypes.c_int32)]
+                ("device_chains", ctypes.c_int32), ("skin", ctypes.c_double)]
 
 
 class rbsog_info_t(ctypes.Structure):
     _fields_ = [("S", ctypes.c_double), ("volume", ctypes.c_double), ("ncell", ctypes.c_int32 * 3),
                 ("k_remaining", ctypes.c_int64), ("evaluations", ctypes.c_int64), ("n", ctypes.c_int64),
-                ("n_sys", ctypes.c_int32), ("near_cells_per_item", ctypes.c_int32), ("rho_chunk", ctypes.c_int32),
-                ("far_block", ctypes.c_int32), ("tuned", ctypes.c_int32)]
+                ("n_sys", ctypes.c_int32), ("rho_chunk", ctypes.c_int32), ("far_block", ctypes.c_int32),
+                ("tuned", ctypes.c_int32), ("list_capacity", ctypes.c_int64), ("list_builds", ctypes.c_int64),
+                ("skin", ctypes.c_double)]
 
 
 _lib = None
@@ -133,13 +134,15 @@ def rbsog_default_opts() -> rbsog_opts:
 
 
 def _opts(precision, device, stream, neutral_tol, mass, graphs, autotune=False, near_table=False, zero_mode=0,
-          device_chains=0):
+          device_chains=0, skin=None):
     o = rbsog_default_opts()
     o.precision, o.device, o.neutral_tol, o.mass, o.graphs = precision, device, neutral_tol, mass, int(graphs)
     o.autotune = int(autotune)
     o.near_table = int(near_table)
     o.zero_mode = int(zero_mode)
     o.device_chains = int(device_chains)
+    if skin is not None:
+        o.skin = float(skin)
     o.stream = stream
     return o
 
@@ -147,12 +150,13 @@ def _opts(precision, device, stream, neutral_tol, mass, graphs, autotune=False, 
 def rbsog_init(pos, q, box, sog: rbsog_sog, rc: float, P: int, seed: int, precision: int = RBSOG_FP64,
                device: int = 0, stream: int | None = None, neutral_tol: float = 1e-10, mass: float = 1.0,
                graphs: bool = True, autotune: bool = False, near_table: bool = False, zero_mode: int = 0,
-               device_chains: int = 0):
+               device_chains: int = 0, skin: float | None = None):
     q = _f64(q, (-1,))
     n = q.size
     pos = _f64(pos, (n, 3))
     box = _f64(box, (3,))
-    o = _opts(precision, device, stream, neutral_tol, mass, graphs, autotune, near_table, zero_mode, device_chains)
+    o = _opts(precision, device, stream, neutral_tol, mass, graphs, autotune, near_table, zero_mode, device_chains,
+              skin)
     ctx = ctypes.c_void_p()
     _check(lib().rbsog_init(ctypes.byref(ctx), n, _ptr(pos), _ptr(q), _ptr(box), ctypes.byref(sog), float(rc),
                             int(P), int(seed), ctypes.byref(o)))
@@ -161,7 +165,8 @@ def rbsog_init(pos, q, box, sog: rbsog_sog, rc: float, P: int, seed: int, precis
 
 def rbsog_init_batch(pos_list, q_list, boxes, sogs, rcs, Ps, seeds, precision: int = RBSOG_FP64, device: int = 0,
                      stream: int | None = None, neutral_tol: float = 1e-10, mass: float = 1.0, graphs: bool = True,
-                     autotune: bool = False, near_table: bool = False, zero_mode: int = 0, device_chains: int = 0):
+                     autotune: bool = False, near_table: bool = False, zero_mode: int = 0, device_chains: int = 0,
+                     skin: float | None = None):
     """One context over len(q_list) systems; particle arrays are concatenated."""
     ns = len(q_list)
     sizes = [int(np.asarray(qq).size) for qq in q_list]
@@ -174,7 +179,8 @@ def rbsog_init_batch(pos_list, q_list, boxes, sogs, rcs, Ps, seeds, precision: i
     rc = _f64(rcs, (ns,))
     Pa = np.ascontiguousarray(np.asarray(Ps, dtype=np.int32).reshape(ns))
     sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64).reshape(ns))
-    o = _opts(precision, device, stream, neutral_tol, mass, graphs, autotune, near_table, zero_mode, device_chains)
+    o = _opts(precision, device, stream, neutral_tol, mass, graphs, autotune, near_table, zero_mode, device_chains,
+              skin)
     ctx = ctypes.c_void_p()
     _check(lib().rbsog_init_batch(ctypes.byref(ctx), ns, _ptr(offsets), _ptr(pos), _ptr(q), _ptr(box),
                                   ctypes.cast(sog_arr, ctypes.c_void_p), _ptr(rc), _ptr(Pa), _ptr(sd),
@@ -262,8 +268,8 @@ def rbsog_info(ctx, sys: int = 0) -> dict:
     _check(lib().rbsog_info(ctx, int(sys), ctypes.byref(info)), ctx)
     return dict(S=info.S, volume=info.volume, ncell=tuple(info.ncell), k_remaining=info.k_remaining,
                 evaluations=info.evaluations, n=info.n, n_sys=info.n_sys,
-                near_cells_per_item=info.near_cells_per_item, rho_chunk=info.rho_chunk, far_block=info.far_block,
-                tuned=bool(info.tuned))
+                rho_chunk=info.rho_chunk, far_block=info.far_block, tuned=bool(info.tuned),
+                list_capacity=info.list_capacity, list_builds=info.list_builds, skin=info.skin)
 
 
 def rbsog_autotune(ctx, reps: int = 5) -> dict:

@@ -98,6 +98,12 @@ def test_option_and_batch_validation(lib):
     with pytest.raises(R.RbsogError) as e:
         R.rbsog_init_batch([pos, pos[:1]], [q, q[:1]], [box, box], [sog, sog], [3.0, 3.0], [10, 10], [1, 2])
     assert e.value.status == -1
+    # the near-list skin is a fraction of r_c in [0, 1]
+    for skin in (-0.1, 1.5, float("nan")):
+        with pytest.raises(R.RbsogError) as e:
+            R.rbsog_init(pos, q, box, sog, 3.0, 10, 1, skin=skin)
+        assert e.value.status == -1 and "skin" in str(e.value)
+    assert R.rbsog_default_opts().skin == 0.1
     # the number of device chains is bounded
     for lam in (-1, 4097):
         with pytest.raises(R.RbsogError) as e:

@@ -82,7 +82,7 @@ def test_mixed_batch_vs_oracle(orc, prec, tol):
             assert abs(got - want) / max(abs(want), 1.0) < tol * 10
         # cell and neighbour lists of the system, local indices, bit-exact
         start, order = R.rbsog_debug_cells(b.ctx, sys=i)
-        _, _, start_o, order_o = orc.cell_list(s["pos"], s["box"], s["rc"])
+        _, _, start_o, order_o = orc.cell_list(s["pos"], s["box"], s["rc"] * (1.0 + R.rbsog_default_opts().skin))
         assert (start == start_o).all() and (order == order_o).all()
         row, cols = R.rbsog_debug_neighbors(b.ctx, sys=i)
         row_o, cols_o = orc.neighbors_brute(s["pos"], s["box"], s["rc"])

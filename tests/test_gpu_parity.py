@@ -30,9 +30,16 @@ def say(*a):
     sys.stdout.flush()
 
 
-def make(pos, q, box, rc, P, seed=11, prec=R.RBSOG_FP64, sog=None):
-    say(f"[gpu] init n={len(q)} box={tuple(np.round(box, 3))} rc={rc} P={P} prec={prec}")
-    return R.System(pos, q, box, rc, P, seed=seed, precision=prec, sog=sog)
+def make(pos, q, box, rc, P, seed=11, prec=R.RBSOG_FP64, sog=None, **kw):
+    say(f"[gpu] init n={len(q)} box={tuple(np.round(box, 3))} rc={rc} P={P} prec={prec} {kw}")
+    return R.System(pos, q, box, rc, P, seed=seed, precision=prec, sog=sog, **kw)
+
+
+def cell_width(rc, skin=None):
+    """Cells of the near list are at least r_c (1 + skin) wide."""
+    if skin is None:
+        skin = R.rbsog_default_opts().skin
+    return rc * (1.0 + skin)
 
 
 def oracle_sog(orc, s: R.rbsog_sog):
@@ -82,8 +89,9 @@ def test_c1_one_evaluation(orc, prec, tol):
 
 
 @pytest.mark.parametrize("prec", [R.RBSOG_FP64, R.RBSOG_FP32C])
-@pytest.mark.parametrize("case", ["c1", "skew", "tiny", "manycells"])
-def test_cell_and_neighbour_lists_bit_exact(orc, prec, case):
+@pytest.mark.parametrize("case,skin", [("c1", None), ("c1", 0.0), ("c1", 0.3), ("skew", None), ("tiny", None),
+                                       ("manycells", None)])
+def test_cell_and_neighbour_lists_bit_exact(orc, prec, case, skin):
     if case == "c1":
         c = W.c1_small()
         pos, q, box, rc = c["pos"], c["q"], c["box"], c["rc"]
@@ -95,7 +103,7 @@ def test_cell_and_neighbour_lists_bit_exact(orc, prec, case):
         q[-1] = 0.0
         rc = 3.1
     elif case == "manycells":
-        # 66^3 = 287,496 cells: the cell-count scan takes its multi-block path
+        # 60^3 = 216,000 cells of width 1.1: the cell-count scan takes its multi-block path
         rng = np.random.default_rng(5)
         box = np.array([66.5, 66.5, 66.5])
         pos = rng.random((20000, 3)) * box
@@ -107,11 +115,11 @@ def test_cell_and_neighbour_lists_bit_exact(orc, prec, case):
         pos = rng.random((64, 3)) * box
         q = np.where(np.arange(64) % 2 == 0, 1.0, -1.0)
         rc = 2.9
-    sysm = make(pos, q, box, rc, 8, prec=prec)
+    sysm = make(pos, q, box, rc, 8, prec=prec, skin=skin)
     sysm.sample_k(1)
     sysm.forces()
     start, order = R.rbsog_debug_cells(sysm.ctx, len(q))
-    nc, _, start_o, order_o = orc.cell_list(pos, box, rc)
+    nc, _, start_o, order_o = orc.cell_list(pos, box, cell_width(rc, skin))
     assert tuple(R.rbsog_info(sysm.ctx)["ncell"]) == tuple(int(v) for v in nc)
     assert (start == start_o).all() and (order == order_o).all()
     row, cols = R.rbsog_debug_neighbors(sysm.ctx, len(q))
@@ -285,7 +293,7 @@ def test_autotune_keeps_results(orc, prec, tol):
     F0, E0 = sysm.forces()
     Fn0, Ff0 = sysm.components()
     info = R.rbsog_autotune(sysm.ctx, 2)
-    say(f"[autotune prec={prec}] shapes cpi={info['near_cells_per_item']} chunk={info['rho_chunk']} "
+    say(f"[autotune prec={prec}] shapes chunk={info['rho_chunk']} "
         f"far_block={info['far_block']} tuned={info['tuned']}")
     assert info["tuned"] and info["k_remaining"] == 2 * c["P"]
     # the tuning recomputed the forces of the same positions with the chosen shapes
@@ -421,3 +429,59 @@ def test_langevin_thermostat_holds_temperature():
     Tm = float(np.mean(temps))
     say(f"[thermostat] kinetic temperature {Tm:.4f} (target {T})")
     assert abs(Tm / T - 1.0) < 0.05
+
+
+@pytest.mark.parametrize("prec,tol", [(R.RBSOG_FP64, F64_TOL), (R.RBSOG_FP32C, F32C_TOL)])
+def test_near_list_rebuilds_keep_pairs_exact(orc, prec, tol):
+    # a hot system and a thin skin: the list is rebuilt many times during the
+    # run; after every chunk of steps (graphs and single eager steps) the near
+    # forces and the neighbour list at the current positions match the oracle
+    n, L, rc, P = 500, 12.0, 3.0, 30
+    pos, q, box = W.ions_rsa(n, n / L ** 3, 1.0, 41)
+    sysm = make(pos, q, box, rc, P, seed=5, prec=prec, skin=0.02)
+    sysm.sample_k(140)
+    R.rbsog_set_velocities(sysm.ctx, None, T=20.0, seed=8)
+    sog = oracle_sog(orc, sysm.sog)
+    builds = [R.rbsog_info(sysm.ctx)["list_builds"]]
+    skins = []
+    for chunk in (1, 6, 1, 9, 12, 1, 8, 40, 3, 50):
+        sysm.step(chunk, 2e-3)
+        x, _ = R.rbsog_get_state(sysm.ctx, n)
+        Fn, _ = sysm.components()
+        Fn_o, _ = orc.near_brute(x, q, box, rc, sog)
+        err = relrms(Fn, Fn_o)
+        row, cols = R.rbsog_debug_neighbors(sysm.ctx, n)
+        row_o, cols_o = orc.neighbors_brute(x, box, rc)
+        info = R.rbsog_info(sysm.ctx)
+        builds.append(info["list_builds"])
+        skins.append(info["skin"])
+        say(f"[list rebuilds prec={prec}] after {chunk} steps: builds {builds[-1]} skin {skins[-1]} "
+            f"near relrms {err:.3e}")
+        assert err < tol
+        assert (row == row_o).all() and (cols == cols_o).all()
+    assert builds[-1] - builds[0] >= 5
+    # lists this short-lived switch the steps to building every time
+    assert 0.0 in skins
+
+
+def test_near_list_skin_does_not_change_the_trajectory(orc):
+    # the skin only changes when the list is rebuilt, not which pairs are
+    # evaluated: trajectories with skins 0, 0.1 and 0.5 agree to rounding
+    n, L, rc, P, steps = 400, 11.0, 3.0, 40, 30
+    pos, q, box = W.ions_rsa(n, n / L ** 3, 1.0, 43)
+    out = []
+    for skin in (0.0, 0.1, 0.5):
+        sysm = make(pos, q, box, rc, P, seed=6, skin=skin)
+        sysm.sample_k(steps + 1)
+        R.rbsog_set_velocities(sysm.ctx, None, T=5.0, seed=9)
+        sysm.step(steps, 2e-3)
+        x, v = R.rbsog_get_state(sysm.ctx, n)
+        info = R.rbsog_info(sysm.ctx)
+        say(f"[skin {skin}] list builds {info['list_builds']} capacity {info['list_capacity']}")
+        out.append((x, v, info["list_builds"]))
+        sysm.close()
+    assert out[0][2] == steps + 1 and out[2][2] < out[1][2] < out[0][2]
+    for x, v, _ in out[1:]:
+        dx = x - out[0][0]
+        dx -= box * np.round(dx / box)
+        assert np.abs(dx).max() < 1e-10 and relrms(v, out[0][1]) < 1e-10
