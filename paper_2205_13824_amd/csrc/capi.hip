@@ -142,6 +142,10 @@ struct rbsog_ctx {
     // stream
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // second stream (default priority) on which the structure factor runs
+    // beside the near part, and the events of the fork and the join
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // device memory
     std::vector<void *> allocs;
     SysDev *dsys = nullptr;
@@ -544,17 +548,28 @@ rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt) {
     const bool f64 = c->prec == RBSOG_FP64;
     const EvalArgs a = make_args(c, stepping, dt);
     TRY(timed(c, K_KDQ, [&] { launch_kdq(a, s); }));
-    TRY(timed(c, K_BIN, [&] { launch_bin(a, s); }));
+    if (!a.always_build) TRY(timed(c, K_BIN, [&] { launch_bin(a, s); }));
     TRY(timed(c, K_SCAN, [&] { launch_scan(a, s); }));
     TRY(timed(c, K_SCATTER, [&] { launch_cell_scatter(a, s); }));
     TRY(timed(c, K_SORTG, [&] { launch_sort_gather(a, s); }));
+    // the structure factor needs the positions and the staged k records
+    // only: it runs on the side stream beside the near part (one stream
+    // while profiling, so that each kernel is timed alone)
+    const bool fork = !c->prof_on;
+    if (fork) {
+        HIPCHK(c, hipEventRecord(c->ev_fork, s));
+        HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+        launch_rho(a, f64, c->rho_items, c->n_rho, c->side);
+        HIPCHK(c, hipEventRecord(c->ev_join, c->side));
+    }
     if (a.always_build) {
         TRY(timed(c, K_NEAR, [&] { launch_near_cells(a, f64, c->near_items, c->n_near, s); }));
     } else {
         TRY(timed(c, K_LIST, [&] { launch_list_build(a, f64, c->list_items, c->n_list, c->build_slots, s); }));
         TRY(timed(c, K_NEAR, [&] { launch_near(a, f64, c->list_items, c->n_list, s); }));
     }
-    TRY(timed(c, K_RHO, [&] { launch_rho(a, f64, c->rho_items, c->n_rho, s); }));
+    if (fork) HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
+    else TRY(timed(c, K_RHO, [&] { launch_rho(a, f64, c->rho_items, c->n_rho, s); }));
     TRY(timed(c, K_RHORED, [&] { launch_rho_reduce(a, s); }));
     TRY(timed(c, K_FAR, [&] { launch_far(a, f64, c->far_items, c->n_far, c->tune.far_block, s); }));
     HIPCHK(c, hipGetLastError());
@@ -1398,6 +1413,12 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
         }
         c->own_stream = true;
     }
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        fail(c, RBSOG_E_DEVICE, "side stream or events");
+        return bail(RBSOG_E_DEVICE);
+    }
     const int64_t N = c->N, C = c->C, K = c->K;
     rbsog_status st = RBSOG_OK;
 #define ALLOC(ptr, cnt)                                   \
@@ -1957,6 +1978,12 @@ void rbsog_destroy(rbsog_ctx *c) {
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     drop_graphs(c);
     for (void *p : c->allocs) (void)hipFree(p);
+    if (c->side) {
+        (void)hipStreamSynchronize(c->side);
+        (void)hipStreamDestroy(c->side);
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }

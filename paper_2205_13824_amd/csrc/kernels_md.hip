@@ -164,12 +164,14 @@ __global__ __launch_bounds__(kBlock) void k_kdq(EvalArgs a, int32_t pblocks) {
         if (bad && valid) atomicOr(a.flag, 1);
     }
     float d2 = 0.f;
+    uint32_t uq[3];
     for (int d = 0; d < 3; ++d) {
         const double r = xs[d] / L[d];
         const double f = r - floor(r);
         double w = floor(f * kTwo32);
         w = w > kTwo32 - 1.0 ? kTwo32 - 1.0 : w;
         const uint32_t ud = (uint32_t)w;
+        uq[d] = ud;
         if (valid) {
             a.u_tmp[d * N + t] = ud;
             x[d * N + t] = f * L[d];
@@ -179,7 +181,13 @@ __global__ __launch_bounds__(kBlock) void k_kdq(EvalArgs a, int32_t pblocks) {
         d2 += dd * dd;
     }
     if (a.always_build) {
+        // every evaluation builds: the cell and the histogram here (no bin pass)
         if (blockIdx.x == 0 && threadIdx.x == 0) *a.rebuild = 1;
+        int64_t c[3];
+        for (int d = 0; d < 3; ++d) c[d] = (int64_t)(((uint64_t)uq[d] * (uint64_t)sd.g.nc[d]) >> 32);
+        const int64_t cell = sd.c0 + c[0] + (int64_t)sd.g.nc[0] * (c[1] + (int64_t)sd.g.nc[1] * c[2]);
+        if (valid) a.cell_of[t] = (int32_t)cell;
+        run_atomic_add(a.cell_count, cell, valid);
     } else {
         // one atomic per wave that found a particle past the threshold
         const bool far_ = valid && !(d2 <= dthr2);
