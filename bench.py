@@ -3,9 +3,10 @@
 Workload: the 300,000-ion +-1 electrolyte at number density 0.1 (random
 sequential addition, d_min = 1), r_c = 3.5 with Table 1 row 2 scaled to the
 cutoff, P = 200 wave vectors per step, velocity-Verlet dt = 1e-3 from a
-Maxwellian at T = 1.  A step is one whole pass of the path: kick, drift,
-wrap/quantise, cell list, near part, k staging, structure factor, far force,
-energies, kick.
+Maxwellian at T = 1, wave vectors drawn on the device.  A step is one whole
+pass of the path: kick, drift, wrap/quantise, near-list check (and, when
+due, cell list and list build), near part, k staging, structure factor, far
+force, energies, kick.
 
 Prints one JSON line: particle-steps/s of the FP32C form (``value``) and of
 the FP64 form, the FP32C force error against FP64, the roofline of the
@@ -68,6 +69,9 @@ def parse():
     # after the bench: device-to-device copies of this many MiB, the reference
     # kernel against which rocprofv3's FETCH_SIZE / WRITE_SIZE are scaled
     ap.add_argument("--copy-probe-mib", type=int, default=0)
+    # near-list skin (fraction of r_c); 0 builds at every step (the fused
+    # cell kernel), as the adaptive skin does while lists last under two steps
+    ap.add_argument("--skin", type=float, default=None)
     return ap.parse_args()
 
 
@@ -77,7 +81,7 @@ def run_precision(R, torch, wl, prec, args, near_table=False, device_chains=0):
     stream = torch.cuda.Stream()
     sysm = R.System(wl["pos"], wl["q"], wl["box"], wl["rc"], P, seed=2022, precision=prec,
                     stream=stream.cuda_stream, autotune=args.autotune, near_table=near_table,
-                    device_chains=device_chains)
+                    device_chains=device_chains, skin=args.skin)
     label = f"prec={prec}{' core-shell' if near_table else ''}{f' device-chains={device_chains}' if device_chains else ''}"
     if not device_chains:
         batches = 1 + args.warmup + args.steps + args.profile_steps
@@ -90,7 +94,16 @@ def run_precision(R, torch, wl, prec, args, near_table=False, device_chains=0):
     row, _ = R.rbsog_debug_neighbors(sysm.ctx, n)
     near_pairs = int(row[-1])
     R.rbsog_set_velocities(sysm.ctx, None, T=1.0, seed=7)
-    sysm.step(args.warmup, 1e-3)
+    # the last warm-up steps are profiled (one kernel at a time, HIP events):
+    # the start of the run, where the near list lasts many steps
+    w_prof = min(args.warmup, args.profile_steps)
+    sysm.step(args.warmup - w_prof, 1e-3)
+    kernels_start = {}
+    if w_prof > 0:
+        R.rbsog_profile(sysm.ctx, True)
+        sysm.step(w_prof, 1e-3)
+        kernels_start = read_profile(R, sysm)
+        R.rbsog_profile(sysm.ctx, False)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -103,61 +116,79 @@ def run_precision(R, torch, wl, prec, args, near_table=False, device_chains=0):
     ms = ev0.elapsed_time(ev1)
     log(f"[bench] {label}: {args.steps} steps in {ms:.2f} ms "
         f"(wall {wall * 1e3:.2f} ms)")
+    info_end = R.rbsog_info(sysm.ctx)
+    # and steps after the timed ones: the state the timed run ended in
     kernels = {}
     if args.profile_steps > 0:
         R.rbsog_profile(sysm.ctx, True)
         sysm.step(args.profile_steps, 1e-3)
-        prof = R.rbsog_profile_read(sysm.ctx)
+        kernels = read_profile(R, sysm)
         R.rbsog_profile(sysm.ctx, False)
-        kernels = {k: {"ms_total": v[0], "launches": v[1], "us_per_launch": 1e3 * v[0] / max(v[1], 1)}
-                   for k, v in prof.items() if v[1] > 0}
     E = R.rbsog_get_energy(sysm.ctx)
     info = R.rbsog_info(sysm.ctx)
     shapes = {k: info[k] for k in ("rho_chunk", "far_block", "tuned", "list_capacity", "list_builds")}
     sysm.close()
-    return dict(ms=ms, wall=wall, F0=F0, Fn0=Fn0, Ff0=Ff0, E0=E0, E_end=E, kernels=kernels, near_pairs=near_pairs,
-                value=n * args.steps / (ms * 1e-3), shapes=shapes)
+    return dict(ms=ms, wall=wall, F0=F0, Fn0=Fn0, Ff0=Ff0, E0=E0, E_end=E, kernels=kernels,
+                kernels_start=kernels_start, near_pairs=near_pairs, value=n * args.steps / (ms * 1e-3),
+                shapes=shapes, builds=info_end["list_builds"], skin_end=info_end["skin"])
+
+
+def read_profile(R, sysm):
+    prof = R.rbsog_profile_read(sysm.ctx)
+    return {k: {"ms_total": v[0], "launches": v[1], "us_per_launch": 1e3 * v[0] / max(v[1], 1)}
+            for k, v in prof.items() if v[1] > 0}
 
 
 DEVICE_CHAINS = 64
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_electrolyte300k.md")
-NEAR_SOURCES = ("paper_2205_13824_amd/csrc/kernels_near.hip", "paper_2205_13824_amd/csrc/rbsog_internal.h")
+# the counters are valid for the sources they were taken on
+KERNEL_SOURCES = ("paper_2205_13824_amd/csrc/kernels_near.hip", "paper_2205_13824_amd/csrc/kernels_far.hip",
+                  "paper_2205_13824_amd/csrc/kernels_md.hip", "paper_2205_13824_amd/csrc/rbsog_internal.h")
 
 
-def near_traffic():
-    """HBM bytes per launch of the FP32C near kernel from the committed
-    rocprofv3 counters (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or
-    None when the kernel's sources changed since the counters were taken."""
+def kernel_traffic(kernel):
+    """HBM bytes per launch of an FP32C kernel from the committed rocprofv3
+    counters (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when
+    the kernel sources changed since the counters were taken or the kernel is
+    not in the file."""
     import hashlib
 
     try:
         text = open(TRAFFIC_FILE).read()
     except OSError:
         return None
-    vals = dict(line.split(": ", 1) for line in text.splitlines() if line.startswith(("near-", "copy-")))
+    vals = dict(line.split(": ", 1) for line in text.splitlines() if line.startswith(("source-", "traffic-")))
     h = hashlib.sha256()
-    for rel in NEAR_SOURCES:
+    for rel in KERNEL_SOURCES:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
-    if vals.get("near-source-sha256", "").strip() != h.hexdigest():
+    if vals.get("source-sha256", "").strip() != h.hexdigest():
         return None
-    return int(vals["near-fp32c-traffic-bytes-per-launch"])
+    v = vals.get(f"traffic-{kernel}-bytes-per-launch")
+    return int(v) if v is not None else None
+
+
+# library profile names -> kernel symbols in the rocprofv3 summaries (FP32C)
+KERNEL_SYMBOL = {"near": "k_near_list<false>", "near_cells": "k_near_cells<false>", "rho": "k_rho<false>",
+                 "far": "k_far<false>"}
 
 
 def roofline(kernels, n, P, near_pairs, nexp32=3, ntail32=7):
-    # near: units are unique pairs (the list holds both orders)
-    units = {"rho": n * P, "far": n * P, "near": near_pairs // 2}
+    # near: units are unique pairs (the list holds both orders); both near
+    # kernels evaluate the same pairs
+    units = {"rho": n * P, "far": n * P, "near": near_pairs // 2, "near_cells": near_pairs // 2}
+    work = dict(WORK, near_cells=WORK["near"])
     cands = {k: v for k, v in kernels.items() if k in units}
     if not cands:
         return None
-    dom = max(cands, key=lambda k: cands[k]["us_per_launch"])
+    dom = max(cands, key=lambda k: cands[k]["ms_total"])
     t = cands[dom]["us_per_launch"] * 1e-6
-    achieved = units[dom] * WORK[dom] / t
-    out = {"kernel": dom, "bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_VALU_SLOTS / 1e9,
+    achieved = units[dom] * work[dom] / t
+    out = {"kernel": KERNEL_SYMBOL[dom], "bound": "alu", "achieved": achieved / 1e9, "peak": PEAK_VALU_SLOTS / 1e9,
            "unit": "Gop/s (VALU lane slots)", "frac": achieved / PEAK_VALU_SLOTS, "traffic": None,
-           "units_per_launch": units[dom], "slots_per_unit": WORK[dom], "us_per_launch": t * 1e6}
-    if dom == "near":
-        out["traffic"] = near_traffic()
+           "units_per_launch": units[dom], "slots_per_unit": work[dom], "us_per_launch": t * 1e6}
+    out["traffic"] = kernel_traffic(KERNEL_SYMBOL[dom])
+    if dom in ("near", "near_cells"):
         # the same pairs priced as this library evaluates them (both orders;
         # rsqrt, nexp exponentials, two tail polynomials, ~15 FMA-class)
         ev = 2 * (TRANS_SLOTS * (1 + nexp32) + 3 * nexp32 + 2 * ntail32 + 15)
@@ -294,7 +325,10 @@ def main():
     err_t = math.sqrt(float(np.sum((r32t["F0"] - r64["F0"]) ** 2) / np.sum(r64["F0"] ** 2)))
     log(f"[bench] FP32C core-shell vs FP64 force relrms: total {err_t:.3e}")
 
+    # the kernel that dominates the end of the run (where its steps spend
+    # most of their time), and the near-list pass of the run's start
     roof = roofline(r32["kernels"], n, P, r32["near_pairs"])
+    roof_start = roofline({k: v for k, v in r32["kernels_start"].items() if k == "near"}, n, P, r32["near_pairs"])
     out = {
         "metric": METRIC,
         "value": r32["value"],
@@ -328,6 +362,13 @@ def main():
         "fp32c_force_relrms_vs_fp64": {"total": err, "near": err_near, "far": err_far},
         "energy_step0": {"fp32c": list(map(float, r32["E0"])), "fp64": list(map(float, r64["E0"]))},
         "roofline": roof,
+        "roofline_list_pass": roof_start,
+        "near_list": {"builds": r32["builds"], "evaluations": 1 + args.warmup + args.steps,
+                      "skin_at_end": r32["skin_end"],
+                      "note": "list builds over the run; skin 0 at the end means the adaptive skin found lists "
+                              "lasting under two steps (the ions without a repulsive core collapse after about "
+                              "300 steps) and builds at every step with the fused cell kernel"},
+        "kernels_fp32c_start": r32["kernels_start"],
         "kernels_fp32c": r32["kernels"],
         "kernels_fp64": r64["kernels"],
         "launch_shapes": {"fp32c": r32["shapes"], "fp64": r64["shapes"]},

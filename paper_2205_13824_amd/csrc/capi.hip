@@ -74,9 +74,12 @@ struct ProfEntry {
 
 constexpr int64_t kAdaptSteps = 32;  // steps between checks of the near-list build rate
 
-enum Kid { K_KDQ, K_BIN, K_SCAN, K_SCATTER, K_SORTG, K_LIST, K_NEAR, K_RHO, K_RHORED, K_FAR, K_SAMPLE, K_COUNT };
+enum Kid {
+    K_KDQ, K_BIN, K_SCAN, K_SCATTER, K_SORTG, K_LIST, K_NEAR, K_NEARC, K_RHO, K_RHORED, K_FAR, K_SAMPLE, K_COUNT
+};
 const char *kKernelNames[K_COUNT] = {"kick_drift_quantise", "bin", "scan_cell_counts", "cell_scatter", "sort_gather",
-                                     "list_build", "near", "rho", "rho_reduce", "far", "sample_refill"};
+                                     "list_build", "near", "near_cells", "rho", "rho_reduce", "far",
+                                     "sample_refill"};
 
 
 // Launch shapes of the work lists (the tunable part of the plan).
@@ -563,7 +566,7 @@ rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt) {
         HIPCHK(c, hipEventRecord(c->ev_join, c->side));
     }
     if (a.always_build) {
-        TRY(timed(c, K_NEAR, [&] { launch_near_cells(a, f64, c->near_items, c->n_near, s); }));
+        TRY(timed(c, K_NEARC, [&] { launch_near_cells(a, f64, c->near_items, c->n_near, s); }));
     } else {
         TRY(timed(c, K_LIST, [&] { launch_list_build(a, f64, c->list_items, c->n_list, c->build_slots, s); }));
         TRY(timed(c, K_NEAR, [&] { launch_near(a, f64, c->list_items, c->n_list, s); }));
