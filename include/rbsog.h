@@ -225,6 +225,23 @@ rbsog_status rbsog_set_velocities(rbsog_ctx *ctx, const double *v, double T, uin
  * gamma = 0 restores NVE velocity Verlet.  E_ARG for gamma < 0 or T < 0. */
 rbsog_status rbsog_set_thermostat(rbsog_ctx *ctx, double gamma, double T, uint64_t seed);
 
+/* Nose-Hoover thermostat (the thermostat of Sec. 5's water runs) for the
+ * steps of rbsog_step: one variable xi per system with thermostat mass
+ * Q = N_f T tau^2, N_f = 3 n_s - 3.  Each step: xi += dt/2 (2K - N_f T)/Q with
+ * the kinetic energy K of the step's start, v *= exp(-xi dt/2), the
+ * velocity-Verlet kick, drift, force and kick, v *= exp(-xi dt/2), then
+ * xi += dt/2 (2K' - N_f T)/Q with the new K'.  tau = 0 turns it off; tau > 0
+ * turns a Langevin thermostat off, and rbsog_set_thermostat with gamma > 0
+ * turns this one off.  xi starts at 0.  E_ARG for tau < 0, or T <= 0 with
+ * tau > 0. */
+rbsog_status rbsog_set_nose_hoover(rbsog_ctx *ctx, double T, double tau);
+
+/* Kinetic energy K = m/2 sum |v|^2 of every system after the latest
+ * evaluation (or as set by rbsog_set_velocities), and the Nose-Hoover xi of
+ * every system (0 without that thermostat): host n_sys doubles each, either
+ * may be NULL.  Each system's K is summed on the device in a fixed order. */
+rbsog_status rbsog_get_kinetic(rbsog_ctx *ctx, double *K, double *xi);
+
 /* Replaces the positions (host n x 3, finite); forces become unknown. */
 rbsog_status rbsog_set_positions(rbsog_ctx *ctx, const double *pos);
 

@@ -111,7 +111,8 @@ struct SysHost {
     int32_t zmode = 0;
     double zu = 0.0, zf = 0.0;
     // work lists
-    int32_t it0 = 0, it1 = 0, jt0 = 0, jt1 = 0, nch = 0, kt = 1, streams = 1;
+    int32_t it0 = 0, it1 = 0, jt0 = 0, jt1 = 0, ft0 = 0, ft1 = 0, nch = 0, kt = 1, streams = 1;
+    double nh_nf = 0.0, nh_Q = 0.0;  // Nose-Hoover: degrees of freedom, thermostat mass
     int64_t pofs = 0, choff = 0;
     // sequence
     MHChain chain;
@@ -176,6 +177,13 @@ struct rbsog_ctx {
     KRec32 *kb32 = nullptr;
     double *wk = nullptr, *rho = nullptr, *ek = nullptr, *partial = nullptr, *epart = nullptr, *E = nullptr;
     double *dip_part = nullptr, *dipole = nullptr;
+    // kinetic energy per far item and per system, finished far items per system
+    double *kpart = nullptr, *kin = nullptr;
+    uint32_t *far_done = nullptr;
+    // Nose-Hoover thermostat: on, target temperature, tau, xi per system
+    bool nh_on = false;
+    double nh_T = 0.0, nh_tau = 0.0;
+    double *nh_xi = nullptr;
     // Langevin thermostat
     double gamma = 0.0, temp = 0.0;
     uint64_t tseed = 0;
@@ -415,6 +423,10 @@ SysDev sysdev_of(const SysHost &h) {
     d.it1 = h.it1;
     d.jt0 = h.jt0;
     d.jt1 = h.jt1;
+    d.ft0 = h.ft0;
+    d.ft1 = h.ft1;
+    d.nh_nf = h.nh_nf;
+    d.nh_Q = h.nh_Q;
     d.pofs = h.pofs;
     d.nch = h.nch;
     d.kt = h.kt;
@@ -533,6 +545,13 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
     a.kick = stepping ? 1 : 0;
     a.hdm = 0.5 * dt / c->mass;
     a.dt = dt;
+    a.mass = c->mass;
+    a.kpart = c->kpart;
+    a.kin = c->kin;
+    a.far_done = c->far_done;
+    a.nh = c->nh_on ? 1 : 0;
+    a.nh_T = c->nh_T;
+    a.nh_xi = c->nh_xi;
     a.thermo = c->gamma > 0.0 ? 1 : 0;
     a.c1 = std::exp(-c->gamma * dt);
     a.c2 = std::sqrt((1.0 - a.c1 * a.c1) * c->temp / c->mass);
@@ -1078,8 +1097,10 @@ void build_work(rbsog_ctx *c, const Tune &t, std::vector<ListItem> &near, std::v
         pofs += (int64_t)h.nch * h.P;
         h.choff = choff;
         choff += h.nch;
+        h.ft0 = (int32_t)far.size();
         for (int64_t i = 0; i < h.n; i += fb)
             far.push_back(FarItem{s, 0, h.p0 + i, h.p0 + std::min(h.n, i + fb)});
+        h.ft1 = (int32_t)far.size();
     }
 }
 
@@ -1473,6 +1494,10 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
             c->sys[s].tbl = dtab + (int64_t)s * kTabSize;
         }
     }
+    ALLOC(kpart, far_cap);
+    ALLOC(kin, nsys);
+    ALLOC(nh_xi, nsys);
+    ALLOC(far_done, nsys);
     ALLOC(list_items, near_cap);
     ALLOC(near_items, C);
     ALLOC(epart_cells, C);
@@ -1519,6 +1544,11 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
                   hipMemcpy(c->kcur, zc.data(), nsys * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->tstep, zc.data(), sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->sys_done, zu.data(), nsys * sizeof(uint32_t), hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(c->far_done, zu.data(), nsys * sizeof(uint32_t), hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(c->kin, std::vector<double>(nsys, 0.0).data(), nsys * sizeof(double),
+                            hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(c->nh_xi, std::vector<double>(nsys, 0.0).data(), nsys * sizeof(double),
+                            hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->flag, &zf, sizeof zf, hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemset(c->cell_count, 0, (size_t)C * sizeof(int32_t)) == hipSuccess;
         if (!ok) {
@@ -1719,11 +1749,27 @@ rbsog_status rbsog_step(rbsog_ctx *c, int64_t n_steps, double dt) {
     return RBSOG_OK;
 }
 
+// Kinetic energy of every system from velocities given in the caller's order
+// (n x 3), summed in particle order, uploaded as the systems' current values.
+static rbsog_status upload_kinetic(rbsog_ctx *c, const double *v) {
+    std::vector<double> K((size_t)c->nsys, 0.0);
+    for (int32_t s = 0; s < c->nsys; ++s) {
+        const SysHost &h = c->sys[s];
+        double acc = 0.0;
+        for (int64_t i = h.p0; i < h.p0 + h.n; ++i)
+            acc += (v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1]) + v[3 * i + 2] * v[3 * i + 2];
+        K[s] = 0.5 * c->mass * acc;
+    }
+    HIPCHK(c, hipMemcpy(c->kin, K.data(), K.size() * sizeof(double), hipMemcpyHostToDevice));
+    return RBSOG_OK;
+}
+
 rbsog_status rbsog_set_velocities(rbsog_ctx *c, const double *v, double T, uint64_t seed) {
     TRY(check_ctx(c));
     if (v) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
-        return upload_by_id(c, v, c->buf[0].v, "velocity");
+        TRY(upload_by_id(c, v, c->buf[0].v, "velocity"));
+        return upload_kinetic(c, v);
     }
     if (!(T >= 0.0) || !std::isfinite(T)) return fail(c, RBSOG_E_ARG, "temperature must be >= 0");
     const double sd = std::sqrt(T / c->mass);
@@ -1747,7 +1793,8 @@ rbsog_status rbsog_set_velocities(rbsog_ctx *c, const double *v, double T, uint6
         }
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    return upload_by_id(c, vv.data(), c->buf[0].v, "velocity");
+    TRY(upload_by_id(c, vv.data(), c->buf[0].v, "velocity"));
+    return upload_kinetic(c, vv.data());
 }
 
 rbsog_status rbsog_set_thermostat(rbsog_ctx *c, double gamma, double T, uint64_t seed) {
@@ -1758,9 +1805,44 @@ rbsog_status rbsog_set_thermostat(rbsog_ctx *c, double gamma, double T, uint64_t
     c->gamma = gamma;
     c->temp = T;
     c->tseed = seed;
+    if (gamma > 0.0) c->nh_on = false;  // one thermostat at a time
     const int64_t z = 0;
     HIPCHK(c, hipMemcpy(c->tstep, &z, sizeof z, hipMemcpyHostToDevice));
     drop_graphs(c);  // the graphs hold the step's constants
+    return RBSOG_OK;
+}
+
+rbsog_status rbsog_set_nose_hoover(rbsog_ctx *c, double T, double tau) {
+    TRY(check_ctx(c));
+    if (!(tau >= 0.0) || !std::isfinite(tau) || !std::isfinite(T) || (tau > 0.0 && !(T > 0.0)))
+        return fail(c, RBSOG_E_ARG, "need tau >= 0, and T > 0 when tau > 0");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->nh_on = tau > 0.0;
+    c->nh_T = T;
+    c->nh_tau = tau;
+    for (int32_t s = 0; s < c->nsys; ++s) {
+        SysHost &h = c->sys[s];
+        h.nh_nf = 3.0 * (double)h.n - 3.0;
+        h.nh_Q = c->nh_on ? h.nh_nf * T * tau * tau : 0.0;
+        TRY(upload_sysdev(c, s));
+    }
+    const std::vector<double> zero((size_t)c->nsys, 0.0);
+    HIPCHK(c, hipMemcpy(c->nh_xi, zero.data(), zero.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (c->nh_on) {
+        c->gamma = 0.0;  // one thermostat at a time
+        std::vector<double> v((size_t)3 * c->N);
+        TRY(download_by_id(c, c->buf[0].v, v.data()));
+        TRY(upload_kinetic(c, v.data()));
+    }
+    drop_graphs(c);  // the graphs hold the step's constants
+    return RBSOG_OK;
+}
+
+rbsog_status rbsog_get_kinetic(rbsog_ctx *c, double *K, double *xi) {
+    TRY(check_ctx(c));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (K) HIPCHK(c, hipMemcpy(K, c->kin, (size_t)c->nsys * sizeof(double), hipMemcpyDeviceToHost));
+    if (xi) HIPCHK(c, hipMemcpy(xi, c->nh_xi, (size_t)c->nsys * sizeof(double), hipMemcpyDeviceToHost));
     return RBSOG_OK;
 }
 

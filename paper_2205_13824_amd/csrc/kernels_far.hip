@@ -369,8 +369,15 @@ __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
 // uniformly; items are runs of up to 256 slots of one system (grid-stride).
 // The near-list rebuild flag is cleared here: every kernel of the
 // evaluation that reads it has run.
+//
+// The kinetic energy of each item's particles after the evaluation is summed
+// in a fixed order into the item's partial; the block that finishes a
+// system's last item sums its partials (fixed order) into the system's
+// kinetic energy and, for a Nose-Hoover step, moves xi its second half step.
 template <bool F64>
 __global__ __launch_bounds__(256) void k_far(EvalArgs a, const FarItem *__restrict__ items, int32_t nitems) {
+    __shared__ double kw[256];
+    __shared__ int32_t last;
     const int64_t n = a.N;
     if (blockIdx.x == 0 && threadIdx.x == 0 && a.rebuild) *a.rebuild = 0;
     for (int32_t itx = blockIdx.x; itx < nitems; itx += gridDim.x) {
@@ -456,6 +463,7 @@ __global__ __launch_bounds__(256) void k_far(EvalArgs a, const FarItem *__restri
             const double qi = -(double)a.cur.qf[i];
             Fx = qi * (Fx + fx); Fy = qi * (Fy + fy); Fz = qi * (Fz + fz);
         }
+        double ke = 0.0;
         if (valid) {
             if (sp->zmode != 0) {
                 const double qi = a.cur.q[i], c = sp->zf * qi;
@@ -469,17 +477,63 @@ __global__ __launch_bounds__(256) void k_far(EvalArgs a, const FarItem *__restri
             a.Ff[i] = Fx;
             a.Ff[n + i] = Fy;
             a.Ff[2 * n + i] = Fz;
+            double vv[3] = {a.cur.v[i], a.cur.v[n + i], a.cur.v[2 * n + i]};
             if (a.kick) {
                 // closing half kick of the velocity-Verlet step
                 const double f[3] = {a.Fn[i] + Fx, a.Fn[n + i] + Fy, a.Fn[2 * n + i] + Fz};
                 bool bad = false;
                 for (int d = 0; d < 3; ++d) {
                     bad |= !isfinite(f[d]);
-                    a.cur.v[d * n + i] += a.hdm * f[d];
+                    vv[d] += a.hdm * f[d];
                 }
+                if (a.nh) {
+                    // Nose-Hoover: the second scaling with the step's half-step xi
+                    // (xi and the kinetic energy still hold the step's start)
+                    const double xh = a.nh_xi[sys] + 0.5 * a.dt * (2.0 * a.kin[sys] - sp->nh_nf * a.nh_T) / sp->nh_Q;
+                    const double sc = exp(-0.5 * a.dt * xh);
+                    for (int d = 0; d < 3; ++d) vv[d] *= sc;
+                }
+                for (int d = 0; d < 3; ++d) a.cur.v[d * n + i] = vv[d];
                 if (bad) atomicOr(a.flag, 1);
             }
+            ke = 0.5 * a.mass * ((vv[0] * vv[0] + vv[1] * vv[1]) + vv[2] * vv[2]);
         }
+        // the item's kinetic energy: lanes in a fixed tree, then the waves in order
+        kw[threadIdx.x] = ke;
+        __syncthreads();
+        for (int o = blockDim.x >> 1; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) kw[threadIdx.x] += kw[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            a.kpart[itx] = kw[0];
+            __threadfence();
+            last = atomicAdd(&a.far_done[sys], 1u) == (uint32_t)(sp->ft1 - sp->ft0 - 1) ? 1 : 0;
+        }
+        __syncthreads();
+        if (last) {
+            __threadfence();
+            const int32_t f0 = sp->ft0, f1 = sp->ft1;
+            double s = 0.0;
+            for (int32_t j = f0 + (int32_t)threadIdx.x; j < f1; j += blockDim.x) s += a.kpart[j];
+            kw[threadIdx.x] = s;
+            __syncthreads();
+            for (int o = blockDim.x >> 1; o > 0; o >>= 1) {
+                if ((int)threadIdx.x < o) kw[threadIdx.x] += kw[threadIdx.x + o];
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) {
+                const double K = kw[0];
+                if (a.kick && a.nh) {
+                    const double nf = sp->nh_nf, Q = sp->nh_Q;
+                    const double xh = a.nh_xi[sys] + 0.5 * a.dt * (2.0 * a.kin[sys] - nf * a.nh_T) / Q;
+                    a.nh_xi[sys] = xh + 0.5 * a.dt * (2.0 * K - nf * a.nh_T) / Q;
+                }
+                a.kin[sys] = K;
+                a.far_done[sys] = 0u;
+            }
+        }
+        __syncthreads();
     }
 }
 

@@ -140,6 +140,15 @@ __global__ __launch_bounds__(kBlock) void k_kdq(EvalArgs a, int32_t pblocks) {
             f[d] = a.Fn[d * N + t] + a.Ff[d * N + t];
             vs[d] = v[d * N + t];
         }
+        if (a.nh) {
+            // Nose-Hoover: xi's first half step with the kinetic energy of the
+            // step's start, then v scaled by exp(-xi dt/2) (the far kernel
+            // scales again after the closing kick and moves xi on)
+            const int32_t s = a.sys_of[t];
+            const double xh = a.nh_xi[s] + 0.5 * a.dt * (2.0 * a.kin[s] - sd.nh_nf * a.nh_T) / sd.nh_Q;
+            const double sc = exp(-0.5 * a.dt * xh);
+            for (int d = 0; d < 3; ++d) vs[d] *= sc;
+        }
         bool bad = false;
         if (a.thermo) {
             // BAOAB: half kick, half drift, Ornstein-Uhlenbeck, half drift

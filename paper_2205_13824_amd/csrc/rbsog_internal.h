@@ -109,6 +109,9 @@ struct SysDev {
     int32_t zmode;
     double zu, zf;
     int64_t choff;        // first structure-factor chunk of the system over the batch
+    int32_t ft0, ft1;     // far items [ft0, ft1)
+    // Nose-Hoover thermostat: degrees of freedom 3n - 3 and thermostat mass N_f T tau^2
+    double nh_nf, nh_Q;
 };
 
 // Near item of the build-every-evaluation mode: a run of cells of one system.
@@ -184,6 +187,15 @@ struct EvalArgs {
     // velocity-Verlet
     int32_t kick;          // nonzero: kick + drift before, kick after
     double hdm, dt;
+    double mass;
+    // kinetic energy per far item, per system (after the evaluation), and the
+    // per-system counters of finished far items
+    double *kpart, *kin;
+    uint32_t *far_done;
+    // Nose-Hoover thermostat (nh != 0): xi per system, target temperature
+    int32_t nh;
+    double nh_T;
+    double *nh_xi;
     // Langevin thermostat (BAOAB): half drift, v <- c1 v + c2 xi, half drift
     int32_t thermo;
     double c1, c2;

@@ -31,7 +31,8 @@ EXPORTS = ("rbsog_default_opts", "rbsog_sog_table1", "rbsog_init", "rbsog_init_b
            "rbsog_step", "rbsog_set_velocities", "rbsog_set_positions", "rbsog_get_state", "rbsog_get_forces",
            "rbsog_get_energy", "rbsog_get_rho", "rbsog_info", "rbsog_debug_cells", "rbsog_debug_neighbors",
            "rbsog_profile", "rbsog_profile_read", "rbsog_sync", "rbsog_last_error", "rbsog_status_string",
-           "rbsog_destroy", "rbsog_autotune", "rbsog_set_thermostat", "rbsog_get_kbatch")
+           "rbsog_destroy", "rbsog_autotune", "rbsog_set_thermostat", "rbsog_get_kbatch",
+           "rbsog_set_nose_hoover", "rbsog_get_kinetic")
 
 
 class RbsogError(RuntimeError):
@@ -87,6 +88,8 @@ def lib():
             "rbsog_get_energy": (i32, [vp, vp]),
             "rbsog_get_rho": (i32, [vp, i32, vp, vp]),
             "rbsog_get_kbatch": (i32, [vp, i32, vp]),
+            "rbsog_set_nose_hoover": (i32, [vp, dbl, dbl]),
+            "rbsog_get_kinetic": (i32, [vp, vp, vp]),
             "rbsog_info": (i32, [vp, i32, P(rbsog_info_t)]),
             "rbsog_debug_cells": (i32, [vp, i32, vp, vp]),
             "rbsog_debug_neighbors": (i32, [vp, i32, vp, vp, i64]),
@@ -261,6 +264,19 @@ def rbsog_get_kbatch(ctx, P: int, sys: int = 0):
     m = np.zeros((P, 3), dtype=np.int32)
     _check(lib().rbsog_get_kbatch(ctx, int(sys), _ptr(m)), ctx)
     return m
+
+
+def rbsog_set_nose_hoover(ctx, T: float, tau: float):
+    _check(lib().rbsog_set_nose_hoover(ctx, float(T), float(tau)), ctx)
+
+
+def rbsog_get_kinetic(ctx):
+    """(K, xi): kinetic energy and Nose-Hoover xi of every system."""
+    ns = n_systems(ctx)
+    K = np.zeros(ns)
+    xi = np.zeros(ns)
+    _check(lib().rbsog_get_kinetic(ctx, _ptr(K), _ptr(xi)), ctx)
+    return K, xi
 
 
 def rbsog_info(ctx, sys: int = 0) -> dict:

@@ -1,0 +1,120 @@
+"""Nose-Hoover thermostat and the kinetic-energy observable through the C ABI,
+against the oracle's Nose-Hoover loop (the same splitting, FP64) on the same
+wave-vector batches."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2205_13824_amd import rbsog as R
+from paper_2205_13824_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def relrms(a, b):
+    return math.sqrt(float(np.sum((a - b) ** 2)) / float(np.sum(b ** 2)))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_sog(orc, s: R.rbsog_sog):
+    return orc.SOG(s.b, s.sigma, s.w0, s.M)
+
+
+@pytest.mark.parametrize("prec,tol", [(R.RBSOG_FP64, 1e-10), (R.RBSOG_FP32C, 1e-5)])
+def test_nose_hoover_steps_match_oracle(orc, prec, tol):
+    from oracle import thermostat as th
+    n, L = 300, 14.0
+    pos, q, box = W.ions_rsa(n, n / L ** 3, 1.0, 81)
+    v0 = W.maxwellian(n, 0.5, 82)
+    rc, P, dt, T, tau, steps = 3.5, 40, 2e-3, 1.5, 0.05, 6
+    out = []
+    for graphs in (False, True):
+        say(f"[gpu] nose-hoover prec={prec} graphs={graphs}")
+        sysm = R.System(pos, q, box, rc, P, seed=8, precision=prec, graphs=graphs)
+        ks = sysm.sample_k(steps + 1)
+        R.rbsog_set_velocities(sysm.ctx, v0)
+        R.rbsog_set_nose_hoover(sysm.ctx, T, tau)
+        sysm.step(steps, dt)
+        x, v = R.rbsog_get_state(sysm.ctx, n)
+        K, xi = R.rbsog_get_kinetic(sysm.ctx)
+        out.append((x, v, K, xi))
+        sysm.close()
+    for a, b in zip(out[0], out[1]):
+        assert (a == b).all()
+    x, v, K, xi = out[0]
+    xo, vo, xio, _, hist = th.nose_hoover_run(orc, pos, v0, q, box, rc, oracle_sog(orc, R.rbsog_sog_table1(2, rc)),
+                                              P, ks, steps, dt, T, tau)
+    dx = x - xo
+    dx -= box * np.round(dx / box)
+    ex, ev = float(np.abs(dx).max()), relrms(v - v0, vo - v0)
+    say(f"[nose-hoover prec={prec}] max|dx| {ex:.2e} dv relrms {ev:.2e} xi {xi[0]:.10g} vs {xio:.10g} "
+        f"K {K[0]:.10g} vs {hist[-1][1]:.10g}")
+    assert abs(xio) > 1e-3  # the thermostat acted
+    assert ex < 10 * tol and ev < 10 * tol
+    assert abs(xi[0] - xio) < 10 * tol * abs(xio) and abs(K[0] - hist[-1][1]) < 10 * tol * hist[-1][1]
+
+
+def test_kinetic_energy_of_every_system():
+    specs = [(1000, 10.0, 3.0, 50, 61), (500, 9.0, 2.9, 37, 62), (64, 6.0, 2.9, 20, 63)]
+    pos_l, q_l, boxes = [], [], []
+    for nn, L, rc, P, sd in specs:
+        p_, q_, b_ = W.ions_uniform(nn, L, sd)
+        pos_l.append(p_), q_l.append(q_), boxes.append(b_)
+    b = R.Batch(pos_l, q_l, boxes, [s[2] for s in specs], [s[3] for s in specs], [s[4] for s in specs],
+                precision=R.RBSOG_FP64, mass=1.7, device_chains=4)
+    R.rbsog_set_velocities(b.ctx, None, T=2.0, seed=5)
+    sizes = b.sizes
+    for stage in ("set", "forces", "steps"):
+        if stage == "forces":
+            b.forces()
+        elif stage == "steps":
+            R.rbsog_step(b.ctx, 7, 1e-3)
+        _, v = R.rbsog_get_state(b.ctx, b.n)
+        K, xi = R.rbsog_get_kinetic(b.ctx)
+        want = [0.5 * 1.7 * float((vs * vs).sum()) for vs in np.split(v, np.cumsum(sizes)[:-1])]
+        say(f"[kinetic {stage}] {K} vs {want}")
+        assert np.allclose(K, want, rtol=1e-12, atol=0) and (xi == 0).all()
+
+
+def test_nose_hoover_off_is_velocity_verlet():
+    n, L = 300, 14.0
+    pos, q, box = W.ions_rsa(n, n / L ** 3, 1.0, 83)
+    out = []
+    for setit in (False, True):
+        sysm = R.System(pos, q, box, 3.5, 40, seed=8, precision=R.RBSOG_FP64)
+        sysm.sample_k(12)
+        R.rbsog_set_velocities(sysm.ctx, None, T=1.0, seed=3)
+        if setit:
+            R.rbsog_set_nose_hoover(sysm.ctx, 2.0, 0.1)
+            R.rbsog_set_nose_hoover(sysm.ctx, 2.0, 0.0)
+        sysm.step(10, 1e-3)
+        out.append(R.rbsog_get_state(sysm.ctx, n))
+        sysm.close()
+    assert (out[0][0] == out[1][0]).all() and (out[0][1] == out[1][1]).all()
+
+
+def test_nose_hoover_holds_temperature():
+    # weak charges, as for the Langevin check: the kinetic temperature
+    # oscillates about T with the thermostat's period and averages to T
+    n = 512
+    pos, q, box = W.ions_rsa(n, 0.1, 1.0, 84)
+    q = 0.1 * q
+    T, tau = 1.5, 0.05
+    sysm = R.System(pos, q, box, 3.5, 50, seed=9, precision=R.RBSOG_FP32C, device_chains=16)
+    R.rbsog_set_velocities(sysm.ctx, None, T=0.3, seed=4)
+    R.rbsog_set_nose_hoover(sysm.ctx, T, tau)
+    sysm.step(500, 2e-3)
+    temps = []
+    for _ in range(60):
+        sysm.step(25, 2e-3)
+        K, _ = R.rbsog_get_kinetic(sysm.ctx)
+        temps.append(2.0 * K[0] / (3 * n - 3))
+    Tm = float(np.mean(temps))
+    say(f"[nose-hoover] kinetic temperature {Tm:.4f} (target {T})")
+    assert abs(Tm / T - 1.0) < 0.05
