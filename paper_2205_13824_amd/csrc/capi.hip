@@ -177,9 +177,8 @@ struct rbsog_ctx {
     KRec32 *kb32 = nullptr;
     double *wk = nullptr, *rho = nullptr, *ek = nullptr, *partial = nullptr, *epart = nullptr, *E = nullptr;
     double *dip_part = nullptr, *dipole = nullptr;
-    // kinetic energy per far item and per system, finished far items per system
+    // kinetic energy per far item and wave, and per system
     double *kpart = nullptr, *kin = nullptr;
-    uint32_t *far_done = nullptr;
     // Nose-Hoover thermostat: on, target temperature, tau, xi per system
     bool nh_on = false;
     double nh_T = 0.0, nh_tau = 0.0;
@@ -206,11 +205,12 @@ struct rbsog_ctx {
     Tune tune;
     bool tuned = false, autotune = false;
     std::string tune_key;
-    // graph of one velocity-Verlet step
+    // graph of one velocity-Verlet step, one per near mode (0: list kept,
+    // 1: every step builds), so that the adaptive skin's switches reuse them
     bool use_graphs = true;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    double graph_dt = 0.0;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+    double graph_dt_m[2] = {0.0, 0.0};
     // profiling
     bool prof_on = false;
     ProfEntry prof[K_COUNT];
@@ -548,7 +548,6 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
     a.mass = c->mass;
     a.kpart = c->kpart;
     a.kin = c->kin;
-    a.far_done = c->far_done;
     a.nh = c->nh_on ? 1 : 0;
     a.nh_T = c->nh_T;
     a.nh_xi = c->nh_xi;
@@ -594,6 +593,7 @@ rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt) {
     else TRY(timed(c, K_RHO, [&] { launch_rho(a, f64, c->rho_items, c->n_rho, s); }));
     TRY(timed(c, K_RHORED, [&] { launch_rho_reduce(a, s); }));
     TRY(timed(c, K_FAR, [&] { launch_far(a, f64, c->far_items, c->n_far, c->tune.far_block, s); }));
+    launch_kinetic(a, s);
     HIPCHK(c, hipGetLastError());
     return RBSOG_OK;
 }
@@ -619,18 +619,27 @@ void account_eval(rbsog_ctx *c) {
 }
 
 void drop_graphs(rbsog_ctx *c) {
-    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
-    c->graph_exec = nullptr;
-    c->graph = nullptr;
+    for (int m = 0; m < 2; ++m) {
+        if (c->graph_exec[m]) (void)hipGraphExecDestroy(c->graph_exec[m]);
+        if (c->graph[m]) (void)hipGraphDestroy(c->graph[m]);
+        c->graph_exec[m] = nullptr;
+        c->graph[m] = nullptr;
+    }
 }
 
+int graph_mode(const rbsog_ctx *c) { return c->skin_cur > 0.0 ? 0 : 1; }
+
 // The graph of one step captures the kernel arguments; it is rebuilt when dt
-// or a buffer changes.  Sequence buffers are reached through the per-system
-// table, so re-sampling does not invalidate it.
+// or a buffer changes.  Sequence buffers, the cell grid and the cell-run
+// items are reached through device tables, so re-sampling and the adaptive
+// skin's switches (one graph per near mode) do not invalidate it.
 rbsog_status ensure_step_graphs(rbsog_ctx *c, double dt) {
-    if (c->graph_exec && c->graph_dt == dt) return RBSOG_OK;
-    drop_graphs(c);
+    const int m = graph_mode(c);
+    if (c->graph_exec[m] && c->graph_dt_m[m] == dt) return RBSOG_OK;
+    if (c->graph_exec[m]) (void)hipGraphExecDestroy(c->graph_exec[m]);
+    if (c->graph[m]) (void)hipGraphDestroy(c->graph[m]);
+    c->graph_exec[m] = nullptr;
+    c->graph[m] = nullptr;
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
     rbsog_status st = enqueue_eval(c, true, dt);
     hipGraph_t g = nullptr;
@@ -640,13 +649,13 @@ rbsog_status ensure_step_graphs(rbsog_ctx *c, double dt) {
         return st;
     }
     if (e != hipSuccess) return fail(c, RBSOG_E_DEVICE, "stream capture: %s", hipGetErrorString(e));
-    c->graph = g;
-    e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+    c->graph[m] = g;
+    e = hipGraphInstantiate(&c->graph_exec[m], g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         drop_graphs(c);
         return fail(c, RBSOG_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
     }
-    c->graph_dt = dt;
+    c->graph_dt_m[m] = dt;
     return RBSOG_OK;
 }
 
@@ -664,7 +673,8 @@ rbsog_status apply_skin(rbsog_ctx *c, double skin) {
     c->skin_cur = skin;
     c->build_slots = build_slots_for(c);
     TRY(upload_cell_items(c));
-    drop_graphs(c);
+    // each mode keeps its own step graph (the grid and items are read from
+    // device tables; the build's slots per pass are fixed per mode)
     return request_build(c);
 }
 
@@ -1147,6 +1157,8 @@ rbsog_status apply_tune(rbsog_ctx *c, const Tune &t) {
     c->n_list = (int32_t)near.size();
     c->n_rho = (int32_t)rho.size();
     c->n_far = (int32_t)far.size();
+    // wave slots of the kinetic-energy partials that a smaller far block leaves unused stay 0
+    HIPCHK(c, hipMemset(c->kpart, 0, (size_t)4 * c->n_far * sizeof(double)));
     for (int32_t s = 0; s < c->nsys; ++s) TRY(upload_sysdev(c, s));
     c->tune = t;
     drop_graphs(c);
@@ -1494,10 +1506,9 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
             c->sys[s].tbl = dtab + (int64_t)s * kTabSize;
         }
     }
-    ALLOC(kpart, far_cap);
+    ALLOC(kpart, 4 * far_cap);
     ALLOC(kin, nsys);
     ALLOC(nh_xi, nsys);
-    ALLOC(far_done, nsys);
     ALLOC(list_items, near_cap);
     ALLOC(near_items, C);
     ALLOC(epart_cells, C);
@@ -1544,7 +1555,6 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
                   hipMemcpy(c->kcur, zc.data(), nsys * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->tstep, zc.data(), sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->sys_done, zu.data(), nsys * sizeof(uint32_t), hipMemcpyHostToDevice) == hipSuccess &&
-                  hipMemcpy(c->far_done, zu.data(), nsys * sizeof(uint32_t), hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->kin, std::vector<double>(nsys, 0.0).data(), nsys * sizeof(double),
                             hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->nh_xi, std::vector<double>(nsys, 0.0).data(), nsys * sizeof(double),
@@ -1732,7 +1742,7 @@ rbsog_status rbsog_step(rbsog_ctx *c, int64_t n_steps, double dt) {
         if (graphs) TRY(ensure_step_graphs(c, dt));
         for (int64_t i = 0; i < chunk; ++i) {
             TRY(refill_if_due(c));
-            if (graphs) HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+            if (graphs) HIPCHK(c, hipGraphLaunch(c->graph_exec[graph_mode(c)], c->stream));
             else TRY(enqueue_eval(c, true, dt));
             account_eval(c);
         }

@@ -369,15 +369,11 @@ __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
 // uniformly; items are runs of up to 256 slots of one system (grid-stride).
 // The near-list rebuild flag is cleared here: every kernel of the
 // evaluation that reads it has run.
-//
-// The kinetic energy of each item's particles after the evaluation is summed
-// in a fixed order into the item's partial; the block that finishes a
-// system's last item sums its partials (fixed order) into the system's
-// kinetic energy and, for a Nose-Hoover step, moves xi its second half step.
+// The kinetic energy of each wave's particles after the evaluation is summed
+// across the wave in a fixed order into partial [item * 4 + wave]
+// (k_kinetic adds them up).
 template <bool F64>
 __global__ __launch_bounds__(256) void k_far(EvalArgs a, const FarItem *__restrict__ items, int32_t nitems) {
-    __shared__ double kw[256];
-    __shared__ int32_t last;
     const int64_t n = a.N;
     if (blockIdx.x == 0 && threadIdx.x == 0 && a.rebuild) *a.rebuild = 0;
     for (int32_t itx = blockIdx.x; itx < nitems; itx += gridDim.x) {
@@ -498,44 +494,38 @@ __global__ __launch_bounds__(256) void k_far(EvalArgs a, const FarItem *__restri
             }
             ke = 0.5 * a.mass * ((vv[0] * vv[0] + vv[1] * vv[1]) + vv[2] * vv[2]);
         }
-        // the item's kinetic energy: lanes in a fixed tree, then the waves in order
-        kw[threadIdx.x] = ke;
-        __syncthreads();
-        for (int o = blockDim.x >> 1; o > 0; o >>= 1) {
-            if ((int)threadIdx.x < o) kw[threadIdx.x] += kw[threadIdx.x + o];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            a.kpart[itx] = kw[0];
-            __threadfence();
-            last = atomicAdd(&a.far_done[sys], 1u) == (uint32_t)(sp->ft1 - sp->ft0 - 1) ? 1 : 0;
-        }
-        __syncthreads();
-        if (last) {
-            __threadfence();
-            const int32_t f0 = sp->ft0, f1 = sp->ft1;
-            double s = 0.0;
-            for (int32_t j = f0 + (int32_t)threadIdx.x; j < f1; j += blockDim.x) s += a.kpart[j];
-            kw[threadIdx.x] = s;
-            __syncthreads();
-            for (int o = blockDim.x >> 1; o > 0; o >>= 1) {
-                if ((int)threadIdx.x < o) kw[threadIdx.x] += kw[threadIdx.x + o];
-                __syncthreads();
-            }
-            if (threadIdx.x == 0) {
-                const double K = kw[0];
-                if (a.kick && a.nh) {
-                    const double nf = sp->nh_nf, Q = sp->nh_Q;
-                    const double xh = a.nh_xi[sys] + 0.5 * a.dt * (2.0 * a.kin[sys] - nf * a.nh_T) / Q;
-                    a.nh_xi[sys] = xh + 0.5 * a.dt * (2.0 * K - nf * a.nh_T) / Q;
-                }
-                a.kin[sys] = K;
-                a.far_done[sys] = 0u;
-            }
-        }
-        __syncthreads();
+        // the wave's kinetic energy (a fixed butterfly), one partial per wave
+        for (int o = 32; o > 0; o >>= 1) ke += __shfl_xor(ke, o, 64);
+        if ((threadIdx.x & 63) == 0) a.kpart[(int64_t)itx * 4 + (threadIdx.x >> 6)] = ke;
     }
 }
+
+// Kinetic energy of every system after the evaluation: one block per
+// system sums its far items' wave partials (unused slots hold 0) in a fixed
+// order; for a Nose-Hoover step xi then moves its second half step with it.
+__global__ __launch_bounds__(256) void k_kinetic(EvalArgs a) {
+    __shared__ double kw[256];
+    const int32_t s = blockIdx.x;
+    const SysDev &sp = a.sys[s];
+    double acc = 0.0;
+    for (int64_t j = (int64_t)sp.ft0 * 4 + threadIdx.x; j < (int64_t)sp.ft1 * 4; j += 256) acc += a.kpart[j];
+    kw[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) kw[threadIdx.x] += kw[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double K = kw[0];
+        if (a.kick && a.nh) {
+            const double nf = sp.nh_nf, Q = sp.nh_Q;
+            const double xh = a.nh_xi[s] + 0.5 * a.dt * (2.0 * a.kin[s] - nf * a.nh_T) / Q;
+            a.nh_xi[s] = xh + 0.5 * a.dt * (2.0 * K - nf * a.nh_T) / Q;
+        }
+        a.kin[s] = K;
+    }
+}
+
 
 }  // namespace
 
@@ -554,6 +544,10 @@ void launch_far(const EvalArgs &a, bool f64, const FarItem *items, int32_t nitem
     dim3 grid((unsigned)nitems), block((unsigned)block_size);
     if (f64) hipLaunchKernelGGL(k_far<true>, grid, block, 0, s, a, items, nitems);
     else hipLaunchKernelGGL(k_far<false>, grid, block, 0, s, a, items, nitems);
+}
+
+void launch_kinetic(const EvalArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_kinetic, dim3((unsigned)a.nsys), dim3(256), 0, s, a);
 }
 
 }  // namespace rbsog

@@ -188,10 +188,9 @@ struct EvalArgs {
     int32_t kick;          // nonzero: kick + drift before, kick after
     double hdm, dt;
     double mass;
-    // kinetic energy per far item, per system (after the evaluation), and the
-    // per-system counters of finished far items
+    // kinetic energy per far item and wave (4 slots per item), and per
+    // system after the evaluation
     double *kpart, *kin;
-    uint32_t *far_done;
     // Nose-Hoover thermostat (nh != 0): xi per system, target temperature
     int32_t nh;
     double nh_T;
@@ -272,5 +271,8 @@ void launch_rho_reduce(const EvalArgs &a, hipStream_t s);
 // (items of at most block_size particles, block_size in {64, 128, 256})
 void launch_far(const EvalArgs &a, bool f64, const FarItem *items, int32_t nitems, int32_t block_size,
                 hipStream_t s);
+// kinetic energy of every system from the far kernel's partials, and the
+// second Nose-Hoover half step of xi when stepping with that thermostat
+void launch_kinetic(const EvalArgs &a, hipStream_t s);
 
 }  // namespace rbsog
