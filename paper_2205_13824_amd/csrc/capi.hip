@@ -171,6 +171,7 @@ struct rbsog_ctx {
     int64_t icap = 0;
     int64_t *nbuild = nullptr;
     int32_t build_slots = 2;  // candidates per lane and test pass of the build
+    int32_t cell_slots = 2;   // the same for the fused cell kernel
     double *Fn = nullptr, *Ff = nullptr;
     int64_t *kcur = nullptr;
     KRec64 *kb64 = nullptr;
@@ -584,7 +585,7 @@ rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt) {
         HIPCHK(c, hipEventRecord(c->ev_join, c->side));
     }
     if (a.always_build) {
-        TRY(timed(c, K_NEARC, [&] { launch_near_cells(a, f64, c->near_items, c->n_near, s); }));
+        TRY(timed(c, K_NEARC, [&] { launch_near_cells(a, f64, c->near_items, c->n_near, c->cell_slots, s); }));
     } else {
         TRY(timed(c, K_LIST, [&] { launch_list_build(a, f64, c->list_items, c->n_list, c->build_slots, s); }));
         TRY(timed(c, K_NEAR, [&] { launch_near(a, f64, c->list_items, c->n_list, s); }));
@@ -662,6 +663,7 @@ rbsog_status ensure_step_graphs(rbsog_ctx *c, double dt) {
 rbsog_status request_build(rbsog_ctx *c);
 rbsog_status upload_cell_items(rbsog_ctx *c);
 int32_t build_slots_for(const rbsog_ctx *c);
+int32_t cell_slots_for(const rbsog_ctx *c);
 void set_geometry(SysHost &h, double skin);
 
 // Installs the cell grid and list thresholds of a skin on every system (the
@@ -672,6 +674,7 @@ rbsog_status apply_skin(rbsog_ctx *c, double skin) {
     for (int32_t s = 0; s < c->nsys; ++s) TRY(upload_sysdev(c, s));
     c->skin_cur = skin;
     c->build_slots = build_slots_for(c);
+    c->cell_slots = cell_slots_for(c);
     TRY(upload_cell_items(c));
     // each mode keeps its own step graph (the grid and items are read from
     // device tables; the build's slots per pass are fixed per mode)
@@ -1288,20 +1291,15 @@ rbsog_status setup_device_chains(rbsog_ctx *c, int32_t lambda) {
     return RBSOG_OK;
 }
 
-// Candidate slots per lane and test pass of the build (2, 3 or 4: passes of
-// 128, 192 or 256 candidates): the choice with the fewest slots tested per
-// home cell, the candidate count of a cell taken as normal with the mean
-// stencil occupancy of the densest system and its square root as spread.
-int32_t build_slots_for(const rbsog_ctx *c) {
-    double cand = 0.0;
-    for (const SysHost &h : c->sys) {
-        const double reach = (h.g.reach[0] ? 3.0 : 1.0) * (h.g.reach[1] ? 3.0 : 1.0) * (h.g.reach[2] ? 3.0 : 1.0);
-        cand = std::max(cand, reach * (double)h.n / (double)h.ncell);
-    }
+// Candidate slots per lane and test pass (2, 3 or 4: passes of 128, 192 or
+// 256 candidates) with the fewest slots tested per home cell, the candidate
+// count of a cell taken as normal with mean `cand` and its square root as
+// spread.
+int32_t slots_for_mean(double cand, int32_t smax) {
     const double sd = std::sqrt(std::max(cand, 1.0));
     int32_t best = 2;
     double best_cost = 1e300;
-    for (int32_t S = 2; S <= 4; ++S) {
+    for (int32_t S = 2; S <= smax; ++S) {
         const double pass = 64.0 * S;
         double cost = 0.0, wsum = 0.0;
         for (int k = -40; k <= 40; ++k) {
@@ -1318,6 +1316,21 @@ int32_t build_slots_for(const rbsog_ctx *c) {
     }
     return best;
 }
+
+// Mean stencil occupancy of the densest system on the grid in use: 27 cells,
+// or 36 for the fused cell kernel's pairs of home cells (rows of >= 6 cells).
+double stencil_mean(const rbsog_ctx *c, bool pairs) {
+    double cand = 0.0;
+    for (const SysHost &h : c->sys) {
+        double cells = (h.g.reach[0] ? 3.0 : 1.0) * (h.g.reach[1] ? 3.0 : 1.0) * (h.g.reach[2] ? 3.0 : 1.0);
+        if (pairs && h.g.nc[0] >= 6) cells *= 4.0 / 3.0;
+        cand = std::max(cand, cells * (double)h.n / (double)h.ncell);
+    }
+    return cand;
+}
+
+int32_t build_slots_for(const rbsog_ctx *c) { return slots_for_mean(stencil_mean(c, false), 4); }
+int32_t cell_slots_for(const rbsog_ctx *c) { return slots_for_mean(stencil_mean(c, true), 3); }
 
 // A list build that only counts, at the initial positions: its largest item
 // count sizes the pair list.  It also puts the state in cell order; the
@@ -1416,6 +1429,7 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     c->N = offsets[nsys];
     c->q_host.assign(q, q + c->N);
     c->build_slots = build_slots_for(c);
+    c->cell_slots = cell_slots_for(c);
     std::vector<std::vector<float4>> tables;
     if (o.near_table) {
         tables.resize(nsys);

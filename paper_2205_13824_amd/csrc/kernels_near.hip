@@ -101,6 +101,36 @@ __device__ __forceinline__ bool row_range(const Geom &g, const int32_t *__restri
     return true;
 }
 
+// Range r (0..17) of the candidate cells of the home cells x = cx .. cx+w-1
+// (w = 1 or 2, one row) in cell order: x runs over cx-1 .. cx+w (w = 2 needs
+// at least 6 cells along x, so that the pieces never overlap).
+__device__ __forceinline__ bool row_range_w(const Geom &g, const int32_t *__restrict__ start, int r, int cx, int cy,
+                                            int cz, int w, int32_t &lo, int32_t &hi) {
+    const int row = r >> 1, part = r & 1;
+    const int oy = row % 3 - 1, oz = row / 3 - 1;
+    if ((oy != 0 && !g.reach[1]) || (oz != 0 && !g.reach[2])) return false;
+    const int jy = wrapc(cy + oy, g.nc[1]), jz = wrapc(cz + oz, g.nc[2]);
+    const int base = g.nc[0] * (jy + g.nc[1] * jz);
+    int xa, xb;
+    if (!g.reach[0]) {
+        if (part) return false;
+        xa = xb = 0;
+    } else {
+        const int x0 = cx - 1, x1 = cx + w;
+        if (x0 < 0) {
+            if (part == 0) { xa = xb = g.nc[0] - 1; } else { xa = 0; xb = x1; }
+        } else if (x1 >= g.nc[0]) {
+            if (part == 0) { xa = x0; xb = g.nc[0] - 1; } else { xa = 0; xb = x1 - g.nc[0]; }
+        } else {
+            if (part) return false;
+            xa = x0; xb = x1;
+        }
+    }
+    lo = start[base + xa];
+    hi = start[base + xb + 1];
+    return true;
+}
+
 __device__ __forceinline__ double mi64(double d, double L, double invL) { return d - L * rint(d * invL); }
 
 // Sum over the wave in a fixed order (the same on every run).
@@ -761,9 +791,12 @@ struct NearLds {
 
 // Steps that build at every evaluation (skin 0) need no list: this kernel
 // finds the pairs and evaluates them in one pass, one wave per run of cells
-// (cells r_c wide), the pair ring evaluated 64 entries at a time.  Blocks
-// past nblk copy the gathered state back into `cur`.
-template <bool F64>
+// (cells r_c wide), the pair ring evaluated 64 entries at a time.  Where a
+// row has at least 6 cells, two neighbouring home cells share one candidate
+// set (their 4 x 3 x 3 stencil), which halves the candidate set-up per home.
+// S: candidate slots per lane and pass.  Blocks past nblk copy the gathered
+// state back into `cur`.
+template <bool F64, int S>
 __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearItem *__restrict__ items,
                                                          int32_t nitems, int32_t nblk) {
     if (!*a.rebuild) return;
@@ -774,7 +807,6 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
     if (blockIdx.x == 0 && threadIdx.x == 0) ++*a.nbuild;
     using Lds = NearLds<F64>;
     using R = typename Lds::R;
-    constexpr int S = 2;  // candidate slots per lane and pass
     constexpr int Q = 512;
     __shared__ Lds lds[kNW];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -858,24 +890,28 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
         }
         wave_sync();
         while (rfl(start[cur + 1]) <= t) ++cur;
-        for (int64_t cell = cur; cell < rb; ++cell) {
-            const int32_t cs = rfl(start[cell]);
-            if (cs >= t_end) break;
-            const int32_t ce = rfl(start[cell + 1]);
-            const int32_t hs = cs > t ? cs : t;
-            const int32_t he = ce < t_end ? ce : t_end;
-            if (hs >= he) continue;
-            const int i0 = hs - t, i1 = he - t;
+        const bool pairs = g.nc[0] >= 6;
+        int w = 1;
+        for (int64_t cell = cur; cell < rb; cell += w) {
             const uint32_t cu32 = (uint32_t)(cell - c0s);
             const int cx = (int)(cu32 % (uint32_t)g.nc[0]);
             const int cy = (int)((cu32 / (uint32_t)g.nc[0]) % (uint32_t)g.nc[1]);
             const int cz = (int)(cu32 / ((uint32_t)g.nc[0] * (uint32_t)g.nc[1]));
+            // home cells cx (and cx + 1 in the same row and item)
+            w = pairs && cx + 1 < g.nc[0] && cell + 1 < rb ? 2 : 1;
+            const int32_t cs = rfl(start[cell]);
+            if (cs >= t_end) break;
+            const int32_t ce = rfl(start[cell + w]);
+            const int32_t hs = cs > t ? cs : t;
+            const int32_t he = ce < t_end ? ce : t_end;
+            if (hs >= he) continue;
+            const int i0 = hs - t, i1 = he - t;
             // lane r < 18 holds candidate range r: first sorted index, and its
             // offsets in the flattened candidate list
             int32_t lo = 0, len = 0;
             if (lane < kRanges) {
                 int32_t ra_, rb_;
-                if (row_range(g, start + c0s, lane, cx, cy, cz, ra_, rb_)) { lo = ra_; len = rb_ - ra_; }
+                if (row_range_w(g, start + c0s, lane, cx, cy, cz, w, ra_, rb_)) { lo = ra_; len = rb_ - ra_; }
             }
             int32_t incl = len;
             for (int o = 1; o < 32; o <<= 1) {
@@ -1105,7 +1141,8 @@ void launch_list_build(const EvalArgs &a, bool f64, const ListItem *items, int32
     }
 }
 
-void launch_near_cells(const EvalArgs &a, bool f64, const NearItem *items, int32_t nitems, hipStream_t s) {
+void launch_near_cells(const EvalArgs &a, bool f64, const NearItem *items, int32_t nitems, int32_t slots,
+                       hipStream_t s) {
     // one item per wave; a multiple of 8 blocks so that the XCD mapping is a
     // permutation of the blocks; then the blocks of the copy back
     int32_t nblk = (nitems + kNW - 1) / kNW;
@@ -1113,8 +1150,13 @@ void launch_near_cells(const EvalArgs &a, bool f64, const NearItem *items, int32
     if (nblk < 8) nblk = 8;
     const int64_t ncopy = std::min<int64_t>(1024, std::max<int64_t>(1, grid_for(a.N, 64 * kNW)));
     const dim3 grid((unsigned)(nblk + ncopy)), block(64 * kNW);
-    if (f64) hipLaunchKernelGGL(k_near_cells<true>, grid, block, 0, s, a, items, nitems, nblk);
-    else hipLaunchKernelGGL(k_near_cells<false>, grid, block, 0, s, a, items, nitems, nblk);
+    if (f64) {
+        if (slots <= 2) hipLaunchKernelGGL((k_near_cells<true, 2>), grid, block, 0, s, a, items, nitems, nblk);
+        else hipLaunchKernelGGL((k_near_cells<true, 3>), grid, block, 0, s, a, items, nitems, nblk);
+    } else {
+        if (slots <= 2) hipLaunchKernelGGL((k_near_cells<false, 2>), grid, block, 0, s, a, items, nitems, nblk);
+        else hipLaunchKernelGGL((k_near_cells<false, 3>), grid, block, 0, s, a, items, nitems, nblk);
+    }
 }
 
 void launch_near(const EvalArgs &a, bool f64, const ListItem *items, int32_t nitems, hipStream_t s) {

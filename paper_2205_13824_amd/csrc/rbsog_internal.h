@@ -251,7 +251,9 @@ void launch_list_build(const EvalArgs &a, bool f64, const ListItem *items, int32
 // build-every-evaluation mode (a.always_build): near forces and energies in
 // one pass over cell runs (no list), and the copy back; returns at once
 // unless *a.rebuild is set
-void launch_near_cells(const EvalArgs &a, bool f64, const NearItem *items, int32_t nitems, hipStream_t s);
+// slots (2 or 3): candidates per lane and test pass
+void launch_near_cells(const EvalArgs &a, bool f64, const NearItem *items, int32_t nitems, int32_t slots,
+                       hipStream_t s);
 // near forces and energies from the list; returns at once if *a.rebuild is
 // set (the build has evaluated them)
 void launch_near(const EvalArgs &a, bool f64, const ListItem *items, int32_t nitems, hipStream_t s);

@@ -485,3 +485,29 @@ def test_near_list_skin_does_not_change_the_trajectory(orc):
         dx = x - out[0][0]
         dx -= box * np.round(dx / box)
         assert np.abs(dx).max() < 1e-10 and relrms(v, out[0][1]) < 1e-10
+
+
+@pytest.mark.parametrize("prec,tol", [(R.RBSOG_FP64, F64_TOL), (R.RBSOG_FP32C, F32C_TOL)])
+@pytest.mark.parametrize("L", [21.5, 39.1])
+def test_fused_cell_kernel_with_paired_home_cells(orc, prec, tol, L):
+    # skin 0: every evaluation builds with the fused cell kernel, which pairs
+    # neighbouring home cells in rows of at least 6 cells (L = 21.5: 6 cells,
+    # both seams of each row inside a pair's stencil; L = 39.1: 11 cells, an
+    # odd row leaves one cell alone); forces and energies vs the oracle over a
+    # few steps, and the neighbour list bit-exact
+    n = int(0.1 * L ** 3) // 2 * 2
+    pos, q, box = W.ions_rsa(n, n / L ** 3, 1.0, 91)
+    rc, P = 3.5, 30
+    sysm = make(pos, q, box, rc, P, seed=4, prec=prec, skin=0.0)
+    m = sysm.sample_k(4)
+    check_eval(orc, sysm, pos, q, box, rc, m[:P], tol, f"paired cells L={L} prec={prec}")
+    R.rbsog_set_velocities(sysm.ctx, None, T=1.0, seed=2)
+    sysm.step(2, 1e-3)
+    x, _ = R.rbsog_get_state(sysm.ctx, n)
+    Fn, _ = sysm.components()
+    Fn_o, _ = orc.near_brute(x, q, box, rc, oracle_sog(orc, sysm.sog))
+    assert relrms(Fn, Fn_o) < tol
+    row, cols = R.rbsog_debug_neighbors(sysm.ctx, n)
+    row_o, cols_o = orc.neighbors_brute(x, box, rc)
+    assert (row == row_o).all() and (cols == cols_o).all()
+    assert R.rbsog_info(sysm.ctx)["ncell"][0] == int(box[0] // rc) >= 6
