@@ -170,7 +170,8 @@ def kernel_traffic(kernel):
     return int(v) if v is not None else None
 
 
-# library profile names -> kernel symbols in the rocprofv3 summaries (FP32C)
+# library profile names -> kernel symbols in the rocprofv3 summaries (FP32C; the
+# kernels templated on a slot count appear there as e.g. k_near_cells<false, 3>)
 KERNEL_SYMBOL = {"near": "k_near_list<false>", "near_cells": "k_near_cells<false>", "rho": "k_rho<false>",
                  "far": "k_far<false>"}
 
