@@ -574,14 +574,15 @@ rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt) {
     TRY(timed(c, K_SCAN, [&] { launch_scan(a, s); }));
     TRY(timed(c, K_SCATTER, [&] { launch_cell_scatter(a, s); }));
     TRY(timed(c, K_SORTG, [&] { launch_sort_gather(a, s); }));
-    // the structure factor needs the positions and the staged k records
-    // only: it runs on the side stream beside the near part (one stream
-    // while profiling, so that each kernel is timed alone)
+    // the structure factor and its reduction need the positions and the
+    // staged k records only: they run on the side stream beside the near part
+    // (one stream while profiling, so that each kernel is timed alone)
     const bool fork = !c->prof_on;
     if (fork) {
         HIPCHK(c, hipEventRecord(c->ev_fork, s));
         HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
         launch_rho(a, f64, c->rho_items, c->n_rho, c->side);
+        launch_rho_reduce(a, c->side);
         HIPCHK(c, hipEventRecord(c->ev_join, c->side));
     }
     if (a.always_build) {
@@ -590,9 +591,12 @@ rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt) {
         TRY(timed(c, K_LIST, [&] { launch_list_build(a, f64, c->list_items, c->n_list, c->build_slots, s); }));
         TRY(timed(c, K_NEAR, [&] { launch_near(a, f64, c->list_items, c->n_list, s); }));
     }
-    if (fork) HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
-    else TRY(timed(c, K_RHO, [&] { launch_rho(a, f64, c->rho_items, c->n_rho, s); }));
-    TRY(timed(c, K_RHORED, [&] { launch_rho_reduce(a, s); }));
+    if (fork) {
+        HIPCHK(c, hipStreamWaitEvent(s, c->ev_join, 0));
+    } else {
+        TRY(timed(c, K_RHO, [&] { launch_rho(a, f64, c->rho_items, c->n_rho, s); }));
+        TRY(timed(c, K_RHORED, [&] { launch_rho_reduce(a, s); }));
+    }
     TRY(timed(c, K_FAR, [&] { launch_far(a, f64, c->far_items, c->n_far, c->tune.far_block, s); }));
     launch_kinetic(a, s);
     HIPCHK(c, hipGetLastError());

@@ -259,11 +259,12 @@ __device__ __forceinline__ double wave_sum(double v) {
 // One wave per k record r: rho = sum over the system's chunks of the
 // partials (fixed order), the per-k energy 1/2 w |rho|^2, and rho written
 // into the records.  The block that reduces the last record of a system
-// (per-system counter) sums that system's energies in a fixed order: U_N
-// from the near items' partials, U*, U_self, U; advances its sequence cursor
-// by P and re-arms the counter.
+// (per-system counter) sums that system's far energy in a fixed order (U*,
+// with the zero-mode term and its dipole), writes U_self, advances the
+// sequence cursor by P and re-arms the counter; U_N and U follow in
+// k_kinetic, after the near part.  Nothing here waits for the near part.
 __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
-    __shared__ double sr[256], si[256];
+    __shared__ double si[256];
     __shared__ int32_t fin[4];
     __shared__ int32_t nfin;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -317,28 +318,12 @@ __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
         __threadfence();
         const int32_t s = fin[f];
         const SysDev &sd = a.sys[s];
-        // eight independent loads in flight per thread, summed in a fixed order
-        double u8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        // near energies per item of the mode in use
-        const double *ep = a.always_build ? a.epart_cells : a.epart;
-        const int64_t i0 = a.always_build ? sd.jt0 : sd.it0, i1 = a.always_build ? sd.jt1 : sd.it1;
-        int64_t i = i0 + threadIdx.x;
-        for (; i + 7 * 256 < i1; i += 8 * 256) {
-#pragma unroll
-            for (int h = 0; h < 8; ++h) u8[h] += ep[i + h * 256];
-        }
-        for (; i < i1; i += 256) u8[0] += ep[i];
-        const double un = ((u8[0] + u8[1]) + (u8[2] + u8[3])) + ((u8[4] + u8[5]) + (u8[6] + u8[7]));
         double us = 0.0;
         for (int64_t k = threadIdx.x; k < sd.P; k += 256) us += a.ek[sd.k0 + k];
-        sr[threadIdx.x] = un;
         si[threadIdx.x] = us;
         __syncthreads();
         for (int o = 128; o > 0; o >>= 1) {
-            if (threadIdx.x < o) {
-                sr[threadIdx.x] += sr[threadIdx.x + o];
-                si[threadIdx.x] += si[threadIdx.x + o];
-            }
+            if (threadIdx.x < o) si[threadIdx.x] += si[threadIdx.x + o];
             __syncthreads();
         }
         if (threadIdx.x == 0) {
@@ -351,12 +336,8 @@ __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
                 u0 = sd.zmode == 1 ? sd.zu * (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) : sd.zu * m[2] * m[2];
             }
             // U* holds the far part with the zero-frequency mode term
-            const double tot = sr[0] + si[0] + u0 - sd.uself;
-            a.E[4 * s] = sr[0];
             a.E[4 * s + 1] = si[0] + u0;
             a.E[4 * s + 2] = sd.uself;
-            a.E[4 * s + 3] = tot;
-            if (!isfinite(tot)) atomicOr(a.flag, 2);
             a.kcur[s] += sd.P;
             a.sys_done[s] = 0u;
             if (s == 0 && a.kick && a.thermo) *a.tstep += 1;
@@ -500,22 +481,42 @@ __global__ __launch_bounds__(256) void k_far(EvalArgs a, const FarItem *__restri
     }
 }
 
-// Kinetic energy of every system after the evaluation: one block per
-// system sums its far items' wave partials (unused slots hold 0) in a fixed
-// order; for a Nose-Hoover step xi then moves its second half step with it.
+// Per system, one block: the near energy U_N from the near items' partials
+// of the mode in use and the total U = U_N + U* - U_self (eight loads in
+// flight per thread, fixed order); the kinetic energy after the evaluation
+// from the far items' wave partials (unused slots hold 0), fixed order; for
+// a Nose-Hoover step xi then moves its second half step with it.
 __global__ __launch_bounds__(256) void k_kinetic(EvalArgs a) {
-    __shared__ double kw[256];
+    __shared__ double kw[256], ew[256];
     const int32_t s = blockIdx.x;
     const SysDev &sp = a.sys[s];
     double acc = 0.0;
     for (int64_t j = (int64_t)sp.ft0 * 4 + threadIdx.x; j < (int64_t)sp.ft1 * 4; j += 256) acc += a.kpart[j];
+    double u8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const double *ep = a.always_build ? a.epart_cells : a.epart;
+    const int64_t i0 = a.always_build ? sp.jt0 : sp.it0, i1 = a.always_build ? sp.jt1 : sp.it1;
+    int64_t i = i0 + threadIdx.x;
+    for (; i + 7 * 256 < i1; i += 8 * 256) {
+#pragma unroll
+        for (int h = 0; h < 8; ++h) u8[h] += ep[i + h * 256];
+    }
+    for (; i < i1; i += 256) u8[0] += ep[i];
     kw[threadIdx.x] = acc;
+    ew[threadIdx.x] = ((u8[0] + u8[1]) + (u8[2] + u8[3])) + ((u8[4] + u8[5]) + (u8[6] + u8[7]));
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) kw[threadIdx.x] += kw[threadIdx.x + o];
+        if ((int)threadIdx.x < o) {
+            kw[threadIdx.x] += kw[threadIdx.x + o];
+            ew[threadIdx.x] += ew[threadIdx.x + o];
+        }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
+        const double un = ew[0];
+        const double tot = un + a.E[4 * s + 1] - a.E[4 * s + 2];
+        a.E[4 * s] = un;
+        a.E[4 * s + 3] = tot;
+        if (!isfinite(tot)) atomicOr(a.flag, 2);
         const double K = kw[0];
         if (a.kick && a.nh) {
             const double nf = sp.nh_nf, Q = sp.nh_Q;

@@ -267,14 +267,16 @@ void launch_neighbor_fill(const EvalArgs &a, int32_t sys, int64_t n, int64_t p0,
 void launch_rho(const EvalArgs &a, bool f64, const RhoItem *items, int32_t nitems, hipStream_t s);
 // rho_e per record from the partials (fixed order), its records and per-k
 // energies; the block that completes a system's records also sums that
-// system's energies and advances its sequence cursor
+// system's far energy (with the zero-mode term) and advances its sequence
+// cursor
 void launch_rho_reduce(const EvalArgs &a, hipStream_t s);
 // far force; with a.kick the closing half kick v += dt/(2m) (F_N + F*) follows
 // (items of at most block_size particles, block_size in {64, 128, 256})
 void launch_far(const EvalArgs &a, bool f64, const FarItem *items, int32_t nitems, int32_t block_size,
                 hipStream_t s);
-// kinetic energy of every system from the far kernel's partials, and the
-// second Nose-Hoover half step of xi when stepping with that thermostat
+// per system: U_N and the total U after the near part and U*, the kinetic
+// energy from the far kernel's partials, and the second Nose-Hoover half
+// step of xi when stepping with that thermostat
 void launch_kinetic(const EvalArgs &a, hipStream_t s);
 
 }  // namespace rbsog
