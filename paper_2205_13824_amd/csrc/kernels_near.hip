@@ -277,21 +277,44 @@ struct HomeView {
     R *hf[3];
 };
 
+// The candidate's data a pair needs: fixed-point coordinates, charge, and
+// the FP64 position in the FP64 form.
 template <bool F64>
-__device__ __forceinline__ void eval_pair(const Geom &g, typename CoefOf<F64>::type *co, const HomeView<F64> &L,
-                                          const uint32_t *__restrict__ su, const double *__restrict__ sx,
-                                          const double *__restrict__ sq, const float *__restrict__ sqf, int64_t n,
-                                          const float4 *__restrict__ tbl, float rin2, const float *ta,
-                                          const float *tb, int lane, uint2 qe, bool have, double &e) {
+struct PairData {
+    uint32_t u[3];
+    typename std::conditional<F64, double, float>::type q;
+    double x[3];
+};
+
+template <bool F64>
+__device__ __forceinline__ PairData<F64> load_pair(const uint32_t *__restrict__ su, const double *__restrict__ sx,
+                                                   const double *__restrict__ sq, const float *__restrict__ sqf,
+                                                   int64_t n, uint2 qe, bool have) {
+    PairData<F64> d;
+    const uint32_t j = have ? qe.y : 0u;
+    d.u[0] = su[j]; d.u[1] = su[n + j]; d.u[2] = su[2 * n + j];
+    if constexpr (F64) {
+        d.q = sq[j];
+        d.x[0] = sx[j]; d.x[1] = sx[n + j]; d.x[2] = sx[2 * n + j];
+    } else {
+        d.q = sqf[j];
+    }
+    return d;
+}
+
+template <bool F64>
+__device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>::type *co, const HomeView<F64> &L,
+                                            const float4 *__restrict__ tbl, float rin2, const float *ta,
+                                            const float *tb, int lane, uint2 qe, bool have, const PairData<F64> &pd,
+                                            double &e) {
     double de = 0.0;
     using R = typename HomeView<F64>::R;
     constexpr int NT = (F64 ? kTailDeg64 : kTailDeg32) + 1;
     R fx = 0, fy = 0, fz = 0;
     const int slot = have ? (int)qe.x : -1;
     if (have) {
-        const uint32_t j = qe.y;
         const uint4 h = L.hu[slot];
-        const uint32_t dux = su[j] - h.x, duy = su[n + j] - h.y, duz = su[2 * n + j] - h.z;
+        const uint32_t dux = pd.u[0] - h.x, duy = pd.u[1] - h.y, duz = pd.u[2] - h.z;
         const float ex_ = (float)(int32_t)dux * g.hf[0];
         const float ey_ = (float)(int32_t)duy * g.hf[1];
         const float ez_ = (float)(int32_t)duz * g.hf[2];
@@ -301,13 +324,13 @@ __device__ __forceinline__ void eval_pair(const Geom &g, typename CoefOf<F64>::t
         if (in) {
             R dx, dy, dz, qq;
             if constexpr (F64) {
-                dx = mi64(sx[j] - L.hx[0][slot], g.L[0], g.invL[0]);
-                dy = mi64(sx[n + j] - L.hx[1][slot], g.L[1], g.invL[1]);
-                dz = mi64(sx[2 * n + j] - L.hx[2][slot], g.L[2], g.invL[2]);
-                qq = L.hq[slot] * sq[j];
+                dx = mi64(pd.x[0] - L.hx[0][slot], g.L[0], g.invL[0]);
+                dy = mi64(pd.x[1] - L.hx[1][slot], g.L[1], g.invL[1]);
+                dz = mi64(pd.x[2] - L.hx[2][slot], g.L[2], g.invL[2]);
+                qq = L.hq[slot] * pd.q;
             } else {
                 dx = ex_; dy = ey_; dz = ez_;
-                qq = L.hq[slot] * sqf[j];
+                qq = L.hq[slot] * pd.q;
             }
             const R r2 = F64 ? dx * dx + dy * dy + dz * dz : r2f;
             R gk, hk;  // force coefficient g and pair potential h of the split
@@ -375,6 +398,16 @@ __device__ __forceinline__ void eval_pair(const Geom &g, typename CoefOf<F64>::t
         atomicAdd(&L.hf[1][slot], fy);
         atomicAdd(&L.hf[2][slot], fz);
     }
+}
+
+template <bool F64>
+__device__ __forceinline__ void eval_pair(const Geom &g, typename CoefOf<F64>::type *co, const HomeView<F64> &L,
+                                          const uint32_t *__restrict__ su, const double *__restrict__ sx,
+                                          const double *__restrict__ sq, const float *__restrict__ sqf, int64_t n,
+                                          const float4 *__restrict__ tbl, float rin2, const float *ta,
+                                          const float *tb, int lane, uint2 qe, bool have, double &e) {
+    const PairData<F64> pd = load_pair<F64>(su, sx, sq, sqf, n, qe, have);
+    eval_loaded<F64>(g, co, L, tbl, rin2, ta, tb, lane, qe, have, pd, e);
 }
 
 template <bool F64, int Q>
@@ -758,11 +791,20 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
         hv.hf[d] = L.hf[d];
     }
     double e = 0.0;
-    // the segment in the build's chunks of 64, in order
+    // the segment in the build's chunks of 64, in order; entries are loaded
+    // two chunks ahead and the candidates' data one chunk ahead, so that the
+    // loads of the next chunks run while this one is evaluated
+    auto entry = [&](int32_t c) { return c + lane < cnt ? pl[c + lane] : make_uint2(0u, 0u); };
+    uint2 qe1 = entry(0), qe2 = entry(64);
+    PairData<F64> pd1 = load_pair<F64>(su, sx, sq, sqf, n, qe1, lane < cnt);
     for (int32_t c = 0; c < cnt; c += 64) {
+        const uint2 qe = qe1;
+        const PairData<F64> pd = pd1;
         const bool have = c + lane < cnt;
-        const uint2 qe = have ? pl[c + lane] : make_uint2(0u, 0u);
-        eval_pair<F64>(g, co, hv, su, sx, sq, sqf, n, tbl, rin2, ta, tb, lane, qe, have, e);
+        qe1 = qe2;
+        qe2 = entry(c + 128);
+        pd1 = load_pair<F64>(su, sx, sq, sqf, n, qe1, c + 64 + lane < cnt);
+        eval_loaded<F64>(g, co, hv, tbl, rin2, ta, tb, lane, qe, have, pd, e);
     }
     wave_sync();
     if (lane < H) {
