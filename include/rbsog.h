@@ -242,6 +242,15 @@ rbsog_status rbsog_set_nose_hoover(rbsog_ctx *ctx, double T, double tau);
  * may be NULL.  Each system's K is summed on the device in a fixed order. */
 rbsog_status rbsog_get_kinetic(rbsog_ctx *ctx, double *K, double *xi);
 
+/* Mean-square displacement (the water runs' MSD of Sec. 5 and its Appendix
+ * formula, over all particles of a system): every step adds its drift,
+ * unwrapped, to a per-particle displacement d; rbsog_get_msd returns
+ * (1/n_s) sum |d|^2 of every system (host n_sys doubles; summed on the device
+ * in a fixed order).  rbsog_set_msd_origin sets d = 0 (the context starts
+ * from 0; rbsog_set_positions also resets it). */
+rbsog_status rbsog_set_msd_origin(rbsog_ctx *ctx);
+rbsog_status rbsog_get_msd(rbsog_ctx *ctx, double *msd);
+
 /* Replaces the positions (host n x 3, finite); forces become unknown. */
 rbsog_status rbsog_set_positions(rbsog_ctx *ctx, const double *pos);
 

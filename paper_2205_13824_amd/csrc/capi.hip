@@ -180,6 +180,7 @@ struct rbsog_ctx {
     double *dip_part = nullptr, *dipole = nullptr;
     // kinetic energy per far item and wave, and per system
     double *kpart = nullptr, *kin = nullptr;
+    double *msd = nullptr;  // mean-square displacement per system (rbsog_get_msd)
     // Nose-Hoover thermostat: on, target temperature, tau, xi per system
     bool nh_on = false;
     double nh_T = 0.0, nh_tau = 0.0;
@@ -1483,6 +1484,7 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
         ALLOC(buf[p].q, N);
         ALLOC(buf[p].qf, N);
         ALLOC(buf[p].id, N);
+        ALLOC(buf[p].dsp, 3 * N);
     }
     ALLOC(dsys, nsys);
     ALLOC(sys_of, N);
@@ -1526,6 +1528,7 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     }
     ALLOC(kpart, 4 * far_cap);
     ALLOC(kin, nsys);
+    ALLOC(msd, nsys);
     ALLOC(nh_xi, nsys);
     ALLOC(list_items, near_cap);
     ALLOC(near_items, C);
@@ -1565,6 +1568,7 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
                   hipMemcpy(b.q, q, N * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(b.qf, qff.data(), N * sizeof(float), hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(b.id, ids.data(), N * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemcpy(b.dsp, zero.data(), zero.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->Fn, zero.data(), zero.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->Ff, zero.data(), zero.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->sys_of, sof.data(), N * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
@@ -1874,11 +1878,30 @@ rbsog_status rbsog_get_kinetic(rbsog_ctx *c, double *K, double *xi) {
     return RBSOG_OK;
 }
 
+rbsog_status rbsog_set_msd_origin(rbsog_ctx *c) {
+    TRY(check_ctx(c));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemset(c->buf[0].dsp, 0, (size_t)3 * c->N * sizeof(double)));
+    return RBSOG_OK;
+}
+
+rbsog_status rbsog_get_msd(rbsog_ctx *c, double *msd) {
+    TRY(check_ctx(c));
+    if (!msd) return fail(c, RBSOG_E_ARG, "msd is null");
+    const EvalArgs a = make_args(c, false, 0.0);
+    launch_msd(a, c->msd, c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(msd, c->msd, (size_t)c->nsys * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return RBSOG_OK;
+}
+
 rbsog_status rbsog_set_positions(rbsog_ctx *c, const double *pos) {
     TRY(check_ctx(c));
     if (!pos) return fail(c, RBSOG_E_ARG, "pos is null");
     HIPCHK(c, hipStreamSynchronize(c->stream));
     TRY(upload_by_id(c, pos, c->buf[0].x, "position"));
+    HIPCHK(c, hipMemset(c->buf[0].dsp, 0, (size_t)3 * c->N * sizeof(double)));  // a new origin
     c->forces_valid = false;
     return request_build(c);
 }

@@ -528,7 +528,32 @@ __global__ __launch_bounds__(256) void k_kinetic(EvalArgs a) {
 }
 
 
+// One block per system: sum of |dsp|^2 over its slots (strided, then a fixed
+// tree), divided by n.
+__global__ __launch_bounds__(256) void k_msd(EvalArgs a, double *__restrict__ msd) {
+    __shared__ double w[256];
+    const int32_t s = blockIdx.x;
+    const SysDev &sp = a.sys[s];
+    const int64_t n = a.N, p0 = sp.p0, p1 = sp.p0 + sp.g.n;
+    double acc = 0.0;
+    for (int64_t i = p0 + threadIdx.x; i < p1; i += 256) {
+        const double dx = a.cur.dsp[i], dy = a.cur.dsp[n + i], dz = a.cur.dsp[2 * n + i];
+        acc += (dx * dx + dy * dy) + dz * dz;
+    }
+    w[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) w[threadIdx.x] += w[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) msd[s] = w[0] / (double)sp.g.n;
+}
+
 }  // namespace
+
+void launch_msd(const EvalArgs &a, double *msd, hipStream_t s) {
+    hipLaunchKernelGGL(k_msd, dim3((unsigned)a.nsys), dim3(256), 0, s, a, msd);
+}
 
 void launch_rho(const EvalArgs &a, bool f64, const RhoItem *items, int32_t nitems, hipStream_t s) {
     dim3 grid((unsigned)nitems), block(1024);

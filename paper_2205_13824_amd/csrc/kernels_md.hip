@@ -134,6 +134,7 @@ __global__ __launch_bounds__(kBlock) void k_kdq(EvalArgs a, int32_t pblocks) {
         uref[d] = a.u[d * N + t];
     }
     const float dthr2 = sd.g.dthr2_f;
+    const double xs0[3] = {xs[0], xs[1], xs[2]};
     if (a.kick) {
         double f[3], vs[3];
         for (int d = 0; d < 3; ++d) {
@@ -171,6 +172,9 @@ __global__ __launch_bounds__(kBlock) void k_kdq(EvalArgs a, int32_t pblocks) {
             }
         }
         if (bad && valid) atomicOr(a.flag, 1);
+        // the step's drift, unwrapped, for the mean-square displacement
+        if (valid)
+            for (int d = 0; d < 3; ++d) a.cur.dsp[d * N + t] += xs[d] - xs0[d];
     }
     float d2 = 0.f;
     uint32_t uq[3];
@@ -365,6 +369,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(EvalArgs a) {
     for (int d = 0; d < 3; ++d) {
         a.nxt.x[d * N + k] = a.cur.x[d * N + t];
         a.nxt.v[d * N + k] = a.cur.v[d * N + t];
+        a.nxt.dsp[d * N + k] = a.cur.dsp[d * N + t];
         a.u[d * N + k] = a.u_tmp[d * N + t];
     }
     a.nxt.q[k] = a.cur.q[t];

@@ -150,6 +150,7 @@ struct StateBufs {
     double *x, *v, *q;
     float *qf;
     int32_t *id;
+    double *dsp;  // displacement since the mean-square-displacement origin (sum of the drifts)
 };
 struct EvalArgs {
     int64_t N;             // particles over all systems
@@ -278,5 +279,8 @@ void launch_far(const EvalArgs &a, bool f64, const FarItem *items, int32_t nitem
 // energy from the far kernel's partials, and the second Nose-Hoover half
 // step of xi when stepping with that thermostat
 void launch_kinetic(const EvalArgs &a, hipStream_t s);
+// mean-square displacement of every system since its origin: msd[s] =
+// (1/n_s) sum |dsp|^2, fixed order
+void launch_msd(const EvalArgs &a, double *msd, hipStream_t s);
 
 }  // namespace rbsog

@@ -32,7 +32,7 @@ EXPORTS = ("rbsog_default_opts", "rbsog_sog_table1", "rbsog_init", "rbsog_init_b
            "rbsog_get_energy", "rbsog_get_rho", "rbsog_info", "rbsog_debug_cells", "rbsog_debug_neighbors",
            "rbsog_profile", "rbsog_profile_read", "rbsog_sync", "rbsog_last_error", "rbsog_status_string",
            "rbsog_destroy", "rbsog_autotune", "rbsog_set_thermostat", "rbsog_get_kbatch",
-           "rbsog_set_nose_hoover", "rbsog_get_kinetic")
+           "rbsog_set_nose_hoover", "rbsog_get_kinetic", "rbsog_set_msd_origin", "rbsog_get_msd")
 
 
 class RbsogError(RuntimeError):
@@ -90,6 +90,8 @@ def lib():
             "rbsog_get_kbatch": (i32, [vp, i32, vp]),
             "rbsog_set_nose_hoover": (i32, [vp, dbl, dbl]),
             "rbsog_get_kinetic": (i32, [vp, vp, vp]),
+            "rbsog_set_msd_origin": (i32, [vp]),
+            "rbsog_get_msd": (i32, [vp, vp]),
             "rbsog_info": (i32, [vp, i32, P(rbsog_info_t)]),
             "rbsog_debug_cells": (i32, [vp, i32, vp, vp]),
             "rbsog_debug_neighbors": (i32, [vp, i32, vp, vp, i64]),
@@ -277,6 +279,17 @@ def rbsog_get_kinetic(ctx):
     xi = np.zeros(ns)
     _check(lib().rbsog_get_kinetic(ctx, _ptr(K), _ptr(xi)), ctx)
     return K, xi
+
+
+def rbsog_set_msd_origin(ctx):
+    _check(lib().rbsog_set_msd_origin(ctx), ctx)
+
+
+def rbsog_get_msd(ctx):
+    """Mean-square displacement of every system since its origin."""
+    out = np.zeros(n_systems(ctx))
+    _check(lib().rbsog_get_msd(ctx, _ptr(out)), ctx)
+    return out
 
 
 def rbsog_info(ctx, sys: int = 0) -> dict:

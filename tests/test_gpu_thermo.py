@@ -118,3 +118,77 @@ def test_nose_hoover_holds_temperature():
     Tm = float(np.mean(temps))
     say(f"[nose-hoover] kinetic temperature {Tm:.4f} (target {T})")
     assert abs(Tm / T - 1.0) < 0.05
+
+
+def min_image(d, box):
+    return d - box * np.round(d / box)
+
+
+@pytest.mark.parametrize("prec,tol", [(R.RBSOG_FP64, 1e-10), (R.RBSOG_FP32C, 1e-5)])
+def test_msd_matches_oracle_trajectory(orc, prec, tol):
+    # a few velocity-Verlet steps (displacements far below L/2): the MSD is the
+    # mean of the squared minimum-image displacement of the final positions,
+    # those of the device and those of the oracle's run on the same batches
+    n, L = 300, 14.0
+    pos, q, box = W.ions_rsa(n, n / L ** 3, 1.0, 91)
+    v0 = W.maxwellian(n, 1.0, 92)
+    rc, P, dt, steps = 3.5, 40, 2e-3, 8
+    say(f"[gpu] msd vs oracle prec={prec}")
+    sysm = R.System(pos, q, box, rc, P, seed=4, precision=prec)
+    ks = sysm.sample_k(steps + 1)
+    R.rbsog_set_velocities(sysm.ctx, v0)
+    assert (R.rbsog_get_msd(sysm.ctx) == 0).all()
+    sysm.step(steps, dt)
+    msd = R.rbsog_get_msd(sysm.ctx)
+    x, _ = R.rbsog_get_state(sysm.ctx, n)
+    own = float(np.mean(np.sum(min_image(x - pos, box) ** 2, axis=1)))
+    xo, _, _, _ = orc.vv_run(pos, v0, q, box, rc, oracle_sog(orc, sysm.sog), P, ks, steps, dt)
+    ref = float(np.mean(np.sum(min_image(xo - pos, box) ** 2, axis=1)))
+    say(f"[msd prec={prec}] {msd[0]:.12g} own positions {own:.12g} oracle {ref:.12g}")
+    assert ref > 1e-4
+    assert abs(msd[0] - own) < 1e-9 * own
+    assert abs(msd[0] - ref) < 10 * tol * ref
+
+
+def test_msd_of_every_system_across_wraps_and_resorts():
+    # Langevin runs long enough that particles cross the box faces and the
+    # cell order changes many times; the host follows each particle's
+    # unwrapped path from minimum-image increments between short chunks
+    specs = [(1000, 10.0, 3.0, 50, 71), (500, 9.0, 2.9, 37, 72), (64, 6.0, 2.9, 20, 73)]
+    pos_l, q_l, boxes = [], [], []
+    for nn, L, rc, P, sd in specs:
+        p_, q_, b_ = W.ions_rsa(nn, nn / L ** 3, 0.7, sd)
+        pos_l.append(p_), q_l.append(0.2 * q_), boxes.append(b_)
+    b = R.Batch(pos_l, q_l, boxes, [s[2] for s in specs], [s[3] for s in specs], [s[4] for s in specs],
+                precision=R.RBSOG_FP64, device_chains=4)
+    R.rbsog_set_velocities(b.ctx, None, T=3.0, seed=6)
+    R.rbsog_set_thermostat(b.ctx, 1.0, 3.0, seed=7)
+    sizes = b.sizes
+    bounds = np.cumsum(sizes)[:-1]
+    box_of = np.concatenate([np.tile(bx, (nn, 1)) for bx, nn in zip(boxes, sizes)])
+    x_prev, _ = R.rbsog_get_state(b.ctx, b.n)
+    unwrapped = np.zeros_like(x_prev)
+    crossings = 0
+    for chunk in range(40):
+        R.rbsog_step(b.ctx, 5, 5e-3)
+        x, _ = R.rbsog_get_state(b.ctx, b.n)
+        unwrapped += min_image(x - x_prev, box_of)
+        crossings += int(np.sum(np.abs(x - x_prev) > 0.5 * box_of))
+        x_prev = x
+        if chunk == 19:
+            # halfway: a new origin
+            R.rbsog_set_msd_origin(b.ctx)
+            assert (R.rbsog_get_msd(b.ctx) == 0).all()
+            unwrapped[:] = 0
+        if chunk in (9, 39):
+            msd = R.rbsog_get_msd(b.ctx)
+            want = [float(np.mean(np.sum(u * u, axis=1))) for u in np.split(unwrapped, bounds)]
+            say(f"[msd batch chunk {chunk}] {msd} vs {want}")
+            assert np.allclose(msd, want, rtol=1e-9, atol=0)
+    # particles crossed the box faces (their stored positions were wrapped)
+    say(f"[msd batch] {crossings} face crossings")
+    assert crossings > 20
+    R.rbsog_set_positions(b.ctx, np.concatenate(pos_l))
+    assert (R.rbsog_get_msd(b.ctx) == 0).all()
+    R.rbsog_step(b.ctx, 3, 5e-3)
+    assert (R.rbsog_get_msd(b.ctx) > 0).all()
