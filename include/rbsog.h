@@ -246,8 +246,9 @@ rbsog_status rbsog_get_kinetic(rbsog_ctx *ctx, double *K, double *xi);
  * formula, over all particles of a system): every step adds its drift,
  * unwrapped, to a per-particle displacement d; rbsog_get_msd returns
  * (1/n_s) sum |d|^2 of every system (host n_sys doubles; summed on the device
- * in a fixed order).  rbsog_set_msd_origin sets d = 0 (the context starts
- * from 0; rbsog_set_positions also resets it). */
+ * in a fixed order).  Tracking starts with the first rbsog_set_msd_origin,
+ * which sets d = 0 (as does rbsog_set_positions); until then steps do not
+ * carry d and rbsog_get_msd returns RBSOG_E_STATE. */
 rbsog_status rbsog_set_msd_origin(rbsog_ctx *ctx);
 rbsog_status rbsog_get_msd(rbsog_ctx *ctx, double *msd);
 

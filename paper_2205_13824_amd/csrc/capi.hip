@@ -213,6 +213,7 @@ struct rbsog_ctx {
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
     double graph_dt_m[2] = {0.0, 0.0};
+    bool msd_on = false;  // displacements tracked since rbsog_set_msd_origin
     // profiling
     bool prof_on = false;
     ProfEntry prof[K_COUNT];
@@ -511,6 +512,7 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
     a.ksys = c->ksys;
     a.cur = c->buf[0];
     a.nxt = c->buf[1];
+    if (!c->msd_on) a.cur.dsp = a.nxt.dsp = nullptr;  // the kernels skip the displacement
     a.u_tmp = c->u_tmp;
     a.u = c->u;
     a.cell_of = c->cell_of;
@@ -1882,12 +1884,17 @@ rbsog_status rbsog_set_msd_origin(rbsog_ctx *c) {
     TRY(check_ctx(c));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemset(c->buf[0].dsp, 0, (size_t)3 * c->N * sizeof(double)));
+    if (!c->msd_on) {
+        c->msd_on = true;
+        drop_graphs(c);  // the captured steps skip the displacement
+    }
     return RBSOG_OK;
 }
 
 rbsog_status rbsog_get_msd(rbsog_ctx *c, double *msd) {
     TRY(check_ctx(c));
     if (!msd) return fail(c, RBSOG_E_ARG, "msd is null");
+    if (!c->msd_on) return fail(c, RBSOG_E_STATE, "no mean-square-displacement origin: call rbsog_set_msd_origin");
     const EvalArgs a = make_args(c, false, 0.0);
     launch_msd(a, c->msd, c->stream);
     HIPCHK(c, hipGetLastError());

@@ -173,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_kdq(EvalArgs a, int32_t pblocks) {
         }
         if (bad && valid) atomicOr(a.flag, 1);
         // the step's drift, unwrapped, for the mean-square displacement
-        if (valid)
+        if (valid && a.cur.dsp)
             for (int d = 0; d < 3; ++d) a.cur.dsp[d * N + t] += xs[d] - xs0[d];
     }
     float d2 = 0.f;
@@ -369,9 +369,10 @@ __global__ __launch_bounds__(kBlock) void k_gather(EvalArgs a) {
     for (int d = 0; d < 3; ++d) {
         a.nxt.x[d * N + k] = a.cur.x[d * N + t];
         a.nxt.v[d * N + k] = a.cur.v[d * N + t];
-        a.nxt.dsp[d * N + k] = a.cur.dsp[d * N + t];
         a.u[d * N + k] = a.u_tmp[d * N + t];
     }
+    if (a.cur.dsp)
+        for (int d = 0; d < 3; ++d) a.nxt.dsp[d * N + k] = a.cur.dsp[d * N + t];
     a.nxt.q[k] = a.cur.q[t];
     a.nxt.qf[k] = a.cur.qf[t];
     a.nxt.id[k] = a.cur.id[t];

@@ -434,9 +434,10 @@ __device__ __forceinline__ void copy_back(const EvalArgs &a, int64_t i0, int64_t
         for (int d = 0; d < 3; ++d) {
             a.cur.x[d * n + i] = a.nxt.x[d * n + i];
             a.cur.v[d * n + i] = a.nxt.v[d * n + i];
-            a.cur.dsp[d * n + i] = a.nxt.dsp[d * n + i];
             a.u_tmp[d * n + i] = a.u[d * n + i];
         }
+        if (a.cur.dsp)
+            for (int d = 0; d < 3; ++d) a.cur.dsp[d * n + i] = a.nxt.dsp[d * n + i];
         a.cur.q[i] = a.nxt.q[i];
         a.cur.qf[i] = a.nxt.qf[i];
         a.cur.id[i] = a.nxt.id[i];

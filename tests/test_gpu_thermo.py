@@ -137,6 +137,10 @@ def test_msd_matches_oracle_trajectory(orc, prec, tol):
     sysm = R.System(pos, q, box, rc, P, seed=4, precision=prec)
     ks = sysm.sample_k(steps + 1)
     R.rbsog_set_velocities(sysm.ctx, v0)
+    with pytest.raises(R.RbsogError) as e:
+        R.rbsog_get_msd(sysm.ctx)  # not tracked before an origin is set
+    assert e.value.status == -9
+    R.rbsog_set_msd_origin(sysm.ctx)
     assert (R.rbsog_get_msd(sysm.ctx) == 0).all()
     sysm.step(steps, dt)
     msd = R.rbsog_get_msd(sysm.ctx)
@@ -163,6 +167,7 @@ def test_msd_of_every_system_across_wraps_and_resorts():
                 precision=R.RBSOG_FP64, device_chains=4)
     R.rbsog_set_velocities(b.ctx, None, T=3.0, seed=6)
     R.rbsog_set_thermostat(b.ctx, 1.0, 3.0, seed=7)
+    R.rbsog_set_msd_origin(b.ctx)
     sizes = b.sizes
     bounds = np.cumsum(sizes)[:-1]
     box_of = np.concatenate([np.tile(bx, (nn, 1)) for bx, nn in zip(boxes, sizes)])
@@ -192,3 +197,21 @@ def test_msd_of_every_system_across_wraps_and_resorts():
     assert (R.rbsog_get_msd(b.ctx) == 0).all()
     R.rbsog_step(b.ctx, 3, 5e-3)
     assert (R.rbsog_get_msd(b.ctx) > 0).all()
+
+
+def test_msd_tracking_leaves_the_trajectory_unchanged():
+    n, L = 500, 12.0
+    pos, q, box = W.ions_rsa(n, n / L ** 3, 1.0, 93)
+    out = []
+    for track in (False, True):
+        sysm = R.System(pos, q, box, 3.0, 50, seed=3, precision=R.RBSOG_FP32C, device_chains=4)
+        R.rbsog_set_velocities(sysm.ctx, None, T=1.0, seed=2)
+        sysm.step(6, 2e-3)
+        if track:
+            R.rbsog_set_msd_origin(sysm.ctx)
+        sysm.step(30, 2e-3)
+        out.append(R.rbsog_get_state(sysm.ctx, n))
+        if track:
+            assert R.rbsog_get_msd(sysm.ctx)[0] > 0
+        sysm.close()
+    assert (out[0][0] == out[1][0]).all() and (out[0][1] == out[1][1]).all()
