@@ -156,6 +156,9 @@ struct rbsog_ctx {
     int32_t *sys_of = nullptr, *ksys = nullptr;
     StateBufs buf[2] = {};
     uint32_t *u_tmp = nullptr, *u = nullptr;
+    uint32_t *rs_u = nullptr;  // the structure factor's copy of the state
+    float *rs_qf = nullptr;
+    double *rs_x = nullptr, *rs_q = nullptr;
     int32_t *cell_of = nullptr, *cell_count = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *src = nullptr,
             *sorted = nullptr, *blocksums = nullptr, *cell_sorted = nullptr;
     // Verlet list: skin (fraction of r_c), pairs, per-item counts and
@@ -515,6 +518,10 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
     if (!c->msd_on) a.cur.dsp = a.nxt.dsp = nullptr;  // the kernels skip the displacement
     a.u_tmp = c->u_tmp;
     a.u = c->u;
+    a.rs_u = c->rs_u;
+    a.rs_qf = c->rs_qf;
+    a.rs_x = c->rs_x;
+    a.rs_q = c->rs_q;
     a.cell_of = c->cell_of;
     a.cell_count = c->cell_count;
     a.cell_start = c->cell_start;
@@ -568,18 +575,18 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
 // every time and return at once unless the displacement check (or the host)
 // asked for a build.  Pure launches: no host state changes, so it can be
 // captured into a graph.
-rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt) {
+// `kinetic`: sum the kinetic energy and U_N, U of the evaluation.  Steps
+// without the Nose-Hoover thermostat leave it to the end of their run of
+// steps (nothing reads the values in between).
+rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt, bool kinetic) {
     hipStream_t s = c->stream;
     const bool f64 = c->prec == RBSOG_FP64;
     const EvalArgs a = make_args(c, stepping, dt);
     TRY(timed(c, K_KDQ, [&] { launch_kdq(a, s); }));
-    if (!a.always_build) TRY(timed(c, K_BIN, [&] { launch_bin(a, s); }));
-    TRY(timed(c, K_SCAN, [&] { launch_scan(a, s); }));
-    TRY(timed(c, K_SCATTER, [&] { launch_cell_scatter(a, s); }));
-    TRY(timed(c, K_SORTG, [&] { launch_sort_gather(a, s); }));
-    // the structure factor and its reduction need the positions and the
-    // staged k records only: they run on the side stream beside the near part
-    // (one stream while profiling, so that each kernel is timed alone)
+    // the structure factor and its reduction need the copy of the positions
+    // and the k records staged by the kick/drift kernel only: they run on the
+    // side stream beside the re-sort and the near part (one stream while
+    // profiling, so that each kernel is timed alone)
     const bool fork = !c->prof_on;
     if (fork) {
         HIPCHK(c, hipEventRecord(c->ev_fork, s));
@@ -588,6 +595,10 @@ rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt) {
         launch_rho_reduce(a, c->side);
         HIPCHK(c, hipEventRecord(c->ev_join, c->side));
     }
+    if (!a.always_build) TRY(timed(c, K_BIN, [&] { launch_bin(a, s); }));
+    TRY(timed(c, K_SCAN, [&] { launch_scan(a, s); }));
+    TRY(timed(c, K_SCATTER, [&] { launch_cell_scatter(a, s); }));
+    TRY(timed(c, K_SORTG, [&] { launch_sort_gather(a, s); }));
     if (a.always_build) {
         TRY(timed(c, K_NEARC, [&] { launch_near_cells(a, f64, c->near_items, c->n_near, c->cell_slots, s); }));
     } else {
@@ -601,7 +612,7 @@ rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt) {
         TRY(timed(c, K_RHORED, [&] { launch_rho_reduce(a, s); }));
     }
     TRY(timed(c, K_FAR, [&] { launch_far(a, f64, c->far_items, c->n_far, c->tune.far_block, s); }));
-    launch_kinetic(a, s);
+    if (kinetic) launch_kinetic(a, s);
     HIPCHK(c, hipGetLastError());
     return RBSOG_OK;
 }
@@ -649,7 +660,7 @@ rbsog_status ensure_step_graphs(rbsog_ctx *c, double dt) {
     c->graph_exec[m] = nullptr;
     c->graph[m] = nullptr;
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
-    rbsog_status st = enqueue_eval(c, true, dt);
+    rbsog_status st = enqueue_eval(c, true, dt, c->nh_on);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->stream, &g);
     if (st != RBSOG_OK) {
@@ -1493,6 +1504,14 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     ALLOC(ksys, K);
     ALLOC(u_tmp, 3 * N);
     ALLOC(u, 3 * N);
+    if (c->prec != RBSOG_FP64) {
+        ALLOC(rs_u, 3 * N);
+        ALLOC(rs_qf, N);
+    }
+    if (c->prec == RBSOG_FP64 || c->sys[0].zmode != 0) {
+        ALLOC(rs_x, 3 * N);
+        ALLOC(rs_q, N);
+    }
     ALLOC(cell_of, N);
     ALLOC(src, N);
     ALLOC(sorted, N);
@@ -1728,7 +1747,7 @@ rbsog_status rbsog_forces(rbsog_ctx *c, double *F_out, double *E_out) {
     TRY(check_ctx(c));
     TRY(check_kseq(c, 1));
     TRY(refill_if_due(c));
-    TRY(enqueue_eval(c, false, 0.0));
+    TRY(enqueue_eval(c, false, 0.0, true));
     account_eval(c);
     {
         int32_t flag = 0;
@@ -1755,7 +1774,7 @@ rbsog_status rbsog_step(rbsog_ctx *c, int64_t n_steps, double dt) {
     TRY(check_kseq(c, n_steps + (c->forces_valid ? 0 : 1)));
     if (!c->forces_valid) {
         TRY(refill_if_due(c));
-        TRY(enqueue_eval(c, false, 0.0));
+        TRY(enqueue_eval(c, false, 0.0, true));
         account_eval(c);
     }
     if (c->autotune && !c->tuned && !c->prof_on) TRY(autotune_now(c, 5));
@@ -1767,8 +1786,14 @@ rbsog_status rbsog_step(rbsog_ctx *c, int64_t n_steps, double dt) {
         for (int64_t i = 0; i < chunk; ++i) {
             TRY(refill_if_due(c));
             if (graphs) HIPCHK(c, hipGraphLaunch(c->graph_exec[graph_mode(c)], c->stream));
-            else TRY(enqueue_eval(c, true, dt));
+            else TRY(enqueue_eval(c, true, dt, c->nh_on));
             account_eval(c);
+        }
+        if (!c->nh_on && chunk > 0) {
+            // the energies of the chunk's last evaluation (before a switch of
+            // the near mode changes where its partial sums are read)
+            launch_kinetic(make_args(c, false, 0.0), c->stream);
+            HIPCHK(c, hipGetLastError());
         }
         k += chunk;
         c->adapt_steps += chunk;

@@ -106,14 +106,12 @@ template <bool F64>
 __global__ __launch_bounds__(1024) void k_rho(EvalArgs a, const RhoItem *__restrict__ items, int32_t nitems) {
     __shared__ double2 red[1024];
     const int64_t n = a.N;
-    // On a step with a near-list build this kernel may run while the
-    // gathered state is copied back into `cur`: it reads the gathered copy
-    // (`nxt`, `u`), which holds the same values in the same order.
-    const bool built = a.rebuild && *a.rebuild;
-    const double *__restrict__ x = built ? a.nxt.x : a.cur.x;
-    const double *__restrict__ q = built ? a.nxt.q : a.cur.q;
-    const float *__restrict__ qf = built ? a.nxt.qf : a.cur.qf;
-    const uint32_t *__restrict__ u = built ? a.u : a.u_tmp;
+    // the state as the kick/drift kernel left it, in its copy: the re-sort of
+    // the state into cell order may run meanwhile
+    const double *__restrict__ x = a.rs_x;
+    const double *__restrict__ q = a.rs_q;
+    const float *__restrict__ qf = a.rs_qf;
+    const uint32_t *__restrict__ u = a.rs_u;
     // the wave index is uniform: readfirstlane lets the particle loads below
     // be scalar loads shared by the whole wave
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));

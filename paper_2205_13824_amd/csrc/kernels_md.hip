@@ -188,10 +188,16 @@ __global__ __launch_bounds__(kBlock) void k_kdq(EvalArgs a, int32_t pblocks) {
         if (valid) {
             a.u_tmp[d * N + t] = ud;
             x[d * N + t] = f * L[d];
+            if (a.rs_u) a.rs_u[d * N + t] = ud;
+            if (a.rs_x) a.rs_x[d * N + t] = f * L[d];
         }
         // the wrapped fixed-point difference is the minimum image
         const float dd = (float)(int32_t)(ud - uref[d]) * hf[d];
         d2 += dd * dd;
+    }
+    if (valid) {
+        if (a.rs_qf) a.rs_qf[t] = a.cur.qf[t];
+        if (a.rs_q) a.rs_q[t] = a.cur.q[t];
     }
     if (a.always_build) {
         // every evaluation builds: the cell and the histogram here (no bin pass)
@@ -263,25 +269,16 @@ __global__ void k_scan_blocks(const int32_t *__restrict__ in, int64_t n, int32_t
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-__global__ void k_scan_sums(int32_t *bsum, int64_t nb, const int32_t *__restrict__ cond) {
-    if (!*cond) return;
-    // one block: exclusive scan of the block totals in place
-    int64_t per = (nb + kBlock - 1) / kBlock;
-    int64_t lo = threadIdx.x * per, hi = lo + per < nb ? lo + per : nb;
-    int32_t s = 0;
-    for (int64_t k = lo; k < hi; ++k) s += bsum[k];
-    int32_t tot;
-    int32_t off = block_exclusive_scan(s, &tot);
-    for (int64_t k = lo; k < hi; ++k) {
-        int32_t v = bsum[k];
-        bsum[k] = off;
-        off += v;
-    }
-}
-
+// Each block adds the totals of the blocks before it (read in parallel from
+// L2 and reduced in a fixed order) to its own exclusive scan.
 __global__ void k_scan_apply(const int32_t *__restrict__ in, int64_t n, const int32_t *__restrict__ bsum,
                              int32_t *__restrict__ out, int32_t *__restrict__ fill, const int32_t *__restrict__ cond) {
     if (!*cond) return;
+    int32_t pre = 0;
+#pragma unroll 4
+    for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += kBlock) pre += bsum[b];
+    int32_t before;
+    block_exclusive_scan(pre, &before);
     int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int32_t vals[kScanItems];
     int32_t s = 0;
@@ -290,7 +287,7 @@ __global__ void k_scan_apply(const int32_t *__restrict__ in, int64_t n, const in
         s += vals[k];
     }
     int32_t tot;
-    int32_t off = block_exclusive_scan(s, &tot) + bsum[blockIdx.x];
+    int32_t off = block_exclusive_scan(s, &tot) + before;
     for (int k = 0; k < kScanItems; ++k) {
         if (base + k < n) {
             out[base + k] = off;
@@ -313,70 +310,103 @@ __global__ __launch_bounds__(kBlock) void k_cell_scatter(int64_t N, const int32_
 }
 
 // Per cell: order of its slots by particle id (the order becomes (cell, id),
-// independent of the scatter's atomic order), written to `sorted`, and reset
-// of its histogram count for the next evaluation.  Cells of up to kRankMax
+// independent of the scatter's atomic order), and reset of its histogram
+// count for the next evaluation; then the block gathers the state of its
+// cells' slots into `nxt` in the new order, one thread per slot (writes are
+// coalesced, reads stay close: particles move little between builds).  The
+// positions become the new list reference `u`.  Cells of up to kRankMax
 // particles load their keys at once and rank them in registers; larger cells
 // take an insertion sort in memory.
 constexpr int kRankMax = 16;
 
-__global__ __launch_bounds__(kBlock) void k_cell_sort(EvalArgs a) {
+__global__ __launch_bounds__(kBlock) void k_sort_gather(EvalArgs a) {
     if (!*a.rebuild) return;
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= a.C) return;
-    const int32_t lo = a.cell_start[c], hi = a.cell_start[c + 1];
-    const int32_t cnt = hi - lo;
-    const int32_t *src = a.src;
+    const int64_t c0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t c = c0 + threadIdx.x;
     int32_t *out = a.sorted;
-    const int32_t *idc = a.cur.id;
-    if (cnt <= kRankMax) {
-        int32_t sv[kRankMax], key[kRankMax];
+    if (c < a.C) {
+        const int32_t lo = a.cell_start[c], hi = a.cell_start[c + 1];
+        const int32_t cnt = hi - lo;
+        const int32_t *src = a.src;
+        const int32_t *idc = a.cur.id;
+        if (cnt <= kRankMax) {
+            int32_t sv[kRankMax], key[kRankMax];
 #pragma unroll
-        for (int i = 0; i < kRankMax; ++i) sv[i] = i < cnt ? src[lo + i] : 0;
+            for (int i = 0; i < kRankMax; ++i) sv[i] = i < cnt ? src[lo + i] : 0;
 #pragma unroll
-        for (int i = 0; i < kRankMax; ++i) key[i] = i < cnt ? idc[sv[i]] : INT32_MAX;
+            for (int i = 0; i < kRankMax; ++i) key[i] = i < cnt ? idc[sv[i]] : INT32_MAX;
 #pragma unroll
-        for (int i = 0; i < kRankMax; ++i) {
-            int32_t rank = 0;
+            for (int i = 0; i < kRankMax; ++i) {
+                int32_t rank = 0;
 #pragma unroll
-            for (int j = 0; j < kRankMax; ++j) rank += key[j] < key[i] ? 1 : 0;
-            if (i < cnt) out[lo + rank] = sv[i];
-        }
-    } else {
-        for (int32_t i = lo; i < hi; ++i) out[i] = src[i];
-        for (int32_t i = lo + 1; i < hi; ++i) {
-            const int32_t v = out[i];
-            const int32_t kv = idc[v];
-            int32_t j = i - 1;
-            while (j >= lo && idc[out[j]] > kv) {
-                out[j + 1] = out[j];
-                --j;
+                for (int j = 0; j < kRankMax; ++j) rank += key[j] < key[i] ? 1 : 0;
+                if (i < cnt) out[lo + rank] = sv[i];
             }
-            out[j + 1] = v;
+        } else {
+            for (int32_t i = lo; i < hi; ++i) out[i] = src[i];
+            for (int32_t i = lo + 1; i < hi; ++i) {
+                const int32_t v = out[i];
+                const int32_t kv = idc[v];
+                int32_t j = i - 1;
+                while (j >= lo && idc[out[j]] > kv) {
+                    out[j + 1] = out[j];
+                    --j;
+                }
+                out[j + 1] = v;
+            }
+        }
+        a.cell_count[c] = 0;
+    }
+    // the block's permutation entries are visible to the whole block here
+    __syncthreads();
+    const int64_t c1 = c0 + kBlock < a.C ? c0 + kBlock : a.C;
+    const int64_t k0 = a.cell_start[c0], k1 = a.cell_start[c1];
+    const int64_t N = a.N;
+    // four slots per thread and pass, all loads issued before the stores
+    constexpr int U = 4;
+    for (int64_t kb = k0 + threadIdx.x; kb < k1; kb += U * kBlock) {
+        int64_t tt[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) tt[j] = kb + j * kBlock < k1 ? out[kb + j * kBlock] : -1;
+        double xv[U][3], vv[U][3], qv[U];
+        uint32_t uv[U][3];
+        float qfv[U];
+        int32_t idv[U], cv[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int64_t t = tt[j] < 0 ? 0 : tt[j];
+            for (int d = 0; d < 3; ++d) {
+                xv[j][d] = a.cur.x[d * N + t];
+                vv[j][d] = a.cur.v[d * N + t];
+                uv[j][d] = a.u_tmp[d * N + t];
+            }
+            qv[j] = a.cur.q[t];
+            qfv[j] = a.cur.qf[t];
+            idv[j] = a.cur.id[t];
+            cv[j] = a.cell_of[t];
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int64_t k = kb + j * kBlock;
+            if (tt[j] < 0) continue;
+            for (int d = 0; d < 3; ++d) {
+                a.nxt.x[d * N + k] = xv[j][d];
+                a.nxt.v[d * N + k] = vv[j][d];
+                a.u[d * N + k] = uv[j][d];
+            }
+            a.nxt.q[k] = qv[j];
+            a.nxt.qf[k] = qfv[j];
+            a.nxt.id[k] = idv[j];
+            a.cell_sorted[k] = cv[j];
+        }
+        if (a.cur.dsp) {
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                if (tt[j] < 0) continue;
+                for (int d = 0; d < 3; ++d) a.nxt.dsp[d * N + kb + j * kBlock] = a.cur.dsp[d * N + tt[j]];
+            }
         }
     }
-    a.cell_count[c] = 0;
-}
-
-// Gather of the state into `nxt` in the new order, one thread per new slot:
-// writes are coalesced and the reads stay close (particles move little
-// between builds).  The positions become the new list reference `u`.
-__global__ __launch_bounds__(kBlock) void k_gather(EvalArgs a) {
-    if (!*a.rebuild) return;
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.N) return;
-    const int64_t N = a.N;
-    const int64_t t = a.sorted[k];
-    for (int d = 0; d < 3; ++d) {
-        a.nxt.x[d * N + k] = a.cur.x[d * N + t];
-        a.nxt.v[d * N + k] = a.cur.v[d * N + t];
-        a.u[d * N + k] = a.u_tmp[d * N + t];
-    }
-    if (a.cur.dsp)
-        for (int d = 0; d < 3; ++d) a.nxt.dsp[d * N + k] = a.cur.dsp[d * N + t];
-    a.nxt.q[k] = a.cur.q[t];
-    a.nxt.qf[k] = a.cur.qf[t];
-    a.nxt.id[k] = a.cur.id[t];
-    a.cell_sorted[k] = a.cell_of[t];
 }
 
 }  // namespace
@@ -399,11 +429,9 @@ void launch_bin(const EvalArgs &a, hipStream_t s) {
 
 void launch_scan(const EvalArgs &a, hipStream_t s) {
     const int64_t n = a.C;
-
-    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(kBlock), 0, s, a.cell_count, n, a.blocksums,
                        (const int32_t *)a.rebuild);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, a.blocksums, nb, (const int32_t *)a.rebuild);
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kBlock), 0, s, a.cell_count, n, a.blocksums,
                        a.cell_start, a.cell_fill, (const int32_t *)a.rebuild);
 }
@@ -414,8 +442,7 @@ void launch_cell_scatter(const EvalArgs &a, hipStream_t s) {
 }
 
 void launch_sort_gather(const EvalArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_cell_sort, dim3(grid_for(a.C, kBlock)), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(k_gather, dim3(grid_for(a.N, kBlock)), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_sort_gather, dim3(grid_for(a.C, kBlock)), dim3(kBlock), 0, s, a);
 }
 
 }  // namespace rbsog

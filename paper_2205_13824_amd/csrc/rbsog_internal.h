@@ -163,6 +163,13 @@ struct EvalArgs {
     StateBufs cur, nxt;
     uint32_t *u_tmp;       // fixed-point coordinates of the current positions
     uint32_t *u;           // fixed-point coordinates at the latest list build (its reference)
+    // copy of the positions and charges taken by the kick/drift kernel for
+    // the structure factor, which runs beside the re-sort of the state:
+    // fixed-point coordinates and FP32 charges (FP32C), FP64 positions and
+    // charges (FP64, or the zero-frequency mode's dipole); null when unused
+    uint32_t *rs_u;
+    float *rs_qf;
+    double *rs_x, *rs_q;
     int32_t *cell_of, *cell_count, *cell_start, *cell_fill, *src, *sorted, *blocksums;
     int32_t *cell_sorted;  // cell of each slot at the latest list build
     double *Fn, *Ff;       // forces in slot order
