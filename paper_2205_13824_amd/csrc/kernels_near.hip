@@ -43,6 +43,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kRanges = 18; // 9 rows of cells x up to 2 contiguous pieces
+constexpr float kFarR2 = 3.0e38f;  // r^2 of a pair that no test admits
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
@@ -138,6 +139,10 @@ __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
+
+// Mask of the active lanes for which p holds (the lane mask the compare
+// already produced, without going through a vector register).
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 // Values the wave holds in common (loaded or broadcast): keep them scalar.
 __device__ __forceinline__ int32_t rfl(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -384,14 +389,14 @@ __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>:
     e += de;
     const int prev = __shfl_up(slot, 1, 64);
     const bool seg = lane == 0 || slot != prev;
-    const uint64_t H = __ballot(seg);
+    const uint64_t H = ballot(seg);
     const uint64_t upto = H & ((2ull << lane) - 1ull);
     const int sstart = 63 - __clzll((long long)upto);
     seg_scan3<R>(fx, fy, fz, lane, sstart);
     // a pass can hold two runs of one home (two candidate passes of the
     // build), so segment totals are added atomically; the adds of one wave
     // into its own slots happen in a fixed order
-    const int count = (int)__popcll(__ballot(have));  // the lanes holding pairs are a prefix
+    const int count = (int)__popcll(ballot(have));  // the lanes holding pairs are a prefix
     const bool tail = have && (lane == count - 1 || (lane < 63 && ((H >> (lane + 1)) & 1ull)));
     if (tail) {
         atomicAdd(&L.hf[0][slot], fx);
@@ -585,7 +590,7 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
         // first slot and its offset in the flattened list (offsets strictly
         // increase, the first is 0)
         const bool ne = lane < kRanges && len > 0;
-        const uint64_t NE = __ballot(ne);
+        const uint64_t NE = ballot(ne);
         const int nne = (int)__popcll(NE);
         if (ne) {
             const int k = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(NE >> 32),
@@ -613,8 +618,8 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
                 wave_sync();
                 if (lane < nne && cex >= base && cex < base + 64) L.flag[cex - base] = 1;
                 wave_sync();
-                const uint64_t B = __ballot(L.flag[lane] != 0);
-                const int before = (int)__popcll(__ballot(lane < nne && cex < base));
+                const uint64_t B = ballot(L.flag[lane] != 0);
+                const int before = (int)__popcll(ballot(lane < nne && cex < base));
                 const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
                 int k = before + (int)__popcll(B & upto) - 1;
                 k = k < 0 ? 0 : k;
@@ -690,7 +695,7 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
                     for (int uu = 0; uu < kU; ++uu) {
 #pragma unroll
                         for (int s2 = 0; s2 < S; ++s2) {
-                            const uint64_t mm = __ballot(acc[uu][s2]);
+                            const uint64_t mm = ballot(acc[uu][s2]);
                             if (acc[uu][s2]) {
                                 const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi(
                                                          (uint32_t)(mm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0));
@@ -968,7 +973,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
             // first slot and its offset in the flattened list (offsets strictly
             // increase, the first is 0)
             const bool ne = lane < kRanges && len > 0;
-            const uint64_t NE = __ballot(ne);
+            const uint64_t NE = ballot(ne);
             const int nne = (int)__popcll(NE);
             if (ne) {
                 const int k = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(NE >> 32),
@@ -997,8 +1002,8 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
                     wave_sync();
                     if (lane < nne && cex >= base && cex < base + 64) L.flag[cex - base] = 1;
                     wave_sync();
-                    const uint64_t B = __ballot(L.flag[lane] != 0);
-                    const int before = (int)__popcll(__ballot(lane < nne && cex < base));
+                    const uint64_t B = ballot(L.flag[lane] != 0);
+                    const int before = (int)__popcll(ballot(lane < nne && cex < base));
                     const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
                     int k = before + (int)__popcll(B & upto) - 1;
                     k = k < 0 ? 0 : k;
@@ -1044,11 +1049,23 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
                     const float hfy = (float)(int32_t)(hme.y - oy) * g.hf[1];
                     const float hfz = (float)(int32_t)(hme.z - oz) * g.hf[2];
                     for (int ii = 0; ii < gn; ii += kU) {
+                        // acceptance of each (home, slot) as a lane predicate
+                        // and as the wave's mask: both come from one compare
+                        // (the home itself and the empty slots are pushed
+                        // past the band by their r^2)
                         bool acc[kU][S];
+                        uint64_t mm[kU][S];
 #pragma unroll
                         for (int uu = 0; uu < kU; ++uu) {
-                            const int h = ii + uu < gn ? ii + uu : ii;
-                            const bool hok = ii + uu < gn;
+                            const int h = ii + uu;
+                            if (h >= gn) {  // uniform: past the group's end
+#pragma unroll
+                                for (int s2 = 0; s2 < S; ++s2) {
+                                    acc[uu][s2] = false;
+                                    mm[uu][s2] = 0ull;
+                                }
+                                continue;
+                            }
                             const uint32_t self = (uint32_t)(t + g0 + h);
                             if (rel) {
                                 const float hx_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfx), h));
@@ -1058,7 +1075,9 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
                                 for (int s2 = 0; s2 < S; ++s2) {
                                     const float dx = cfx[s2] - hx_, dy = cfy[s2] - hy_, dz = cfz[s2] - hz_;
                                     const float r2 = dx * dx + dy * dy + dz * dz;
-                                    acc[uu][s2] = hok && r2 < g.band_hi_f && cj[s2] != self;
+                                    const float r2x = cj[s2] == self ? kFarR2 : r2;
+                                    acc[uu][s2] = r2x < g.band_hi_f;
+                                    mm[uu][s2] = ballot(r2x < g.band_hi_f);
                                 }
                             } else {
                                 const uint32_t hux = (uint32_t)__builtin_amdgcn_readlane((int)hme.x, h);
@@ -1067,7 +1086,9 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
 #pragma unroll
                                 for (int s2 = 0; s2 < S; ++s2) {
                                     const float r2 = fixed_r2(g, cux[s2] - hux, cuy[s2] - huy, cuz[s2] - huz);
-                                    acc[uu][s2] = hok && cj[s2] != kNoCand && r2 < g.band_hi_f && cj[s2] != self;
+                                    const float r2x = cj[s2] == self || cj[s2] == kNoCand ? kFarR2 : r2;
+                                    acc[uu][s2] = r2x < g.band_hi_f;
+                                    mm[uu][s2] = ballot(r2x < g.band_hi_f);
                                 }
                             }
                         }
@@ -1075,13 +1096,13 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
                         for (int uu = 0; uu < kU; ++uu) {
 #pragma unroll
                             for (int s2 = 0; s2 < S; ++s2) {
-                                const uint64_t mm = __ballot(acc[uu][s2]);
+                                const uint64_t m = mm[uu][s2];
                                 if (acc[uu][s2]) {
-                                    const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi(
-                                                             (uint32_t)(mm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0));
+                                    const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
+                                        (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)qn));
                                     L.q[pos & (Q - 1)] = make_uint2((uint32_t)(g0 + ii + uu), cj[s2]);
                                 }
-                                qn += (int)__popcll(mm);
+                                qn += (int)__popcll(m);
                             }
                         }
                         // at most 63 + kU * S * 64 entries are pending: the ring holds them
