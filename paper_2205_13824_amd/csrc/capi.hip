@@ -73,6 +73,10 @@ struct ProfEntry {
 };
 
 constexpr int64_t kAdaptSteps = 32;  // steps between checks of the near-list build rate
+constexpr int kGraphSteps = 8;       // steps in the longer step graph
+// step graphs: one step without the near energies, one step with them (the
+// last step of a run), kGraphSteps steps without them
+enum { GV_STEP = 0, GV_STEP_E = 1, GV_MULTI = 2, GV_COUNT = 3 };
 
 enum Kid {
     K_KDQ, K_BIN, K_SCAN, K_SCATTER, K_SORTG, K_LIST, K_NEAR, K_NEARC, K_RHO, K_RHORED, K_FAR, K_SAMPLE, K_COUNT
@@ -210,12 +214,13 @@ struct rbsog_ctx {
     Tune tune;
     bool tuned = false, autotune = false;
     std::string tune_key;
-    // graph of one velocity-Verlet step, one per near mode (0: list kept,
-    // 1: every step builds), so that the adaptive skin's switches reuse them
+    // graphs of velocity-Verlet steps, per near mode (0: list kept, 1: every
+    // step builds, so that the adaptive skin's switches reuse them) and per
+    // variant (GV_*)
     bool use_graphs = true;
-    hipGraph_t graph[2] = {nullptr, nullptr};
-    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
-    double graph_dt_m[2] = {0.0, 0.0};
+    hipGraph_t graph[2][GV_COUNT] = {};
+    hipGraphExec_t graph_exec[2][GV_COUNT] = {};
+    double graph_dt_m[2][GV_COUNT] = {};
     bool msd_on = false;  // displacements tracked since rbsog_set_msd_origin
     // profiling
     bool prof_on = false;
@@ -554,6 +559,7 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
     a.flag = c->flag;
     a.sys_done = c->sys_done;
     a.kick = stepping ? 1 : 0;
+    a.energy = 1;
     a.hdm = 0.5 * dt / c->mass;
     a.dt = dt;
     a.mass = c->mass;
@@ -575,13 +581,15 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
 // every time and return at once unless the displacement check (or the host)
 // asked for a build.  Pure launches: no host state changes, so it can be
 // captured into a graph.
-// `kinetic`: sum the kinetic energy and U_N, U of the evaluation.  Steps
-// without the Nose-Hoover thermostat leave it to the end of their run of
-// steps (nothing reads the values in between).
-rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt, bool kinetic) {
+// `kinetic`: sum the kinetic energy and U_N, U of the evaluation; `energy`:
+// the near kernels sum the pair energies.  Steps without the Nose-Hoover
+// thermostat leave both to the last step of their run (nothing reads the
+// values in between).
+rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt, bool kinetic, bool energy) {
     hipStream_t s = c->stream;
     const bool f64 = c->prec == RBSOG_FP64;
-    const EvalArgs a = make_args(c, stepping, dt);
+    EvalArgs a = make_args(c, stepping, dt);
+    a.energy = energy ? 1 : 0;
     TRY(timed(c, K_KDQ, [&] { launch_kdq(a, s); }));
     // the structure factor and its reduction need the copy of the positions
     // and the k records staged by the kick/drift kernel only: they run on the
@@ -637,30 +645,32 @@ void account_eval(rbsog_ctx *c) {
     c->forces_valid = true;
 }
 
+void drop_graph(rbsog_ctx *c, int m, int v) {
+    if (c->graph_exec[m][v]) (void)hipGraphExecDestroy(c->graph_exec[m][v]);
+    if (c->graph[m][v]) (void)hipGraphDestroy(c->graph[m][v]);
+    c->graph_exec[m][v] = nullptr;
+    c->graph[m][v] = nullptr;
+}
+
 void drop_graphs(rbsog_ctx *c) {
-    for (int m = 0; m < 2; ++m) {
-        if (c->graph_exec[m]) (void)hipGraphExecDestroy(c->graph_exec[m]);
-        if (c->graph[m]) (void)hipGraphDestroy(c->graph[m]);
-        c->graph_exec[m] = nullptr;
-        c->graph[m] = nullptr;
-    }
+    for (int m = 0; m < 2; ++m)
+        for (int v = 0; v < GV_COUNT; ++v) drop_graph(c, m, v);
 }
 
 int graph_mode(const rbsog_ctx *c) { return c->skin_cur > 0.0 ? 0 : 1; }
 
-// The graph of one step captures the kernel arguments; it is rebuilt when dt
-// or a buffer changes.  Sequence buffers, the cell grid and the cell-run
-// items are reached through device tables, so re-sampling and the adaptive
-// skin's switches (one graph per near mode) do not invalidate it.
-rbsog_status ensure_step_graphs(rbsog_ctx *c, double dt) {
+// A step graph captures the kernel arguments; it is rebuilt when dt or a
+// buffer changes.  Sequence buffers, the cell grid and the cell-run items are
+// reached through device tables, so re-sampling and the adaptive skin's
+// switches (one graph per near mode) do not invalidate it.
+rbsog_status ensure_step_graph(rbsog_ctx *c, double dt, int v) {
     const int m = graph_mode(c);
-    if (c->graph_exec[m] && c->graph_dt_m[m] == dt) return RBSOG_OK;
-    if (c->graph_exec[m]) (void)hipGraphExecDestroy(c->graph_exec[m]);
-    if (c->graph[m]) (void)hipGraphDestroy(c->graph[m]);
-    c->graph_exec[m] = nullptr;
-    c->graph[m] = nullptr;
+    if (c->graph_exec[m][v] && c->graph_dt_m[m][v] == dt) return RBSOG_OK;
+    drop_graph(c, m, v);
+    const int len = v == GV_MULTI ? kGraphSteps : 1;
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
-    rbsog_status st = enqueue_eval(c, true, dt, c->nh_on);
+    rbsog_status st = RBSOG_OK;
+    for (int i = 0; i < len && st == RBSOG_OK; ++i) st = enqueue_eval(c, true, dt, c->nh_on, v == GV_STEP_E);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->stream, &g);
     if (st != RBSOG_OK) {
@@ -668,13 +678,13 @@ rbsog_status ensure_step_graphs(rbsog_ctx *c, double dt) {
         return st;
     }
     if (e != hipSuccess) return fail(c, RBSOG_E_DEVICE, "stream capture: %s", hipGetErrorString(e));
-    c->graph[m] = g;
-    e = hipGraphInstantiate(&c->graph_exec[m], g, nullptr, nullptr, 0);
+    c->graph[m][v] = g;
+    e = hipGraphInstantiate(&c->graph_exec[m][v], g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         drop_graphs(c);
         return fail(c, RBSOG_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
     }
-    c->graph_dt_m[m] = dt;
+    c->graph_dt_m[m][v] = dt;
     return RBSOG_OK;
 }
 
@@ -1747,7 +1757,7 @@ rbsog_status rbsog_forces(rbsog_ctx *c, double *F_out, double *E_out) {
     TRY(check_ctx(c));
     TRY(check_kseq(c, 1));
     TRY(refill_if_due(c));
-    TRY(enqueue_eval(c, false, 0.0, true));
+    TRY(enqueue_eval(c, false, 0.0, true, true));
     account_eval(c);
     {
         int32_t flag = 0;
@@ -1774,7 +1784,7 @@ rbsog_status rbsog_step(rbsog_ctx *c, int64_t n_steps, double dt) {
     TRY(check_kseq(c, n_steps + (c->forces_valid ? 0 : 1)));
     if (!c->forces_valid) {
         TRY(refill_if_due(c));
-        TRY(enqueue_eval(c, false, 0.0, true));
+        TRY(enqueue_eval(c, false, 0.0, true, true));
         account_eval(c);
     }
     if (c->autotune && !c->tuned && !c->prof_on) TRY(autotune_now(c, 5));
@@ -1782,15 +1792,29 @@ rbsog_status rbsog_step(rbsog_ctx *c, int64_t n_steps, double dt) {
     for (int64_t k = 0; k < n_steps;) {
         // up to the next check of the build rate
         const int64_t chunk = std::min<int64_t>(n_steps - k, kAdaptSteps - c->adapt_steps);
-        if (graphs) TRY(ensure_step_graphs(c, dt));
-        for (int64_t i = 0; i < chunk; ++i) {
+        for (int64_t i = 0; i < chunk;) {
             TRY(refill_if_due(c));
-            if (graphs) HIPCHK(c, hipGraphLaunch(c->graph_exec[graph_mode(c)], c->stream));
-            else TRY(enqueue_eval(c, true, dt, c->nh_on));
-            account_eval(c);
+            // only the run's last step sums the near energies
+            const bool last = k + i + 1 == n_steps;
+            if (graphs) {
+                // kGraphSteps steps at once when they fit in the chunk, stop
+                // short of the last step and need no refill of the chains
+                const int64_t room = c->lambda ? (int64_t)c->lambda - c->sys[0].cursor / c->sys[0].P : INT64_MAX;
+                const bool multi = i + kGraphSteps <= chunk && k + i + kGraphSteps < n_steps && room >= kGraphSteps;
+                const int v = multi ? GV_MULTI : (last ? GV_STEP_E : GV_STEP);
+                TRY(ensure_step_graph(c, dt, v));
+                HIPCHK(c, hipGraphLaunch(c->graph_exec[graph_mode(c)][v], c->stream));
+                const int len = multi ? kGraphSteps : 1;
+                for (int j = 0; j < len; ++j) account_eval(c);
+                i += len;
+            } else {
+                TRY(enqueue_eval(c, true, dt, c->nh_on, last));
+                account_eval(c);
+                ++i;
+            }
         }
-        if (!c->nh_on && chunk > 0) {
-            // the energies of the chunk's last evaluation (before a switch of
+        if (!c->nh_on && k + chunk == n_steps) {
+            // the energies of the run's last evaluation (before a switch of
             // the near mode changes where its partial sums are read)
             launch_kinetic(make_args(c, false, 0.0), c->stream);
             HIPCHK(c, hipGetLastError());

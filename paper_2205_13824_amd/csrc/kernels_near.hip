@@ -280,6 +280,7 @@ struct HomeView {
     const R *hq;
     const double *hx[3];   // FP64 positions (FP64 form only)
     R *hf[3];
+    bool we;               // sum the pair energies (else forces only)
 };
 
 // The candidate's data a pair needs: fixed-point coordinates, charge, and
@@ -352,9 +353,10 @@ __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>:
                     const float ri = __builtin_amdgcn_rsqf(r2f);
                     float pa = ta[kTabQ - 1], pb = tb[kTabQ - 1];
 #pragma unroll
-                    for (int t = kTabQ - 2; t >= 0; --t) {
-                        pa = fmaf(pa, r2f, ta[t]);
-                        pb = fmaf(pb, r2f, tb[t]);
+                    for (int t = kTabQ - 2; t >= 0; --t) pa = fmaf(pa, r2f, ta[t]);
+                    if (L.we) {
+#pragma unroll
+                        for (int t = kTabQ - 2; t >= 0; --t) pb = fmaf(pb, r2f, tb[t]);
                     }
                     gk = ri * ri * ri - 2.0f * pa;
                     hk = ri - pb;
@@ -365,15 +367,22 @@ __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>:
                 else rinv = __builtin_amdgcn_rsqf(r2);
 #pragma unroll
                 for (int t = NT - 1; t >= 0; --t) {
-                    if constexpr (F64) { gs = fma(gs, r2, co->ft[t]); ph = fma(ph, r2, co->pt[t]); }
-                    else { gs = fmaf(gs, r2, co->ft[t]); ph = fmaf(ph, r2, co->pt[t]); }
+                    if constexpr (F64) gs = fma(gs, r2, co->ft[t]);
+                    else gs = fmaf(gs, r2, co->ft[t]);
+                }
+                if (L.we) {
+#pragma unroll
+                    for (int t = NT - 1; t >= 0; --t) {
+                        if constexpr (F64) ph = fma(ph, r2, co->pt[t]);
+                        else ph = fmaf(ph, r2, co->pt[t]);
+                    }
                 }
                 for (int l = 0; l < co->nexp; ++l) {
                     R ex;
                     if constexpr (F64) ex = exp(-r2 * co->a[l]);
                     else ex = __builtin_amdgcn_exp2f(-r2 * co->a[l]);
                     gs += co->cw[l] * ex;
-                    ph += co->w[l] * ex;
+                    if (L.we) ph += co->w[l] * ex;
                 }
                 gk = rinv * rinv * rinv - gs;
                 hk = rinv - ph;
@@ -383,10 +392,10 @@ __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>:
             fx = -coef * dx;
             fy = -coef * dy;
             fz = -coef * dz;
-            de = 0.5 * (double)(qq * hk);
+            if (L.we) de = 0.5 * (double)(qq * hk);
         }
     }
-    e += de;
+    if (L.we) e += de;
     const int prev = __shfl_up(slot, 1, 64);
     const bool seg = lane == 0 || slot != prev;
     const uint64_t H = ballot(seg);
@@ -512,6 +521,7 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
     HomeView<F64> hv;
     hv.hu = L.hu;
     hv.hq = L.hq;
+    hv.we = a.energy != 0;
     for (int d = 0; d < 3; ++d) {
         hv.hx[d] = L.hx[d];
         hv.hf[d] = L.hf[d];
@@ -793,6 +803,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
     HomeView<F64> hv;
     hv.hu = L.hu;
     hv.hq = L.hq;
+    hv.we = a.energy != 0;
     for (int d = 0; d < 3; ++d) {
         hv.hx[d] = L.hx[d];
         hv.hf[d] = L.hf[d];
@@ -871,6 +882,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
     HomeView<F64> hv;
     hv.hu = L.hu;
     hv.hq = L.hq;
+    hv.we = a.energy != 0;
     for (int d = 0; d < 3; ++d) {
         hv.hx[d] = L.hx[d];
         hv.hf[d] = L.hf[d];

@@ -188,6 +188,7 @@ struct EvalArgs {
     KRec32 *kb32;
     double *wk, *rho, *ek, *partial, *epart, *E;
     double *epart_cells;   // near energies per cell-run item (build-every-evaluation mode)
+    int32_t energy;        // 1: the near kernels sum the pair energies (else forces only)
     double *dip_part;      // dipole partials per structure-factor chunk (3 per chunk)
     double *dipole;        // dipole moment M per system (3 per system)
     int32_t *flag;         // bit 0: non-finite force, bit 1: non-finite energy, bit 3: list overflow

@@ -219,6 +219,28 @@ def test_velocity_verlet_matches_oracle(orc, prec, tol):
     assert np.abs(v_g.sum(0) - v0.sum(0)).max() < (1e-9 if prec == R.RBSOG_FP64 else 1e-7)
 
 
+@pytest.mark.parametrize("prec,tol", [(R.RBSOG_FP64, 1e-10), (R.RBSOG_FP32C, 1e-5)])
+def test_energies_after_a_run_of_steps(orc, prec, tol):
+    # the steps of a run sum no energies but the last: after 21 steps (graphs
+    # of several steps, then the last step alone) the energies are those of
+    # the final positions and the last wave-vector batch
+    n, L = 300, 12.0
+    pos, q, box = W.ions_rsa(n, n / L ** 3, 1.0, 23)
+    rc, P, steps, dt = 3.0, 40, 21, 1e-3
+    sysm = make(pos, q, box, rc, P, seed=12, prec=prec)
+    m = sysm.sample_k(steps + 1)
+    R.rbsog_set_velocities(sysm.ctx, None, T=1.0, seed=5)
+    sysm.step(steps, dt)
+    x, _ = R.rbsog_get_state(sysm.ctx, n)
+    E = R.rbsog_get_energy(sysm.ctx)
+    sog = oracle_sog(orc, sysm.sog)
+    _, Un = orc.near_brute(x, q, box, rc, sog)
+    _, Us, _, _ = orc.far_rb(x, q, box, sog, m[steps * P:], P)
+    say(f"[energies after steps prec={prec}] U_N {E[0]:.12g} vs {Un:.12g}, U* {E[1]:.12g} vs {Us:.12g}")
+    assert abs(E[0] - Un) < tol * abs(Un) and abs(E[1] - Us) < tol * abs(Us)
+    assert abs(E[3] - (E[0] + E[1] - E[2])) < 1e-12 * abs(E[1])
+
+
 def test_maxwellian_velocities_have_zero_momentum_and_temperature(orc):
     c = W.c1_small()
     sysm = make(c["pos"], c["q"], c["box"], c["rc"], c["P"])
@@ -270,10 +292,11 @@ def test_graph_replay_equals_eager(orc, prec):
     for graphs in (False, True):
         say(f"[gpu] graph replay check prec={prec} graphs={graphs}")
         sysm = R.System(pos, q, box, 3.0, 50, seed=3, precision=prec, graphs=graphs)
-        sysm.sample_k(40)
+        sysm.sample_k(70)
         R.rbsog_set_velocities(sysm.ctx, v0)
         states = []
-        for chunk in (5, 7, 3, 9):
+        # runs of 9 and 20 steps take the graphs of several steps
+        for chunk in (5, 7, 3, 9, 20):
             sysm.step(chunk, 1e-3)
             states.append(R.rbsog_get_state(sysm.ctx, n))
         states.append(tuple(sysm.components()))
