@@ -21,6 +21,10 @@ constexpr double kTwoPi = 6.283185307179586476925286766559;
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
+// The cell scan works on tiles of kScanTile cells.
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kBlock * kScanItems;
+
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -234,8 +238,6 @@ __global__ __launch_bounds__(kBlock) void k_bin(EvalArgs a) {
 }
 
 // ---- exclusive scan of int32 counts: 1024 elements per block --------------
-constexpr int kScanItems = 4;
-constexpr int kScanTile = kBlock * kScanItems;
 
 __device__ int32_t block_exclusive_scan(int32_t v, int32_t *total) {
     __shared__ int32_t wsum[kBlock / 64];
@@ -269,16 +271,10 @@ __global__ void k_scan_blocks(const int32_t *__restrict__ in, int64_t n, int32_t
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-// Each block adds the totals of the blocks before it (read in parallel from
-// L2 and reduced in a fixed order) to its own exclusive scan.
-__global__ void k_scan_apply(const int32_t *__restrict__ in, int64_t n, const int32_t *__restrict__ bsum,
-                             int32_t *__restrict__ out, int32_t *__restrict__ fill, const int32_t *__restrict__ cond) {
-    if (!*cond) return;
-    int32_t pre = 0;
-#pragma unroll 4
-    for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += kBlock) pre += bsum[b];
-    int32_t before;
-    block_exclusive_scan(pre, &before);
+// Exclusive scan of the tile: counts in registers, the block's scan, plus
+// `before` (the count of the cells before the tile).
+__device__ __forceinline__ void scan_tile(const int32_t *__restrict__ in, int64_t n, int32_t before,
+                                          int32_t *__restrict__ out, int32_t *__restrict__ fill) {
     int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int32_t vals[kScanItems];
     int32_t s = 0;
@@ -296,6 +292,19 @@ __global__ void k_scan_apply(const int32_t *__restrict__ in, int64_t n, const in
         off += vals[k];
         if (base + k == n - 1) out[n] = off;
     }
+}
+
+// Each block adds the totals of the tiles before it (read in parallel from
+// L2 and reduced in a fixed order) to its own exclusive scan.
+__global__ void k_scan_apply(const int32_t *__restrict__ in, int64_t n, const int32_t *__restrict__ bsum,
+                             int32_t *__restrict__ out, int32_t *__restrict__ fill, const int32_t *__restrict__ cond) {
+    if (!*cond) return;
+    int32_t pre = 0;
+#pragma unroll 4
+    for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += kBlock) pre += bsum[b];
+    int32_t before;
+    block_exclusive_scan(pre, &before);
+    scan_tile(in, n, before, out, fill);
 }
 
 __global__ __launch_bounds__(kBlock) void k_cell_scatter(int64_t N, const int32_t *__restrict__ cell_of,
@@ -319,12 +328,14 @@ __global__ __launch_bounds__(kBlock) void k_cell_scatter(int64_t N, const int32_
 // take an insertion sort in memory.
 constexpr int kRankMax = 16;
 
+constexpr int kSortCells = 64;  // cells per block of the sort and gather
+
 __global__ __launch_bounds__(kBlock) void k_sort_gather(EvalArgs a) {
     if (!*a.rebuild) return;
-    const int64_t c0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t c0 = (int64_t)blockIdx.x * kSortCells;
     const int64_t c = c0 + threadIdx.x;
     int32_t *out = a.sorted;
-    if (c < a.C) {
+    if (threadIdx.x < kSortCells && c < a.C) {
         const int32_t lo = a.cell_start[c], hi = a.cell_start[c + 1];
         const int32_t cnt = hi - lo;
         const int32_t *src = a.src;
@@ -359,11 +370,11 @@ __global__ __launch_bounds__(kBlock) void k_sort_gather(EvalArgs a) {
     }
     // the block's permutation entries are visible to the whole block here
     __syncthreads();
-    const int64_t c1 = c0 + kBlock < a.C ? c0 + kBlock : a.C;
+    const int64_t c1 = c0 + kSortCells < a.C ? c0 + kSortCells : a.C;
     const int64_t k0 = a.cell_start[c0], k1 = a.cell_start[c1];
     const int64_t N = a.N;
-    // four slots per thread and pass, all loads issued before the stores
-    constexpr int U = 4;
+    // two slots per thread and pass, all loads issued before the stores
+    constexpr int U = 2;
     for (int64_t kb = k0 + threadIdx.x; kb < k1; kb += U * kBlock) {
         int64_t tt[U];
 #pragma unroll
@@ -442,7 +453,7 @@ void launch_cell_scatter(const EvalArgs &a, hipStream_t s) {
 }
 
 void launch_sort_gather(const EvalArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_sort_gather, dim3(grid_for(a.C, kBlock)), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_sort_gather, dim3(grid_for(a.C, kSortCells)), dim3(kBlock), 0, s, a);
 }
 
 }  // namespace rbsog
