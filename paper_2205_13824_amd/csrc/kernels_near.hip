@@ -844,7 +844,8 @@ struct NearLds {
     R hq[HC];
     double hx[3][XH];
     R hf[3][HC];           // force accumulators of the home batch
-    uint2 q[512];          // ring of queued pairs: (home index in the batch, candidate slot)
+    uint2 q[512 + 64];     // ring of queued pairs: (home index in the batch, candidate slot),
+                           // then one spare entry per lane for the stores of rejected pairs
     int32_t rlo[32], rex[32];  // non-empty candidate ranges of the cell: first slot, offset in the list
     int32_t flag[64];          // range starts inside the current 64-slot window
 };
@@ -1053,6 +1054,9 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
                 // exclusion of the home itself, are applied when the pair is
                 // evaluated).  kU homes x S slots are tested independently, then
                 // their accepted pairs are appended to the ring, home after home.
+                // the rel / fixed-point choice is made once, outside the loops
+                auto test_homes = [&](auto relc) {
+                constexpr bool REL = decltype(relc)::value;
                 for (int g0 = i0; g0 < i1; g0 += 64) {
                     const int gn = i1 - g0 < 64 ? i1 - g0 : 64;
                     const int gi = g0 + lane;
@@ -1064,22 +1068,17 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
                         // acceptance of each (home, slot) as a lane predicate
                         // and as the wave's mask: both come from one compare
                         // (the home itself and the empty slots are pushed
-                        // past the band by their r^2)
+                        // past the band by their r^2; a home past the group's
+                        // end compares against a negative limit)
                         bool acc[kU][S];
                         uint64_t mm[kU][S];
 #pragma unroll
                         for (int uu = 0; uu < kU; ++uu) {
-                            const int h = ii + uu;
-                            if (h >= gn) {  // uniform: past the group's end
-#pragma unroll
-                                for (int s2 = 0; s2 < S; ++s2) {
-                                    acc[uu][s2] = false;
-                                    mm[uu][s2] = 0ull;
-                                }
-                                continue;
-                            }
+                            const bool hok = ii + uu < gn;
+                            const int h = hok ? ii + uu : ii;
+                            const float lim = hok ? g.band_hi_f : -1.0f;
                             const uint32_t self = (uint32_t)(t + g0 + h);
-                            if (rel) {
+                            if constexpr (REL) {
                                 const float hx_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfx), h));
                                 const float hy_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfy), h));
                                 const float hz_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfz), h));
@@ -1088,8 +1087,8 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
                                     const float dx = cfx[s2] - hx_, dy = cfy[s2] - hy_, dz = cfz[s2] - hz_;
                                     const float r2 = dx * dx + dy * dy + dz * dz;
                                     const float r2x = cj[s2] == self ? kFarR2 : r2;
-                                    acc[uu][s2] = r2x < g.band_hi_f;
-                                    mm[uu][s2] = ballot(r2x < g.band_hi_f);
+                                    acc[uu][s2] = r2x < lim;
+                                    mm[uu][s2] = ballot(r2x < lim);
                                 }
                             } else {
                                 const uint32_t hux = (uint32_t)__builtin_amdgcn_readlane((int)hme.x, h);
@@ -1099,8 +1098,8 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
                                 for (int s2 = 0; s2 < S; ++s2) {
                                     const float r2 = fixed_r2(g, cux[s2] - hux, cuy[s2] - huy, cuz[s2] - huz);
                                     const float r2x = cj[s2] == self || cj[s2] == kNoCand ? kFarR2 : r2;
-                                    acc[uu][s2] = r2x < g.band_hi_f;
-                                    mm[uu][s2] = ballot(r2x < g.band_hi_f);
+                                    acc[uu][s2] = r2x < lim;
+                                    mm[uu][s2] = ballot(r2x < lim);
                                 }
                             }
                         }
@@ -1109,11 +1108,12 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
 #pragma unroll
                             for (int s2 = 0; s2 < S; ++s2) {
                                 const uint64_t m = mm[uu][s2];
-                                if (acc[uu][s2]) {
-                                    const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
-                                        (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)qn));
-                                    L.q[pos & (Q - 1)] = make_uint2((uint32_t)(g0 + ii + uu), cj[s2]);
-                                }
+                                // every lane stores (no branch on the lane mask): a
+                                // rejected pair goes to the lane's spare entry
+                                const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
+                                    (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)qn));
+                                L.q[acc[uu][s2] ? (pos & (Q - 1)) : (uint32_t)(Q + lane)] =
+                                    make_uint2((uint32_t)(g0 + ii + uu), cj[s2]);
                                 qn += (int)__popcll(m);
                             }
                         }
@@ -1126,6 +1126,9 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
                         }
                     }
                 }
+                };
+                if (rel) test_homes(std::true_type{});
+                else test_homes(std::false_type{});
             }
         }
         // the queue refers to this batch's home slots: drain it, then write
