@@ -73,6 +73,7 @@ struct ProfEntry {
 };
 
 constexpr int64_t kAdaptSteps = 32;  // steps between checks of the near-list build rate
+constexpr int64_t kProbeSteps = 8;   // steps of a renewed try of the caller's skin
 constexpr int kGraphSteps = 8;       // steps in the longer step graph
 // step graphs: one step without the near energies, one step with them (the
 // last step of a run), kGraphSteps steps without them
@@ -172,6 +173,7 @@ struct rbsog_ctx {
     // adaptive skin: steps and builds since the last check, checks left in
     // the build-every-step mode, and the length of the next such period
     int64_t adapt_steps = 0, adapt_nb0 = 0;
+    int64_t adapt_window = kAdaptSteps;  // steps to the next check
     int32_t hold = 0, hold_len = 4;
     uint2 *pairs = nullptr;
     int32_t *pcnt = nullptr, *rebuild = nullptr, *pmax = nullptr;
@@ -714,8 +716,9 @@ rbsog_status apply_skin(rbsog_ctx *c, double skin) {
 // oppositely charged ions without a repulsive core fall onto each other),
 // keeping a list costs more than it saves, so the steps build every time at
 // skin 0 (cells r_c wide, no list written); after a hold of a few checks the
-// caller's skin is tried again, and the hold doubles (up to 32 checks) each
-// time that try fails.  The pairs evaluated are the same in either mode.
+// caller's skin is tried again for kProbeSteps steps (failing when half of
+// them build), and the hold doubles (up to 32 checks) each time that try
+// fails.  The pairs evaluated are the same in either mode.
 rbsog_status adapt_skin(rbsog_ctx *c) {
     c->adapt_steps = 0;
     if (!(c->skin > 0.0)) return RBSOG_OK;
@@ -724,7 +727,8 @@ rbsog_status adapt_skin(rbsog_ctx *c) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const int64_t builds = nb - c->adapt_nb0;
     c->adapt_nb0 = nb;
-    const bool busy = 2 * builds >= kAdaptSteps;
+    const bool busy = 2 * builds >= c->adapt_window;
+    c->adapt_window = kAdaptSteps;
     if (c->skin_cur > 0.0) {
         if (busy) {
             c->hold = c->hold_len;
@@ -734,7 +738,9 @@ rbsog_status adapt_skin(rbsog_ctx *c) {
             c->hold_len = 4;
         }
     } else if (--c->hold <= 0) {
+        // a short try: lists that still fail cost few steps of builds
         TRY(apply_skin(c, c->skin));
+        c->adapt_window = kProbeSteps;
     }
     return RBSOG_OK;
 }
@@ -1791,7 +1797,7 @@ rbsog_status rbsog_step(rbsog_ctx *c, int64_t n_steps, double dt) {
     const bool graphs = c->use_graphs && !c->prof_on && n_steps > 1;
     for (int64_t k = 0; k < n_steps;) {
         // up to the next check of the build rate
-        const int64_t chunk = std::min<int64_t>(n_steps - k, kAdaptSteps - c->adapt_steps);
+        const int64_t chunk = std::min<int64_t>(n_steps - k, c->adapt_window - c->adapt_steps);
         for (int64_t i = 0; i < chunk;) {
             TRY(refill_if_due(c));
             // only the run's last step sums the near energies
@@ -1821,7 +1827,7 @@ rbsog_status rbsog_step(rbsog_ctx *c, int64_t n_steps, double dt) {
         }
         k += chunk;
         c->adapt_steps += chunk;
-        if (c->adapt_steps >= kAdaptSteps) TRY(adapt_skin(c));
+        if (c->adapt_steps >= c->adapt_window) TRY(adapt_skin(c));
     }
     int32_t flag = 0;
     HIPCHK(c, hipMemcpyAsync(&flag, c->flag, sizeof flag, hipMemcpyDeviceToHost, c->stream));
