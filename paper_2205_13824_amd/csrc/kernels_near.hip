@@ -432,7 +432,8 @@ struct BuildLds {
     R hq[kQuarter];
     double hx[3][XH];
     R hf[3][kQuarter];         // force accumulators of the wave's homes
-    uint2 q[Q];                // ring of accepted pairs: (home index in the quarter, candidate slot)
+    uint2 q[Q + 64];           // ring of accepted pairs: (home index in the quarter, candidate slot),
+                               // then one spare entry per lane for the stores of rejected pairs
     int32_t rlo[32], rex[32];  // non-empty candidate ranges of the cell: first slot, offset in the list
     int32_t flag[64];          // range starts inside the current 64-slot window
 };
@@ -666,6 +667,9 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
             // slots are tested independently, then their accepted pairs are
             // appended to the ring, home after home (so one home's pairs of
             // a pass are contiguous).  The home itself is left out.
+            // the rel / fixed-point choice is made once, outside the loops
+            auto test_homes = [&](auto relc) {
+            constexpr bool REL = decltype(relc)::value;
             for (int g0 = i0; g0 < i1; g0 += 64) {
                 const int gn = i1 - g0 < 64 ? i1 - g0 : 64;
                 const int gi = g0 + lane;
@@ -674,13 +678,19 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
                 const float hfy = (float)(int32_t)(hme.y - oy) * g.hf[1];
                 const float hfz = (float)(int32_t)(hme.z - oz) * g.hf[2];
                 for (int ii = 0; ii < gn; ii += kU) {
+                    // acceptance as a lane predicate and as the wave's mask,
+                    // both from one compare (the home itself and empty slots
+                    // are pushed past r_l by their r^2; a home past the
+                    // group's end compares against a negative limit)
                     bool acc[kU][S];
+                    uint64_t mm[kU][S];
 #pragma unroll
                     for (int uu = 0; uu < kU; ++uu) {
-                        const int h = ii + uu < gn ? ii + uu : ii;
-                        const bool hv = ii + uu < gn;
+                        const bool hok = ii + uu < gn;
+                        const int h = hok ? ii + uu : ii;
+                        const float lim = hok ? g.rl2_f : -1.0f;
                         const uint32_t self = (uint32_t)(t + g0 + h);
-                        if (rel) {
+                        if constexpr (REL) {
                             const float hx_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfx), h));
                             const float hy_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfy), h));
                             const float hz_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfz), h));
@@ -688,7 +698,9 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
                             for (int s2 = 0; s2 < S; ++s2) {
                                 const float dx = cfx[s2] - hx_, dy = cfy[s2] - hy_, dz = cfz[s2] - hz_;
                                 const float r2 = dx * dx + dy * dy + dz * dz;
-                                acc[uu][s2] = hv && r2 < g.rl2_f && cj[s2] != self;
+                                const float r2x = cj[s2] == self ? kFarR2 : r2;
+                                acc[uu][s2] = r2x < lim;
+                                mm[uu][s2] = ballot(r2x < lim);
                             }
                         } else {
                             const uint32_t hux = (uint32_t)__builtin_amdgcn_readlane((int)hme.x, h);
@@ -697,7 +709,9 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
 #pragma unroll
                             for (int s2 = 0; s2 < S; ++s2) {
                                 const float r2 = fixed_r2(g, cux[s2] - hux, cuy[s2] - huy, cuz[s2] - huz);
-                                acc[uu][s2] = hv && cj[s2] != kNoCand && r2 < g.rl2_f && cj[s2] != self;
+                                const float r2x = cj[s2] == self || cj[s2] == kNoCand ? kFarR2 : r2;
+                                acc[uu][s2] = r2x < lim;
+                                mm[uu][s2] = ballot(r2x < lim);
                             }
                         }
                     }
@@ -705,13 +719,14 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
                     for (int uu = 0; uu < kU; ++uu) {
 #pragma unroll
                         for (int s2 = 0; s2 < S; ++s2) {
-                            const uint64_t mm = ballot(acc[uu][s2]);
-                            if (acc[uu][s2]) {
-                                const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi(
-                                                         (uint32_t)(mm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mm, 0));
-                                L.q[pos & (Q - 1)] = make_uint2((uint32_t)(g0 + ii + uu), cj[s2]);
-                            }
-                            qn += (int)__popcll(mm);
+                            const uint64_t m = mm[uu][s2];
+                            // every lane stores (no branch on the lane mask): a
+                            // rejected pair goes to the lane's spare entry
+                            const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)qn));
+                            L.q[acc[uu][s2] ? (pos & (Q - 1)) : (uint32_t)(Q + lane)] =
+                                make_uint2((uint32_t)(g0 + ii + uu), cj[s2]);
+                            qn += (int)__popcll(m);
                         }
                     }
                     // at most 63 + kU * S * 64 entries are pending: the ring holds them
@@ -724,6 +739,9 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
                     }
                 }
             }
+            };
+            if (rel) test_homes(std::true_type{});
+            else test_homes(std::false_type{});
         }
     }
     wave_sync();
