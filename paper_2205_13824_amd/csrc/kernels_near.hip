@@ -44,6 +44,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kRanges = 18; // 9 rows of cells x up to 2 contiguous pieces
 constexpr float kFarR2 = 3.0e38f;  // r^2 of a pair that no test admits
+constexpr int kExpRegs = 4;        // narrow Gaussians evaluated with constants held in registers
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
@@ -187,14 +188,18 @@ __device__ __forceinline__ R dpp(R v) {
 // Segmented inclusive sum across the wave: lane l ends with the sum of lanes
 // [max(sstart, .), l] of its segment (segments are runs of lanes; sstart is
 // the first lane of l's segment).  In-row shifts 1, 2, 4, 8, then the row
-// totals: lane 15 into rows 1 and 3, lane 31 into rows 2 and 3.
+// totals: lane 15 into rows 1 and 3, lane 31 into rows 2 and 3.  A moved
+// value from outside the segment is multiplied by 0 rather than skipped, so
+// that no step changes the lane mask (the moves write 0 where they have no
+// source lane).
 template <typename R>
 __device__ __forceinline__ void seg_scan3(R &x, R &y, R &z, int lane, int sstart) {
-    const int pos = lane & 15;
+    const int len = lane - sstart;  // lanes of the segment before this one
 #define RBSOG_SHR(N)                                                                     \
     {                                                                                    \
         const R tx = dpp<0x110 + N, 0xf>(x), ty = dpp<0x110 + N, 0xf>(y), tz = dpp<0x110 + N, 0xf>(z); \
-        if (pos >= N && lane - N >= sstart) { x += tx; y += ty; z += tz; }              \
+        const R m = len >= N ? (R)1 : (R)0;                                              \
+        x = fma(tx, m, x); y = fma(ty, m, y); z = fma(tz, m, z);                         \
     }
     RBSOG_SHR(1)
     RBSOG_SHR(2)
@@ -205,12 +210,14 @@ __device__ __forceinline__ void seg_scan3(R &x, R &y, R &z, int lane, int sstart
         // row_bcast:15 to rows 1 and 3 (row mask 0xa)
         const R tx = dpp<0x142, 0xa>(x), ty = dpp<0x142, 0xa>(y), tz = dpp<0x142, 0xa>(z);
         const int row = lane >> 4;
-        if ((row == 1 || row == 3) && row * 16 - 1 >= sstart) { x += tx; y += ty; z += tz; }
+        const R m = (row == 1 || row == 3) && row * 16 - 1 >= sstart ? (R)1 : (R)0;
+        x = fma(tx, m, x); y = fma(ty, m, y); z = fma(tz, m, z);
     }
     {
         // row_bcast:31 to rows 2 and 3 (row mask 0xc)
         const R tx = dpp<0x143, 0xc>(x), ty = dpp<0x143, 0xc>(y), tz = dpp<0x143, 0xc>(z);
-        if (lane >= 32 && 31 >= sstart) { x += tx; y += ty; z += tz; }
+        const R m = lane >= 32 && 31 >= sstart ? (R)1 : (R)0;
+        x = fma(tx, m, x); y = fma(ty, m, y); z = fma(tz, m, z);
     }
 }
 
@@ -377,7 +384,18 @@ __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>:
                         else ph = fmaf(ph, r2, co->pt[t]);
                     }
                 }
-                for (int l = 0; l < co->nexp; ++l) {
+                // the first kExpRegs terms at fixed indices (their constants
+                // stay in scalar registers across the kernel's loops)
+#pragma unroll
+                for (int l = 0; l < kExpRegs; ++l) {
+                    if (l >= co->nexp) break;
+                    R ex;
+                    if constexpr (F64) ex = exp(-r2 * co->a[l]);
+                    else ex = __builtin_amdgcn_exp2f(-r2 * co->a[l]);
+                    gs += co->cw[l] * ex;
+                    if (L.we) ph += co->w[l] * ex;
+                }
+                for (int l = kExpRegs; l < co->nexp; ++l) {
                     R ex;
                     if constexpr (F64) ex = exp(-r2 * co->a[l]);
                     else ex = __builtin_amdgcn_exp2f(-r2 * co->a[l]);
