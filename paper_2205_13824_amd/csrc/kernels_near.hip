@@ -317,8 +317,8 @@ __device__ __forceinline__ PairData<F64> load_pair(const uint32_t *__restrict__ 
 
 template <bool F64>
 __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>::type *co, const HomeView<F64> &L,
-                                            const float4 *__restrict__ tbl, float rin2, const float *ta,
-                                            const float *tb, int lane, uint2 qe, bool have, const PairData<F64> &pd,
+                                            const float4 *__restrict__ tbl, float rin2, CSys *csp,
+                                             int lane, uint2 qe, bool have, const PairData<F64> &pd,
                                             double &e) {
     double de = 0.0;
     using R = typename HomeView<F64>::R;
@@ -358,12 +358,12 @@ __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>:
                 } else {
                     // core: Taylor terms of the Gaussians, 1/r and 1/r^3 computed
                     const float ri = __builtin_amdgcn_rsqf(r2f);
-                    float pa = ta[kTabQ - 1], pb = tb[kTabQ - 1];
+                    float pa = csp->ta[kTabQ - 1], pb = csp->tb[kTabQ - 1];
 #pragma unroll
-                    for (int t = kTabQ - 2; t >= 0; --t) pa = fmaf(pa, r2f, ta[t]);
+                    for (int t = kTabQ - 2; t >= 0; --t) pa = fmaf(pa, r2f, csp->ta[t]);
                     if (L.we) {
 #pragma unroll
-                        for (int t = kTabQ - 2; t >= 0; --t) pb = fmaf(pb, r2f, tb[t]);
+                        for (int t = kTabQ - 2; t >= 0; --t) pb = fmaf(pb, r2f, csp->tb[t]);
                     }
                     gk = ri * ri * ri - 2.0f * pa;
                     hk = ri - pb;
@@ -436,10 +436,10 @@ template <bool F64>
 __device__ __forceinline__ void eval_pair(const Geom &g, typename CoefOf<F64>::type *co, const HomeView<F64> &L,
                                           const uint32_t *__restrict__ su, const double *__restrict__ sx,
                                           const double *__restrict__ sq, const float *__restrict__ sqf, int64_t n,
-                                          const float4 *__restrict__ tbl, float rin2, const float *ta,
-                                          const float *tb, int lane, uint2 qe, bool have, double &e) {
+                                          const float4 *__restrict__ tbl, float rin2, CSys *csp,
+                                           int lane, uint2 qe, bool have, double &e) {
     const PairData<F64> pd = load_pair<F64>(su, sx, sq, sqf, n, qe, have);
-    eval_loaded<F64>(g, co, L, tbl, rin2, ta, tb, lane, qe, have, pd, e);
+    eval_loaded<F64>(g, co, L, tbl, rin2, csp, lane, qe, have, pd, e);
 }
 
 template <bool F64, int Q>
@@ -483,11 +483,11 @@ __device__ __forceinline__ void eval_ring(const uint2 *ring, const HomeView<F64>
                                           typename CoefOf<F64>::type *co, const uint32_t *__restrict__ su,
                                           const double *__restrict__ sx, const double *__restrict__ sq,
                                           const float *__restrict__ sqf, int64_t n, const float4 *__restrict__ tbl,
-                                          float rin2, const float *ta, const float *tb, int lane, int head, int count,
+                                          float rin2, CSys *csp,  int lane, int head, int count,
                                           double &e) {
     const bool have = lane < count;
     const uint2 qe = have ? ring[(head + lane) & (Q - 1)] : make_uint2(0u, 0u);
-    eval_pair<F64>(g, co, hv, su, sx, sq, sqf, n, tbl, rin2, ta, tb, lane, qe, have, e);
+    eval_pair<F64>(g, co, hv, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qe, have, e);
 }
 
 // Ring entries [head, head + count): written to the wave's list segment
@@ -500,13 +500,13 @@ __device__ __forceinline__ void drain_ring(const BuildLds<F64, Q> &L, const Home
                                            typename CoefOf<F64>::type *co, const uint32_t *__restrict__ su,
                                            const double *__restrict__ sx, const double *__restrict__ sq,
                                            const float *__restrict__ sqf, int64_t n, const float4 *__restrict__ tbl,
-                                           float rin2, const float *ta, const float *tb, int lane, int head,
+                                           float rin2, CSys *csp,  int lane, int head,
                                            int count, double &e) {
     const bool have = lane < count;
     const int idx = head + lane;
     const uint2 qe = have ? L.q[idx & (Q - 1)] : make_uint2(0u, 0u);
     if (have && out && idx < cap) out[idx] = qe;
-    eval_pair<F64>(g, co, hv, su, sx, sq, sqf, n, tbl, rin2, ta, tb, lane, qe, have, e);
+    eval_pair<F64>(g, co, hv, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qe, have, e);
 }
 
 // The build also evaluates this step's near forces from the same candidate
@@ -562,11 +562,7 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
     else co = &sp->co32;
     const float4 *tbl = F64 ? nullptr : sp->tbl;
     const float rin2 = sp->rin2;
-    float ta[kTabQ], tb[kTabQ];
-    for (int k = 0; k < kTabQ; ++k) {
-        ta[k] = sp->ta[k];
-        tb[k] = sp->tb[k];
-    }
+    CSys *csp = sp;  // the core-shell Taylor constants are read where used
     double e = 0.0;
     // this wave's quarter of the item's homes and of its list
     const int32_t t = (int32_t)std::min<int64_t>(item.t0 + wave * kQuarter, item.t1);
@@ -751,7 +747,7 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
                     static_assert(63 + kU * S * 64 < Q, "ring too small");
                     while (qn - qh >= 64) {
                         wave_sync();
-                        drain_ring<F64, Q>(L, hv, out, cap, g, co, su, sx, sq, sqf, n, tbl, rin2, ta, tb, lane, qh, 64,
+                        drain_ring<F64, Q>(L, hv, out, cap, g, co, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qh, 64,
                                            e);
                         qh += 64;
                     }
@@ -764,7 +760,7 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
     }
     wave_sync();
     if (qn > qh)
-        drain_ring<F64, Q>(L, hv, out, cap, g, co, su, sx, sq, sqf, n, tbl, rin2, ta, tb, lane, qh, qn - qh, e);
+        drain_ring<F64, Q>(L, hv, out, cap, g, co, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qh, qn - qh, e);
     wave_sync();
     if (lane < t_end - t) {
         const int64_t tt = t + lane;
@@ -811,11 +807,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
     else co = &sp->co32;
     const float4 *tbl = F64 ? nullptr : sp->tbl;
     const float rin2 = sp->rin2;
-    float ta[kTabQ], tb[kTabQ];
-    for (int k = 0; k < kTabQ; ++k) {
-        ta[k] = sp->ta[k];
-        tb[k] = sp->tb[k];
-    }
+    CSys *csp = sp;  // the core-shell Taylor constants are read where used
     // this wave's quarter of the homes and its segment of the list
     const int64_t t0 = std::min<int64_t>(item.t0 + w * kQuarter, item.t1);
     const int H = (int)(std::min<int64_t>(item.t0 + (w + 1) * kQuarter, item.t1) - t0);
@@ -858,7 +850,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
         qe1 = qe2;
         qe2 = entry(c + 128);
         pd1 = load_pair<F64>(su, sx, sq, sqf, n, qe1, c + 64 + lane < cnt);
-        eval_loaded<F64>(g, co, hv, tbl, rin2, ta, tb, lane, qe, have, pd, e);
+        eval_loaded<F64>(g, co, hv, tbl, rin2, csp, lane, qe, have, pd, e);
     }
     wave_sync();
     if (lane < H) {
@@ -940,11 +932,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
     const int64_t c0s = sp->c0;
     const float4 *tbl = F64 ? nullptr : sp->tbl;
     const float rin2 = sp->rin2;
-    float ta[kTabQ], tb[kTabQ];
-    for (int t = 0; t < kTabQ; ++t) {
-        ta[t] = sp->ta[t];
-        tb[t] = sp->tb[t];
-    }
+    CSys *csp = sp;  // the core-shell Taylor constants are read where used
     const int64_t ra = item.c_begin, rb = item.c_end;
     double e = 0.0;
     int qn = 0, qh = 0;  // ring tail (pairs queued) and head (pairs evaluated)
@@ -1157,7 +1145,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
                         static_assert(63 + kU * S * 64 < Q, "ring too small");
                         while (qn - qh >= 64) {
                             wave_sync();
-                            eval_ring<F64, Q>(L.q, hv, g, co, su, sx, sq, sqf, n, tbl, rin2, ta, tb, lane, qh, 64, e);
+                            eval_ring<F64, Q>(L.q, hv, g, co, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qh, 64, e);
                             qh += 64;
                         }
                     }
@@ -1169,7 +1157,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
         }
         // the queue refers to this batch's home slots: drain it, then write
         wave_sync();
-        if (qn > qh) eval_ring<F64, Q>(L.q, hv, g, co, su, sx, sq, sqf, n, tbl, rin2, ta, tb, lane, qh, qn - qh, e);
+        if (qn > qh) eval_ring<F64, Q>(L.q, hv, g, co, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qh, qn - qh, e);
         qn = 0;
         qh = 0;
         wave_sync();
