@@ -524,7 +524,6 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
     }
     constexpr int Q = ring_size(S);
     using Lds = BuildLds<F64, Q>;
-    using R = typename Lds::R;
     __shared__ Lds lds[kNW];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
