@@ -165,7 +165,7 @@ struct rbsog_ctx {
     float *rs_qf = nullptr;
     double *rs_x = nullptr, *rs_q = nullptr;
     int32_t *cell_of = nullptr, *cell_count = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *src = nullptr,
-            *sorted = nullptr, *blocksums = nullptr, *cell_sorted = nullptr;
+            *sorted = nullptr, *blocksums = nullptr, *cell_sorted = nullptr, *skey = nullptr;
     // Verlet list: skin (fraction of r_c), pairs, per-item counts and
     // capacity, rebuild flag, largest count of the latest build, builds made
     double skin = 0.1;      // the caller's
@@ -534,6 +534,7 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
     a.cell_start = c->cell_start;
     a.cell_fill = c->cell_fill;
     a.src = c->src;
+    a.skey = c->skey;
     a.sorted = c->sorted;
     a.blocksums = c->blocksums;
     a.cell_sorted = c->cell_sorted;
@@ -1530,6 +1531,7 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     }
     ALLOC(cell_of, N);
     ALLOC(src, N);
+    ALLOC(skey, N);
     ALLOC(sorted, N);
     ALLOC(cell_count, C);
     ALLOC(cell_start, C + 1);

@@ -307,15 +307,22 @@ __global__ void k_scan_apply(const int32_t *__restrict__ in, int64_t n, const in
     scan_tile(in, n, before, out, fill);
 }
 
+// Each particle to a slot of its cell (atomic order), with its id beside it
+// for the per-cell sort.
 __global__ __launch_bounds__(kBlock) void k_cell_scatter(int64_t N, const int32_t *__restrict__ cell_of,
-                                                         int32_t *__restrict__ fill, int32_t *__restrict__ src,
+                                                         const int32_t *__restrict__ id, int32_t *__restrict__ fill,
+                                                         int32_t *__restrict__ src, int32_t *__restrict__ skey,
                                                          const int32_t *__restrict__ cond) {
     if (!*cond) return;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = t < N;
     const int32_t cell = valid ? cell_of[t] : 0;
+    const int32_t key = valid ? id[t] : 0;
     const int32_t dst = run_atomic_add(fill, cell, valid);
-    if (valid) src[dst] = (int32_t)t;
+    if (valid) {
+        src[dst] = (int32_t)t;
+        skey[dst] = key;
+    }
 }
 
 // Per cell: order of its slots by particle id (the order becomes (cell, id),
@@ -343,9 +350,10 @@ __global__ __launch_bounds__(kBlock) void k_sort_gather(EvalArgs a) {
         if (cnt <= kRankMax) {
             int32_t sv[kRankMax], key[kRankMax];
 #pragma unroll
-            for (int i = 0; i < kRankMax; ++i) sv[i] = i < cnt ? src[lo + i] : 0;
-#pragma unroll
-            for (int i = 0; i < kRankMax; ++i) key[i] = i < cnt ? idc[sv[i]] : INT32_MAX;
+            for (int i = 0; i < kRankMax; ++i) {
+                sv[i] = i < cnt ? src[lo + i] : 0;
+                key[i] = i < cnt ? a.skey[lo + i] : INT32_MAX;
+            }
 #pragma unroll
             for (int i = 0; i < kRankMax; ++i) {
                 int32_t rank = 0;
@@ -448,8 +456,8 @@ void launch_scan(const EvalArgs &a, hipStream_t s) {
 }
 
 void launch_cell_scatter(const EvalArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_cell_scatter, dim3(grid_for(a.N, kBlock)), dim3(kBlock), 0, s, a.N, a.cell_of, a.cell_fill,
-                       a.src, (const int32_t *)a.rebuild);
+    hipLaunchKernelGGL(k_cell_scatter, dim3(grid_for(a.N, kBlock)), dim3(kBlock), 0, s, a.N, a.cell_of, a.cur.id,
+                       a.cell_fill, a.src, a.skey, (const int32_t *)a.rebuild);
 }
 
 void launch_sort_gather(const EvalArgs &a, hipStream_t s) {

@@ -171,6 +171,7 @@ struct EvalArgs {
     float *rs_qf;
     double *rs_x, *rs_q;
     int32_t *cell_of, *cell_count, *cell_start, *cell_fill, *src, *sorted, *blocksums;
+    int32_t *skey;         // particle id of each scattered slot (the per-cell sort's key)
     int32_t *cell_sorted;  // cell of each slot at the latest list build
     double *Fn, *Ff;       // forces in slot order
     // Verlet list: rebuild flag (set by the displacement check, cleared by the
