@@ -165,6 +165,7 @@ __device__ __forceinline__ double bcast64(double v, int src) {
 // Per-system constants are read through the constant address space, so that
 // uniform reads become scalar loads.
 typedef const SysDev __attribute__((address_space(4))) CSys;
+typedef const int32_t __attribute__((address_space(4))) CI32;
 typedef const SplitCoef64 __attribute__((address_space(4))) CCoef64;
 typedef const SplitCoef32 __attribute__((address_space(4))) CCoef32;
 // DPP lane moves (row = 16 lanes): row_shr:n, and row_bcast:15 / row_bcast:31.
@@ -529,6 +530,8 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
     const int lane = threadIdx.x & 63;
     Lds &L = lds[wave];
     const int32_t *__restrict__ start = a.cell_start;
+    // the same array for reads at uniform indices (scalar loads)
+    CI32 *cstart = (CI32 *)a.cell_start;
     // the build runs on the gathered state (`nxt` and the new reference `u`,
     // which are the current positions in the new order)
     const uint32_t *__restrict__ su = a.u;
@@ -551,7 +554,11 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
     const int32_t it = (b % 8) * (nblk / 8) + b / 8;
     if (it >= nitems) return;
     {
-    const ListItem item = items[it];
+    const __attribute__((address_space(4))) ListItem *ip = (const __attribute__((address_space(4))) ListItem *)(items + it);
+    ListItem item;
+    item.sys = ip->sys;
+    item.t0 = ip->t0;
+    item.t1 = ip->t1;
     const int32_t sys = rfl(item.sys);
     CSys *sp = (CSys *)(a.sys + sys);
     const Geom g = load_geom(sp);
@@ -584,10 +591,10 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
     }
     wave_sync();
     int qn = 0, qh = 0;  // ring tail (pairs accepted) and head (pairs written)
-    for (int64_t cell = t < t_end ? rfl(a.cell_sorted[t]) : 0; t < t_end; ++cell) {
-        const int32_t cs = rfl(start[cell]);
+    for (int64_t cell = t < t_end ? ((CI32 *)a.cell_sorted)[t] : 0; t < t_end; ++cell) {
+        const int32_t cs = cstart[cell];
         if (cs >= t_end) break;
-        const int32_t ce = rfl(start[cell + 1]);
+        const int32_t ce = cstart[cell + 1];
         const int32_t hs = cs > t ? cs : t;
         const int32_t he = ce < t_end ? ce : t_end;
         if (hs >= he) continue;
@@ -797,7 +804,11 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
     const int32_t b = blockIdx.x;
     const int32_t it = (b % 8) * (nblk / 8) + b / 8;
     if (it >= nitems) return;
-    const ListItem item = items[it];
+    const __attribute__((address_space(4))) ListItem *ip = (const __attribute__((address_space(4))) ListItem *)(items + it);
+    ListItem item;
+    item.sys = ip->sys;
+    item.t0 = ip->t0;
+    item.t1 = ip->t1;
     const int32_t sys = rfl(item.sys);
     CSys *sp = (CSys *)(a.sys + sys);
     const Geom g = load_geom(sp);
@@ -825,7 +836,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
     }
     wave_sync();
     const int64_t cap = a.icap / kNW;
-    const int32_t cnt = rfl(a.pcnt[(int64_t)it * kNW + w]);
+    const int32_t cnt = ((CI32 *)a.pcnt)[(int64_t)it * kNW + w];
     const uint2 *__restrict__ pl = a.pairs + (int64_t)it * a.icap + w * cap;
     HomeView<F64> hv;
     hv.hu = L.hu;
@@ -902,6 +913,8 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
     Lds &L = lds[wave];
     const int64_t n = a.N;  // stride of the structure-of-arrays
     const int32_t *__restrict__ start = a.cell_start;
+    // the same array for reads at uniform indices (scalar loads)
+    CI32 *cstart = (CI32 *)a.cell_start;
     const uint32_t *__restrict__ su = a.u;
     const double *__restrict__ sx = a.nxt.x;
     const double *__restrict__ sq = a.nxt.q;
@@ -921,7 +934,11 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
     const int32_t b = blockIdx.x;
     const int32_t chunk = (b % 8) * (nblk / 8) + b / 8;
     for (int32_t it = chunk * kNW + wave; it < nitems; it += nblk * kNW) {
-    const NearItem item = items[it];
+    const __attribute__((address_space(4))) NearItem *ip = (const __attribute__((address_space(4))) NearItem *)(items + it);
+    NearItem item;
+    item.sys = ip->sys;
+    item.c_begin = ip->c_begin;
+    item.c_end = ip->c_end;
     const int32_t sys = rfl(item.sys);
     CSys *sp = (CSys *)(a.sys + sys);
     const Geom g = load_geom(sp);
@@ -935,8 +952,8 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
     const int64_t ra = item.c_begin, rb = item.c_end;
     double e = 0.0;
     int qn = 0, qh = 0;  // ring tail (pairs queued) and head (pairs evaluated)
-    int32_t t = ra < rb ? rfl(start[ra]) : 0;
-    const int32_t t_hi = ra < rb ? rfl(start[rb]) : 0;
+    int32_t t = ra < rb ? cstart[ra] : 0;
+    const int32_t t_hi = ra < rb ? cstart[rb] : 0;
     int64_t cur = ra;  // cell containing home t
     const bool rel = g.nc[0] >= 4 && g.nc[1] >= 4 && g.nc[2] >= 4;
     while (t < t_hi) {
@@ -974,7 +991,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
             }
         }
         wave_sync();
-        while (rfl(start[cur + 1]) <= t) ++cur;
+        while (cstart[cur + 1] <= t) ++cur;
         const bool pairs = g.nc[0] >= 6;
         int w = 1;
         for (int64_t cell = cur; cell < rb; cell += w) {
@@ -984,9 +1001,9 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
             const int cz = (int)(cu32 / ((uint32_t)g.nc[0] * (uint32_t)g.nc[1]));
             // home cells cx (and cx + 1 in the same row and item)
             w = pairs && cx + 1 < g.nc[0] && cell + 1 < rb ? 2 : 1;
-            const int32_t cs = rfl(start[cell]);
+            const int32_t cs = cstart[cell];
             if (cs >= t_end) break;
-            const int32_t ce = rfl(start[cell + w]);
+            const int32_t ce = cstart[cell + w];
             const int32_t hs = cs > t ? cs : t;
             const int32_t he = ce < t_end ? ce : t_end;
             if (hs >= he) continue;
