@@ -220,6 +220,8 @@ __global__ __launch_bounds__(kBlock) void k_kdq(EvalArgs a, int32_t pblocks) {
 
 // Cell c_d = (u n_d) >> 32 of each particle and the cell histogram.
 __global__ __launch_bounds__(kBlock) void k_bin(EvalArgs a) {
+    // the critical path's waves ahead of the structure factor's beside them
+    __builtin_amdgcn_s_setprio(2);
     if (!*a.rebuild) return;
     const int64_t t0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool valid = t0 < a.N;
@@ -261,6 +263,8 @@ __device__ int32_t block_exclusive_scan(int32_t v, int32_t *total) {
 
 __global__ void k_scan_blocks(const int32_t *__restrict__ in, int64_t n, int32_t *__restrict__ bsum,
                               const int32_t *__restrict__ cond) {
+    // the critical path's waves ahead of the structure factor's beside them
+    __builtin_amdgcn_s_setprio(2);
     if (!*cond) return;
     int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
     int32_t s = 0;
@@ -298,6 +302,8 @@ __device__ __forceinline__ void scan_tile(const int32_t *__restrict__ in, int64_
 // L2 and reduced in a fixed order) to its own exclusive scan.
 __global__ void k_scan_apply(const int32_t *__restrict__ in, int64_t n, const int32_t *__restrict__ bsum,
                              int32_t *__restrict__ out, int32_t *__restrict__ fill, const int32_t *__restrict__ cond) {
+    // the critical path's waves ahead of the structure factor's beside them
+    __builtin_amdgcn_s_setprio(2);
     if (!*cond) return;
     int32_t pre = 0;
 #pragma unroll 4
@@ -313,6 +319,8 @@ __global__ __launch_bounds__(kBlock) void k_cell_scatter(int64_t N, const int32_
                                                          const int32_t *__restrict__ id, int32_t *__restrict__ fill,
                                                          int32_t *__restrict__ src, int32_t *__restrict__ skey,
                                                          const int32_t *__restrict__ cond) {
+    // the critical path's waves ahead of the structure factor's beside them
+    __builtin_amdgcn_s_setprio(2);
     if (!*cond) return;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = t < N;
@@ -338,6 +346,8 @@ constexpr int kRankMax = 16;
 constexpr int kSortCells = 64;  // cells per block of the sort and gather
 
 __global__ __launch_bounds__(kBlock) void k_sort_gather(EvalArgs a) {
+    // the critical path's waves ahead of the structure factor's beside them
+    __builtin_amdgcn_s_setprio(2);
     if (!*a.rebuild) return;
     const int64_t c0 = (int64_t)blockIdx.x * kSortCells;
     const int64_t c = c0 + threadIdx.x;

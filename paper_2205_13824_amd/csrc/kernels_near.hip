@@ -517,6 +517,8 @@ __device__ __forceinline__ void drain_ring(const BuildLds<F64, Q> &L, const Home
 template <bool F64, int S>
 __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListItem *__restrict__ items,
                                                          int32_t nitems, int32_t nblk) {
+    // the critical path's waves ahead of the structure factor's beside them
+    __builtin_amdgcn_s_setprio(2);
     if (!*a.rebuild) return;
     const int64_t n = a.N;  // stride of the structure-of-arrays
     if ((int32_t)blockIdx.x >= nblk) {
@@ -787,6 +789,8 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
 template <bool F64>
 __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListItem *__restrict__ items,
                                                         int32_t nitems, int32_t nblk) {
+    // the critical path's waves ahead of the structure factor's beside them
+    __builtin_amdgcn_s_setprio(2);
     using Lds = EvalLds<F64>;
     __shared__ Lds lds[kNW];
     __shared__ double es_w[kNW];
@@ -898,6 +902,8 @@ struct NearLds {
 template <bool F64, int S>
 __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearItem *__restrict__ items,
                                                          int32_t nitems, int32_t nblk) {
+    // the critical path's waves ahead of the structure factor's beside them
+    __builtin_amdgcn_s_setprio(2);
     if (!*a.rebuild) return;
     if ((int32_t)blockIdx.x >= nblk) {
         copy_back(a, (int64_t)(blockIdx.x - nblk) * blockDim.x + threadIdx.x, (int64_t)(gridDim.x - nblk) * blockDim.x);
