@@ -73,7 +73,7 @@ struct ProfEntry {
 };
 
 constexpr int64_t kAdaptSteps = 32;  // steps between checks of the near-list build rate
-constexpr int64_t kProbeSteps = 8;   // steps of a renewed try of the caller's skin
+constexpr int64_t kProbeSteps = 4;   // steps of a renewed try of the caller's skin
 constexpr int kGraphSteps = 8;       // steps in the longer step graph
 // step graphs: one step without the near energies, one step with them (the
 // last step of a run), kGraphSteps steps without them
