@@ -859,6 +859,8 @@ void build_split(SysHost &h, int nexp64, int nexp32) {
         const double sgn = (k & 1) ? -1.0 : 1.0;
         return std::make_pair(sgn * sp / fact, sgn * sf / fact);
     };
+    // value-initialised: the constants past nexp are zero (the kernels run
+    // the first few terms without testing the count)
     h.co64 = SplitCoef64{};
     h.co32 = SplitCoef32{};
     h.co64.nexp = nexp64;

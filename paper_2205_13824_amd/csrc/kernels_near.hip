@@ -385,16 +385,16 @@ __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>:
                         else ph = fmaf(ph, r2, co->pt[t]);
                     }
                 }
-                // the first kExpRegs terms at fixed indices (their constants
-                // stay in scalar registers across the kernel's loops)
+                // the first kExpRegs terms at fixed indices, with no test of
+                // the count: the constants past it are zero (a term of weight
+                // 0 adds exactly 0)
 #pragma unroll
                 for (int l = 0; l < kExpRegs; ++l) {
-                    if (l >= co->nexp) break;
                     R ex;
                     if constexpr (F64) ex = exp(-r2 * co->a[l]);
                     else ex = __builtin_amdgcn_exp2f(-r2 * co->a[l]);
                     gs += co->cw[l] * ex;
-                    if (L.we) ph += co->w[l] * ex;
+                    ph += co->w[l] * ex;
                 }
                 for (int l = kExpRegs; l < co->nexp; ++l) {
                     R ex;
