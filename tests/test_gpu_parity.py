@@ -281,19 +281,23 @@ def test_c2_full_size_sampled(orc, c2, prec, tol):
     assert np.abs(Ff.sum(0)).max() < (1e-9 if prec == R.RBSOG_FP64 else 1e-3) * np.abs(Ff).max() * math.sqrt(n)
 
 
-@pytest.mark.parametrize("prec", [R.RBSOG_FP64, R.RBSOG_FP32C])
-def test_graph_replay_equals_eager(orc, prec):
-    # rbsog_step replays one captured graph per step; interleave replays with
-    # host reads (synchronisations) and compare with eager launches bit for bit
+@pytest.mark.parametrize("prec,nh", [(R.RBSOG_FP64, False), (R.RBSOG_FP32C, False), (R.RBSOG_FP32C, True)])
+def test_graph_replay_equals_eager(orc, prec, nh):
+    # rbsog_step replays captured graphs of one and of several steps; interleave
+    # replays with host reads (synchronisations) and compare with eager
+    # launches bit for bit (also with the Nose-Hoover thermostat, whose
+    # kinetic-energy sum runs inside every step)
     n, L = 500, 12.0
     pos, q, box = W.ions_rsa(n, n / L ** 3, 1.0, 31)
     v0 = W.maxwellian(n, 1.0, 32)
     out = []
     for graphs in (False, True):
-        say(f"[gpu] graph replay check prec={prec} graphs={graphs}")
+        say(f"[gpu] graph replay check prec={prec} nh={nh} graphs={graphs}")
         sysm = R.System(pos, q, box, 3.0, 50, seed=3, precision=prec, graphs=graphs)
         sysm.sample_k(70)
         R.rbsog_set_velocities(sysm.ctx, v0)
+        if nh:
+            R.rbsog_set_nose_hoover(sysm.ctx, 1.2, 0.05)
         states = []
         # runs of 9 and 20 steps take the graphs of several steps
         for chunk in (5, 7, 3, 9, 20):
@@ -301,6 +305,7 @@ def test_graph_replay_equals_eager(orc, prec):
             states.append(R.rbsog_get_state(sysm.ctx, n))
         states.append(tuple(sysm.components()))
         states.append((R.rbsog_get_energy(sysm.ctx),))
+        states.append(R.rbsog_get_kinetic(sysm.ctx))
         out.append(states)
         sysm.close()
     for a, b in zip(*out):
