@@ -191,34 +191,68 @@ __device__ __forceinline__ R dpp(R v) {
 // the first lane of l's segment).  In-row shifts 1, 2, 4, 8, then the row
 // totals: lane 15 into rows 1 and 3, lane 31 into rows 2 and 3.  A moved
 // value from outside the segment is multiplied by 0 rather than skipped, so
-// that no step changes the lane mask (the moves write 0 where they have no
+// that no step changes the lane mask (the moves read 0 where they have no
 // source lane).
 template <typename R>
 __device__ __forceinline__ void seg_scan3(R &x, R &y, R &z, int lane, int sstart) {
-    const int len = lane - sstart;  // lanes of the segment before this one
+    if constexpr (sizeof(R) == 4) {
+        // FP32: each step is one multiply-add that reads the moved value
+        // through DPP (x += m * x[lane - N]), three per step.  A DPP source
+        // needs two wait states after the VALU write of it: the leading nop
+        // covers the writes before the block, and inside it each accumulator
+        // is written two instructions before it is read again.  Lanes of rows
+        // that a broadcast step masks out keep their value.
+        // the 0/1 factors by clamping integer-valued differences to [0, 1]
+        // (no compare and select, whose mask write a select would wait for)
+        const float fs = (float)sstart;
+        const float d = (float)lane - fs;  // = len
+        const float m1 = __builtin_amdgcn_fmed3f(d, 0.0f, 1.0f);          // len >= 1
+        const float m2 = __builtin_amdgcn_fmed3f(d - 1.0f, 0.0f, 1.0f);   // len >= 2
+        const float m4 = __builtin_amdgcn_fmed3f(d - 3.0f, 0.0f, 1.0f);   // len >= 4
+        const float m8 = __builtin_amdgcn_fmed3f(d - 7.0f, 0.0f, 1.0f);   // len >= 8
+        // rows 1 and 3 only: lane 16 r - 1 lies in the segment
+        const float m15 = __builtin_amdgcn_fmed3f((float)(lane & ~15) - fs, 0.0f, 1.0f);
+        const float m31 = __builtin_amdgcn_fmed3f(32.0f - fs, 0.0f, 1.0f);  // rows 2 and 3 only
+#define RBSOG_FMAC3(M, CTRL, RM)                                                             \
+    "v_fmac_f32_dpp %0, %0, " M " " CTRL " row_mask:" RM " bank_mask:0xf bound_ctrl:1\n\t" \
+    "v_fmac_f32_dpp %1, %1, " M " " CTRL " row_mask:" RM " bank_mask:0xf bound_ctrl:1\n\t" \
+    "v_fmac_f32_dpp %2, %2, " M " " CTRL " row_mask:" RM " bank_mask:0xf bound_ctrl:1\n\t"
+        asm volatile("s_nop 1\n\t"
+                     RBSOG_FMAC3("%3", "row_shr:1", "0xf")
+                     RBSOG_FMAC3("%4", "row_shr:2", "0xf")
+                     RBSOG_FMAC3("%5", "row_shr:4", "0xf")
+                     RBSOG_FMAC3("%6", "row_shr:8", "0xf")
+                     RBSOG_FMAC3("%7", "row_bcast:15", "0xa")
+                     RBSOG_FMAC3("%8", "row_bcast:31", "0xc")
+                     : "+v"(x), "+v"(y), "+v"(z)
+                     : "v"(m1), "v"(m2), "v"(m4), "v"(m8), "v"(m15), "v"(m31));
+#undef RBSOG_FMAC3
+    } else {
+        const int len = lane - sstart;  // lanes of the segment before this one
 #define RBSOG_SHR(N)                                                                     \
     {                                                                                    \
         const R tx = dpp<0x110 + N, 0xf>(x), ty = dpp<0x110 + N, 0xf>(y), tz = dpp<0x110 + N, 0xf>(z); \
         const R m = len >= N ? (R)1 : (R)0;                                              \
         x = fma(tx, m, x); y = fma(ty, m, y); z = fma(tz, m, z);                         \
     }
-    RBSOG_SHR(1)
-    RBSOG_SHR(2)
-    RBSOG_SHR(4)
-    RBSOG_SHR(8)
+        RBSOG_SHR(1)
+        RBSOG_SHR(2)
+        RBSOG_SHR(4)
+        RBSOG_SHR(8)
 #undef RBSOG_SHR
-    {
-        // row_bcast:15 to rows 1 and 3 (row mask 0xa)
-        const R tx = dpp<0x142, 0xa>(x), ty = dpp<0x142, 0xa>(y), tz = dpp<0x142, 0xa>(z);
-        const int row = lane >> 4;
-        const R m = (row == 1 || row == 3) && row * 16 - 1 >= sstart ? (R)1 : (R)0;
-        x = fma(tx, m, x); y = fma(ty, m, y); z = fma(tz, m, z);
-    }
-    {
-        // row_bcast:31 to rows 2 and 3 (row mask 0xc)
-        const R tx = dpp<0x143, 0xc>(x), ty = dpp<0x143, 0xc>(y), tz = dpp<0x143, 0xc>(z);
-        const R m = lane >= 32 && 31 >= sstart ? (R)1 : (R)0;
-        x = fma(tx, m, x); y = fma(ty, m, y); z = fma(tz, m, z);
+        {
+            // row_bcast:15 to rows 1 and 3 (row mask 0xa)
+            const R tx = dpp<0x142, 0xa>(x), ty = dpp<0x142, 0xa>(y), tz = dpp<0x142, 0xa>(z);
+            const int row = lane >> 4;
+            const R m = (row == 1 || row == 3) && row * 16 - 1 >= sstart ? (R)1 : (R)0;
+            x = fma(tx, m, x); y = fma(ty, m, y); z = fma(tz, m, z);
+        }
+        {
+            // row_bcast:31 to rows 2 and 3 (row mask 0xc)
+            const R tx = dpp<0x143, 0xc>(x), ty = dpp<0x143, 0xc>(y), tz = dpp<0x143, 0xc>(z);
+            const R m = lane >= 32 && 31 >= sstart ? (R)1 : (R)0;
+            x = fma(tx, m, x); y = fma(ty, m, y); z = fma(tz, m, z);
+        }
     }
 }
 
@@ -424,8 +458,11 @@ __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>:
     // a pass can hold two runs of one home (two candidate passes of the
     // build), so segment totals are added atomically; the adds of one wave
     // into its own slots happen in a fixed order
-    const int count = (int)__popcll(ballot(have));  // the lanes holding pairs are a prefix
-    const bool tail = have && (lane == count - 1 || (lane < 63 && ((H >> (lane + 1)) & 1ull)));
+    // the lanes holding pairs are a prefix: its last lane, and every lane
+    // before a segment start, ends a segment
+    const uint64_t HM = ballot(have);
+    const uint64_t TM = ((H >> 1) | (HM ^ (HM >> 1))) & HM;
+    const bool tail = (TM >> lane) & 1ull;
     if (tail) {
         atomicAdd(&L.hf[0][slot], fx);
         atomicAdd(&L.hf[1][slot], fy);
