@@ -193,6 +193,19 @@ __device__ __forceinline__ R dpp(R v) {
 // value from outside the segment is multiplied by 0 rather than skipped, so
 // that no step changes the lane mask (the moves read 0 where they have no
 // source lane).
+// Inclusive sum over lanes 0..31 by DPP moves (lanes 32..63 hold sums of
+// their own half): in-row shifts 1, 2, 4, 8 (a move reads 0 where it has no
+// source lane), then row 1 adds lane 15 (the broadcast leaves rows 0 and 2
+// with the move's old value 0).
+__device__ __forceinline__ int32_t incl_scan32(int32_t v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
+    return v;
+}
+
 template <typename R>
 __device__ __forceinline__ void seg_scan3(R &x, R &y, R &z, int lane, int sstart) {
     if constexpr (sizeof(R) == 4) {
@@ -926,7 +939,7 @@ struct NearLds {
     uint2 q[512 + 64];     // ring of queued pairs: (home index in the batch, candidate slot),
                            // then one spare entry per lane for the stores of rejected pairs
     int32_t rlo[32], rex[32];  // non-empty candidate ranges of the cell: first slot, offset in the list
-    int32_t flag[64];          // range starts inside the current 64-slot window
+    uint32_t flag4[64];        // byte flags: range starts in a pass's (up to 4) 64-slot windows
 };
 
 // Steps that build at every evaluation (skin 0) need no list: this kernel
@@ -1058,11 +1071,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
                 int32_t ra_, rb_;
                 if (row_range_w(g, start + c0s, lane, cx, cy, cz, w, ra_, rb_)) { lo = ra_; len = rb_ - ra_; }
             }
-            int32_t incl = len;
-            for (int o = 1; o < 32; o <<= 1) {
-                const int32_t v = __shfl_up(incl, o, 64);
-                if (lane >= o) incl += v;
-            }
+            const int32_t incl = incl_scan32(len);
             const int32_t excl = incl - len;
             const int32_t C = __builtin_amdgcn_readlane(incl, kRanges - 1);
             // the non-empty ranges, compacted: lane k < nne holds the k-th one's
@@ -1078,35 +1087,39 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
                 L.rex[k] = excl;
             }
             wave_sync();
-            const int32_t clo = lane < nne ? L.rlo[lane < 32 ? lane : 0] : 0;
             const int32_t cex = lane < nne ? L.rex[lane < 32 ? lane : 0] : 0x7fffffff;
+            // slot of the range's first candidate minus its offset in the list
+            const int32_t cdl = lane < nne ? L.rlo[lane < 32 ? lane : 0] - cex : 0;
             // origin of the cell-relative float coordinates used by the test:
             // the first home of the cell
             const uint4 o4 = L.hu[i0];
             const uint32_t ox = (uint32_t)rfl((int)o4.x), oy = (uint32_t)rfl((int)o4.y),
                            oz = (uint32_t)rfl((int)o4.z);
             for (int32_t cb = 0; cb < C; cb += 64 * S) {
-                // candidates of this pass in registers.  For each 64-slot window,
-                // the starts of ranges inside it are flagged in LDS; a slot's
-                // range is the number of range starts at or before it (those
-                // before the window, plus the flagged ones up to its lane) - 1.
+                // candidates of this pass in registers.  The starts of ranges
+                // inside the pass's S windows of 64 slots are flagged in LDS
+                // (one byte per slot); a slot's range is the number of range
+                // starts at or before it (those before the pass, those of the
+                // earlier windows, and the flagged ones up to its lane) - 1.
+                static_assert(S <= 4, "byte flags for at most four windows");
                 uint32_t cj[S];
+                uint8_t *flag = (uint8_t *)L.flag4;
+                L.flag4[lane] = 0u;
+                wave_sync();
+                if (lane < nne && cex >= cb && cex < cb + 64 * S) flag[cex - cb] = 1;
+                wave_sync();
+                int before = (int)__popcll(ballot(lane < nne && cex < cb));
+                const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
 #pragma unroll
                 for (int s2 = 0; s2 < S; ++s2) {
-                    const int32_t base = cb + s2 * 64;
-                    L.flag[lane] = 0;
-                    wave_sync();
-                    if (lane < nne && cex >= base && cex < base + 64) L.flag[cex - base] = 1;
-                    wave_sync();
-                    const uint64_t B = ballot(L.flag[lane] != 0);
-                    const int before = (int)__popcll(ballot(lane < nne && cex < base));
-                    const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+                    const uint64_t B = ballot(flag[s2 * 64 + lane] != 0);
                     int k = before + (int)__popcll(B & upto) - 1;
                     k = k < 0 ? 0 : k;
-                    // the permutes read other lanes' registers: the whole wave is active
-                    cj[s2] = (uint32_t)(__shfl(clo, k, 64) + (base + lane - __shfl(cex, k, 64)));
-                    wave_sync();
+                    before += (int)__popcll(B);
+                    // the permute reads other lanes' registers: the whole wave is active
+                    cj[s2] = (uint32_t)(__shfl(cdl, k, 64) + (cb + s2 * 64 + lane));
                 }
+                wave_sync();
                 uint32_t cux[S], cuy[S], cuz[S];
 #pragma unroll
                 for (int s2 = 0; s2 < S; ++s2) {
