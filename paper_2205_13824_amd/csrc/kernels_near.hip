@@ -363,7 +363,9 @@ __device__ __forceinline__ PairData<F64> load_pair(const uint32_t *__restrict__ 
     return d;
 }
 
-template <bool F64>
+// SELF: the ring may hold the home itself (the fused cell kernel's test does
+// not leave it out); such an entry is rejected here by its slot.
+template <bool F64, bool SELF = false>
 __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>::type *co, const HomeView<F64> &L,
                                             const float4 *__restrict__ tbl, float rin2, CSys *csp,
                                              int lane, uint2 qe, bool have, const PairData<F64> &pd,
@@ -382,6 +384,7 @@ __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>:
         const float r2f = ex_ * ex_ + ey_ * ey_ + ez_ * ez_;
         bool in = r2f <= g.band_lo_f;
         if (!in && r2f < g.band_hi_f) in = exact_in(g, dux, duy, duz);
+        if constexpr (SELF) in = in && qe.y != h.w;
         if (in) {
             R dx, dy, dz, qq;
             if constexpr (F64) {
@@ -483,14 +486,14 @@ __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>:
     }
 }
 
-template <bool F64>
+template <bool F64, bool SELF = false>
 __device__ __forceinline__ void eval_pair(const Geom &g, typename CoefOf<F64>::type *co, const HomeView<F64> &L,
                                           const uint32_t *__restrict__ su, const double *__restrict__ sx,
                                           const double *__restrict__ sq, const float *__restrict__ sqf, int64_t n,
                                           const float4 *__restrict__ tbl, float rin2, CSys *csp,
                                            int lane, uint2 qe, bool have, double &e) {
     const PairData<F64> pd = load_pair<F64>(su, sx, sq, sqf, n, qe, have);
-    eval_loaded<F64>(g, co, L, tbl, rin2, csp, lane, qe, have, pd, e);
+    eval_loaded<F64, SELF>(g, co, L, tbl, rin2, csp, lane, qe, have, pd, e);
 }
 
 template <bool F64, int Q>
@@ -538,7 +541,7 @@ __device__ __forceinline__ void eval_ring(const uint2 *ring, const HomeView<F64>
                                           double &e) {
     const bool have = lane < count;
     const uint2 qe = have ? ring[(head + lane) & (Q - 1)] : make_uint2(0u, 0u);
-    eval_pair<F64>(g, co, hv, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qe, have, e);
+    eval_pair<F64, true>(g, co, hv, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qe, have, e);
 }
 
 // Ring entries [head, head + count): written to the wave's list segment
@@ -1163,9 +1166,9 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
                     for (int ii = 0; ii < gn; ii += kU) {
                         // acceptance of each (home, slot) as a lane predicate
                         // and as the wave's mask: both come from one compare
-                        // (the home itself and the empty slots are pushed
-                        // past the band by their r^2; a home past the group's
-                        // end compares against a negative limit)
+                        // (the empty slots are pushed past the band by their
+                        // r^2; a home past the group's end compares against a
+                        // negative limit; the home itself is admitted)
                         bool acc[kU][S];
                         uint64_t mm[kU][S];
 #pragma unroll
@@ -1173,7 +1176,6 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
                             const bool hok = ii + uu < gn;
                             const int h = hok ? ii + uu : ii;
                             const float lim = hok ? g.band_hi_f : -1.0f;
-                            const uint32_t self = (uint32_t)(t + g0 + h);
                             if constexpr (REL) {
                                 const float hx_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfx), h));
                                 const float hy_ = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hfy), h));
@@ -1182,9 +1184,8 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
                                 for (int s2 = 0; s2 < S; ++s2) {
                                     const float dx = cfx[s2] - hx_, dy = cfy[s2] - hy_, dz = cfz[s2] - hz_;
                                     const float r2 = dx * dx + dy * dy + dz * dz;
-                                    const float r2x = cj[s2] == self ? kFarR2 : r2;
-                                    acc[uu][s2] = r2x < lim;
-                                    mm[uu][s2] = ballot(r2x < lim);
+                                    acc[uu][s2] = r2 < lim;
+                                    mm[uu][s2] = ballot(r2 < lim);
                                 }
                             } else {
                                 const uint32_t hux = (uint32_t)__builtin_amdgcn_readlane((int)hme.x, h);
@@ -1193,7 +1194,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
 #pragma unroll
                                 for (int s2 = 0; s2 < S; ++s2) {
                                     const float r2 = fixed_r2(g, cux[s2] - hux, cuy[s2] - huy, cuz[s2] - huz);
-                                    const float r2x = cj[s2] == self || cj[s2] == kNoCand ? kFarR2 : r2;
+                                    const float r2x = cj[s2] == kNoCand ? kFarR2 : r2;
                                     acc[uu][s2] = r2x < lim;
                                     mm[uu][s2] = ballot(r2x < lim);
                                 }
