@@ -420,17 +420,19 @@ __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>:
                     hk = ri - pb;
                 }
             } else {
-                R rinv, gs = 0, ph = 0;
+                // Horner from the leading coefficient
+                R rinv, gs = co->ft[NT - 1], ph = 0;
                 if constexpr (F64) rinv = rsqrt(r2);
                 else rinv = __builtin_amdgcn_rsqf(r2);
 #pragma unroll
-                for (int t = NT - 1; t >= 0; --t) {
+                for (int t = NT - 2; t >= 0; --t) {
                     if constexpr (F64) gs = fma(gs, r2, co->ft[t]);
                     else gs = fmaf(gs, r2, co->ft[t]);
                 }
                 if (L.we) {
+                    ph = co->pt[NT - 1];
 #pragma unroll
-                    for (int t = NT - 1; t >= 0; --t) {
+                    for (int t = NT - 2; t >= 0; --t) {
                         if constexpr (F64) ph = fma(ph, r2, co->pt[t]);
                         else ph = fmaf(ph, r2, co->pt[t]);
                     }
@@ -438,13 +440,20 @@ __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>:
                 // the first kExpRegs terms at fixed indices, with no test of
                 // the count: the constants past it are zero (a term of weight
                 // 0 adds exactly 0)
+                R exv[kExpRegs];
 #pragma unroll
                 for (int l = 0; l < kExpRegs; ++l) {
-                    R ex;
-                    if constexpr (F64) ex = exp(-r2 * co->a[l]);
-                    else ex = __builtin_amdgcn_exp2f(-r2 * co->a[l]);
-                    gs += co->cw[l] * ex;
-                    ph += co->w[l] * ex;
+                    if constexpr (F64) exv[l] = exp(-r2 * co->a[l]);
+                    else exv[l] = __builtin_amdgcn_exp2f(-r2 * co->a[l]);
+                    gs += co->cw[l] * exv[l];
+                }
+                // the potential's terms only when energies are summed: a
+                // uniform branch, kept a branch by the empty asm statement
+                // (which the compiler does not speculate)
+                if (L.we) {
+                    asm volatile("");
+#pragma unroll
+                    for (int l = 0; l < kExpRegs; ++l) ph += co->w[l] * exv[l];
                 }
                 for (int l = kExpRegs; l < co->nexp; ++l) {
                     R ex;
@@ -461,10 +470,16 @@ __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>:
             fx = -coef * dx;
             fy = -coef * dy;
             fz = -coef * dz;
-            if (L.we) de = 0.5 * (double)(qq * hk);
+            if (L.we) {
+                asm volatile("");
+                de = 0.5 * (double)(qq * hk);
+            }
         }
     }
-    if (L.we) e += de;
+    if (L.we) {
+        asm volatile("");
+        e += de;
+    }
     const int prev = __shfl_up(slot, 1, 64);
     const bool seg = lane == 0 || slot != prev;
     const uint64_t H = ballot(seg);
