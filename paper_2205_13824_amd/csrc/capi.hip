@@ -80,11 +80,12 @@ constexpr int kGraphSteps = 8;       // steps in the longer step graph
 enum { GV_STEP = 0, GV_STEP_E = 1, GV_MULTI = 2, GV_COUNT = 3 };
 
 enum Kid {
-    K_KDQ, K_BIN, K_SCAN, K_SCATTER, K_SORTG, K_LIST, K_NEAR, K_NEARC, K_RHO, K_RHORED, K_FAR, K_SAMPLE, K_COUNT
+    K_KDQ, K_BIN, K_SCAN, K_SCATTER, K_SORTG, K_LIST, K_NEAR, K_NEARC, K_RHO, K_RHORED, K_FAR, K_SAMPLE, K_FARFIN,
+    K_COUNT
 };
 const char *kKernelNames[K_COUNT] = {"kick_drift_quantise", "bin", "scan_cell_counts", "cell_scatter", "sort_gather",
                                      "list_build", "near", "near_cells", "rho", "rho_reduce", "far",
-                                     "sample_refill"};
+                                     "sample_refill", "far_finish"};
 
 
 // Launch shapes of the work lists (the tunable part of the plan).
@@ -182,6 +183,7 @@ struct rbsog_ctx {
     int32_t build_slots = 2;  // candidates per lane and test pass of the build
     int32_t cell_slots = 2;   // the same for the fused cell kernel
     double *Fn = nullptr, *Ff = nullptr;
+    double *Ff_side = nullptr;  // build-every-step mode: far forces before the re-sort
     int64_t *kcur = nullptr;
     KRec64 *kb64 = nullptr;
     KRec32 *kb32 = nullptr;
@@ -547,6 +549,7 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
     a.nbuild = c->nbuild;
     a.Fn = c->Fn;
     a.Ff = c->Ff;
+    a.Ff_side = c->Ff_side;
     a.kcur = c->kcur;
     a.kb64 = c->kb64;
     a.kb32 = c->kb32;
@@ -599,11 +602,16 @@ rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt, bool kinetic, 
     // side stream beside the re-sort and the near part (one stream while
     // profiling, so that each kernel is timed alone)
     const bool fork = !c->prof_on;
+    // building at every step, the far force joins them there (the near part
+    // is long enough to hide it); it is then read back in the new order
+    const bool far_side = a.always_build != 0;
+    const int32_t fb = c->tune.far_block;
     if (fork) {
         HIPCHK(c, hipEventRecord(c->ev_fork, s));
         HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
         launch_rho(a, f64, c->rho_items, c->n_rho, c->side);
         launch_rho_reduce(a, c->side);
+        if (far_side) launch_far_side(a, f64, c->far_items, c->n_far, fb, c->side);
         HIPCHK(c, hipEventRecord(c->ev_join, c->side));
     }
     if (!a.always_build) TRY(timed(c, K_BIN, [&] { launch_bin(a, s); }));
@@ -621,8 +629,10 @@ rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt, bool kinetic, 
     } else {
         TRY(timed(c, K_RHO, [&] { launch_rho(a, f64, c->rho_items, c->n_rho, s); }));
         TRY(timed(c, K_RHORED, [&] { launch_rho_reduce(a, s); }));
+        if (far_side) TRY(timed(c, K_FAR, [&] { launch_far_side(a, f64, c->far_items, c->n_far, fb, s); }));
     }
-    TRY(timed(c, K_FAR, [&] { launch_far(a, f64, c->far_items, c->n_far, c->tune.far_block, s); }));
+    if (far_side) TRY(timed(c, K_FARFIN, [&] { launch_far_finish(a, c->far_items, c->n_far, fb, s); }));
+    else TRY(timed(c, K_FAR, [&] { launch_far(a, f64, c->far_items, c->n_far, fb, s); }));
     if (kinetic) launch_kinetic(a, s);
     HIPCHK(c, hipGetLastError());
     return RBSOG_OK;
@@ -1541,6 +1551,7 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     ALLOC(blocksums, scan_blocksums_size(C));
     ALLOC(Fn, 3 * N);
     ALLOC(Ff, 3 * N);
+    ALLOC(Ff_side, 3 * N);
     ALLOC(kcur, nsys);
     ALLOC(kb64, K);
     ALLOC(kb32, K);

@@ -344,138 +344,199 @@ __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
     }
 }
 
-// Far force, one particle per lane, the P records of its system streamed
-// uniformly; items are runs of up to 256 slots of one system (grid-stride).
-// The near-list rebuild flag is cleared here: every kernel of the
-// evaluation that reads it has run.
-// The kinetic energy of each wave's particles after the evaluation is summed
-// across the wave in a fixed order into partial [item * 4 + wave]
-// (k_kinetic adds them up).
+// Far force on particle i (the factor -q_i included) from its system's P
+// records, streamed as uniform loads: positions and charges from (u, qf) in
+// FP32C, (x, q) in FP64.
+template <bool F64>
+__device__ __forceinline__ void far_sum(CSys *sp, CRec64 *kb64, CRec32 *kb32, int32_t P, int64_t n, int64_t i,
+                                        const uint32_t *__restrict__ u, const float *__restrict__ qf,
+                                        const double *__restrict__ x, const double *__restrict__ q, double &Fx,
+                                        double &Fy, double &Fz) {
+    Fx = 0.0; Fy = 0.0; Fz = 0.0;
+    // records are consumed in groups so that their uniform loads overlap
+    if constexpr (F64) {
+        const double sx = x[i] * sp->g.invL[0], sy = x[n + i] * sp->g.invL[1], sz = x[2 * n + i] * sp->g.invL[2];
+        constexpr int G = 2;
+        int32_t e = 0;
+        for (; e + G <= P; e += G) {
+            KRec64 r[G];
+#pragma unroll
+            for (int h = 0; h < G; ++h) r[h] = ld(kb64 + e + h);
+#pragma unroll
+            for (int h = 0; h < G; ++h) {
+                const double t = r[h].mx * sx + r[h].my * sy + r[h].mz * sz;
+                double sn, cs;
+                sincos2pi(t - rint(t), &sn, &cs);
+                const double v = cs * r[h].im - sn * r[h].re;
+                Fx = fma(r[h].ckx, v, Fx);
+                Fy = fma(r[h].cky, v, Fy);
+                Fz = fma(r[h].ckz, v, Fz);
+            }
+        }
+        for (; e < P; ++e) {
+            const KRec64 r = ld(kb64 + e);
+            const double t = r.mx * sx + r.my * sy + r.mz * sz;
+            double sn, cs;
+            sincos2pi(t - rint(t), &sn, &cs);
+            const double v = cs * r.im - sn * r.re;
+            Fx = fma(r.ckx, v, Fx);
+            Fy = fma(r.cky, v, Fy);
+            Fz = fma(r.ckz, v, Fz);
+        }
+        const double qi = q[i];
+        Fx *= -qi; Fy *= -qi; Fz *= -qi;
+    } else {
+        const uint32_t ux = u[i], uy = u[n + i], uz = u[2 * n + i];
+        constexpr int G = 4;
+        int32_t e = 0;
+        // FP32 partial sums over 64 records, then accumulated in FP64
+        for (; e + 16 * G <= P; e += 16 * G) {
+            float fx = 0.f, fy = 0.f, fz = 0.f;
+#pragma unroll
+            for (int h4 = 0; h4 < 16; ++h4) {
+                KRec32 r[G];
+#pragma unroll
+                for (int h = 0; h < G; ++h) r[h] = ld(kb32 + e + h4 * G + h);
+#pragma unroll
+                for (int h = 0; h < G; ++h) {
+                    const uint32_t t = (uint32_t)r[h].mx * ux + (uint32_t)r[h].my * uy + (uint32_t)r[h].mz * uz;
+                    const float f = (float)(int32_t)t * 0x1.0p-32f;
+                    const float v = __builtin_amdgcn_cosf(f) * r[h].im - __builtin_amdgcn_sinf(f) * r[h].re;
+                    fx = fmaf(r[h].ckx, v, fx);
+                    fy = fmaf(r[h].cky, v, fy);
+                    fz = fmaf(r[h].ckz, v, fz);
+                }
+            }
+            Fx += fx; Fy += fy; Fz += fz;
+        }
+        float fx = 0.f, fy = 0.f, fz = 0.f;
+        for (; e < P; ++e) {
+            const KRec32 r = ld(kb32 + e);
+            const uint32_t t = (uint32_t)r.mx * ux + (uint32_t)r.my * uy + (uint32_t)r.mz * uz;
+            const float f = (float)(int32_t)t * 0x1.0p-32f;
+            const float v = __builtin_amdgcn_cosf(f) * r.im - __builtin_amdgcn_sinf(f) * r.re;
+            fx = fmaf(r.ckx, v, fx);
+            fy = fmaf(r.cky, v, fy);
+            fz = fmaf(r.ckz, v, fz);
+        }
+        const double qi = -(double)qf[i];
+        Fx = qi * (Fx + fx); Fy = qi * (Fy + fy); Fz = qi * (Fz + fz);
+    }
+}
+
+// The end of an evaluation for slot i (current order) given its far force:
+// the zero-frequency mode term, the far force stored, the closing half kick
+// (and the second Nose-Hoover scaling) when stepping, and the kinetic energy
+// of each wave's particles summed across the wave in a fixed order into
+// partial [item * 4 + wave] (k_kinetic adds them up).
+__device__ __forceinline__ void far_finish(const EvalArgs &a, CSys *sp, int32_t sys, int64_t i, bool valid,
+                                           double Fx, double Fy, double Fz, int32_t itx) {
+    const int64_t n = a.N;
+    double ke = 0.0;
+    if (valid) {
+        if (sp->zmode != 0) {
+            const double qi = a.cur.q[i], c = sp->zf * qi;
+            const double *M = a.dipole + 3 * sys;
+            if (sp->zmode == 1) {
+                Fx += c * M[0];
+                Fy += c * M[1];
+            }
+            Fz += c * M[2];
+        }
+        a.Ff[i] = Fx;
+        a.Ff[n + i] = Fy;
+        a.Ff[2 * n + i] = Fz;
+        double vv[3] = {a.cur.v[i], a.cur.v[n + i], a.cur.v[2 * n + i]};
+        if (a.kick) {
+            // closing half kick of the velocity-Verlet step
+            const double f[3] = {a.Fn[i] + Fx, a.Fn[n + i] + Fy, a.Fn[2 * n + i] + Fz};
+            bool bad = false;
+            for (int d = 0; d < 3; ++d) {
+                bad |= !isfinite(f[d]);
+                vv[d] += a.hdm * f[d];
+            }
+            if (a.nh) {
+                // Nose-Hoover: the second scaling with the step's half-step xi
+                // (xi and the kinetic energy still hold the step's start)
+                const double xh = a.nh_xi[sys] + 0.5 * a.dt * (2.0 * a.kin[sys] - sp->nh_nf * a.nh_T) / sp->nh_Q;
+                const double sc = exp(-0.5 * a.dt * xh);
+                for (int d = 0; d < 3; ++d) vv[d] *= sc;
+            }
+            for (int d = 0; d < 3; ++d) a.cur.v[d * n + i] = vv[d];
+            if (bad) atomicOr(a.flag, 1);
+        }
+        ke = 0.5 * a.mass * ((vv[0] * vv[0] + vv[1] * vv[1]) + vv[2] * vv[2]);
+    }
+    // the wave's kinetic energy (a fixed butterfly), one partial per wave
+    for (int o = 32; o > 0; o >>= 1) ke += __shfl_xor(ke, o, 64);
+    if ((threadIdx.x & 63) == 0) a.kpart[(int64_t)itx * 4 + (threadIdx.x >> 6)] = ke;
+}
+
+// Far force and the end of the evaluation, one particle per lane; items are
+// runs of up to 256 slots of one system (grid-stride).  The near-list
+// rebuild flag is cleared here: every kernel of the evaluation that reads it
+// has run.
 template <bool F64>
 __global__ __launch_bounds__(256) void k_far(EvalArgs a, const FarItem *__restrict__ items, int32_t nitems) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.rebuild) *a.rebuild = 0;
+    for (int32_t itx = blockIdx.x; itx < nitems; itx += gridDim.x) {
+        const FarItem item = items[itx];
+        const int32_t sys = rfl(item.sys);
+        CSys *sp = (CSys *)(a.sys + sys);
+        const int64_t t0 = rfl64(item.t0), t1 = rfl64(item.t1);
+        const int64_t i0 = t0 + threadIdx.x;
+        const bool valid = i0 < t1;
+        const int64_t i = valid ? i0 : t0;
+        double Fx, Fy, Fz;
+        far_sum<F64>(sp, (CRec64 *)(a.kb64 + sp->k0), (CRec32 *)(a.kb32 + sp->k0), sp->P, a.N, i, a.u_tmp,
+                     a.cur.qf, a.cur.x, a.cur.q, Fx, Fy, Fz);
+        far_finish(a, sp, sys, i, valid, Fx, Fy, Fz, itx);
+    }
+}
+
+// Build-every-step mode: the far force computed beside the re-sort and the
+// near part, on the structure factor's stream, from the copy of the state
+// that the kick/drift kernel wrote (its order: the slots before the re-sort),
+// into Ff_side.
+template <bool F64>
+__global__ __launch_bounds__(256) void k_far_side(EvalArgs a, const FarItem *__restrict__ items, int32_t nitems) {
+    const int64_t n = a.N;
+    for (int32_t itx = blockIdx.x; itx < nitems; itx += gridDim.x) {
+        const FarItem item = items[itx];
+        CSys *sp = (CSys *)(a.sys + rfl(item.sys));
+        const int64_t t0 = rfl64(item.t0), t1 = rfl64(item.t1);
+        const int64_t i0 = t0 + threadIdx.x;
+        const bool valid = i0 < t1;
+        const int64_t i = valid ? i0 : t0;
+        double Fx, Fy, Fz;
+        far_sum<F64>(sp, (CRec64 *)(a.kb64 + sp->k0), (CRec32 *)(a.kb32 + sp->k0), sp->P, n, i, a.rs_u, a.rs_qf,
+                     a.rs_x, a.rs_q, Fx, Fy, Fz);
+        if (valid) {
+            a.Ff_side[i] = Fx;
+            a.Ff_side[n + i] = Fy;
+            a.Ff_side[2 * n + i] = Fz;
+        }
+    }
+}
+
+// Build-every-step mode, after the near part: slot i of the new order takes
+// the far force of its particle's slot before the re-sort (`sorted`, which
+// the re-sort writes at every evaluation of this mode), then the end of the
+// evaluation as in k_far.  Clears the rebuild flag.
+__global__ __launch_bounds__(256) void k_far_finish(EvalArgs a, const FarItem *__restrict__ items, int32_t nitems) {
     const int64_t n = a.N;
     if (blockIdx.x == 0 && threadIdx.x == 0 && a.rebuild) *a.rebuild = 0;
     for (int32_t itx = blockIdx.x; itx < nitems; itx += gridDim.x) {
         const FarItem item = items[itx];
         const int32_t sys = rfl(item.sys);
         CSys *sp = (CSys *)(a.sys + sys);
-        const int32_t P = sp->P;
-        CRec64 *kb64 = (CRec64 *)(a.kb64 + sp->k0);
-        CRec32 *kb32 = (CRec32 *)(a.kb32 + sp->k0);
         const int64_t t0 = rfl64(item.t0), t1 = rfl64(item.t1);
         const int64_t i0 = t0 + threadIdx.x;
         const bool valid = i0 < t1;
         const int64_t i = valid ? i0 : t0;
-        double Fx = 0.0, Fy = 0.0, Fz = 0.0;
-        // records are consumed in groups so that their uniform loads overlap
-        if constexpr (F64) {
-            const double *__restrict__ x = a.cur.x;
-            const double sx = x[i] * sp->g.invL[0], sy = x[n + i] * sp->g.invL[1], sz = x[2 * n + i] * sp->g.invL[2];
-            constexpr int G = 2;
-            int32_t e = 0;
-            for (; e + G <= P; e += G) {
-                KRec64 r[G];
-#pragma unroll
-                for (int h = 0; h < G; ++h) r[h] = ld(kb64 + e + h);
-#pragma unroll
-                for (int h = 0; h < G; ++h) {
-                    const double t = r[h].mx * sx + r[h].my * sy + r[h].mz * sz;
-                    double sn, cs;
-                    sincos2pi(t - rint(t), &sn, &cs);
-                    const double v = cs * r[h].im - sn * r[h].re;
-                    Fx = fma(r[h].ckx, v, Fx);
-                    Fy = fma(r[h].cky, v, Fy);
-                    Fz = fma(r[h].ckz, v, Fz);
-                }
-            }
-            for (; e < P; ++e) {
-                const KRec64 r = ld(kb64 + e);
-                const double t = r.mx * sx + r.my * sy + r.mz * sz;
-                double sn, cs;
-                sincos2pi(t - rint(t), &sn, &cs);
-                const double v = cs * r.im - sn * r.re;
-                Fx = fma(r.ckx, v, Fx);
-                Fy = fma(r.cky, v, Fy);
-                Fz = fma(r.ckz, v, Fz);
-            }
-            const double qi = a.cur.q[i];
-            Fx *= -qi; Fy *= -qi; Fz *= -qi;
-        } else {
-            const uint32_t *__restrict__ u = a.u_tmp;
-            const uint32_t ux = u[i], uy = u[n + i], uz = u[2 * n + i];
-            constexpr int G = 4;
-            int32_t e = 0;
-            // FP32 partial sums over 64 records, then accumulated in FP64
-            for (; e + 16 * G <= P; e += 16 * G) {
-                float fx = 0.f, fy = 0.f, fz = 0.f;
-#pragma unroll
-                for (int h4 = 0; h4 < 16; ++h4) {
-                    KRec32 r[G];
-#pragma unroll
-                    for (int h = 0; h < G; ++h) r[h] = ld(kb32 + e + h4 * G + h);
-#pragma unroll
-                    for (int h = 0; h < G; ++h) {
-                        const uint32_t t = (uint32_t)r[h].mx * ux + (uint32_t)r[h].my * uy + (uint32_t)r[h].mz * uz;
-                        const float f = (float)(int32_t)t * 0x1.0p-32f;
-                        const float v = __builtin_amdgcn_cosf(f) * r[h].im - __builtin_amdgcn_sinf(f) * r[h].re;
-                        fx = fmaf(r[h].ckx, v, fx);
-                        fy = fmaf(r[h].cky, v, fy);
-                        fz = fmaf(r[h].ckz, v, fz);
-                    }
-                }
-                Fx += fx; Fy += fy; Fz += fz;
-            }
-            float fx = 0.f, fy = 0.f, fz = 0.f;
-            for (; e < P; ++e) {
-                const KRec32 r = ld(kb32 + e);
-                const uint32_t t = (uint32_t)r.mx * ux + (uint32_t)r.my * uy + (uint32_t)r.mz * uz;
-                const float f = (float)(int32_t)t * 0x1.0p-32f;
-                const float v = __builtin_amdgcn_cosf(f) * r.im - __builtin_amdgcn_sinf(f) * r.re;
-                fx = fmaf(r.ckx, v, fx);
-                fy = fmaf(r.cky, v, fy);
-                fz = fmaf(r.ckz, v, fz);
-            }
-            const double qi = -(double)a.cur.qf[i];
-            Fx = qi * (Fx + fx); Fy = qi * (Fy + fy); Fz = qi * (Fz + fz);
-        }
-        double ke = 0.0;
-        if (valid) {
-            if (sp->zmode != 0) {
-                const double qi = a.cur.q[i], c = sp->zf * qi;
-                const double *M = a.dipole + 3 * sys;
-                if (sp->zmode == 1) {
-                    Fx += c * M[0];
-                    Fy += c * M[1];
-                }
-                Fz += c * M[2];
-            }
-            a.Ff[i] = Fx;
-            a.Ff[n + i] = Fy;
-            a.Ff[2 * n + i] = Fz;
-            double vv[3] = {a.cur.v[i], a.cur.v[n + i], a.cur.v[2 * n + i]};
-            if (a.kick) {
-                // closing half kick of the velocity-Verlet step
-                const double f[3] = {a.Fn[i] + Fx, a.Fn[n + i] + Fy, a.Fn[2 * n + i] + Fz};
-                bool bad = false;
-                for (int d = 0; d < 3; ++d) {
-                    bad |= !isfinite(f[d]);
-                    vv[d] += a.hdm * f[d];
-                }
-                if (a.nh) {
-                    // Nose-Hoover: the second scaling with the step's half-step xi
-                    // (xi and the kinetic energy still hold the step's start)
-                    const double xh = a.nh_xi[sys] + 0.5 * a.dt * (2.0 * a.kin[sys] - sp->nh_nf * a.nh_T) / sp->nh_Q;
-                    const double sc = exp(-0.5 * a.dt * xh);
-                    for (int d = 0; d < 3; ++d) vv[d] *= sc;
-                }
-                for (int d = 0; d < 3; ++d) a.cur.v[d * n + i] = vv[d];
-                if (bad) atomicOr(a.flag, 1);
-            }
-            ke = 0.5 * a.mass * ((vv[0] * vv[0] + vv[1] * vv[1]) + vv[2] * vv[2]);
-        }
-        // the wave's kinetic energy (a fixed butterfly), one partial per wave
-        for (int o = 32; o > 0; o >>= 1) ke += __shfl_xor(ke, o, 64);
-        if ((threadIdx.x & 63) == 0) a.kpart[(int64_t)itx * 4 + (threadIdx.x >> 6)] = ke;
+        const int64_t o = a.sorted[i];
+        const double Fx = a.Ff_side[o], Fy = a.Ff_side[n + o], Fz = a.Ff_side[2 * n + o];
+        far_finish(a, sp, sys, i, valid, Fx, Fy, Fz, itx);
     }
 }
 
@@ -568,6 +629,17 @@ void launch_far(const EvalArgs &a, bool f64, const FarItem *items, int32_t nitem
     dim3 grid((unsigned)nitems), block((unsigned)block_size);
     if (f64) hipLaunchKernelGGL(k_far<true>, grid, block, 0, s, a, items, nitems);
     else hipLaunchKernelGGL(k_far<false>, grid, block, 0, s, a, items, nitems);
+}
+
+void launch_far_side(const EvalArgs &a, bool f64, const FarItem *items, int32_t nitems, int32_t block_size,
+                     hipStream_t s) {
+    dim3 grid((unsigned)nitems), block((unsigned)block_size);
+    if (f64) hipLaunchKernelGGL(k_far_side<true>, grid, block, 0, s, a, items, nitems);
+    else hipLaunchKernelGGL(k_far_side<false>, grid, block, 0, s, a, items, nitems);
+}
+
+void launch_far_finish(const EvalArgs &a, const FarItem *items, int32_t nitems, int32_t block_size, hipStream_t s) {
+    hipLaunchKernelGGL(k_far_finish, dim3((unsigned)nitems), dim3((unsigned)block_size), 0, s, a, items, nitems);
 }
 
 void launch_kinetic(const EvalArgs &a, hipStream_t s) {

@@ -174,6 +174,7 @@ struct EvalArgs {
     int32_t *skey;         // particle id of each scattered slot (the per-cell sort's key)
     int32_t *cell_sorted;  // cell of each slot at the latest list build
     double *Fn, *Ff;       // forces in slot order
+    double *Ff_side;       // build-every-step mode: far forces in the order before the re-sort
     // Verlet list: rebuild flag (set by the displacement check, cleared by the
     // near kernel), pairs (home index in the item, candidate slot), counts,
     // capacity per item, largest count of the latest build, builds made
@@ -284,6 +285,9 @@ void launch_rho_reduce(const EvalArgs &a, hipStream_t s);
 // (items of at most block_size particles, block_size in {64, 128, 256})
 void launch_far(const EvalArgs &a, bool f64, const FarItem *items, int32_t nitems, int32_t block_size,
                 hipStream_t s);
+void launch_far_side(const EvalArgs &a, bool f64, const FarItem *items, int32_t nitems, int32_t block_size,
+                     hipStream_t s);
+void launch_far_finish(const EvalArgs &a, const FarItem *items, int32_t nitems, int32_t block_size, hipStream_t s);
 // per system: U_N and the total U after the near part and U*, the kinetic
 // energy from the far kernel's partials, and the second Nose-Hoover half
 // step of xi when stepping with that thermostat
