@@ -434,6 +434,11 @@ __device__ __forceinline__ void far_finish(const EvalArgs &a, CSys *sp, int32_t 
     const int64_t n = a.N;
     double ke = 0.0;
     if (valid) {
+        // the velocity and the near force are loaded before the far force is
+        // stored (the stores could alias them for the compiler), so that
+        // their loads overlap the ones before
+        double vv[3] = {a.cur.v[i], a.cur.v[n + i], a.cur.v[2 * n + i]};
+        const double fn[3] = {a.Fn[i], a.Fn[n + i], a.Fn[2 * n + i]};
         if (sp->zmode != 0) {
             const double qi = a.cur.q[i], c = sp->zf * qi;
             const double *M = a.dipole + 3 * sys;
@@ -446,10 +451,9 @@ __device__ __forceinline__ void far_finish(const EvalArgs &a, CSys *sp, int32_t 
         a.Ff[i] = Fx;
         a.Ff[n + i] = Fy;
         a.Ff[2 * n + i] = Fz;
-        double vv[3] = {a.cur.v[i], a.cur.v[n + i], a.cur.v[2 * n + i]};
         if (a.kick) {
             // closing half kick of the velocity-Verlet step
-            const double f[3] = {a.Fn[i] + Fx, a.Fn[n + i] + Fy, a.Fn[2 * n + i] + Fz};
+            const double f[3] = {fn[0] + Fx, fn[1] + Fy, fn[2] + Fz};
             bool bad = false;
             for (int d = 0; d < 3; ++d) {
                 bad |= !isfinite(f[d]);
