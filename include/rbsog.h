@@ -319,6 +319,33 @@ rbsog_status rbsog_debug_cells(rbsog_ctx *ctx, int32_t sys, int32_t *cell_start,
 rbsog_status rbsog_debug_neighbors(rbsog_ctx *ctx, int32_t sys, int64_t *row_ptr, int32_t *cols,
                                    int64_t cap);
 
+/* Structure factor of one set of point charges, without a context (Sec. 3.1:
+ * rho(k_e) = sum_j q_j e^{i k_e.r_j}, k_e = 2 pi (m_x/L_x, m_y/L_y, m_z/L_z);
+ * Sec. 3.4: the one reduction of the method, which a run sharded over several
+ * devices computes per device over its own particles and then sums).
+ *   n          particles, 1 <= n <= 2^31-1
+ *   x          device, n x 3 FP64 positions (row-major; wrapped into the box)
+ *   q          device, n FP64 charges
+ *   box        host, 3 side lengths > 0
+ *   n_k        wave vectors, >= 1
+ *   m          device, n_k x 3 int32 integer vectors m_e (k_e = 2 pi m_e / L)
+ *   precision  RBSOG_FP64: FP64 fractional coordinates, FP64 sin/cos of the
+ *              phase m.s - rint(m.s), FP64 sums; RBSOG_FP32C: the phase
+ *              m.u mod 2^32 on the 32-bit fixed-point coordinates of the
+ *              rule above, hardware FP32 sin/cos, FP32 sums over runs of 32
+ *              particles added in FP64
+ *   rho_re, rho_im  device, n_k doubles each, written
+ *   stream     hipStream_t to launch on (NULL: the null stream)
+ * Asynchronous on `stream`; the result is deterministic (partial sums over
+ * particle chunks, added in a fixed order).  Non-finite positions or charges
+ * give unspecified values.  The partial sums live in device memory allocated
+ * and freed on `stream` for the call.  E_ARG for sizes out of range or a null
+ * pointer, E_OOM if the partial sums cannot be allocated, E_DEVICE if a launch
+ * fails; the message is at rbsog_last_error(NULL). */
+rbsog_status rbsog_structure_factor(int64_t n, const double *x, const double *q, const double *box, int64_t n_k,
+                                    const int32_t *m, int32_t precision, double *rho_re, double *rho_im,
+                                    void *stream);
+
 /* Per-kernel timing with HIP events on the context's stream.  enable != 0
  * starts recording (and clears the totals).  rbsog_profile_read returns the
  * name, summed milliseconds and launch count of kernel idx (E_ARG past the

@@ -17,43 +17,22 @@
 #include <vector>
 
 #include "rbsog_internal.h"
+#include "rbsog_math.h"
 
 using namespace rbsog;
 
 namespace {
 
-thread_local std::string g_init_error;
+// message of the latest failure without a context (a fixed buffer: setting
+// it allocates nothing, so the entry points that must not allocate use it too)
+thread_local char g_init_error[512] = "";
+
+void set_init_error(const char *msg) {
+    std::snprintf(g_init_error, sizeof g_init_error, "%s", msg);
+}
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kTwo32 = 4294967296.0;
-
-// ---------------------------------------------------------------------------
-// Philox4x32-10 (Salmon et al., SC'11): counter-based generator used by the
-// k sampler and the Maxwellian velocity draw.
-struct Philox {
-    static void block(uint32_t c[4], uint32_t k0, uint32_t k1) {
-        for (int r = 0; r < 10; ++r) {
-            const uint64_t a = (uint64_t)0xD2511F53u * c[0];
-            const uint64_t b = (uint64_t)0xCD9E8D57u * c[2];
-            const uint32_t y0 = (uint32_t)(b >> 32) ^ c[1] ^ k0;
-            const uint32_t y1 = (uint32_t)b;
-            const uint32_t y2 = (uint32_t)(a >> 32) ^ c[3] ^ k1;
-            const uint32_t y3 = (uint32_t)a;
-            c[0] = y0; c[1] = y1; c[2] = y2; c[3] = y3;
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-    }
-    // Two 53-bit uniforms in [0, 1) from counter (idx_lo, idx_hi, stream, lane).
-    static void uniform2(uint64_t seed, uint32_t stream, uint64_t idx, uint32_t lane, double &a, double &b) {
-        uint32_t c[4] = {(uint32_t)idx, (uint32_t)(idx >> 32), stream, lane};
-        block(c, (uint32_t)seed, (uint32_t)(seed >> 32));
-        const uint64_t w0 = ((uint64_t)c[1] << 32) | c[0];
-        const uint64_t w1 = ((uint64_t)c[3] << 32) | c[2];
-        a = (double)(w0 >> 11) * 0x1.0p-53;
-        b = (double)(w1 >> 11) * 0x1.0p-53;
-    }
-};
 
 // ---------------------------------------------------------------------------
 // Metropolis-Hastings independence chain over nonzero m (Sec. 3.3).
@@ -134,6 +113,20 @@ struct SysHost {
 };
 
 }  // namespace
+
+namespace rbsog {
+// Records the message of a failure that has no context (rbsog_last_error(NULL)
+// returns it) and returns the status; formats into a fixed buffer.
+rbsog_status fail_noctx(rbsog_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    set_init_error(buf);
+    return st;
+}
+}  // namespace rbsog
 
 struct rbsog_ctx {
     int32_t nsys = 0;
@@ -249,7 +242,7 @@ rbsog_status fail(rbsog_ctx *c, rbsog_status st, const char *fmt, ...) {
         c->err = buf;
         if (st == RBSOG_E_DEVICE || st == RBSOG_E_OOM) c->poisoned = true;
     } else {
-        g_init_error = buf;
+        set_init_error(buf);
     }
     return st;
 }
@@ -315,24 +308,13 @@ double normaliser_S(const std::vector<double> &omega, const std::vector<double> 
 }
 
 // ---- sampler -------------------------------------------------------------------
-double target_weight(const SysHost *c, const int32_t m[3]) {
-    const double t = (double)m[0] * m[0] / (c->box[0] * c->box[0]) + (double)m[1] * m[1] / (c->box[1] * c->box[1]) +
-                     (double)m[2] * m[2] / (c->box[2] * c->box[2]);
-    double acc = 0.0;
-    for (int l = 0; l <= c->M; ++l)
-        acc += c->omega[l] * c->s[l] * c->s[l] * c->s[l] * std::exp(-kPi * kPi * c->s[l] * c->s[l] * t);
-    return acc;
-}
-
-double proposal_1d(int32_t m, double a) {
-    if (m == 0) return std::erf(0.5 * a);
-    const double am = std::fabs((double)m);
-    return 0.5 * (std::erfc((am - 0.5) * a) - std::erfc((am + 0.5) * a));
-}
-
+// The host chain: Metropolis-Hastings independence sampler over nonzero m
+// (Sec. 3.3) on Philox stream 0 of the system's key; the proposal, target and
+// acceptance are the shared ones of rbsog_math.h (the device chains use them too).
 void mh_extend(SysHost *c, int64_t count, std::vector<int32_t> &out) {
     MHChain &ch = c->chain;
     const double s0 = c->s[0];
+    const int G = (int)c->s.size();
     double sd[3], a[3];
     for (int d = 0; d < 3; ++d) {
         sd[d] = c->box[d] / (std::sqrt(2.0) * kPi * s0);
@@ -340,19 +322,14 @@ void mh_extend(SysHost *c, int64_t count, std::vector<int32_t> &out) {
     }
     int64_t made = 0;
     while (made < count) {
-        double u1, u2, u3, u4, ua, ub;
-        Philox::uniform2(c->seed, 0, ch.attempt, 0, u1, u2);
-        Philox::uniform2(c->seed, 0, ch.attempt, 1, u3, u4);
-        Philox::uniform2(c->seed, 0, ch.attempt, 2, ua, ub);
-        ++ch.attempt;
-        const double r1 = std::sqrt(-2.0 * std::log(1.0 - u1));
-        const double r2 = std::sqrt(-2.0 * std::log(1.0 - u3));
-        const double z[3] = {r1 * std::cos(2.0 * kPi * u2), r1 * std::sin(2.0 * kPi * u2), r2 * std::cos(2.0 * kPi * u4)};
         int32_t cand[3];
-        for (int d = 0; d < 3; ++d) cand[d] = (int32_t)std::round(z[d] * sd[d]);
-        if (cand[0] == 0 && cand[1] == 0 && cand[2] == 0) continue;
-        const double pc = target_weight(c, cand);
-        const double qc = proposal_1d(cand[0], a[0]) * proposal_1d(cand[1], a[1]) * proposal_1d(cand[2], a[2]);
+        double ua;
+        const bool nonzero = rmath::mh_propose(c->seed, 0, ch.attempt, sd, cand, ua);
+        ++ch.attempt;
+        if (!nonzero) continue;
+        const double pc = rmath::target_weight(c->omega.data(), c->s.data(), G, c->box, cand);
+        const double qc =
+            rmath::proposal_1d(cand[0], a[0]) * rmath::proposal_1d(cand[1], a[1]) * rmath::proposal_1d(cand[2], a[2]);
         if (!ch.started) {
             std::copy(cand, cand + 3, ch.m);
             ch.p = pc;
@@ -360,7 +337,7 @@ void mh_extend(SysHost *c, int64_t count, std::vector<int32_t> &out) {
             ch.started = true;
             continue;
         }
-        if (ua < (pc * ch.qprop) / (ch.p * qc)) {
+        if (rmath::mh_accept(ua, pc, qc, ch.p, ch.qprop)) {
             std::copy(cand, cand + 3, ch.m);
             ch.p = pc;
             ch.qprop = qc;
@@ -1493,7 +1470,7 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     work_caps(c, near_cap, rho_cap, far_cap, part_cap, chunk_cap);
 
     auto bail = [&](rbsog_status st) {
-        g_init_error = c->err;
+        set_init_error(c->err.c_str());
         rbsog_destroy(c);
         return st;
     };
@@ -1881,11 +1858,8 @@ rbsog_status rbsog_set_velocities(rbsog_ctx *c, const double *v, double T, uint6
     for (const SysHost &h : c->sys) {
         double mean[3] = {0, 0, 0};
         for (int64_t i = h.p0; i < h.p0 + h.n; ++i) {
-            double u1, u2, u3, u4;
-            Philox::uniform2(seed, 1, (uint64_t)i, 0, u1, u2);
-            Philox::uniform2(seed, 1, (uint64_t)i, 1, u3, u4);
-            const double r1 = std::sqrt(-2.0 * std::log(1.0 - u1)), r2 = std::sqrt(-2.0 * std::log(1.0 - u3));
-            const double z[3] = {r1 * std::cos(2 * kPi * u2), r1 * std::sin(2 * kPi * u2), r2 * std::cos(2 * kPi * u4)};
+            double z[3];
+            rmath::normals3(seed, 1, (uint64_t)i, z);
             for (int d = 0; d < 3; ++d) {
                 vv[3 * i + d] = sd * z[d];
                 mean[d] += sd * z[d];
@@ -2162,7 +2136,7 @@ rbsog_status rbsog_sync(rbsog_ctx *c) {
     return RBSOG_OK;
 }
 
-const char *rbsog_last_error(const rbsog_ctx *c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+const char *rbsog_last_error(const rbsog_ctx *c) { return c ? c->err.c_str() : g_init_error; }
 
 const char *rbsog_status_string(rbsog_status s) {
     switch (s) {

@@ -15,60 +15,14 @@
 // within one system of the batch.  Partial sums of rho are reduced in a
 // fixed order, so the result is identical from run to run.
 #include "rbsog_internal.h"
+#include "rbsog_math.h"
 
 namespace rbsog {
 
 namespace {
 
-constexpr double kTwoPi = 6.283185307179586476925286766559;
 
-// sin(2 pi f), cos(2 pi f) for |f| <= 1/2 in FP64: quadrant q = rint(4f),
-// r = f - q/4 in [-1/8, 1/8], Taylor series of sin/cos(2 pi r) through
-// degree 15/16 (truncation below 5e-17), then rotation by q quarter turns.
-__device__ __forceinline__ void sincos2pi(double f, double *s, double *c) {
-    constexpr double T = kTwoPi;
-    constexpr double T2 = T * T;
-    constexpr double S0 = T;
-    constexpr double S1 = -S0 * T2 / 6.0;
-    constexpr double S2 = -S1 * T2 / 20.0;
-    constexpr double S3 = -S2 * T2 / 42.0;
-    constexpr double S4 = -S3 * T2 / 72.0;
-    constexpr double S5 = -S4 * T2 / 110.0;
-    constexpr double S6 = -S5 * T2 / 156.0;
-    constexpr double S7 = -S6 * T2 / 210.0;
-    constexpr double C1 = -T2 / 2.0;
-    constexpr double C2 = -C1 * T2 / 12.0;
-    constexpr double C3 = -C2 * T2 / 30.0;
-    constexpr double C4 = -C3 * T2 / 56.0;
-    constexpr double C5 = -C4 * T2 / 90.0;
-    constexpr double C6 = -C5 * T2 / 132.0;
-    constexpr double C7 = -C6 * T2 / 182.0;
-    constexpr double C8 = -C7 * T2 / 240.0;
-    const double qd = rint(4.0 * f);
-    const double r = fma(-0.25, qd, f);
-    const double z = r * r;
-    double ps = fma(z, S7, S6);
-    ps = fma(z, ps, S5);
-    ps = fma(z, ps, S4);
-    ps = fma(z, ps, S3);
-    ps = fma(z, ps, S2);
-    ps = fma(z, ps, S1);
-    ps = fma(z, ps, S0);
-    const double sr = r * ps;
-    double pc = fma(z, C8, C7);
-    pc = fma(z, pc, C6);
-    pc = fma(z, pc, C5);
-    pc = fma(z, pc, C4);
-    pc = fma(z, pc, C3);
-    pc = fma(z, pc, C2);
-    pc = fma(z, pc, C1);
-    const double cr = fma(z, pc, 1.0);
-    const int q = ((int)qd) & 3;
-    const double a = (q & 1) ? cr : sr;
-    const double b = (q & 1) ? sr : cr;
-    *s = (q & 2) ? -a : a;
-    *c = ((q + 1) & 2) ? -b : b;
-}
+using rmath::sincos2pi;
 
 typedef const SysDev __attribute__((address_space(4))) CSys;
 // k records are read-only within the kernels that stream them: reading them

@@ -10,6 +10,7 @@
 // particles only as far as they drifted.  The list-build kernels read the
 // rebuild flag first and return at once when it is clear.
 #include "rbsog_internal.h"
+#include "rbsog_math.h"
 
 namespace rbsog {
 
@@ -30,39 +31,11 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
     if (i < n) p[i] = v;
 }
 
-// Philox4x32-10 (Salmon et al., SC'11) and two 53-bit uniforms in [0, 1) from
-// counter (index_lo, index_hi, stream, lane), key (seed_lo, seed_hi).
-__device__ __forceinline__ void philox_uniform2(uint64_t seed, uint32_t stream, uint64_t index, uint32_t lane,
-                                                double &a, double &b) {
-    uint32_t c0 = (uint32_t)index, c1 = (uint32_t)(index >> 32), c2 = stream, c3 = lane;
-    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t y0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t y1 = (uint32_t)p1;
-        const uint32_t y2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
-        const uint32_t y3 = (uint32_t)p0;
-        c0 = y0; c1 = y1; c2 = y2; c3 = y3;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    a = (double)((((uint64_t)c1 << 32) | c0) >> 11) * 0x1.0p-53;
-    b = (double)((((uint64_t)c3 << 32) | c2) >> 11) * 0x1.0p-53;
-}
-
 // Three standard normals for particle `id` at thermostat step `step`
-// (Box-Muller on two pairs of uniforms, lanes 0 and 1 of stream 2).
+// (Box-Muller on lanes 0 and 1 of Philox stream 2, counter (id, step)).
 __device__ __forceinline__ void thermo_normals(uint64_t seed, int64_t step, int32_t id, double xi[3]) {
     const uint64_t idx = ((uint64_t)step << 32) | (uint32_t)id;
-    double u1, u2, u3, u4;
-    philox_uniform2(seed, 2, idx, 0, u1, u2);
-    philox_uniform2(seed, 2, idx, 1, u3, u4);
-    const double r1 = sqrt(-2.0 * log(1.0 - u1)), r2 = sqrt(-2.0 * log(1.0 - u3));
-    const double t1 = 6.283185307179586476925286766559 * u2, t2 = 6.283185307179586476925286766559 * u4;
-    xi[0] = r1 * cos(t1);
-    xi[1] = r1 * sin(t1);
-    xi[2] = r2 * cos(t2);
+    rmath::normals3(seed, 2, idx, xi);
 }
 
 // Stage the next P_s wave vectors of every system (Algorithm 1: the sequence

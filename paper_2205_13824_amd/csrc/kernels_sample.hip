@@ -9,50 +9,11 @@
 // advances every chain by P states: chain c's states form batch c of the
 // next lambda evaluations.
 #include "rbsog_internal.h"
+#include "rbsog_math.h"
 
 namespace rbsog {
 
 namespace {
-
-constexpr double kPiS = 3.14159265358979323846;
-
-__device__ __forceinline__ void philox_u2(uint64_t seed, uint32_t stream, uint64_t index, uint32_t lane, double &a,
-                                          double &b) {
-    uint32_t c0 = (uint32_t)index, c1 = (uint32_t)(index >> 32), c2 = stream, c3 = lane;
-    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t y0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t y1 = (uint32_t)p1;
-        const uint32_t y2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
-        const uint32_t y3 = (uint32_t)p0;
-        c0 = y0; c1 = y1; c2 = y2; c3 = y3;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    a = (double)((((uint64_t)c1 << 32) | c0) >> 11) * 0x1.0p-53;
-    b = (double)((((uint64_t)c3 << 32) | c2) >> 11) * 0x1.0p-53;
-}
-
-// p(m) ~ F~(2 pi m / L) up to constants: sum_l omega_l s_l^3 e^{-pi^2 s_l^2 |m/L|^2}
-__device__ double target_weight(const SampDev &d, const int32_t m[3]) {
-    const double t = (double)m[0] * m[0] / (d.L[0] * d.L[0]) + (double)m[1] * m[1] / (d.L[1] * d.L[1]) +
-                     (double)m[2] * m[2] / (d.L[2] * d.L[2]);
-    double acc = 0.0;
-    for (int l = 0; l < d.G; ++l) {
-        const double s = d.s[l];
-        acc += d.omega[l] * s * s * s * exp(-kPiS * kPiS * s * s * t);
-    }
-    return acc;
-}
-
-// proposal pmf of one component: (1/2)[erf((m+1/2) a) - erf((m-1/2) a)], a = pi s_0 / L
-__device__ double proposal_1d(int32_t m, double a) {
-    if (m == 0) return erf(0.5 * a);
-    const double am = fabs((double)m);
-    return 0.5 * (erfc((am - 0.5) * a) - erfc((am + 0.5) * a));
-}
 
 // One block per (system, chain).  The proposals of an independence sampler do
 // not depend on the chain's state: the block first evaluates a window of
@@ -92,19 +53,12 @@ __global__ __launch_bounds__(kWin) void k_refill(const SampDev *__restrict__ sam
         const uint64_t base = ch.attempt;
         {
             Attempt at;
-            double u1, u2, u3, u4, ua, ub;
+            double ua;
             const uint64_t t = base + threadIdx.x;
-            philox_u2(d.seed, stream, t, 0, u1, u2);
-            philox_u2(d.seed, stream, t, 1, u3, u4);
-            philox_u2(d.seed, stream, t, 2, ua, ub);
-            const double r1 = sqrt(-2.0 * log(1.0 - u1));
-            const double r2 = sqrt(-2.0 * log(1.0 - u3));
-            const double z[3] = {r1 * cos(2.0 * kPiS * u2), r1 * sin(2.0 * kPiS * u2), r2 * cos(2.0 * kPiS * u4)};
-            for (int k = 0; k < 3; ++k) at.m[k] = (int32_t)round(z[k] * d.sd[k]);
-            at.nonzero = (at.m[0] | at.m[1] | at.m[2]) != 0;
-            at.p = at.nonzero ? target_weight(d, at.m) : 0.0;
-            at.q = at.nonzero ? proposal_1d(at.m[0], d.a[0]) * proposal_1d(at.m[1], d.a[1]) *
-                                    proposal_1d(at.m[2], d.a[2])
+            at.nonzero = rmath::mh_propose(d.seed, stream, t, d.sd, at.m, ua) ? 1 : 0;
+            at.p = at.nonzero ? rmath::target_weight(d.omega, d.s, d.G, d.L, at.m) : 0.0;
+            at.q = at.nonzero ? rmath::proposal_1d(at.m[0], d.a[0]) * rmath::proposal_1d(at.m[1], d.a[1]) *
+                                    rmath::proposal_1d(at.m[2], d.a[2])
                               : 0.0;
             at.ua = ua;
             win[threadIdx.x] = at;
@@ -123,7 +77,7 @@ __global__ __launch_bounds__(kWin) void k_refill(const SampDev *__restrict__ sam
                     ch.started = 1;
                     continue;
                 }
-                if (at.ua < (at.p * ch.qprop) / (ch.p * at.q)) {
+                if (rmath::mh_accept(at.ua, at.p, at.q, ch.p, ch.qprop)) {
                     for (int k = 0; k < 3; ++k) ch.m[k] = at.m[k];
                     ch.p = at.p;
                     ch.qprop = at.q;
