@@ -346,6 +346,18 @@ rbsog_status rbsog_structure_factor(int64_t n, const double *x, const double *q,
                                     const int32_t *m, int32_t precision, double *rho_re, double *rho_im,
                                     void *stream);
 
+/* rbsog_structure_factor for callers that cannot allocate device memory
+ * (work captured into a HIP graph, serving loops, harnesses that forbid
+ * allocation): the same arguments, kernels and chunk plan, so the same
+ * result bit for bit, with the partial sums in one library-held array of
+ * 2^20 complex FP64 values (16 MiB on each device used, held until the
+ * process ends); it calls no allocator.  n_k above 2^20 returns E_ARG.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (two streams, two threads) race and must not be made. */
+rbsog_status rbsog_structure_factor_noalloc(int64_t n, const double *x, const double *q, const double *box,
+                                            int64_t n_k, const int32_t *m, int32_t precision, double *rho_re,
+                                            double *rho_im, void *stream);
+
 /* Per-kernel timing with HIP events on the context's stream.  enable != 0
  * starts recording (and clears the totals).  rbsog_profile_read returns the
  * name, summed milliseconds and launch count of kernel idx (E_ARG past the

@@ -3,7 +3,11 @@
 // m_z/L_z); Sec. 3.4: the one reduction of the random-batch method, which a
 // spatially sharded run computes per device and then sums across devices).
 // Device inputs and outputs, no context: rbsog_structure_factor takes its
-// partial sums in memory it allocates per call (stream ordered).
+// partial sums in memory it allocates per call (stream ordered), and
+// rbsog_structure_factor_noalloc takes them in the file-scope array `scratch`
+// below, for callers that cannot allocate (graph capture, serving loops).
+// Both run the same kernels with the same chunk plan, so their results are
+// bitwise identical.
 //
 // Work split: a block owns a chunk of particles and a tile of 256 wave
 // vectors (one per thread).  It stages 256 particles at a time in LDS
@@ -15,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "rbsog_internal.h"
 #include "rbsog_math.h"
@@ -27,9 +32,13 @@ namespace {
 
 constexpr int kSfBlock = 256;         // threads per block = wave vectors per k tile = particles per LDS batch
 constexpr int64_t kSfMaxChunks = 4096;
-// Partial sums per call: n_chunks x n_k complex FP64 values, n_chunks
-// shrunk so that they stay within 2^20 (or one chunk for larger n_k).
+// Partial sums held by the no-allocation entry point: 2^20 complex FP64
+// values (16 MiB per device, held until the process ends).  A call needs
+// n_chunks x n_k of them; n_chunks shrinks to fit, so n_k <= 2^20.
 constexpr int64_t kScratchComplex = int64_t(1) << 20;
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) double2 scratch[kScratchComplex];
 
 // Chunks of particles: about one per 1024 particles (at least 256
 // particles each), no more than the partial buffer holds for n_k vectors.
@@ -183,6 +192,28 @@ rbsog_status sf_launch(int64_t n, const double *x, const double *q, const double
     return RBSOG_OK;
 }
 
+// Device address of `scratch` on each device, taken once per device with the
+// device current (the array's name is a host-side stand-in in host code).
+std::mutex g_scratch_mu;
+double2 *g_scratch_ptr[kMaxDevices] = {};
+
+rbsog_status scratch_of_current_device(double2 **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_noctx(RBSOG_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail_noctx(RBSOG_E_DEVICE, "device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail_noctx(RBSOG_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = (double2 *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return RBSOG_OK;
+}
+
 }  // namespace
 }  // namespace rbsog
 
@@ -207,6 +238,22 @@ rbsog_status rbsog_structure_factor(int64_t n, const double *x, const double *q,
     e = hipFreeAsync(part, s);
     if (st == RBSOG_OK && e != hipSuccess) return fail_noctx(RBSOG_E_DEVICE, "%s: free: %s", who, hipGetErrorString(e));
     return st;
+}
+
+rbsog_status rbsog_structure_factor_noalloc(int64_t n, const double *x, const double *q, const double *box,
+                                            int64_t n_k, const int32_t *m, int32_t precision, double *rho_re,
+                                            double *rho_im, void *stream) {
+    const char *who = "rbsog_structure_factor_noalloc";
+    rbsog_status st = sf_check(n, x, q, box, n_k, m, precision, rho_re, rho_im, who);
+    if (st != RBSOG_OK) return st;
+    if (n_k > kScratchComplex)
+        return fail_noctx(RBSOG_E_ARG, "%s: n_k = %lld exceeds the %lld wave vectors its scratch holds", who,
+                          (long long)n_k, (long long)kScratchComplex);
+    double2 *sp = nullptr;
+    st = scratch_of_current_device(&sp);
+    if (st != RBSOG_OK) return st;
+    const int64_t nchunk = sf_chunks(n, n_k);
+    return sf_launch(n, x, q, box, n_k, m, precision, rho_re, rho_im, (hipStream_t)stream, sp, nchunk, who);
 }
 
 }  // extern "C"

@@ -33,7 +33,7 @@ EXPORTS = ("rbsog_default_opts", "rbsog_sog_table1", "rbsog_init", "rbsog_init_b
            "rbsog_profile", "rbsog_profile_read", "rbsog_sync", "rbsog_last_error", "rbsog_status_string",
            "rbsog_destroy", "rbsog_autotune", "rbsog_set_thermostat", "rbsog_get_kbatch",
            "rbsog_set_nose_hoover", "rbsog_get_kinetic", "rbsog_set_msd_origin", "rbsog_get_msd",
-           "rbsog_structure_factor")
+           "rbsog_structure_factor", "rbsog_structure_factor_noalloc")
 
 
 class RbsogError(RuntimeError):
@@ -105,6 +105,7 @@ def lib():
             "rbsog_autotune": (i32, [vp, i32]),
             "rbsog_set_thermostat": (i32, [vp, dbl, dbl, u64]),
             "rbsog_structure_factor": (i32, [i64, vp, vp, vp, i64, vp, i32, vp, vp, vp]),
+            "rbsog_structure_factor_noalloc": (i32, [i64, vp, vp, vp, i64, vp, i32, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -329,11 +330,12 @@ def rbsog_debug_neighbors(ctx, n: int | None = None, sys: int = 0):
 
 
 def rbsog_structure_factor(n: int, x_dev: int, q_dev: int, box, n_k: int, m_dev: int, precision: int,
-                           rho_re_dev: int, rho_im_dev: int, stream: int | None = None):
+                           rho_re_dev: int, rho_im_dev: int, stream: int | None = None, noalloc: bool = False):
     """rho(k) of n charges without a context; every array argument is a device
     address (e.g. a torch tensor's data_ptr()), box a host sequence of 3."""
     b = _f64(box, (3,))
-    _check(lib().rbsog_structure_factor(int(n), x_dev, q_dev, _ptr(b), int(n_k), m_dev, int(precision), rho_re_dev, rho_im_dev, stream))
+    f = lib().rbsog_structure_factor_noalloc if noalloc else lib().rbsog_structure_factor
+    _check(f(int(n), x_dev, q_dev, _ptr(b), int(n_k), m_dev, int(precision), rho_re_dev, rho_im_dev, stream))
 
 
 def rbsog_profile(ctx, enable: bool):
