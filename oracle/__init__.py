@@ -85,8 +85,21 @@ def lib():
         L.orc_mh_sample.argtypes = [_dp, c_int, _dp, _dp, c_u64, c_u32, c_i64, c_i64, _i32p,
                                     ctypes.POINTER(c_dbl)]
         L.orc_mh_sample.restype = c_int
+        L.orc_far_realspace_cut.argtypes = [c_i64, _dp, _dp, _dp, c_int, _dp, _dp, c_dbl, c_i64, _i64p, _dp]
+        L.orc_max_threads.argtypes = []
+        L.orc_max_threads.restype = c_int
+        L.orc_set_threads.argtypes = [c_int]
         _lib = L
     return _lib
+
+
+def max_threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(lib().orc_max_threads())
+
+
+def set_threads(t: int) -> None:
+    lib().orc_set_threads(int(t))
 
 
 def _f64(a, shape=None):
@@ -392,6 +405,62 @@ def gauss_realspace_force(pos, q, box, omega_l, s_l, nimg, targets):
     F = np.zeros((t.size, 3))
     lib().orc_gauss_realspace_force(pos.shape[0], pos, _f64(q), _f64(box), float(omega_l), float(s_l),
                                     int(nimg), t.size, t, F)
+    return F
+
+
+def far_realspace_cut(pos, q, box, omega, s, targets, tail: float = 37.0):
+    """Far force on the targets of the Gaussians (omega_l, s_l) summed over
+    periodic images in real space out to sqrt(tail) s_l (rbsog_oracle.c)."""
+    pos = _f64(pos, (-1, 3))
+    omega = _f64(omega, (-1,))
+    s = _f64(s, (-1,))
+    assert omega.size == s.size and 0 < s.size <= 64
+    t = np.ascontiguousarray(targets, dtype=np.int64)
+    F = np.zeros((t.size, 3))
+    lib().orc_far_realspace_cut(pos.shape[0], pos, _f64(q), _f64(box), s.size, omega, s, float(tail), t.size, t, F)
+    return F
+
+
+def kvectors_half(smin: float, box, tail: float = 37.0) -> np.ndarray:
+    """One of each pair +-m (m != 0) with smin^2 k^2 / 4 <= tail: first nonzero
+    component positive."""
+    box = np.asarray(box, dtype=np.float64)
+    kmax = 2.0 * math.sqrt(tail) / smin
+    mmax = [int(math.floor(kmax * L / (2.0 * math.pi))) for L in box]
+    gx, gy, gz = np.meshgrid(*[np.arange(-mm, mm + 1) for mm in mmax], indexing="ij")
+    m = np.stack([gx.ravel(), gy.ravel(), gz.ravel()], axis=1)
+    k = 2.0 * math.pi * m / box
+    keep = (np.sum(k * k, axis=1) * smin ** 2 / 4.0 <= tail)
+    keep &= (m[:, 0] > 0) | ((m[:, 0] == 0) & (m[:, 1] > 0)) | ((m[:, 0] == 0) & (m[:, 1] == 0) & (m[:, 2] > 0))
+    return np.ascontiguousarray(m[keep], dtype=np.int32)
+
+
+def far_split(pos, q, box, sog: SOG, targets, n_real: int, tail: float = 37.0):
+    """The full far force (every k != 0) on the targets, Gaussian by Gaussian
+    through the Poisson identity (Sec. 3.3): the n_real narrowest Gaussians as
+    real-space image sums out to sqrt(tail) s_l, the wider ones as their
+    Fourier series over k != 0 with s_l^2 k^2 / 4 <= tail, each pair +-k once
+    with twice its weight (rho(-k) = conj rho(k) gives both the same term):
+      F_i = -(q_i / V) sum_k 2 w(k) k Im(e^{-i k.r_i} rho(k)),
+      w(k) = pi^{3/2} sum_{l >= n_real} omega_l s_l^3 exp(-s_l^2 k^2 / 4).
+    For systems too large for the plain Fourier sum (far_full)."""
+    box = np.asarray(box, dtype=np.float64)
+    t = np.asarray(targets, dtype=np.int64)
+    F = np.zeros((t.size, 3))
+    if n_real > 0:
+        if math.sqrt(tail) * sog.s[n_real - 1] > 8.0 * float(box.max()):
+            raise ValueError("real-space radius of the widest real-space Gaussian exceeds 8 box lengths")
+        F += far_realspace_cut(pos, q, box, sog.omega[:n_real], sog.s[:n_real], t, tail)
+    if n_real <= sog.M:
+        m = kvectors_half(sog.s[n_real], box, tail)
+        k = 2.0 * math.pi * m / box
+        k2 = np.sum(k * k, axis=1)
+        w = np.zeros(m.shape[0])
+        for l in range(n_real, sog.M + 1):
+            w += sog.omega[l] * sog.s[l] ** 3 * np.exp(-sog.s[l] ** 2 * k2 / 4.0)
+        w *= 2.0 * math.pi ** 1.5 / volume(box)
+        Fk, _, _, _ = far_kspace(pos, q, box, m, w, targets=t)
+        F += Fk
     return F
 
 

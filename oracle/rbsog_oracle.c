@@ -29,6 +29,7 @@
  * This file must be compiled with -ffp-contract=off.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -404,6 +405,107 @@ void orc_gauss_realspace_force(int64_t n, const double *pos, const double *q, co
 }
 
 /* ------------------------------------------------------------------------ */
+/* Far force on selected targets of the Gaussians l = 0..nl-1 (omega_l, s_l as
+ * given) summed over periodic images in real space, each out to the radius
+ * sqrt(tail) s_l, beyond which its terms are below exp(-tail) of its weight.
+ * This is the real-space side of the Poisson identity
+ *   sum_n exp(-|r + nL|^2/s^2) = (pi^{3/2} s^3/V) sum_k exp(-s^2 k^2/4) exp(i k.r)
+ * (Sec. 3.3; the k = 0 term is a constant and carries no force):
+ *   F_i = q_i sum_l omega_l sum_{(j, n): |d| < sqrt(tail) s_l} q_j (2/s_l^2) exp(-|d|^2/s_l^2) d,
+ *   d = r_i - r_j + n L   (j = i with n = 0 gives d = 0 and adds nothing).
+ * Candidates (j, n) come from a grid of cells of the box tiled periodically:
+ * every image of every cell within the widest radius of the target's cell is
+ * visited once.  Sums per target are compensated. */
+static int64_t floor_div(int64_t a, int64_t b) {
+    int64_t q = a / b;
+    if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+    return q;
+}
+
+void orc_far_realspace_cut(int64_t n, const double *pos, const double *q, const double *box, int nl,
+                           const double *omega, const double *s, double tail, int64_t nt, const int64_t *targets,
+                           double *F) {
+    double smax = 0.0;
+    for (int l = 0; l < nl; ++l) smax = s[l] > smax ? s[l] : smax;
+    const double R = sqrt(tail) * smax, R2 = R * R;
+    double *xw = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    int32_t nc[3];
+    double cw[3];
+    for (int d = 0; d < 3; ++d) {
+        int64_t k = (int64_t)floor(box[d] / (R / 16.0));
+        nc[d] = (int32_t)(k < 1 ? 1 : (k > 256 ? 256 : k));
+        cw[d] = box[d] / nc[d];
+    }
+    const int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
+    int64_t *cell_of = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *start = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c[3];
+        for (int d = 0; d < 3; ++d) {
+            double t = pos[3 * i + d] / box[d];
+            xw[3 * i + d] = (t - floor(t)) * box[d];
+            int64_t cd = (int64_t)floor(xw[3 * i + d] / cw[d]);
+            c[d] = cd < 0 ? 0 : (cd >= nc[d] ? nc[d] - 1 : cd);
+        }
+        cell_of[i] = c[0] + nc[0] * (c[1] + (int64_t)nc[1] * c[2]);
+        start[cell_of[i] + 1] += 1;
+    }
+    for (int64_t c = 0; c < ncell; ++c) start[c + 1] += start[c];
+    {
+        int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)ncell);
+        memcpy(fill, start, sizeof(int64_t) * (size_t)ncell);
+        for (int64_t i = 0; i < n; ++i) order[fill[cell_of[i]]++] = i;
+        free(fill);
+    }
+    double lim[64];
+    for (int l = 0; l < nl && l < 64; ++l) lim[l] = tail * s[l] * s[l];
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t i = targets[t];
+        const double *xi = xw + 3 * i;
+        int64_t ci[3], K[3];
+        for (int d = 0; d < 3; ++d) {
+            int64_t cd = (int64_t)floor(xi[d] / cw[d]);
+            ci[d] = cd < 0 ? 0 : (cd >= nc[d] ? nc[d] - 1 : cd);
+            K[d] = (int64_t)ceil(R / cw[d]) + 1;
+        }
+        nsum_t f[3] = {{0, 0}, {0, 0}, {0, 0}};
+        for (int64_t oz = -K[2]; oz <= K[2]; ++oz) {
+            const int64_t cz = ci[2] + oz, iz = floor_div(cz, nc[2]), mz = cz - iz * nc[2];
+            for (int64_t oy = -K[1]; oy <= K[1]; ++oy) {
+                const int64_t cy = ci[1] + oy, iy = floor_div(cy, nc[1]), my = cy - iy * nc[1];
+                for (int64_t ox = -K[0]; ox <= K[0]; ++ox) {
+                    const int64_t cx = ci[0] + ox, ix = floor_div(cx, nc[0]), mx = cx - ix * nc[0];
+                    const double shift[3] = {ix * box[0], iy * box[1], iz * box[2]};
+                    const int64_t cell = mx + nc[0] * (my + (int64_t)nc[1] * mz);
+                    for (int64_t p = start[cell]; p < start[cell + 1]; ++p) {
+                        const int64_t j = order[p];
+                        const double d0 = xi[0] - (xw[3 * j] + shift[0]);
+                        const double d1 = xi[1] - (xw[3 * j + 1] + shift[1]);
+                        const double d2 = xi[2] - (xw[3 * j + 2] + shift[2]);
+                        const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                        if (r2 >= R2) continue;
+                        double c = 0.0;
+                        for (int l = 0; l < nl; ++l)
+                            if (r2 < lim[l]) c += omega[l] * (2.0 / (s[l] * s[l])) * exp(-r2 / (s[l] * s[l]));
+                        c *= q[j];
+                        nadd(&f[0], c * d0);
+                        nadd(&f[1], c * d1);
+                        nadd(&f[2], c * d2);
+                    }
+                }
+            }
+        }
+        for (int d = 0; d < 3; ++d) F[3 * t + d] = q[i] * nval(&f[d]);
+    }
+    free(order);
+    free(start);
+    free(cell_of);
+    free(xw);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Classical Ewald summation (Sec. 2, eq. "splitting"), tinfoil boundary, used
  * only as an independent validator of the whole splitting on small systems.
  * Real-space part over images |n_d| <= nimg:
@@ -579,3 +681,8 @@ int orc_mh_sample(const double *box, int M, const double *omega, const double *s
     if (acc_rate) *acc_rate = nsamp > 0 ? (double)accepted / (double)nsamp : 0.0;
     return 0;
 }
+
+/* Threads of the OpenMP loops above (used to time the oracle on one core and
+ * on all cores; no arithmetic). */
+int orc_max_threads(void) { return omp_get_max_threads(); }
+void orc_set_threads(int t) { omp_set_num_threads(t > 0 ? t : 1); }

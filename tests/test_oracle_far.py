@@ -162,3 +162,84 @@ def test_rb_estimator_unbiased_with_lemma1_variance(orc):
     assert ratio < 6.0
     var_emp = ((acc - Ffull[None]) ** 2).sum(2).mean(0)
     assert abs(var_emp.sum() / var_pred.sum() - 1) < 0.08
+
+
+@pytest.mark.parametrize("box,rc,n", [((10.0, 10.0, 10.0), 3.0, 120), ((12.0, 9.0, 11.0), 2.9, 90),
+                                      ((16.0, 16.0, 16.0), 3.5, 200)])
+@pytest.mark.parametrize("n_real", [0, 1, 3, 5])
+def test_poisson_split_far_field_equals_full_fourier_sum(orc, box, rc, n, n_real):
+    # The large-system far field (Sec. 3.3, each Gaussian through the Poisson
+    # identity: the narrowest in real space with a radius cutoff over a cell
+    # grid of the periodically tiled box, the widest over half the k lattice)
+    # against the plain Fourier sum over every k != 0: two independent codes.
+    rng = np.random.default_rng(n + n_real)
+    box = np.asarray(box)
+    pos = rng.random((n, 3)) * box
+    q = np.where(np.arange(n) < n // 2, 1.0, -1.0)
+    sog = orc.sog_row2(rc)
+    t = np.arange(0, n, 7)
+    Ffull, _, _, _ = orc.far_full(pos, q, box, sog, targets=t)
+    Fs = orc.far_split(pos, q, box, sog, t, n_real)
+    assert relrms(Fs, Ffull) < 1e-12
+
+
+def test_poisson_split_real_space_alone_equals_image_sum(orc):
+    # The cutoff real-space sum of one Gaussian against the plain image sum
+    # over every image within the same reach (no cells, no cutoff).
+    pos, q, box = random_system(50, 9.0, 8)
+    sog = orc.sog_row2(3.0)
+    t = np.arange(0, 50, 5)
+    for l in (0, 2, 4):
+        Fc = orc.far_realspace_cut(pos, q, box, sog.omega[l:l + 1], sog.s[l:l + 1], t)
+        nimg = int(math.ceil(6.1 * sog.s[l] / 9.0)) + 1
+        Fi = orc.gauss_realspace_force(pos, q, box, sog.omega[l], sog.s[l], nimg, t)
+        # rounding of the O(omega_l / s_l) terms that cancel to the total
+        assert np.abs(Fc - Fi).max() < 1e-11 * np.abs(Fi).max() + 1e-12 * sog.omega[l] / sog.s[l]
+
+
+def _truncation_error(orc, sog_full_row, rc, M, pos, q, box):
+    """R^F(M) = |U_err^F / U*| of Theorem 1 summed directly: the Gaussians
+    l > M (nominal omega_l) over every k != 0 against the far energy of the
+    split truncated at M (Sec. 4.1, eqs. "UerrF" and "uF")."""
+    b, sig10, w0, _ = sog_full_row
+    sigma = sig10 * rc / 10.0
+    sog = orc.SOG(b, sigma, w0, M)
+    m = orc.kvectors_full(sog, box)
+    k = 2 * math.pi * m / box
+    k2 = (k * k).sum(1)
+    re, im = orc.structure_factor(pos, q, box, m)
+    rho2 = re * re + im * im
+    tail = np.zeros_like(k2)
+    for l in range(M + 1, M + 400):
+        om = math.sqrt(2.0 / math.pi) * math.log(b) / (sigma * b ** l)
+        s = math.sqrt(2.0) * b ** l * sigma
+        term = om * s ** 3 * np.exp(-s * s * k2 / 4.0)
+        tail += term
+        if term.max() < 1e-300:
+            break
+    V = orc.volume(box)
+    Uerr = math.pi ** 1.5 * float((tail * rho2).sum()) / (2 * V)
+    Uf = float((sog.Ftilde_vec(k2) * rho2).sum()) / (2 * V)
+    return abs(Uerr / Uf), orc.theorem1_bound(b, sigma, M, float(np.max(box)))
+
+
+@pytest.mark.parametrize("L,rc,n", [(10.0, 3.0, 200), (20.0, 3.0, 400), (30.0, 3.5, 300)])
+def test_theorem1_bound_holds_with_the_true_decay_rate(orc, L, rc, n):
+    # Theorem 1: R^F(M) <= b^{2M} exp(-2 (b^{2M} - 1) (pi b sigma / L)^2).
+    # Directly summed, the error stays below the bound for every M, and once
+    # the first omitted Gaussian dominates (M >= 4) the ratio bound / R^F no
+    # longer changes with M: the bound's exponent is the true decay rate (a
+    # dropped factor b, 2 or pi in it would make the ratio run away or fall
+    # below 1 within a few M).
+    pos, q, box = random_system(n, L, 17)
+    ratios = {}
+    for M in range(1, 9):
+        R, bound = _truncation_error(orc, ROW2, rc, M, pos, q, box)
+        if R < 1e-290:
+            break
+        assert R <= bound, (M, R, bound)
+        ratios[M] = bound / R
+    assert 4 in ratios and 5 in ratios
+    for M in sorted(ratios):
+        if M >= 4 and M + 1 in ratios:
+            assert abs(ratios[M + 1] / ratios[M] - 1.0) < 0.05, ratios
