@@ -262,6 +262,14 @@ rbsog_status rbsog_get_state(rbsog_ctx *ctx, double *pos, double *vel);
  * each, either may be NULL).  E_STATE if no evaluation has been made. */
 rbsog_status rbsog_get_forces(rbsog_ctx *ctx, double *F_near, double *F_far);
 
+/* The near and far parts of the latest force evaluation on m particles only,
+ * named by their caller indices (host ids[m], 0 <= id < n), without copying
+ * the whole system (sampled checks of large systems, observables of a few
+ * particles): F_near, F_far host m x 3 each, either may be NULL.  E_ARG for an
+ * index out of range, E_STATE if no evaluation has been made. */
+rbsog_status rbsog_get_forces_subset(rbsog_ctx *ctx, int64_t m, const int64_t *ids, double *F_near,
+                                     double *F_far);
+
 /* Copies the latest energies (host 4 * n_sys doubles: U_N, U*, U_self, U of
  * each system) and the structure factors of system sys (host P doubles each
  * for rho_re, rho_im; either may be NULL). */
@@ -293,19 +301,30 @@ typedef struct {
                                      (rbsog_step checks every 32 steps: when lists last under two
                                      steps it builds at every step, with r_c-wide cells and no list,
                                      and tries the caller's skin again after 4 to 32 checks) */
+    int32_t rho_ktile;            /* launch shapes in use (see rbsog_autotune): k tiles of 64 per
+                                     structure-factor block (largest over the systems), */
+    int32_t build_slots;          /* candidate slots of 64 per lane and test pass of the list build, */
+    int32_t cell_slots;           /* and of the fused cell kernel of the build-every-step mode */
 } rbsog_info_t;
 rbsog_status rbsog_info(rbsog_ctx *ctx, int32_t sys, rbsog_info_t *info);
 
-/* Tunes the launch shapes of the batch on the data of the latest evaluation:
- * particles per structure-factor chunk (256..8192) and particles per far
- * block (64, 128, 256), one phase after the other, each candidate timed over
- * `reps` launches of its kernel with HIP events; the fastest are kept.  Only
- * the structure-factor and far kernels run (the sequence is not consumed;
- * forces are recomputed for the same positions).  The choice is cached for the process under (GPU
- * architecture, precision, batch size, log2 n, P, log2 cells) and, if the
- * environment variable RBSOG_TUNE_CACHE names a file, appended to it; new
- * contexts of the same kind start from the cached shapes.
- * E_STATE before the first evaluation. */
+/* Tunes the launch shapes of the batch on the data of the latest evaluation,
+ * one phase after the other, each candidate timed over `reps` launches of its
+ * kernels with HIP events (after one untimed launch); the fastest are kept:
+ *   particles per structure-factor chunk (256..32768) and k tiles of 64 per
+ *   structure-factor block (1..16; the block's other waves split the chunk);
+ *   particles per far block (64, 128, 256), timed on the far kernels of the
+ *   near mode in use (after the near list, or beside the near part when every
+ *   step builds);
+ *   candidate slots of 64 per lane and test pass of the near kernel in use
+ *   (the list build: 2..4; the fused cell kernel of the build-every-step
+ *   mode: 2, 3), each trial a rebuild at the current positions.
+ * The sequence is not consumed and the positions do not move; the near and
+ * far forces are recomputed with the chosen shapes (same pairs, same data).
+ * The choice is cached for the process under (GPU architecture, precision,
+ * batch size, log2 n, P, log2 cells) and, if the environment variable
+ * RBSOG_TUNE_CACHE names a file, appended to it; new contexts of the same
+ * kind start from the cached shapes.  E_STATE before the first evaluation. */
 rbsog_status rbsog_autotune(rbsog_ctx *ctx, int32_t reps);
 
 /* Debug exports of system sys: the cell list of the latest near-list build
@@ -357,6 +376,25 @@ rbsog_status rbsog_structure_factor(int64_t n, const double *x, const double *q,
 rbsog_status rbsog_structure_factor_noalloc(int64_t n, const double *x, const double *q, const double *box,
                                             int64_t n_k, const int32_t *m, int32_t precision, double *rho_re,
                                             double *rho_im, void *stream);
+
+/* Debug record of the pairs the near kernels accept: with cap > 0 (at most
+ * 2^31-1) every later evaluation records, from the near kernel that runs it
+ * (the list build, the list pass or the fused cell kernel of the
+ * build-every-step mode), each pair that passes the pair rule of the header's
+ * conventions, as the kernel evaluates it; rbsog_step then launches kernel by
+ * kernel (no graphs).  cap = 0 stops recording and frees the record.
+ * rbsog_debug_pairs returns the latest evaluation's record for system sys as
+ * CSR over local ids (rows ascending i, columns ascending j; each pair in both
+ * orders), and in *kinds which kernels recorded: bit 0 the list build, bit 1
+ * the list pass, bit 2 the fused cell kernel.  E_STATE if recording is off or
+ * the record overflowed; E_ARG (row_ptr filled) if cap is smaller than the
+ * entry count.
+ * rbsog_debug_list returns the near list of the latest build (the pairs within
+ * r_c (1 + skin) by its FP32 test) in the same form; E_STATE at skin 0. */
+rbsog_status rbsog_debug_record_pairs(rbsog_ctx *ctx, int64_t cap);
+rbsog_status rbsog_debug_pairs(rbsog_ctx *ctx, int32_t sys, int32_t *kinds, int64_t *row_ptr, int32_t *cols,
+                               int64_t cap);
+rbsog_status rbsog_debug_list(rbsog_ctx *ctx, int32_t sys, int64_t *row_ptr, int32_t *cols, int64_t cap);
 
 /* Per-kernel timing with HIP events on the context's stream.  enable != 0
  * starts recording (and clears the totals).  rbsog_profile_read returns the

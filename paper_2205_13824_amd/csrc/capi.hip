@@ -60,17 +60,20 @@ enum { GV_STEP = 0, GV_STEP_E = 1, GV_MULTI = 2, GV_COUNT = 3 };
 
 enum Kid {
     K_KDQ, K_BIN, K_SCAN, K_SCATTER, K_SORTG, K_LIST, K_NEAR, K_NEARC, K_RHO, K_RHORED, K_FAR, K_SAMPLE, K_FARFIN,
-    K_COUNT
+    K_FARSIDE, K_COUNT
 };
 const char *kKernelNames[K_COUNT] = {"kick_drift_quantise", "bin", "scan_cell_counts", "cell_scatter", "sort_gather",
                                      "list_build", "near", "near_cells", "rho", "rho_reduce", "far",
-                                     "sample_refill", "far_finish"};
+                                     "sample_refill", "far_finish", "far_side"};
 
 
 // Launch shapes of the work lists (the tunable part of the plan).
 struct Tune {
-    int32_t rho_chunk = 0;  // particles per structure-factor chunk
-    int32_t far_block = 0;  // particles per far item (= block size)
+    int32_t rho_chunk = 0;    // particles per structure-factor chunk
+    int32_t far_block = 0;    // particles per far item (= block size)
+    int32_t rho_kt = 0;       // k tiles of 64 per structure-factor block (the other waves split the chunk); 0: 16
+    int32_t build_slots = 0;  // candidate slots per lane and test pass of the list build (2..4); 0: from occupancy
+    int32_t cell_slots = 0;   // the same for the fused cell kernel (2, 3); 0: from occupancy
 };
 
 // One system of the batch: host-side parameters, sampler and sequence.
@@ -185,6 +188,16 @@ struct rbsog_ctx {
     // kinetic energy per far item and wave, and per system
     double *kpart = nullptr, *kin = nullptr;
     double *msd = nullptr;  // mean-square displacement per system (rbsog_get_msd)
+    // debug record of the pairs the near kernels accept (rbsog_debug_record_pairs)
+    uint2 *dbg_pairs = nullptr;
+    int32_t *dbg_cnt = nullptr, *dbg_kind = nullptr;
+    int32_t dbg_cap = 0;
+    // rbsog_get_forces_subset: inverse id permutation, requested ids and the
+    // gathered forces (allocated at the first call, grown as needed)
+    int32_t *slot_of = nullptr;
+    int64_t *sub_ids = nullptr;
+    double *sub_out = nullptr;
+    int64_t sub_cap = 0;
     // Nose-Hoover thermostat: on, target temperature, tau, xi per system
     bool nh_on = false;
     double nh_T = 0.0, nh_tau = 0.0;
@@ -556,6 +569,10 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
     a.c2 = std::sqrt((1.0 - a.c1 * a.c1) * c->temp / c->mass);
     a.tseed = c->tseed;
     a.tstep = c->tstep;
+    a.dbg_pairs = c->dbg_pairs;
+    a.dbg_cnt = c->dbg_cnt;
+    a.dbg_cap = c->dbg_cap;
+    a.dbg_kind = c->dbg_kind;
     return a;
 }
 
@@ -573,6 +590,11 @@ rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt, bool kinetic, 
     const bool f64 = c->prec == RBSOG_FP64;
     EvalArgs a = make_args(c, stepping, dt);
     a.energy = energy ? 1 : 0;
+    if (c->dbg_pairs) {
+        // the record holds this evaluation's pairs only
+        launch_fill_i32(c->dbg_cnt, 1, 0, s);
+        launch_fill_i32(c->dbg_kind, 1, 0, s);
+    }
     TRY(timed(c, K_KDQ, [&] { launch_kdq(a, s); }));
     // the structure factor and its reduction need the copy of the positions
     // and the k records staged by the kick/drift kernel only: they run on the
@@ -606,7 +628,7 @@ rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt, bool kinetic, 
     } else {
         TRY(timed(c, K_RHO, [&] { launch_rho(a, f64, c->rho_items, c->n_rho, s); }));
         TRY(timed(c, K_RHORED, [&] { launch_rho_reduce(a, s); }));
-        if (far_side) TRY(timed(c, K_FAR, [&] { launch_far_side(a, f64, c->far_items, c->n_far, fb, s); }));
+        if (far_side) TRY(timed(c, K_FARSIDE, [&] { launch_far_side(a, f64, c->far_items, c->n_far, fb, s); }));
     }
     if (far_side) TRY(timed(c, K_FARFIN, [&] { launch_far_finish(a, c->far_items, c->n_far, fb, s); }));
     else TRY(timed(c, K_FAR, [&] { launch_far(a, f64, c->far_items, c->n_far, fb, s); }));
@@ -682,6 +704,7 @@ rbsog_status request_build(rbsog_ctx *c);
 rbsog_status upload_cell_items(rbsog_ctx *c);
 int32_t build_slots_for(const rbsog_ctx *c);
 int32_t cell_slots_for(const rbsog_ctx *c);
+void set_slots(rbsog_ctx *c);
 void set_geometry(SysHost &h, double skin);
 
 // Installs the cell grid and list thresholds of a skin on every system (the
@@ -691,8 +714,7 @@ rbsog_status apply_skin(rbsog_ctx *c, double skin) {
     for (SysHost &h : c->sys) set_geometry(h, skin);
     for (int32_t s = 0; s < c->nsys; ++s) TRY(upload_sysdev(c, s));
     c->skin_cur = skin;
-    c->build_slots = build_slots_for(c);
-    c->cell_slots = cell_slots_for(c);
+    set_slots(c);
     TRY(upload_cell_items(c));
     // each mode keeps its own step graph (the grid and items are read from
     // device tables; the build's slots per pass are fixed per mode)
@@ -1074,13 +1096,13 @@ void tune_cache_load_locked() {
     if (!path || !*path) return;
     FILE *f = std::fopen(path, "r");
     if (!f) return;
-    char key[256];
-    int b, d;
-    while (std::fscanf(f, "%255s %d %d", key, &b, &d) == 3) {
+    char line[512], key[256];
+    while (std::fgets(line, sizeof line, f)) {
         Tune t;
-        t.rho_chunk = b;
-        t.far_block = d;
-        g_tune_cache[key] = t;
+        // key rho_chunk far_block [rho_kt build_slots cell_slots]
+        if (std::sscanf(line, "%255s %d %d %d %d %d", key, &t.rho_chunk, &t.far_block, &t.rho_kt, &t.build_slots,
+                        &t.cell_slots) >= 3)
+            g_tune_cache[key] = t;
     }
     std::fclose(f);
 }
@@ -1101,7 +1123,8 @@ void tune_cache_store(const std::string &key, const Tune &t) {
     const char *path = std::getenv("RBSOG_TUNE_CACHE");
     if (!path || !*path) return;
     if (FILE *f = std::fopen(path, "a")) {
-        std::fprintf(f, "%s %d %d\n", key.c_str(), t.rho_chunk, t.far_block);
+        std::fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), t.rho_chunk, t.far_block, t.rho_kt, t.build_slots,
+                     t.cell_slots);
         std::fclose(f);
     }
 }
@@ -1120,7 +1143,7 @@ void build_work(rbsog_ctx *c, const Tune &t, std::vector<ListItem> &near, std::v
             near.push_back(ListItem{s, 0, h.p0 + i, h.p0 + std::min<int64_t>(h.n, i + kListHomes)});
         h.it1 = (int32_t)near.size();
         const int32_t ktiles = (h.P + 63) / 64;
-        h.kt = std::min(ktiles, 16);
+        h.kt = std::min(ktiles, t.rho_kt > 0 ? std::min(t.rho_kt, 16) : 16);
         h.streams = std::max(1, 16 / h.kt);
         const int32_t kgroups = (ktiles + h.kt - 1) / h.kt;
         h.nch = (int32_t)std::max<int64_t>(1, (h.n + chunk - 1) / chunk);
@@ -1157,9 +1180,10 @@ void work_caps(const rbsog_ctx *c, int64_t &near_cap, int64_t &rho_cap, int64_t 
     near_cap = rho_cap = far_cap = part_cap = chunk_cap = 0;
     for (const SysHost &h : c->sys) {
         near_cap += (h.n + kListHomes - 1) / kListHomes;
-        const int64_t ktiles = (h.P + 63) / 64, kt = std::min<int64_t>(ktiles, 16);
+        // the most items any k-tile grouping makes: one k tile per group
+        const int64_t ktiles = (h.P + 63) / 64;
         const int64_t nch = std::max<int64_t>(1, (h.n + 255) / 256);
-        rho_cap += ((ktiles + kt - 1) / kt) * nch;
+        rho_cap += ktiles * nch;
         part_cap += nch * h.P;
         chunk_cap += nch;
         far_cap += (h.n + 63) / 64;
@@ -1167,7 +1191,9 @@ void work_caps(const rbsog_ctx *c, int64_t &near_cap, int64_t &rho_cap, int64_t 
 }
 
 bool valid_tune(const Tune &t) {
-    return t.rho_chunk >= 256 && (t.far_block == 64 || t.far_block == 128 || t.far_block == 256);
+    return t.rho_chunk >= 256 && (t.far_block == 64 || t.far_block == 128 || t.far_block == 256) &&
+           t.rho_kt >= 0 && t.rho_kt <= 16 && (t.build_slots == 0 || (t.build_slots >= 2 && t.build_slots <= 4)) &&
+           (t.cell_slots == 0 || t.cell_slots == 2 || t.cell_slots == 3);
 }
 
 // Installs a set of shapes: builds and uploads the work lists and the
@@ -1188,6 +1214,7 @@ rbsog_status apply_tune(rbsog_ctx *c, const Tune &t) {
     HIPCHK(c, hipMemset(c->kpart, 0, (size_t)4 * c->n_far * sizeof(double)));
     for (int32_t s = 0; s < c->nsys; ++s) TRY(upload_sysdev(c, s));
     c->tune = t;
+    set_slots(c);
     drop_graphs(c);
     return RBSOG_OK;
 }
@@ -1214,48 +1241,104 @@ rbsog_status upload_cell_items(rbsog_ctx *c) {
     return RBSOG_OK;
 }
 
-// Times each phase's candidate shapes on the latest evaluation's data (the
-// structure-factor and far kernels only: no cursor moves, no state changes
-// beyond recomputing the same forces) and keeps the fastest.
+// Times each phase's candidate shapes on the latest evaluation's data and
+// keeps the fastest, one phase after the other: the structure factor's chunk
+// size and its k tiles per block (k_rho with k_rho_reduce, whose advance of
+// the sequence cursors is undone), the far block (k_far, or k_far_side
+// with k_far_finish when every step builds), the candidate slots per pass of
+// the near kernel in use (k_list_build with the near list, k_near_cells when
+// every step builds; each trial rebuilds at the current positions).  No
+// cursor moves and no state changes beyond recomputing the same forces with
+// the chosen shapes at the end (the build counter is restored).
 rbsog_status autotune_now(rbsog_ctx *c, int32_t reps) {
     if (c->evals == 0 || !c->forces_valid)
         return fail(c, RBSOG_E_STATE, "autotuning needs the forces of the current positions first");
     if (reps < 1) reps = 1;
     const bool f64 = c->prec == RBSOG_FP64;
-    EvalArgs a = make_args(c, false, 0.0);
-    a.rebuild = nullptr;  // the far kernel leaves the near-list flag alone
+    hipStream_t st = c->stream;
+    int64_t nbuild0 = 0;
+    HIPCHK(c, hipStreamSynchronize(st));
+    HIPCHK(c, hipMemcpy(&nbuild0, c->nbuild, sizeof nbuild0, hipMemcpyDeviceToHost));
     hipEvent_t e0 = get_event(c), e1 = get_event(c);
     if (!e0 || !e1) return fail(c, RBSOG_E_DEVICE, "hipEventCreate failed");
+    const bool every = !(c->skin_cur > 0.0);
+    // a full build at the current positions (the state is in cell order
+    // already, so the re-sort is the identity), its near kernel with `slots`
+    auto build = [&]() {
+        EvalArgs a = make_args(c, false, 0.0);
+        launch_bin(a, st);
+        launch_scan(a, st);
+        launch_cell_scatter(a, st);
+        launch_sort_gather(a, st);
+        return a;
+    };
+    enum { PH_CHUNK, PH_KT, PH_FAR, PH_SLOTS, PH_N };
+    // one timed launch of the phase's kernel(s) (summed over reps), after the
+    // set-up the trial needs
     auto time_of = [&](int phase, double &ms) -> rbsog_status {
-        auto launch = [&] {
-            if (phase == 1) launch_rho(a, f64, c->rho_items, c->n_rho, c->stream);
-            else launch_far(a, f64, c->far_items, c->n_far, c->tune.far_block, c->stream);
-        };
-        launch();
-        HIPCHK(c, hipEventRecord(e0, c->stream));
-        for (int r = 0; r < reps; ++r) launch();
-        HIPCHK(c, hipEventRecord(e1, c->stream));
-        HIPCHK(c, hipEventSynchronize(e1));
-        HIPCHK(c, hipGetLastError());
-        float f = 0.f;
-        HIPCHK(c, hipEventElapsedTime(&f, e0, e1));
-        ms = f / reps;
+        double tot = 0.0;
+        for (int r = 0; r <= reps; ++r) {
+            EvalArgs a = make_args(c, false, 0.0);
+            a.rebuild = nullptr;  // the far kernels leave the near-list flag alone
+            if (phase == PH_SLOTS) {
+                TRY(request_build(c));
+                a = build();
+            }
+            HIPCHK(c, hipEventRecord(e0, st));
+            if (phase == PH_CHUNK || phase == PH_KT) {
+                // the partial sums and their reduction: the chunk count sets both
+                launch_rho(a, f64, c->rho_items, c->n_rho, st);
+                launch_rho_reduce(a, st);
+            } else if (phase == PH_FAR) {
+                if (every) {
+                    launch_far_side(a, f64, c->far_items, c->n_far, c->tune.far_block, st);
+                    launch_far_finish(a, c->far_items, c->n_far, c->tune.far_block, st);
+                } else {
+                    launch_far(a, f64, c->far_items, c->n_far, c->tune.far_block, st);
+                }
+            } else if (every) {
+                launch_near_cells(a, f64, c->near_items, c->n_near, c->cell_slots, st);
+            } else {
+                launch_list_build(a, f64, c->list_items, c->n_list, c->build_slots, st);
+            }
+            HIPCHK(c, hipEventRecord(e1, st));
+            HIPCHK(c, hipEventSynchronize(e1));
+            HIPCHK(c, hipGetLastError());
+            float f = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&f, e0, e1));
+            if (r > 0) tot += f;  // the first launch warms caches and code
+        }
+        ms = tot / reps;
         return RBSOG_OK;
     };
     Tune best = c->tune;
     const Tune dflt = default_tune(c);
     int64_t nmax = 0;
-    for (const SysHost &h : c->sys) nmax = std::max(nmax, h.n);
-    std::vector<int32_t> chunks = {256, 512, 1024, 2048, 4096, 8192, dflt.rho_chunk};
-    std::vector<int32_t> blocks = {64, 128, 256};
-    for (int phase = 1; phase < 3; ++phase) {
-        const std::vector<int32_t> &cand = phase == 1 ? chunks : blocks;
+    int32_t ktmax = 1;
+    for (const SysHost &h : c->sys) {
+        nmax = std::max(nmax, h.n);
+        ktmax = std::max<int32_t>(ktmax, std::min<int32_t>(16, (h.P + 63) / 64));
+    }
+    const std::vector<int32_t> cand[PH_N] = {
+        {256, 512, 1024, 2048, 4096, 8192, 16384, 32768, dflt.rho_chunk},
+        {1, 2, 4, 8, 16},
+        {64, 128, 256},
+        every ? std::vector<int32_t>{2, 3} : std::vector<int32_t>{2, 3, 4}};
+    auto field = [](Tune &t, int phase) -> int32_t & {
+        return phase == PH_CHUNK ? t.rho_chunk
+               : phase == PH_KT  ? t.rho_kt
+               : phase == PH_FAR ? t.far_block
+                                 : t.build_slots;
+    };
+    for (int phase = 0; phase < PH_N; ++phase) {
         double best_ms = 1e30;
-        int32_t best_v = phase == 1 ? best.rho_chunk : best.far_block;
-        for (int32_t v : cand) {
-            if (phase == 1 && v > std::max<int64_t>(256, nmax)) continue;
+        int32_t best_v = 0;
+        for (int32_t v : cand[phase]) {
+            if (phase == PH_CHUNK && v > std::max<int64_t>(256, nmax)) continue;
+            if (phase == PH_KT && v > ktmax) continue;
             Tune t = best;
-            (phase == 1 ? t.rho_chunk : t.far_block) = v;
+            if (phase == PH_SLOTS) (every ? t.cell_slots : t.build_slots) = v;
+            else field(t, phase) = v;
             TRY(apply_tune(c, t));
             double ms = 0.0;
             TRY(time_of(phase, ms));
@@ -1264,15 +1347,38 @@ rbsog_status autotune_now(rbsog_ctx *c, int32_t reps) {
                 best_v = v;
             }
         }
-        (phase == 1 ? best.rho_chunk : best.far_block) = best_v;
+        if (best_v == 0) continue;
+        if (phase == PH_SLOTS) (every ? best.cell_slots : best.build_slots) = best_v;
+        else field(best, phase) = best_v;
     }
     c->ev_pool.push_back(e0);
     c->ev_pool.push_back(e1);
     TRY(apply_tune(c, best));
-    // the last trial's far pass left the forces of another shape: recompute
-    // them with the chosen shapes (same data, same arithmetic per particle)
-    launch_far(a, f64, c->far_items, c->n_far, c->tune.far_block, c->stream);
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // the trials left forces of other shapes: the structure factors (and U*),
+    // the near part and the far force again with the chosen ones (same data,
+    // same wave vectors, same pairs); then the sequence cursors, the build
+    // counter and the build flag as they were
+    {
+        EvalArgs ar = make_args(c, false, 0.0);
+        launch_rho(ar, f64, c->rho_items, c->n_rho, st);
+        launch_rho_reduce(ar, st);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipStreamSynchronize(st));
+        for (int32_t s = 0; s < c->nsys; ++s) TRY(upload_cursor(c, s));
+        TRY(request_build(c));
+        EvalArgs a = build();
+        if (every) launch_near_cells(a, f64, c->near_items, c->n_near, c->cell_slots, st);
+        else launch_list_build(a, f64, c->list_items, c->n_list, c->build_slots, st);
+        // the far force of the current order (the re-sorts above left the
+        // side copy of the positions out of step with the permutation)
+        a.rebuild = nullptr;
+        launch_far(a, f64, c->far_items, c->n_far, c->tune.far_block, st);
+        HIPCHK(c, hipGetLastError());
+        const int32_t zero = 0;
+        HIPCHK(c, hipMemcpyAsync(c->rebuild, &zero, sizeof zero, hipMemcpyHostToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(c->nbuild, &nbuild0, sizeof nbuild0, hipMemcpyHostToDevice, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+    }
     c->tuned = true;
     tune_cache_store(c->tune_key, best);
     return RBSOG_OK;
@@ -1355,6 +1461,13 @@ double stencil_mean(const rbsog_ctx *c, bool pairs) {
 
 int32_t build_slots_for(const rbsog_ctx *c) { return slots_for_mean(stencil_mean(c, false), 4); }
 int32_t cell_slots_for(const rbsog_ctx *c) { return slots_for_mean(stencil_mean(c, true), 3); }
+
+// Slots per pass of the near kernels: the tuned ones, else from the mean
+// stencil occupancy of the grid in use.
+void set_slots(rbsog_ctx *c) {
+    c->build_slots = c->tune.build_slots > 0 ? c->tune.build_slots : build_slots_for(c);
+    c->cell_slots = c->tune.cell_slots > 0 ? c->tune.cell_slots : cell_slots_for(c);
+}
 
 // A list build that only counts, at the initial positions: its largest item
 // count sizes the pair list.  It also puts the state in cell order; the
@@ -1452,8 +1565,7 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     }
     c->N = offsets[nsys];
     c->q_host.assign(q, q + c->N);
-    c->build_slots = build_slots_for(c);
-    c->cell_slots = cell_slots_for(c);
+    set_slots(c);
     std::vector<std::vector<float4>> tables;
     if (o.near_table) {
         tables.resize(nsys);
@@ -1786,7 +1898,7 @@ rbsog_status rbsog_step(rbsog_ctx *c, int64_t n_steps, double dt) {
         account_eval(c);
     }
     if (c->autotune && !c->tuned && !c->prof_on) TRY(autotune_now(c, 5));
-    const bool graphs = c->use_graphs && !c->prof_on && n_steps > 1;
+    const bool graphs = c->use_graphs && !c->prof_on && !c->dbg_pairs && n_steps > 1;
     for (int64_t k = 0; k < n_steps;) {
         // up to the next check of the build rate
         const int64_t chunk = std::min<int64_t>(n_steps - k, c->adapt_window - c->adapt_steps);
@@ -1981,6 +2093,43 @@ rbsog_status rbsog_get_forces(rbsog_ctx *c, double *F_near, double *F_far) {
     return RBSOG_OK;
 }
 
+rbsog_status rbsog_get_forces_subset(rbsog_ctx *c, int64_t m, const int64_t *ids, double *F_near, double *F_far) {
+    TRY(check_ctx(c));
+    if (c->evals == 0) return fail(c, RBSOG_E_STATE, "no force evaluation yet");
+    if (m < 0 || (m > 0 && !ids)) return fail(c, RBSOG_E_ARG, "need m >= 0 caller indices");
+    for (int64_t k = 0; k < m; ++k)
+        if (ids[k] < 0 || ids[k] >= c->N)
+            return fail(c, RBSOG_E_ARG, "index %lld of entry %lld out of range", (long long)ids[k], (long long)k);
+    if (m == 0) return RBSOG_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (!c->slot_of) TRY(dalloc(c, &c->slot_of, c->N));
+    if (m > c->sub_cap) {
+        for (void *p : {(void *)c->sub_ids, (void *)c->sub_out}) {
+            if (!p) continue;
+            c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), p), c->allocs.end());
+            (void)hipFree(p);
+        }
+        c->sub_ids = nullptr;
+        c->sub_out = nullptr;
+        c->sub_cap = 0;
+        TRY(dalloc(c, &c->sub_ids, m));
+        TRY(dalloc(c, &c->sub_out, 6 * m));
+        c->sub_cap = m;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->sub_ids, ids, (size_t)m * sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+    launch_subset_forces(make_args(c, false, 0.0), m, c->sub_ids, c->slot_of, c->sub_out, c->stream);
+    HIPCHK(c, hipGetLastError());
+    std::vector<double> out((size_t)(6 * m));
+    HIPCHK(c, hipMemcpyAsync(out.data(), c->sub_out, out.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int64_t k = 0; k < m; ++k)
+        for (int d = 0; d < 3; ++d) {
+            if (F_near) F_near[3 * k + d] = out[6 * k + d];
+            if (F_far) F_far[3 * k + d] = out[6 * k + 3 + d];
+        }
+    return RBSOG_OK;
+}
+
 rbsog_status rbsog_get_energy(rbsog_ctx *c, double *E) {
     TRY(check_ctx(c));
     if (c->evals == 0) return fail(c, RBSOG_E_STATE, "no force evaluation yet");
@@ -2023,6 +2172,7 @@ rbsog_status rbsog_info(rbsog_ctx *c, int32_t sys, rbsog_info_t *info) {
     TRY(check_sys(c, sys));
     if (!info) return fail(c, RBSOG_E_ARG, "info is null");
     const SysHost &h = c->sys[sys];
+    *info = rbsog_info_t{};
     info->S = h.S;
     info->volume = h.V;
     for (int d = 0; d < 3; ++d) info->ncell[d] = h.g.nc[d];
@@ -2036,6 +2186,9 @@ rbsog_status rbsog_info(rbsog_ctx *c, int32_t sys, rbsog_info_t *info) {
     HIPCHK(c, hipMemcpy(&info->list_builds, c->nbuild, sizeof(int64_t), hipMemcpyDeviceToHost));
     info->rho_chunk = c->tune.rho_chunk;
     info->far_block = c->tune.far_block;
+    for (const SysHost &h : c->sys) info->rho_ktile = std::max(info->rho_ktile, h.kt);
+    info->build_slots = c->build_slots;
+    info->cell_slots = c->cell_slots;
     info->tuned = c->tuned ? 1 : 0;
     return RBSOG_OK;
 }
@@ -2106,6 +2259,99 @@ rbsog_status rbsog_debug_neighbors(rbsog_ctx *c, int32_t sys, int64_t *row_ptr, 
     (void)hipFree(dcount);
     if (e != hipSuccess) return fail(c, RBSOG_E_DEVICE, "neighbour fill: %s", hipGetErrorString(e));
     return RBSOG_OK;
+}
+
+rbsog_status rbsog_debug_record_pairs(rbsog_ctx *c, int64_t cap) {
+    TRY(check_ctx(c));
+    if (cap < 0 || cap > (int64_t)INT32_MAX) return fail(c, RBSOG_E_ARG, "cap must be in [0, 2^31-1]");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (void *p : {(void *)c->dbg_pairs, (void *)c->dbg_cnt, (void *)c->dbg_kind}) {
+        if (!p) continue;
+        c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), p), c->allocs.end());
+        (void)hipFree(p);
+    }
+    c->dbg_pairs = nullptr;
+    c->dbg_cnt = c->dbg_kind = nullptr;
+    c->dbg_cap = 0;
+    drop_graphs(c);  // the captured steps hold the kernels' debug arguments
+    if (cap == 0) return RBSOG_OK;
+    TRY(dalloc(c, &c->dbg_pairs, cap));
+    TRY(dalloc(c, &c->dbg_cnt, 1));
+    TRY(dalloc(c, &c->dbg_kind, 1));
+    HIPCHK(c, hipMemset(c->dbg_cnt, 0, sizeof(int32_t)));
+    HIPCHK(c, hipMemset(c->dbg_kind, 0, sizeof(int32_t)));
+    c->dbg_cap = (int32_t)cap;
+    return RBSOG_OK;
+}
+
+// CSR over the local ids of system sys from (row, col) caller-index pairs:
+// rows ascending, columns ascending within a row.  E_ARG (row_ptr filled) if
+// cols holds fewer than the entries.
+static rbsog_status csr_of_pairs(rbsog_ctx *c, const SysHost &h, const std::vector<uint2> &pairs, int64_t *row_ptr,
+                                 int32_t *cols, int64_t cap) {
+    std::vector<std::pair<int32_t, int32_t>> loc;
+    loc.reserve(pairs.size());
+    for (const uint2 &p : pairs) {
+        const int64_t i = (int64_t)p.x - h.p0, j = (int64_t)p.y - h.p0;
+        if (i >= 0 && i < h.n && j >= 0 && j < h.n) loc.emplace_back((int32_t)i, (int32_t)j);
+    }
+    std::sort(loc.begin(), loc.end());
+    for (int64_t i = 0; i <= h.n; ++i) row_ptr[i] = 0;
+    for (const auto &e : loc) row_ptr[e.first + 1] += 1;
+    for (int64_t i = 0; i < h.n; ++i) row_ptr[i + 1] += row_ptr[i];
+    if (!cols || cap < (int64_t)loc.size())
+        return fail(c, RBSOG_E_ARG, "cols needs %lld entries", (long long)loc.size());
+    for (size_t k = 0; k < loc.size(); ++k) cols[k] = loc[k].second;
+    return RBSOG_OK;
+}
+
+rbsog_status rbsog_debug_pairs(rbsog_ctx *c, int32_t sys, int32_t *kinds, int64_t *row_ptr, int32_t *cols,
+                               int64_t cap) {
+    TRY(check_ctx(c));
+    TRY(check_sys(c, sys));
+    if (!c->dbg_pairs) return fail(c, RBSOG_E_STATE, "pair recording is off (rbsog_debug_record_pairs)");
+    if (!row_ptr) return fail(c, RBSOG_E_ARG, "row_ptr is null");
+    int32_t cnt = 0, kind = 0;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(&cnt, c->dbg_cnt, sizeof cnt, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(&kind, c->dbg_kind, sizeof kind, hipMemcpyDeviceToHost));
+    if (kinds) *kinds = kind;
+    if (cnt > c->dbg_cap)
+        return fail(c, RBSOG_E_STATE, "the record holds %d pairs, the evaluation accepted %d", c->dbg_cap, cnt);
+    std::vector<uint2> pairs((size_t)cnt);
+    if (cnt > 0) HIPCHK(c, hipMemcpy(pairs.data(), c->dbg_pairs, (size_t)cnt * sizeof(uint2), hipMemcpyDeviceToHost));
+    return csr_of_pairs(c, c->sys[sys], pairs, row_ptr, cols, cap);
+}
+
+rbsog_status rbsog_debug_list(rbsog_ctx *c, int32_t sys, int64_t *row_ptr, int32_t *cols, int64_t cap) {
+    TRY(check_ctx(c));
+    TRY(check_sys(c, sys));
+    if (!(c->skin_cur > 0.0) || !c->pairs) return fail(c, RBSOG_E_STATE, "no near list is kept (skin 0)");
+    if (c->evals == 0) return fail(c, RBSOG_E_STATE, "no force evaluation yet");
+    if (!row_ptr) return fail(c, RBSOG_E_ARG, "row_ptr is null");
+    const SysHost &h = c->sys[sys];
+    const int64_t nit = h.it1 - h.it0, seg = c->icap / kListWaves;
+    std::vector<int32_t> pc((size_t)(nit * kListWaves));
+    std::vector<uint2> ent((size_t)(nit * c->icap));
+    std::vector<int32_t> id;
+    TRY(current_ids(c, id));
+    HIPCHK(c, hipMemcpy(pc.data(), c->pcnt + (int64_t)h.it0 * kListWaves, pc.size() * sizeof(int32_t),
+                        hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(ent.data(), c->pairs + (int64_t)h.it0 * c->icap, ent.size() * sizeof(uint2),
+                        hipMemcpyDeviceToHost));
+    std::vector<uint2> pairs;
+    for (int64_t it = 0; it < nit; ++it) {
+        const int64_t t0 = h.p0 + it * kListHomes;
+        for (int w = 0; w < kListWaves; ++w) {
+            const int64_t base = it * c->icap + w * seg;
+            for (int32_t k = 0; k < pc[(size_t)(it * kListWaves + w)]; ++k) {
+                const uint2 e = ent[(size_t)(base + k)];
+                const int64_t home = t0 + w * (kListHomes / kListWaves) + e.x;
+                pairs.push_back(make_uint2((uint32_t)id[(size_t)home], (uint32_t)id[e.y]));
+            }
+        }
+    }
+    return csr_of_pairs(c, h, pairs, row_ptr, cols, cap);
 }
 
 rbsog_status rbsog_profile(rbsog_ctx *c, int32_t enable) {

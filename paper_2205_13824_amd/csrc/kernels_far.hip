@@ -17,6 +17,8 @@
 #include "rbsog_internal.h"
 #include "rbsog_math.h"
 
+#include <type_traits>
+
 namespace rbsog {
 
 namespace {
@@ -29,19 +31,59 @@ typedef const SysDev __attribute__((address_space(4))) CSys;
 // through the constant address space makes the uniform reads scalar loads
 typedef const KRec64 __attribute__((address_space(4))) CRec64;
 typedef const KRec32 __attribute__((address_space(4))) CRec32;
+// whole records (one scalar load each)
 __device__ __forceinline__ KRec64 ld(CRec64 *p) {
     KRec64 r;
     r.mx = p->mx; r.my = p->my; r.mz = p->mz;
-    r.ckx = p->ckx; r.cky = p->cky; r.ckz = p->ckz;
-    r.re = p->re; r.im = p->im;
+    r.phi = p->phi;
+    r.ax = p->ax; r.ay = p->ay; r.az = p->az;
+    r.pad = p->pad;
     return r;
 }
 __device__ __forceinline__ KRec32 ld(CRec32 *p) {
+    // four 8-byte words, so that the record is one 32-byte load
+    typedef const unsigned long long __attribute__((address_space(4))) CU64;
+    const unsigned long long w0 = ((CU64 *)p)[0], w1 = ((CU64 *)p)[1], w2 = ((CU64 *)p)[2], w3 = ((CU64 *)p)[3];
     KRec32 r;
-    r.mx = p->mx; r.my = p->my; r.mz = p->mz;
-    r.ckx = p->ckx; r.cky = p->cky; r.ckz = p->ckz;
-    r.re = p->re; r.im = p->im;
+    r.mx = (int32_t)(uint32_t)w0; r.my = (int32_t)(uint32_t)(w0 >> 32);
+    r.mz = (int32_t)(uint32_t)w1; r.phi = (uint32_t)(w1 >> 32);
+    r.ax = __uint_as_float((uint32_t)w2); r.ay = __uint_as_float((uint32_t)(w2 >> 32));
+    r.az = __uint_as_float((uint32_t)w3); r.pad = __uint_as_float((uint32_t)(w3 >> 32));
     return r;
+}
+
+// sin(2 pi f) for |f| <= 1/2 in FP64: reflected into |g| <= 1/4 (sin(pi - x)
+// = sin x), then the Taylor series of sin(2 pi g) through degree 23
+// (truncation below 2e-18 at |2 pi g| <= pi/2), Horner in g^2.
+__device__ __forceinline__ double sin2pi(double f) {
+    constexpr double T = rmath::kTwoPi;
+    constexpr double T2 = T * T;
+    constexpr double C0 = T;
+    constexpr double C1 = -C0 * T2 / 6.0;
+    constexpr double C2 = -C1 * T2 / 20.0;
+    constexpr double C3 = -C2 * T2 / 42.0;
+    constexpr double C4 = -C3 * T2 / 72.0;
+    constexpr double C5 = -C4 * T2 / 110.0;
+    constexpr double C6 = -C5 * T2 / 156.0;
+    constexpr double C7 = -C6 * T2 / 210.0;
+    constexpr double C8 = -C7 * T2 / 272.0;
+    constexpr double C9 = -C8 * T2 / 342.0;
+    constexpr double C10 = -C9 * T2 / 420.0;
+    constexpr double C11 = -C10 * T2 / 506.0;
+    const double g = f > 0.25 ? 0.5 - f : (f < -0.25 ? -0.5 - f : f);
+    const double z = g * g;
+    double p = fma(z, C11, C10);
+    p = fma(z, p, C9);
+    p = fma(z, p, C8);
+    p = fma(z, p, C7);
+    p = fma(z, p, C6);
+    p = fma(z, p, C5);
+    p = fma(z, p, C4);
+    p = fma(z, p, C3);
+    p = fma(z, p, C2);
+    p = fma(z, p, C1);
+    p = fma(z, p, C0);
+    return g * p;
 }
 
 // Uniform values loaded from memory: keep them scalar.
@@ -53,12 +95,23 @@ __device__ __forceinline__ int64_t rfl64(int64_t v) {
 }
 
 // Structure factor partial sums over the work items (grid-stride).  Item
-// (s, kg, chunk, [j0, j1)): wave w handles k tile (w % kt) of group kg for
-// particle stream (w / kt) of the slot range; the streams' sums are added in
-// a fixed order.  Blocks have 16 waves; kt * streams <= 16 per system.
+// (s, kg, chunk, [j0, j1)): wave w handles k tile (w % kt) of group kg (one
+// wave vector per lane) for particle stream (w / kt); kt * streams <= 16
+// waves per block.  The block stages kStage particles at a time in LDS (one
+// coalesced load per thread: fixed-point coordinates and FP32 charge in
+// FP32C, fractional coordinates and charge in FP64); stream st then reads
+// every streams-th staged particle from st on, each read an LDS broadcast to
+// the wave.  The streams' sums are added in a fixed order.
+constexpr int kStage = 1024;
+struct Stage64 {
+    double sx, sy, sz, q;
+};
+
 template <bool F64>
-__global__ __launch_bounds__(1024) void k_rho(EvalArgs a, const RhoItem *__restrict__ items, int32_t nitems) {
+__global__ __launch_bounds__(1024, F64 ? 1 : 8) void k_rho(EvalArgs a, const RhoItem *__restrict__ items, int32_t nitems) {
     __shared__ double2 red[1024];
+    __shared__ uint4 st32[F64 ? 1 : kStage];
+    __shared__ Stage64 st64[F64 ? kStage : 1];
     const int64_t n = a.N;
     // the state as the kick/drift kernel left it, in its copy: the re-sort of
     // the state into cell order may run meanwhile
@@ -66,8 +119,6 @@ __global__ __launch_bounds__(1024) void k_rho(EvalArgs a, const RhoItem *__restr
     const double *__restrict__ q = a.rs_q;
     const float *__restrict__ qf = a.rs_qf;
     const uint32_t *__restrict__ u = a.rs_u;
-    // the wave index is uniform: readfirstlane lets the particle loads below
-    // be scalar loads shared by the whole wave
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     for (int32_t itx = blockIdx.x; itx < nitems; itx += gridDim.x) {
@@ -80,74 +131,96 @@ __global__ __launch_bounds__(1024) void k_rho(EvalArgs a, const RhoItem *__restr
         const bool active = k < P && st < streams;
         const int32_t kk = k0 + (k < P ? k : 0);
         const int64_t j0 = rfl64(item.j0), j1 = rfl64(item.j1);
-        const int64_t per = (j1 - j0 + streams - 1) / streams;
-        const int64_t ja = st < streams ? (j0 + st * per < j1 ? j0 + st * per : j1) : j1;
-        const int64_t jb = ja + per < j1 ? ja + per : j1;
         double re = 0.0, im = 0.0;
-        // particles are consumed in groups of G so that the uniform loads of
-        // a group are issued together and their latency is paid once per group
-        constexpr int G = 8;
         if constexpr (F64) {
             const double mx = a.kb64[kk].mx, my = a.kb64[kk].my, mz = a.kb64[kk].mz;
             const double ix = sp->g.invL[0], iy = sp->g.invL[1], iz = sp->g.invL[2];
-            int64_t j = ja;
-            for (; j + G <= jb; j += G) {
-                double px[G], py[G], pz[G], pq[G];
-#pragma unroll
-                for (int h = 0; h < G; ++h) {
-                    px[h] = x[j + h]; py[h] = x[n + j + h]; pz[h] = x[2 * n + j + h]; pq[h] = q[j + h];
+            for (int64_t jb = j0; jb < j1; jb += kStage) {
+                const int cnt = (int)(j1 - jb < kStage ? j1 - jb : kStage);
+                if ((int)threadIdx.x < cnt) {
+                    const int64_t j = jb + threadIdx.x;
+                    st64[threadIdx.x] = Stage64{x[j] * ix, x[n + j] * iy, x[2 * n + j] * iz, q[j]};
                 }
+                __syncthreads();
+                if (st < streams) {
+                    // four staged particles read at once, then used
+                    int h = st;
+                    for (; h + 4 * streams <= cnt; h += 4 * streams) {
+                        Stage64 p[4];
 #pragma unroll
-                for (int h = 0; h < G; ++h) {
-                    const double t = mx * (px[h] * ix) + my * (py[h] * iy) + mz * (pz[h] * iz);
-                    double sn, cs;
-                    sincos2pi(t - rint(t), &sn, &cs);
-                    re = fma(pq[h], cs, re);
-                    im = fma(pq[h], sn, im);
+                        for (int g = 0; g < 4; ++g) p[g] = st64[h + g * streams];
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) {
+                            const double t = mx * p[g].sx + my * p[g].sy + mz * p[g].sz;
+                            double sn, cs;
+                            sincos2pi(t - rint(t), &sn, &cs);
+                            re = fma(p[g].q, cs, re);
+                            im = fma(p[g].q, sn, im);
+                        }
+                    }
+                    for (; h < cnt; h += streams) {
+                        const Stage64 p = st64[h];
+                        const double t = mx * p.sx + my * p.sy + mz * p.sz;
+                        double sn, cs;
+                        sincos2pi(t - rint(t), &sn, &cs);
+                        re = fma(p.q, cs, re);
+                        im = fma(p.q, sn, im);
+                    }
                 }
-            }
-            for (; j < jb; ++j) {
-                const double t = mx * (x[j] * ix) + my * (x[n + j] * iy) + mz * (x[2 * n + j] * iz);
-                double sn, cs;
-                sincos2pi(t - rint(t), &sn, &cs);
-                re = fma(q[j], cs, re);
-                im = fma(q[j], sn, im);
+                __syncthreads();
             }
         } else {
             const uint32_t mx = (uint32_t)a.kb32[kk].mx, my = (uint32_t)a.kb32[kk].my, mz = (uint32_t)a.kb32[kk].mz;
-            int64_t j = ja;
-            // FP32 partial sums over 32 particles, then accumulated in FP64
-            for (; j + 4 * G <= jb; j += 4 * G) {
-                float rf = 0.f, fi = 0.f;
-#pragma unroll
-                for (int h4 = 0; h4 < 4; ++h4) {
-                    uint32_t px[G], py[G], pz[G];
-                    float pq[G];
-#pragma unroll
-                    for (int h = 0; h < G; ++h) {
-                        const int64_t jj = j + h4 * G + h;
-                        px[h] = u[jj]; py[h] = u[n + jj]; pz[h] = u[2 * n + jj]; pq[h] = qf[jj];
-                    }
-#pragma unroll
-                    for (int h = 0; h < G; ++h) {
-                        const uint32_t t = mx * px[h] + my * py[h] + mz * pz[h];
-                        const float f = (float)(int32_t)t * 0x1.0p-32f;
-                        rf = fmaf(pq[h], __builtin_amdgcn_cosf(f), rf);
-                        fi = fmaf(pq[h], __builtin_amdgcn_sinf(f), fi);
-                    }
+            for (int64_t jb = j0; jb < j1; jb += kStage) {
+                const int cnt = (int)(j1 - jb < kStage ? j1 - jb : kStage);
+                if ((int)threadIdx.x < cnt) {
+                    const int64_t j = jb + threadIdx.x;
+                    st32[threadIdx.x] = make_uint4(u[j], u[n + j], u[2 * n + j], __float_as_uint(qf[j]));
                 }
-                re += rf;
-                im += fi;
+                __syncthreads();
+                if (st < streams) {
+                    // FP32 sums over runs of 32 of the stream's particles, then
+                    // FP64; eight staged particles are read at once, then used
+                    // (one stream: contiguous reads at fixed offsets)
+                    auto runs = [&](auto one) {
+                        constexpr bool ONE = decltype(one)::value;
+                        const int sd = ONE ? 1 : streams;
+                        int h = st;
+                        for (; h + 32 * sd <= cnt; h += 32 * sd) {
+                            float rf = 0.f, fi = 0.f;
+                            for (int g0 = 0; g0 < 32; g0 += 8) {
+                                uint4 p[8];
+#pragma unroll
+                                for (int g = 0; g < 8; ++g) p[g] = st32[h + (g0 + g) * sd];
+#pragma unroll
+                                for (int g = 0; g < 8; ++g) {
+                                    const uint32_t t = mx * p[g].x + my * p[g].y + mz * p[g].z;
+                                    const float f = rmath::phase_rev(t);
+                                    const float pq = __uint_as_float(p[g].w);
+                                    rf = fmaf(pq, __builtin_amdgcn_cosf(f), rf);
+                                    fi = fmaf(pq, __builtin_amdgcn_sinf(f), fi);
+                                }
+                            }
+                            re += rf;
+                            im += fi;
+                        }
+                        float rf = 0.f, fi = 0.f;
+                        for (; h < cnt; h += sd) {
+                            const uint4 p = st32[h];
+                            const uint32_t t = mx * p.x + my * p.y + mz * p.z;
+                            const float f = rmath::phase_rev(t);
+                            const float pq = __uint_as_float(p.w);
+                            rf = fmaf(pq, __builtin_amdgcn_cosf(f), rf);
+                            fi = fmaf(pq, __builtin_amdgcn_sinf(f), fi);
+                        }
+                        re += rf;
+                        im += fi;
+                    };
+                    if (streams == 1) runs(std::true_type{});
+                    else runs(std::false_type{});
+                }
+                __syncthreads();
             }
-            float rf = 0.f, fi = 0.f;
-            for (; j < jb; ++j) {
-                const uint32_t t = mx * u[j] + my * u[n + j] + mz * u[2 * n + j];
-                const float f = (float)(int32_t)t * 0x1.0p-32f;
-                rf = fmaf(qf[j], __builtin_amdgcn_cosf(f), rf);
-                fi = fmaf(qf[j], __builtin_amdgcn_sinf(f), fi);
-            }
-            re += rf;
-            im += fi;
         }
         red[threadIdx.x] = make_double2(re, im);
         __syncthreads();
@@ -246,11 +319,26 @@ __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
         if (lane == 0) {
             a.rho[r] = re;
             a.rho[a.K + r] = im;
-            a.kb64[r].re = re;
-            a.kb64[r].im = im;
-            a.kb32[r].re = (float)re;
-            a.kb32[r].im = (float)im;
-            a.ek[r] = 0.5 * a.wk[r] * (re * re + im * im);
+            const double w = a.wk[r];
+            a.ek[r] = 0.5 * w * (re * re + im * im);
+            // amplitude-phase record: phi = arg(rho) / (2 pi), a = w |rho| k
+            const double phi = atan2(im, re) * (1.0 / rmath::kTwoPi);
+            const double mag = hypot(re, im);
+            const double c = w * mag * rmath::kTwoPi;
+            const double ax = c * a.kb64[r].mx * sd.g.invL[0], ay = c * a.kb64[r].my * sd.g.invL[1],
+                         az = c * a.kb64[r].mz * sd.g.invL[2];
+            a.kb64[r].phi = phi;
+            a.kb64[r].ax = ax;
+            a.kb64[r].ay = ay;
+            a.kb64[r].az = az;
+            // FP32 form: phi in 2^-32 turns, plus 2^9 units: the FP32 phases of
+            // the structure factor and of the far force are each truncated
+            // to 2^-23 turns (half a unit of it low on average), which this
+            // offset takes back
+            a.kb32[r].phi = (uint32_t)(int64_t)rint(phi * 4294967296.0) + 512u;
+            a.kb32[r].ax = (float)ax;
+            a.kb32[r].ay = (float)ay;
+            a.kb32[r].az = (float)az;
         }
     }
     if (threadIdx.x == 0) nfin = 0;
@@ -299,8 +387,9 @@ __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
 }
 
 // Far force on particle i (the factor -q_i included) from its system's P
-// records, streamed as uniform loads: positions and charges from (u, qf) in
-// FP32C, (x, q) in FP64.
+// amplitude-phase records, streamed as uniform loads: one sine per record,
+// F_i = -q_i sum_e a_e sin(2 pi (phi_e - m_e.s_i)).  Positions and charges
+// from (u, qf) in FP32C (the phase phi - m.u mod 2^32), (x, q) in FP64.
 template <bool F64>
 __device__ __forceinline__ void far_sum(CSys *sp, CRec64 *kb64, CRec32 *kb32, int32_t P, int64_t n, int64_t i,
                                         const uint32_t *__restrict__ u, const float *__restrict__ qf,
@@ -310,7 +399,7 @@ __device__ __forceinline__ void far_sum(CSys *sp, CRec64 *kb64, CRec32 *kb32, in
     // records are consumed in groups so that their uniform loads overlap
     if constexpr (F64) {
         const double sx = x[i] * sp->g.invL[0], sy = x[n + i] * sp->g.invL[1], sz = x[2 * n + i] * sp->g.invL[2];
-        constexpr int G = 2;
+        constexpr int G = 4;
         int32_t e = 0;
         for (; e + G <= P; e += G) {
             KRec64 r[G];
@@ -318,24 +407,20 @@ __device__ __forceinline__ void far_sum(CSys *sp, CRec64 *kb64, CRec32 *kb32, in
             for (int h = 0; h < G; ++h) r[h] = ld(kb64 + e + h);
 #pragma unroll
             for (int h = 0; h < G; ++h) {
-                const double t = r[h].mx * sx + r[h].my * sy + r[h].mz * sz;
-                double sn, cs;
-                sincos2pi(t - rint(t), &sn, &cs);
-                const double v = cs * r[h].im - sn * r[h].re;
-                Fx = fma(r[h].ckx, v, Fx);
-                Fy = fma(r[h].cky, v, Fy);
-                Fz = fma(r[h].ckz, v, Fz);
+                const double t = r[h].phi - (r[h].mx * sx + r[h].my * sy + r[h].mz * sz);
+                const double v = sin2pi(t - rint(t));
+                Fx = fma(r[h].ax, v, Fx);
+                Fy = fma(r[h].ay, v, Fy);
+                Fz = fma(r[h].az, v, Fz);
             }
         }
         for (; e < P; ++e) {
             const KRec64 r = ld(kb64 + e);
-            const double t = r.mx * sx + r.my * sy + r.mz * sz;
-            double sn, cs;
-            sincos2pi(t - rint(t), &sn, &cs);
-            const double v = cs * r.im - sn * r.re;
-            Fx = fma(r.ckx, v, Fx);
-            Fy = fma(r.cky, v, Fy);
-            Fz = fma(r.ckz, v, Fz);
+            const double t = r.phi - (r.mx * sx + r.my * sy + r.mz * sz);
+            const double v = sin2pi(t - rint(t));
+            Fx = fma(r.ax, v, Fx);
+            Fy = fma(r.ay, v, Fy);
+            Fz = fma(r.az, v, Fz);
         }
         const double qi = q[i];
         Fx *= -qi; Fy *= -qi; Fz *= -qi;
@@ -353,12 +438,12 @@ __device__ __forceinline__ void far_sum(CSys *sp, CRec64 *kb64, CRec32 *kb32, in
                 for (int h = 0; h < G; ++h) r[h] = ld(kb32 + e + h4 * G + h);
 #pragma unroll
                 for (int h = 0; h < G; ++h) {
-                    const uint32_t t = (uint32_t)r[h].mx * ux + (uint32_t)r[h].my * uy + (uint32_t)r[h].mz * uz;
-                    const float f = (float)(int32_t)t * 0x1.0p-32f;
-                    const float v = __builtin_amdgcn_cosf(f) * r[h].im - __builtin_amdgcn_sinf(f) * r[h].re;
-                    fx = fmaf(r[h].ckx, v, fx);
-                    fy = fmaf(r[h].cky, v, fy);
-                    fz = fmaf(r[h].ckz, v, fz);
+                    const uint32_t t = r[h].phi - ((uint32_t)r[h].mx * ux + (uint32_t)r[h].my * uy +
+                                                   (uint32_t)r[h].mz * uz);
+                    const float v = __builtin_amdgcn_sinf(rmath::phase_rev(t));
+                    fx = fmaf(r[h].ax, v, fx);
+                    fy = fmaf(r[h].ay, v, fy);
+                    fz = fmaf(r[h].az, v, fz);
                 }
             }
             Fx += fx; Fy += fy; Fz += fz;
@@ -366,12 +451,11 @@ __device__ __forceinline__ void far_sum(CSys *sp, CRec64 *kb64, CRec32 *kb32, in
         float fx = 0.f, fy = 0.f, fz = 0.f;
         for (; e < P; ++e) {
             const KRec32 r = ld(kb32 + e);
-            const uint32_t t = (uint32_t)r.mx * ux + (uint32_t)r.my * uy + (uint32_t)r.mz * uz;
-            const float f = (float)(int32_t)t * 0x1.0p-32f;
-            const float v = __builtin_amdgcn_cosf(f) * r.im - __builtin_amdgcn_sinf(f) * r.re;
-            fx = fmaf(r.ckx, v, fx);
-            fy = fmaf(r.cky, v, fy);
-            fz = fmaf(r.ckz, v, fz);
+            const uint32_t t = r.phi - ((uint32_t)r.mx * ux + (uint32_t)r.my * uy + (uint32_t)r.mz * uz);
+            const float v = __builtin_amdgcn_sinf(rmath::phase_rev(t));
+            fx = fmaf(r.ax, v, fx);
+            fy = fmaf(r.ay, v, fy);
+            fz = fmaf(r.az, v, fz);
         }
         const double qi = -(double)qf[i];
         Fx = qi * (Fx + fx); Fy = qi * (Fy + fy); Fz = qi * (Fz + fz);

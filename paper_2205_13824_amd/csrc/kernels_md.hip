@@ -18,7 +18,6 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr double kTwo32 = 4294967296.0;
-constexpr double kTwoPi = 6.283185307179586476925286766559;
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
@@ -48,16 +47,14 @@ __device__ void stage_records(const EvalArgs &a, int64_t r) {
     const int64_t e = a.kcur[s] + (r - sd.k0);
     const int32_t mx = sd.kseq[3 * e], my = sd.kseq[3 * e + 1], mz = sd.kseq[3 * e + 2];
     const double w = sd.kw ? sd.kw[e] : sd.w_rb;
-    const double kx = kTwoPi * sd.g.invL[0] * mx, ky = kTwoPi * sd.g.invL[1] * my, kz = kTwoPi * sd.g.invL[2] * mz;
+    // phi and a follow from rho in the structure-factor reduction
     KRec64 h;
     h.mx = mx; h.my = my; h.mz = mz;
-    h.ckx = w * kx; h.cky = w * ky; h.ckz = w * kz;
-    h.re = 0.0; h.im = 0.0;
+    h.phi = 0.0; h.ax = 0.0; h.ay = 0.0; h.az = 0.0; h.pad = 0.0;
     a.kb64[r] = h;
     KRec32 f;
     f.mx = mx; f.my = my; f.mz = mz;
-    f.ckx = (float)h.ckx; f.cky = (float)h.cky; f.ckz = (float)h.ckz;
-    f.re = 0.f; f.im = 0.f;
+    f.phi = 0u; f.ax = 0.f; f.ay = 0.f; f.az = 0.f; f.pad = 0.f;
     a.kb32[r] = f;
     a.wk[r] = w;
 }
@@ -411,7 +408,36 @@ __global__ __launch_bounds__(kBlock) void k_sort_gather(EvalArgs a) {
     }
 }
 
+// Slot of every caller index (the inverse of the id permutation of the
+// current order), then the near and far forces of the requested indices.
+__global__ __launch_bounds__(kBlock) void k_invert_ids(int64_t N, const int32_t *__restrict__ id,
+                                                       int32_t *__restrict__ slot_of) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < N) slot_of[id[t]] = (int32_t)t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather_forces(int64_t N, int64_t m, const int64_t *__restrict__ ids,
+                                                          const int32_t *__restrict__ slot_of,
+                                                          const double *__restrict__ Fn, const double *__restrict__ Ff,
+                                                          double *__restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= m) return;
+    const int64_t t = slot_of[ids[k]];
+    for (int d = 0; d < 3; ++d) {
+        out[6 * k + d] = Fn[d * N + t];
+        out[6 * k + 3 + d] = Ff[d * N + t];
+    }
+}
+
 }  // namespace
+
+void launch_subset_forces(const EvalArgs &a, int64_t m, const int64_t *ids, int32_t *slot_of, double *out,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_invert_ids, dim3(grid_for(a.N, kBlock)), dim3(kBlock), 0, s, a.N, a.cur.id, slot_of);
+    if (m > 0)
+        hipLaunchKernelGGL(k_gather_forces, dim3(grid_for(m, kBlock)), dim3(kBlock), 0, s, a.N, m, ids, slot_of,
+                           a.Fn, a.Ff, out);
+}
 
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, p, n, v);

@@ -326,6 +326,16 @@ struct EvalLds {
 // entries are contiguous within a build pass, so forces are summed by a
 // segmented scan across the wave and the last lane of each segment adds the
 // total to the wave's accumulator of that home.
+// Debug record of the pairs a near kernel accepts (the debug launches
+// only): the caller indices of home and candidate, appended at an atomic
+// counter (entries past the capacity are counted, not written).
+struct PairRec {
+    const int32_t *id;  // caller index of each slot of the order the kernel reads
+    uint2 *out;
+    int32_t *cnt;
+    int32_t cap;
+};
+
 // Homes of one item in LDS, as the evaluation reads them; `hf` is the
 // accumulator set the pairs add to.
 template <bool F64>
@@ -336,6 +346,7 @@ struct HomeView {
     const double *hx[3];   // FP64 positions (FP64 form only)
     R *hf[3];
     bool we;               // sum the pair energies (else forces only)
+    const PairRec *rec;    // debug launches: where accepted pairs are recorded
 };
 
 // The candidate's data a pair needs: fixed-point coordinates, charge, and
@@ -364,8 +375,9 @@ __device__ __forceinline__ PairData<F64> load_pair(const uint32_t *__restrict__ 
 }
 
 // SELF: the ring may hold the home itself (the fused cell kernel's test does
-// not leave it out); such an entry is rejected here by its slot.
-template <bool F64, bool SELF = false>
+// not leave it out); such an entry is rejected here by its slot.  DBG: record
+// every accepted pair (debug launches).
+template <bool F64, bool SELF = false, bool DBG = false>
 __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>::type *co, const HomeView<F64> &L,
                                             const float4 *__restrict__ tbl, float rin2, CSys *csp,
                                              int lane, uint2 qe, bool have, const PairData<F64> &pd,
@@ -385,6 +397,12 @@ __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>:
         bool in = r2f <= g.band_lo_f;
         if (!in && r2f < g.band_hi_f) in = exact_in(g, dux, duy, duz);
         if constexpr (SELF) in = in && qe.y != h.w;
+        if constexpr (DBG) {
+            if (in) {
+                const int32_t k = atomicAdd(L.rec->cnt, 1);
+                if (k < L.rec->cap) L.rec->out[k] = make_uint2((uint32_t)L.rec->id[h.w], (uint32_t)L.rec->id[qe.y]);
+            }
+        }
         if (in) {
             R dx, dy, dz, qq;
             if constexpr (F64) {
@@ -501,14 +519,14 @@ __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>:
     }
 }
 
-template <bool F64, bool SELF = false>
+template <bool F64, bool SELF = false, bool DBG = false>
 __device__ __forceinline__ void eval_pair(const Geom &g, typename CoefOf<F64>::type *co, const HomeView<F64> &L,
                                           const uint32_t *__restrict__ su, const double *__restrict__ sx,
                                           const double *__restrict__ sq, const float *__restrict__ sqf, int64_t n,
                                           const float4 *__restrict__ tbl, float rin2, CSys *csp,
                                            int lane, uint2 qe, bool have, double &e) {
     const PairData<F64> pd = load_pair<F64>(su, sx, sq, sqf, n, qe, have);
-    eval_loaded<F64, SELF>(g, co, L, tbl, rin2, csp, lane, qe, have, pd, e);
+    eval_loaded<F64, SELF, DBG>(g, co, L, tbl, rin2, csp, lane, qe, have, pd, e);
 }
 
 template <bool F64, int Q>
@@ -547,7 +565,7 @@ __device__ __forceinline__ void copy_back(const EvalArgs &a, int64_t i0, int64_t
 }
 
 // Ring entries [head, head + count), one per lane.
-template <bool F64, int Q>
+template <bool F64, int Q, bool DBG>
 __device__ __forceinline__ void eval_ring(const uint2 *ring, const HomeView<F64> &hv, const Geom &g,
                                           typename CoefOf<F64>::type *co, const uint32_t *__restrict__ su,
                                           const double *__restrict__ sx, const double *__restrict__ sq,
@@ -556,14 +574,14 @@ __device__ __forceinline__ void eval_ring(const uint2 *ring, const HomeView<F64>
                                           double &e) {
     const bool have = lane < count;
     const uint2 qe = have ? ring[(head + lane) & (Q - 1)] : make_uint2(0u, 0u);
-    eval_pair<F64, true>(g, co, hv, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qe, have, e);
+    eval_pair<F64, true, DBG>(g, co, hv, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qe, have, e);
 }
 
 // Ring entries [head, head + count): written to the wave's list segment
 // (entries at or beyond its capacity are dropped; the caller flags the
 // overflow) and evaluated, one per lane, in the chunks of 64 in which the
 // list pass reads the segment.
-template <bool F64, int Q>
+template <bool F64, int Q, bool DBG>
 __device__ __forceinline__ void drain_ring(const BuildLds<F64, Q> &L, const HomeView<F64> &hv,
                                            uint2 *__restrict__ out, int64_t cap, const Geom &g,
                                            typename CoefOf<F64>::type *co, const uint32_t *__restrict__ su,
@@ -575,19 +593,27 @@ __device__ __forceinline__ void drain_ring(const BuildLds<F64, Q> &L, const Home
     const int idx = head + lane;
     const uint2 qe = have ? L.q[idx & (Q - 1)] : make_uint2(0u, 0u);
     if (have && out && idx < cap) out[idx] = qe;
-    eval_pair<F64>(g, co, hv, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qe, have, e);
+    eval_pair<F64, false, DBG>(g, co, hv, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qe, have, e);
 }
 
 // The build also evaluates this step's near forces from the same candidate
 // tests (every pair it lists passes through the ring, where the pair rule
 // and the force are applied), so a step with a build needs no list pass.
 // S: candidate slots per lane and pass (64 S candidates tested per pass)
-template <bool F64, int S>
+template <bool F64, int S, bool DBG = false>
 __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListItem *__restrict__ items,
                                                          int32_t nitems, int32_t nblk) {
     // the critical path's waves ahead of the structure factor's beside them
     __builtin_amdgcn_s_setprio(2);
     if (!*a.rebuild) return;
+    __shared__ PairRec rec;
+    if constexpr (DBG) {
+        if (threadIdx.x == 0) {
+            rec = PairRec{a.nxt.id, a.dbg_pairs, a.dbg_cnt, a.dbg_cap};
+            if (blockIdx.x == 0) atomicOr(a.dbg_kind, 1);
+        }
+        __syncthreads();
+    }
     const int64_t n = a.N;  // stride of the structure-of-arrays
     if ((int32_t)blockIdx.x >= nblk) {
         copy_back(a, (int64_t)(blockIdx.x - nblk) * blockDim.x + threadIdx.x, (int64_t)(gridDim.x - nblk) * blockDim.x);
@@ -613,6 +639,7 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
     hv.hu = L.hu;
     hv.hq = L.hq;
     hv.we = a.energy != 0;
+    hv.rec = DBG ? &rec : nullptr;
     for (int d = 0; d < 3; ++d) {
         hv.hx[d] = L.hx[d];
         hv.hf[d] = L.hf[d];
@@ -823,7 +850,7 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
                     static_assert(63 + kU * S * 64 < Q, "ring too small");
                     while (qn - qh >= 64) {
                         wave_sync();
-                        drain_ring<F64, Q>(L, hv, out, cap, g, co, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qh, 64,
+                        drain_ring<F64, Q, DBG>(L, hv, out, cap, g, co, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qh, 64,
                                            e);
                         qh += 64;
                     }
@@ -836,7 +863,7 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
     }
     wave_sync();
     if (qn > qh)
-        drain_ring<F64, Q>(L, hv, out, cap, g, co, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qh, qn - qh, e);
+        drain_ring<F64, Q, DBG>(L, hv, out, cap, g, co, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qh, qn - qh, e);
     wave_sync();
     if (lane < t_end - t) {
         const int64_t tt = t + lane;
@@ -854,7 +881,7 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
     }
 }
 
-template <bool F64>
+template <bool F64, bool DBG = false>
 __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListItem *__restrict__ items,
                                                         int32_t nitems, int32_t nblk) {
     // the critical path's waves ahead of the structure factor's beside them
@@ -864,6 +891,14 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
     __shared__ double es_w[kNW];
     // a build in this evaluation has evaluated the forces already
     if (*a.rebuild) return;
+    __shared__ PairRec rec;
+    if constexpr (DBG) {
+        if (threadIdx.x == 0) {
+            rec = PairRec{a.cur.id, a.dbg_pairs, a.dbg_cnt, a.dbg_cap};
+            if (blockIdx.x == 0) atomicOr(a.dbg_kind, 2);
+        }
+        __syncthreads();
+    }
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     Lds &L = lds[w];
@@ -914,6 +949,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
     hv.hu = L.hu;
     hv.hq = L.hq;
     hv.we = a.energy != 0;
+    hv.rec = DBG ? &rec : nullptr;
     for (int d = 0; d < 3; ++d) {
         hv.hx[d] = L.hx[d];
         hv.hf[d] = L.hf[d];
@@ -932,7 +968,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
         qe1 = qe2;
         qe2 = entry(c + 128);
         pd1 = load_pair<F64>(su, sx, sq, sqf, n, qe1, c + 64 + lane < cnt);
-        eval_loaded<F64>(g, co, hv, tbl, rin2, csp, lane, qe, have, pd, e);
+        eval_loaded<F64, false, DBG>(g, co, hv, tbl, rin2, csp, lane, qe, have, pd, e);
     }
     wave_sync();
     if (lane < H) {
@@ -967,12 +1003,20 @@ struct NearLds {
 // set (their 4 x 3 x 3 stencil), which halves the candidate set-up per home.
 // S: candidate slots per lane and pass.  Blocks past nblk copy the gathered
 // state back into `cur`.
-template <bool F64, int S>
+template <bool F64, int S, bool DBG = false>
 __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearItem *__restrict__ items,
                                                          int32_t nitems, int32_t nblk) {
     // the critical path's waves ahead of the structure factor's beside them
     __builtin_amdgcn_s_setprio(2);
     if (!*a.rebuild) return;
+    __shared__ PairRec rec;
+    if constexpr (DBG) {
+        if (threadIdx.x == 0) {
+            rec = PairRec{a.nxt.id, a.dbg_pairs, a.dbg_cnt, a.dbg_cap};
+            if (blockIdx.x == 0) atomicOr(a.dbg_kind, 4);
+        }
+        __syncthreads();
+    }
     if ((int32_t)blockIdx.x >= nblk) {
         copy_back(a, (int64_t)(blockIdx.x - nblk) * blockDim.x + threadIdx.x, (int64_t)(gridDim.x - nblk) * blockDim.x);
         return;
@@ -998,6 +1042,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
     hv.hu = L.hu;
     hv.hq = L.hq;
     hv.we = a.energy != 0;
+    hv.rec = DBG ? &rec : nullptr;
     for (int d = 0; d < 3; ++d) {
         hv.hx[d] = L.hx[d];
         hv.hf[d] = L.hf[d];
@@ -1233,7 +1278,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
                         static_assert(63 + kU * S * 64 < Q, "ring too small");
                         while (qn - qh >= 64) {
                             wave_sync();
-                            eval_ring<F64, Q>(L.q, hv, g, co, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qh, 64, e);
+                            eval_ring<F64, Q, DBG>(L.q, hv, g, co, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qh, 64, e);
                             qh += 64;
                         }
                     }
@@ -1245,7 +1290,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_cells(EvalArgs a, const NearI
         }
         // the queue refers to this batch's home slots: drain it, then write
         wave_sync();
-        if (qn > qh) eval_ring<F64, Q>(L.q, hv, g, co, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qh, qn - qh, e);
+        if (qn > qh) eval_ring<F64, Q, DBG>(L.q, hv, g, co, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qh, qn - qh, e);
         qn = 0;
         qh = 0;
         wave_sync();
@@ -1311,6 +1356,32 @@ __global__ void k_neighbors(EvalArgs a, int32_t sys, int64_t nloc, int64_t p0, c
     }
 }
 
+template <bool DBG>
+void list_build_launch(const EvalArgs &a, bool f64, int32_t slots, dim3 grid, dim3 block, const ListItem *items,
+                       int32_t nitems, int32_t nblk, hipStream_t s) {
+    if (f64) {
+        if (slots <= 2) hipLaunchKernelGGL((k_list_build<true, 2, DBG>), grid, block, 0, s, a, items, nitems, nblk);
+        else if (slots == 3) hipLaunchKernelGGL((k_list_build<true, 3, DBG>), grid, block, 0, s, a, items, nitems, nblk);
+        else hipLaunchKernelGGL((k_list_build<true, 4, DBG>), grid, block, 0, s, a, items, nitems, nblk);
+    } else {
+        if (slots <= 2) hipLaunchKernelGGL((k_list_build<false, 2, DBG>), grid, block, 0, s, a, items, nitems, nblk);
+        else if (slots == 3) hipLaunchKernelGGL((k_list_build<false, 3, DBG>), grid, block, 0, s, a, items, nitems, nblk);
+        else hipLaunchKernelGGL((k_list_build<false, 4, DBG>), grid, block, 0, s, a, items, nitems, nblk);
+    }
+}
+
+template <bool DBG>
+void near_cells_launch(const EvalArgs &a, bool f64, int32_t slots, dim3 grid, dim3 block, const NearItem *items,
+                       int32_t nitems, int32_t nblk, hipStream_t s) {
+    if (f64) {
+        if (slots <= 2) hipLaunchKernelGGL((k_near_cells<true, 2, DBG>), grid, block, 0, s, a, items, nitems, nblk);
+        else hipLaunchKernelGGL((k_near_cells<true, 3, DBG>), grid, block, 0, s, a, items, nitems, nblk);
+    } else {
+        if (slots <= 2) hipLaunchKernelGGL((k_near_cells<false, 2, DBG>), grid, block, 0, s, a, items, nitems, nblk);
+        else hipLaunchKernelGGL((k_near_cells<false, 3, DBG>), grid, block, 0, s, a, items, nitems, nblk);
+    }
+}
+
 }  // namespace
 
 void launch_list_build(const EvalArgs &a, bool f64, const ListItem *items, int32_t nitems, int32_t slots,
@@ -1322,15 +1393,8 @@ void launch_list_build(const EvalArgs &a, bool f64, const ListItem *items, int32
     if (nblk < 8) nblk = 8;
     const int64_t ncopy = std::min<int64_t>(1024, std::max<int64_t>(1, grid_for(a.N, 64 * kNW)));
     const dim3 grid((unsigned)(nblk + ncopy)), block(64 * kNW);
-    if (f64) {
-        if (slots <= 2) hipLaunchKernelGGL((k_list_build<true, 2>), grid, block, 0, s, a, items, nitems, nblk);
-        else if (slots == 3) hipLaunchKernelGGL((k_list_build<true, 3>), grid, block, 0, s, a, items, nitems, nblk);
-        else hipLaunchKernelGGL((k_list_build<true, 4>), grid, block, 0, s, a, items, nitems, nblk);
-    } else {
-        if (slots <= 2) hipLaunchKernelGGL((k_list_build<false, 2>), grid, block, 0, s, a, items, nitems, nblk);
-        else if (slots == 3) hipLaunchKernelGGL((k_list_build<false, 3>), grid, block, 0, s, a, items, nitems, nblk);
-        else hipLaunchKernelGGL((k_list_build<false, 4>), grid, block, 0, s, a, items, nitems, nblk);
-    }
+    if (a.dbg_pairs) list_build_launch<true>(a, f64, slots, grid, block, items, nitems, nblk, s);
+    else list_build_launch<false>(a, f64, slots, grid, block, items, nitems, nblk, s);
 }
 
 void launch_near_cells(const EvalArgs &a, bool f64, const NearItem *items, int32_t nitems, int32_t slots,
@@ -1342,13 +1406,8 @@ void launch_near_cells(const EvalArgs &a, bool f64, const NearItem *items, int32
     if (nblk < 8) nblk = 8;
     const int64_t ncopy = std::min<int64_t>(1024, std::max<int64_t>(1, grid_for(a.N, 64 * kNW)));
     const dim3 grid((unsigned)(nblk + ncopy)), block(64 * kNW);
-    if (f64) {
-        if (slots <= 2) hipLaunchKernelGGL((k_near_cells<true, 2>), grid, block, 0, s, a, items, nitems, nblk);
-        else hipLaunchKernelGGL((k_near_cells<true, 3>), grid, block, 0, s, a, items, nitems, nblk);
-    } else {
-        if (slots <= 2) hipLaunchKernelGGL((k_near_cells<false, 2>), grid, block, 0, s, a, items, nitems, nblk);
-        else hipLaunchKernelGGL((k_near_cells<false, 3>), grid, block, 0, s, a, items, nitems, nblk);
-    }
+    if (a.dbg_pairs) near_cells_launch<true>(a, f64, slots, grid, block, items, nitems, nblk, s);
+    else near_cells_launch<false>(a, f64, slots, grid, block, items, nitems, nblk, s);
 }
 
 void launch_near(const EvalArgs &a, bool f64, const ListItem *items, int32_t nitems, hipStream_t s) {
@@ -1356,8 +1415,13 @@ void launch_near(const EvalArgs &a, bool f64, const ListItem *items, int32_t nit
     int32_t nblk = (nitems + 7) / 8 * 8;
     if (nblk < 8) nblk = 8;
     dim3 grid((unsigned)nblk), block(64 * kNW);
-    if (f64) hipLaunchKernelGGL(k_near_list<true>, grid, block, 0, s, a, items, nitems, nblk);
-    else hipLaunchKernelGGL(k_near_list<false>, grid, block, 0, s, a, items, nitems, nblk);
+    if (a.dbg_pairs) {
+        if (f64) hipLaunchKernelGGL((k_near_list<true, true>), grid, block, 0, s, a, items, nitems, nblk);
+        else hipLaunchKernelGGL((k_near_list<false, true>), grid, block, 0, s, a, items, nitems, nblk);
+    } else {
+        if (f64) hipLaunchKernelGGL((k_near_list<true, false>), grid, block, 0, s, a, items, nitems, nblk);
+        else hipLaunchKernelGGL((k_near_list<false, false>), grid, block, 0, s, a, items, nitems, nblk);
+    }
 }
 
 void launch_neighbor_count(const EvalArgs &a, int32_t sys, int64_t n, int64_t p0, const int32_t *id_cur,

@@ -19,18 +19,26 @@ namespace rbsog {
 
 constexpr int kMaxGauss = 160;  // M + 1 <= kMaxGauss
 
-// Per-k record read uniformly by every lane of the far-force kernel
-// (FP64 form): integer m as doubles, w k (the weighted wave vector), rho.
+// Per-k record read uniformly by every lane of the far-force kernel, in
+// amplitude-phase form: with rho_e = |rho_e| e^{2 pi i phi_e},
+//   Im(e^{-i k.r} rho) = |rho| sin(2 pi (phi - m.s)),  s = r/L (fractional),
+// so the far force is F_i = -q_i sum_e a_e sin(2 pi (phi_e - m_e.s_i)) with
+// a_e = w_e |rho_e| k_e: one sine per (particle, wave vector).  The kick/drift
+// kernel stages m; the structure-factor reduction fills phi and a.
+// FP64 form: m as doubles, phi in revolutions, a.
 struct KRec64 {
     double mx, my, mz;
-    double ckx, cky, ckz;
-    double re, im;
+    double phi;
+    double ax, ay, az;
+    double pad;
 };
-// FP32 form: m as int32, w k and rho rounded to float.
+// FP32 form: m as int32, phi as a 32-bit fixed-point fraction of a turn
+// (mod 2^32), a rounded to float.
 struct KRec32 {
     int32_t mx, my, mz;
-    float ckx, cky, ckz;
-    float re, im;
+    uint32_t phi;
+    float ax, ay, az;
+    float pad;
 };
 
 // Geometry of one system.
@@ -194,6 +202,14 @@ struct EvalArgs {
     double *dip_part;      // dipole partials per structure-factor chunk (3 per chunk)
     double *dipole;        // dipole moment M per system (3 per system)
     int32_t *flag;         // bit 0: non-finite force, bit 1: non-finite energy, bit 3: list overflow
+    // debug launches only (null otherwise): the near kernels record every pair
+    // they accept as (caller index of the home, of the candidate) at
+    // dbg_pairs[atomicAdd(dbg_cnt, 1)] below dbg_cap, and set bit 0 (list
+    // build), 1 (list pass) or 2 (fused cell kernel) of *dbg_kind
+    uint2 *dbg_pairs;
+    int32_t *dbg_cnt;
+    int32_t dbg_cap;
+    int32_t *dbg_kind;
     uint32_t *sys_done;    // per-system counters of reduced k records
     // velocity-Verlet
     int32_t kick;          // nonzero: kick + drift before, kick after
@@ -251,6 +267,10 @@ void launch_scan(const EvalArgs &a, hipStream_t s);
 int64_t scan_blocksums_size(int64_t n);
 void launch_cell_scatter(const EvalArgs &a, hipStream_t s);
 void launch_sort_gather(const EvalArgs &a, hipStream_t s);
+// near and far forces (6 doubles each) of the caller indices ids[0..m) from
+// the current order (slot_of: N int32 of scratch for the inverse permutation)
+void launch_subset_forces(const EvalArgs &a, int64_t m, const int64_t *ids, int32_t *slot_of, double *out,
+                          hipStream_t s);
 
 // ---- near part (kernels_near.hip) ------------------------------------------
 // Verlet list of every item (a.pairs null: not written) with this

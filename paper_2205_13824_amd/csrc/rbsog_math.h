@@ -104,6 +104,18 @@ __host__ __device__ inline bool mh_accept(double ua, double pc, double qc, doubl
     return ua < (pc * q) / (p * qc);
 }
 
+// The revolution of a 32-bit fixed-point phase t (the fraction t / 2^32 of a
+// turn) as an FP32 value for the hardware sin/cos, which take revolutions:
+// 1.0's exponent with the top 23 bits of t as the mantissa, 1 + t / 2^32 in
+// [1, 2) up to the 9 low bits of t (one funnel shift).  sin and cos of a whole
+// turn plus the fraction are those of the fraction.  The truncation offsets
+// every phase by half a unit of 2^-23 turns on average and by at most 2^-23
+// turns: the common part cancels between the structure factor and the far
+// force, which multiply e^{i theta_j} by e^{-i theta_i}.
+__device__ __forceinline__ float phase_rev(uint32_t t) {
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, t, 9u));
+}
+
 // sin(2 pi f), cos(2 pi f) for |f| <= 1/2 in FP64: quadrant q = rint(4f),
 // r = f - q/4 in [-1/8, 1/8], Taylor series of sin/cos(2 pi r) through
 // degree 15/16 (truncation below 5e-17), then rotation by q quarter turns.

@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kSfBlock) void k_sf_partial(int64_t n, const double
                 for (int h = h0; h < h1; ++h) {
                     const uint4 p = st32[h];
                     const uint32_t t = ux * p.x + uy * p.y + uz * p.z;
-                    const float f = (float)(int32_t)t * 0x1.0p-32f;
+                    const float f = rmath::phase_rev(t);
                     const float qf = __uint_as_float(p.w);
                     rf = fmaf(qf, __builtin_amdgcn_cosf(f), rf);
                     fi = fmaf(qf, __builtin_amdgcn_sinf(f), fi);

@@ -33,7 +33,8 @@ EXPORTS = ("rbsog_default_opts", "rbsog_sog_table1", "rbsog_init", "rbsog_init_b
            "rbsog_profile", "rbsog_profile_read", "rbsog_sync", "rbsog_last_error", "rbsog_status_string",
            "rbsog_destroy", "rbsog_autotune", "rbsog_set_thermostat", "rbsog_get_kbatch",
            "rbsog_set_nose_hoover", "rbsog_get_kinetic", "rbsog_set_msd_origin", "rbsog_get_msd",
-           "rbsog_structure_factor", "rbsog_structure_factor_noalloc")
+           "rbsog_structure_factor", "rbsog_structure_factor_noalloc", "rbsog_get_forces_subset",
+           "rbsog_debug_record_pairs", "rbsog_debug_pairs", "rbsog_debug_list")
 
 
 class RbsogError(RuntimeError):
@@ -58,7 +59,8 @@ class rbsog_info_t(ctypes.Structure):
                 ("k_remaining", ctypes.c_int64), ("evaluations", ctypes.c_int64), ("n", ctypes.c_int64),
                 ("n_sys", ctypes.c_int32), ("rho_chunk", ctypes.c_int32), ("far_block", ctypes.c_int32),
                 ("tuned", ctypes.c_int32), ("list_capacity", ctypes.c_int64), ("list_builds", ctypes.c_int64),
-                ("skin", ctypes.c_double)]
+                ("skin", ctypes.c_double), ("rho_ktile", ctypes.c_int32), ("build_slots", ctypes.c_int32),
+                ("cell_slots", ctypes.c_int32)]
 
 
 _lib = None
@@ -86,6 +88,7 @@ def lib():
             "rbsog_set_positions": (i32, [vp, vp]),
             "rbsog_get_state": (i32, [vp, vp, vp]),
             "rbsog_get_forces": (i32, [vp, vp, vp]),
+            "rbsog_get_forces_subset": (i32, [vp, i64, vp, vp, vp]),
             "rbsog_get_energy": (i32, [vp, vp]),
             "rbsog_get_rho": (i32, [vp, i32, vp, vp]),
             "rbsog_get_kbatch": (i32, [vp, i32, vp]),
@@ -96,6 +99,9 @@ def lib():
             "rbsog_info": (i32, [vp, i32, P(rbsog_info_t)]),
             "rbsog_debug_cells": (i32, [vp, i32, vp, vp]),
             "rbsog_debug_neighbors": (i32, [vp, i32, vp, vp, i64]),
+            "rbsog_debug_record_pairs": (i32, [vp, i64]),
+            "rbsog_debug_pairs": (i32, [vp, i32, vp, vp, vp, i64]),
+            "rbsog_debug_list": (i32, [vp, i32, vp, vp, i64]),
             "rbsog_profile": (i32, [vp, i32]),
             "rbsog_profile_read": (i32, [vp, i32, P(ctypes.c_char_p), P(dbl), P(i64)]),
             "rbsog_sync": (i32, [vp]),
@@ -251,6 +257,15 @@ def rbsog_get_forces(ctx, n: int):
     return Fn, Ff
 
 
+def rbsog_get_forces_subset(ctx, ids):
+    """(F_near, F_far) of the latest evaluation on the given caller indices."""
+    ids = np.ascontiguousarray(np.asarray(ids, dtype=np.int64).reshape(-1))
+    Fn = np.zeros((ids.size, 3))
+    Ff = np.zeros((ids.size, 3))
+    _check(lib().rbsog_get_forces_subset(ctx, ids.size, _ptr(ids), _ptr(Fn), _ptr(Ff)), ctx)
+    return Fn, Ff
+
+
 def rbsog_get_energy(ctx):
     E = np.zeros(4 * n_systems(ctx))
     _check(lib().rbsog_get_energy(ctx, _ptr(E)), ctx)
@@ -301,7 +316,8 @@ def rbsog_info(ctx, sys: int = 0) -> dict:
     return dict(S=info.S, volume=info.volume, ncell=tuple(info.ncell), k_remaining=info.k_remaining,
                 evaluations=info.evaluations, n=info.n, n_sys=info.n_sys,
                 rho_chunk=info.rho_chunk, far_block=info.far_block, tuned=bool(info.tuned),
-                list_capacity=info.list_capacity, list_builds=info.list_builds, skin=info.skin)
+                list_capacity=info.list_capacity, list_builds=info.list_builds, skin=info.skin,
+                rho_ktile=info.rho_ktile, build_slots=info.build_slots, cell_slots=info.cell_slots)
 
 
 def rbsog_autotune(ctx, reps: int = 5) -> dict:
@@ -336,6 +352,34 @@ def rbsog_structure_factor(n: int, x_dev: int, q_dev: int, box, n_k: int, m_dev:
     b = _f64(box, (3,))
     f = lib().rbsog_structure_factor_noalloc if noalloc else lib().rbsog_structure_factor
     _check(f(int(n), x_dev, q_dev, _ptr(b), int(n_k), m_dev, int(precision), rho_re_dev, rho_im_dev, stream))
+
+
+def rbsog_debug_record_pairs(ctx, cap: int):
+    _check(lib().rbsog_debug_record_pairs(ctx, int(cap)), ctx)
+
+
+def _csr_call(ctx, sys, fn, *pre):
+    n = rbsog_info(ctx, sys)["n"]
+    row = np.zeros(n + 1, dtype=np.int64)
+    st = fn(ctx, int(sys), *pre, _ptr(row), None, 0)
+    if st not in (0, -1):
+        _check(st, ctx)
+    cols = np.zeros(max(int(row[-1]), 1), dtype=np.int32)
+    _check(fn(ctx, int(sys), *pre, _ptr(row), _ptr(cols), cols.size), ctx)
+    return row, cols[:int(row[-1])]
+
+
+def rbsog_debug_pairs(ctx, sys: int = 0):
+    """(row_ptr, cols, kinds): pairs the near kernels accepted in the latest
+    evaluation (CSR over local ids) and which kernels recorded them."""
+    kinds = ctypes.c_int32(0)
+    row, cols = _csr_call(ctx, sys, lib().rbsog_debug_pairs, ctypes.byref(kinds))
+    return row, cols, kinds.value
+
+
+def rbsog_debug_list(ctx, sys: int = 0):
+    """(row_ptr, cols): the near list of the latest build (CSR over local ids)."""
+    return _csr_call(ctx, sys, lib().rbsog_debug_list)
 
 
 def rbsog_profile(ctx, enable: bool):

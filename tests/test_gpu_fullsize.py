@@ -8,8 +8,15 @@ unbiasedness of the random-batch far force drawn by the library's sampler.
 * About 2e7 ions (r_c = 3.5, P = 1000): near forces of sampled ions, rho of
   sampled wave vectors, the exact zero sum of the random-batch far force, and
   momentum over velocity-Verlet steps.
+* About 2e7 ions against stored oracle values (tests/golden/make_c5_far.py):
+  the sampled wave vectors, every structure factor and the far force of
+  1000 ions of one random batch; and the mean of many random batches drawn
+  by the library against the oracle's full far field of those ions (every
+  k != 0 through the Poisson identity): 300 batches here, 10,000 in the
+  gpu_long test.
 * Unbiasedness (Sec. 3.3, Lemma 1): the mean of many random-batch far forces
   drawn by the library equals the oracle's full Fourier sum."""
+import os
 import math
 import sys
 import time
@@ -153,3 +160,83 @@ def test_random_batch_mean_is_full_sum(orc):
     # rejections), which can only raise the variance above the iid value
     assert 0.9 < vr < 3.0
     sysm.close()
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def c5_golden():
+    """Stored oracle values of the 2e7-ion system (tests/golden/make_c5_far.py)."""
+    sub = np.loadtxt(os.path.join(GOLDEN, "c5_far_subset.txt"))
+    ids = sub[:, 0].astype(np.int64)
+    batch_path = os.path.join(GOLDEN, "c5_rb_batch.txt")
+    head = [ln for ln in open(batch_path) if ln.startswith("# Ustar")]
+    batch = np.loadtxt(batch_path)
+    return dict(ids=ids, F_full=sub[:, 1:4], F_rb=sub[:, 4:7], m=batch[:, :3].astype(np.int32),
+                re=batch[:, 3], im=batch[:, 4], Ustar=float(head[0].split("=")[1]))
+
+
+@pytest.mark.parametrize("prec,tol", [(R.RBSOG_FP64, F64_TOL), (R.RBSOG_FP32C, F32C_TOL)])
+def test_20M_far_force_of_one_batch_matches_stored_oracle(large, prec, tol):
+    # the host chain keyed 55 gives the stored batch bit for bit; rho over
+    # all 2e7 ions and the far force of the 1000 stored ions match the oracle
+    c = large
+    g = c5_golden()
+    sysm = R.System(c["pos"], c["q"], c["box"], c["rc"], c["P"], seed=55, precision=prec)
+    m = sysm.sample_k(1)
+    assert np.array_equal(m, g["m"])
+    _, E = R.rbsog_forces(sysm.ctx, len(c["q"]), want_forces=False)
+    re, im = R.rbsog_get_rho(sysm.ctx, c["P"])
+    e_rho = math.sqrt(float(np.sum((re - g["re"]) ** 2 + (im - g["im"]) ** 2))
+                      / float(np.sum(g["re"] ** 2 + g["im"] ** 2)))
+    _, Ff = R.rbsog_get_forces_subset(sysm.ctx, g["ids"])
+    e_f = relrms(Ff, g["F_rb"])
+    e_u = abs(E[1] - g["Ustar"]) / abs(g["Ustar"])
+    say(f"[large prec={prec}] vs stored oracle: rho relrms {e_rho:.3e}, far force of 1000 ions {e_f:.3e}, "
+        f"U* rel {e_u:.3e}")
+    assert e_rho < tol and e_f < tol and e_u < 10 * tol
+    sysm.close()
+
+
+def mean_of_batches(c, g, draws, prec=R.RBSOG_FP32C):
+    """Far force of the stored ions over `draws` random batches drawn by the
+    library's device chains (64 chains: consecutive batches come from
+    different chains), summed per batch on the host."""
+    sysm = R.System(c["pos"], c["q"], c["box"], c["rc"], c["P"], seed=56, precision=prec, device_chains=64)
+    acc = np.zeros((len(g["ids"]), 3))
+    acc2 = np.zeros_like(acc)
+    t0 = time.time()
+    for b in range(draws):
+        R.rbsog_forces(sysm.ctx, len(c["q"]), want_forces=False, want_energy=False)
+        _, Ff = R.rbsog_get_forces_subset(sysm.ctx, g["ids"])
+        acc += Ff
+        acc2 += Ff * Ff
+        if (b + 1) % 1000 == 0:
+            say(f"[unbiased 2e7] {b + 1} batches, {time.time() - t0:.0f} s")
+    sysm.close()
+    mean = acc / draws
+    var = (acc2 - draws * mean * mean) / (draws - 1)
+    return mean, var
+
+
+def check_unbiased(mean, var, draws, F_full, tag):
+    se = np.sqrt(var / draws)
+    z = (mean - F_full) / se
+    rms_z = math.sqrt(float(np.mean(z * z)))
+    err = math.sqrt(float(np.sum((mean - F_full) ** 2)))
+    pred = math.sqrt(float(np.sum(var)) / draws)
+    say(f"[{tag}] {draws} batches: rms z {rms_z:.3f}, max |z| {np.abs(z).max():.2f}, "
+        f"|mean - full| / predicted standard error {err / pred:.2f}, relative error of the mean "
+        f"{err / math.sqrt(float(np.sum(F_full ** 2))):.3e}")
+    # C5 criteria: per-component z-scores with RMS in [0.8, 1.2] and max below
+    # 5, and the error of the mean within 3 predicted standard errors
+    assert 0.8 <= rms_z <= 1.2
+    assert np.abs(z).max() < 5.0
+    assert err <= 3.0 * pred
+
+
+def test_20M_random_batch_mean_is_full_far_field(large):
+    g = c5_golden()
+    draws = 300
+    mean, var = mean_of_batches(large, g, draws)
+    check_unbiased(mean, var, draws, g["F_full"], "unbiased 2e7")

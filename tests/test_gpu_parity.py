@@ -318,19 +318,23 @@ def test_graph_replay_equals_eager(orc, prec, nh, skin):
 
 
 @pytest.mark.parametrize("prec,tol", [(R.RBSOG_FP64, F64_TOL), (R.RBSOG_FP32C, F32C_TOL)])
-def test_autotune_keeps_results(orc, prec, tol):
+@pytest.mark.parametrize("skin", [None, 0.0])
+def test_autotune_keeps_results(orc, prec, tol, skin):
     c = W.c1_small()
-    sysm = make(c["pos"], c["q"], c["box"], c["rc"], c["P"], seed=101, prec=prec)
+    sysm = make(c["pos"], c["q"], c["box"], c["rc"], c["P"], seed=101, prec=prec, skin=skin)
     m = sysm.sample_k(3)
     F0, E0 = sysm.forces()
     Fn0, Ff0 = sysm.components()
     info = R.rbsog_autotune(sysm.ctx, 2)
-    say(f"[autotune prec={prec}] shapes chunk={info['rho_chunk']} "
-        f"far_block={info['far_block']} tuned={info['tuned']}")
+    say(f"[autotune prec={prec} skin={skin}] shapes chunk={info['rho_chunk']} ktile={info['rho_ktile']} "
+        f"far_block={info['far_block']} slots={info['build_slots']}/{info['cell_slots']} tuned={info['tuned']}")
     assert info["tuned"] and info["k_remaining"] == 2 * c["P"]
-    # the tuning recomputed the forces of the same positions with the chosen shapes
+    # the tuning recomputed the forces of the same positions with the chosen
+    # shapes (the near kernel's slots per pass and the structure factor's
+    # chunks order the FP32 sums)
     Fn1, Ff1 = sysm.components()
-    assert relrms(Fn1, Fn0) < 1e-13 and relrms(Ff1, Ff0) < 1e-13
+    rt = 1e-13 if prec == R.RBSOG_FP64 else 1e-6
+    assert relrms(Fn1, Fn0) < rt and relrms(Ff1, Ff0) < rt
     # and later evaluations still match the oracle
     check_eval(orc, sysm, c["pos"], c["q"], c["box"], c["rc"], m[c["P"]:2 * c["P"]], tol, f"tuned prec={prec}")
 
