@@ -197,7 +197,10 @@ rbsog_status rbsog_set_k(rbsog_ctx *ctx, int32_t sys, int64_t n_k, const int32_t
  * force, energies.
  *   F_out  NULL, or host n x 3 total force F_N + F*
  *   E_out  NULL, or host 4 * n_sys doubles: U_N, U*, U_self, U of each system
- * E_KSEQ if a system has fewer than P vectors left (nothing is computed). */
+ * E_KSEQ if a system has fewer than P vectors left (nothing is computed);
+ * E_NONFINITE if a returned force or energy is not finite (coincident ions,
+ * positions run off to infinity).  The report is made once: the context
+ * stays usable, and new finite positions or a loaded state run on. */
 rbsog_status rbsog_forces(rbsog_ctx *ctx, double *F_out, double *E_out);
 
 /* n_steps velocity-Verlet steps of size dt (kick dt/2, drift, wrap, forces
@@ -205,7 +208,11 @@ rbsog_status rbsog_forces(rbsog_ctx *ctx, double *F_out, double *E_out);
  * Langevin BAOAB step of rbsog_set_thermostat).  If the
  * forces of the current positions are not known yet, one evaluation is made
  * first.  E_KSEQ (before any work) if the sequence cannot serve every
- * evaluation; E_NONFINITE if a non-finite force appeared. */
+ * evaluation; E_NONFINITE if a force or energy of any step was not finite
+ * (the steps are still made: positions that went non-finite stay so, and
+ * fall in cell 0 of their system; when they overflow its near list the
+ * context is left unusable and can only be destroyed); E_STATE if a device
+ * chain exceeded its proposal limit. */
 rbsog_status rbsog_step(rbsog_ctx *ctx, int64_t n_steps, double dt);
 
 /* Sets velocities: v host n x 3, or NULL to draw v ~ N(0, T/m) per component
@@ -403,6 +410,31 @@ rbsog_status rbsog_debug_list(rbsog_ctx *ctx, int32_t sys, int64_t *row_ptr, int
 rbsog_status rbsog_profile(rbsog_ctx *ctx, int32_t enable);
 rbsog_status rbsog_profile_read(rbsog_ctx *ctx, int32_t idx, const char **name, double *ms,
                                 int64_t *launches);
+
+/* Checkpoint and resume: every quantity a later step reads, so that a run
+ * resumed from a saved state continues bit for bit as the uninterrupted run
+ * would (Algorithm 1 consumes the wave-vector sequence in order: the chain
+ * states, the sequence and its cursor are part of the state): positions,
+ * velocities and charges in the current cell order with the caller indices,
+ * the fixed-point coordinates and those of the latest near-list build, the
+ * cell starts, the near list (its used entries), the near and far forces of
+ * the latest evaluation, energies, structure factors and the staged wave
+ * vectors, the host chain, sequence and cursor of every system (or the
+ * device chains and their batches), the Langevin step counter, the
+ * Nose-Hoover xi and kinetic energies, the mean-square-displacement origin
+ * and displacements, the skin in use with the adaptive-skin counters, the
+ * thermostat settings and the launch shapes.
+ * rbsog_save_state: with buf NULL only *size (bytes needed) is set; else
+ * buf (host, cap bytes) receives the state and *size its length; E_ARG if
+ * cap is too small.  The bytes are an opaque format of this library build.
+ * rbsog_load_state: restores a state into a context created by the same
+ * rbsog_init / rbsog_init_batch call (same systems, charges, boxes, cutoffs,
+ * P, seeds and options; the positions given at creation are replaced);
+ * E_ARG if the state belongs to a context of another shape or is truncated:
+ * the context is unchanged unless only the near list at the end is cut short
+ * (then it must be loaded again or destroyed). */
+rbsog_status rbsog_save_state(rbsog_ctx *ctx, void *buf, int64_t cap, int64_t *size);
+rbsog_status rbsog_load_state(rbsog_ctx *ctx, const void *buf, int64_t len);
 
 /* Blocks until all work of the context has finished. */
 rbsog_status rbsog_sync(rbsog_ctx *ctx);

@@ -803,6 +803,18 @@ rbsog_status check_list(rbsog_ctx *c, int32_t flag) {
     return RBSOG_OK;
 }
 
+// Non-finite forces or energies (bits 1 and 2) and a device chain past its
+// proposal limit (bit 4) are reported once: the bits are cleared so that a
+// context given new finite state (positions, a loaded state) runs on.
+rbsog_status check_flag(rbsog_ctx *c, int32_t flag) {
+    if (!(flag & 7)) return RBSOG_OK;
+    const int32_t keep = flag & ~7;
+    HIPCHK(c, hipMemcpyAsync(c->flag, &keep, sizeof keep, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (flag & 4) return fail(c, RBSOG_E_STATE, "a device chain exceeded its proposal limit (flag %d)", flag);
+    return fail(c, RBSOG_E_NONFINITE, "non-finite force or energy (flag %d)", flag);
+}
+
 rbsog_status check_ctx(rbsog_ctx *c) {
     if (!c) return fail(nullptr, RBSOG_E_ARG, "null context");
     if (c->poisoned) return fail(c, RBSOG_E_STATE, "context is poisoned after a device error: %s", c->err.c_str());
@@ -1874,16 +1886,23 @@ rbsog_status rbsog_forces(rbsog_ctx *c, double *F_out, double *E_out) {
         HIPCHK(c, hipMemcpyAsync(&flag, c->flag, sizeof flag, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         TRY(check_list(c, flag));
+        TRY(check_flag(c, flag));
     }
     if (F_out) {
         std::vector<double> b((size_t)3 * c->N);
         TRY(download_by_id(c, c->Fn, F_out));
         TRY(download_by_id(c, c->Ff, b.data()));
         for (size_t i = 0; i < b.size(); ++i) F_out[i] += b[i];
+        // without a kick no kernel looks at the sum of the two forces
+        for (size_t i = 0; i < b.size(); ++i)
+            if (!std::isfinite(F_out[i]))
+                return fail(c, RBSOG_E_NONFINITE, "force entry %lld is not finite", (long long)i);
     }
     if (E_out) {
         HIPCHK(c, hipMemcpyAsync(E_out, c->E, 4 * (size_t)c->nsys * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int64_t i = 0; i < 4 * (int64_t)c->nsys; ++i)
+            if (!std::isfinite(E_out[i])) return fail(c, RBSOG_E_NONFINITE, "energy entry %lld is not finite", (long long)i);
     }
     return RBSOG_OK;
 }
@@ -1936,10 +1955,14 @@ rbsog_status rbsog_step(rbsog_ctx *c, int64_t n_steps, double dt) {
     int32_t flag = 0;
     HIPCHK(c, hipMemcpyAsync(&flag, c->flag, sizeof flag, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if ((flag & 3) && (flag & 8)) {
+        // particles that went non-finite pile into cell 0 and overflow the
+        // list: the cause is reported, the list is beyond repair
+        c->poisoned = true;
+        return fail(c, RBSOG_E_NONFINITE, "non-finite force or energy, and the near list overflowed (flag %d)", flag);
+    }
     TRY(check_list(c, flag));
-    if (flag & 4) return fail(c, RBSOG_E_STATE, "a device chain exceeded its proposal limit (flag %d)", flag);
-    if (flag) return fail(c, RBSOG_E_NONFINITE, "non-finite force or energy (flag %d)", flag);
-    return RBSOG_OK;
+    return check_flag(c, flag);
 }
 
 // Kinetic energy of every system from velocities given in the caller's order
@@ -2373,6 +2396,308 @@ rbsog_status rbsog_profile_read(rbsog_ctx *c, int32_t idx, const char **name, do
     if (name) *name = c->prof[idx].name;
     if (ms) *ms = c->prof[idx].ms;
     if (launches) *launches = c->prof[idx].launches;
+    return RBSOG_OK;
+}
+
+}  // extern "C"
+
+// ---- checkpoint ------------------------------------------------------------
+// A saved state: a fixed header that names the context's shape, then every
+// host and device quantity a later step reads, in a fixed order.  One writer
+// serves both the size query (no buffer) and the copy.
+namespace {
+
+constexpr char kStateMagic[8] = {'R', 'B', 'S', 'O', 'G', 'S', 'T', '1'};
+
+struct StateWriter {
+    uint8_t *buf;  // null: count only
+    int64_t cap, pos = 0;
+    bool overflow = false;
+    void raw(const void *p, int64_t n) {
+        if (buf) {
+            if (pos + n > cap) overflow = true;
+            else std::memcpy(buf + pos, p, (size_t)n);
+        }
+        pos += n;
+    }
+    template <class T>
+    void val(const T &v) { raw(&v, sizeof v); }
+};
+
+struct StateReader {
+    const uint8_t *buf;
+    int64_t len, pos = 0;
+    bool bad = false;
+    void raw(void *p, int64_t n) {
+        if (pos + n > len) {
+            bad = true;
+            return;
+        }
+        std::memcpy(p, buf + pos, (size_t)n);
+        pos += n;
+    }
+    template <class T>
+    T val() {
+        T v{};
+        raw(&v, sizeof v);
+        return v;
+    }
+};
+
+// Device arrays of the state: (pointer, bytes).  The near list is saved by
+// segment (its used entries only) elsewhere.
+std::vector<std::pair<void *, int64_t>> device_state(rbsog_ctx *c) {
+    const int64_t N = c->N;
+    std::vector<std::pair<void *, int64_t>> v = {
+        {c->buf[0].x, 3 * N * 8}, {c->buf[0].v, 3 * N * 8},  {c->buf[0].q, N * 8},
+        {c->buf[0].qf, N * 4},    {c->buf[0].id, N * 4},     {c->buf[0].dsp, 3 * N * 8},
+        {c->u_tmp, 3 * N * 4},    {c->u, 3 * N * 4},         {c->cell_sorted, N * 4},
+        {c->cell_start, (c->C + 1) * 4}, {c->Fn, 3 * N * 8}, {c->Ff, 3 * N * 8},
+        {c->rebuild, 4},          {c->nbuild, 8},            {c->kcur, (int64_t)c->nsys * 8},
+        {c->kin, (int64_t)c->nsys * 8}, {c->nh_xi, (int64_t)c->nsys * 8}, {c->tstep, 8},
+        {c->E, 4 * (int64_t)c->nsys * 8}, {c->rho, 2 * (int64_t)c->K * 8},
+        {c->kb64, (int64_t)c->K * (int64_t)sizeof(KRec64)}, {c->kb32, (int64_t)c->K * (int64_t)sizeof(KRec32)},
+        {c->wk, (int64_t)c->K * 8}, {c->dipole, 3 * (int64_t)c->nsys * 8}, {c->flag, 4}};
+    if (c->lambda) {
+        v.push_back({c->chains, (int64_t)c->nsys * c->lambda * (int64_t)sizeof(ChainState)});
+        for (const SysHost &h : c->sys) v.push_back({h.dkseq, (int64_t)c->lambda * h.P * 3 * 4});
+    }
+    return v;
+}
+
+rbsog_status write_state(rbsog_ctx *c, StateWriter &w) {
+    w.raw(kStateMagic, 8);
+    w.val<int32_t>(c->nsys);
+    w.val<int64_t>(c->N);
+    w.val<int64_t>(c->C);
+    w.val<int32_t>(c->K);
+    w.val<int32_t>(c->prec);
+    w.val<int32_t>(c->lambda);
+    for (const SysHost &h : c->sys) {
+        w.val(h.n);
+        w.val(h.P);
+        w.raw(h.box, sizeof h.box);
+        w.val(h.rc);
+        w.val(h.seed);
+    }
+    // host state
+    w.val(c->evals);
+    w.val<int32_t>(c->forces_valid);
+    w.val(c->skin_cur);
+    w.val(c->adapt_steps);
+    w.val(c->adapt_nb0);
+    w.val(c->adapt_window);
+    w.val(c->hold);
+    w.val(c->hold_len);
+    w.val(c->gamma);
+    w.val(c->temp);
+    w.val(c->tseed);
+    w.val<int32_t>(c->nh_on);
+    w.val(c->nh_T);
+    w.val(c->nh_tau);
+    w.val<int32_t>(c->msd_on);
+    w.val(c->tune);
+    w.val<int32_t>(c->tuned);
+    w.val(c->icap);
+    for (const SysHost &h : c->sys) {
+        w.val(h.chain);
+        w.val(h.cursor);
+        w.val<int32_t>(h.custom_w);
+        w.val<int64_t>((int64_t)h.kseq.size());
+        w.raw(h.kseq.data(), (int64_t)h.kseq.size() * 4);
+        w.val<int64_t>((int64_t)h.kw.size());
+        w.raw(h.kw.data(), (int64_t)h.kw.size() * 8);
+        w.val(h.nh_nf);
+        w.val(h.nh_Q);
+    }
+    // device state
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (const auto &a : device_state(c)) {
+        if (w.buf && w.pos + a.second <= w.cap) {
+            HIPCHK(c, hipMemcpy(w.buf + w.pos, a.first, (size_t)a.second, hipMemcpyDeviceToHost));
+        } else if (w.buf) {
+            w.overflow = true;
+        }
+        w.pos += a.second;
+    }
+    // the near list, segment by segment (used entries)
+    const bool list = c->skin_cur > 0.0 && c->pairs;
+    w.val<int32_t>(list ? 1 : 0);
+    if (list) {
+        std::vector<int32_t> pc((size_t)kListWaves * c->n_list);
+        HIPCHK(c, hipMemcpy(pc.data(), c->pcnt, pc.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        w.raw(pc.data(), (int64_t)pc.size() * 4);
+        const int64_t seg = c->icap / kListWaves;
+        for (size_t g = 0; g < pc.size(); ++g) {
+            const int64_t bytes = (int64_t)std::min<int64_t>(pc[g], seg) * (int64_t)sizeof(uint2);
+            if (w.buf && w.pos + bytes <= w.cap && bytes > 0) {
+                HIPCHK(c, hipMemcpy(w.buf + w.pos, c->pairs + (int64_t)g * seg, (size_t)bytes,
+                                    hipMemcpyDeviceToHost));
+            } else if (w.buf && bytes > 0) {
+                w.overflow = true;
+            }
+            w.pos += bytes;
+        }
+    }
+    return RBSOG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rbsog_status rbsog_save_state(rbsog_ctx *c, void *buf, int64_t cap, int64_t *size) {
+    TRY(check_ctx(c));
+    StateWriter probe{nullptr, 0};
+    TRY(write_state(c, probe));
+    if (size) *size = probe.pos;
+    if (!buf) return RBSOG_OK;
+    if (cap < probe.pos) return fail(c, RBSOG_E_ARG, "the state needs %lld bytes", (long long)probe.pos);
+    StateWriter w{(uint8_t *)buf, cap};
+    TRY(write_state(c, w));
+    if (w.overflow) return fail(c, RBSOG_E_ARG, "the state needs %lld bytes", (long long)w.pos);
+    return RBSOG_OK;
+}
+
+rbsog_status rbsog_load_state(rbsog_ctx *c, const void *buf, int64_t len) {
+    TRY(check_ctx(c));
+    if (!buf || len < 8) return fail(c, RBSOG_E_ARG, "no state");
+    StateReader r{(const uint8_t *)buf, len};
+    char magic[8];
+    r.raw(magic, 8);
+    if (std::memcmp(magic, kStateMagic, 8) != 0) return fail(c, RBSOG_E_ARG, "not a saved state of this library");
+    const int32_t nsys = r.val<int32_t>();
+    const int64_t N = r.val<int64_t>(), C = r.val<int64_t>();
+    const int32_t K = r.val<int32_t>(), prec = r.val<int32_t>(), lambda = r.val<int32_t>();
+    if (nsys != c->nsys || N != c->N || C != c->C || K != c->K || prec != c->prec || lambda != c->lambda)
+        return fail(c, RBSOG_E_ARG, "the state belongs to a context of another shape (systems, particles, "
+                                    "cells, wave vectors, precision or device chains differ)");
+    for (const SysHost &h : c->sys) {
+        const int64_t n = r.val<int64_t>();
+        const int32_t P = r.val<int32_t>();
+        double box[3];
+        r.raw(box, sizeof box);
+        const double rc = r.val<double>();
+        const uint64_t seed = r.val<uint64_t>();
+        if (n != h.n || P != h.P || std::memcmp(box, h.box, sizeof box) != 0 || rc != h.rc || seed != h.seed)
+            return fail(c, RBSOG_E_ARG, "the state belongs to other systems (n, P, box, r_c or seed differ)");
+    }
+    if (r.bad) return fail(c, RBSOG_E_ARG, "truncated state");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // host state (applied once the whole buffer has been read)
+    const int64_t evals = r.val<int64_t>();
+    const int32_t forces_valid = r.val<int32_t>();
+    const double skin_cur = r.val<double>();
+    const int64_t adapt_steps = r.val<int64_t>(), adapt_nb0 = r.val<int64_t>(), adapt_window = r.val<int64_t>();
+    const int32_t hold = r.val<int32_t>(), hold_len = r.val<int32_t>();
+    const double gamma = r.val<double>(), temp = r.val<double>();
+    const uint64_t tseed = r.val<uint64_t>();
+    const int32_t nh_on = r.val<int32_t>();
+    const double nh_T = r.val<double>(), nh_tau = r.val<double>();
+    const int32_t msd_on = r.val<int32_t>();
+    const Tune tune = r.val<Tune>();
+    const int32_t tuned = r.val<int32_t>();
+    const int64_t icap = r.val<int64_t>();
+    struct SysState {
+        MHChain chain;
+        int64_t cursor;
+        int32_t custom_w;
+        std::vector<int32_t> kseq;
+        std::vector<double> kw;
+        double nh_nf, nh_Q;
+    };
+    std::vector<SysState> ss((size_t)c->nsys);
+    for (SysState &x : ss) {
+        x.chain = r.val<MHChain>();
+        x.cursor = r.val<int64_t>();
+        x.custom_w = r.val<int32_t>();
+        const int64_t nk = r.val<int64_t>();
+        if (r.bad || nk < 0 || nk > (len - r.pos) / 4) return fail(c, RBSOG_E_ARG, "truncated state");
+        x.kseq.resize((size_t)nk);
+        r.raw(x.kseq.data(), nk * 4);
+        const int64_t nw = r.val<int64_t>();
+        if (r.bad || nw < 0 || nw > (len - r.pos) / 8) return fail(c, RBSOG_E_ARG, "truncated state");
+        x.kw.resize((size_t)nw);
+        r.raw(x.kw.data(), nw * 8);
+        x.nh_nf = r.val<double>();
+        x.nh_Q = r.val<double>();
+    }
+    if (r.bad || !valid_tune(tune) || !(skin_cur >= 0.0)) return fail(c, RBSOG_E_ARG, "corrupt state");
+    {
+        // the device arrays (fixed sizes for this shape) must all be there
+        // before anything of the context changes
+        int64_t dev = 0;
+        for (const auto &a : device_state(c)) dev += a.second;
+        if (r.pos + dev + 4 > len) return fail(c, RBSOG_E_ARG, "truncated state");
+    }
+    // the saved grid, shapes and list capacity first (they size what follows)
+    for (SysHost &h : c->sys) set_geometry(h, skin_cur);
+    c->skin_cur = skin_cur;
+    TRY(apply_tune(c, tune));
+    c->tuned = tuned != 0;
+    TRY(upload_cell_items(c));
+    if (skin_cur > 0.0 && icap != c->icap) {
+        // a list of the saved capacity
+        uint2 *np = nullptr;
+        if (hipMalloc((void **)&np, (size_t)c->n_list * (size_t)icap * sizeof(uint2)) != hipSuccess)
+            return fail(c, RBSOG_E_OOM, "pair list of %lld x %lld entries", (long long)c->n_list, (long long)icap);
+        if (c->pairs) {
+            c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), (void *)c->pairs), c->allocs.end());
+            (void)hipFree(c->pairs);
+        }
+        c->pairs = np;
+        c->allocs.push_back(np);
+        c->icap = icap;
+    }
+    // sequences of the host chains: device copies of the right capacity
+    for (int32_t s = 0; s < c->nsys; ++s) {
+        SysHost &h = c->sys[s];
+        h.chain = ss[s].chain;
+        h.cursor = ss[s].cursor;
+        h.custom_w = ss[s].custom_w != 0;
+        h.kseq = std::move(ss[s].kseq);
+        h.kw = std::move(ss[s].kw);
+        h.nh_nf = ss[s].nh_nf;
+        h.nh_Q = ss[s].nh_Q;
+        if (!c->lambda) TRY(upload_k(c, s, 0));
+        TRY(upload_sysdev(c, s));
+    }
+    for (const auto &a : device_state(c)) {
+        if (r.pos + a.second > len) return fail(c, RBSOG_E_ARG, "truncated state");
+        HIPCHK(c, hipMemcpy(a.first, r.buf + r.pos, (size_t)a.second, hipMemcpyHostToDevice));
+        r.pos += a.second;
+    }
+    const int32_t list = r.val<int32_t>();
+    if (list) {
+        if (!(skin_cur > 0.0)) return fail(c, RBSOG_E_ARG, "corrupt state");
+        std::vector<int32_t> pc((size_t)kListWaves * c->n_list);
+        r.raw(pc.data(), (int64_t)pc.size() * 4);
+        if (r.bad) return fail(c, RBSOG_E_ARG, "truncated state");
+        HIPCHK(c, hipMemcpy(c->pcnt, pc.data(), pc.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        const int64_t seg = c->icap / kListWaves;
+        for (size_t g = 0; g < pc.size(); ++g) {
+            const int64_t bytes = (int64_t)std::min<int64_t>(pc[g], seg) * (int64_t)sizeof(uint2);
+            if (r.pos + bytes > len) return fail(c, RBSOG_E_ARG, "truncated state");
+            if (bytes > 0)
+                HIPCHK(c, hipMemcpy(c->pairs + (int64_t)g * seg, r.buf + r.pos, (size_t)bytes, hipMemcpyHostToDevice));
+            r.pos += bytes;
+        }
+    }
+    c->evals = evals;
+    c->forces_valid = forces_valid != 0;
+    c->adapt_steps = adapt_steps;
+    c->adapt_nb0 = adapt_nb0;
+    c->adapt_window = adapt_window;
+    c->hold = hold;
+    c->hold_len = hold_len;
+    c->gamma = gamma;
+    c->temp = temp;
+    c->tseed = tseed;
+    c->nh_on = nh_on != 0;
+    c->nh_T = nh_T;
+    c->nh_tau = nh_tau;
+    c->msd_on = msd_on != 0;
+    drop_graphs(c);  // the captured steps hold the old constants
     return RBSOG_OK;
 }
 

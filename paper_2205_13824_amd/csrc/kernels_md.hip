@@ -156,7 +156,8 @@ __global__ __launch_bounds__(kBlock) void k_kdq(EvalArgs a, int32_t pblocks) {
         const double r = xs[d] / L[d];
         const double f = r - floor(r);
         double w = floor(f * kTwo32);
-        w = w > kTwo32 - 1.0 ? kTwo32 - 1.0 : w;
+        // a non-finite position (reported by the flag) falls in cell 0
+        w = w >= 0.0 ? (w > kTwo32 - 1.0 ? kTwo32 - 1.0 : w) : 0.0;
         const uint32_t ud = (uint32_t)w;
         uq[d] = ud;
         if (valid) {

@@ -88,7 +88,8 @@ __global__ __launch_bounds__(kSfBlock) void k_sf_partial(int64_t n, const double
                 uint32_t u[3];
                 for (int d = 0; d < 3; ++d) {
                     double w = floor(s[d] * kTwo32);
-                    w = w > kTwo32 - 1.0 ? kTwo32 - 1.0 : w;
+                    // non-finite positions give 0 instead of an undefined conversion
+                    w = w >= 0.0 ? (w > kTwo32 - 1.0 ? kTwo32 - 1.0 : w) : 0.0;
                     u[d] = (uint32_t)w;
                 }
                 st32[threadIdx.x] = make_uint4(u[0], u[1], u[2], __float_as_uint((float)q[j]));

@@ -34,7 +34,8 @@ EXPORTS = ("rbsog_default_opts", "rbsog_sog_table1", "rbsog_init", "rbsog_init_b
            "rbsog_destroy", "rbsog_autotune", "rbsog_set_thermostat", "rbsog_get_kbatch",
            "rbsog_set_nose_hoover", "rbsog_get_kinetic", "rbsog_set_msd_origin", "rbsog_get_msd",
            "rbsog_structure_factor", "rbsog_structure_factor_noalloc", "rbsog_get_forces_subset",
-           "rbsog_debug_record_pairs", "rbsog_debug_pairs", "rbsog_debug_list")
+           "rbsog_debug_record_pairs", "rbsog_debug_pairs", "rbsog_debug_list", "rbsog_save_state",
+           "rbsog_load_state")
 
 
 class RbsogError(RuntimeError):
@@ -100,6 +101,8 @@ def lib():
             "rbsog_debug_cells": (i32, [vp, i32, vp, vp]),
             "rbsog_debug_neighbors": (i32, [vp, i32, vp, vp, i64]),
             "rbsog_debug_record_pairs": (i32, [vp, i64]),
+            "rbsog_save_state": (i32, [vp, vp, i64, P(i64)]),
+            "rbsog_load_state": (i32, [vp, vp, i64]),
             "rbsog_debug_pairs": (i32, [vp, i32, vp, vp, vp, i64]),
             "rbsog_debug_list": (i32, [vp, i32, vp, vp, i64]),
             "rbsog_profile": (i32, [vp, i32]),
@@ -399,6 +402,20 @@ def rbsog_profile_read(ctx) -> dict:
         out[name.value.decode()] = (ms.value, cnt.value)
         i += 1
     return out
+
+
+def rbsog_save_state(ctx) -> bytes:
+    """The context's complete evolving state (opaque bytes)."""
+    size = ctypes.c_int64(0)
+    _check(lib().rbsog_save_state(ctx, None, 0, ctypes.byref(size)), ctx)
+    buf = ctypes.create_string_buffer(size.value)
+    _check(lib().rbsog_save_state(ctx, ctypes.cast(buf, ctypes.c_void_p), size.value, ctypes.byref(size)), ctx)
+    return buf.raw[:size.value]
+
+
+def rbsog_load_state(ctx, state: bytes):
+    buf = ctypes.create_string_buffer(state, len(state))
+    _check(lib().rbsog_load_state(ctx, ctypes.cast(buf, ctypes.c_void_p), len(state)), ctx)
 
 
 def rbsog_sync(ctx):

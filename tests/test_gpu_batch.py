@@ -47,11 +47,11 @@ def mixed_systems():
     return out
 
 
-def make_batch(systems, prec):
-    say(f"[gpu] batch of {len(systems)} systems, n={[len(s['q']) for s in systems]} prec={prec}")
+def make_batch(systems, prec, **kw):
+    say(f"[gpu] batch of {len(systems)} systems, n={[len(s['q']) for s in systems]} prec={prec} {kw}")
     return R.Batch([s["pos"] for s in systems], [s["q"] for s in systems], [s["box"] for s in systems],
                    [s["rc"] for s in systems], [s["P"] for s in systems], [s["seed"] for s in systems],
-                   precision=prec)
+                   precision=prec, **kw)
 
 
 def split(arr, sizes):
@@ -59,9 +59,12 @@ def split(arr, sizes):
 
 
 @pytest.mark.parametrize("prec,tol", [(R.RBSOG_FP64, F64_TOL), (R.RBSOG_FP32C, F32C_TOL)])
-def test_mixed_batch_vs_oracle(orc, prec, tol):
+@pytest.mark.parametrize("skin", [None, 0.0])
+def test_mixed_batch_vs_oracle(orc, prec, tol, skin):
+    # skin 0: every evaluation builds (fused cell kernel, far force beside it
+    # in the order before the re-sort, taken back through the permutation)
     systems = mixed_systems()
-    b = make_batch(systems, prec)
+    b = make_batch(systems, prec, skin=skin)
     m_all = b.sample_k(1)
     F, E = b.forces()
     Fn, Ff = b.components()
@@ -82,7 +85,8 @@ def test_mixed_batch_vs_oracle(orc, prec, tol):
             assert abs(got - want) / max(abs(want), 1.0) < tol * 10
         # cell and neighbour lists of the system, local indices, bit-exact
         start, order = R.rbsog_debug_cells(b.ctx, sys=i)
-        _, _, start_o, order_o = orc.cell_list(s["pos"], s["box"], s["rc"] * (1.0 + R.rbsog_default_opts().skin))
+        width = s["rc"] * (1.0 + (R.rbsog_default_opts().skin if skin is None else skin))
+        _, _, start_o, order_o = orc.cell_list(s["pos"], s["box"], width)
         assert (start == start_o).all() and (order == order_o).all()
         row, cols = R.rbsog_debug_neighbors(b.ctx, sys=i)
         row_o, cols_o = orc.neighbors_brute(s["pos"], s["box"], s["rc"])
@@ -118,13 +122,14 @@ def test_batch_matches_single_contexts():
 
 
 @pytest.mark.parametrize("prec", [R.RBSOG_FP64, R.RBSOG_FP32C])
-def test_batch_graph_replay_equals_eager(prec):
+@pytest.mark.parametrize("skin", [None, 0.0])
+def test_batch_graph_replay_equals_eager(prec, skin):
     systems = mixed_systems()
     runs = []
     for graphs in (True, False):
         b = R.Batch([s["pos"] for s in systems], [s["q"] for s in systems], [s["box"] for s in systems],
                     [s["rc"] for s in systems], [s["P"] for s in systems], [s["seed"] for s in systems],
-                    precision=prec, graphs=graphs)
+                    precision=prec, graphs=graphs, skin=skin)
         b.sample_k(12)
         R.rbsog_set_velocities(b.ctx, None, T=1.0, seed=9)
         states = []
@@ -153,4 +158,33 @@ def test_replica_ensemble_sampled(orc):
         e = relrms(Fi, Fn_o + Ff_o)
         say(f"[ensemble {i}] n={len(s['q'])} L={s['box'][0]:.2f} relrms {e:.3e}")
         assert e < F32C_TOL
+    b.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(R.RBSOG_FP64, 1e-10), (R.RBSOG_FP32C, 2e-5)])
+def test_mixed_batch_steps_building_every_step(orc, prec, tol):
+    # skin 0 over several velocity-Verlet steps: after every step the near
+    # and far forces of each system match the oracle at the library's own
+    # positions (the far force crosses the re-sort's permutation, which now
+    # moves particles within every system's slot range)
+    systems = mixed_systems()
+    b = make_batch(systems, prec, skin=0.0)
+    b.sample_k(8)
+    b.forces()
+    R.rbsog_set_velocities(b.ctx, None, T=3.0, seed=13)
+    for step in range(3):
+        b.step(1, 2e-3)
+        x, _ = R.rbsog_get_state(b.ctx, b.n)
+        Fn, Ff = b.components()
+        # the batch of each system's latest evaluation (the sequences
+        # themselves are checked bit for bit elsewhere)
+        ms = [R.rbsog_get_kbatch(b.ctx, s["P"], sys=i) for i, s in enumerate(systems)]
+        for i, (s, xi, Fni, Ffi, m) in enumerate(zip(systems, split(x, b.sizes), split(Fn, b.sizes),
+                                                     split(Ff, b.sizes), ms)):
+            sog = orc.SOG(b.sogs[i].b, b.sogs[i].sigma, b.sogs[i].w0, b.sogs[i].M)
+            Fn_o, _ = orc.near_brute(xi, s["q"], s["box"], s["rc"], sog)
+            Ff_o, _, _, _ = orc.far_rb(xi, s["q"], s["box"], sog, m, s["P"])
+            e_n, e_f = relrms(Fni, Fn_o), relrms(Ffi, Ff_o)
+            say(f"[batch skin 0 step {step + 1} sys {i}] near {e_n:.3e} far {e_f:.3e}")
+            assert e_n < tol and e_f < tol
     b.close()

@@ -552,3 +552,31 @@ def test_fused_cell_kernel_with_paired_home_cells(orc, prec, tol, L):
     row_o, cols_o = orc.neighbors_brute(x, box, rc)
     assert (row == row_o).all() and (cols == cols_o).all()
     assert R.rbsog_info(sysm.ctx)["ncell"][0] == int(box[0] // rc) >= 6
+
+
+@pytest.mark.parametrize("prec", [R.RBSOG_FP64, R.RBSOG_FP32C])
+def test_coincident_ions_report_nonfinite_and_context_recovers(prec):
+    # two ions at one point: the pair term 1/r of the near part is infinite
+    # (Eq. (6)), so both rbsog_forces and rbsog_step report E_NONFINITE
+    n, L = 300, 10.0
+    pos, q, box = W.ions_rsa(n, n / L ** 3, 1.0, 41)
+    bad = pos.copy()
+    bad[7] = bad[3]
+    sysm = make(bad, q, box, 3.0, 20, seed=2, prec=prec)
+    sysm.sample_k(40)
+    for want_F, want_E in ((True, False), (False, True)):
+        with pytest.raises(R.RbsogError) as e:
+            R.rbsog_forces(sysm.ctx, n, want_F, want_E)
+        assert e.value.status == -7
+    with pytest.raises(R.RbsogError) as e:
+        R.rbsog_step(sysm.ctx, 1, 1e-3)
+    assert e.value.status == -7
+    # the report is made once; finite positions run on with finite forces
+    R.rbsog_set_positions(sysm.ctx, pos)
+    R.rbsog_set_velocities(sysm.ctx, np.zeros((n, 3)))
+    F, E = R.rbsog_forces(sysm.ctx, n)
+    assert np.isfinite(F).all() and np.isfinite(E).all()
+    R.rbsog_step(sysm.ctx, 2, 1e-3)
+    x, v = R.rbsog_get_state(sysm.ctx, n)
+    assert np.isfinite(x).all() and np.isfinite(v).all()
+    sysm.close()
