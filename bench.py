@@ -120,13 +120,22 @@ def run_leg(R, torch, wl, prec, args, steps, near_table=False, autotune=True, pr
     setup = time.time() - t0
     ms = timed_steps(torch, sysm, stream, steps)
     info_end = R.rbsog_info(sysm.ctx)
-    kernels = {}
+    kernels, alone = {}, {}
     ps = args.profile_steps if profile_steps is None else profile_steps
     if ps > 0:
-        R.rbsog_profile(sysm.ctx, True)
+        # kernel by kernel with HIP events on the stream each kernel runs on:
+        # first as in the timed steps (the structure factor beside the near
+        # part on the second stream), then every kernel alone
+        R.rbsog_profile(sysm.ctx, 2)
         sysm.step(ps, DT)
         kernels = read_profile(R, sysm.ctx)
-        R.rbsog_profile(sysm.ctx, False)
+        R.rbsog_profile(sysm.ctx, 1)
+        sysm.step(ps, DT)
+        alone = read_profile(R, sysm.ctx)
+        R.rbsog_profile(sysm.ctx, 0)
+        for k, v in kernels.items():
+            if k in alone:
+                v["us_alone"] = alone[k]["us_per_launch"]
     info = R.rbsog_info(sysm.ctx)
     sysm.close()
     label = f"{n} prec={prec}{' core-shell' if near_table else ''}"
@@ -147,10 +156,37 @@ def count_near_pairs(R, wl):
     return int(row[-1]) // 2
 
 
-def rooflines(kernels, n, P, near_pairs, fp64):
-    """Per kernel: algorithmic flops per launch / measured launch time against
-    the published vector peak of the precision, and the same work in VALU
-    issue slots against the slot rate."""
+# kernel names (as rocprofv3 shows them, without the template's later
+# arguments) of the profile keys
+KERNEL_NAMES = {"rho": "k_rho", "far": "k_far", "far_side": "k_far_side", "near": "k_near_list",
+                "near_cells": "k_near_cells", "list_build": "k_list_build"}
+
+
+def traffic_table(workload):
+    """HBM bytes per launch from the committed counter summary of the
+    workload, if it was taken from the current kernel sources (else {})."""
+    from paper_2205_13824_amd import profsummary
+
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
+    if not os.path.exists(path):
+        return {}
+    sha, tab = profsummary.read_traffic(path)
+    return tab if sha == profsummary.sources_sha256() else {}
+
+
+def traffic_of(tab, key, fp64):
+    want = f"{KERNEL_NAMES[key]}<{'true' if fp64 else 'false'}"
+    for k, (rd, wr) in tab.items():
+        if k == want + ">" or k.startswith(want + ","):
+            return rd + wr
+    return None
+
+
+def rooflines(kernels, n, P, near_pairs, fp64, traffic=None):
+    """Per kernel: algorithmic flops per launch / measured launch time (HIP
+    events, as in the timed steps) against the published vector peak of the
+    precision; the same with the kernel alone on the device; and the work in
+    VALU issue slots against the slot rate."""
     units = {"rho": n * P, "far": n * P, "far_side": n * P, "near": near_pairs, "near_cells": near_pairs}
     kind = {"rho": "rho", "far": "far", "far_side": "far", "near": "near", "near_cells": "near"}
     peak = PEAK_FP64_TFLOPS if fp64 else PEAK_FP32_TFLOPS
@@ -162,8 +198,11 @@ def rooflines(kernels, n, P, near_pairs, fp64):
         flops = units[k] * FLOPS[kind[k]]
         achieved = flops / t / 1e12
         out[k] = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                  "traffic": None, "units_per_launch": units[k], "flops_per_unit": FLOPS[kind[k]],
-                  "us_per_launch": v["us_per_launch"], "launches": v["launches"]}
+                  "traffic": traffic_of(traffic or {}, k, fp64), "units_per_launch": units[k],
+                  "flops_per_unit": FLOPS[kind[k]], "us_per_launch": v["us_per_launch"], "launches": v["launches"]}
+        if "us_alone" in v:
+            a = flops / (v["us_alone"] * 1e-6) / 1e12
+            out[k]["alone"] = {"us_per_launch": v["us_alone"], "achieved": a, "frac": a / peak}
         if not fp64:
             slots = units[k] * SLOTS[kind[k]] / t
             out[k]["lane_slots"] = {"achieved": slots / 1e12, "peak": PEAK_VALU_SLOTS / 1e12,
@@ -265,7 +304,7 @@ def other_workloads(R, W, torch, args, near_pairs_c2=None):
     r32t = run_leg(R, torch, c2, R.RBSOG_FP32C, args, steps, near_table=True, autotune=not args.no_autotune,
                    profile_steps=5)
     pairs2 = count_near_pairs(R, c2)
-    rl2 = rooflines(r32["kernels"], n2, c2["P"], pairs2, False)
+    rl2 = rooflines(r32["kernels"], n2, c2["P"], pairs2, False, traffic_table("c2_electrolyte300k"))
     out["electrolyte_300k"] = {
         "workload": f"{n2}-ion +-1 electrolyte, density 0.1, RSA d_min=1, r_c=3.5, P={c2['P']}, velocity-Verlet",
         "fp32c": {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "shapes": r32["shapes"]},
@@ -353,8 +392,9 @@ def main():
            "far": relrms(r32["Ff0"], r64["Ff0"])}
     log(f"[bench] FP32C vs FP64 force relrms: {err}")
     pairs = count_near_pairs(R, wl)
-    rl32 = rooflines(r32["kernels"], n, P, pairs, False)
-    rl64 = rooflines(r64["kernels"], n, P, pairs, True)
+    traffic = traffic_table("c5_ions20M")
+    rl32 = rooflines(r32["kernels"], n, P, pairs, False, traffic)
+    rl64 = rooflines(r64["kernels"], n, P, pairs, True, traffic)
     out = {
         "metric": METRIC,
         "value": r32["value"],

@@ -141,7 +141,8 @@ rbsog_status rbsog_sog_table1(int32_t row, double rc, rbsog_sog *out);
 
 /* Creates a context for one periodic system (Sec. 2 problem statement;
  * Algorithm 1, step 1): a batch of one.
- *   n     number of particles, >= 2
+ *   n     number of particles, 2 <= n <= 2^28 (a near-list entry holds a
+ *         particle slot in 28 bits)
  *   pos   host, n x 3, any finite values (wrapped into the box)
  *   q     host, n charges, finite, neutral within opts->neutral_tol
  *   box   host, 3 side lengths > 0
@@ -161,7 +162,8 @@ rbsog_status rbsog_init(rbsog_ctx **out, int64_t n, const double *pos, const dou
  * [offsets[s], offsets[s+1]) of pos (n x 3) and q, box boxes[3s..3s+2], split
  * sog[s], cutoff rc[s], P[s] wave vectors per evaluation and sampler key
  * seeds[s]; each is validated as by rbsog_init (errors name the system).
- *   offsets  host n_sys+1 int64, offsets[0] = 0, at least 2 particles each
+ *   offsets  host n_sys+1 int64, offsets[0] = 0, at least 2 particles each,
+ *            at most 2^28 in all
  * Precision, device, stream, mass and graphs of opts apply to all systems. */
 rbsog_status rbsog_init_batch(rbsog_ctx **out, int32_t n_sys, const int64_t *offsets,
                               const double *pos, const double *q, const double *boxes,
@@ -403,10 +405,14 @@ rbsog_status rbsog_debug_pairs(rbsog_ctx *ctx, int32_t sys, int32_t *kinds, int6
                                int64_t cap);
 rbsog_status rbsog_debug_list(rbsog_ctx *ctx, int32_t sys, int64_t *row_ptr, int32_t *cols, int64_t cap);
 
-/* Per-kernel timing with HIP events on the context's stream.  enable != 0
- * starts recording (and clears the totals).  rbsog_profile_read returns the
- * name, summed milliseconds and launch count of kernel idx (E_ARG past the
- * last one). */
+/* Per-kernel timing with HIP events; later steps launch kernel by kernel (no
+ * graphs).  enable 1: every kernel alone on the context's stream (its time
+ * with the whole device); enable 2: as in the steps, the structure factor (and
+ * the far force when every step builds) on the second stream beside the
+ * near part, each kernel timed on the stream it runs on (its time while it
+ * shares the device); 0 stops; 1 and 2 clear the totals; other values E_ARG.
+ * rbsog_profile_read returns the name, summed milliseconds and launch count
+ * of kernel idx (E_ARG past the last one). */
 rbsog_status rbsog_profile(rbsog_ctx *ctx, int32_t enable);
 rbsog_status rbsog_profile_read(rbsog_ctx *ctx, int32_t idx, const char **name, double *ms,
                                 int64_t *launches);

@@ -172,7 +172,7 @@ struct rbsog_ctx {
     int64_t adapt_steps = 0, adapt_nb0 = 0;
     int64_t adapt_window = kAdaptSteps;  // steps to the next check
     int32_t hold = 0, hold_len = 4;
-    uint2 *pairs = nullptr;
+    uint32_t *pairs = nullptr;
     int32_t *pcnt = nullptr, *rebuild = nullptr, *pmax = nullptr;
     int64_t icap = 0;
     int64_t *nbuild = nullptr;
@@ -233,7 +233,9 @@ struct rbsog_ctx {
     double graph_dt_m[2][GV_COUNT] = {};
     bool msd_on = false;  // displacements tracked since rbsog_set_msd_origin
     // profiling
-    bool prof_on = false;
+    // per-kernel timing: 0 off, 1 every kernel alone on the one stream, 2 as
+    // in the steps (the second stream kept, events on each kernel's stream)
+    int prof_on = 0;
     ProfEntry prof[K_COUNT];
     std::vector<hipEvent_t> ev_pool;
     struct Pending {
@@ -395,19 +397,24 @@ rbsog_status prof_collect(rbsog_ctx *c) {
 }
 
 template <class F>
-rbsog_status timed(rbsog_ctx *c, int kid, F &&launch) {
+rbsog_status timed_on(rbsog_ctx *c, int kid, hipStream_t s, F &&launch) {
     if (!c->prof_on) {
         launch();
         return RBSOG_OK;
     }
     hipEvent_t a = get_event(c), b = get_event(c);
     if (!a || !b) return fail(c, RBSOG_E_DEVICE, "hipEventCreate failed");
-    HIPCHK(c, hipEventRecord(a, c->stream));
+    HIPCHK(c, hipEventRecord(a, s));
     launch();
-    HIPCHK(c, hipEventRecord(b, c->stream));
+    HIPCHK(c, hipEventRecord(b, s));
     c->pending.push_back({kid, a, b});
     if (c->pending.size() > 8192) return prof_collect(c);
     return RBSOG_OK;
+}
+
+template <class F>
+rbsog_status timed(rbsog_ctx *c, int kid, F &&launch) {
+    return timed_on(c, kid, c->stream, launch);
 }
 
 // ---- device orchestration --------------------------------------------------------
@@ -599,8 +606,8 @@ rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt, bool kinetic, 
     // the structure factor and its reduction need the copy of the positions
     // and the k records staged by the kick/drift kernel only: they run on the
     // side stream beside the re-sort and the near part (one stream while
-    // profiling, so that each kernel is timed alone)
-    const bool fork = !c->prof_on;
+    // profiling kernels alone)
+    const bool fork = c->prof_on != 1;
     // building at every step, the far force joins them there (the near part
     // is long enough to hide it); it is then read back in the new order
     const bool far_side = a.always_build != 0;
@@ -608,9 +615,10 @@ rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt, bool kinetic, 
     if (fork) {
         HIPCHK(c, hipEventRecord(c->ev_fork, s));
         HIPCHK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
-        launch_rho(a, f64, c->rho_items, c->n_rho, c->side);
-        launch_rho_reduce(a, c->side);
-        if (far_side) launch_far_side(a, f64, c->far_items, c->n_far, fb, c->side);
+        TRY(timed_on(c, K_RHO, c->side, [&] { launch_rho(a, f64, c->rho_items, c->n_rho, c->side); }));
+        TRY(timed_on(c, K_RHORED, c->side, [&] { launch_rho_reduce(a, c->side); }));
+        if (far_side)
+            TRY(timed_on(c, K_FARSIDE, c->side, [&] { launch_far_side(a, f64, c->far_items, c->n_far, fb, c->side); }));
         HIPCHK(c, hipEventRecord(c->ev_join, c->side));
     }
     if (!a.always_build) TRY(timed(c, K_BIN, [&] { launch_bin(a, s); }));
@@ -773,8 +781,8 @@ rbsog_status size_list(rbsog_ctx *c, int64_t largest) {
     const int64_t want = kListWaves * ((2 * std::max<int64_t>(largest, 64) + 63) / 64 * 64);
     if (c->pairs && want <= c->icap) return RBSOG_OK;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    uint2 *np = nullptr;
-    if (hipMalloc((void **)&np, (size_t)c->n_list * (size_t)want * sizeof(uint2)) != hipSuccess)
+    uint32_t *np = nullptr;
+    if (hipMalloc((void **)&np, (size_t)c->n_list * (size_t)want * sizeof(uint32_t)) != hipSuccess)
         return fail(c, RBSOG_E_OOM, "pair list of %lld x %lld entries", (long long)c->n_list, (long long)want);
     if (c->pairs) {
         c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), (void *)c->pairs), c->allocs.end());
@@ -1522,7 +1530,7 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     if (offsets[0] != 0) return fail(nullptr, RBSOG_E_ARG, "offsets[0] must be 0");
     for (int32_t s = 0; s < nsys; ++s)
         if (offsets[s + 1] < offsets[s] + 2) return fail(nullptr, RBSOG_E_ARG, "system %d has fewer than 2 particles", s);
-    if (offsets[nsys] > (int64_t)INT32_MAX) return fail(nullptr, RBSOG_E_ARG, "more than 2^31-1 particles");
+    if (offsets[nsys] > kMaxParticles) return fail(nullptr, RBSOG_E_ARG, "more than 2^28 particles");
     rbsog_opts o;
     rbsog_default_opts(&o);
     if (opts) o = *opts;
@@ -1801,7 +1809,7 @@ rbsog_status rbsog_init(rbsog_ctx **out, int64_t n, const double *pos, const dou
                         const rbsog_sog *sog, double rc, int32_t P, uint64_t seed, const rbsog_opts *opts) {
     if (!out) return fail(nullptr, RBSOG_E_ARG, "out is null");
     *out = nullptr;
-    if (n < 2 || n > (int64_t)INT32_MAX) return fail(nullptr, RBSOG_E_ARG, "n must be in [2, 2^31-1]");
+    if (n < 2 || n > kMaxParticles) return fail(nullptr, RBSOG_E_ARG, "n must be in [2, 2^28]");
     const int64_t offsets[2] = {0, n};
     return init_batch(out, 1, offsets, pos, q, box, sog, &rc, &P, &seed, opts);
 }
@@ -2355,12 +2363,12 @@ rbsog_status rbsog_debug_list(rbsog_ctx *c, int32_t sys, int64_t *row_ptr, int32
     const SysHost &h = c->sys[sys];
     const int64_t nit = h.it1 - h.it0, seg = c->icap / kListWaves;
     std::vector<int32_t> pc((size_t)(nit * kListWaves));
-    std::vector<uint2> ent((size_t)(nit * c->icap));
+    std::vector<uint32_t> ent((size_t)(nit * c->icap));
     std::vector<int32_t> id;
     TRY(current_ids(c, id));
     HIPCHK(c, hipMemcpy(pc.data(), c->pcnt + (int64_t)h.it0 * kListWaves, pc.size() * sizeof(int32_t),
                         hipMemcpyDeviceToHost));
-    HIPCHK(c, hipMemcpy(ent.data(), c->pairs + (int64_t)h.it0 * c->icap, ent.size() * sizeof(uint2),
+    HIPCHK(c, hipMemcpy(ent.data(), c->pairs + (int64_t)h.it0 * c->icap, ent.size() * sizeof(uint32_t),
                         hipMemcpyDeviceToHost));
     std::vector<uint2> pairs;
     for (int64_t it = 0; it < nit; ++it) {
@@ -2368,9 +2376,9 @@ rbsog_status rbsog_debug_list(rbsog_ctx *c, int32_t sys, int64_t *row_ptr, int32
         for (int w = 0; w < kListWaves; ++w) {
             const int64_t base = it * c->icap + w * seg;
             for (int32_t k = 0; k < pc[(size_t)(it * kListWaves + w)]; ++k) {
-                const uint2 e = ent[(size_t)(base + k)];
-                const int64_t home = t0 + w * (kListHomes / kListWaves) + e.x;
-                pairs.push_back(make_uint2((uint32_t)id[(size_t)home], (uint32_t)id[e.y]));
+                const uint32_t e = ent[(size_t)(base + k)];
+                const int64_t home = t0 + w * (kListHomes / kListWaves) + (e >> kListSlotBits);
+                pairs.push_back(make_uint2((uint32_t)id[(size_t)home], (uint32_t)id[e & kListSlotMask]));
             }
         }
     }
@@ -2379,8 +2387,9 @@ rbsog_status rbsog_debug_list(rbsog_ctx *c, int32_t sys, int64_t *row_ptr, int32
 
 rbsog_status rbsog_profile(rbsog_ctx *c, int32_t enable) {
     TRY(check_ctx(c));
+    if (enable < 0 || enable > 2) return fail(c, RBSOG_E_ARG, "enable must be 0, 1 or 2");
     TRY(prof_collect(c));
-    c->prof_on = enable != 0;
+    c->prof_on = enable;
     if (enable)
         for (int k = 0; k < K_COUNT; ++k) {
             c->prof[k].ms = 0.0;
@@ -2529,7 +2538,7 @@ rbsog_status write_state(rbsog_ctx *c, StateWriter &w) {
         w.raw(pc.data(), (int64_t)pc.size() * 4);
         const int64_t seg = c->icap / kListWaves;
         for (size_t g = 0; g < pc.size(); ++g) {
-            const int64_t bytes = (int64_t)std::min<int64_t>(pc[g], seg) * (int64_t)sizeof(uint2);
+            const int64_t bytes = (int64_t)std::min<int64_t>(pc[g], seg) * (int64_t)sizeof(uint32_t);
             if (w.buf && w.pos + bytes <= w.cap && bytes > 0) {
                 HIPCHK(c, hipMemcpy(w.buf + w.pos, c->pairs + (int64_t)g * seg, (size_t)bytes,
                                     hipMemcpyDeviceToHost));
@@ -2638,8 +2647,8 @@ rbsog_status rbsog_load_state(rbsog_ctx *c, const void *buf, int64_t len) {
     TRY(upload_cell_items(c));
     if (skin_cur > 0.0 && icap != c->icap) {
         // a list of the saved capacity
-        uint2 *np = nullptr;
-        if (hipMalloc((void **)&np, (size_t)c->n_list * (size_t)icap * sizeof(uint2)) != hipSuccess)
+        uint32_t *np = nullptr;
+        if (hipMalloc((void **)&np, (size_t)c->n_list * (size_t)icap * sizeof(uint32_t)) != hipSuccess)
             return fail(c, RBSOG_E_OOM, "pair list of %lld x %lld entries", (long long)c->n_list, (long long)icap);
         if (c->pairs) {
             c->allocs.erase(std::remove(c->allocs.begin(), c->allocs.end(), (void *)c->pairs), c->allocs.end());
@@ -2676,7 +2685,7 @@ rbsog_status rbsog_load_state(rbsog_ctx *c, const void *buf, int64_t len) {
         HIPCHK(c, hipMemcpy(c->pcnt, pc.data(), pc.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         const int64_t seg = c->icap / kListWaves;
         for (size_t g = 0; g < pc.size(); ++g) {
-            const int64_t bytes = (int64_t)std::min<int64_t>(pc[g], seg) * (int64_t)sizeof(uint2);
+            const int64_t bytes = (int64_t)std::min<int64_t>(pc[g], seg) * (int64_t)sizeof(uint32_t);
             if (r.pos + bytes > len) return fail(c, RBSOG_E_ARG, "truncated state");
             if (bytes > 0)
                 HIPCHK(c, hipMemcpy(c->pairs + (int64_t)g * seg, r.buf + r.pos, (size_t)bytes, hipMemcpyHostToDevice));

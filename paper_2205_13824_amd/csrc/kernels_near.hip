@@ -583,7 +583,7 @@ __device__ __forceinline__ void eval_ring(const uint2 *ring, const HomeView<F64>
 // list pass reads the segment.
 template <bool F64, int Q, bool DBG>
 __device__ __forceinline__ void drain_ring(const BuildLds<F64, Q> &L, const HomeView<F64> &hv,
-                                           uint2 *__restrict__ out, int64_t cap, const Geom &g,
+                                           uint32_t *__restrict__ out, int64_t cap, const Geom &g,
                                            typename CoefOf<F64>::type *co, const uint32_t *__restrict__ su,
                                            const double *__restrict__ sx, const double *__restrict__ sq,
                                            const float *__restrict__ sqf, int64_t n, const float4 *__restrict__ tbl,
@@ -592,7 +592,7 @@ __device__ __forceinline__ void drain_ring(const BuildLds<F64, Q> &L, const Home
     const bool have = lane < count;
     const int idx = head + lane;
     const uint2 qe = have ? L.q[idx & (Q - 1)] : make_uint2(0u, 0u);
-    if (have && out && idx < cap) out[idx] = qe;
+    if (have && out && idx < cap) out[idx] = (qe.x << kListSlotBits) | qe.y;
     eval_pair<F64, false, DBG>(g, co, hv, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qe, have, e);
 }
 
@@ -671,7 +671,7 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
     const int32_t t = (int32_t)std::min<int64_t>(item.t0 + wave * kQuarter, item.t1);
     const int32_t t_end = (int32_t)std::min<int64_t>(item.t0 + (wave + 1) * kQuarter, item.t1);
     const int64_t cap = a.icap / kNW;
-    uint2 *out = a.pairs ? a.pairs + (int64_t)it * a.icap + wave * cap : nullptr;
+    uint32_t *out = a.pairs ? a.pairs + (int64_t)it * a.icap + wave * cap : nullptr;
     const bool rel = g.nc[0] >= 4 && g.nc[1] >= 4 && g.nc[2] >= 4;
     if (lane < t_end - t) {
         const int64_t tt = t + lane;
@@ -944,7 +944,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
     wave_sync();
     const int64_t cap = a.icap / kNW;
     const int32_t cnt = ((CI32 *)a.pcnt)[(int64_t)it * kNW + w];
-    const uint2 *__restrict__ pl = a.pairs + (int64_t)it * a.icap + w * cap;
+    const uint32_t *__restrict__ pl = a.pairs + (int64_t)it * a.icap + w * cap;
     HomeView<F64> hv;
     hv.hu = L.hu;
     hv.hq = L.hq;
@@ -958,7 +958,10 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
     // the segment in the build's chunks of 64, in order; entries are loaded
     // two chunks ahead and the candidates' data one chunk ahead, so that the
     // loads of the next chunks run while this one is evaluated
-    auto entry = [&](int32_t c) { return c + lane < cnt ? pl[c + lane] : make_uint2(0u, 0u); };
+    auto entry = [&](int32_t c) {
+        const uint32_t v = c + lane < cnt ? pl[c + lane] : 0u;
+        return make_uint2(v >> kListSlotBits, v & kListSlotMask);
+    };
     uint2 qe1 = entry(0), qe2 = entry(64);
     PairData<F64> pd1 = load_pair<F64>(su, sx, sq, sqf, n, qe1, lane < cnt);
     for (int32_t c = 0; c < cnt; c += 64) {

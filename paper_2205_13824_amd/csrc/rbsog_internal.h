@@ -160,6 +160,13 @@ struct StateBufs {
     int32_t *id;
     double *dsp;  // displacement since the mean-square-displacement origin (sum of the drifts)
 };
+// A near-list entry packs the home (index among the 16 homes of a wave's
+// quarter of an item) above the candidate's slot, so slots must stay below
+// 2^kListSlotBits (the limit on the particles of a context).
+constexpr int kListSlotBits = 28;
+constexpr uint32_t kListSlotMask = (1u << kListSlotBits) - 1u;
+constexpr int64_t kMaxParticles = (int64_t)1 << kListSlotBits;
+
 struct EvalArgs {
     int64_t N;             // particles over all systems
     int64_t C;             // cells over all systems
@@ -184,11 +191,12 @@ struct EvalArgs {
     double *Fn, *Ff;       // forces in slot order
     double *Ff_side;       // build-every-step mode: far forces in the order before the re-sort
     // Verlet list: rebuild flag (set by the displacement check, cleared by the
-    // near kernel), pairs (home index in the item, candidate slot), counts,
+    // near kernel), pairs (one u32 each: home index in the wave's quarter of
+    // the item in the top kListHomeBits bits, candidate slot below), counts,
     // capacity per item, largest count of the latest build, builds made
     int32_t *rebuild;
     int32_t always_build;  // nonzero: every evaluation builds (no displacement check, no list kept)
-    uint2 *pairs;
+    uint32_t *pairs;
     int32_t *pcnt;
     int64_t icap;
     int32_t *pmax;

@@ -385,8 +385,10 @@ def rbsog_debug_list(ctx, sys: int = 0):
     return _csr_call(ctx, sys, lib().rbsog_debug_list)
 
 
-def rbsog_profile(ctx, enable: bool):
-    _check(lib().rbsog_profile(ctx, 1 if enable else 0), ctx)
+def rbsog_profile(ctx, enable):
+    """enable: False/0 off, True/1 every kernel alone, 2 as in the steps
+    (second stream kept)."""
+    _check(lib().rbsog_profile(ctx, int(enable)), ctx)
 
 
 def rbsog_profile_read(ctx) -> dict:
