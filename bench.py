@@ -54,6 +54,13 @@ SLOTS = {"rho": 5 + 2 * TRANS_SLOTS, "far": 8 + 2 * TRANS_SLOTS, "near": 40 + 18
 DEVICE_CHAINS = 64
 DT = 1e-3
 
+# workloads the timed legs can run on: (generator in workloads.py, description)
+WORKLOADS = {
+    "ions20M": ("c5_large", "+-1 ions (272^3 jittered simple-cubic lattice), density 0.1, r_c=3.5"),
+    "electrolyte300k": ("c2_electrolyte", "+-1 electrolyte, density 0.1, RSA d_min=1, r_c=3.5"),
+    "water3M": ("c3_water", "water sites (10^6 SPC/E-shaped 3-site molecules as point charges), r_c=10"),
+}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -73,6 +80,9 @@ def parse():
     # after the bench: device-to-device copies of this many MiB, the reference
     # kernel against which rocprofv3's FETCH_SIZE / WRITE_SIZE are scaled
     ap.add_argument("--copy-probe-mib", type=int, default=0)
+    # the workload of the two timed legs (profiling runs of the other
+    # workloads name them here; the reported headline is ions20M)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="ions20M")
     return ap.parse_args()
 
 
@@ -382,7 +392,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     t0 = time.time()
-    wl = W.c5_large()
+    gen, desc = WORKLOADS[args.workload]
+    wl = getattr(W, gen)()
     n, P = len(wl["q"]), wl["P"]
     log(f"[bench] headline workload built in {time.time() - t0:.1f} s: n={n} L={wl['box'][0]:.4f} P={P}")
 
@@ -392,7 +403,7 @@ def main():
            "far": relrms(r32["Ff0"], r64["Ff0"])}
     log(f"[bench] FP32C vs FP64 force relrms: {err}")
     pairs = count_near_pairs(R, wl)
-    traffic = traffic_table("c5_ions20M")
+    traffic = traffic_table(args.workload)
     rl32 = rooflines(r32["kernels"], n, P, pairs, False, traffic)
     rl64 = rooflines(r64["kernels"], n, P, pairs, True, traffic)
     out = {
@@ -408,9 +419,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{n} +-1 ions (272^3 jittered simple-cubic lattice), density 0.1, r_c=3.5, "
-                               f"P={P}, Table 1 row 2, velocity-Verlet dt=1e-3 from a Maxwellian at T=1, "
-                               f"wave vectors drawn on the device ({DEVICE_CHAINS} Metropolis-Hastings chains)",
+        "config": {"workload": f"{n} {desc}, P={P}, Table 1 row 2, velocity-Verlet dt=1e-3 from a Maxwellian "
+                               f"at T=1, wave vectors drawn on the device ({DEVICE_CHAINS} Metropolis-Hastings chains)",
+                   "name": args.workload,
                    "n": n, "P": P, "rc": wl["rc"], "box": float(wl["box"][0])},
         "fp64": {"value": r64["value"], "ms_per_step": r64["ms_per_step"], "dtype": "f64",
                  "roofline": dominant(rl64), "rooflines": rl64},
@@ -428,7 +439,7 @@ def main():
         "kernels_fp64": r64["kernels"],
         "setup_s": {"fp32c": r32["setup_s"], "fp64": r64["setup_s"]},
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "ions20M":
         out["cpu_baseline"] = cpu_baseline(wl, P)
         log(f"[bench] cpu baseline: {out['cpu_baseline']['value']:.3e} particle-steps/s")
     del wl

@@ -387,15 +387,16 @@ rbsog_status rbsog_structure_factor_noalloc(int64_t n, const double *x, const do
                                             double *rho_im, void *stream);
 
 /* Debug record of the pairs the near kernels accept: with cap > 0 (at most
- * 2^31-1) every later evaluation records, from the near kernel that runs it
- * (the list build, the list pass or the fused cell kernel of the
+ * 2^31-1) every later evaluation records, from the near kernel that evaluates
+ * it (the list pass, which evaluates every evaluation with the near list, the
+ * ones with a list build included, or the fused cell kernel of the
  * build-every-step mode), each pair that passes the pair rule of the header's
  * conventions, as the kernel evaluates it; rbsog_step then launches kernel by
  * kernel (no graphs).  cap = 0 stops recording and frees the record.
  * rbsog_debug_pairs returns the latest evaluation's record for system sys as
  * CSR over local ids (rows ascending i, columns ascending j; each pair in both
- * orders), and in *kinds which kernels recorded: bit 0 the list build, bit 1
- * the list pass, bit 2 the fused cell kernel.  E_STATE if recording is off or
+ * orders), and in *kinds which kernels recorded: bit 1 the list pass, bit 2
+ * the fused cell kernel (bit 0 is not used).  E_STATE if recording is off or
  * the record overflowed; E_ARG (row_ptr filled) if cap is smaller than the
  * entry count.
  * rbsog_debug_list returns the near list of the latest build (the pairs within
@@ -441,6 +442,22 @@ rbsog_status rbsog_profile_read(rbsog_ctx *ctx, int32_t idx, const char **name, 
  * (then it must be loaded again or destroyed). */
 rbsog_status rbsog_save_state(rbsog_ctx *ctx, void *buf, int64_t cap, int64_t *size);
 rbsog_status rbsog_load_state(rbsog_ctx *ctx, const void *buf, int64_t len);
+
+/* Measured issue rates of the vector instructions the kernels are built
+ * from (the peaks their instruction counts are priced against; no passage of
+ * the paper: the method's work is stated per pair and per wave vector, the
+ * rate at which a device retires it is measured here).  Probe i runs
+ * independent chains of one instruction or mix on every lane of 16 waves per
+ * SIMD; rbsog_probe_name(i) names it (NULL past the last), rbsog_probe_count()
+ * gives how many there are.  rbsog_probe_rates times each probe reps times on
+ * its own stream of `device` (HIP events, best of reps) and writes
+ * lane-instructions per second (a mix counts each of its instructions) into
+ * rates[0 .. count-1] (host, n >= count entries).  E_ARG for a short array or
+ * reps < 1, E_DEVICE if a launch fails; messages at rbsog_last_error(NULL).
+ * Allocates and frees 4 MiB of device memory. */
+int32_t rbsog_probe_count(void);
+const char *rbsog_probe_name(int32_t i);
+rbsog_status rbsog_probe_rates(int32_t device, int32_t reps, double *rates, int32_t n);
 
 /* Blocks until all work of the context has finished. */
 rbsog_status rbsog_sync(rbsog_ctx *ctx);

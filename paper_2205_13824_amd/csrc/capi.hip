@@ -158,6 +158,8 @@ struct rbsog_ctx {
     int32_t *sys_of = nullptr, *ksys = nullptr;
     StateBufs buf[2] = {};
     uint32_t *u_tmp = nullptr, *u = nullptr;
+    uint4 *pk = nullptr;       // the list pass's gather records (EvalArgs::pk, pkx)
+    PosQ64 *pkx = nullptr;
     uint32_t *rs_u = nullptr;  // the structure factor's copy of the state
     float *rs_qf = nullptr;
     double *rs_x = nullptr, *rs_q = nullptr;
@@ -526,6 +528,8 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
     a.u = c->u;
     a.rs_u = c->rs_u;
     a.rs_qf = c->rs_qf;
+    a.pk = c->pk;
+    a.pkx = c->pkx;
     a.rs_x = c->rs_x;
     a.rs_q = c->rs_q;
     a.cell_of = c->cell_of;
@@ -772,13 +776,21 @@ rbsog_status request_build(rbsog_ctx *c) {
     return RBSOG_OK;
 }
 
-// Capacity of the pair list: every item holds kListWaves segments (one per
-// quarter of its homes) of icap / kListWaves pairs.  Sized from the largest
-// segment count of a build with room to spare; a build whose largest count
-// passes 3/4 of the capacity makes the next call grow it (and build again),
-// and one that overflows fails the call.
+// Capacity of the pair list: every item holds icap / kListHomes rows of
+// kListHomes entries, one column per home.  Sized from the largest count of
+// one home at a build with room to spare; a build whose largest count passes
+// 3/4 of the rows makes the next call grow it (and build again), and one that
+// overflows fails the call.
+// Rows of item it's block of the near list that hold entries: its longest
+// column (counts pc, kListHomes per item), at most the rows stored.
+int64_t list_rows(const std::vector<int32_t> &pc, int64_t it, int64_t icap) {
+    int64_t m = 0;
+    for (int h = 0; h < kListHomes; ++h) m = std::max<int64_t>(m, pc[(size_t)(it * kListHomes + h)]);
+    return std::min<int64_t>(m, icap / kListHomes);
+}
+
 rbsog_status size_list(rbsog_ctx *c, int64_t largest) {
-    const int64_t want = kListWaves * ((2 * std::max<int64_t>(largest, 64) + 63) / 64 * 64);
+    const int64_t want = kListHomes * ((2 * std::max<int64_t>(largest, 8) + 3) / 4 * 4);
     if (c->pairs && want <= c->icap) return RBSOG_OK;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     uint32_t *np = nullptr;
@@ -792,7 +804,7 @@ rbsog_status size_list(rbsog_ctx *c, int64_t largest) {
     c->allocs.push_back(np);
     c->icap = want;
     // no item of the new buffer holds pairs until the next build
-    HIPCHK(c, hipMemset(c->pcnt, 0, (size_t)kListWaves * c->n_list * sizeof(int32_t)));
+    HIPCHK(c, hipMemset(c->pcnt, 0, (size_t)kListHomes * c->n_list * sizeof(int32_t)));
     drop_graphs(c);
     return request_build(c);
 }
@@ -802,12 +814,12 @@ rbsog_status size_list(rbsog_ctx *c, int64_t largest) {
 rbsog_status check_list(rbsog_ctx *c, int32_t flag) {
     if (flag & 8) {
         c->poisoned = true;
-        return fail(c, RBSOG_E_STATE, "a near-list segment exceeded its capacity of %lld pairs",
-                    (long long)(c->icap / kListWaves));
+        return fail(c, RBSOG_E_STATE, "a home's near list exceeded its capacity of %lld pairs",
+                    (long long)(c->icap / kListHomes));
     }
     int32_t pm = 0;
     HIPCHK(c, hipMemcpy(&pm, c->pmax, sizeof pm, hipMemcpyDeviceToHost));
-    if (4 * (int64_t)pm > 3 * (c->icap / kListWaves)) TRY(size_list(c, pm));
+    if (4 * (int64_t)pm > 3 * (c->icap / kListHomes)) TRY(size_list(c, pm));
     return RBSOG_OK;
 }
 
@@ -1387,8 +1399,12 @@ rbsog_status autotune_now(rbsog_ctx *c, int32_t reps) {
         for (int32_t s = 0; s < c->nsys; ++s) TRY(upload_cursor(c, s));
         TRY(request_build(c));
         EvalArgs a = build();
-        if (every) launch_near_cells(a, f64, c->near_items, c->n_near, c->cell_slots, st);
-        else launch_list_build(a, f64, c->list_items, c->n_list, c->build_slots, st);
+        if (every) {
+            launch_near_cells(a, f64, c->near_items, c->n_near, c->cell_slots, st);
+        } else {
+            launch_list_build(a, f64, c->list_items, c->n_list, c->build_slots, st);
+            launch_near(a, f64, c->list_items, c->n_list, st);
+        }
         // the far force of the current order (the re-sorts above left the
         // side copy of the positions out of step with the permutation)
         a.rebuild = nullptr;
@@ -1642,6 +1658,8 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     ALLOC(ksys, K);
     ALLOC(u_tmp, 3 * N);
     ALLOC(u, 3 * N);
+    ALLOC(pk, N);
+    if (c->prec == RBSOG_FP64) ALLOC(pkx, N);
     if (c->prec != RBSOG_FP64) {
         ALLOC(rs_u, 3 * N);
         ALLOC(rs_qf, N);
@@ -1694,7 +1712,7 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     ALLOC(list_items, near_cap);
     ALLOC(near_items, C);
     ALLOC(epart_cells, C);
-    ALLOC(pcnt, kListWaves * near_cap);
+    ALLOC(pcnt, kListHomes * near_cap);
     ALLOC(cell_sorted, N);
     ALLOC(rebuild, 1);
     ALLOC(pmax, 1);
@@ -2361,24 +2379,22 @@ rbsog_status rbsog_debug_list(rbsog_ctx *c, int32_t sys, int64_t *row_ptr, int32
     if (c->evals == 0) return fail(c, RBSOG_E_STATE, "no force evaluation yet");
     if (!row_ptr) return fail(c, RBSOG_E_ARG, "row_ptr is null");
     const SysHost &h = c->sys[sys];
-    const int64_t nit = h.it1 - h.it0, seg = c->icap / kListWaves;
-    std::vector<int32_t> pc((size_t)(nit * kListWaves));
+    const int64_t nit = h.it1 - h.it0;
+    std::vector<int32_t> pc((size_t)(nit * kListHomes));
     std::vector<uint32_t> ent((size_t)(nit * c->icap));
     std::vector<int32_t> id;
     TRY(current_ids(c, id));
-    HIPCHK(c, hipMemcpy(pc.data(), c->pcnt + (int64_t)h.it0 * kListWaves, pc.size() * sizeof(int32_t),
+    HIPCHK(c, hipMemcpy(pc.data(), c->pcnt + (int64_t)h.it0 * kListHomes, pc.size() * sizeof(int32_t),
                         hipMemcpyDeviceToHost));
     HIPCHK(c, hipMemcpy(ent.data(), c->pairs + (int64_t)h.it0 * c->icap, ent.size() * sizeof(uint32_t),
                         hipMemcpyDeviceToHost));
     std::vector<uint2> pairs;
     for (int64_t it = 0; it < nit; ++it) {
         const int64_t t0 = h.p0 + it * kListHomes;
-        for (int w = 0; w < kListWaves; ++w) {
-            const int64_t base = it * c->icap + w * seg;
-            for (int32_t k = 0; k < pc[(size_t)(it * kListWaves + w)]; ++k) {
-                const uint32_t e = ent[(size_t)(base + k)];
-                const int64_t home = t0 + w * (kListHomes / kListWaves) + (e >> kListSlotBits);
-                pairs.push_back(make_uint2((uint32_t)id[(size_t)home], (uint32_t)id[e & kListSlotMask]));
+        for (int hh = 0; hh < kListHomes; ++hh) {
+            for (int32_t k = 0; k < pc[(size_t)(it * kListHomes + hh)]; ++k) {
+                const uint32_t e = ent[(size_t)(it * c->icap + (int64_t)k * kListHomes + hh)];
+                pairs.push_back(make_uint2((uint32_t)id[(size_t)(t0 + hh)], (uint32_t)id[e & kListSlotMask]));
             }
         }
     }
@@ -2529,19 +2545,18 @@ rbsog_status write_state(rbsog_ctx *c, StateWriter &w) {
         }
         w.pos += a.second;
     }
-    // the near list, segment by segment (used entries)
+    // the near list, item by item: the counts, then the rows up to the
+    // item's longest column
     const bool list = c->skin_cur > 0.0 && c->pairs;
     w.val<int32_t>(list ? 1 : 0);
     if (list) {
-        std::vector<int32_t> pc((size_t)kListWaves * c->n_list);
+        std::vector<int32_t> pc((size_t)kListHomes * c->n_list);
         HIPCHK(c, hipMemcpy(pc.data(), c->pcnt, pc.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
         w.raw(pc.data(), (int64_t)pc.size() * 4);
-        const int64_t seg = c->icap / kListWaves;
-        for (size_t g = 0; g < pc.size(); ++g) {
-            const int64_t bytes = (int64_t)std::min<int64_t>(pc[g], seg) * (int64_t)sizeof(uint32_t);
+        for (int64_t it = 0; it < c->n_list; ++it) {
+            const int64_t bytes = list_rows(pc, it, c->icap) * kListHomes * (int64_t)sizeof(uint32_t);
             if (w.buf && w.pos + bytes <= w.cap && bytes > 0) {
-                HIPCHK(c, hipMemcpy(w.buf + w.pos, c->pairs + (int64_t)g * seg, (size_t)bytes,
-                                    hipMemcpyDeviceToHost));
+                HIPCHK(c, hipMemcpy(w.buf + w.pos, c->pairs + it * c->icap, (size_t)bytes, hipMemcpyDeviceToHost));
             } else if (w.buf && bytes > 0) {
                 w.overflow = true;
             }
@@ -2679,16 +2694,15 @@ rbsog_status rbsog_load_state(rbsog_ctx *c, const void *buf, int64_t len) {
     const int32_t list = r.val<int32_t>();
     if (list) {
         if (!(skin_cur > 0.0)) return fail(c, RBSOG_E_ARG, "corrupt state");
-        std::vector<int32_t> pc((size_t)kListWaves * c->n_list);
+        std::vector<int32_t> pc((size_t)kListHomes * c->n_list);
         r.raw(pc.data(), (int64_t)pc.size() * 4);
         if (r.bad) return fail(c, RBSOG_E_ARG, "truncated state");
         HIPCHK(c, hipMemcpy(c->pcnt, pc.data(), pc.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-        const int64_t seg = c->icap / kListWaves;
-        for (size_t g = 0; g < pc.size(); ++g) {
-            const int64_t bytes = (int64_t)std::min<int64_t>(pc[g], seg) * (int64_t)sizeof(uint32_t);
+        for (int64_t it = 0; it < c->n_list; ++it) {
+            const int64_t bytes = list_rows(pc, it, c->icap) * kListHomes * (int64_t)sizeof(uint32_t);
             if (r.pos + bytes > len) return fail(c, RBSOG_E_ARG, "truncated state");
             if (bytes > 0)
-                HIPCHK(c, hipMemcpy(c->pairs + (int64_t)g * seg, r.buf + r.pos, (size_t)bytes, hipMemcpyHostToDevice));
+                HIPCHK(c, hipMemcpy(c->pairs + it * c->icap, r.buf + r.pos, (size_t)bytes, hipMemcpyHostToDevice));
             r.pos += bytes;
         }
     }

@@ -194,7 +194,7 @@ __global__ __launch_bounds__(1024, F64 ? 1 : 8) void k_rho(EvalArgs a, const Rho
                                 for (int g = 0; g < 8; ++g) p[g] = st32[h + (g0 + g) * sd];
 #pragma unroll
                                 for (int g = 0; g < 8; ++g) {
-                                    const uint32_t t = mx * p[g].x + my * p[g].y + mz * p[g].z;
+                                    const uint32_t t = rmath::dot3_mod32_v(mx, my, mz, p[g].x, p[g].y, p[g].z);
                                     const float f = rmath::phase_rev(t);
                                     const float pq = __uint_as_float(p[g].w);
                                     rf = fmaf(pq, __builtin_amdgcn_cosf(f), rf);
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(1024, F64 ? 1 : 8) void k_rho(EvalArgs a, const Rho
                         float rf = 0.f, fi = 0.f;
                         for (; h < cnt; h += sd) {
                             const uint4 p = st32[h];
-                            const uint32_t t = mx * p.x + my * p.y + mz * p.z;
+                            const uint32_t t = rmath::dot3_mod32_v(mx, my, mz, p.x, p.y, p.z);
                             const float f = rmath::phase_rev(t);
                             const float pq = __uint_as_float(p.w);
                             rf = fmaf(pq, __builtin_amdgcn_cosf(f), rf);
@@ -438,8 +438,8 @@ __device__ __forceinline__ void far_sum(CSys *sp, CRec64 *kb64, CRec32 *kb32, in
                 for (int h = 0; h < G; ++h) r[h] = ld(kb32 + e + h4 * G + h);
 #pragma unroll
                 for (int h = 0; h < G; ++h) {
-                    const uint32_t t = r[h].phi - ((uint32_t)r[h].mx * ux + (uint32_t)r[h].my * uy +
-                                                   (uint32_t)r[h].mz * uz);
+                    const uint32_t t = r[h].phi - rmath::dot3_mod32_s((uint32_t)r[h].mx, (uint32_t)r[h].my,
+                                                                      (uint32_t)r[h].mz, ux, uy, uz);
                     const float v = __builtin_amdgcn_sinf(rmath::phase_rev(t));
                     fx = fmaf(r[h].ax, v, fx);
                     fy = fmaf(r[h].ay, v, fy);
@@ -451,7 +451,7 @@ __device__ __forceinline__ void far_sum(CSys *sp, CRec64 *kb64, CRec32 *kb32, in
         float fx = 0.f, fy = 0.f, fz = 0.f;
         for (; e < P; ++e) {
             const KRec32 r = ld(kb32 + e);
-            const uint32_t t = r.phi - ((uint32_t)r.mx * ux + (uint32_t)r.my * uy + (uint32_t)r.mz * uz);
+            const uint32_t t = r.phi - rmath::dot3_mod32_s((uint32_t)r.mx, (uint32_t)r.my, (uint32_t)r.mz, ux, uy, uz);
             const float v = __builtin_amdgcn_sinf(rmath::phase_rev(t));
             fx = fmaf(r.ax, v, fx);
             fy = fmaf(r.ay, v, fy);

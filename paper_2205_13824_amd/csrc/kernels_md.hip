@@ -171,8 +171,11 @@ __global__ __launch_bounds__(kBlock) void k_kdq(EvalArgs a, int32_t pblocks) {
         d2 += dd * dd;
     }
     if (valid) {
-        if (a.rs_qf) a.rs_qf[t] = a.cur.qf[t];
+        const float qf = a.cur.qf[t];
+        if (a.rs_qf) a.rs_qf[t] = qf;
         if (a.rs_q) a.rs_q[t] = a.cur.q[t];
+        a.pk[t] = make_uint4(uq[0], uq[1], uq[2], __float_as_uint(qf));
+        if (a.pkx) a.pkx[t] = PosQ64{x[t], x[N + t], x[2 * N + t], a.cur.q[t]};
     }
     if (a.always_build) {
         // every evaluation builds: the cell and the histogram here (no bin pass)

@@ -358,61 +358,100 @@ struct PairData {
     double x[3];
 };
 
+// The candidate's data from its gather records: one 16-byte load (and one
+// 32-byte record in the FP64 form).
+template <bool F64>
+__device__ __forceinline__ PairData<F64> load_packed(const uint4 *__restrict__ pk, const PosQ64 *__restrict__ pkx,
+                                                     uint32_t j) {
+    PairData<F64> d;
+    const uint4 r = pk[j & kListSlotMask];
+    d.u[0] = r.x; d.u[1] = r.y; d.u[2] = r.z;
+    if constexpr (F64) {
+        const PosQ64 w = pkx[j & kListSlotMask];
+        d.x[0] = w.x; d.x[1] = w.y; d.x[2] = w.z;
+        d.q = w.q;
+    } else {
+        d.q = __uint_as_float(r.w);
+    }
+    return d;
+}
+
 template <bool F64>
 __device__ __forceinline__ PairData<F64> load_pair(const uint32_t *__restrict__ su, const double *__restrict__ sx,
                                                    const double *__restrict__ sq, const float *__restrict__ sqf,
                                                    int64_t n, uint2 qe, bool have) {
     PairData<F64> d;
-    const uint32_t j = have ? qe.y : 0u;
-    d.u[0] = su[j]; d.u[1] = su[n + j]; d.u[2] = su[2 * n + j];
+    // slots are below 2^28 (a context's limit): 32-bit byte offsets from the
+    // arrays' (scalar) bases
+    const uint32_t j = have ? (qe.y & kListSlotMask) : 0u;
+    const uint32_t o4 = j * 4u, o8 = j * 8u;
+    auto at4 = [&](const void *base) { return *(const uint32_t *)((const char *)base + o4); };
+    auto at8 = [&](const void *base) { return *(const double *)((const char *)base + o8); };
+    d.u[0] = at4(su); d.u[1] = at4(su + n); d.u[2] = at4(su + 2 * n);
     if constexpr (F64) {
-        d.q = sq[j];
-        d.x[0] = sx[j]; d.x[1] = sx[n + j]; d.x[2] = sx[2 * n + j];
+        d.q = at8(sq);
+        d.x[0] = at8(sx); d.x[1] = at8(sx + n); d.x[2] = at8(sx + 2 * n);
     } else {
-        d.q = sqf[j];
+        d.q = __uint_as_float(at4(sqf));
     }
     return d;
 }
 
-// SELF: the ring may hold the home itself (the fused cell kernel's test does
-// not leave it out); such an entry is rejected here by its slot.  DBG: record
-// every accepted pair (debug launches).
+// The home of a pair as the evaluation needs it: fixed-point coordinates,
+// its slot, charge, and the FP64 position in the FP64 form.
+template <bool F64>
+struct HomeData {
+    using R = typename std::conditional<F64, double, float>::type;
+    uint32_t u[3];
+    uint32_t slot;
+    R q;
+    double x[3];
+};
+
+// One pair (home h, candidate pd at slot cslot) when `have`: the pair rule at
+// the current positions (the fixed-point r^2 in FP32 decides below the lower
+// band edge, the exact FP64 rule inside the band), then the exact
+// displacement (fixed point for FP32C, wrapped FP64 coordinates for FP64),
+// the pair force on the home (fx, fy, fz) and, with energies, half the pair
+// energy (de).  Returns whether the pair was accepted; a rejected pair leaves
+// the outputs 0.  SELF: the candidate may be the home itself (the fused cell
+// kernel's test does not leave it out), rejected here by its slot.  DBG:
+// record every accepted pair (debug launches).
 template <bool F64, bool SELF = false, bool DBG = false>
-__device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>::type *co, const HomeView<F64> &L,
-                                            const float4 *__restrict__ tbl, float rin2, CSys *csp,
-                                             int lane, uint2 qe, bool have, const PairData<F64> &pd,
-                                            double &e) {
-    double de = 0.0;
-    using R = typename HomeView<F64>::R;
+__device__ __forceinline__ void pair_force(const Geom &g, typename CoefOf<F64>::type *co, const HomeData<F64> &h,
+                                           bool we, const PairRec *rec, const float4 *__restrict__ tbl, float rin2,
+                                           CSys *csp, uint32_t cslot, bool have, const PairData<F64> &pd,
+                                           typename HomeData<F64>::R &fx, typename HomeData<F64>::R &fy,
+                                           typename HomeData<F64>::R &fz, double &de) {
+    using R = typename HomeData<F64>::R;
     constexpr int NT = (F64 ? kTailDeg64 : kTailDeg32) + 1;
-    R fx = 0, fy = 0, fz = 0;
-    const int slot = have ? (int)qe.x : -1;
+    fx = 0; fy = 0; fz = 0;
+    de = 0.0;
     if (have) {
-        const uint4 h = L.hu[slot];
-        const uint32_t dux = pd.u[0] - h.x, duy = pd.u[1] - h.y, duz = pd.u[2] - h.z;
+        const uint32_t dux = pd.u[0] - h.u[0], duy = pd.u[1] - h.u[1], duz = pd.u[2] - h.u[2];
         const float ex_ = (float)(int32_t)dux * g.hf[0];
         const float ey_ = (float)(int32_t)duy * g.hf[1];
         const float ez_ = (float)(int32_t)duz * g.hf[2];
         const float r2f = ex_ * ex_ + ey_ * ey_ + ez_ * ez_;
         bool in = r2f <= g.band_lo_f;
         if (!in && r2f < g.band_hi_f) in = exact_in(g, dux, duy, duz);
-        if constexpr (SELF) in = in && qe.y != h.w;
+        if constexpr (SELF) in = in && cslot != h.slot;
         if constexpr (DBG) {
             if (in) {
-                const int32_t k = atomicAdd(L.rec->cnt, 1);
-                if (k < L.rec->cap) L.rec->out[k] = make_uint2((uint32_t)L.rec->id[h.w], (uint32_t)L.rec->id[qe.y]);
+                const int32_t k = atomicAdd(rec->cnt, 1);
+                if (k < rec->cap) rec->out[k] = make_uint2((uint32_t)rec->id[h.slot], (uint32_t)rec->id[cslot]);
             }
         }
         if (in) {
             R dx, dy, dz, qq;
             if constexpr (F64) {
-                dx = mi64(pd.x[0] - L.hx[0][slot], g.L[0], g.invL[0]);
-                dy = mi64(pd.x[1] - L.hx[1][slot], g.L[1], g.invL[1]);
-                dz = mi64(pd.x[2] - L.hx[2][slot], g.L[2], g.invL[2]);
-                qq = L.hq[slot] * pd.q;
+                dx = mi64(pd.x[0] - h.x[0], g.L[0], g.invL[0]);
+                dy = mi64(pd.x[1] - h.x[1], g.L[1], g.invL[1]);
+                dz = mi64(pd.x[2] - h.x[2], g.L[2], g.invL[2]);
+                qq = h.q * pd.q;
             } else {
                 dx = ex_; dy = ey_; dz = ez_;
-                qq = L.hq[slot] * pd.q;
+                qq = h.q * pd.q;
             }
             const R r2 = F64 ? dx * dx + dy * dy + dz * dz : r2f;
             R gk, hk;  // force coefficient g and pair potential h of the split
@@ -430,7 +469,7 @@ __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>:
                     float pa = csp->ta[kTabQ - 1], pb = csp->tb[kTabQ - 1];
 #pragma unroll
                     for (int t = kTabQ - 2; t >= 0; --t) pa = fmaf(pa, r2f, csp->ta[t]);
-                    if (L.we) {
+                    if (we) {
 #pragma unroll
                         for (int t = kTabQ - 2; t >= 0; --t) pb = fmaf(pb, r2f, csp->tb[t]);
                     }
@@ -447,7 +486,7 @@ __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>:
                     if constexpr (F64) gs = fma(gs, r2, co->ft[t]);
                     else gs = fmaf(gs, r2, co->ft[t]);
                 }
-                if (L.we) {
+                if (we) {
                     ph = co->pt[NT - 1];
 #pragma unroll
                     for (int t = NT - 2; t >= 0; --t) {
@@ -468,7 +507,7 @@ __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>:
                 // the potential's terms only when energies are summed: a
                 // uniform branch, kept a branch by the empty asm statement
                 // (which the compiler does not speculate)
-                if (L.we) {
+                if (we) {
                     asm volatile("");
 #pragma unroll
                     for (int l = 0; l < kExpRegs; ++l) ph += co->w[l] * exv[l];
@@ -478,7 +517,7 @@ __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>:
                     if constexpr (F64) ex = exp(-r2 * co->a[l]);
                     else ex = __builtin_amdgcn_exp2f(-r2 * co->a[l]);
                     gs += co->cw[l] * ex;
-                    if (L.we) ph += co->w[l] * ex;
+                    if (we) ph += co->w[l] * ex;
                 }
                 gk = rinv * rinv * rinv - gs;
                 hk = rinv - ph;
@@ -488,12 +527,38 @@ __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>:
             fx = -coef * dx;
             fy = -coef * dy;
             fz = -coef * dz;
-            if (L.we) {
+            if (we) {
                 asm volatile("");
                 de = 0.5 * (double)(qq * hk);
             }
         }
     }
+}
+
+// One ring entry per lane (`have`), home `slot` of the wave's LDS homes: the
+// pair force, then the wave's segmented sum.  One home's entries are
+// contiguous within a pass, so forces are summed by a segmented scan across
+// the wave and the last lane of each segment adds the total to the wave's
+// accumulator of that home.
+template <bool F64, bool SELF = false, bool DBG = false>
+__device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>::type *co, const HomeView<F64> &L,
+                                            const float4 *__restrict__ tbl, float rin2, CSys *csp,
+                                             int lane, uint2 qe, bool have, const PairData<F64> &pd,
+                                            double &e) {
+    using R = typename HomeView<F64>::R;
+    R fx, fy, fz;
+    double de;
+    const int slot = have ? (int)qe.x : -1;
+    HomeData<F64> h;
+    if (have) {
+        const uint4 hu = L.hu[slot];
+        h.u[0] = hu.x; h.u[1] = hu.y; h.u[2] = hu.z; h.slot = hu.w;
+        h.q = L.hq[slot];
+        if constexpr (F64) {
+            h.x[0] = L.hx[0][slot]; h.x[1] = L.hx[1][slot]; h.x[2] = L.hx[2][slot];
+        }
+    }
+    pair_force<F64, SELF, DBG>(g, co, h, L.we, L.rec, tbl, rin2, csp, qe.y, have, pd, fx, fy, fz, de);
     if (L.we) {
         asm volatile("");
         e += de;
@@ -529,23 +594,15 @@ __device__ __forceinline__ void eval_pair(const Geom &g, typename CoefOf<F64>::t
     eval_loaded<F64, SELF, DBG>(g, co, L, tbl, rin2, csp, lane, qe, have, pd, e);
 }
 
-template <bool F64, int Q>
+template <int Q>
 struct BuildLds {
-    using R = typename std::conditional<F64, double, float>::type;
-    static constexpr int XH = F64 ? kQuarter : 1;
     uint4 hu[kQuarter];        // home u_x, u_y, u_z, slot
-    R hq[kQuarter];
-    double hx[3][XH];
-    R hf[3][kQuarter];         // force accumulators of the wave's homes
     uint2 q[Q + 64];           // ring of accepted pairs: (home index in the quarter, candidate slot),
                                // then one spare entry per lane for the stores of rejected pairs
     int32_t rlo[32], rex[32];  // non-empty candidate ranges of the cell: first slot, offset in the list
     int32_t flag[64];          // range starts inside the current 64-slot window
 };
 
-// Ring entries [head, head + count): written to the item's list (entries at
-// or beyond the capacity are dropped; the caller flags the overflow) and
-// evaluated, one per lane.
 // The state gathered into `nxt` goes back to `cur`; the new reference
 // positions are the current ones (grid-stride from i0).
 __device__ __forceinline__ void copy_back(const EvalArgs &a, int64_t i0, int64_t stride) {
@@ -561,6 +618,8 @@ __device__ __forceinline__ void copy_back(const EvalArgs &a, int64_t i0, int64_t
         a.cur.q[i] = a.nxt.q[i];
         a.cur.qf[i] = a.nxt.qf[i];
         a.cur.id[i] = a.nxt.id[i];
+        a.pk[i] = make_uint4(a.u[i], a.u[n + i], a.u[2 * n + i], __float_as_uint(a.nxt.qf[i]));
+        if (a.pkx) a.pkx[i] = PosQ64{a.nxt.x[i], a.nxt.x[n + i], a.nxt.x[2 * n + i], a.nxt.q[i]};
     }
 }
 
@@ -577,73 +636,66 @@ __device__ __forceinline__ void eval_ring(const uint2 *ring, const HomeView<F64>
     eval_pair<F64, true, DBG>(g, co, hv, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qe, have, e);
 }
 
-// Ring entries [head, head + count): written to the wave's list segment
-// (entries at or beyond its capacity are dropped; the caller flags the
-// overflow) and evaluated, one per lane, in the chunks of 64 in which the
-// list pass reads the segment.
-template <bool F64, int Q, bool DBG>
-__device__ __forceinline__ void drain_ring(const BuildLds<F64, Q> &L, const HomeView<F64> &hv,
-                                           uint32_t *__restrict__ out, int64_t cap, const Geom &g,
-                                           typename CoefOf<F64>::type *co, const uint32_t *__restrict__ su,
-                                           const double *__restrict__ sx, const double *__restrict__ sq,
-                                           const float *__restrict__ sqf, int64_t n, const float4 *__restrict__ tbl,
-                                           float rin2, CSys *csp,  int lane, int head,
-                                           int count, double &e) {
+// Ring entries [head, head + count) appended to the columns of their homes:
+// the k-th pair of home h of the item is entry k * kListHomes + h of the
+// item's block of the list, so that the list pass reads one row of entries
+// (one per home) at a time.  The entries of one home keep their ring order.
+// hcnt: lane h < kQuarter holds the pair count of the wave's home h; entries
+// at or beyond `rows` are counted, not stored (the caller flags the
+// overflow).  The homes present are taken one at a time (a uniform loop over
+// the distinct homes of the 64 entries).
+template <int Q>
+__device__ __forceinline__ void drain_cols(const uint2 *ring, int head, int count, int lane,
+                                           uint32_t *__restrict__ out, int32_t rows, int colbase, int32_t &hcnt) {
     const bool have = lane < count;
-    const int idx = head + lane;
-    const uint2 qe = have ? L.q[idx & (Q - 1)] : make_uint2(0u, 0u);
-    if (have && out && idx < cap) out[idx] = (qe.x << kListSlotBits) | qe.y;
-    eval_pair<F64, false, DBG>(g, co, hv, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qe, have, e);
+    const uint2 qe = have ? ring[(head + lane) & (Q - 1)] : make_uint2(0xffffffffu, 0u);
+    int32_t pos = 0;
+    uint64_t rem = ballot(have);
+    while (rem) {
+        const int l0 = (int)__builtin_ctzll(rem);
+        const int h = __builtin_amdgcn_readlane((int)qe.x, l0);
+        const bool mine = qe.x == (uint32_t)h;
+        const uint64_t m = ballot(mine);
+        const int32_t c0 = __builtin_amdgcn_readlane(hcnt, h);
+        const int32_t r = (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        pos = mine ? c0 + r : pos;
+        hcnt = lane == h ? c0 + (int32_t)__popcll(m) : hcnt;
+        rem &= ~m;
+    }
+    if (have && out && pos < rows) out[(int64_t)pos * kListHomes + colbase + (int)qe.x] = qe.y;
 }
 
-// The build also evaluates this step's near forces from the same candidate
-// tests (every pair it lists passes through the ring, where the pair rule
-// and the force are applied), so a step with a build needs no list pass.
+// The build lists, for each home, the candidates within r_l = r_c (1 + skin)
+// by the FP32 test, in the column layout of drain_cols; it evaluates no
+// forces (the list pass that follows it in the same evaluation does, as on
+// every step), so a build step and a list step sum a home's pairs alike.
+// out == nullptr (the counting build of the set-up) only counts.
 // S: candidate slots per lane and pass (64 S candidates tested per pass)
-template <bool F64, int S, bool DBG = false>
+template <int S>
 __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListItem *__restrict__ items,
                                                          int32_t nitems, int32_t nblk) {
     // the critical path's waves ahead of the structure factor's beside them
     __builtin_amdgcn_s_setprio(2);
     if (!*a.rebuild) return;
-    __shared__ PairRec rec;
-    if constexpr (DBG) {
-        if (threadIdx.x == 0) {
-            rec = PairRec{a.nxt.id, a.dbg_pairs, a.dbg_cnt, a.dbg_cap};
-            if (blockIdx.x == 0) atomicOr(a.dbg_kind, 1);
-        }
-        __syncthreads();
-    }
     const int64_t n = a.N;  // stride of the structure-of-arrays
     if ((int32_t)blockIdx.x >= nblk) {
         copy_back(a, (int64_t)(blockIdx.x - nblk) * blockDim.x + threadIdx.x, (int64_t)(gridDim.x - nblk) * blockDim.x);
         return;
     }
     constexpr int Q = ring_size(S);
-    using Lds = BuildLds<F64, Q>;
+    using Lds = BuildLds<Q>;
     __shared__ Lds lds[kNW];
+    __shared__ int32_t wmax[kNW];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     Lds &L = lds[wave];
     const int32_t *__restrict__ start = a.cell_start;
     // the same array for reads at uniform indices (scalar loads)
     CI32 *cstart = (CI32 *)a.cell_start;
-    // the build runs on the gathered state (`nxt` and the new reference `u`,
-    // which are the current positions in the new order)
+    // the build runs on the new reference positions `u` (the current
+    // positions in the new order)
     const uint32_t *__restrict__ su = a.u;
-    const double *__restrict__ sx = a.nxt.x;
-    const double *__restrict__ sq = a.nxt.q;
-    const float *__restrict__ sqf = a.nxt.qf;
-    __shared__ double es_w[kNW];
-    HomeView<F64> hv;
-    hv.hu = L.hu;
-    hv.hq = L.hq;
-    hv.we = a.energy != 0;
-    hv.rec = DBG ? &rec : nullptr;
-    for (int d = 0; d < 3; ++d) {
-        hv.hx[d] = L.hx[d];
-        hv.hf[d] = L.hf[d];
-    }
     if (blockIdx.x == 0 && threadIdx.x == 0) ++*a.nbuild;
     // one item per block; blocks are dealt to the 8 XCDs round robin: block b
     // (on XCD b % 8) takes item (b % 8) * (nblk / 8) + b / 8
@@ -660,31 +712,18 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
     CSys *sp = (CSys *)(a.sys + sys);
     const Geom g = load_geom(sp);
     const int64_t c0s = sp->c0;
-    typename CoefOf<F64>::type *co;
-    if constexpr (F64) co = &sp->co64;
-    else co = &sp->co32;
-    const float4 *tbl = F64 ? nullptr : sp->tbl;
-    const float rin2 = sp->rin2;
-    CSys *csp = sp;  // the core-shell Taylor constants are read where used
-    double e = 0.0;
-    // this wave's quarter of the item's homes and of its list
+    // this wave's quarter of the item's homes: columns [wave kQuarter, ...)
+    // of the item's block of the list
     const int32_t t = (int32_t)std::min<int64_t>(item.t0 + wave * kQuarter, item.t1);
     const int32_t t_end = (int32_t)std::min<int64_t>(item.t0 + (wave + 1) * kQuarter, item.t1);
-    const int64_t cap = a.icap / kNW;
-    uint32_t *out = a.pairs ? a.pairs + (int64_t)it * a.icap + wave * cap : nullptr;
+    const int32_t rows = (int32_t)(a.icap / kListHomes);
+    uint32_t *out = a.pairs ? a.pairs + (int64_t)it * a.icap : nullptr;
+    const int colbase = wave * kQuarter;
+    int32_t hcnt = 0;  // lane h < kQuarter: pairs of home h so far
     const bool rel = g.nc[0] >= 4 && g.nc[1] >= 4 && g.nc[2] >= 4;
     if (lane < t_end - t) {
         const int64_t tt = t + lane;
         L.hu[lane] = make_uint4(su[tt], su[n + tt], su[2 * n + tt], (uint32_t)tt);
-        if constexpr (F64) {
-            L.hq[lane] = sq[tt];
-            L.hx[0][lane] = sx[tt]; L.hx[1][lane] = sx[n + tt]; L.hx[2][lane] = sx[2 * n + tt];
-        } else {
-            L.hq[lane] = sqf[tt];
-        }
-    }
-    if (lane < kQuarter) {
-        L.hf[0][lane] = 0; L.hf[1][lane] = 0; L.hf[2][lane] = 0;
     }
     wave_sync();
     int qn = 0, qh = 0;  // ring tail (pairs accepted) and head (pairs written)
@@ -850,8 +889,7 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
                     static_assert(63 + kU * S * 64 < Q, "ring too small");
                     while (qn - qh >= 64) {
                         wave_sync();
-                        drain_ring<F64, Q, DBG>(L, hv, out, cap, g, co, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qh, 64,
-                                           e);
+                        drain_cols<Q>(L.q, qh, 64, lane, out, rows, colbase, hcnt);
                         qh += 64;
                     }
                 }
@@ -862,35 +900,37 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
         }
     }
     wave_sync();
-    if (qn > qh)
-        drain_ring<F64, Q, DBG>(L, hv, out, cap, g, co, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qh, qn - qh, e);
-    wave_sync();
-    if (lane < t_end - t) {
-        const int64_t tt = t + lane;
-        a.Fn[tt] = (double)L.hf[0][lane]; a.Fn[n + tt] = (double)L.hf[1][lane]; a.Fn[2 * n + tt] = (double)L.hf[2][lane];
-    }
-    const double es = wave_sum(e);
-    if (lane == 0) {
-        es_w[wave] = es;
-        a.pcnt[(int64_t)it * kNW + wave] = (int64_t)qn < cap || !out ? qn : (int32_t)cap;
-        atomicMax(a.pmax, qn);
-        if (out && (int64_t)qn > cap) atomicOr(a.flag, 8);
-    }
+    if (qn > qh) drain_cols<Q>(L.q, qh, qn - qh, lane, out, rows, colbase, hcnt);
+    // the counts (capped at the rows stored), the largest of the block to the
+    // context's maximum (one atomic per block) and an overflow flag
+    const int nh = t_end - t;
+    if (lane < nh) a.pcnt[(int64_t)it * kListHomes + colbase + lane] = hcnt < rows || !out ? hcnt : rows;
+    int32_t mx = lane < nh ? hcnt : 0;
+    for (int o = 8; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+    if (lane == 0) wmax[wave] = mx;
     __syncthreads();
-    if (threadIdx.x == 0) a.epart[it] = ((es_w[0] + es_w[1]) + es_w[2]) + es_w[3];
+    if (threadIdx.x == 0) {
+        const int32_t bm = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+        atomicMax(a.pmax, bm);
+        if (out && bm > rows) atomicOr(a.flag, 8);
+    }
     }
 }
 
+// List pass: one block per item, one lane per home (lane h holds home h of
+// the item in registers), wave w evaluating rows w, w + 4, ... of the item's
+// columns (row k holds the k-th listed pair of every home); each lane sums
+// its home's pairs in registers, and the four waves' sums are added in a
+// fixed order.  Runs at every evaluation with the near list, a build's
+// included.
 template <bool F64, bool DBG = false>
 __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListItem *__restrict__ items,
                                                         int32_t nitems, int32_t nblk) {
     // the critical path's waves ahead of the structure factor's beside them
     __builtin_amdgcn_s_setprio(2);
-    using Lds = EvalLds<F64>;
-    __shared__ Lds lds[kNW];
+    using R = typename std::conditional<F64, double, float>::type;
+    __shared__ R pf[kNW][3][kListHomes];
     __shared__ double es_w[kNW];
-    // a build in this evaluation has evaluated the forces already
-    if (*a.rebuild) return;
     __shared__ PairRec rec;
     if constexpr (DBG) {
         if (threadIdx.x == 0) {
@@ -901,7 +941,6 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
     }
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    Lds &L = lds[w];
     const int64_t n = a.N;
     const uint32_t *__restrict__ su = a.u_tmp;
     const double *__restrict__ sx = a.cur.x;
@@ -925,62 +964,67 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
     const float4 *tbl = F64 ? nullptr : sp->tbl;
     const float rin2 = sp->rin2;
     CSys *csp = sp;  // the core-shell Taylor constants are read where used
-    // this wave's quarter of the homes and its segment of the list
-    const int64_t t0 = std::min<int64_t>(item.t0 + w * kQuarter, item.t1);
-    const int H = (int)(std::min<int64_t>(item.t0 + (w + 1) * kQuarter, item.t1) - t0);
-    if (lane < H) {
-        const int64_t tt = t0 + lane;
-        L.hu[lane] = make_uint4(su[tt], su[n + tt], su[2 * n + tt], (uint32_t)tt);
-        if constexpr (F64) {
-            L.hq[lane] = sq[tt];
-            L.hx[0][lane] = sx[tt]; L.hx[1][lane] = sx[n + tt]; L.hx[2][lane] = sx[2 * n + tt];
-        } else {
-            L.hq[lane] = sqf[tt];
+    const bool we = a.energy != 0;
+    const int64_t t0 = item.t0;
+    const int H = (int)(item.t1 - t0);
+    const bool home = lane < H;
+    const int64_t tt = t0 + (home ? lane : 0);
+    HomeData<F64> hd;
+    hd.u[0] = su[tt]; hd.u[1] = su[n + tt]; hd.u[2] = su[2 * n + tt];
+    hd.slot = (uint32_t)tt;
+    if constexpr (F64) {
+        hd.q = sq[tt];
+        hd.x[0] = sx[tt]; hd.x[1] = sx[n + tt]; hd.x[2] = sx[2 * n + tt];
+    } else {
+        hd.q = sqf[tt];
+    }
+    const int32_t cnt = home ? a.pcnt[(int64_t)it * kListHomes + lane] : 0;
+    int32_t mc = cnt;
+    for (int o = 32; o > 0; o >>= 1) mc = max(mc, __shfl_xor(mc, o, 64));
+    const int32_t maxcnt = rfl(mc);
+    // this lane's column; rows past the stored ones are read as the last
+    // stored row and not used (loads without a branch)
+    const uint32_t *__restrict__ col = a.pairs + (int64_t)it * a.icap + lane;
+    const int32_t rlast = (int32_t)(a.icap / kListHomes) - 1;
+    auto entry = [&](int32_t r) -> uint32_t {
+        const uint32_t v = col[(int64_t)min(r, rlast) * kListHomes];
+        return r < cnt ? (v & kListSlotMask) : 0u;
+    };
+    R fx = 0, fy = 0, fz = 0;
+    double e = 0.0;
+    // rows w, w + kNW, ...: the entries two rows ahead and the candidate's
+    // data of the next row are loaded while this one is evaluated
+    int32_t k = w;
+    uint32_t e1 = entry(k), e2 = entry(k + kNW);
+    PairData<F64> pd = load_packed<F64>(a.pk, a.pkx, e1);
+    for (; k < maxcnt; k += kNW) {
+        const bool have = k < cnt;
+        const uint32_t cj = e1;
+        const PairData<F64> cur = pd;
+        e1 = e2;
+        e2 = entry(k + 2 * kNW);
+        pd = load_packed<F64>(a.pk, a.pkx, e1);
+        R px, py, pz;
+        double de;
+        pair_force<F64, false, DBG>(g, co, hd, we, DBG ? &rec : nullptr, tbl, rin2, csp, cj, have, cur, px, py, pz,
+                                    de);
+        fx += px; fy += py; fz += pz;
+        if (we) {
+            asm volatile("");
+            e += de;
         }
     }
-    if (lane < kQuarter) {
-        L.hf[0][lane] = 0; L.hf[1][lane] = 0; L.hf[2][lane] = 0;
-    }
-    wave_sync();
-    const int64_t cap = a.icap / kNW;
-    const int32_t cnt = ((CI32 *)a.pcnt)[(int64_t)it * kNW + w];
-    const uint32_t *__restrict__ pl = a.pairs + (int64_t)it * a.icap + w * cap;
-    HomeView<F64> hv;
-    hv.hu = L.hu;
-    hv.hq = L.hq;
-    hv.we = a.energy != 0;
-    hv.rec = DBG ? &rec : nullptr;
-    for (int d = 0; d < 3; ++d) {
-        hv.hx[d] = L.hx[d];
-        hv.hf[d] = L.hf[d];
-    }
-    double e = 0.0;
-    // the segment in the build's chunks of 64, in order; entries are loaded
-    // two chunks ahead and the candidates' data one chunk ahead, so that the
-    // loads of the next chunks run while this one is evaluated
-    auto entry = [&](int32_t c) {
-        const uint32_t v = c + lane < cnt ? pl[c + lane] : 0u;
-        return make_uint2(v >> kListSlotBits, v & kListSlotMask);
-    };
-    uint2 qe1 = entry(0), qe2 = entry(64);
-    PairData<F64> pd1 = load_pair<F64>(su, sx, sq, sqf, n, qe1, lane < cnt);
-    for (int32_t c = 0; c < cnt; c += 64) {
-        const uint2 qe = qe1;
-        const PairData<F64> pd = pd1;
-        const bool have = c + lane < cnt;
-        qe1 = qe2;
-        qe2 = entry(c + 128);
-        pd1 = load_pair<F64>(su, sx, sq, sqf, n, qe1, c + 64 + lane < cnt);
-        eval_loaded<F64, false, DBG>(g, co, hv, tbl, rin2, csp, lane, qe, have, pd, e);
-    }
-    wave_sync();
-    if (lane < H) {
-        const int64_t tt = t0 + lane;
-        a.Fn[tt] = (double)L.hf[0][lane]; a.Fn[n + tt] = (double)L.hf[1][lane]; a.Fn[2 * n + tt] = (double)L.hf[2][lane];
-    }
+    pf[w][0][lane] = fx;
+    pf[w][1][lane] = fy;
+    pf[w][2][lane] = fz;
     const double es = wave_sum(e);
     if (lane == 0) es_w[w] = es;
     __syncthreads();
+    if (w == 0 && home) {
+        for (int d = 0; d < 3; ++d)
+            a.Fn[d * n + tt] = (((double)pf[0][d][lane] + (double)pf[1][d][lane]) + (double)pf[2][d][lane]) +
+                               (double)pf[3][d][lane];
+    }
     if (threadIdx.x == 0) a.epart[it] = ((es_w[0] + es_w[1]) + es_w[2]) + es_w[3];
 }
 
@@ -1359,18 +1403,11 @@ __global__ void k_neighbors(EvalArgs a, int32_t sys, int64_t nloc, int64_t p0, c
     }
 }
 
-template <bool DBG>
-void list_build_launch(const EvalArgs &a, bool f64, int32_t slots, dim3 grid, dim3 block, const ListItem *items,
+void list_build_launch(const EvalArgs &a, int32_t slots, dim3 grid, dim3 block, const ListItem *items,
                        int32_t nitems, int32_t nblk, hipStream_t s) {
-    if (f64) {
-        if (slots <= 2) hipLaunchKernelGGL((k_list_build<true, 2, DBG>), grid, block, 0, s, a, items, nitems, nblk);
-        else if (slots == 3) hipLaunchKernelGGL((k_list_build<true, 3, DBG>), grid, block, 0, s, a, items, nitems, nblk);
-        else hipLaunchKernelGGL((k_list_build<true, 4, DBG>), grid, block, 0, s, a, items, nitems, nblk);
-    } else {
-        if (slots <= 2) hipLaunchKernelGGL((k_list_build<false, 2, DBG>), grid, block, 0, s, a, items, nitems, nblk);
-        else if (slots == 3) hipLaunchKernelGGL((k_list_build<false, 3, DBG>), grid, block, 0, s, a, items, nitems, nblk);
-        else hipLaunchKernelGGL((k_list_build<false, 4, DBG>), grid, block, 0, s, a, items, nitems, nblk);
-    }
+    if (slots <= 2) hipLaunchKernelGGL((k_list_build<2>), grid, block, 0, s, a, items, nitems, nblk);
+    else if (slots == 3) hipLaunchKernelGGL((k_list_build<3>), grid, block, 0, s, a, items, nitems, nblk);
+    else hipLaunchKernelGGL((k_list_build<4>), grid, block, 0, s, a, items, nitems, nblk);
 }
 
 template <bool DBG>
@@ -1396,8 +1433,8 @@ void launch_list_build(const EvalArgs &a, bool f64, const ListItem *items, int32
     if (nblk < 8) nblk = 8;
     const int64_t ncopy = std::min<int64_t>(1024, std::max<int64_t>(1, grid_for(a.N, 64 * kNW)));
     const dim3 grid((unsigned)(nblk + ncopy)), block(64 * kNW);
-    if (a.dbg_pairs) list_build_launch<true>(a, f64, slots, grid, block, items, nitems, nblk, s);
-    else list_build_launch<false>(a, f64, slots, grid, block, items, nitems, nblk, s);
+    (void)f64;  // the build's test is the same in both precisions
+    list_build_launch(a, slots, grid, block, items, nitems, nblk, s);
 }
 
 void launch_near_cells(const EvalArgs &a, bool f64, const NearItem *items, int32_t nitems, int32_t slots,

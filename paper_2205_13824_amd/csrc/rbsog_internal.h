@@ -129,10 +129,11 @@ struct NearItem {
     int64_t c_begin, c_end;
 };
 // Near list item: up to kListHomes consecutive particle slots [t0, t1) of one
-// system (in the cell order of the latest list build).  Its homes come in
-// kListWaves quarters; the pairs of quarter w are entries
-// [item icap + w icap/kListWaves, ... + pcnt[item kListWaves + w]) of the
-// pair list.
+// system (in the cell order of the latest list build).  Its block of the pair
+// list is icap entries: rows of kListHomes, the k-th pair of home h (slot
+// t0 + h) at entry k kListHomes + h (the candidate's slot), for
+// k < pcnt[item kListHomes + h].  The build writes the columns of its
+// kListWaves quarters of homes, one wave each.
 constexpr int kListHomes = 64;
 constexpr int kListWaves = 4;
 struct ListItem {
@@ -160,12 +161,17 @@ struct StateBufs {
     int32_t *id;
     double *dsp;  // displacement since the mean-square-displacement origin (sum of the drifts)
 };
-// A near-list entry packs the home (index among the 16 homes of a wave's
-// quarter of an item) above the candidate's slot, so slots must stay below
-// 2^kListSlotBits (the limit on the particles of a context).
+// Slots of a context stay below 2^kListSlotBits (its particle limit): the
+// near kernels gather by 32-bit byte offsets and keep a build's ring entries
+// and list entries within kListSlotMask.
 constexpr int kListSlotBits = 28;
 constexpr uint32_t kListSlotMask = (1u << kListSlotBits) - 1u;
 constexpr int64_t kMaxParticles = (int64_t)1 << kListSlotBits;
+
+// FP64 position and charge of a slot in one 32-byte record.
+struct alignas(32) PosQ64 {
+    double x, y, z, q;
+};
 
 struct EvalArgs {
     int64_t N;             // particles over all systems
@@ -185,6 +191,12 @@ struct EvalArgs {
     uint32_t *rs_u;
     float *rs_qf;
     double *rs_x, *rs_q;
+    // what the list pass gathers of a listed candidate, one record per slot
+    // in the current order (written by the kick/drift kernel, and in the new
+    // order by a build's copy back): fixed-point coordinates with the FP32
+    // charge's bits; the FP64 position and charge (FP64 form; else null)
+    uint4 *pk;
+    PosQ64 *pkx;
     int32_t *cell_of, *cell_count, *cell_start, *cell_fill, *src, *sorted, *blocksums;
     int32_t *skey;         // particle id of each scattered slot (the per-cell sort's key)
     int32_t *cell_sorted;  // cell of each slot at the latest list build

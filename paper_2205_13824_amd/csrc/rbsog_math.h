@@ -116,6 +116,31 @@ __device__ __forceinline__ float phase_rev(uint32_t t) {
     return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, t, 9u));
 }
 
+// Fixed-point phase m.u mod 2^32 of three products as a chain of
+// v_mad_u64_u32 (a full-rate instruction on gfx950): the first product takes
+// the inline constant 0 as its addend and each later one adds the previous
+// 64-bit result, whose low half is the running sum mod 2^32 (the high half
+// never reaches the low one).  Three instructions where separate products
+// and a sum take four.  `s` forms take the first factor from a scalar
+// register (wave-uniform wave vectors), `v` forms from a vector register.
+// The carry output of the instruction is not used.
+__device__ __forceinline__ uint32_t dot3_mod32_v(uint32_t ax, uint32_t ay, uint32_t az, uint32_t bx, uint32_t by,
+                                                 uint32_t bz) {
+    uint64_t p, q, r, c0, c1, c2;
+    asm("v_mad_u64_u32 %0, %1, %2, %3, 0" : "=v"(p), "=s"(c0) : "v"(az), "v"(bz));
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(q), "=s"(c1) : "v"(ay), "v"(by), "v"(p));
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(c2) : "v"(ax), "v"(bx), "v"(q));
+    return (uint32_t)r;
+}
+__device__ __forceinline__ uint32_t dot3_mod32_s(uint32_t ax, uint32_t ay, uint32_t az, uint32_t bx, uint32_t by,
+                                                 uint32_t bz) {
+    uint64_t p, q, r, c0, c1, c2;
+    asm("v_mad_u64_u32 %0, %1, %2, %3, 0" : "=v"(p), "=s"(c0) : "s"(az), "v"(bz));
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(q), "=s"(c1) : "s"(ay), "v"(by), "v"(p));
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(c2) : "s"(ax), "v"(bx), "v"(q));
+    return (uint32_t)r;
+}
+
 // sin(2 pi f), cos(2 pi f) for |f| <= 1/2 in FP64: quadrant q = rint(4f),
 // r = f - q/4 in [-1/8, 1/8], Taylor series of sin/cos(2 pi r) through
 // degree 15/16 (truncation below 5e-17), then rotation by q quarter turns.

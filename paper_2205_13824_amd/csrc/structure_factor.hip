@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kSfBlock) void k_sf_partial(int64_t n, const double
                 float rf = 0.f, fi = 0.f;
                 for (int h = h0; h < h1; ++h) {
                     const uint4 p = st32[h];
-                    const uint32_t t = ux * p.x + uy * p.y + uz * p.z;
+                    const uint32_t t = rmath::dot3_mod32_v(ux, uy, uz, p.x, p.y, p.z);
                     const float f = rmath::phase_rev(t);
                     const float qf = __uint_as_float(p.w);
                     rf = fmaf(qf, __builtin_amdgcn_cosf(f), rf);

@@ -35,7 +35,7 @@ EXPORTS = ("rbsog_default_opts", "rbsog_sog_table1", "rbsog_init", "rbsog_init_b
            "rbsog_set_nose_hoover", "rbsog_get_kinetic", "rbsog_set_msd_origin", "rbsog_get_msd",
            "rbsog_structure_factor", "rbsog_structure_factor_noalloc", "rbsog_get_forces_subset",
            "rbsog_debug_record_pairs", "rbsog_debug_pairs", "rbsog_debug_list", "rbsog_save_state",
-           "rbsog_load_state")
+           "rbsog_load_state", "rbsog_probe_count", "rbsog_probe_name", "rbsog_probe_rates")
 
 
 class RbsogError(RuntimeError):
@@ -115,6 +115,9 @@ def lib():
             "rbsog_set_thermostat": (i32, [vp, dbl, dbl, u64]),
             "rbsog_structure_factor": (i32, [i64, vp, vp, vp, i64, vp, i32, vp, vp, vp]),
             "rbsog_structure_factor_noalloc": (i32, [i64, vp, vp, vp, i64, vp, i32, vp, vp, vp]),
+            "rbsog_probe_count": (i32, []),
+            "rbsog_probe_name": (ctypes.c_char_p, [i32]),
+            "rbsog_probe_rates": (i32, [i32, i32, vp, i32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -418,6 +421,14 @@ def rbsog_save_state(ctx) -> bytes:
 def rbsog_load_state(ctx, state: bytes):
     buf = ctypes.create_string_buffer(state, len(state))
     _check(lib().rbsog_load_state(ctx, ctypes.cast(buf, ctypes.c_void_p), len(state)), ctx)
+
+
+def rbsog_probe_rates(device: int = 0, reps: int = 3) -> dict:
+    """{probe name: lane-instructions per second} measured on `device`."""
+    n = lib().rbsog_probe_count()
+    rates = np.zeros(n, dtype=np.float64)
+    _check(lib().rbsog_probe_rates(int(device), int(reps), _ptr(rates), n))
+    return {lib().rbsog_probe_name(i).decode(): float(rates[i]) for i in range(n)}
 
 
 def rbsog_sync(ctx):

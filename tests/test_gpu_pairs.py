@@ -194,11 +194,14 @@ def test_kernel_pairs_at_the_cutoff_edges_bit_exact(orc, prec, table, skin):
     npairs = int(row_o[-1]) // 2
     print(f"prec={prec} table={table} skin={skin}: {npairs} neighbour pairs of {len(q) // 2} placed, "
           f"kernels {kinds}", flush=True)
-    assert kinds == (1 if skin > 0 else 4)
+    assert kinds == (2 if skin > 0 else 4)
     assert_same_csr(row, cols, row_o, cols_o, "first evaluation")
     if skin > 0:
         # the same positions again: the list pass evaluates the stored list
+        # without a build
+        nb = R.rbsog_info(sysm.ctx)["list_builds"]
         sysm.forces()
+        assert R.rbsog_info(sysm.ctx)["list_builds"] == nb
         row2, cols2, kinds2 = recorded_pairs(sysm)
         assert kinds2 == 2
         assert_same_csr(row2, cols2, row_o, cols_o, "list pass")
@@ -243,7 +246,7 @@ def test_kernel_pairs_in_single_cell_dimensions(orc, prec, skin):
     sysm.forces()
     row, cols, kinds = recorded_pairs(sysm)
     row_o, cols_o = orc.neighbors_brute(pos, box, rc)
-    assert kinds == (1 if skin > 0 else 4)
+    assert kinds == (2 if skin > 0 else 4)
     assert_same_csr(row, cols, row_o, cols_o, "single-cell z")
     sysm.close()
 
@@ -276,7 +279,5 @@ def test_kernel_pairs_along_a_trajectory(orc, prec, skin):
         assert_same_csr(row, cols, rowd, colsd, f"step {s + 1}")
         seen.add(kinds)
     print(f"prec={prec} skin={skin}: kernels seen {sorted(seen)}", flush=True)
-    assert seen <= ({1, 2} if skin > 0 else {4})
-    if skin > 0:
-        assert 2 in seen
+    assert seen == ({2} if skin > 0 else {4})
     sysm.close()
