@@ -304,7 +304,7 @@ typedef struct {
     int32_t rho_chunk;            /* launch shapes in use (see rbsog_autotune) */
     int32_t far_block;
     int32_t tuned;                /* 1 if the shapes come from tuning (now or cached) */
-    int64_t list_capacity;        /* near-list pairs per 64-particle item */
+    int64_t list_capacity;        /* near-list entries per 64-particle item (64 x the pairs one home can hold) */
     int64_t list_builds;          /* near-list builds made by evaluations so far */
     double skin;                  /* skin in use: the caller's, or 0 while the steps build every time
                                      (rbsog_step checks every 32 steps: when lists last under two
@@ -314,6 +314,9 @@ typedef struct {
                                      structure-factor block (largest over the systems), */
     int32_t build_slots;          /* candidate slots of 64 per lane and test pass of the list build, */
     int32_t cell_slots;           /* and of the fused cell kernel of the build-every-step mode */
+    int32_t list_home_major;      /* 1: the near list is kept home by home (lists of more than 128
+                                     pairs of one home at sizing; one home per wave in the list
+                                     pass), 0: in columns (one home per lane) */
 } rbsog_info_t;
 rbsog_status rbsog_info(rbsog_ctx *ctx, int32_t sys, rbsog_info_t *info);
 

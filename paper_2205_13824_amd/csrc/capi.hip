@@ -177,6 +177,7 @@ struct rbsog_ctx {
     uint32_t *pairs = nullptr;
     int32_t *pcnt = nullptr, *rebuild = nullptr, *pmax = nullptr;
     int64_t icap = 0;
+    bool list_hm = false;  // home-major blocks (lists longer than kHomeMajorMin at sizing)
     int64_t *nbuild = nullptr;
     int32_t build_slots = 2;  // candidates per lane and test pass of the build
     int32_t cell_slots = 2;   // the same for the fused cell kernel
@@ -546,6 +547,7 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
     a.always_build = c->skin_cur > 0.0 ? 0 : 1;
     a.pcnt = c->pcnt;
     a.icap = c->icap;
+    a.list_hm = c->list_hm ? 1 : 0;
     a.pmax = c->pmax;
     a.nbuild = c->nbuild;
     a.Fn = c->Fn;
@@ -769,6 +771,29 @@ rbsog_status adapt_skin(rbsog_ctx *c) {
 
 // Asks for a list build at the next evaluation (positions set from the host,
 // a larger list, or a new cell grid).
+// The near list of the latest build again, from the context's reference
+// positions, cells and launch shapes (after a state load): the build kernel
+// alone, without its copy back of the state.  The build counter, the rebuild
+// flag and the largest count keep their values.
+rbsog_status relist(rbsog_ctx *c) {
+    int64_t nb = 0;
+    int32_t rb = 0, pm = 0;
+    const int32_t one = 1;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(&nb, c->nbuild, sizeof nb, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(&rb, c->rebuild, sizeof rb, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(&pm, c->pmax, sizeof pm, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(c->rebuild, &one, sizeof one, hipMemcpyHostToDevice));
+    EvalArgs a = make_args(c, false, 0.0);
+    launch_list_build(a, c->prec == RBSOG_FP64, c->list_items, c->n_list, c->build_slots, c->stream, false);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->nbuild, &nb, sizeof nb, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->rebuild, &rb, sizeof rb, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->pmax, &pm, sizeof pm, hipMemcpyHostToDevice));
+    return RBSOG_OK;
+}
+
 rbsog_status request_build(rbsog_ctx *c) {
     const int32_t one = 1;
     HIPCHK(c, hipMemcpyAsync(c->rebuild, &one, sizeof one, hipMemcpyHostToDevice, c->stream));
@@ -776,22 +801,21 @@ rbsog_status request_build(rbsog_ctx *c) {
     return RBSOG_OK;
 }
 
+// Lists longer than this (pairs of one home at the sizing build) are kept in
+// home-major blocks, evaluated one home per wave; shorter ones in columns, one
+// home per lane.
+constexpr int64_t kHomeMajorMin = 128;
+
 // Capacity of the pair list: every item holds icap / kListHomes rows of
-// kListHomes entries, one column per home.  Sized from the largest count of
+// kListHomes entries, one list per home.  Sized from the largest count of
 // one home at a build with room to spare; a build whose largest count passes
 // 3/4 of the rows makes the next call grow it (and build again), and one that
 // overflows fails the call.
-// Rows of item it's block of the near list that hold entries: its longest
-// column (counts pc, kListHomes per item), at most the rows stored.
-int64_t list_rows(const std::vector<int32_t> &pc, int64_t it, int64_t icap) {
-    int64_t m = 0;
-    for (int h = 0; h < kListHomes; ++h) m = std::max<int64_t>(m, pc[(size_t)(it * kListHomes + h)]);
-    return std::min<int64_t>(m, icap / kListHomes);
-}
-
 rbsog_status size_list(rbsog_ctx *c, int64_t largest) {
     const int64_t want = kListHomes * ((2 * std::max<int64_t>(largest, 8) + 3) / 4 * 4);
     if (c->pairs && want <= c->icap) return RBSOG_OK;
+    // long lists (beyond kHomeMajorMin pairs of one home) in home-major blocks
+    c->list_hm = largest > kHomeMajorMin;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     uint32_t *np = nullptr;
     if (hipMalloc((void **)&np, (size_t)c->n_list * (size_t)want * sizeof(uint32_t)) != hipSuccess)
@@ -2238,6 +2262,7 @@ rbsog_status rbsog_info(rbsog_ctx *c, int32_t sys, rbsog_info_t *info) {
     for (const SysHost &h : c->sys) info->rho_ktile = std::max(info->rho_ktile, h.kt);
     info->build_slots = c->build_slots;
     info->cell_slots = c->cell_slots;
+    info->list_home_major = c->list_hm ? 1 : 0;
     info->tuned = c->tuned ? 1 : 0;
     return RBSOG_OK;
 }
@@ -2393,7 +2418,8 @@ rbsog_status rbsog_debug_list(rbsog_ctx *c, int32_t sys, int64_t *row_ptr, int32
         const int64_t t0 = h.p0 + it * kListHomes;
         for (int hh = 0; hh < kListHomes; ++hh) {
             for (int32_t k = 0; k < pc[(size_t)(it * kListHomes + hh)]; ++k) {
-                const uint32_t e = ent[(size_t)(it * c->icap + (int64_t)k * kListHomes + hh)];
+                const int64_t at = c->list_hm ? (int64_t)hh * (c->icap / kListHomes) + k : (int64_t)k * kListHomes + hh;
+                const uint32_t e = ent[(size_t)(it * c->icap + at)];
                 pairs.push_back(make_uint2((uint32_t)id[(size_t)(t0 + hh)], (uint32_t)id[e & kListSlotMask]));
             }
         }
@@ -2545,24 +2571,11 @@ rbsog_status write_state(rbsog_ctx *c, StateWriter &w) {
         }
         w.pos += a.second;
     }
-    // the near list, item by item: the counts, then the rows up to the
-    // item's longest column
+    // the near list is not stored: it is a function of the saved reference
+    // positions, cells and launch shapes, and loading lists it again
     const bool list = c->skin_cur > 0.0 && c->pairs;
     w.val<int32_t>(list ? 1 : 0);
-    if (list) {
-        std::vector<int32_t> pc((size_t)kListHomes * c->n_list);
-        HIPCHK(c, hipMemcpy(pc.data(), c->pcnt, pc.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-        w.raw(pc.data(), (int64_t)pc.size() * 4);
-        for (int64_t it = 0; it < c->n_list; ++it) {
-            const int64_t bytes = list_rows(pc, it, c->icap) * kListHomes * (int64_t)sizeof(uint32_t);
-            if (w.buf && w.pos + bytes <= w.cap && bytes > 0) {
-                HIPCHK(c, hipMemcpy(w.buf + w.pos, c->pairs + it * c->icap, (size_t)bytes, hipMemcpyDeviceToHost));
-            } else if (w.buf && bytes > 0) {
-                w.overflow = true;
-            }
-            w.pos += bytes;
-        }
-    }
+    w.val<int32_t>(c->list_hm ? 1 : 0);
     return RBSOG_OK;
 }
 
@@ -2692,19 +2705,14 @@ rbsog_status rbsog_load_state(rbsog_ctx *c, const void *buf, int64_t len) {
         r.pos += a.second;
     }
     const int32_t list = r.val<int32_t>();
+    const int32_t list_hm = r.val<int32_t>();
+    if (r.bad) return fail(c, RBSOG_E_ARG, "truncated state");
     if (list) {
-        if (!(skin_cur > 0.0)) return fail(c, RBSOG_E_ARG, "corrupt state");
-        std::vector<int32_t> pc((size_t)kListHomes * c->n_list);
-        r.raw(pc.data(), (int64_t)pc.size() * 4);
-        if (r.bad) return fail(c, RBSOG_E_ARG, "truncated state");
-        HIPCHK(c, hipMemcpy(c->pcnt, pc.data(), pc.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-        for (int64_t it = 0; it < c->n_list; ++it) {
-            const int64_t bytes = list_rows(pc, it, c->icap) * kListHomes * (int64_t)sizeof(uint32_t);
-            if (r.pos + bytes > len) return fail(c, RBSOG_E_ARG, "truncated state");
-            if (bytes > 0)
-                HIPCHK(c, hipMemcpy(c->pairs + it * c->icap, r.buf + r.pos, (size_t)bytes, hipMemcpyHostToDevice));
-            r.pos += bytes;
-        }
+        if (!(skin_cur > 0.0) || !c->pairs) return fail(c, RBSOG_E_ARG, "corrupt state");
+        // the list of the saved build, listed again from the saved reference
+        // positions and cells by the build kernel (no re-sort, no copy back)
+        c->list_hm = list_hm != 0;
+        TRY(relist(c));
     }
     c->evals = evals;
     c->forces_valid = forces_valid != 0;

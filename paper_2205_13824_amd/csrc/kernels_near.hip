@@ -140,6 +140,10 @@ __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
+__device__ __forceinline__ float wave_sum(float v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
 
 // Mask of the active lanes for which p holds (the lane mask the compare
 // already produced, without going through a vector register).
@@ -636,17 +640,19 @@ __device__ __forceinline__ void eval_ring(const uint2 *ring, const HomeView<F64>
     eval_pair<F64, true, DBG>(g, co, hv, su, sx, sq, sqf, n, tbl, rin2, csp, lane, qe, have, e);
 }
 
-// Ring entries [head, head + count) appended to the columns of their homes:
-// the k-th pair of home h of the item is entry k * kListHomes + h of the
-// item's block of the list, so that the list pass reads one row of entries
-// (one per home) at a time.  The entries of one home keep their ring order.
+// Ring entries [head, head + count) appended to the lists of their homes in
+// the item's block of the list: the k-th pair of home h is entry
+// k * kListHomes + h (column blocks: the list pass reads one row of entries,
+// one per home, at a time) or h * rows + k (home-major blocks, for long
+// lists).  The entries of one home keep their ring order.
 // hcnt: lane h < kQuarter holds the pair count of the wave's home h; entries
 // at or beyond `rows` are counted, not stored (the caller flags the
 // overflow).  The homes present are taken one at a time (a uniform loop over
 // the distinct homes of the 64 entries).
 template <int Q>
 __device__ __forceinline__ void drain_cols(const uint2 *ring, int head, int count, int lane,
-                                           uint32_t *__restrict__ out, int32_t rows, int colbase, int32_t &hcnt) {
+                                           uint32_t *__restrict__ out, int32_t rows, bool hm, int colbase,
+                                           int32_t &hcnt) {
     const bool have = lane < count;
     const uint2 qe = have ? ring[(head + lane) & (Q - 1)] : make_uint2(0xffffffffu, 0u);
     int32_t pos = 0;
@@ -663,7 +669,10 @@ __device__ __forceinline__ void drain_cols(const uint2 *ring, int head, int coun
         hcnt = lane == h ? c0 + (int32_t)__popcll(m) : hcnt;
         rem &= ~m;
     }
-    if (have && out && pos < rows) out[(int64_t)pos * kListHomes + colbase + (int)qe.x] = qe.y;
+    if (have && out && pos < rows) {
+        const int hcol = colbase + (int)qe.x;
+        out[hm ? (int64_t)hcol * rows + pos : (int64_t)pos * kListHomes + hcol] = qe.y;
+    }
 }
 
 // The build lists, for each home, the candidates within r_l = r_c (1 + skin)
@@ -719,6 +728,7 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
     const int32_t rows = (int32_t)(a.icap / kListHomes);
     uint32_t *out = a.pairs ? a.pairs + (int64_t)it * a.icap : nullptr;
     const int colbase = wave * kQuarter;
+    const bool hm = a.list_hm != 0;
     int32_t hcnt = 0;  // lane h < kQuarter: pairs of home h so far
     const bool rel = g.nc[0] >= 4 && g.nc[1] >= 4 && g.nc[2] >= 4;
     if (lane < t_end - t) {
@@ -889,7 +899,7 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
                     static_assert(63 + kU * S * 64 < Q, "ring too small");
                     while (qn - qh >= 64) {
                         wave_sync();
-                        drain_cols<Q>(L.q, qh, 64, lane, out, rows, colbase, hcnt);
+                        drain_cols<Q>(L.q, qh, 64, lane, out, rows, hm, colbase, hcnt);
                         qh += 64;
                     }
                 }
@@ -900,7 +910,7 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
         }
     }
     wave_sync();
-    if (qn > qh) drain_cols<Q>(L.q, qh, qn - qh, lane, out, rows, colbase, hcnt);
+    if (qn > qh) drain_cols<Q>(L.q, qh, qn - qh, lane, out, rows, hm, colbase, hcnt);
     // the counts (capped at the rows stored), the largest of the block to the
     // context's maximum (one atomic per block) and an overflow flag
     const int nh = t_end - t;
@@ -917,13 +927,13 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
     }
 }
 
-// List pass: one block per item, one lane per home (lane h holds home h of
-// the item in registers), wave w evaluating rows w, w + 4, ... of the item's
-// columns (row k holds the k-th listed pair of every home); each lane sums
-// its home's pairs in registers, and the four waves' sums are added in a
-// fixed order.  Runs at every evaluation with the near list, a build's
-// included.
-template <bool F64, bool DBG = false>
+// List pass: one block per item; runs at every evaluation with the near
+// list, a build's included.  Column blocks: one lane per home (lane h holds
+// home h of the item in registers), wave w evaluating rows w, w + 4, ... of
+// the item's columns (row k holds the k-th listed pair of every home); each
+// lane sums its home's pairs in registers, and the four waves' sums are added
+// in a fixed order.  Home-major blocks: see below.
+template <bool F64, bool HM, bool DBG = false>
 __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListItem *__restrict__ items,
                                                         int32_t nitems, int32_t nblk) {
     // the critical path's waves ahead of the structure factor's beside them
@@ -967,6 +977,63 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
     const bool we = a.energy != 0;
     const int64_t t0 = item.t0;
     const int H = (int)(item.t1 - t0);
+    const int32_t rlast = (int32_t)(a.icap / kListHomes) - 1;
+    double e = 0.0;
+    if constexpr (HM) {
+        // home-major blocks (long lists): wave w takes homes w, w + kNW, ...
+        // of the item one at a time, its lanes on 64 consecutive entries of
+        // the home's list (neighbouring candidates: the gathers stay local);
+        // the next chunk's entries and data are loaded while one is
+        // evaluated; each home's sums close with a fixed-order wave sum
+        for (int hh = w; hh < H; hh += kNW) {
+            const int64_t th = t0 + hh;
+            HomeData<F64> hd;
+            hd.u[0] = su[th]; hd.u[1] = su[n + th]; hd.u[2] = su[2 * n + th];
+            hd.slot = (uint32_t)th;
+            if constexpr (F64) {
+                hd.q = sq[th];
+                hd.x[0] = sx[th]; hd.x[1] = sx[n + th]; hd.x[2] = sx[2 * n + th];
+            } else {
+                hd.q = sqf[th];
+            }
+            const int32_t cnt = ((CI32 *)a.pcnt)[(int64_t)it * kListHomes + hh];
+            const uint32_t *__restrict__ rowp = a.pairs + (int64_t)it * a.icap + (int64_t)hh * (rlast + 1);
+            auto entry = [&](int32_t r) -> uint32_t {
+                const uint32_t v = rowp[min(r, rlast)];
+                return r < cnt ? (v & kListSlotMask) : 0u;
+            };
+            R fx = 0, fy = 0, fz = 0;
+            uint32_t e1 = entry(lane);
+            PairData<F64> pd = load_packed<F64>(a.pk, a.pkx, e1);
+            for (int32_t c = 0; c < cnt; c += 64) {
+                const bool have = c + lane < cnt;
+                const uint32_t cj = e1;
+                const PairData<F64> cur = pd;
+                e1 = entry(c + 64 + lane);
+                pd = load_packed<F64>(a.pk, a.pkx, e1);
+                R px, py, pz;
+                double de;
+                pair_force<F64, false, DBG>(g, co, hd, we, DBG ? &rec : nullptr, tbl, rin2, csp, cj, have, cur, px,
+                                            py, pz, de);
+                fx += px; fy += py; fz += pz;
+                if (we) {
+                    asm volatile("");
+                    e += de;
+                }
+            }
+            fx = wave_sum(fx);
+            fy = wave_sum(fy);
+            fz = wave_sum(fz);
+            if (lane == 0) {
+                a.Fn[th] = (double)fx;
+                a.Fn[n + th] = (double)fy;
+                a.Fn[2 * n + th] = (double)fz;
+            }
+        }
+        const double es = wave_sum(e);
+        if (lane == 0) es_w[w] = es;
+        __syncthreads();
+    } else {
     const bool home = lane < H;
     const int64_t tt = t0 + (home ? lane : 0);
     HomeData<F64> hd;
@@ -985,13 +1052,11 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
     // this lane's column; rows past the stored ones are read as the last
     // stored row and not used (loads without a branch)
     const uint32_t *__restrict__ col = a.pairs + (int64_t)it * a.icap + lane;
-    const int32_t rlast = (int32_t)(a.icap / kListHomes) - 1;
     auto entry = [&](int32_t r) -> uint32_t {
         const uint32_t v = col[(int64_t)min(r, rlast) * kListHomes];
         return r < cnt ? (v & kListSlotMask) : 0u;
     };
     R fx = 0, fy = 0, fz = 0;
-    double e = 0.0;
     // rows w, w + kNW, ...: the entries two rows ahead and the candidate's
     // data of the next row are loaded while this one is evaluated
     int32_t k = w;
@@ -1024,6 +1089,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
         for (int d = 0; d < 3; ++d)
             a.Fn[d * n + tt] = (((double)pf[0][d][lane] + (double)pf[1][d][lane]) + (double)pf[2][d][lane]) +
                                (double)pf[3][d][lane];
+    }
     }
     if (threadIdx.x == 0) a.epart[it] = ((es_w[0] + es_w[1]) + es_w[2]) + es_w[3];
 }
@@ -1425,13 +1491,13 @@ void near_cells_launch(const EvalArgs &a, bool f64, int32_t slots, dim3 grid, di
 }  // namespace
 
 void launch_list_build(const EvalArgs &a, bool f64, const ListItem *items, int32_t nitems, int32_t slots,
-                       hipStream_t s) {
+                       hipStream_t s, bool copy_back) {
     // one item per block (a wave per quarter); a multiple of 8 blocks so that
     // the XCD mapping is a permutation of the blocks; then the blocks of the
     // copy back
     int32_t nblk = (nitems + 7) / 8 * 8;
     if (nblk < 8) nblk = 8;
-    const int64_t ncopy = std::min<int64_t>(1024, std::max<int64_t>(1, grid_for(a.N, 64 * kNW)));
+    const int64_t ncopy = copy_back ? std::min<int64_t>(1024, std::max<int64_t>(1, grid_for(a.N, 64 * kNW))) : 0;
     const dim3 grid((unsigned)(nblk + ncopy)), block(64 * kNW);
     (void)f64;  // the build's test is the same in both precisions
     list_build_launch(a, slots, grid, block, items, nitems, nblk, s);
@@ -1455,13 +1521,21 @@ void launch_near(const EvalArgs &a, bool f64, const ListItem *items, int32_t nit
     int32_t nblk = (nitems + 7) / 8 * 8;
     if (nblk < 8) nblk = 8;
     dim3 grid((unsigned)nblk), block(64 * kNW);
-    if (a.dbg_pairs) {
-        if (f64) hipLaunchKernelGGL((k_near_list<true, true>), grid, block, 0, s, a, items, nitems, nblk);
-        else hipLaunchKernelGGL((k_near_list<false, true>), grid, block, 0, s, a, items, nitems, nblk);
-    } else {
-        if (f64) hipLaunchKernelGGL((k_near_list<true, false>), grid, block, 0, s, a, items, nitems, nblk);
-        else hipLaunchKernelGGL((k_near_list<false, false>), grid, block, 0, s, a, items, nitems, nblk);
-    }
+    // one instantiation per layout: each keeps its own register budget
+    auto go = [&](auto f64c, auto hmc, auto dbgc) {
+        hipLaunchKernelGGL((k_near_list<decltype(f64c)::value, decltype(hmc)::value, decltype(dbgc)::value>), grid,
+                           block, 0, s, a, items, nitems, nblk);
+    };
+    auto by_hm = [&](auto f64c, auto dbgc) {
+        if (a.list_hm) go(f64c, std::true_type{}, dbgc);
+        else go(f64c, std::false_type{}, dbgc);
+    };
+    auto by_f64 = [&](auto dbgc) {
+        if (f64) by_hm(std::true_type{}, dbgc);
+        else by_hm(std::false_type{}, dbgc);
+    };
+    if (a.dbg_pairs) by_f64(std::true_type{});
+    else by_f64(std::false_type{});
 }
 
 void launch_neighbor_count(const EvalArgs &a, int32_t sys, int64_t n, int64_t p0, const int32_t *id_cur,

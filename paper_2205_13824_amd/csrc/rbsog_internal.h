@@ -130,10 +130,11 @@ struct NearItem {
 };
 // Near list item: up to kListHomes consecutive particle slots [t0, t1) of one
 // system (in the cell order of the latest list build).  Its block of the pair
-// list is icap entries: rows of kListHomes, the k-th pair of home h (slot
-// t0 + h) at entry k kListHomes + h (the candidate's slot), for
-// k < pcnt[item kListHomes + h].  The build writes the columns of its
-// kListWaves quarters of homes, one wave each.
+// list is icap entries (rows = icap / kListHomes): the k-th pair of home h
+// (slot t0 + h), k < pcnt[item kListHomes + h], is the candidate's slot at
+// entry k kListHomes + h (column blocks) or h rows + k (home-major blocks,
+// for long lists).  The build writes the lists of its four quarters of
+// homes, one wave each.
 constexpr int kListHomes = 64;
 constexpr int kListWaves = 4;
 struct ListItem {
@@ -207,6 +208,7 @@ struct EvalArgs {
     // the item in the top kListHomeBits bits, candidate slot below), counts,
     // capacity per item, largest count of the latest build, builds made
     int32_t *rebuild;
+    int32_t list_hm;       // nonzero: home-major blocks of the near list (long lists)
     int32_t always_build;  // nonzero: every evaluation builds (no displacement check, no list kept)
     uint32_t *pairs;
     int32_t *pcnt;
@@ -297,8 +299,9 @@ void launch_subset_forces(const EvalArgs &a, int64_t m, const int64_t *ids, int3
 // evaluation's near forces and energies, and the copy of the gathered state
 // back into `cur`; returns at once unless *a.rebuild is set.  slots (2..4):
 // candidates per lane and test pass
+// copy_back false: the list only (the state stays where it is)
 void launch_list_build(const EvalArgs &a, bool f64, const ListItem *items, int32_t nitems, int32_t slots,
-                       hipStream_t s);
+                       hipStream_t s, bool copy_back = true);
 // build-every-evaluation mode (a.always_build): near forces and energies in
 // one pass over cell runs (no list), and the copy back; returns at once
 // unless *a.rebuild is set

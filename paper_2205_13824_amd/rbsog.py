@@ -61,7 +61,7 @@ class rbsog_info_t(ctypes.Structure):
                 ("n_sys", ctypes.c_int32), ("rho_chunk", ctypes.c_int32), ("far_block", ctypes.c_int32),
                 ("tuned", ctypes.c_int32), ("list_capacity", ctypes.c_int64), ("list_builds", ctypes.c_int64),
                 ("skin", ctypes.c_double), ("rho_ktile", ctypes.c_int32), ("build_slots", ctypes.c_int32),
-                ("cell_slots", ctypes.c_int32)]
+                ("cell_slots", ctypes.c_int32), ("list_home_major", ctypes.c_int32)]
 
 
 _lib = None
@@ -323,7 +323,8 @@ def rbsog_info(ctx, sys: int = 0) -> dict:
                 evaluations=info.evaluations, n=info.n, n_sys=info.n_sys,
                 rho_chunk=info.rho_chunk, far_block=info.far_block, tuned=bool(info.tuned),
                 list_capacity=info.list_capacity, list_builds=info.list_builds, skin=info.skin,
-                rho_ktile=info.rho_ktile, build_slots=info.build_slots, cell_slots=info.cell_slots)
+                rho_ktile=info.rho_ktile, build_slots=info.build_slots, cell_slots=info.cell_slots,
+                list_home_major=bool(info.list_home_major))
 
 
 def rbsog_autotune(ctx, reps: int = 5) -> dict:

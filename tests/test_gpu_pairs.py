@@ -281,3 +281,34 @@ def test_kernel_pairs_along_a_trajectory(orc, prec, skin):
     print(f"prec={prec} skin={skin}: kernels seen {sorted(seen)}", flush=True)
     assert seen == ({2} if skin > 0 else {4})
     sysm.close()
+
+
+@pytest.mark.parametrize("prec", [R.RBSOG_FP64, R.RBSOG_FP32C])
+@pytest.mark.parametrize("dense", [False, True])
+def test_list_layouts_pairs_and_forces(orc, prec, dense):
+    # short lists are kept in columns (one home per lane in the list pass),
+    # long ones home by home (one home per wave): both give the oracle's
+    # neighbour set bit for bit and its near forces, at a build and after it
+    rng = np.random.default_rng(31)
+    n, Lb, rc = (1500, 10.0, 3.0) if dense else (3000, 30.0, 3.0)
+    pos = rng.random((n, 3)) * Lb
+    q = np.where(np.arange(n) < n // 2, 1.0, -1.0)
+    box = np.array([Lb] * 3)
+    sysm = R.System(pos, q, box, rc, 8, seed=5, precision=prec)
+    assert R.rbsog_info(sysm.ctx)["list_home_major"] == dense
+    R.rbsog_debug_record_pairs(sysm.ctx, 1 << 21)
+    sysm.sample_k(4)
+    row_o, cols_o = orc.neighbors_brute(pos, box, rc)
+    s = sysm.sog
+    Fo, _ = orc.near_brute(pos, q, box, rc, orc.SOG(s.b, s.sigma, s.w0, s.M))
+    tol = 1e-11 if prec == R.RBSOG_FP64 else 1e-5
+    for what in ("build", "list pass"):
+        sysm.forces()
+        row, cols, kinds = recorded_pairs(sysm)
+        assert kinds == 2
+        assert_same_csr(row, cols, row_o, cols_o, what)
+        Fn, _ = sysm.components()
+        err = np.sqrt(np.sum((Fn - Fo) ** 2) / np.sum(Fo ** 2))
+        print(f"dense={dense} prec={prec} {what}: near relrms {err:.2e}", flush=True)
+        assert err < tol
+    sysm.close()
