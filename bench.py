@@ -72,7 +72,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     # steps after the timed ones that run kernel by kernel with HIP events
-    ap.add_argument("--profile-steps", type=int, default=3)
+    ap.add_argument("--profile-steps", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-other", action="store_true")
     ap.add_argument("--other-steps", type=int, default=200)
@@ -90,10 +90,25 @@ def relrms(a, b):
     return math.sqrt(float(np.sum((a - b) ** 2)) / float(np.sum(b ** 2)))
 
 
-def read_profile(R, ctx):
-    prof = R.rbsog_profile_read(ctx)
-    return {k: {"ms_total": v[0], "launches": v[1], "us_per_launch": 1e3 * v[0] / max(v[1], 1)}
-            for k, v in prof.items() if v[1] > 0}
+def profile_steps_split(R, obj, mode, steps):
+    """Per-kernel HIP-event times over `steps` single steps in profile mode
+    `mode`: ({kernel: mean over the steps without a near-list build},
+    {kernel: mean over the steps with one})."""
+    acc = ({}, {})
+    for _ in range(steps):
+        nb0 = R.rbsog_info(obj.ctx)["list_builds"]
+        R.rbsog_profile(obj.ctx, mode)
+        obj.step(1, DT)
+        prof = R.rbsog_profile_read(obj.ctx)
+        built = R.rbsog_info(obj.ctx)["list_builds"] > nb0
+        for k, (t, cnt) in prof.items():
+            if cnt > 0:
+                a = acc[1 if built else 0].setdefault(k, [0.0, 0])
+                a[0] += t
+                a[1] += cnt
+    R.rbsog_profile(obj.ctx, 0)
+    return tuple({k: {"ms_total": v[0], "launches": v[1], "us_per_launch": 1e3 * v[0] / v[1]} for k, v in d.items()}
+                 for d in acc)
 
 
 def timed_steps(torch, obj, stream, steps):
@@ -130,19 +145,15 @@ def run_leg(R, torch, wl, prec, args, steps, near_table=False, autotune=True, pr
     setup = time.time() - t0
     ms = timed_steps(torch, sysm, stream, steps)
     info_end = R.rbsog_info(sysm.ctx)
-    kernels, alone = {}, {}
+    kernels, alone, build_step = {}, {}, {}
     ps = args.profile_steps if profile_steps is None else profile_steps
     if ps > 0:
         # kernel by kernel with HIP events on the stream each kernel runs on:
         # first as in the timed steps (the structure factor beside the near
-        # part on the second stream), then every kernel alone
-        R.rbsog_profile(sysm.ctx, 2)
-        sysm.step(ps, DT)
-        kernels = read_profile(R, sysm.ctx)
-        R.rbsog_profile(sysm.ctx, 1)
-        sysm.step(ps, DT)
-        alone = read_profile(R, sysm.ctx)
-        R.rbsog_profile(sysm.ctx, 0)
+        # part on the second stream for systems with little far work), then
+        # every kernel alone; steps that built a near list kept apart
+        kernels, build_step = profile_steps_split(R, sysm, 2, ps)
+        alone, _ = profile_steps_split(R, sysm, 1, ps)
         for k, v in kernels.items():
             if k in alone:
                 v["us_alone"] = alone[k]["us_per_launch"]
@@ -150,7 +161,7 @@ def run_leg(R, torch, wl, prec, args, steps, near_table=False, autotune=True, pr
     sysm.close()
     label = f"{n} prec={prec}{' core-shell' if near_table else ''}"
     log(f"[bench] {label}: {steps} steps in {ms:.2f} ms ({ms / steps:.4f} ms/step), setup {setup:.1f} s")
-    return dict(ms=ms, steps=steps, F0=F0, Fn0=Fn0, Ff0=Ff0, E0=E0, kernels=kernels,
+    return dict(ms=ms, steps=steps, F0=F0, Fn0=Fn0, Ff0=Ff0, E0=E0, kernels=kernels, build_step=build_step,
                 value=n * steps / (ms * 1e-3), ms_per_step=ms / steps, tune=tune,
                 shapes={k: info[k] for k in ("rho_chunk", "far_block", "rho_ktile", "build_slots", "cell_slots", "tuned", "list_capacity")},
                 builds=info_end["list_builds"], skin_end=info_end["skin"], setup_s=setup)
@@ -437,6 +448,7 @@ def main():
                           "tuning": {"fp32c": r32["tune"], "fp64": r64["tune"]}},
         "kernels_fp32c": r32["kernels"],
         "kernels_fp64": r64["kernels"],
+        "kernels_fp32c_build_steps": r32["build_step"],
         "setup_s": {"fp32c": r32["setup_s"], "fp64": r64["setup_s"]},
     }
     if not args.no_cpu_baseline and args.workload == "ions20M":

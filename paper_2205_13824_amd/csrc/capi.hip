@@ -231,6 +231,12 @@ struct rbsog_ctx {
     // step builds, so that the adaptive skin's switches reuse them) and per
     // variant (GV_*)
     bool use_graphs = true;
+    // the structure factor on a second stream beside the re-sort and the near
+    // part: when its (particle, k) work is small enough that the two do not
+    // each fill the device (sum of n P <= kSideMaxWork); larger systems run
+    // the kernels one after the other (both are bound by vector issue there,
+    // and the overlap only shares the same units)
+    bool use_side = true;
     hipGraph_t graph[2][GV_COUNT] = {};
     hipGraphExec_t graph_exec[2][GV_COUNT] = {};
     double graph_dt_m[2][GV_COUNT] = {};
@@ -612,8 +618,8 @@ rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt, bool kinetic, 
     // the structure factor and its reduction need the copy of the positions
     // and the k records staged by the kick/drift kernel only: they run on the
     // side stream beside the re-sort and the near part (one stream while
-    // profiling kernels alone)
-    const bool fork = c->prof_on != 1;
+    // profiling kernels alone, and for systems with a lot of far work)
+    const bool fork = c->prof_on != 1 && c->use_side;
     // building at every step, the far force joins them there (the near part
     // is long enough to hide it); it is then read back in the new order
     const bool far_side = a.always_build != 0;
@@ -800,6 +806,10 @@ rbsog_status request_build(rbsog_ctx *c) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return RBSOG_OK;
 }
+
+// (particle, k) pairs of one evaluation up to which the structure factor runs
+// beside the near part on the second stream
+constexpr double kSideMaxWork = 4e9;
 
 // Lists longer than this (pairs of one home at the sizing build) are kept in
 // home-major blocks, evaluated one home per wave; shorter ones in columns, one
@@ -1594,6 +1604,11 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     c->use_graphs = o.graphs != 0;
     c->skin = o.skin;
     c->skin_cur = o.skin;
+    {
+        double work = 0.0;
+        for (int32_t s = 0; s < nsys; ++s) work += (double)(offsets[s + 1] - offsets[s]) * (double)P[s];
+        c->use_side = work <= kSideMaxWork;
+    }
     for (int k = 0; k < K_COUNT; ++k) c->prof[k].name = kKernelNames[k];
     for (int32_t s = 0; s < nsys; ++s) {
         SysHost &h = c->sys[s];

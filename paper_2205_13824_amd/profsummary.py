@@ -99,23 +99,59 @@ def trace(directory, prefix):
         out.append("")
     tr = os.path.join(directory, f"{prefix}_kernel_trace.csv")
     if os.path.exists(tr):
-        per = defaultdict(list)
-        for r in _rows(tr):
-            dur = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
-            per[short_name(r["Kernel_Name"])].append((_grid(r), dur, None))
-        out.append("Steady-state dispatches (the grid size most dispatches used; dispatches shorter than a "
-                   "tenth of that group's median, which returned at once, left out):\n")
-        out.append("| kernel | grid | dispatches | mean us | median us | min us | max us |")
-        out.append("|---|---:|---:|---:|---:|---:|---:|")
         rows = []
-        for k, ds in per.items():
-            grid, st = steady(ds)
-            t = [d[1] / 1e3 for d in st]
-            rows.append((sum(t), f"| `{k}` | {grid} | {len(t)} / {len(ds)} | {statistics.mean(t):.1f} | "
-                                 f"{statistics.median(t):.1f} | {min(t):.1f} | {max(t):.1f} |"))
-        out += [r for _, r in sorted(rows, key=lambda x: -x[0])]
-        out.append("")
+        for r in _rows(tr):
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short_name(r["Kernel_Name"]), _grid(r)))
+        rows.sort()
+        windows = build_windows(rows)
+        per, per_b = defaultdict(list), defaultdict(list)
+        for s0, e0, k, g in rows:
+            (per_b if in_windows(windows, s0) else per)[k].append((g, e0 - s0, None))
+        out.append(f"Steady-state dispatches of steps without a near-list build ({len(windows)} steps with one left "
+                   "out; the grid size most dispatches used; dispatches shorter than a tenth of that group's "
+                   "median, which returned at once, left out):\n")
+        out += _steady_table(per)
+        if per_b:
+            out.append("Steps with a near-list build (same filters):\n")
+            out += _steady_table(per_b)
     return "\n".join(out)
+
+
+def _steady_table(per):
+    out = ["| kernel | grid | dispatches | mean us | median us | min us | max us |",
+           "|---|---:|---:|---:|---:|---:|---:|"]
+    rows = []
+    for k, ds in per.items():
+        grid, st = steady(ds)
+        t = [d[1] / 1e3 for d in st]
+        rows.append((sum(t), f"| `{k}` | {grid} | {len(t)} / {len(ds)} | {statistics.mean(t):.1f} | "
+                             f"{statistics.median(t):.1f} | {min(t):.1f} | {max(t):.1f} |"))
+    out += [r for _, r in sorted(rows, key=lambda x: -x[0])]
+    out.append("")
+    return out
+
+
+def build_windows(rows):
+    """[start, end] of the steps that built a near list: from the last k_kdq
+    dispatch before a working k_list_build (one longer than a quarter of the
+    longest) to the end of the first far-force dispatch after it.  rows:
+    sorted (start, end, kernel, grid)."""
+    builds = [(s, e) for s, e, k, _ in rows if k.startswith("k_list_build")]
+    if not builds:
+        return []
+    longest = max(e - s for s, e in builds)
+    out = []
+    for s, e in builds:
+        if e - s < 0.25 * longest:
+            continue
+        w0 = max((r[0] for r in rows if r[2] == "k_kdq" and r[0] <= s), default=s)
+        w1 = min((r[1] for r in rows if r[2].startswith(("k_far<", "k_far_finish")) and r[0] >= e), default=e)
+        out.append((w0, w1))
+    return out
+
+
+def in_windows(windows, t):
+    return any(w0 <= t <= w1 for w0, w1 in windows)
 
 
 def _counter_table(paths):
@@ -157,18 +193,20 @@ def traffic(directory, fetch_prefix, write_prefix, copy_mib):
     w = _counter_table([os.path.join(directory, f"{write_prefix}_counter_collection.csv")])
     kib = copy_mib * 1024
 
-    def probe(tab, counter):
-        # the copies: the dispatches whose count is nearest to the copy's size
-        best = None
-        for k, (_, _, _, vals) in tab.items():
-            if k.startswith("k_") or counter not in vals:
-                continue
-            v = vals[counter]
-            if best is None or abs(v - kib) / kib < abs(best[1] - kib) / kib:
-                best = (k, v)
-        return best
+    def probe(path, counter):
+        # the copies: the non-library dispatches with the largest count (the
+        # copy probe moves far more than any other copy of the run), mean of
+        # those within 10 % of it
+        vals = [(short_name(r["Kernel_Name"]), float(r["Counter_Value"])) for r in _rows(path)
+                if r["Counter_Name"] == counter and not short_name(r["Kernel_Name"]).startswith("k_")]
+        if not vals:
+            return None
+        top = max(v for _, v in vals)
+        sel = [(k, v) for k, v in vals if v >= 0.9 * top]
+        return sel[0][0], statistics.mean(v for _, v in sel)
 
-    pf, pw = probe(f, "FETCH_SIZE"), probe(w, "WRITE_SIZE")
+    pf = probe(os.path.join(directory, f"{fetch_prefix}_counter_collection.csv"), "FETCH_SIZE")
+    pw = probe(os.path.join(directory, f"{write_prefix}_counter_collection.csv"), "WRITE_SIZE")
     if pf is None or pw is None:
         raise SystemExit("no copy-probe dispatch in the counter files")
     sf, sw = kib / pf[1], kib / pw[1]
