@@ -44,7 +44,11 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kRanges = 18; // 9 rows of cells x up to 2 contiguous pieces
 constexpr float kFarR2 = 3.0e38f;  // r^2 of a pair that no test admits
-constexpr int kExpRegs = 4;        // narrow Gaussians evaluated with constants held in registers
+// narrow Gaussians evaluated with constants held in registers, no test of
+// their count (Table 1 row 2 at any cutoff has 3 below the FP32 tail's
+// threshold and 5 below the FP64 one; further ones take a counted loop)
+template <bool F64>
+constexpr int kExpRegs = F64 ? 5 : 3;
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
@@ -368,10 +372,12 @@ template <bool F64>
 __device__ __forceinline__ PairData<F64> load_packed(const uint4 *__restrict__ pk, const PosQ64 *__restrict__ pkx,
                                                      uint32_t j) {
     PairData<F64> d;
-    const uint4 r = pk[j & kListSlotMask];
+    // slots below 2^28: 32-bit byte offsets from the arrays' (scalar) bases
+    const uint32_t jj = j & kListSlotMask;
+    const uint4 r = *(const uint4 *)((const char *)pk + (jj << 4));
     d.u[0] = r.x; d.u[1] = r.y; d.u[2] = r.z;
     if constexpr (F64) {
-        const PosQ64 w = pkx[j & kListSlotMask];
+        const PosQ64 w = *(const PosQ64 *)((const char *)pkx + (jj << 5));
         d.x[0] = w.x; d.x[1] = w.y; d.x[2] = w.z;
         d.q = w.q;
     } else {
@@ -429,113 +435,113 @@ __device__ __forceinline__ void pair_force(const Geom &g, typename CoefOf<F64>::
                                            typename HomeData<F64>::R &fz, double &de) {
     using R = typename HomeData<F64>::R;
     constexpr int NT = (F64 ? kTailDeg64 : kTailDeg32) + 1;
-    fx = 0; fy = 0; fz = 0;
-    de = 0.0;
-    if (have) {
-        const uint32_t dux = pd.u[0] - h.u[0], duy = pd.u[1] - h.u[1], duz = pd.u[2] - h.u[2];
-        const float ex_ = (float)(int32_t)dux * g.hf[0];
-        const float ey_ = (float)(int32_t)duy * g.hf[1];
-        const float ez_ = (float)(int32_t)duz * g.hf[2];
-        const float r2f = ex_ * ex_ + ey_ * ey_ + ez_ * ez_;
-        bool in = r2f <= g.band_lo_f;
-        if (!in && r2f < g.band_hi_f) in = exact_in(g, dux, duy, duz);
-        if constexpr (SELF) in = in && cslot != h.slot;
-        if constexpr (DBG) {
-            if (in) {
-                const int32_t k = atomicAdd(rec->cnt, 1);
-                if (k < rec->cap) rec->out[k] = make_uint2((uint32_t)rec->id[h.slot], (uint32_t)rec->id[cslot]);
-            }
-        }
+    // every lane computes (no branch on `have` or on the pair rule: a lane
+    // mask change costs more than the arithmetic); a select zeroes what a
+    // rejected or empty lane produced, whatever its value
+    const uint32_t dux = pd.u[0] - h.u[0], duy = pd.u[1] - h.u[1], duz = pd.u[2] - h.u[2];
+    const float ex_ = (float)(int32_t)dux * g.hf[0];
+    const float ey_ = (float)(int32_t)duy * g.hf[1];
+    const float ez_ = (float)(int32_t)duz * g.hf[2];
+    const float r2f = ex_ * ex_ + ey_ * ey_ + ez_ * ez_;
+    bool in = r2f <= g.band_lo_f;
+    // the exact rule only inside the narrow band (rare: a branch)
+    if (have && !in && r2f < g.band_hi_f) in = exact_in(g, dux, duy, duz);
+    in = in && have;
+    if constexpr (SELF) in = in && cslot != h.slot;
+    if constexpr (DBG) {
         if (in) {
-            R dx, dy, dz, qq;
-            if constexpr (F64) {
-                dx = mi64(pd.x[0] - h.x[0], g.L[0], g.invL[0]);
-                dy = mi64(pd.x[1] - h.x[1], g.L[1], g.invL[1]);
-                dz = mi64(pd.x[2] - h.x[2], g.L[2], g.invL[2]);
-                qq = h.q * pd.q;
-            } else {
-                dx = ex_; dy = ey_; dz = ez_;
-                qq = h.q * pd.q;
-            }
-            const R r2 = F64 ? dx * dx + dy * dy + dz * dz : r2f;
-            R gk, hk;  // force coefficient g and pair potential h of the split
-            if (!F64 && tbl) {
-                if (r2 >= rin2) {
-                    // shell: table point from the FP32 bits of r^2, linear in r^2
-                    const uint32_t bits = __float_as_uint(r2f);
-                    const float4 tv = tbl[(bits >> (23 - kTabBman)) & (kTabSize - 1)];
-                    const float fr = (float)(bits & ((1u << (23 - kTabBman)) - 1u)) * (1.0f / (1 << (23 - kTabBman)));
-                    gk = fmaf(fr, tv.y, tv.x);
-                    hk = fmaf(fr, tv.w, tv.z);
-                } else {
-                    // core: Taylor terms of the Gaussians, 1/r and 1/r^3 computed
-                    const float ri = __builtin_amdgcn_rsqf(r2f);
-                    float pa = csp->ta[kTabQ - 1], pb = csp->tb[kTabQ - 1];
+            const int32_t k = atomicAdd(rec->cnt, 1);
+            if (k < rec->cap) rec->out[k] = make_uint2((uint32_t)rec->id[h.slot], (uint32_t)rec->id[cslot]);
+        }
+    }
+    R dx, dy, dz, qq;
+    if constexpr (F64) {
+        dx = mi64(pd.x[0] - h.x[0], g.L[0], g.invL[0]);
+        dy = mi64(pd.x[1] - h.x[1], g.L[1], g.invL[1]);
+        dz = mi64(pd.x[2] - h.x[2], g.L[2], g.invL[2]);
+    } else {
+        dx = ex_; dy = ey_; dz = ez_;
+    }
+    qq = h.q * pd.q;
+    const R r2 = F64 ? dx * dx + dy * dy + dz * dz : r2f;
+    R gk, hk;  // force coefficient g and pair potential h of the split
+    if (!F64 && tbl) {
+        if (r2 >= rin2) {
+            // shell: table point from the FP32 bits of r^2, linear in r^2
+            const uint32_t bits = __float_as_uint(r2f);
+            const float4 tv = tbl[(bits >> (23 - kTabBman)) & (kTabSize - 1)];
+            const float fr = (float)(bits & ((1u << (23 - kTabBman)) - 1u)) * (1.0f / (1 << (23 - kTabBman)));
+            gk = fmaf(fr, tv.y, tv.x);
+            hk = fmaf(fr, tv.w, tv.z);
+        } else {
+            // core: Taylor terms of the Gaussians, 1/r and 1/r^3 computed
+            const float ri = __builtin_amdgcn_rsqf(r2f);
+            float pa = csp->ta[kTabQ - 1], pb = csp->tb[kTabQ - 1];
 #pragma unroll
-                    for (int t = kTabQ - 2; t >= 0; --t) pa = fmaf(pa, r2f, csp->ta[t]);
-                    if (we) {
-#pragma unroll
-                        for (int t = kTabQ - 2; t >= 0; --t) pb = fmaf(pb, r2f, csp->tb[t]);
-                    }
-                    gk = ri * ri * ri - 2.0f * pa;
-                    hk = ri - pb;
-                }
-            } else {
-                // Horner from the leading coefficient
-                R rinv, gs = co->ft[NT - 1], ph = 0;
-                if constexpr (F64) rinv = rsqrt(r2);
-                else rinv = __builtin_amdgcn_rsqf(r2);
-#pragma unroll
-                for (int t = NT - 2; t >= 0; --t) {
-                    if constexpr (F64) gs = fma(gs, r2, co->ft[t]);
-                    else gs = fmaf(gs, r2, co->ft[t]);
-                }
-                if (we) {
-                    ph = co->pt[NT - 1];
-#pragma unroll
-                    for (int t = NT - 2; t >= 0; --t) {
-                        if constexpr (F64) ph = fma(ph, r2, co->pt[t]);
-                        else ph = fmaf(ph, r2, co->pt[t]);
-                    }
-                }
-                // the first kExpRegs terms at fixed indices, with no test of
-                // the count: the constants past it are zero (a term of weight
-                // 0 adds exactly 0)
-                R exv[kExpRegs];
-#pragma unroll
-                for (int l = 0; l < kExpRegs; ++l) {
-                    if constexpr (F64) exv[l] = exp(-r2 * co->a[l]);
-                    else exv[l] = __builtin_amdgcn_exp2f(-r2 * co->a[l]);
-                    gs += co->cw[l] * exv[l];
-                }
-                // the potential's terms only when energies are summed: a
-                // uniform branch, kept a branch by the empty asm statement
-                // (which the compiler does not speculate)
-                if (we) {
-                    asm volatile("");
-#pragma unroll
-                    for (int l = 0; l < kExpRegs; ++l) ph += co->w[l] * exv[l];
-                }
-                for (int l = kExpRegs; l < co->nexp; ++l) {
-                    R ex;
-                    if constexpr (F64) ex = exp(-r2 * co->a[l]);
-                    else ex = __builtin_amdgcn_exp2f(-r2 * co->a[l]);
-                    gs += co->cw[l] * ex;
-                    if (we) ph += co->w[l] * ex;
-                }
-                gk = rinv * rinv * rinv - gs;
-                hk = rinv - ph;
-            }
-            const R coef = qq * gk;
-            // force on the home along r_i - r_j = -(dx, dy, dz)
-            fx = -coef * dx;
-            fy = -coef * dy;
-            fz = -coef * dz;
+            for (int t = kTabQ - 2; t >= 0; --t) pa = fmaf(pa, r2f, csp->ta[t]);
             if (we) {
-                asm volatile("");
-                de = 0.5 * (double)(qq * hk);
+#pragma unroll
+                for (int t = kTabQ - 2; t >= 0; --t) pb = fmaf(pb, r2f, csp->tb[t]);
+            }
+            gk = ri * ri * ri - 2.0f * pa;
+            hk = ri - pb;
+        }
+    } else {
+        // Horner from the leading coefficient
+        R rinv, gs = co->ft[NT - 1], ph = 0;
+        if constexpr (F64) rinv = rsqrt(r2);
+        else rinv = __builtin_amdgcn_rsqf(r2);
+#pragma unroll
+        for (int t = NT - 2; t >= 0; --t) {
+            if constexpr (F64) gs = fma(gs, r2, co->ft[t]);
+            else gs = fmaf(gs, r2, co->ft[t]);
+        }
+        if (we) {
+            ph = co->pt[NT - 1];
+#pragma unroll
+            for (int t = NT - 2; t >= 0; --t) {
+                if constexpr (F64) ph = fma(ph, r2, co->pt[t]);
+                else ph = fmaf(ph, r2, co->pt[t]);
             }
         }
+        // the first kExpRegs terms at fixed indices, with no test of
+        // the count: the constants past it are zero (a term of weight
+        // 0 adds exactly 0)
+        constexpr int NE = kExpRegs<F64>;
+        R exv[NE];
+#pragma unroll
+        for (int l = 0; l < NE; ++l) {
+            if constexpr (F64) exv[l] = exp(-r2 * co->a[l]);
+            else exv[l] = __builtin_amdgcn_exp2f(-r2 * co->a[l]);
+            gs += co->cw[l] * exv[l];
+        }
+        // the potential's terms only when energies are summed: a
+        // uniform branch, kept a branch by the empty asm statement
+        // (which the compiler does not speculate)
+        if (we) {
+            asm volatile("");
+#pragma unroll
+            for (int l = 0; l < NE; ++l) ph += co->w[l] * exv[l];
+        }
+        for (int l = NE; l < co->nexp; ++l) {
+            R ex;
+            if constexpr (F64) ex = exp(-r2 * co->a[l]);
+            else ex = __builtin_amdgcn_exp2f(-r2 * co->a[l]);
+            gs += co->cw[l] * ex;
+            if (we) ph += co->w[l] * ex;
+        }
+        gk = rinv * rinv * rinv - gs;
+        hk = rinv - ph;
+    }
+    // force on the home along r_i - r_j = -(dx, dy, dz); zero unless accepted
+    const R coef = in ? qq * gk : (R)0;
+    fx = -coef * dx;
+    fy = -coef * dy;
+    fz = -coef * dz;
+    de = 0.0;
+    if (we) {
+        asm volatile("");
+        de = in ? 0.5 * (double)(qq * hk) : 0.0;
     }
 }
 
@@ -553,14 +559,14 @@ __device__ __forceinline__ void eval_loaded(const Geom &g, typename CoefOf<F64>:
     R fx, fy, fz;
     double de;
     const int slot = have ? (int)qe.x : -1;
+    // an empty lane reads home 0 (its pair is not accepted)
+    const int hs = have ? slot : 0;
     HomeData<F64> h;
-    if (have) {
-        const uint4 hu = L.hu[slot];
-        h.u[0] = hu.x; h.u[1] = hu.y; h.u[2] = hu.z; h.slot = hu.w;
-        h.q = L.hq[slot];
-        if constexpr (F64) {
-            h.x[0] = L.hx[0][slot]; h.x[1] = L.hx[1][slot]; h.x[2] = L.hx[2][slot];
-        }
+    const uint4 hu = L.hu[hs];
+    h.u[0] = hu.x; h.u[1] = hu.y; h.u[2] = hu.z; h.slot = hu.w;
+    h.q = L.hq[hs];
+    if constexpr (F64) {
+        h.x[0] = L.hx[0][hs]; h.x[1] = L.hx[1][hs]; h.x[2] = L.hx[2][hs];
     }
     pair_force<F64, SELF, DBG>(g, co, h, L.we, L.rec, tbl, rin2, csp, qe.y, have, pd, fx, fy, fz, de);
     if (L.we) {
@@ -1051,9 +1057,9 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
     const int32_t maxcnt = rfl(mc);
     // this lane's column; rows past the stored ones are read as the last
     // stored row and not used (loads without a branch)
-    const uint32_t *__restrict__ col = a.pairs + (int64_t)it * a.icap + lane;
+    const char *__restrict__ blk = (const char *)(a.pairs + (int64_t)it * a.icap);
     auto entry = [&](int32_t r) -> uint32_t {
-        const uint32_t v = col[(int64_t)min(r, rlast) * kListHomes];
+        const uint32_t v = *(const uint32_t *)(blk + (uint32_t)((min(r, rlast) * kListHomes + lane) * 4));
         return r < cnt ? (v & kListSlotMask) : 0u;
     };
     R fx = 0, fy = 0, fz = 0;
