@@ -37,19 +37,15 @@ METRIC = "particle-steps/s, RBSOG forces FP32-comp vs FP64, at <=1e-5 rel RMS fo
 # flops per lane), vector FP64 78.6 TFLOP/s, HBM3E 8 TB/s
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
-# VALU issue slots per second for non-packed instructions (256 CUs x 4 SIMDs x
-# 16 lanes x 2.4 GHz); a transcendental (sin, cos, exp, rsqrt) takes two of
-# them (a probe on the card: 1.85e13 v_sin_f32 lane-ops/s against 3.71e13
-# v_fma_f32)
-PEAK_VALU_SLOTS = 256 * 4 * 16 * 2.4e9
-TRANS_SLOTS = 2
-# Algorithmic work per unit, flops (FMA = 2, transcendental = 1), as the
-# method states it (candidate rejects and list doubling are overhead):
-#   structure factor per (particle, k): phase 3 FMA-class + accumulate 2 FMA, sin + cos
-#   far force per (particle, k): phase 3 + Im 2 + accumulate 3 FMA-class, sin + cos
-#   near part per unique pair inside r_c: rsqrt + M+1 = 17 exp + ~40 FMA-class
-FLOPS = {"rho": 2 * 5 + 2, "far": 2 * 8 + 2, "near": 2 * 40 + 18}
-SLOTS = {"rho": 5 + 2 * TRANS_SLOTS, "far": 8 + 2 * TRANS_SLOTS, "near": 40 + 18 * TRANS_SLOTS}
+# Algorithmic work per unit as the method states it (candidate rejects and
+# the full list's second evaluation of a pair are overhead): FMA-class
+# operations and transcendentals
+#   structure factor per (particle, k): phase 3 + accumulate 2, sin + cos
+#   far force per (particle, k): phase 3 + Im 2 + accumulate 3, sin + cos
+#   near part per unique pair inside r_c: ~40 FMA-class, rsqrt + M+1 = 17 exp
+OPS = {"rho": (5, 2), "far": (8, 2), "near": (40, 18)}
+# flops: an FMA-class operation 2, a transcendental 1
+FLOPS = {k: 2 * f + t for k, (f, t) in OPS.items()}
 
 DEVICE_CHAINS = 64
 DT = 1e-3
@@ -203,11 +199,13 @@ def traffic_of(tab, key, fp64):
     return None
 
 
-def rooflines(kernels, n, P, near_pairs, fp64, traffic=None):
+def rooflines(kernels, n, P, near_pairs, fp64, traffic=None, rates=None):
     """Per kernel: algorithmic flops per launch / measured launch time (HIP
     events, as in the timed steps) against the published vector peak of the
-    precision; the same with the kernel alone on the device; and the work in
-    VALU issue slots against the slot rate."""
+    precision; the same with the kernel alone on the device; and (FP32) the
+    time the algorithmic operations take at this device's measured issue
+    rates (FMA-class at the FP32 FMA rate, transcendentals at the sin/cos
+    rate), as a fraction of the launch time."""
     units = {"rho": n * P, "far": n * P, "far_side": n * P, "near": near_pairs, "near_cells": near_pairs}
     kind = {"rho": "rho", "far": "far", "far_side": "far", "near": "near", "near_cells": "near"}
     peak = PEAK_FP64_TFLOPS if fp64 else PEAK_FP32_TFLOPS
@@ -224,11 +222,11 @@ def rooflines(kernels, n, P, near_pairs, fp64, traffic=None):
         if "us_alone" in v:
             a = flops / (v["us_alone"] * 1e-6) / 1e12
             out[k]["alone"] = {"us_per_launch": v["us_alone"], "achieved": a, "frac": a / peak}
-        if not fp64:
-            slots = units[k] * SLOTS[kind[k]] / t
-            out[k]["lane_slots"] = {"achieved": slots / 1e12, "peak": PEAK_VALU_SLOTS / 1e12,
-                                    "unit": "T VALU lane-slots/s", "frac": slots / PEAK_VALU_SLOTS,
-                                    "slots_per_unit": SLOTS[kind[k]]}
+        if rates and not fp64:
+            f, tr = OPS[kind[k]]
+            tb = units[k] * (f / rates["v_fma_f32"] + tr / rates["v_sin_f32"])
+            out[k]["measured_rates"] = {"us_at_rates": tb * 1e6, "frac": tb / t,
+                                        "fma_per_unit": f, "trans_per_unit": tr}
     return out
 
 
@@ -325,7 +323,7 @@ def other_workloads(R, W, torch, args, near_pairs_c2=None):
     r32t = run_leg(R, torch, c2, R.RBSOG_FP32C, args, steps, near_table=True, autotune=not args.no_autotune,
                    profile_steps=5)
     pairs2 = count_near_pairs(R, c2)
-    rl2 = rooflines(r32["kernels"], n2, c2["P"], pairs2, False, traffic_table("c2_electrolyte300k"))
+    rl2 = rooflines(r32["kernels"], n2, c2["P"], pairs2, False, traffic_table("electrolyte300k"))
     out["electrolyte_300k"] = {
         "workload": f"{n2}-ion +-1 electrolyte, density 0.1, RSA d_min=1, r_c=3.5, P={c2['P']}, velocity-Verlet",
         "fp32c": {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "shapes": r32["shapes"]},
@@ -408,6 +406,8 @@ def main():
     n, P = len(wl["q"]), wl["P"]
     log(f"[bench] headline workload built in {time.time() - t0:.1f} s: n={n} L={wl['box'][0]:.4f} P={P}")
 
+    # this device's issue rates (lane-instructions/s) for the measured-rate bounds
+    rates = R.rbsog_probe_rates(0, 3)
     r32 = run_leg(R, torch, wl, R.RBSOG_FP32C, args, args.steps, autotune=not args.no_autotune)
     r64 = run_leg(R, torch, wl, R.RBSOG_FP64, args, args.steps, autotune=not args.no_autotune)
     err = {"total": relrms(r32["F0"], r64["F0"]), "near": relrms(r32["Fn0"], r64["Fn0"]),
@@ -415,8 +415,8 @@ def main():
     log(f"[bench] FP32C vs FP64 force relrms: {err}")
     pairs = count_near_pairs(R, wl)
     traffic = traffic_table(args.workload)
-    rl32 = rooflines(r32["kernels"], n, P, pairs, False, traffic)
-    rl64 = rooflines(r64["kernels"], n, P, pairs, True, traffic)
+    rl32 = rooflines(r32["kernels"], n, P, pairs, False, traffic, rates)
+    rl64 = rooflines(r64["kernels"], n, P, pairs, True, traffic, rates)
     out = {
         "metric": METRIC,
         "value": r32["value"],
@@ -442,6 +442,7 @@ def main():
         "roofline": dominant(rl32),
         "rooflines": rl32,
         "near_pairs": pairs,
+        "measured_rates": {"unit": "lane-instructions/s", **rates},
         "near_list": {"builds": r32["builds"], "evaluations": 1 + args.warmup + args.steps,
                       "skin_at_end": r32["skin_end"]},
         "launch_shapes": {"fp32c": r32["shapes"], "fp64": r64["shapes"],
