@@ -181,14 +181,14 @@ KERNEL_NAMES = {"rho": "k_rho", "far": "k_far", "far_side": "k_far_side", "near"
 
 def traffic_table(workload):
     """HBM bytes per launch from the committed counter summary of the
-    workload, if it was taken from the current kernel sources (else {})."""
+    workload, for the kernels whose sources have not changed since (else
+    none)."""
     from paper_2205_13824_amd import profsummary
 
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
     if not os.path.exists(path):
         return {}
-    sha, tab = profsummary.read_traffic(path)
-    return tab if sha == profsummary.sources_sha256() else {}
+    return profsummary.read_traffic(path)
 
 
 def traffic_of(tab, key, fp64):

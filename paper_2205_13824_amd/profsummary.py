@@ -4,15 +4,16 @@
         kernel durations from <prefix>_kernel_stats.csv (every dispatch) and
         <prefix>_kernel_trace.csv (the steady-state dispatches: those of the
         grid size most dispatches of the kernel used, without the ones that
-        returned at once)
+        returned at once, steps with a near-list build apart)
     python3 -m paper_2205_13824_amd.profsummary counters <dir> <prefix> [...]
         per-dispatch counter means from <prefix>_counter_collection.csv files
         (steady-state dispatches as above)
     python3 -m paper_2205_13824_amd.profsummary traffic <dir> <fetch_prefix> <write_prefix> <copy_mib>
         HBM bytes per dispatch: FETCH_SIZE and WRITE_SIZE (KiB) scaled by what
         they read for the plain device-to-device copies of <copy_mib> MiB that
-        bench.py --copy-probe-mib runs last; ends with the SHA-256 of the
-        kernel sources, which bench.py compares before it reports the bytes
+        bench.py --copy-probe-mib runs last; each row carries the hash of
+        its kernel's source file and the shared headers, which bench.py
+        compares before it reports the bytes
 
 Only files that rocprofv3 wrote are read; nothing here runs on the GPU.
 """
@@ -38,6 +39,36 @@ def sources_sha256() -> str:
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()
+
+
+# the source file that defines each kernel of the library
+KERNEL_FILES = {
+    "k_rho": "kernels_far.hip", "k_rho_reduce": "kernels_far.hip", "k_far": "kernels_far.hip",
+    "k_far_side": "kernels_far.hip", "k_far_finish": "kernels_far.hip",
+    "k_near_list": "kernels_near.hip", "k_near_cells": "kernels_near.hip", "k_list_build": "kernels_near.hip",
+    "k_neighbors": "kernels_near.hip",
+    "k_kdq": "kernels_md.hip", "k_bin": "kernels_md.hip", "k_scan_blocks": "kernels_md.hip",
+    "k_scan_apply": "kernels_md.hip", "k_cell_scatter": "kernels_md.hip", "k_sort_gather": "kernels_md.hip",
+    "k_kinetic": "kernels_md.hip", "k_msd": "kernels_md.hip", "k_fill_i32": "kernels_md.hip",
+    "k_refill": "kernels_sample.hip", "k_sf_partial": "structure_factor.hip", "k_sf_reduce": "structure_factor.hip",
+    "k_probe": "probe_rates.hip",
+}
+
+
+def kernel_sha16(kernel: str):
+    """First 16 hex digits of the hash of the file that defines `kernel`
+    (short name, template arguments allowed) and the shared headers; None
+    for kernels outside the library."""
+    base = kernel.split("<")[0]
+    src = KERNEL_FILES.get(base)
+    if src is None:
+        return None
+    h = hashlib.sha256()
+    for name in (src, "rbsog_internal.h", "rbsog_math.h"):
+        with open(os.path.join(HERE, "csrc", name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def short_name(name: str) -> str:
@@ -213,8 +244,8 @@ def traffic(directory, fetch_prefix, write_prefix, copy_mib):
     out = [f"Scale factors from the plain copy (`{pf[0]}`, {copy_mib} MiB read and written per dispatch):\n",
            f"* FETCH_SIZE reads {pf[1]:.0f} KiB per copy: scale {sf:.4f}",
            f"* WRITE_SIZE reads {pw[1]:.0f} KiB per copy: scale {sw:.4f}", "",
-           "| kernel | dispatches | FETCH_SIZE KiB | read bytes / launch | WRITE_SIZE KiB | written bytes / launch |",
-           "|---|---:|---:|---:|---:|---:|"]
+           "| kernel | dispatches | FETCH_SIZE KiB | read bytes / launch | WRITE_SIZE KiB | written bytes / launch | source sha256 |",
+           "|---|---:|---:|---:|---:|---:|---|"]
     for k in sorted(f, key=lambda k: -f[k][3].get("FETCH_SIZE", 0.0)):
         if not k.startswith("k_"):
             continue
@@ -223,23 +254,22 @@ def traffic(directory, fetch_prefix, write_prefix, copy_mib):
         if fv is None or wv is None:
             continue
         out.append(f"| `{k}` | {f[k][1]} / {f[k][2]} | {fv:.0f} | {fv * sf * 1024:.4g} | {wv:.0f} | "
-                   f"{wv * sw * 1024:.4g} |")
+                   f"{wv * sw * 1024:.4g} | {kernel_sha16(k)} |")
     out.append("")
-    out.append(f"sources-sha256: {sources_sha256()}")
     return "\n".join(out) + "\n"
 
 
 def read_traffic(path):
-    """(sources hash, {kernel: (read bytes, written bytes)}) of a traffic summary."""
-    sha, tab = None, {}
+    """{kernel: (read bytes, written bytes)} of a traffic summary, for the
+    kernels whose source still hashes to the value recorded there."""
+    tab = {}
     with open(path) as f:
         for line in f:
-            if line.startswith("sources-sha256:"):
-                sha = line.split(":", 1)[1].strip()
-            m = re.match(r"\| `(k_[^`]+)` \| [^|]+\| [^|]+\| ([0-9.e+]+) \| [^|]+\| ([0-9.e+]+) \|", line)
-            if m:
+            m = re.match(r"\| `(k_[^`]+)` \| [^|]+\| [^|]+\| ([0-9.e+]+) \| [^|]+\| ([0-9.e+]+) \| ([0-9a-f]+) \|",
+                         line)
+            if m and m.group(4) == kernel_sha16(m.group(1)):
                 tab[m.group(1)] = (float(m.group(2)), float(m.group(3)))
-    return sha, tab
+    return tab
 
 
 def main(argv):
