@@ -4,9 +4,10 @@
 //   F*_i     = -q_i sum_e w_e k_e (Im rho_e cos th_ie - Re rho_e sin th_ie),  th_ie = k_e.r_i
 //   U*       = 1/2 sum_e w_e |rho_e|^2
 // Phases are taken in revolutions of the fractional coordinate, th/(2 pi) =
-// m.s with s = x/L: FP64 forms evaluate f = m.s - rint(m.s) and a polynomial
-// sin/cos of 2 pi f; FP32 forms take m.u mod 2^32 exactly on the 32-bit
-// fixed-point coordinate and the hardware sin/cos of the revolution.
+// m.s with s = x/L: FP64 forms evaluate t = m.s in FP64 and sin/cos of 2 pi t
+// through a table of 256 turns in LDS and short polynomials of the rest;
+// FP32 forms take m.u mod 2^32 exactly on the 32-bit fixed-point coordinate
+// and the hardware sin/cos of the revolution.
 //
 // Work split: the structure factor puts one wave vector on each lane and
 // streams particles uniformly through the wave (no cross-lane reduction in
@@ -52,40 +53,6 @@ __device__ __forceinline__ KRec32 ld(CRec32 *p) {
     return r;
 }
 
-// sin(2 pi f) for |f| <= 1/2 in FP64: reflected into |g| <= 1/4 (sin(pi - x)
-// = sin x), then the Taylor series of sin(2 pi g) through degree 23
-// (truncation below 2e-18 at |2 pi g| <= pi/2), Horner in g^2.
-__device__ __forceinline__ double sin2pi(double f) {
-    constexpr double T = rmath::kTwoPi;
-    constexpr double T2 = T * T;
-    constexpr double C0 = T;
-    constexpr double C1 = -C0 * T2 / 6.0;
-    constexpr double C2 = -C1 * T2 / 20.0;
-    constexpr double C3 = -C2 * T2 / 42.0;
-    constexpr double C4 = -C3 * T2 / 72.0;
-    constexpr double C5 = -C4 * T2 / 110.0;
-    constexpr double C6 = -C5 * T2 / 156.0;
-    constexpr double C7 = -C6 * T2 / 210.0;
-    constexpr double C8 = -C7 * T2 / 272.0;
-    constexpr double C9 = -C8 * T2 / 342.0;
-    constexpr double C10 = -C9 * T2 / 420.0;
-    constexpr double C11 = -C10 * T2 / 506.0;
-    const double g = f > 0.25 ? 0.5 - f : (f < -0.25 ? -0.5 - f : f);
-    const double z = g * g;
-    double p = fma(z, C11, C10);
-    p = fma(z, p, C9);
-    p = fma(z, p, C8);
-    p = fma(z, p, C7);
-    p = fma(z, p, C6);
-    p = fma(z, p, C5);
-    p = fma(z, p, C4);
-    p = fma(z, p, C3);
-    p = fma(z, p, C2);
-    p = fma(z, p, C1);
-    p = fma(z, p, C0);
-    return g * p;
-}
-
 // Uniform values loaded from memory: keep them scalar.
 __device__ __forceinline__ int32_t rfl(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ int64_t rfl64(int64_t v) {
@@ -112,6 +79,17 @@ __global__ __launch_bounds__(1024, F64 ? 1 : 8) void k_rho(EvalArgs a, const Rho
     __shared__ double2 red[1024];
     __shared__ uint4 st32[F64 ? 1 : kStage];
     __shared__ Stage64 st64[F64 ? kStage : 1];
+    // FP64: cos and sin of the kTurnTab turns (sincos2pi_tab); the staging
+    // loop's first barrier orders the fill before any use
+    __shared__ double2 turn[F64 ? rmath::kTurnTab : 1];
+    if constexpr (F64) {
+        if ((int)threadIdx.x < rmath::kTurnTab) {
+            const double f = (double)threadIdx.x / rmath::kTurnTab;
+            double sn, cs;
+            sincos2pi(f - rint(f), &sn, &cs);
+            turn[threadIdx.x] = make_double2(cs, sn);
+        }
+    }
     const int64_t n = a.N;
     // the state as the kick/drift kernel left it, in its copy: the re-sort of
     // the state into cell order may run meanwhile
@@ -153,7 +131,7 @@ __global__ __launch_bounds__(1024, F64 ? 1 : 8) void k_rho(EvalArgs a, const Rho
                         for (int g = 0; g < 4; ++g) {
                             const double t = mx * p[g].sx + my * p[g].sy + mz * p[g].sz;
                             double sn, cs;
-                            sincos2pi(t - rint(t), &sn, &cs);
+                            rmath::sincos2pi_tab(t, turn, &sn, &cs);
                             re = fma(p[g].q, cs, re);
                             im = fma(p[g].q, sn, im);
                         }
@@ -162,7 +140,7 @@ __global__ __launch_bounds__(1024, F64 ? 1 : 8) void k_rho(EvalArgs a, const Rho
                         const Stage64 p = st64[h];
                         const double t = mx * p.sx + my * p.sy + mz * p.sz;
                         double sn, cs;
-                        sincos2pi(t - rint(t), &sn, &cs);
+                        rmath::sincos2pi_tab(t, turn, &sn, &cs);
                         re = fma(p.q, cs, re);
                         im = fma(p.q, sn, im);
                     }
@@ -386,6 +364,18 @@ __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
     }
 }
 
+// cos and sin of the kTurnTab turns in LDS for sincos2pi_tab (FP64 forms);
+// all threads of the block reach the barrier.
+__device__ __forceinline__ void fill_turns(double2 *turn) {
+    for (int j = threadIdx.x; j < rmath::kTurnTab; j += blockDim.x) {
+        const double f = (double)j / rmath::kTurnTab;
+        double sn, cs;
+        sincos2pi(f - rint(f), &sn, &cs);
+        turn[j] = make_double2(cs, sn);
+    }
+    __syncthreads();
+}
+
 // Far force on particle i (the factor -q_i included) from its system's P
 // amplitude-phase records, streamed as uniform loads: one sine per record,
 // F_i = -q_i sum_e a_e sin(2 pi (phi_e - m_e.s_i)).  Positions and charges
@@ -393,8 +383,8 @@ __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
 template <bool F64>
 __device__ __forceinline__ void far_sum(CSys *sp, CRec64 *kb64, CRec32 *kb32, int32_t P, int64_t n, int64_t i,
                                         const uint32_t *__restrict__ u, const float *__restrict__ qf,
-                                        const double *__restrict__ x, const double *__restrict__ q, double &Fx,
-                                        double &Fy, double &Fz) {
+                                        const double *__restrict__ x, const double *__restrict__ q,
+                                        const double2 *turn, double &Fx, double &Fy, double &Fz) {
     Fx = 0.0; Fy = 0.0; Fz = 0.0;
     // records are consumed in groups so that their uniform loads overlap
     if constexpr (F64) {
@@ -408,7 +398,8 @@ __device__ __forceinline__ void far_sum(CSys *sp, CRec64 *kb64, CRec32 *kb32, in
 #pragma unroll
             for (int h = 0; h < G; ++h) {
                 const double t = r[h].phi - (r[h].mx * sx + r[h].my * sy + r[h].mz * sz);
-                const double v = sin2pi(t - rint(t));
+                double v, cv;
+                rmath::sincos2pi_tab(t, turn, &v, &cv);
                 Fx = fma(r[h].ax, v, Fx);
                 Fy = fma(r[h].ay, v, Fy);
                 Fz = fma(r[h].az, v, Fz);
@@ -417,7 +408,8 @@ __device__ __forceinline__ void far_sum(CSys *sp, CRec64 *kb64, CRec32 *kb32, in
         for (; e < P; ++e) {
             const KRec64 r = ld(kb64 + e);
             const double t = r.phi - (r.mx * sx + r.my * sy + r.mz * sz);
-            const double v = sin2pi(t - rint(t));
+            double v, cv;
+            rmath::sincos2pi_tab(t, turn, &v, &cv);
             Fx = fma(r.ax, v, Fx);
             Fy = fma(r.ay, v, Fy);
             Fz = fma(r.az, v, Fz);
@@ -520,6 +512,8 @@ __device__ __forceinline__ void far_finish(const EvalArgs &a, CSys *sp, int32_t 
 // has run.
 template <bool F64>
 __global__ __launch_bounds__(256) void k_far(EvalArgs a, const FarItem *__restrict__ items, int32_t nitems) {
+    __shared__ double2 turn[F64 ? rmath::kTurnTab : 1];
+    if constexpr (F64) fill_turns(turn);
     if (blockIdx.x == 0 && threadIdx.x == 0 && a.rebuild) *a.rebuild = 0;
     for (int32_t itx = blockIdx.x; itx < nitems; itx += gridDim.x) {
         const FarItem item = items[itx];
@@ -531,7 +525,7 @@ __global__ __launch_bounds__(256) void k_far(EvalArgs a, const FarItem *__restri
         const int64_t i = valid ? i0 : t0;
         double Fx, Fy, Fz;
         far_sum<F64>(sp, (CRec64 *)(a.kb64 + sp->k0), (CRec32 *)(a.kb32 + sp->k0), sp->P, a.N, i, a.u_tmp,
-                     a.cur.qf, a.cur.x, a.cur.q, Fx, Fy, Fz);
+                     a.cur.qf, a.cur.x, a.cur.q, turn, Fx, Fy, Fz);
         far_finish(a, sp, sys, i, valid, Fx, Fy, Fz, itx);
     }
 }
@@ -542,6 +536,8 @@ __global__ __launch_bounds__(256) void k_far(EvalArgs a, const FarItem *__restri
 // into Ff_side.
 template <bool F64>
 __global__ __launch_bounds__(256) void k_far_side(EvalArgs a, const FarItem *__restrict__ items, int32_t nitems) {
+    __shared__ double2 turn[F64 ? rmath::kTurnTab : 1];
+    if constexpr (F64) fill_turns(turn);
     const int64_t n = a.N;
     for (int32_t itx = blockIdx.x; itx < nitems; itx += gridDim.x) {
         const FarItem item = items[itx];
@@ -552,7 +548,7 @@ __global__ __launch_bounds__(256) void k_far_side(EvalArgs a, const FarItem *__r
         const int64_t i = valid ? i0 : t0;
         double Fx, Fy, Fz;
         far_sum<F64>(sp, (CRec64 *)(a.kb64 + sp->k0), (CRec32 *)(a.kb32 + sp->k0), sp->P, n, i, a.rs_u, a.rs_qf,
-                     a.rs_x, a.rs_q, Fx, Fy, Fz);
+                     a.rs_x, a.rs_q, turn, Fx, Fy, Fz);
         if (valid) {
             a.Ff_side[i] = Fx;
             a.Ff_side[n + i] = Fy;

@@ -141,6 +141,33 @@ __device__ __forceinline__ uint32_t dot3_mod32_s(uint32_t ax, uint32_t ay, uint3
     return (uint32_t)r;
 }
 
+// sin(2 pi t), cos(2 pi t) in FP64 for any t of moderate size through a
+// table of the kTurnTab turns 2 pi j / kTurnTab (tab[j] = (cos, sin), filled
+// with sincos2pi below): j = rint(kTurnTab t), r = t - j / kTurnTab (exact,
+// |r| <= 1 / (2 kTurnTab) turns), the Taylor series of sin and cos of 2 pi r
+// through degree 7 and 8 (truncation below 2e-23 at |2 pi r| <= pi / 256),
+// then the angle sum with entry j mod kTurnTab.
+constexpr int kTurnTab = 256;
+__device__ __forceinline__ void sincos2pi_tab(double t, const double2 *tab, double *s, double *c) {
+    constexpr double T = kTwoPi;
+    constexpr double T2 = T * T;
+    constexpr double S1 = -T * T2 / 6.0;
+    constexpr double S2 = -S1 * T2 / 20.0;
+    constexpr double S3 = -S2 * T2 / 42.0;
+    constexpr double C1 = -T2 / 2.0;
+    constexpr double C2 = -C1 * T2 / 12.0;
+    constexpr double C3 = -C2 * T2 / 30.0;
+    constexpr double C4 = -C3 * T2 / 56.0;
+    const double jd = rint(t * (double)kTurnTab);
+    const double r = fma(jd, -1.0 / kTurnTab, t);
+    const double2 e = tab[(int)jd & (kTurnTab - 1)];
+    const double z = r * r;
+    const double sr = r * fma(z, fma(z, fma(z, S3, S2), S1), T);
+    const double cr = fma(z, fma(z, fma(z, fma(z, C4, C3), C2), C1), 1.0);
+    *s = fma(e.y, cr, e.x * sr);
+    *c = fma(e.x, cr, -(e.y * sr));
+}
+
 // sin(2 pi f), cos(2 pi f) for |f| <= 1/2 in FP64: quadrant q = rint(4f),
 // r = f - q/4 in [-1/8, 1/8], Taylor series of sin/cos(2 pi r) through
 // degree 15/16 (truncation below 5e-17), then rotation by q quarter turns.
