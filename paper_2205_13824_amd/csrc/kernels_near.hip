@@ -36,6 +36,7 @@
 #include <type_traits>
 
 #include "rbsog_internal.h"
+#include "rbsog_math.h"
 
 namespace rbsog {
 
@@ -45,10 +46,10 @@ constexpr int kBlock = 256;
 constexpr int kRanges = 18; // 9 rows of cells x up to 2 contiguous pieces
 constexpr float kFarR2 = 3.0e38f;  // r^2 of a pair that no test admits
 // narrow Gaussians evaluated with constants held in registers, no test of
-// their count (Table 1 row 2 at any cutoff has 3 below the FP32 tail's
-// threshold and 5 below the FP64 one; further ones take a counted loop)
+// their count (Table 1 row 2 at any cutoff has 3 above the tail's threshold;
+// further ones take a counted loop)
 template <bool F64>
-constexpr int kExpRegs = F64 ? 5 : 3;
+constexpr int kExpRegs = 3;
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
@@ -511,7 +512,7 @@ __device__ __forceinline__ void pair_force(const Geom &g, typename CoefOf<F64>::
         R exv[NE];
 #pragma unroll
         for (int l = 0; l < NE; ++l) {
-            if constexpr (F64) exv[l] = exp(-r2 * co->a[l]);
+            if constexpr (F64) exv[l] = rmath::exp_nonpos(-r2 * co->a[l]);
             else exv[l] = __builtin_amdgcn_exp2f(-r2 * co->a[l]);
             gs += co->cw[l] * exv[l];
         }
@@ -525,7 +526,7 @@ __device__ __forceinline__ void pair_force(const Geom &g, typename CoefOf<F64>::
         }
         for (int l = NE; l < co->nexp; ++l) {
             R ex;
-            if constexpr (F64) ex = exp(-r2 * co->a[l]);
+            if constexpr (F64) ex = rmath::exp_nonpos(-r2 * co->a[l]);
             else ex = __builtin_amdgcn_exp2f(-r2 * co->a[l]);
             gs += co->cw[l] * ex;
             if (we) ph += co->w[l] * ex;

@@ -58,10 +58,11 @@ struct Geom {
 // The near kernel evaluates the narrow Gaussians (r_c^2 / s_l^2 > tau) with an
 // exponential each and replaces the wide ones (s_l grows with l, so they are
 // l >= nexp) by the Taylor polynomial of their sum in x = r^2.  Truncation per
-// Gaussian: tau^(deg+1)/(deg+1)! of its weight, 5e-18 (FP64) and 1.2e-8 (FP32).
-constexpr double kTailTau64 = 0.05;
+// Gaussian: tau^(deg+1)/(deg+1)! of its weight, 2.4e-18 (FP64) and 1.2e-8
+// (FP32).
+constexpr double kTailTau64 = 0.25;
 constexpr double kTailTau32 = 0.25;
-constexpr int kTailDeg64 = 8;
+constexpr int kTailDeg64 = 12;
 constexpr int kTailDeg32 = 6;
 constexpr int kMaxExp = 24;  // narrow Gaussians per split (more is rejected)
 

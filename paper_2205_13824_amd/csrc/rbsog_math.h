@@ -141,6 +141,35 @@ __device__ __forceinline__ uint32_t dot3_mod32_s(uint32_t ax, uint32_t ay, uint3
     return (uint32_t)r;
 }
 
+// e^y in FP64 for finite y <= 0 (the narrow Gaussians of the near part),
+// by Cody and Waite's reduction: n = rint(y / ln 2), r = y - n ln 2 with
+// ln 2 in two parts (|r| <= ln 2 / 2), the Taylor series of e^r through
+// degree 11 (truncation below 1e-23 relative), scaled by 2^n.  No overflow
+// case (y <= 0); large negative y scale to 0.
+__device__ __forceinline__ double exp_nonpos(double y) {
+    constexpr double kLog2e = 1.4426950408889634;
+    constexpr double kLn2Hi = 0.6931471805599453;       // ln 2 rounded to FP64
+    constexpr double kLn2Lo = 2.3190468138462996e-17;   // ln 2 - kLn2Hi
+    const double nd = rint(y * kLog2e);
+    double r = fma(nd, -kLn2Hi, y);
+    r = fma(nd, -kLn2Lo, r);
+    double p = 1.0 / 39916800.0;  // 1/11!
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    // 2^n with n clamped (below -1100 the result is 0 either way)
+    const int n = (int)fmax(nd, -1100.0);
+    return ldexp(p, n);
+}
+
 // sin(2 pi t), cos(2 pi t) in FP64 for any t of moderate size through a
 // table of the kTurnTab turns 2 pi j / kTurnTab (tab[j] = (cos, sin), filled
 // with sincos2pi below): j = rint(kTurnTab t), r = t - j / kTurnTab (exact,
