@@ -102,7 +102,10 @@ typedef struct {
     void *stream;         /* hipStream_t to launch on; NULL = the context creates one */
     double neutral_tol;   /* default 1e-10 */
     double mass;          /* mass of every particle; default 1 */
-    int32_t graphs;       /* nonzero: rbsog_step replays one captured HIP graph per step; default 1 */
+    int32_t graphs;       /* nonzero: rbsog_step replays captured HIP graphs of one or eight steps;
+                             plain velocity-Verlet steps on a kept near list then fuse each step's
+                             closing kick with the next one's kick and drift (the same arithmetic in
+                             the same order; each call still ends on a whole step); default 1 */
     int32_t autotune;     /* nonzero: the first rbsog_step tunes the launch shapes (rbsog_autotune
                              with 5 repetitions) unless a cached tuning applies; default 0 */
     int32_t near_table;   /* FP32C only, nonzero: core-shell near kernel (Sec. 3.4): pairs with

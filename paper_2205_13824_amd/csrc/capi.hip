@@ -54,9 +54,25 @@ struct ProfEntry {
 constexpr int64_t kAdaptSteps = 32;  // steps between checks of the near-list build rate
 constexpr int64_t kProbeSteps = 4;   // steps of a renewed try of the caller's skin
 constexpr int kGraphSteps = 8;       // steps in the longer step graph
-// step graphs: one step without the near energies, one step with them (the
-// last step of a run), kGraphSteps steps without them
-enum { GV_STEP = 0, GV_STEP_E = 1, GV_MULTI = 2, GV_COUNT = 3 };
+// Step graphs: one step without the near energies, one step with them (the
+// last step of a run), kGraphSteps steps without them; and fused steps,
+// whose far kernel opens the next step: kGraphSteps or one of them after an
+// unfused step (HEAD) or after a fused one (MID), and the unfused step that
+// ends their run, without and with the near energies (TAIL)
+enum {
+    GV_STEP, GV_STEP_E, GV_MULTI, GV_F_HEAD8, GV_F_HEAD1, GV_F_MID8, GV_F_MID1, GV_F_TAIL, GV_F_TAIL_E, GV_COUNT
+};
+struct GraphShape {
+    int len;      // steps
+    bool opened;  // the first step was opened by the step before
+    bool fused;   // every step opens the next
+    bool energy;  // the (single) step sums the near energies
+};
+constexpr GraphShape kShapes[GV_COUNT] = {
+    {1, false, false, false},           {1, false, false, true},          {kGraphSteps, false, false, false},
+    {kGraphSteps, false, true, false},  {1, false, true, false},          {kGraphSteps, true, true, false},
+    {1, true, true, false},             {1, true, false, false},          {1, true, false, true},
+};
 
 enum Kid {
     K_KDQ, K_BIN, K_SCAN, K_SCATTER, K_SORTG, K_LIST, K_NEAR, K_NEARC, K_RHO, K_RHORED, K_FAR, K_SAMPLE, K_FARFIN,
@@ -592,6 +608,7 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
     a.dbg_cnt = c->dbg_cnt;
     a.dbg_cap = c->dbg_cap;
     a.dbg_kind = c->dbg_kind;
+    a.fuse = 0;
     return a;
 }
 
@@ -604,17 +621,24 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
 // the near kernels sum the pair energies.  Steps without the Nose-Hoover
 // thermostat leave both to the last step of their run (nothing reads the
 // values in between).
-rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt, bool kinetic, bool energy) {
+// Fused steps (plain velocity Verlet on a kept list, fusable(c)): `fuse`
+// has the far kernel open the next step, whose enqueue then passes `head`
+// false: it stages its k records and skips the kick/drift kernel.  Every
+// value is computed as in the unfused steps, in the same order.
+rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt, bool kinetic, bool energy, bool head = true,
+                          bool fuse = false) {
     hipStream_t s = c->stream;
     const bool f64 = c->prec == RBSOG_FP64;
     EvalArgs a = make_args(c, stepping, dt);
     a.energy = energy ? 1 : 0;
+    a.fuse = fuse ? 1 : 0;
     if (c->dbg_pairs) {
         // the record holds this evaluation's pairs only
         launch_fill_i32(c->dbg_cnt, 1, 0, s);
         launch_fill_i32(c->dbg_kind, 1, 0, s);
     }
-    TRY(timed(c, K_KDQ, [&] { launch_kdq(a, s); }));
+    if (head) TRY(timed(c, K_KDQ, [&] { launch_kdq(a, s); }));
+    else launch_stage(a, s);
     // the structure factor and its reduction need the copy of the positions
     // and the k records staged by the kick/drift kernel only: they run on the
     // side stream beside the re-sort and the near part (one stream while
@@ -691,6 +715,13 @@ void drop_graphs(rbsog_ctx *c) {
 
 int graph_mode(const rbsog_ctx *c) { return c->skin_cur > 0.0 ? 0 : 1; }
 
+// Steps whose far kernel may open the next step: plain velocity Verlet (no
+// thermostat) on a kept near list, without kernel timing or pair records.
+bool fusable(const rbsog_ctx *c) {
+    return c->skin_cur > 0.0 && !c->nh_on && !(c->gamma > 0.0) && !c->prof_on && !c->dbg_pairs && c->n_list > 0 &&
+           c->n_far > 0;
+}
+
 // A step graph captures the kernel arguments; it is rebuilt when dt or a
 // buffer changes.  Sequence buffers, the cell grid and the cell-run items are
 // reached through device tables, so re-sampling and the adaptive skin's
@@ -699,10 +730,13 @@ rbsog_status ensure_step_graph(rbsog_ctx *c, double dt, int v) {
     const int m = graph_mode(c);
     if (c->graph_exec[m][v] && c->graph_dt_m[m][v] == dt) return RBSOG_OK;
     drop_graph(c, m, v);
-    const int len = v == GV_MULTI ? kGraphSteps : 1;
+    const GraphShape &g0 = kShapes[v];
     HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
     rbsog_status st = RBSOG_OK;
-    for (int i = 0; i < len && st == RBSOG_OK; ++i) st = enqueue_eval(c, true, dt, c->nh_on, v == GV_STEP_E);
+    for (int i = 0; i < g0.len && st == RBSOG_OK; ++i) {
+        const bool head = i == 0 ? !g0.opened : !g0.fused;
+        st = enqueue_eval(c, true, dt, c->nh_on, g0.energy, head, g0.fused);
+    }
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->stream, &g);
     if (st != RBSOG_OK) {
@@ -1986,6 +2020,11 @@ rbsog_status rbsog_step(rbsog_ctx *c, int64_t n_steps, double dt) {
     for (int64_t k = 0; k < n_steps;) {
         // up to the next check of the build rate
         const int64_t chunk = std::min<int64_t>(n_steps - k, c->adapt_window - c->adapt_steps);
+        // fused steps within the chunk: each opens the next, the chunk's last
+        // step is unfused (the state between calls and at a check is a
+        // step's end)
+        const bool fuse = graphs && fusable(c);
+        bool opened = false;
         for (int64_t i = 0; i < chunk;) {
             TRY(refill_if_due(c));
             // only the run's last step sums the near energies
@@ -1994,11 +2033,21 @@ rbsog_status rbsog_step(rbsog_ctx *c, int64_t n_steps, double dt) {
                 // kGraphSteps steps at once when they fit in the chunk, stop
                 // short of the last step and need no refill of the chains
                 const int64_t room = c->lambda ? (int64_t)c->lambda - c->sys[0].cursor / c->sys[0].P : INT64_MAX;
-                const bool multi = i + kGraphSteps <= chunk && k + i + kGraphSteps < n_steps && room >= kGraphSteps;
-                const int v = multi ? GV_MULTI : (last ? GV_STEP_E : GV_STEP);
+                int v;
+                if (fuse) {
+                    const int64_t rem = chunk - i;
+                    if (rem == 1) v = opened ? (last ? GV_F_TAIL_E : GV_F_TAIL) : (last ? GV_STEP_E : GV_STEP);
+                    else if (rem > kGraphSteps && room >= kGraphSteps) v = opened ? GV_F_MID8 : GV_F_HEAD8;
+                    else v = opened ? GV_F_MID1 : GV_F_HEAD1;
+                    opened = rem > 1;
+                } else {
+                    const bool multi =
+                        i + kGraphSteps <= chunk && k + i + kGraphSteps < n_steps && room >= kGraphSteps;
+                    v = multi ? GV_MULTI : (last ? GV_STEP_E : GV_STEP);
+                }
                 TRY(ensure_step_graph(c, dt, v));
                 HIPCHK(c, hipGraphLaunch(c->graph_exec[graph_mode(c)][v], c->stream));
-                const int len = multi ? kGraphSteps : 1;
+                const int len = kShapes[v].len;
                 for (int j = 0; j < len; ++j) account_eval(c);
                 i += len;
             } else {

@@ -458,63 +458,97 @@ __device__ __forceinline__ void far_sum(CSys *sp, CRec64 *kb64, CRec32 *kb32, in
 // the zero-frequency mode term, the far force stored, the closing half kick
 // (and the second Nose-Hoover scaling) when stepping, and the kinetic energy
 // of each wave's particles summed across the wave in a fixed order into
-// partial [item * 4 + wave] (k_kinetic adds them up).
+// partial [item * 4 + wave] (k_kinetic adds them up).  FUSE: the next step
+// starts here, as the kick/drift kernel would start it: its opening half kick
+// with the same force, its drift, wrap and quantisation, and its
+// displacement check.  Lanes past the item (valid false) hold slot i = t0 and
+// store nothing.
+template <bool FUSE>
 __device__ __forceinline__ void far_finish(const EvalArgs &a, CSys *sp, int32_t sys, int64_t i, bool valid,
                                            double Fx, double Fy, double Fz, int32_t itx) {
     const int64_t n = a.N;
-    double ke = 0.0;
-    if (valid) {
-        // the velocity and the near force are loaded before the far force is
-        // stored (the stores could alias them for the compiler), so that
-        // their loads overlap the ones before
-        double vv[3] = {a.cur.v[i], a.cur.v[n + i], a.cur.v[2 * n + i]};
-        const double fn[3] = {a.Fn[i], a.Fn[n + i], a.Fn[2 * n + i]};
-        if (sp->zmode != 0) {
-            const double qi = a.cur.q[i], c = sp->zf * qi;
-            const double *M = a.dipole + 3 * sys;
-            if (sp->zmode == 1) {
-                Fx += c * M[0];
-                Fy += c * M[1];
-            }
-            Fz += c * M[2];
+    // the velocity and the near force are loaded before the far force is
+    // stored (the stores could alias them for the compiler), so that their
+    // loads overlap the ones before
+    double vv[3] = {a.cur.v[i], a.cur.v[n + i], a.cur.v[2 * n + i]};
+    const double fn[3] = {a.Fn[i], a.Fn[n + i], a.Fn[2 * n + i]};
+    double xs[3], L[3];
+    float hf[3];
+    uint32_t uref[3];
+    if constexpr (FUSE) {
+        for (int d = 0; d < 3; ++d) {
+            xs[d] = a.cur.x[d * n + i];
+            uref[d] = a.u[d * n + i];
+            L[d] = sp->g.L[d];
+            hf[d] = sp->g.hf[d];
         }
+    }
+    if (sp->zmode != 0) {
+        const double qi = a.cur.q[i], c = sp->zf * qi;
+        const double *M = a.dipole + 3 * sys;
+        if (sp->zmode == 1) {
+            Fx += c * M[0];
+            Fy += c * M[1];
+        }
+        Fz += c * M[2];
+    }
+    if (valid) {
         a.Ff[i] = Fx;
         a.Ff[n + i] = Fy;
         a.Ff[2 * n + i] = Fz;
-        if (a.kick) {
-            // closing half kick of the velocity-Verlet step
-            const double f[3] = {fn[0] + Fx, fn[1] + Fy, fn[2] + Fz};
-            bool bad = false;
-            for (int d = 0; d < 3; ++d) {
-                bad |= !isfinite(f[d]);
-                vv[d] += a.hdm * f[d];
-            }
-            if (a.nh) {
-                // Nose-Hoover: the second scaling with the step's half-step xi
-                // (xi and the kinetic energy still hold the step's start)
-                const double xh = a.nh_xi[sys] + 0.5 * a.dt * (2.0 * a.kin[sys] - sp->nh_nf * a.nh_T) / sp->nh_Q;
-                const double sc = exp(-0.5 * a.dt * xh);
-                for (int d = 0; d < 3; ++d) vv[d] *= sc;
-            }
-            for (int d = 0; d < 3; ++d) a.cur.v[d * n + i] = vv[d];
-            if (bad) atomicOr(a.flag, 1);
-        }
-        ke = 0.5 * a.mass * ((vv[0] * vv[0] + vv[1] * vv[1]) + vv[2] * vv[2]);
     }
+    const double f[3] = {fn[0] + Fx, fn[1] + Fy, fn[2] + Fz};
+    if (a.kick) {
+        // closing half kick of the velocity-Verlet step
+        bool bad = false;
+        for (int d = 0; d < 3; ++d) {
+            bad |= !isfinite(f[d]);
+            vv[d] += a.hdm * f[d];
+        }
+        if (!FUSE && a.nh) {
+            // Nose-Hoover: the second scaling with the step's half-step xi
+            // (xi and the kinetic energy still hold the step's start)
+            const double xh = a.nh_xi[sys] + 0.5 * a.dt * (2.0 * a.kin[sys] - sp->nh_nf * a.nh_T) / sp->nh_Q;
+            const double sc = exp(-0.5 * a.dt * xh);
+            for (int d = 0; d < 3; ++d) vv[d] *= sc;
+        }
+        if (!FUSE && valid)
+            for (int d = 0; d < 3; ++d) a.cur.v[d * n + i] = vv[d];
+        if (bad && valid) atomicOr(a.flag, 1);
+    }
+    double ke = valid ? 0.5 * a.mass * ((vv[0] * vv[0] + vv[1] * vv[1]) + vv[2] * vv[2]) : 0.0;
     // the wave's kinetic energy (a fixed butterfly), one partial per wave
     for (int o = 32; o > 0; o >>= 1) ke += __shfl_xor(ke, o, 64);
     if ((threadIdx.x & 63) == 0) a.kpart[(int64_t)itx * 4 + (threadIdx.x >> 6)] = ke;
+    if constexpr (FUSE) {
+        // the next step: half kick and drift, the drift kept for the
+        // mean-square displacement, then wrap and quantise
+        const double xs0[3] = {xs[0], xs[1], xs[2]};
+        for (int d = 0; d < 3; ++d) {
+            vv[d] += a.hdm * f[d];
+            xs[d] += a.dt * vv[d];
+            if (valid) a.cur.v[d * n + i] = vv[d];
+        }
+        if (valid && a.cur.dsp)
+            for (int d = 0; d < 3; ++d) a.cur.dsp[d * n + i] += xs[d] - xs0[d];
+        uint32_t uq[3];
+        const float d2 = wrap_store(a, i, valid, xs, L, hf, uref, uq);
+        // one atomic per wave that found a particle past the threshold
+        const bool far_ = valid && !(d2 <= sp->g.dthr2_f);
+        if (__ballot(far_) != 0ull && (threadIdx.x & 63) == 0) atomicOr(a.rebuild, 1);
+    }
 }
 
 // Far force and the end of the evaluation, one particle per lane; items are
 // runs of up to 256 slots of one system (grid-stride).  The near-list
-// rebuild flag is cleared here: every kernel of the evaluation that reads it
-// has run.
-template <bool F64>
+// rebuild flag is cleared here (every kernel of the evaluation that reads it
+// has run), unless the kernel opens the next step (FUSE), whose displacement
+// check sets it: the list pass has cleared it then.
+template <bool F64, bool FUSE>
 __global__ __launch_bounds__(256) void k_far(EvalArgs a, const FarItem *__restrict__ items, int32_t nitems) {
     __shared__ double2 turn[F64 ? rmath::kTurnTab : 1];
     if constexpr (F64) fill_turns(turn);
-    if (blockIdx.x == 0 && threadIdx.x == 0 && a.rebuild) *a.rebuild = 0;
+    if (!FUSE && blockIdx.x == 0 && threadIdx.x == 0 && a.rebuild) *a.rebuild = 0;
     for (int32_t itx = blockIdx.x; itx < nitems; itx += gridDim.x) {
         const FarItem item = items[itx];
         const int32_t sys = rfl(item.sys);
@@ -526,7 +560,7 @@ __global__ __launch_bounds__(256) void k_far(EvalArgs a, const FarItem *__restri
         double Fx, Fy, Fz;
         far_sum<F64>(sp, (CRec64 *)(a.kb64 + sp->k0), (CRec32 *)(a.kb32 + sp->k0), sp->P, a.N, i, a.u_tmp,
                      a.cur.qf, a.cur.x, a.cur.q, turn, Fx, Fy, Fz);
-        far_finish(a, sp, sys, i, valid, Fx, Fy, Fz, itx);
+        far_finish<FUSE>(a, sp, sys, i, valid, Fx, Fy, Fz, itx);
     }
 }
 
@@ -574,7 +608,7 @@ __global__ __launch_bounds__(256) void k_far_finish(EvalArgs a, const FarItem *_
         const int64_t i = valid ? i0 : t0;
         const int64_t o = a.sorted[i];
         const double Fx = a.Ff_side[o], Fy = a.Ff_side[n + o], Fz = a.Ff_side[2 * n + o];
-        far_finish(a, sp, sys, i, valid, Fx, Fy, Fz, itx);
+        far_finish<false>(a, sp, sys, i, valid, Fx, Fy, Fz, itx);
     }
 }
 
@@ -665,8 +699,13 @@ void launch_rho_reduce(const EvalArgs &a, hipStream_t s) {
 void launch_far(const EvalArgs &a, bool f64, const FarItem *items, int32_t nitems, int32_t block_size,
                 hipStream_t s) {
     dim3 grid((unsigned)nitems), block((unsigned)block_size);
-    if (f64) hipLaunchKernelGGL(k_far<true>, grid, block, 0, s, a, items, nitems);
-    else hipLaunchKernelGGL(k_far<false>, grid, block, 0, s, a, items, nitems);
+    if (a.fuse) {
+        if (f64) hipLaunchKernelGGL((k_far<true, true>), grid, block, 0, s, a, items, nitems);
+        else hipLaunchKernelGGL((k_far<false, true>), grid, block, 0, s, a, items, nitems);
+    } else {
+        if (f64) hipLaunchKernelGGL((k_far<true, false>), grid, block, 0, s, a, items, nitems);
+        else hipLaunchKernelGGL((k_far<false, false>), grid, block, 0, s, a, items, nitems);
+    }
 }
 
 void launch_far_side(const EvalArgs &a, bool f64, const FarItem *items, int32_t nitems, int32_t block_size,

@@ -17,8 +17,6 @@ namespace rbsog {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr double kTwo32 = 4294967296.0;
-
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 // The cell scan works on tiles of kScanTile cells.
@@ -150,33 +148,8 @@ __global__ __launch_bounds__(kBlock) void k_kdq(EvalArgs a, int32_t pblocks) {
         if (valid && a.cur.dsp)
             for (int d = 0; d < 3; ++d) a.cur.dsp[d * N + t] += xs[d] - xs0[d];
     }
-    float d2 = 0.f;
     uint32_t uq[3];
-    for (int d = 0; d < 3; ++d) {
-        const double r = xs[d] / L[d];
-        const double f = r - floor(r);
-        double w = floor(f * kTwo32);
-        // a non-finite position (reported by the flag) falls in cell 0
-        w = w >= 0.0 ? (w > kTwo32 - 1.0 ? kTwo32 - 1.0 : w) : 0.0;
-        const uint32_t ud = (uint32_t)w;
-        uq[d] = ud;
-        if (valid) {
-            a.u_tmp[d * N + t] = ud;
-            x[d * N + t] = f * L[d];
-            if (a.rs_u) a.rs_u[d * N + t] = ud;
-            if (a.rs_x) a.rs_x[d * N + t] = f * L[d];
-        }
-        // the wrapped fixed-point difference is the minimum image
-        const float dd = (float)(int32_t)(ud - uref[d]) * hf[d];
-        d2 += dd * dd;
-    }
-    if (valid) {
-        const float qf = a.cur.qf[t];
-        if (a.rs_qf) a.rs_qf[t] = qf;
-        if (a.rs_q) a.rs_q[t] = a.cur.q[t];
-        a.pk[t] = make_uint4(uq[0], uq[1], uq[2], __float_as_uint(qf));
-        if (a.pkx) a.pkx[t] = PosQ64{x[t], x[N + t], x[2 * N + t], a.cur.q[t]};
-    }
+    const float d2 = wrap_store(a, t, valid, xs, L, hf, uref, uq);
     if (a.always_build) {
         // every evaluation builds: the cell and the histogram here (no bin pass)
         if (blockIdx.x == 0 && threadIdx.x == 0) *a.rebuild = 1;
@@ -190,6 +163,10 @@ __global__ __launch_bounds__(kBlock) void k_kdq(EvalArgs a, int32_t pblocks) {
         const bool far_ = valid && !(d2 <= dthr2);
         if (__ballot(far_) != 0ull && (threadIdx.x & 63) == 0) atomicOr(a.rebuild, 1);
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_stage(EvalArgs a) {
+    stage_records(a, (int64_t)blockIdx.x * kBlock + threadIdx.x);
 }
 
 // Cell c_d = (u n_d) >> 32 of each particle and the cell histogram.
@@ -451,6 +428,10 @@ void launch_kdq(const EvalArgs &a, hipStream_t s) {
     const int32_t pb = (int32_t)grid_for(a.N, kBlock);
     const int32_t kb = (int32_t)grid_for(a.K, kBlock);
     hipLaunchKernelGGL(k_kdq, dim3((unsigned)(pb + kb)), dim3(kBlock), 0, s, a, pb);
+}
+
+void launch_stage(const EvalArgs &a, hipStream_t s) {
+    if (a.K > 0) hipLaunchKernelGGL(k_stage, dim3(grid_for(a.K, kBlock)), dim3(kBlock), 0, s, a);
 }
 
 int64_t scan_blocksums_size(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }

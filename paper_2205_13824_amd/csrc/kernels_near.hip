@@ -966,6 +966,9 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
     // one item per block, dealt to the XCDs as in the build
     const int32_t b = blockIdx.x;
     const int32_t it = (b % 8) * (nblk / 8) + b / 8;
+    // the far kernel that follows opens the next step and sets the flag: the
+    // list build, its last reader in this evaluation, has run
+    if (a.fuse && b == 0 && threadIdx.x == 0) *a.rebuild = 0;
     if (it >= nitems) return;
     const __attribute__((address_space(4))) ListItem *ip = (const __attribute__((address_space(4))) ListItem *)(items + it);
     ListItem item;

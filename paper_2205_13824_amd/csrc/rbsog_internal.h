@@ -205,8 +205,9 @@ struct EvalArgs {
     double *Fn, *Ff;       // forces in slot order
     double *Ff_side;       // build-every-step mode: far forces in the order before the re-sort
     // Verlet list: rebuild flag (set by the displacement check, cleared by the
-    // near kernel), pairs (one u32 each: home index in the wave's quarter of
-    // the item in the top kListHomeBits bits, candidate slot below), counts,
+    // far kernel, or by the list pass when the far kernel opens the next
+    // step), pairs (one u32 each: the candidate's slot, laid out as the near
+    // list items state), counts,
     // capacity per item, largest count of the latest build, builds made
     int32_t *rebuild;
     int32_t list_hm;       // nonzero: home-major blocks of the near list (long lists)
@@ -250,7 +251,55 @@ struct EvalArgs {
     double c1, c2;
     uint64_t tseed;
     int64_t *tstep;        // thermostatted steps taken (noise counter)
+    // nonzero (plain velocity Verlet on a kept near list): the far kernel
+    // also opens the next step (its half kick with the same force, its drift
+    // and quantisation, its displacement check), the near list pass clears
+    // the rebuild flag in its place, and the next step starts with the
+    // staging of its k records alone
+    int32_t fuse;
 };
+
+// Wrap of drifted positions into [0, L) (x_w = frac(x/L) L) and their
+// fixed-point coordinates u = min(2^32-1, floor(frac(x/L) 2^32)), stored for
+// slot t with the copies the structure factor and the near part read (a
+// non-finite position, reported by the flag, falls at u = 0).  Returns the
+// squared minimum-image displacement from the build's coordinates `uref` in
+// FP32 (the wrapped fixed-point difference times hf).  Shared by the
+// kick/drift kernel and the far kernel's fused step.
+__device__ __forceinline__ float wrap_store(const EvalArgs &a, int64_t t, bool valid, const double xs[3],
+                                            const double L[3], const float hf[3], const uint32_t uref[3],
+                                            uint32_t uq[3]) {
+    constexpr double two32 = 4294967296.0;
+    const int64_t N = a.N;
+    float d2 = 0.f;
+    double xw[3];
+    for (int d = 0; d < 3; ++d) {
+        const double r = xs[d] / L[d];
+        const double f = r - floor(r);
+        double w = floor(f * two32);
+        w = w >= 0.0 ? (w > two32 - 1.0 ? two32 - 1.0 : w) : 0.0;
+        const uint32_t ud = (uint32_t)w;
+        uq[d] = ud;
+        xw[d] = f * L[d];
+        if (valid) {
+            a.u_tmp[d * N + t] = ud;
+            a.cur.x[d * N + t] = xw[d];
+            if (a.rs_u) a.rs_u[d * N + t] = ud;
+            if (a.rs_x) a.rs_x[d * N + t] = xw[d];
+        }
+        const float dd = (float)(int32_t)(ud - uref[d]) * hf[d];
+        d2 += dd * dd;
+    }
+    if (valid) {
+        const float qf = a.cur.qf[t];
+        const double q = a.cur.q[t];
+        if (a.rs_qf) a.rs_qf[t] = qf;
+        if (a.rs_q) a.rs_q[t] = q;
+        a.pk[t] = make_uint4(uq[0], uq[1], uq[2], __float_as_uint(qf));
+        if (a.pkx) a.pkx[t] = PosQ64{xw[0], xw[1], xw[2], q};
+    }
+    return d2;
+}
 
 // ---- on-device sampler (kernels_sample.hip) ---------------------------------
 // State of one Metropolis-Hastings chain.
@@ -281,6 +330,9 @@ void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 // the list reference (sets *a.rebuild); extra blocks stage the k batch of
 // every system
 void launch_kdq(const EvalArgs &a, hipStream_t s);
+// the k batch of every system staged alone (a step whose kick and drift the
+// previous step's far kernel made)
+void launch_stage(const EvalArgs &a, hipStream_t s);
 // The list build: each of these returns at once unless *a.rebuild is set.
 // Cell of each particle and the histogram; exclusive scan of the counts;
 // scatter into cells; per cell: id sort of its segment, reset of its count,

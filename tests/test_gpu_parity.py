@@ -317,6 +317,44 @@ def test_graph_replay_equals_eager(orc, prec, nh, skin):
             assert (x == y).all()
 
 
+@pytest.mark.parametrize("prec", [R.RBSOG_FP64, R.RBSOG_FP32C])
+def test_fused_steps_equal_unfused(orc, prec):
+    # with graphs, plain velocity-Verlet steps on a kept list are fused: the
+    # far kernel opens the next step (its kick, drift, quantisation and
+    # displacement check) and the next step stages its k records alone.
+    # Eager launches are never fused: the two must agree bit for bit, with
+    # list builds inside fused runs (dt large enough for the displacement
+    # check to fire), runs that cross the build-rate check, fused graphs of
+    # one and of several steps, and the mean-square displacement tracked.
+    n, L = 500, 12.0
+    pos, q, box = W.ions_rsa(n, n / L ** 3, 1.0, 41)
+    v0 = W.maxwellian(n, 1.0, 42)
+    out = []
+    for graphs in (False, True):
+        say(f"[gpu] fused vs unfused steps prec={prec} graphs={graphs}")
+        sysm = R.System(pos, q, box, 3.0, 50, seed=5, precision=prec, graphs=graphs)
+        sysm.sample_k(200)
+        R.rbsog_set_velocities(sysm.ctx, v0)
+        R.rbsog_set_msd_origin(sysm.ctx)
+        states = []
+        for chunk in (2, 11, 17, 40, 1, 9):
+            sysm.step(chunk, 5e-3)
+            states.append(R.rbsog_get_state(sysm.ctx, n))
+            states.append((np.asarray(R.rbsog_get_msd(sysm.ctx)),))
+        states.append(tuple(sysm.components()))
+        states.append((R.rbsog_get_energy(sysm.ctx),))
+        states.append(R.rbsog_get_kinetic(sysm.ctx))
+        info = R.rbsog_info(sysm.ctx)
+        states.append((np.array([info["list_builds"]]),))
+        say(f"[gpu]   list builds {info['list_builds']} skin {info['skin']}")
+        assert info["list_builds"] >= 3
+        out.append(states)
+        sysm.close()
+    for a, b in zip(*out):
+        for x, y in zip(a, b):
+            assert (np.asarray(x) == np.asarray(y)).all()
+
+
 @pytest.mark.parametrize("prec,tol", [(R.RBSOG_FP64, F64_TOL), (R.RBSOG_FP32C, F32C_TOL)])
 @pytest.mark.parametrize("skin", [None, 0.0])
 def test_autotune_keeps_results(orc, prec, tol, skin):
