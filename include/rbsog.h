@@ -327,7 +327,9 @@ rbsog_status rbsog_info(rbsog_ctx *ctx, int32_t sys, rbsog_info_t *info);
  * one phase after the other, each candidate timed over `reps` launches of its
  * kernels with HIP events (after one untimed launch); the fastest are kept:
  *   particles per structure-factor chunk (256..32768) and k tiles of 64 per
- *   structure-factor block (1..16; the block's other waves split the chunk);
+ *   structure-factor block (1..16; the block's other waves split the chunk),
+ *   timed on the latest evaluation's wave vectors (left as they are when
+ *   rbsog_set_k or rbsog_sample_k has since started a new sequence);
  *   particles per far block (64, 128, 256), timed on the far kernels of the
  *   near mode in use (after the near list, or beside the near part when every
  *   step builds);

@@ -202,7 +202,7 @@ struct rbsog_ctx {
     int64_t *kcur = nullptr;
     KRec64 *kb64 = nullptr;
     KRec32 *kb32 = nullptr;
-    double *wk = nullptr, *rho = nullptr, *ek = nullptr, *partial = nullptr, *epart = nullptr, *E = nullptr;
+    double *rho = nullptr, *ek = nullptr, *partial = nullptr, *epart = nullptr, *E = nullptr;
     double *dip_part = nullptr, *dipole = nullptr;
     // kinetic energy per far item and wave, and per system
     double *kpart = nullptr, *kin = nullptr;
@@ -492,6 +492,29 @@ rbsog_status upload_cursor(rbsog_ctx *c, int32_t s) {
     return RBSOG_OK;
 }
 
+// Whether the latest evaluation's wave vectors are the batch just below
+// every system's cursor: only evaluations move a cursor on, by P, and a new
+// sequence (or a refill of the device chains, which an evaluation follows
+// at once) sets it to 0.
+bool batch_below_cursors(const rbsog_ctx *c) {
+    if (c->evals == 0) return false;
+    for (const SysHost &h : c->sys)
+        if (h.cursor < h.P) return false;
+    return true;
+}
+
+// Every device cursor back by one batch, at the latest evaluation's wave
+// vectors (the structure factor reads the batch at the cursor): the tuner's
+// trials of the structure factor and its reduction (which moves the cursor
+// on) evaluate that batch again.  Needs batch_below_cursors(c).
+rbsog_status rewind_cursors(rbsog_ctx *c) {
+    std::vector<int64_t> cur((size_t)c->nsys);
+    for (int32_t s = 0; s < c->nsys; ++s) cur[s] = c->sys[s].cursor - c->sys[s].P;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->kcur, cur.data(), cur.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    return RBSOG_OK;
+}
+
 rbsog_status ensure_kcap(rbsog_ctx *c, int32_t s, int64_t nvec) {
     SysHost &h = c->sys[s];
     if (nvec <= h.kcap) return RBSOG_OK;
@@ -578,7 +601,6 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
     a.kcur = c->kcur;
     a.kb64 = c->kb64;
     a.kb32 = c->kb32;
-    a.wk = c->wk;
     a.rho = c->rho;
     a.ek = c->ek;
     a.partial = c->partial;
@@ -623,8 +645,8 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
 // values in between).
 // Fused steps (plain velocity Verlet on a kept list, fusable(c)): `fuse`
 // has the far kernel open the next step, whose enqueue then passes `head`
-// false: it stages its k records and skips the kick/drift kernel.  Every
-// value is computed as in the unfused steps, in the same order.
+// false: it starts with the structure factor.  Every value is computed as in
+// the unfused steps, in the same order.
 rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt, bool kinetic, bool energy, bool head = true,
                           bool fuse = false) {
     hipStream_t s = c->stream;
@@ -638,9 +660,8 @@ rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt, bool kinetic, 
         launch_fill_i32(c->dbg_kind, 1, 0, s);
     }
     if (head) TRY(timed(c, K_KDQ, [&] { launch_kdq(a, s); }));
-    else launch_stage(a, s);
     // the structure factor and its reduction need the copy of the positions
-    // and the k records staged by the kick/drift kernel only: they run on the
+    // taken by the kick/drift (or the previous far) kernel only: they run on the
     // side stream beside the re-sort and the near part (one stream while
     // profiling kernels alone, and for systems with a lot of far work)
     const bool fork = c->prof_on != 1 && c->use_side;
@@ -1343,8 +1364,9 @@ rbsog_status upload_cell_items(rbsog_ctx *c) {
 
 // Times each phase's candidate shapes on the latest evaluation's data and
 // keeps the fastest, one phase after the other: the structure factor's chunk
-// size and its k tiles per block (k_rho with k_rho_reduce, whose advance of
-// the sequence cursors is undone), the far block (k_far, or k_far_side
+// size and its k tiles per block (k_rho with k_rho_reduce on the latest
+// batch again, the cursors rewound by one batch before each trial; skipped
+// when a new sequence has replaced that batch), the far block (k_far, or k_far_side
 // with k_far_finish when every step builds), the candidate slots per pass of
 // the near kernel in use (k_list_build with the near list, k_near_cells when
 // every step builds; each trial rebuilds at the current positions).  No
@@ -1384,6 +1406,7 @@ rbsog_status autotune_now(rbsog_ctx *c, int32_t reps) {
                 TRY(request_build(c));
                 a = build();
             }
+            if (phase == PH_CHUNK || phase == PH_KT) TRY(rewind_cursors(c));
             HIPCHK(c, hipEventRecord(e0, st));
             if (phase == PH_CHUNK || phase == PH_KT) {
                 // the partial sums and their reduction: the chunk count sets both
@@ -1430,7 +1453,11 @@ rbsog_status autotune_now(rbsog_ctx *c, int32_t reps) {
                : phase == PH_FAR ? t.far_block
                                  : t.build_slots;
     };
+    // the structure factor's trials evaluate the latest batch again: with a
+    // new sequence since, its shapes stay as they are
+    const bool sf_trials = batch_below_cursors(c);
     for (int phase = 0; phase < PH_N; ++phase) {
+        if (!sf_trials && (phase == PH_CHUNK || phase == PH_KT)) continue;
         double best_ms = 1e30;
         int32_t best_v = 0;
         for (int32_t v : cand[phase]) {
@@ -1459,12 +1486,15 @@ rbsog_status autotune_now(rbsog_ctx *c, int32_t reps) {
     // same wave vectors, same pairs); then the sequence cursors, the build
     // counter and the build flag as they were
     {
-        EvalArgs ar = make_args(c, false, 0.0);
-        launch_rho(ar, f64, c->rho_items, c->n_rho, st);
-        launch_rho_reduce(ar, st);
-        HIPCHK(c, hipGetLastError());
-        HIPCHK(c, hipStreamSynchronize(st));
-        for (int32_t s = 0; s < c->nsys; ++s) TRY(upload_cursor(c, s));
+        if (sf_trials) {
+            TRY(rewind_cursors(c));
+            EvalArgs ar = make_args(c, false, 0.0);
+            launch_rho(ar, f64, c->rho_items, c->n_rho, st);
+            launch_rho_reduce(ar, st);
+            HIPCHK(c, hipGetLastError());
+            HIPCHK(c, hipStreamSynchronize(st));
+            for (int32_t s = 0; s < c->nsys; ++s) TRY(upload_cursor(c, s));
+        }
         TRY(request_build(c));
         EvalArgs a = build();
         if (every) {
@@ -1755,7 +1785,6 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     ALLOC(kcur, nsys);
     ALLOC(kb64, K);
     ALLOC(kb32, K);
-    ALLOC(wk, K);
     ALLOC(rho, 2 * K);
     ALLOC(ek, K);
     ALLOC(partial, 2 * part_cap);
@@ -2572,7 +2601,7 @@ std::vector<std::pair<void *, int64_t>> device_state(rbsog_ctx *c) {
         {c->kin, (int64_t)c->nsys * 8}, {c->nh_xi, (int64_t)c->nsys * 8}, {c->tstep, 8},
         {c->E, 4 * (int64_t)c->nsys * 8}, {c->rho, 2 * (int64_t)c->K * 8},
         {c->kb64, (int64_t)c->K * (int64_t)sizeof(KRec64)}, {c->kb32, (int64_t)c->K * (int64_t)sizeof(KRec32)},
-        {c->wk, (int64_t)c->K * 8}, {c->dipole, 3 * (int64_t)c->nsys * 8}, {c->flag, 4}};
+        {c->dipole, 3 * (int64_t)c->nsys * 8}, {c->flag, 4}};
     if (c->lambda) {
         v.push_back({c->chains, (int64_t)c->nsys * c->lambda * (int64_t)sizeof(ChainState)});
         for (const SysHost &h : c->sys) v.push_back({h.dkseq, (int64_t)c->lambda * h.P * 3 * 4});

@@ -103,15 +103,16 @@ __global__ __launch_bounds__(1024, F64 ? 1 : 8) void k_rho(EvalArgs a, const Rho
         const RhoItem item = items[itx];
         const int32_t sys = rfl(item.sys), kg = rfl(item.kg), chunk = rfl(item.chunk);
         CSys *sp = (CSys *)(a.sys + sys);
-        const int32_t P = sp->P, kt = sp->kt, streams = sp->streams, k0 = sp->k0;
+        const int32_t P = sp->P, kt = sp->kt, streams = sp->streams;
         const int kti = wave % kt, st = wave / kt;
         const int32_t k = (kg * kt + kti) * 64 + lane;
         const bool active = k < P && st < streams;
-        const int32_t kk = k0 + (k < P ? k : 0);
+        // the batch's wave vectors, read from the sequence at the cursor
+        const int32_t *__restrict__ mk = sp->kseq + 3 * (rfl64(a.kcur[sys]) + (k < P ? k : 0));
         const int64_t j0 = rfl64(item.j0), j1 = rfl64(item.j1);
         double re = 0.0, im = 0.0;
         if constexpr (F64) {
-            const double mx = a.kb64[kk].mx, my = a.kb64[kk].my, mz = a.kb64[kk].mz;
+            const double mx = mk[0], my = mk[1], mz = mk[2];
             const double ix = sp->g.invL[0], iy = sp->g.invL[1], iz = sp->g.invL[2];
             for (int64_t jb = j0; jb < j1; jb += kStage) {
                 const int cnt = (int)(j1 - jb < kStage ? j1 - jb : kStage);
@@ -148,7 +149,7 @@ __global__ __launch_bounds__(1024, F64 ? 1 : 8) void k_rho(EvalArgs a, const Rho
                 __syncthreads();
             }
         } else {
-            const uint32_t mx = (uint32_t)a.kb32[kk].mx, my = (uint32_t)a.kb32[kk].my, mz = (uint32_t)a.kb32[kk].mz;
+            const uint32_t mx = (uint32_t)mk[0], my = (uint32_t)mk[1], mz = (uint32_t)mk[2];
             for (int64_t jb = j0; jb < j1; jb += kStage) {
                 const int cnt = (int)(j1 - jb < kStage ? j1 - jb : kStage);
                 if ((int)threadIdx.x < cnt) {
@@ -297,26 +298,40 @@ __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
         if (lane == 0) {
             a.rho[r] = re;
             a.rho[a.K + r] = im;
-            const double w = a.wk[r];
+            // the batch's k-th vector of the sequence and its weight (the
+            // cursor moves once every record of the system is reduced)
+            const int64_t e = a.kcur[sys] + k;
+            const int32_t m[3] = {sd.kseq[3 * e], sd.kseq[3 * e + 1], sd.kseq[3 * e + 2]};
+            const double w = sd.kw ? sd.kw[e] : sd.w_rb;
             a.ek[r] = 0.5 * w * (re * re + im * im);
             // amplitude-phase record: phi = arg(rho) / (2 pi), a = w |rho| k
             const double phi = atan2(im, re) * (1.0 / rmath::kTwoPi);
             const double mag = hypot(re, im);
             const double c = w * mag * rmath::kTwoPi;
-            const double ax = c * a.kb64[r].mx * sd.g.invL[0], ay = c * a.kb64[r].my * sd.g.invL[1],
-                         az = c * a.kb64[r].mz * sd.g.invL[2];
-            a.kb64[r].phi = phi;
-            a.kb64[r].ax = ax;
-            a.kb64[r].ay = ay;
-            a.kb64[r].az = az;
+            KRec64 h;
+            h.mx = m[0];
+            h.my = m[1];
+            h.mz = m[2];
+            h.phi = phi;
+            h.ax = c * h.mx * sd.g.invL[0];
+            h.ay = c * h.my * sd.g.invL[1];
+            h.az = c * h.mz * sd.g.invL[2];
+            h.pad = 0.0;
+            a.kb64[r] = h;
             // FP32 form: phi in 2^-32 turns, plus 2^9 units: the FP32 phases of
             // the structure factor and of the far force are each truncated
             // to 2^-23 turns (half a unit of it low on average), which this
             // offset takes back
-            a.kb32[r].phi = (uint32_t)(int64_t)rint(phi * 4294967296.0) + 512u;
-            a.kb32[r].ax = (float)ax;
-            a.kb32[r].ay = (float)ay;
-            a.kb32[r].az = (float)az;
+            KRec32 f;
+            f.mx = m[0];
+            f.my = m[1];
+            f.mz = m[2];
+            f.phi = (uint32_t)(int64_t)rint(phi * 4294967296.0) + 512u;
+            f.ax = (float)h.ax;
+            f.ay = (float)h.ay;
+            f.az = (float)h.az;
+            f.pad = 0.f;
+            a.kb32[r] = f;
         }
     }
     if (threadIdx.x == 0) nfin = 0;

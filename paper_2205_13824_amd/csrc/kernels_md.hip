@@ -1,8 +1,8 @@
 // Particle bookkeeping kernels of librbsog for gfx950: the velocity-Verlet
 // kick/drift, wrap and quantise with the displacement check of the Verlet
 // list, the cell list of a list build (histogram, exclusive scan, scatter,
-// per-cell id sort and gather of the state into cell order) and the staging
-// of each evaluation's wave vectors.
+// per-cell id sort and gather of the state into cell order), the kinetic
+// energy sum and the mean-square displacement.
 //
 // Arrays are structure-of-arrays over all systems of the batch: component d
 // of slot t is at [d*N + t].  The state is in the cell order of the latest
@@ -35,28 +35,6 @@ __device__ __forceinline__ void thermo_normals(uint64_t seed, int64_t step, int3
     rmath::normals3(seed, 2, idx, xi);
 }
 
-// Stage the next P_s wave vectors of every system (Algorithm 1: the sequence
-// is consumed in order, one batch per evaluation): per-k records for both
-// precisions and the weights.  The cursors advance once the batch is reduced.
-__device__ void stage_records(const EvalArgs &a, int64_t r) {
-    if (r >= a.K) return;
-    const int32_t s = a.ksys[r];
-    const SysDev &sd = a.sys[s];
-    const int64_t e = a.kcur[s] + (r - sd.k0);
-    const int32_t mx = sd.kseq[3 * e], my = sd.kseq[3 * e + 1], mz = sd.kseq[3 * e + 2];
-    const double w = sd.kw ? sd.kw[e] : sd.w_rb;
-    // phi and a follow from rho in the structure-factor reduction
-    KRec64 h;
-    h.mx = mx; h.my = my; h.mz = mz;
-    h.phi = 0.0; h.ax = 0.0; h.ay = 0.0; h.az = 0.0; h.pad = 0.0;
-    a.kb64[r] = h;
-    KRec32 f;
-    f.mx = mx; f.my = my; f.mz = mz;
-    f.phi = 0u; f.ax = 0.f; f.ay = 0.f; f.az = 0.f; f.pad = 0.f;
-    a.kb32[r] = f;
-    a.wk[r] = w;
-}
-
 // Lanes holding the same cell in a run of consecutive lanes (the state is in
 // cell order, so runs are the rule) share one atomic: the run's first lane
 // adds the run length and the others take their offset in the run.  Returns
@@ -81,13 +59,8 @@ __device__ __forceinline__ int32_t run_atomic_add(int32_t *ctr, int64_t cell, bo
 // floor(frac(x/L) 2^32)).  A particle farther than skin r_c / 2 from its
 // position at the latest list build sets the rebuild flag: the list holds
 // every pair within r_c (1 + skin) at the build, so it holds every pair
-// within r_c while no particle has moved farther.  Blocks past the particles
-// stage the k records.
-__global__ __launch_bounds__(kBlock) void k_kdq(EvalArgs a, int32_t pblocks) {
-    if ((int32_t)blockIdx.x >= pblocks) {
-        stage_records(a, (int64_t)(blockIdx.x - pblocks) * kBlock + threadIdx.x);
-        return;
-    }
+// within r_c while no particle has moved farther.
+__global__ __launch_bounds__(kBlock) void k_kdq(EvalArgs a) {
     const int64_t t0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const bool valid = t0 < a.N;
     const int64_t t = valid ? t0 : a.N - 1;
@@ -163,10 +136,6 @@ __global__ __launch_bounds__(kBlock) void k_kdq(EvalArgs a, int32_t pblocks) {
         const bool far_ = valid && !(d2 <= dthr2);
         if (__ballot(far_) != 0ull && (threadIdx.x & 63) == 0) atomicOr(a.rebuild, 1);
     }
-}
-
-__global__ __launch_bounds__(kBlock) void k_stage(EvalArgs a) {
-    stage_records(a, (int64_t)blockIdx.x * kBlock + threadIdx.x);
 }
 
 // Cell c_d = (u n_d) >> 32 of each particle and the cell histogram.
@@ -425,13 +394,7 @@ void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
 }
 
 void launch_kdq(const EvalArgs &a, hipStream_t s) {
-    const int32_t pb = (int32_t)grid_for(a.N, kBlock);
-    const int32_t kb = (int32_t)grid_for(a.K, kBlock);
-    hipLaunchKernelGGL(k_kdq, dim3((unsigned)(pb + kb)), dim3(kBlock), 0, s, a, pb);
-}
-
-void launch_stage(const EvalArgs &a, hipStream_t s) {
-    if (a.K > 0) hipLaunchKernelGGL(k_stage, dim3(grid_for(a.K, kBlock)), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_kdq, dim3(grid_for(a.N, kBlock)), dim3(kBlock), 0, s, a);
 }
 
 int64_t scan_blocksums_size(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }

@@ -23,8 +23,9 @@ constexpr int kMaxGauss = 160;  // M + 1 <= kMaxGauss
 // amplitude-phase form: with rho_e = |rho_e| e^{2 pi i phi_e},
 //   Im(e^{-i k.r} rho) = |rho| sin(2 pi (phi - m.s)),  s = r/L (fractional),
 // so the far force is F_i = -q_i sum_e a_e sin(2 pi (phi_e - m_e.s_i)) with
-// a_e = w_e |rho_e| k_e: one sine per (particle, wave vector).  The kick/drift
-// kernel stages m; the structure-factor reduction fills phi and a.
+// a_e = w_e |rho_e| k_e: one sine per (particle, wave vector).  The
+// structure-factor reduction writes the records of the batch (the structure
+// factor itself reads m from the sequence at the cursor).
 // FP64 form: m as doubles, phi in revolutions, a.
 struct KRec64 {
     double mx, my, mz;
@@ -220,7 +221,7 @@ struct EvalArgs {
     int64_t *kcur;         // per-system sequence cursor
     KRec64 *kb64;
     KRec32 *kb32;
-    double *wk, *rho, *ek, *partial, *epart, *E;
+    double *rho, *ek, *partial, *epart, *E;
     double *epart_cells;   // near energies per cell-run item (build-every-evaluation mode)
     int32_t energy;        // 1: the near kernels sum the pair energies (else forces only)
     double *dip_part;      // dipole partials per structure-factor chunk (3 per chunk)
@@ -254,8 +255,8 @@ struct EvalArgs {
     // nonzero (plain velocity Verlet on a kept near list): the far kernel
     // also opens the next step (its half kick with the same force, its drift
     // and quantisation, its displacement check), the near list pass clears
-    // the rebuild flag in its place, and the next step starts with the
-    // staging of its k records alone
+    // the rebuild flag in its place, and the next step starts with its
+    // structure factor
     int32_t fuse;
 };
 
@@ -327,12 +328,8 @@ void launch_refill(const SampDev *samp, int32_t nsys, int32_t lambda, ChainState
 // ---- kernel launchers (kernels_md.hip) --------------------------------------
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 // kick dt/2 + drift (if a.kick), wrap, quantise, displacement check against
-// the list reference (sets *a.rebuild); extra blocks stage the k batch of
-// every system
+// the list reference (sets *a.rebuild)
 void launch_kdq(const EvalArgs &a, hipStream_t s);
-// the k batch of every system staged alone (a step whose kick and drift the
-// previous step's far kernel made)
-void launch_stage(const EvalArgs &a, hipStream_t s);
 // The list build: each of these returns at once unless *a.rebuild is set.
 // Cell of each particle and the histogram; exclusive scan of the counts;
 // scatter into cells; per cell: id sort of its segment, reset of its count,

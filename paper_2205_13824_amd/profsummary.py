@@ -47,7 +47,7 @@ KERNEL_FILES = {
     "k_far_side": "kernels_far.hip", "k_far_finish": "kernels_far.hip",
     "k_near_list": "kernels_near.hip", "k_near_cells": "kernels_near.hip", "k_list_build": "kernels_near.hip",
     "k_neighbors": "kernels_near.hip",
-    "k_kdq": "kernels_md.hip", "k_stage": "kernels_md.hip", "k_bin": "kernels_md.hip", "k_scan_blocks": "kernels_md.hip",
+    "k_kdq": "kernels_md.hip", "k_bin": "kernels_md.hip", "k_scan_blocks": "kernels_md.hip",
     "k_scan_apply": "kernels_md.hip", "k_cell_scatter": "kernels_md.hip", "k_sort_gather": "kernels_md.hip",
     "k_kinetic": "kernels_md.hip", "k_msd": "kernels_md.hip", "k_fill_i32": "kernels_md.hip",
     "k_refill": "kernels_sample.hip", "k_sf_partial": "structure_factor.hip", "k_sf_reduce": "structure_factor.hip",

@@ -377,6 +377,33 @@ def test_autotune_keeps_results(orc, prec, tol, skin):
     check_eval(orc, sysm, c["pos"], c["q"], c["box"], c["rc"], m[c["P"]:2 * c["P"]], tol, f"tuned prec={prec}")
 
 
+@pytest.mark.parametrize("prec", [R.RBSOG_FP64, R.RBSOG_FP32C])
+def test_autotune_after_new_sequence(orc, prec):
+    # the structure factor reads the batch at the sequence cursor, and the
+    # tuner times it on the latest evaluation's batch again; after set_k
+    # that batch is gone: the tuner keeps the structure factor's shapes, the
+    # forces stay those of the evaluation, and the next evaluation takes the
+    # new sequence from its start
+    c = W.c1_small()
+    sysm = make(c["pos"], c["q"], c["box"], c["rc"], c["P"], seed=102, prec=prec)
+    sysm.sample_k(2)
+    sysm.forces()
+    Fn0, Ff0 = sysm.components()
+    shapes0 = R.rbsog_info(sysm.ctx)
+    rng = np.random.default_rng(9)
+    mnew = rng.integers(-4, 5, size=(3 * c["P"], 3)).astype(np.int32)
+    mnew[np.all(mnew == 0, axis=1)] = (1, 0, 0)
+    sysm.set_k(mnew)
+    info = R.rbsog_autotune(sysm.ctx, 2)
+    assert info["tuned"] and info["k_remaining"] == 3 * c["P"]
+    assert info["rho_chunk"] == shapes0["rho_chunk"] and info["rho_ktile"] == shapes0["rho_ktile"]
+    Fn1, Ff1 = sysm.components()
+    rt = 1e-13 if prec == R.RBSOG_FP64 else 1e-6
+    assert relrms(Fn1, Fn0) < rt and relrms(Ff1, Ff0) < rt
+    tol = F64_TOL if prec == R.RBSOG_FP64 else F32C_TOL
+    check_eval(orc, sysm, c["pos"], c["q"], c["box"], c["rc"], mnew[:c["P"]], tol, f"tuned after set_k prec={prec}")
+
+
 def test_autotune_option_in_step():
     c = W.c1_small()
     runs = []
