@@ -4,8 +4,9 @@
 //   F*_i     = -q_i sum_e w_e k_e (Im rho_e cos th_ie - Re rho_e sin th_ie),  th_ie = k_e.r_i
 //   U*       = 1/2 sum_e w_e |rho_e|^2
 // Phases are taken in revolutions of the fractional coordinate, th/(2 pi) =
-// m.s with s = x/L: FP64 forms evaluate t = m.s in FP64 and sin/cos of 2 pi t
-// through a table of 256 turns in LDS and short polynomials of the rest;
+// m.s with s = x/L: FP64 forms evaluate kTurnTab t = m.(kTurnTab s) in FP64
+// and sin/cos of 2 pi t through a table of 1024 turns in LDS and short
+// polynomials of the rest;
 // FP32 forms take m.u mod 2^32 exactly on the 32-bit fixed-point coordinate
 // and the hardware sin/cos of the revolution.
 //
@@ -83,11 +84,11 @@ __global__ __launch_bounds__(1024, F64 ? 1 : 8) void k_rho(EvalArgs a, const Rho
     // loop's first barrier orders the fill before any use
     __shared__ double2 turn[F64 ? rmath::kTurnTab : 1];
     if constexpr (F64) {
-        if ((int)threadIdx.x < rmath::kTurnTab) {
-            const double f = (double)threadIdx.x / rmath::kTurnTab;
+        for (int j = threadIdx.x; j < rmath::kTurnTab; j += blockDim.x) {
+            const double f = (double)j / rmath::kTurnTab;
             double sn, cs;
             sincos2pi(f - rint(f), &sn, &cs);
-            turn[threadIdx.x] = make_double2(cs, sn);
+            turn[j] = make_double2(cs, sn);
         }
     }
     const int64_t n = a.N;
@@ -113,7 +114,9 @@ __global__ __launch_bounds__(1024, F64 ? 1 : 8) void k_rho(EvalArgs a, const Rho
         double re = 0.0, im = 0.0;
         if constexpr (F64) {
             const double mx = mk[0], my = mk[1], mz = mk[2];
-            const double ix = sp->g.invL[0], iy = sp->g.invL[1], iz = sp->g.invL[2];
+            // fractional coordinates in table units (kTurnTab per box length)
+            const double ix = sp->g.invL[0] * rmath::kTurnTab, iy = sp->g.invL[1] * rmath::kTurnTab,
+                         iz = sp->g.invL[2] * rmath::kTurnTab;
             for (int64_t jb = j0; jb < j1; jb += kStage) {
                 const int cnt = (int)(j1 - jb < kStage ? j1 - jb : kStage);
                 if ((int)threadIdx.x < cnt) {
@@ -312,7 +315,7 @@ __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
             h.mx = m[0];
             h.my = m[1];
             h.mz = m[2];
-            h.phi = phi;
+            h.phi = phi * rmath::kTurnTab;
             h.ax = c * h.mx * sd.g.invL[0];
             h.ay = c * h.my * sd.g.invL[1];
             h.az = c * h.mz * sd.g.invL[2];
@@ -403,7 +406,10 @@ __device__ __forceinline__ void far_sum(CSys *sp, CRec64 *kb64, CRec32 *kb32, in
     Fx = 0.0; Fy = 0.0; Fz = 0.0;
     // records are consumed in groups so that their uniform loads overlap
     if constexpr (F64) {
-        const double sx = x[i] * sp->g.invL[0], sy = x[n + i] * sp->g.invL[1], sz = x[2 * n + i] * sp->g.invL[2];
+        // fractional coordinates in table units, as the records' phase
+        constexpr double tu = rmath::kTurnTab;
+        const double sx = x[i] * (sp->g.invL[0] * tu), sy = x[n + i] * (sp->g.invL[1] * tu),
+                     sz = x[2 * n + i] * (sp->g.invL[2] * tu);
         constexpr int G = 4;
         int32_t e = 0;
         for (; e + G <= P; e += G) {

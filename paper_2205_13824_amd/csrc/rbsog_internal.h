@@ -26,7 +26,8 @@ constexpr int kMaxGauss = 160;  // M + 1 <= kMaxGauss
 // a_e = w_e |rho_e| k_e: one sine per (particle, wave vector).  The
 // structure-factor reduction writes the records of the batch (the structure
 // factor itself reads m from the sequence at the cursor).
-// FP64 form: m as doubles, phi in revolutions, a.
+// FP64 form: m as doubles, phi in 1/kTurnTab revolutions (the unit of the
+// FP64 phases, rbsog_math.h), a.
 struct KRec64 {
     double mx, my, mz;
     double phi;

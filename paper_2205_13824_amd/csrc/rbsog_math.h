@@ -170,29 +170,29 @@ __device__ __forceinline__ double exp_nonpos(double y) {
     return ldexp(p, n);
 }
 
-// sin(2 pi t), cos(2 pi t) in FP64 for any t of moderate size through a
-// table of the kTurnTab turns 2 pi j / kTurnTab (tab[j] = (cos, sin), filled
-// with sincos2pi below): j = rint(kTurnTab t), r = t - j / kTurnTab (exact,
-// |r| <= 1 / (2 kTurnTab) turns), the Taylor series of sin and cos of 2 pi r
-// through degree 7 and 8 (truncation below 2e-23 at |2 pi r| <= pi / 256),
-// then the angle sum with entry j mod kTurnTab.
-constexpr int kTurnTab = 256;
-__device__ __forceinline__ void sincos2pi_tab(double t, const double2 *tab, double *s, double *c) {
-    constexpr double T = kTwoPi;
+// sin(2 pi t), cos(2 pi t) in FP64, from u = kTurnTab t (t in turns, u of
+// moderate size), through a table of the kTurnTab turns 2 pi j / kTurnTab
+// (tab[j] = (cos, sin), filled with sincos2pi below): j = rint(u), r = u - j
+// (exact, |r| <= 1/2), x = 2 pi r / kTurnTab (|x| <= pi / kTurnTab), the
+// Taylor series of sin x through degree 5 and of cos x through degree 4
+// (truncation below x^7/5040 < 6e-22 and x^6/720 < 1.2e-18 at |x| <= pi/1024,
+// well under an FP64 ulp of sin x and cos x), then the angle sum with entry
+// j mod kTurnTab.  Callers scale their positions by kTurnTab (a power of 2,
+// so u is exactly kTurnTab times the phase they would form in turns).
+constexpr int kTurnTab = 1024;
+__device__ __forceinline__ void sincos2pi_tab(double u, const double2 *tab, double *s, double *c) {
+    constexpr double T = kTwoPi / kTurnTab;
     constexpr double T2 = T * T;
     constexpr double S1 = -T * T2 / 6.0;
     constexpr double S2 = -S1 * T2 / 20.0;
-    constexpr double S3 = -S2 * T2 / 42.0;
     constexpr double C1 = -T2 / 2.0;
     constexpr double C2 = -C1 * T2 / 12.0;
-    constexpr double C3 = -C2 * T2 / 30.0;
-    constexpr double C4 = -C3 * T2 / 56.0;
-    const double jd = rint(t * (double)kTurnTab);
-    const double r = fma(jd, -1.0 / kTurnTab, t);
+    const double jd = rint(u);
+    const double r = u - jd;
     const double2 e = tab[(int)jd & (kTurnTab - 1)];
     const double z = r * r;
-    const double sr = r * fma(z, fma(z, fma(z, S3, S2), S1), T);
-    const double cr = fma(z, fma(z, fma(z, fma(z, C4, C3), C2), C1), 1.0);
+    const double sr = r * fma(z, fma(z, S2, S1), T);
+    const double cr = fma(z, fma(z, C2, C1), 1.0);
     *s = fma(e.y, cr, e.x * sr);
     *c = fma(e.x, cr, -(e.y * sr));
 }
