@@ -631,6 +631,11 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
     a.dbg_cap = c->dbg_cap;
     a.dbg_kind = c->dbg_kind;
     a.fuse = 0;
+    // four waves per record once a system has more chunks than one wave
+    // takes in a round of eight loads per lane
+    int32_t nch = 0;
+    for (const SysHost &h : c->sys) nch = std::max(nch, h.nch);
+    a.red_waves = nch > 512 ? 4 : 1;
     return a;
 }
 

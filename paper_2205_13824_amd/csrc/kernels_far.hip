@@ -263,13 +263,16 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// One wave per k record r: rho = sum over the system's chunks of the
-// partials (fixed order), the per-k energy 1/2 w |rho|^2, and rho written
-// into the records.  The block that reduces the last record of a system
-// (per-system counter) sums that system's far energy in a fixed order (U*,
-// with the zero-mode term and its dipole), writes U_self, advances the
-// sequence cursor by P and re-arms the counter; U_N and U follow in
-// k_kinetic, after the near part.  Nothing here waits for the near part.
+// The structure factor's reduction.  Per k record r: rho = sum over the
+// system's chunks of the partials (fixed order), the per-k energy
+// 1/2 w |rho|^2, and rho written into the records.  The block that reduces
+// the last record of a system (per-system counter) sums that system's far
+// energy in a fixed order (U*, with the zero-mode term and its dipole),
+// writes U_self, advances the sequence cursor by P and re-arms the counter;
+// U_N and U follow in k_kinetic, after the near part.  Nothing here waits
+// for the near part.
+// k_rho_reduce: one wave per record, four records per block (systems of few
+// chunks, many of them in a batch).
 __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
     __shared__ double si[256];
     __shared__ int32_t fin[4];
@@ -375,6 +378,143 @@ __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
             a.E[4 * s + 1] = si[0] + u0;
             a.E[4 * s + 2] = sd.uself;
             a.kcur[s] += sd.P;
+            a.sys_done[s] = 0u;
+            if (s == 0 && a.kick && a.thermo) *a.tstep += 1;
+        }
+        __syncthreads();
+    }
+}
+
+// k_rho_reduce_block: one block per record (systems of many chunks): each
+// thread a fixed strided subset of the chunks with eight loads in flight,
+// then a fixed butterfly across each wave and the four waves in order; the
+// finishing block sums the energies and the dipole with all its threads.
+__global__ __launch_bounds__(256) void k_rho_reduce_block(EvalArgs a) {
+    constexpr int W = 4, R = 1;
+    __shared__ double2 red[4];
+    __shared__ int32_t fin[R];
+    __shared__ int32_t nfin;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * R + wave / W;
+    const int tr = (wave % W) * 64 + lane;  // thread of the record
+    if (threadIdx.x == 0) nfin = 0;
+    double re = 0.0, im = 0.0;
+    int32_t sys = 0, k = 0;
+    if (r < a.K) {
+        sys = a.ksys[r];
+        const SysDev &sd = a.sys[sys];
+        k = (int32_t)(r - sd.k0);
+        const double2 *pk = reinterpret_cast<const double2 *>(a.partial) + sd.pofs + (int64_t)k * sd.nch;
+        const int32_t nch = sd.nch;
+        constexpr int T = 64 * W;
+        double2 v[8];
+#pragma unroll
+        for (int h = 0; h < 8; ++h) v[h] = make_double2(0.0, 0.0);
+        int32_t c = tr;
+        for (; c + 7 * T < nch; c += 8 * T) {
+            double2 w[8];
+#pragma unroll
+            for (int h = 0; h < 8; ++h) w[h] = pk[c + h * T];
+#pragma unroll
+            for (int h = 0; h < 8; ++h) {
+                v[h].x += w[h].x;
+                v[h].y += w[h].y;
+            }
+        }
+        for (; c < nch; c += T) {
+            const double2 w = pk[c];
+            v[0].x += w.x;
+            v[0].y += w.y;
+        }
+        re = ((v[0].x + v[1].x) + (v[2].x + v[3].x)) + ((v[4].x + v[5].x) + (v[6].x + v[7].x));
+        im = ((v[0].y + v[1].y) + (v[2].y + v[3].y)) + ((v[4].y + v[5].y) + (v[6].y + v[7].y));
+        re = wave_sum(re);
+        im = wave_sum(im);
+    }
+    if constexpr (W > 1) {
+        if (lane == 0) red[wave] = make_double2(re, im);
+        __syncthreads();
+        re = (red[0].x + red[1].x) + (red[2].x + red[3].x);
+        im = (red[0].y + red[1].y) + (red[2].y + red[3].y);
+    }
+    __syncthreads();
+    const SysDev &sd = a.sys[sys];
+    if (r < a.K && tr == 0) {
+        a.rho[r] = re;
+        a.rho[a.K + r] = im;
+        // the batch's k-th vector of the sequence and its weight (the
+        // cursor moves once every record of the system is reduced)
+        const int64_t e = a.kcur[sys] + k;
+        const int32_t m[3] = {sd.kseq[3 * e], sd.kseq[3 * e + 1], sd.kseq[3 * e + 2]};
+        const double w = sd.kw ? sd.kw[e] : sd.w_rb;
+        a.ek[r] = 0.5 * w * (re * re + im * im);
+        // amplitude-phase record: phi = arg(rho) / (2 pi), a = w |rho| k
+        const double phi = atan2(im, re) * (1.0 / rmath::kTwoPi);
+        const double mag = hypot(re, im);
+        const double c = w * mag * rmath::kTwoPi;
+        KRec64 h;
+        h.mx = m[0];
+        h.my = m[1];
+        h.mz = m[2];
+        h.phi = phi * rmath::kTurnTab;
+        h.ax = c * h.mx * sd.g.invL[0];
+        h.ay = c * h.my * sd.g.invL[1];
+        h.az = c * h.mz * sd.g.invL[2];
+        h.pad = 0.0;
+        a.kb64[r] = h;
+        // FP32 form: phi in 2^-32 turns, plus 2^9 units: the FP32 phases of
+        // the structure factor and of the far force are each truncated
+        // to 2^-23 turns (half a unit of it low on average), which this
+        // offset takes back
+        KRec32 f;
+        f.mx = m[0];
+        f.my = m[1];
+        f.mz = m[2];
+        f.phi = (uint32_t)(int64_t)rint(phi * 4294967296.0) + 512u;
+        f.ax = (float)h.ax;
+        f.ay = (float)h.ay;
+        f.az = (float)h.az;
+        f.pad = 0.f;
+        a.kb32[r] = f;
+        __threadfence();
+        if (atomicAdd(&a.sys_done[sys], 1u) == (uint32_t)sd.P - 1u) fin[atomicAdd(&nfin, 1)] = sys;
+    }
+    __syncthreads();
+    const int nf = nfin;
+    __shared__ double si[4][256];
+    for (int f = 0; f < nf; ++f) {
+        // a system's last record: its far energy and the sequence cursor
+        __threadfence();
+        const int32_t s = fin[f];
+        const SysDev &sf = a.sys[s];
+        double us = 0.0;
+        for (int64_t e = threadIdx.x; e < sf.P; e += 256) us += a.ek[sf.k0 + e];
+        // the dipole moment from the chunks' partials (zero-frequency modes)
+        double m[3] = {0.0, 0.0, 0.0};
+        if (sf.zmode != 0)
+            for (int32_t ch = threadIdx.x; ch < sf.nch; ch += 256)
+                for (int d = 0; d < 3; ++d) m[d] += a.dip_part[3 * (sf.choff + ch) + d];
+        si[0][threadIdx.x] = us;
+        si[1][threadIdx.x] = m[0];
+        si[2][threadIdx.x] = m[1];
+        si[3][threadIdx.x] = m[2];
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o)
+                for (int j = 0; j < 4; ++j) si[j][threadIdx.x] += si[j][threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            double u0 = 0.0;
+            if (sf.zmode != 0) {
+                const double M[3] = {si[1][0], si[2][0], si[3][0]};
+                for (int d = 0; d < 3; ++d) a.dipole[3 * s + d] = M[d];
+                u0 = sf.zmode == 1 ? sf.zu * (M[0] * M[0] + M[1] * M[1] + M[2] * M[2]) : sf.zu * M[2] * M[2];
+            }
+            // U* holds the far part with the zero-frequency mode term
+            a.E[4 * s + 1] = si[0][0] + u0;
+            a.E[4 * s + 2] = sf.uself;
+            a.kcur[s] += sf.P;
             a.sys_done[s] = 0u;
             if (s == 0 && a.kick && a.thermo) *a.tstep += 1;
         }
@@ -714,7 +854,9 @@ void launch_rho(const EvalArgs &a, bool f64, const RhoItem *items, int32_t nitem
 }
 
 void launch_rho_reduce(const EvalArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_rho_reduce, dim3((unsigned)((a.K + 3) / 4)), dim3(256), 0, s, a);
+    if (a.K <= 0) return;
+    if (a.red_waves == 4) hipLaunchKernelGGL(k_rho_reduce_block, dim3((unsigned)a.K), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_rho_reduce, dim3((unsigned)((a.K + 3) / 4)), dim3(256), 0, s, a);
 }
 
 void launch_far(const EvalArgs &a, bool f64, const FarItem *items, int32_t nitems, int32_t block_size,

@@ -143,20 +143,24 @@ __global__ __launch_bounds__(kBlock) void k_bin(EvalArgs a) {
     // the critical path's waves ahead of the structure factor's beside them
     __builtin_amdgcn_s_setprio(2);
     if (!*a.rebuild) return;
-    const int64_t t0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const bool valid = t0 < a.N;
-    const int64_t t = valid ? t0 : a.N - 1;
     const int64_t N = a.N;
-    const SysDev &sd = a.sys[a.sys_of[t]];
-    int64_t c[3];
-    int32_t nc[3];
-    for (int d = 0; d < 3; ++d) {
-        nc[d] = sd.g.nc[d];
-        c[d] = (int64_t)(((uint64_t)a.u_tmp[d * N + t] * (uint64_t)nc[d]) >> 32);
+    // grid-stride over blocks of kBlock slots (the grid is capped: on the
+    // steps that do not build, few blocks return at once)
+    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < N; base += (int64_t)gridDim.x * kBlock) {
+        const int64_t t0 = base + threadIdx.x;
+        const bool valid = t0 < N;
+        const int64_t t = valid ? t0 : N - 1;
+        const SysDev &sd = a.sys[a.sys_of[t]];
+        int64_t c[3];
+        int32_t nc[3];
+        for (int d = 0; d < 3; ++d) {
+            nc[d] = sd.g.nc[d];
+            c[d] = (int64_t)(((uint64_t)a.u_tmp[d * N + t] * (uint64_t)nc[d]) >> 32);
+        }
+        const int64_t cell = sd.c0 + c[0] + (int64_t)nc[0] * (c[1] + (int64_t)nc[1] * c[2]);
+        if (valid) a.cell_of[t] = (int32_t)cell;
+        run_atomic_add(a.cell_count, cell, valid);
     }
-    const int64_t cell = sd.c0 + c[0] + (int64_t)nc[0] * (c[1] + (int64_t)nc[1] * c[2]);
-    if (valid) a.cell_of[t] = (int32_t)cell;
-    run_atomic_add(a.cell_count, cell, valid);
 }
 
 // ---- exclusive scan of int32 counts: 1024 elements per block --------------
@@ -242,14 +246,18 @@ __global__ __launch_bounds__(kBlock) void k_cell_scatter(int64_t N, const int32_
     // the critical path's waves ahead of the structure factor's beside them
     __builtin_amdgcn_s_setprio(2);
     if (!*cond) return;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = t < N;
-    const int32_t cell = valid ? cell_of[t] : 0;
-    const int32_t key = valid ? id[t] : 0;
-    const int32_t dst = run_atomic_add(fill, cell, valid);
-    if (valid) {
-        src[dst] = (int32_t)t;
-        skey[dst] = key;
+    // grid-stride as in k_bin (the order of the atomics within a cell is
+    // undone by the per-cell id sort)
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < N; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = base + threadIdx.x;
+        const bool valid = t < N;
+        const int32_t cell = valid ? cell_of[t] : 0;
+        const int32_t key = valid ? id[t] : 0;
+        const int32_t dst = run_atomic_add(fill, cell, valid);
+        if (valid) {
+            src[dst] = (int32_t)t;
+            skey[dst] = key;
+        }
     }
 }
 
@@ -269,92 +277,97 @@ __global__ __launch_bounds__(kBlock) void k_sort_gather(EvalArgs a) {
     // the critical path's waves ahead of the structure factor's beside them
     __builtin_amdgcn_s_setprio(2);
     if (!*a.rebuild) return;
-    const int64_t c0 = (int64_t)blockIdx.x * kSortCells;
-    const int64_t c = c0 + threadIdx.x;
     int32_t *out = a.sorted;
-    if (threadIdx.x < kSortCells && c < a.C) {
-        const int32_t lo = a.cell_start[c], hi = a.cell_start[c + 1];
-        const int32_t cnt = hi - lo;
-        const int32_t *src = a.src;
-        const int32_t *idc = a.cur.id;
-        if (cnt <= kRankMax) {
-            int32_t sv[kRankMax], key[kRankMax];
+    // grid-stride over groups of kSortCells cells (the grid is capped)
+    for (int64_t c0 = (int64_t)blockIdx.x * kSortCells; c0 < a.C; c0 += (int64_t)gridDim.x * kSortCells) {
+        const int64_t c = c0 + threadIdx.x;
+        if (threadIdx.x < kSortCells && c < a.C) {
+            const int32_t lo = a.cell_start[c], hi = a.cell_start[c + 1];
+            const int32_t cnt = hi - lo;
+            const int32_t *src = a.src;
+            const int32_t *idc = a.cur.id;
+            if (cnt <= kRankMax) {
+                int32_t sv[kRankMax], key[kRankMax];
 #pragma unroll
-            for (int i = 0; i < kRankMax; ++i) {
-                sv[i] = i < cnt ? src[lo + i] : 0;
-                key[i] = i < cnt ? a.skey[lo + i] : INT32_MAX;
-            }
-#pragma unroll
-            for (int i = 0; i < kRankMax; ++i) {
-                int32_t rank = 0;
-#pragma unroll
-                for (int j = 0; j < kRankMax; ++j) rank += key[j] < key[i] ? 1 : 0;
-                if (i < cnt) out[lo + rank] = sv[i];
-            }
-        } else {
-            for (int32_t i = lo; i < hi; ++i) out[i] = src[i];
-            for (int32_t i = lo + 1; i < hi; ++i) {
-                const int32_t v = out[i];
-                const int32_t kv = idc[v];
-                int32_t j = i - 1;
-                while (j >= lo && idc[out[j]] > kv) {
-                    out[j + 1] = out[j];
-                    --j;
+                for (int i = 0; i < kRankMax; ++i) {
+                    sv[i] = i < cnt ? src[lo + i] : 0;
+                    key[i] = i < cnt ? a.skey[lo + i] : INT32_MAX;
                 }
-                out[j + 1] = v;
-            }
-        }
-        a.cell_count[c] = 0;
-    }
-    // the block's permutation entries are visible to the whole block here
-    __syncthreads();
-    const int64_t c1 = c0 + kSortCells < a.C ? c0 + kSortCells : a.C;
-    const int64_t k0 = a.cell_start[c0], k1 = a.cell_start[c1];
-    const int64_t N = a.N;
-    // two slots per thread and pass, all loads issued before the stores
-    constexpr int U = 2;
-    for (int64_t kb = k0 + threadIdx.x; kb < k1; kb += U * kBlock) {
-        int64_t tt[U];
 #pragma unroll
-        for (int j = 0; j < U; ++j) tt[j] = kb + j * kBlock < k1 ? out[kb + j * kBlock] : -1;
-        double xv[U][3], vv[U][3], qv[U];
-        uint32_t uv[U][3];
-        float qfv[U];
-        int32_t idv[U], cv[U];
+                for (int i = 0; i < kRankMax; ++i) {
+                    int32_t rank = 0;
 #pragma unroll
-        for (int j = 0; j < U; ++j) {
-            const int64_t t = tt[j] < 0 ? 0 : tt[j];
-            for (int d = 0; d < 3; ++d) {
-                xv[j][d] = a.cur.x[d * N + t];
-                vv[j][d] = a.cur.v[d * N + t];
-                uv[j][d] = a.u_tmp[d * N + t];
+                    for (int j = 0; j < kRankMax; ++j) rank += key[j] < key[i] ? 1 : 0;
+                    if (i < cnt) out[lo + rank] = sv[i];
+                }
+            } else {
+                for (int32_t i = lo; i < hi; ++i) out[i] = src[i];
+                for (int32_t i = lo + 1; i < hi; ++i) {
+                    const int32_t v = out[i];
+                    const int32_t kv = idc[v];
+                    int32_t j = i - 1;
+                    while (j >= lo && idc[out[j]] > kv) {
+                        out[j + 1] = out[j];
+                        --j;
+                    }
+                    out[j + 1] = v;
+                }
             }
-            qv[j] = a.cur.q[t];
-            qfv[j] = a.cur.qf[t];
-            idv[j] = a.cur.id[t];
-            cv[j] = a.cell_of[t];
+            a.cell_count[c] = 0;
         }
+        // the block's permutation entries are visible to the whole block here
+        __syncthreads();
+        const int64_t c1 = c0 + kSortCells < a.C ? c0 + kSortCells : a.C;
+        const int64_t k0 = a.cell_start[c0], k1 = a.cell_start[c1];
+        const int64_t N = a.N;
+        // two slots per thread and pass, all loads issued before the stores
+        constexpr int U = 2;
+        for (int64_t kb = k0 + threadIdx.x; kb < k1; kb += U * kBlock) {
+            int64_t tt[U];
 #pragma unroll
-        for (int j = 0; j < U; ++j) {
-            const int64_t k = kb + j * kBlock;
-            if (tt[j] < 0) continue;
-            for (int d = 0; d < 3; ++d) {
-                a.nxt.x[d * N + k] = xv[j][d];
-                a.nxt.v[d * N + k] = vv[j][d];
-                a.u[d * N + k] = uv[j][d];
-            }
-            a.nxt.q[k] = qv[j];
-            a.nxt.qf[k] = qfv[j];
-            a.nxt.id[k] = idv[j];
-            a.cell_sorted[k] = cv[j];
-        }
-        if (a.cur.dsp) {
+            for (int j = 0; j < U; ++j) tt[j] = kb + j * kBlock < k1 ? out[kb + j * kBlock] : -1;
+            double xv[U][3], vv[U][3], qv[U];
+            uint32_t uv[U][3];
+            float qfv[U];
+            int32_t idv[U], cv[U];
 #pragma unroll
             for (int j = 0; j < U; ++j) {
+                const int64_t t = tt[j] < 0 ? 0 : tt[j];
+                for (int d = 0; d < 3; ++d) {
+                    xv[j][d] = a.cur.x[d * N + t];
+                    vv[j][d] = a.cur.v[d * N + t];
+                    uv[j][d] = a.u_tmp[d * N + t];
+                }
+                qv[j] = a.cur.q[t];
+                qfv[j] = a.cur.qf[t];
+                idv[j] = a.cur.id[t];
+                cv[j] = a.cell_of[t];
+            }
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int64_t k = kb + j * kBlock;
                 if (tt[j] < 0) continue;
-                for (int d = 0; d < 3; ++d) a.nxt.dsp[d * N + kb + j * kBlock] = a.cur.dsp[d * N + tt[j]];
+                for (int d = 0; d < 3; ++d) {
+                    a.nxt.x[d * N + k] = xv[j][d];
+                    a.nxt.v[d * N + k] = vv[j][d];
+                    a.u[d * N + k] = uv[j][d];
+                }
+                a.nxt.q[k] = qv[j];
+                a.nxt.qf[k] = qfv[j];
+                a.nxt.id[k] = idv[j];
+                a.cell_sorted[k] = cv[j];
+            }
+            if (a.cur.dsp) {
+#pragma unroll
+                for (int j = 0; j < U; ++j) {
+                    if (tt[j] < 0) continue;
+                    for (int d = 0; d < 3; ++d) a.nxt.dsp[d * N + kb + j * kBlock] = a.cur.dsp[d * N + tt[j]];
+                }
             }
         }
+        // the next group's permutation entries are written after every
+        // thread has read this group's
+        __syncthreads();
     }
 }
 
@@ -399,8 +412,13 @@ void launch_kdq(const EvalArgs &a, hipStream_t s) {
 
 int64_t scan_blocksums_size(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
+// Grids of the list-build kernels that stride: a step without a build
+// dispatches this many blocks at most, each returning at once.
+constexpr int64_t kBuildGrid = 2048;
+inline unsigned capped(int64_t blocks) { return (unsigned)(blocks < kBuildGrid ? (blocks < 1 ? 1 : blocks) : kBuildGrid); }
+
 void launch_bin(const EvalArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_bin, dim3(grid_for(a.N, kBlock)), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_bin, dim3(capped(grid_for(a.N, kBlock))), dim3(kBlock), 0, s, a);
 }
 
 void launch_scan(const EvalArgs &a, hipStream_t s) {
@@ -413,12 +431,12 @@ void launch_scan(const EvalArgs &a, hipStream_t s) {
 }
 
 void launch_cell_scatter(const EvalArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_cell_scatter, dim3(grid_for(a.N, kBlock)), dim3(kBlock), 0, s, a.N, a.cell_of, a.cur.id,
+    hipLaunchKernelGGL(k_cell_scatter, dim3(capped(grid_for(a.N, kBlock))), dim3(kBlock), 0, s, a.N, a.cell_of, a.cur.id,
                        a.cell_fill, a.src, a.skey, (const int32_t *)a.rebuild);
 }
 
 void launch_sort_gather(const EvalArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_sort_gather, dim3(grid_for(a.C, kSortCells)), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_sort_gather, dim3(capped(grid_for(a.C, kSortCells))), dim3(kBlock), 0, s, a);
 }
 
 }  // namespace rbsog

@@ -690,13 +690,13 @@ __device__ __forceinline__ void drain_cols(const uint2 *ring, int head, int coun
 // S: candidate slots per lane and pass (64 S candidates tested per pass)
 template <int S>
 __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListItem *__restrict__ items,
-                                                         int32_t nitems, int32_t nblk) {
+                                                         int32_t nitems, int32_t nblk, int32_t gblk) {
     // the critical path's waves ahead of the structure factor's beside them
     __builtin_amdgcn_s_setprio(2);
     if (!*a.rebuild) return;
     const int64_t n = a.N;  // stride of the structure-of-arrays
-    if ((int32_t)blockIdx.x >= nblk) {
-        copy_back(a, (int64_t)(blockIdx.x - nblk) * blockDim.x + threadIdx.x, (int64_t)(gridDim.x - nblk) * blockDim.x);
+    if ((int32_t)blockIdx.x >= gblk) {
+        copy_back(a, (int64_t)(blockIdx.x - gblk) * blockDim.x + threadIdx.x, (int64_t)(gridDim.x - gblk) * blockDim.x);
         return;
     }
     constexpr int Q = ring_size(S);
@@ -713,11 +713,14 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
     // positions in the new order)
     const uint32_t *__restrict__ su = a.u;
     if (blockIdx.x == 0 && threadIdx.x == 0) ++*a.nbuild;
-    // one item per block; blocks are dealt to the 8 XCDs round robin: block b
-    // (on XCD b % 8) takes item (b % 8) * (nblk / 8) + b / 8
-    const int32_t b = blockIdx.x;
+    // one item per virtual block b: blocks are dealt to the 8 XCDs round
+    // robin, and b (on XCD b % 8) takes item (b % 8) * (nblk / 8) + b / 8.
+    // The gblk blocks launched (a multiple of 8, so that a block stays with
+    // its XCD's items) take the nblk virtual ones grid-stride: on the steps
+    // that do not build, few blocks return at once.
+    for (int32_t b = blockIdx.x; b < nblk; b += gblk) {
     const int32_t it = (b % 8) * (nblk / 8) + b / 8;
-    if (it >= nitems) return;
+    if (it >= nitems) continue;
     {
     const __attribute__((address_space(4))) ListItem *ip = (const __attribute__((address_space(4))) ListItem *)(items + it);
     ListItem item;
@@ -930,6 +933,9 @@ __global__ __launch_bounds__(64 * kNW) void k_list_build(EvalArgs a, const ListI
         const int32_t bm = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
         atomicMax(a.pmax, bm);
         if (out && bm > rows) atomicOr(a.flag, 8);
+    }
+    // the next item reuses the LDS of the waves and wmax
+    __syncthreads();
     }
     }
 }
@@ -1480,10 +1486,10 @@ __global__ void k_neighbors(EvalArgs a, int32_t sys, int64_t nloc, int64_t p0, c
 }
 
 void list_build_launch(const EvalArgs &a, int32_t slots, dim3 grid, dim3 block, const ListItem *items,
-                       int32_t nitems, int32_t nblk, hipStream_t s) {
-    if (slots <= 2) hipLaunchKernelGGL((k_list_build<2>), grid, block, 0, s, a, items, nitems, nblk);
-    else if (slots == 3) hipLaunchKernelGGL((k_list_build<3>), grid, block, 0, s, a, items, nitems, nblk);
-    else hipLaunchKernelGGL((k_list_build<4>), grid, block, 0, s, a, items, nitems, nblk);
+                       int32_t nitems, int32_t nblk, int32_t gblk, hipStream_t s) {
+    if (slots <= 2) hipLaunchKernelGGL((k_list_build<2>), grid, block, 0, s, a, items, nitems, nblk, gblk);
+    else if (slots == 3) hipLaunchKernelGGL((k_list_build<3>), grid, block, 0, s, a, items, nitems, nblk, gblk);
+    else hipLaunchKernelGGL((k_list_build<4>), grid, block, 0, s, a, items, nitems, nblk, gblk);
 }
 
 template <bool DBG>
@@ -1502,15 +1508,17 @@ void near_cells_launch(const EvalArgs &a, bool f64, int32_t slots, dim3 grid, di
 
 void launch_list_build(const EvalArgs &a, bool f64, const ListItem *items, int32_t nitems, int32_t slots,
                        hipStream_t s, bool copy_back) {
-    // one item per block (a wave per quarter); a multiple of 8 blocks so that
-    // the XCD mapping is a permutation of the blocks; then the blocks of the
-    // copy back
+    // one item per virtual block (a wave per quarter); a multiple of 8 so
+    // that the XCD mapping is a permutation of the blocks; at most kBuildBlocks
+    // launched (grid-stride), then the blocks of the copy back
+    constexpr int32_t kBuildBlocks = 4096;
     int32_t nblk = (nitems + 7) / 8 * 8;
     if (nblk < 8) nblk = 8;
+    const int32_t gblk = std::min(nblk, kBuildBlocks);
     const int64_t ncopy = copy_back ? std::min<int64_t>(1024, std::max<int64_t>(1, grid_for(a.N, 64 * kNW))) : 0;
-    const dim3 grid((unsigned)(nblk + ncopy)), block(64 * kNW);
+    const dim3 grid((unsigned)(gblk + ncopy)), block(64 * kNW);
     (void)f64;  // the build's test is the same in both precisions
-    list_build_launch(a, slots, grid, block, items, nitems, nblk, s);
+    list_build_launch(a, slots, grid, block, items, nitems, nblk, gblk, s);
 }
 
 void launch_near_cells(const EvalArgs &a, bool f64, const NearItem *items, int32_t nitems, int32_t slots,

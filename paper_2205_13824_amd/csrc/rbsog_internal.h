@@ -226,6 +226,7 @@ struct EvalArgs {
     double *epart_cells;   // near energies per cell-run item (build-every-evaluation mode)
     int32_t energy;        // 1: the near kernels sum the pair energies (else forces only)
     double *dip_part;      // dipole partials per structure-factor chunk (3 per chunk)
+    int32_t red_waves;     // waves per k record of the structure factor's reduction (1 or 4)
     double *dipole;        // dipole moment M per system (3 per system)
     int32_t *flag;         // bit 0: non-finite force, bit 1: non-finite energy, bit 3: list overflow
     // debug launches only (null otherwise): the near kernels record every pair
