@@ -1013,19 +1013,24 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
                 hd.q = sqf[th];
             }
             const int32_t cnt = ((CI32 *)a.pcnt)[(int64_t)it * kListHomes + hh];
-            const uint32_t *__restrict__ rowp = a.pairs + (int64_t)it * a.icap + (int64_t)hh * (rlast + 1);
+            // the home's block of the list (a uniform base; 32-bit offsets)
+            const char *__restrict__ rowp =
+                (const char *)(a.pairs + (int64_t)it * a.icap + (int64_t)hh * (rlast + 1));
             auto entry = [&](int32_t r) -> uint32_t {
-                const uint32_t v = rowp[min(r, rlast)];
+                const uint32_t v = *(const uint32_t *)(rowp + (uint32_t)(min(r, rlast) * 4));
                 return r < cnt ? (v & kListSlotMask) : 0u;
             };
             R fx = 0, fy = 0, fz = 0;
-            uint32_t e1 = entry(lane);
+            // the entries two chunks ahead and the candidates' data of the
+            // next chunk are loaded while one chunk is evaluated
+            uint32_t e1 = entry(lane), e2 = entry(64 + lane);
             PairData<F64> pd = load_packed<F64>(a.pk, a.pkx, e1);
             for (int32_t c = 0; c < cnt; c += 64) {
                 const bool have = c + lane < cnt;
                 const uint32_t cj = e1;
                 const PairData<F64> cur = pd;
-                e1 = entry(c + 64 + lane);
+                e1 = e2;
+                e2 = entry(c + 128 + lane);
                 pd = load_packed<F64>(a.pk, a.pkx, e1);
                 R px, py, pz;
                 double de;
