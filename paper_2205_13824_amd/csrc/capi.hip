@@ -2518,7 +2518,7 @@ rbsog_status rbsog_debug_list(rbsog_ctx *c, int32_t sys, int64_t *row_ptr, int32
             for (int32_t k = 0; k < pc[(size_t)(it * kListHomes + hh)]; ++k) {
                 const int64_t at = c->list_hm ? (int64_t)hh * (c->icap / kListHomes) + k : (int64_t)k * kListHomes + hh;
                 const uint32_t e = ent[(size_t)(it * c->icap + at)];
-                pairs.push_back(make_uint2((uint32_t)id[(size_t)(t0 + hh)], (uint32_t)id[e & kListSlotMask]));
+                pairs.push_back(make_uint2((uint32_t)id[(size_t)(t0 + hh)], (uint32_t)id[e >> 4]));
             }
         }
     }

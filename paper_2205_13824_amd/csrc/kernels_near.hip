@@ -367,18 +367,18 @@ struct PairData {
     double x[3];
 };
 
-// The candidate's data from its gather records: one 16-byte load (and one
+// The candidate's data from its gather records, given the list entry (the
+// byte offset 16 j of candidate slot j's record): one 16-byte load (and one
 // 32-byte record in the FP64 form).
 template <bool F64>
 __device__ __forceinline__ PairData<F64> load_packed(const uint4 *__restrict__ pk, const PosQ64 *__restrict__ pkx,
-                                                     uint32_t j) {
+                                                     uint32_t off) {
     PairData<F64> d;
     // slots below 2^28: 32-bit byte offsets from the arrays' (scalar) bases
-    const uint32_t jj = j & kListSlotMask;
-    const uint4 r = *(const uint4 *)((const char *)pk + (jj << 4));
+    const uint4 r = *(const uint4 *)((const char *)pk + off);
     d.u[0] = r.x; d.u[1] = r.y; d.u[2] = r.z;
     if constexpr (F64) {
-        const PosQ64 w = *(const PosQ64 *)((const char *)pkx + (jj << 5));
+        const PosQ64 w = *(const PosQ64 *)((const char *)pkx + (off << 1));
         d.x[0] = w.x; d.x[1] = w.y; d.x[2] = w.z;
         d.q = w.q;
     } else {
@@ -677,8 +677,9 @@ __device__ __forceinline__ void drain_cols(const uint2 *ring, int head, int coun
         rem &= ~m;
     }
     if (have && out && pos < rows) {
+        // the entry: the byte offset of the candidate's gather record
         const int hcol = colbase + (int)qe.x;
-        out[hm ? (int64_t)hcol * rows + pos : (int64_t)pos * kListHomes + hcol] = qe.y;
+        out[hm ? (int64_t)hcol * rows + pos : (int64_t)pos * kListHomes + hcol] = qe.y << 4;
     }
 }
 
@@ -1018,7 +1019,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
                 (const char *)(a.pairs + (int64_t)it * a.icap + (int64_t)hh * (rlast + 1));
             auto entry = [&](int32_t r) -> uint32_t {
                 const uint32_t v = *(const uint32_t *)(rowp + (uint32_t)(min(r, rlast) * 4));
-                return r < cnt ? (v & kListSlotMask) : 0u;
+                return r < cnt ? v : 0u;
             };
             R fx = 0, fy = 0, fz = 0;
             // the entries two chunks ahead and the candidates' data of the
@@ -1027,7 +1028,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
             PairData<F64> pd = load_packed<F64>(a.pk, a.pkx, e1);
             for (int32_t c = 0; c < cnt; c += 64) {
                 const bool have = c + lane < cnt;
-                const uint32_t cj = e1;
+                const uint32_t cj = e1 >> 4;  // the slot (pair records of debug launches)
                 const PairData<F64> cur = pd;
                 e1 = e2;
                 e2 = entry(c + 128 + lane);
@@ -1075,7 +1076,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
     const char *__restrict__ blk = (const char *)(a.pairs + (int64_t)it * a.icap);
     auto entry = [&](int32_t r) -> uint32_t {
         const uint32_t v = *(const uint32_t *)(blk + (uint32_t)((min(r, rlast) * kListHomes + lane) * 4));
-        return r < cnt ? (v & kListSlotMask) : 0u;
+        return r < cnt ? v : 0u;
     };
     R fx = 0, fy = 0, fz = 0;
     // rows w, w + kNW, ...: the entries two rows ahead and the candidate's
@@ -1085,7 +1086,7 @@ __global__ __launch_bounds__(64 * kNW) void k_near_list(EvalArgs a, const ListIt
     PairData<F64> pd = load_packed<F64>(a.pk, a.pkx, e1);
     for (; k < maxcnt; k += kNW) {
         const bool have = k < cnt;
-        const uint32_t cj = e1;
+        const uint32_t cj = e1 >> 4;  // the slot (pair records of debug launches)
         const PairData<F64> cur = pd;
         e1 = e2;
         e2 = entry(k + 2 * kNW);

@@ -134,10 +134,11 @@ struct NearItem {
 // Near list item: up to kListHomes consecutive particle slots [t0, t1) of one
 // system (in the cell order of the latest list build).  Its block of the pair
 // list is icap entries (rows = icap / kListHomes): the k-th pair of home h
-// (slot t0 + h), k < pcnt[item kListHomes + h], is the candidate's slot at
-// entry k kListHomes + h (column blocks) or h rows + k (home-major blocks,
-// for long lists).  The build writes the lists of its four quarters of
-// homes, one wave each.
+// (slot t0 + h), k < pcnt[item kListHomes + h], is entry k kListHomes + h
+// (column blocks) or h rows + k (home-major blocks, for long lists); an
+// entry is 16 j for candidate slot j (the byte offset of its gather
+// record).  The build writes the lists of its four quarters of homes, one
+// wave each.
 constexpr int kListHomes = 64;
 constexpr int kListWaves = 4;
 struct ListItem {
@@ -166,8 +167,8 @@ struct StateBufs {
     double *dsp;  // displacement since the mean-square-displacement origin (sum of the drifts)
 };
 // Slots of a context stay below 2^kListSlotBits (its particle limit): the
-// near kernels gather by 32-bit byte offsets and keep a build's ring entries
-// and list entries within kListSlotMask.
+// near kernels gather by 32-bit byte offsets (list entries are 16 j) and
+// keep a build's ring entries within kListSlotMask.
 constexpr int kListSlotBits = 28;
 constexpr uint32_t kListSlotMask = (1u << kListSlotBits) - 1u;
 constexpr int64_t kMaxParticles = (int64_t)1 << kListSlotBits;
@@ -208,8 +209,8 @@ struct EvalArgs {
     double *Ff_side;       // build-every-step mode: far forces in the order before the re-sort
     // Verlet list: rebuild flag (set by the displacement check, cleared by the
     // far kernel, or by the list pass when the far kernel opens the next
-    // step), pairs (one u32 each: the candidate's slot, laid out as the near
-    // list items state), counts,
+    // step), pairs (one u32 each: 16 times the candidate's slot, laid out as
+    // the near list items state), counts,
     // capacity per item, largest count of the latest build, builds made
     int32_t *rebuild;
     int32_t list_hm;       // nonzero: home-major blocks of the near list (long lists)
