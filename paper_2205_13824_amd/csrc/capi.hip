@@ -231,6 +231,7 @@ struct rbsog_ctx {
     ChainState *chains = nullptr;
     int32_t *flag = nullptr;
     uint32_t *sys_done = nullptr;
+    uint32_t *bin_done = nullptr;
     ListItem *list_items = nullptr;
     NearItem *near_items = nullptr;  // cell runs of the build-every-evaluation mode
     int32_t n_near = 0;
@@ -611,6 +612,7 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
     a.dipole = c->dipole;
     a.flag = c->flag;
     a.sys_done = c->sys_done;
+    a.bin_done = c->bin_done;
     a.kick = stepping ? 1 : 0;
     a.energy = 1;
     a.hdm = 0.5 * dt / c->mass;
@@ -683,8 +685,8 @@ rbsog_status enqueue_eval(rbsog_ctx *c, bool stepping, double dt, bool kinetic, 
             TRY(timed_on(c, K_FARSIDE, c->side, [&] { launch_far_side(a, f64, c->far_items, c->n_far, fb, c->side); }));
         HIPCHK(c, hipEventRecord(c->ev_join, c->side));
     }
-    if (!a.always_build) TRY(timed(c, K_BIN, [&] { launch_bin(a, s); }));
-    TRY(timed(c, K_SCAN, [&] { launch_scan(a, s); }));
+    if (!a.always_build) TRY(timed(c, K_BIN, [&] { launch_bin_scan(a, s); }));
+    else TRY(timed(c, K_SCAN, [&] { launch_scan(a, s); }));
     TRY(timed(c, K_SCATTER, [&] { launch_cell_scatter(a, s); }));
     TRY(timed(c, K_SORTG, [&] { launch_sort_gather(a, s); }));
     if (a.always_build) {
@@ -1393,8 +1395,7 @@ rbsog_status autotune_now(rbsog_ctx *c, int32_t reps) {
     // already, so the re-sort is the identity), its near kernel with `slots`
     auto build = [&]() {
         EvalArgs a = make_args(c, false, 0.0);
-        launch_bin(a, st);
-        launch_scan(a, st);
+        launch_bin_scan(a, st);
         launch_cell_scatter(a, st);
         launch_sort_gather(a, st);
         return a;
@@ -1625,8 +1626,7 @@ rbsog_status first_build(rbsog_ctx *c) {
     a.icap = 0;
     hipStream_t s = c->stream;
     launch_kdq(a, s);
-    launch_bin(a, s);
-    launch_scan(a, s);
+    launch_bin_scan(a, s);
     launch_cell_scatter(a, s);
     launch_sort_gather(a, s);
     launch_list_build(a, c->prec == RBSOG_FP64, c->list_items, c->n_list, c->build_slots, s);
@@ -1800,6 +1800,7 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     ALLOC(dipole, 3 * (int64_t)nsys);
     ALLOC(flag, 1);
     ALLOC(sys_done, nsys);
+    ALLOC(bin_done, 1);
     float4 *dtab = nullptr;
     if (o.near_table) {
         if ((st = dalloc(c, &dtab, (int64_t)nsys * kTabSize)) != RBSOG_OK) return bail(st);
@@ -1863,6 +1864,7 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
                   hipMemcpy(c->kcur, zc.data(), nsys * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->tstep, zc.data(), sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->sys_done, zu.data(), nsys * sizeof(uint32_t), hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMemset(c->bin_done, 0, sizeof(uint32_t)) == hipSuccess &&
                   hipMemcpy(c->kin, std::vector<double>(nsys, 0.0).data(), nsys * sizeof(double),
                             hipMemcpyHostToDevice) == hipSuccess &&
                   hipMemcpy(c->nh_xi, std::vector<double>(nsys, 0.0).data(), nsys * sizeof(double),

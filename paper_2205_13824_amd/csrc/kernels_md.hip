@@ -138,7 +138,53 @@ __global__ __launch_bounds__(kBlock) void k_kdq(EvalArgs a) {
     }
 }
 
-// Cell c_d = (u n_d) >> 32 of each particle and the cell histogram.
+// ---- exclusive scan of int32 counts: 1024 elements per block --------------
+
+__device__ int32_t block_exclusive_scan(int32_t v, int32_t *total) {
+    __shared__ int32_t wsum[kBlock / 64];
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int32_t incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        int32_t t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    int32_t base = 0, tot = 0;
+    for (int w = 0; w < kBlock / 64; ++w) {
+        if (w < wid) base += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + incl - v;
+}
+
+// Exclusive scan of the counts of n cells by one block (few cells): each
+// thread sums a contiguous run, the block scans the run totals, each thread
+// writes its run's starts (cell_start, and the scatter's fill counters), and
+// out[n] = the total.
+__device__ void scan_counts_block(const int32_t *in, int64_t n, int32_t *out, int32_t *fill) {
+    const int64_t per = (n + kBlock - 1) / kBlock;
+    const int64_t b = (int64_t)threadIdx.x * per;
+    const int64_t e = b + per < n ? b + per : n;
+    int32_t sum = 0;
+    for (int64_t c = b; c < e; ++c) sum += in[c];
+    int32_t tot;
+    int32_t off = block_exclusive_scan(sum, &tot);
+    for (int64_t c = b; c < e; ++c) {
+        const int32_t v = in[c];
+        out[c] = off;
+        fill[c] = off;
+        off += v;
+    }
+    if (threadIdx.x == 0) out[n] = tot;
+}
+
+// Cell c_d = (u n_d) >> 32 of each particle and the cell histogram.  SCAN
+// (few cells): the last block to finish also scans the counts (the scan
+// kernels are not launched).
+template <bool SCAN>
 __global__ __launch_bounds__(kBlock) void k_bin(EvalArgs a) {
     // the critical path's waves ahead of the structure factor's beside them
     __builtin_amdgcn_s_setprio(2);
@@ -161,28 +207,18 @@ __global__ __launch_bounds__(kBlock) void k_bin(EvalArgs a) {
         if (valid) a.cell_of[t] = (int32_t)cell;
         run_atomic_add(a.cell_count, cell, valid);
     }
-}
-
-// ---- exclusive scan of int32 counts: 1024 elements per block --------------
-
-__device__ int32_t block_exclusive_scan(int32_t v, int32_t *total) {
-    __shared__ int32_t wsum[kBlock / 64];
-    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int32_t incl = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        int32_t t = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += t;
+    if constexpr (SCAN) {
+        __shared__ int32_t last;
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) last = atomicAdd(a.bin_done, 1u) == gridDim.x - 1 ? 1 : 0;
+        __syncthreads();
+        if (!last) return;
+        // every block's counts are in: scan them, then re-arm the counter
+        __threadfence();
+        scan_counts_block(a.cell_count, a.C, a.cell_start, a.cell_fill);
+        if (threadIdx.x == 0) *a.bin_done = 0u;
     }
-    if (lane == 63) wsum[wid] = incl;
-    __syncthreads();
-    int32_t base = 0, tot = 0;
-    for (int w = 0; w < kBlock / 64; ++w) {
-        if (w < wid) base += wsum[w];
-        tot += wsum[w];
-    }
-    __syncthreads();
-    *total = tot;
-    return base + incl - v;
 }
 
 __global__ void k_scan_blocks(const int32_t *__restrict__ in, int64_t n, int32_t *__restrict__ bsum,
@@ -417,8 +453,18 @@ int64_t scan_blocksums_size(int64_t n) { return (n + kScanTile - 1) / kScanTile 
 constexpr int64_t kBuildGrid = 2048;
 inline unsigned capped(int64_t blocks) { return (unsigned)(blocks < kBuildGrid ? (blocks < 1 ? 1 : blocks) : kBuildGrid); }
 
-void launch_bin(const EvalArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_bin, dim3(capped(grid_for(a.N, kBlock))), dim3(kBlock), 0, s, a);
+// Cell counts scanned by the last block of the bin pass up to this many
+// cells (one block reads them twice); above, by the two scan kernels.
+constexpr int64_t kScanInBin = 65536;
+
+void launch_bin_scan(const EvalArgs &a, hipStream_t s) {
+    const dim3 grid(capped(grid_for(a.N, kBlock)));
+    if (a.C <= kScanInBin) {
+        hipLaunchKernelGGL(k_bin<true>, grid, dim3(kBlock), 0, s, a);
+    } else {
+        hipLaunchKernelGGL(k_bin<false>, grid, dim3(kBlock), 0, s, a);
+        launch_scan(a, s);
+    }
 }
 
 void launch_scan(const EvalArgs &a, hipStream_t s) {

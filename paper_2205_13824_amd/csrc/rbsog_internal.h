@@ -239,6 +239,7 @@ struct EvalArgs {
     int32_t dbg_cap;
     int32_t *dbg_kind;
     uint32_t *sys_done;    // per-system counters of reduced k records
+    uint32_t *bin_done;    // blocks of the bin pass done (its last block scans the counts; re-armed to 0)
     // velocity-Verlet
     int32_t kick;          // nonzero: kick + drift before, kick after
     double hdm, dt;
@@ -334,10 +335,12 @@ void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 // the list reference (sets *a.rebuild)
 void launch_kdq(const EvalArgs &a, hipStream_t s);
 // The list build: each of these returns at once unless *a.rebuild is set.
-// Cell of each particle and the histogram; exclusive scan of the counts;
+// Cell of each particle and the histogram, then the exclusive scan of the
+// counts (by the bin pass's last block when the cells are few, else by the
+// scan kernels); the scan alone (the kick/drift kernel made the histogram);
 // scatter into cells; per cell: id sort of its segment, reset of its count,
 // gather of the state into `nxt` in the new order
-void launch_bin(const EvalArgs &a, hipStream_t s);
+void launch_bin_scan(const EvalArgs &a, hipStream_t s);
 void launch_scan(const EvalArgs &a, hipStream_t s);
 int64_t scan_blocksums_size(int64_t n);
 void launch_cell_scatter(const EvalArgs &a, hipStream_t s);
