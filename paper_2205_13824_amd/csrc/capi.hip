@@ -232,6 +232,7 @@ struct rbsog_ctx {
     int32_t *flag = nullptr;
     uint32_t *sys_done = nullptr;
     uint32_t *bin_done = nullptr;
+    double *kin_part = nullptr;
     ListItem *list_items = nullptr;
     NearItem *near_items = nullptr;  // cell runs of the build-every-evaluation mode
     int32_t n_near = 0;
@@ -636,8 +637,16 @@ EvalArgs make_args(rbsog_ctx *c, bool stepping, double dt) {
     // four waves per record once a system has more chunks than one wave
     // takes in a round of eight loads per lane
     int32_t nch = 0;
-    for (const SysHost &h : c->sys) nch = std::max(nch, h.nch);
+    int64_t parts = 0;
+    for (const SysHost &h : c->sys) {
+        nch = std::max(nch, h.nch);
+        parts = std::max<int64_t>({parts, 4 * (int64_t)(h.ft1 - h.ft0), (int64_t)(h.it1 - h.it0),
+                                   (int64_t)(h.jt1 - h.jt0)});
+    }
     a.red_waves = nch > 512 ? 4 : 1;
+    // the energy sums: a block per 32768 partials of the largest system
+    a.kin_part = c->kin_part;
+    a.kin_blocks = (int32_t)std::min<int64_t>(kKinBlocks, std::max<int64_t>(1, (parts + 32767) / 32768));
     return a;
 }
 
@@ -1801,6 +1810,7 @@ rbsog_status init_batch(rbsog_ctx **out, int32_t nsys, const int64_t *offsets, c
     ALLOC(flag, 1);
     ALLOC(sys_done, nsys);
     ALLOC(bin_done, 1);
+    ALLOC(kin_part, (int64_t)nsys * 2 * kKinBlocks);
     float4 *dtab = nullptr;
     if (o.near_table) {
         if ((st = dalloc(c, &dtab, (int64_t)nsys * kTabSize)) != RBSOG_OK) return bail(st);

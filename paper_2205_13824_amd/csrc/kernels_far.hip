@@ -263,6 +263,49 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Record r of system sys (its k-th wave vector) from its rho: rho and the
+// per-k energy stored, and the amplitude-phase records of both forms
+// written.  The cursor still points at the batch.
+__device__ __forceinline__ void write_record(const EvalArgs &a, const SysDev &sd, int32_t sys, int64_t r, int32_t k,
+                                             double re, double im) {
+    a.rho[r] = re;
+    a.rho[a.K + r] = im;
+    // the batch's k-th vector of the sequence and its weight (the
+    // cursor moves once every record of the system is reduced)
+    const int64_t e = a.kcur[sys] + k;
+    const int32_t m[3] = {sd.kseq[3 * e], sd.kseq[3 * e + 1], sd.kseq[3 * e + 2]};
+    const double w = sd.kw ? sd.kw[e] : sd.w_rb;
+    a.ek[r] = 0.5 * w * (re * re + im * im);
+    // amplitude-phase record: phi = arg(rho) / (2 pi), a = w |rho| k
+    const double phi = atan2(im, re) * (1.0 / rmath::kTwoPi);
+    const double mag = hypot(re, im);
+    const double c = w * mag * rmath::kTwoPi;
+    KRec64 h;
+    h.mx = m[0];
+    h.my = m[1];
+    h.mz = m[2];
+    h.phi = phi * rmath::kTurnTab;
+    h.ax = c * h.mx * sd.g.invL[0];
+    h.ay = c * h.my * sd.g.invL[1];
+    h.az = c * h.mz * sd.g.invL[2];
+    h.pad = 0.0;
+    a.kb64[r] = h;
+    // FP32 form: phi in 2^-32 turns, plus 2^9 units: the FP32 phases of
+    // the structure factor and of the far force are each truncated
+    // to 2^-23 turns (half a unit of it low on average), which this
+    // offset takes back
+    KRec32 f;
+    f.mx = m[0];
+    f.my = m[1];
+    f.mz = m[2];
+    f.phi = (uint32_t)(int64_t)rint(phi * 4294967296.0) + 512u;
+    f.ax = (float)h.ax;
+    f.ay = (float)h.ay;
+    f.az = (float)h.az;
+    f.pad = 0.f;
+    a.kb32[r] = f;
+}
+
 // The structure factor's reduction.  Per k record r: rho = sum over the
 // system's chunks of the partials (fixed order), the per-k energy
 // 1/2 w |rho|^2, and rho written into the records.  The block that reduces
@@ -301,44 +344,7 @@ __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
         double re = (v0.x + v1.x) + (v2.x + v3.x), im = (v0.y + v1.y) + (v2.y + v3.y);
         re = wave_sum(re);
         im = wave_sum(im);
-        if (lane == 0) {
-            a.rho[r] = re;
-            a.rho[a.K + r] = im;
-            // the batch's k-th vector of the sequence and its weight (the
-            // cursor moves once every record of the system is reduced)
-            const int64_t e = a.kcur[sys] + k;
-            const int32_t m[3] = {sd.kseq[3 * e], sd.kseq[3 * e + 1], sd.kseq[3 * e + 2]};
-            const double w = sd.kw ? sd.kw[e] : sd.w_rb;
-            a.ek[r] = 0.5 * w * (re * re + im * im);
-            // amplitude-phase record: phi = arg(rho) / (2 pi), a = w |rho| k
-            const double phi = atan2(im, re) * (1.0 / rmath::kTwoPi);
-            const double mag = hypot(re, im);
-            const double c = w * mag * rmath::kTwoPi;
-            KRec64 h;
-            h.mx = m[0];
-            h.my = m[1];
-            h.mz = m[2];
-            h.phi = phi * rmath::kTurnTab;
-            h.ax = c * h.mx * sd.g.invL[0];
-            h.ay = c * h.my * sd.g.invL[1];
-            h.az = c * h.mz * sd.g.invL[2];
-            h.pad = 0.0;
-            a.kb64[r] = h;
-            // FP32 form: phi in 2^-32 turns, plus 2^9 units: the FP32 phases of
-            // the structure factor and of the far force are each truncated
-            // to 2^-23 turns (half a unit of it low on average), which this
-            // offset takes back
-            KRec32 f;
-            f.mx = m[0];
-            f.my = m[1];
-            f.mz = m[2];
-            f.phi = (uint32_t)(int64_t)rint(phi * 4294967296.0) + 512u;
-            f.ax = (float)h.ax;
-            f.ay = (float)h.ay;
-            f.az = (float)h.az;
-            f.pad = 0.f;
-            a.kb32[r] = f;
-        }
+        if (lane == 0) write_record(a, sd, sys, r, k, re, im);
     }
     if (threadIdx.x == 0) nfin = 0;
     __syncthreads();
@@ -390,135 +396,82 @@ __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
 // then a fixed butterfly across each wave and the four waves in order; the
 // finishing block sums the energies and the dipole with all its threads.
 __global__ __launch_bounds__(256) void k_rho_reduce_block(EvalArgs a) {
-    constexpr int W = 4, R = 1;
     __shared__ double2 red[4];
-    __shared__ int32_t fin[R];
-    __shared__ int32_t nfin;
+    __shared__ int32_t last;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t r = (int64_t)blockIdx.x * R + wave / W;
-    const int tr = (wave % W) * 64 + lane;  // thread of the record
-    if (threadIdx.x == 0) nfin = 0;
-    double re = 0.0, im = 0.0;
-    int32_t sys = 0, k = 0;
-    if (r < a.K) {
-        sys = a.ksys[r];
-        const SysDev &sd = a.sys[sys];
-        k = (int32_t)(r - sd.k0);
-        const double2 *pk = reinterpret_cast<const double2 *>(a.partial) + sd.pofs + (int64_t)k * sd.nch;
-        const int32_t nch = sd.nch;
-        constexpr int T = 64 * W;
-        double2 v[8];
+    const int64_t r = blockIdx.x;
+    const int32_t sys = a.ksys[r];
+    const SysDev &sd = a.sys[sys];
+    const int32_t k = (int32_t)(r - sd.k0);
+    const double2 *pk = reinterpret_cast<const double2 *>(a.partial) + sd.pofs + (int64_t)k * sd.nch;
+    const int32_t nch = sd.nch;
+    double2 v[8];
 #pragma unroll
-        for (int h = 0; h < 8; ++h) v[h] = make_double2(0.0, 0.0);
-        int32_t c = tr;
-        for (; c + 7 * T < nch; c += 8 * T) {
-            double2 w[8];
+    for (int h = 0; h < 8; ++h) v[h] = make_double2(0.0, 0.0);
+    int32_t c = threadIdx.x;
+    for (; c + 7 * 256 < nch; c += 8 * 256) {
+        double2 w[8];
 #pragma unroll
-            for (int h = 0; h < 8; ++h) w[h] = pk[c + h * T];
+        for (int h = 0; h < 8; ++h) w[h] = pk[c + h * 256];
 #pragma unroll
-            for (int h = 0; h < 8; ++h) {
-                v[h].x += w[h].x;
-                v[h].y += w[h].y;
-            }
+        for (int h = 0; h < 8; ++h) {
+            v[h].x += w[h].x;
+            v[h].y += w[h].y;
         }
-        for (; c < nch; c += T) {
-            const double2 w = pk[c];
-            v[0].x += w.x;
-            v[0].y += w.y;
-        }
-        re = ((v[0].x + v[1].x) + (v[2].x + v[3].x)) + ((v[4].x + v[5].x) + (v[6].x + v[7].x));
-        im = ((v[0].y + v[1].y) + (v[2].y + v[3].y)) + ((v[4].y + v[5].y) + (v[6].y + v[7].y));
-        re = wave_sum(re);
-        im = wave_sum(im);
     }
-    if constexpr (W > 1) {
-        if (lane == 0) red[wave] = make_double2(re, im);
-        __syncthreads();
+    for (; c < nch; c += 256) {
+        const double2 w = pk[c];
+        v[0].x += w.x;
+        v[0].y += w.y;
+    }
+    double re = ((v[0].x + v[1].x) + (v[2].x + v[3].x)) + ((v[4].x + v[5].x) + (v[6].x + v[7].x));
+    double im = ((v[0].y + v[1].y) + (v[2].y + v[3].y)) + ((v[4].y + v[5].y) + (v[6].y + v[7].y));
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane == 0) red[wave] = make_double2(re, im);
+    __syncthreads();
+    if (threadIdx.x == 0) {
         re = (red[0].x + red[1].x) + (red[2].x + red[3].x);
         im = (red[0].y + red[1].y) + (red[2].y + red[3].y);
-    }
-    __syncthreads();
-    const SysDev &sd = a.sys[sys];
-    if (r < a.K && tr == 0) {
-        a.rho[r] = re;
-        a.rho[a.K + r] = im;
-        // the batch's k-th vector of the sequence and its weight (the
-        // cursor moves once every record of the system is reduced)
-        const int64_t e = a.kcur[sys] + k;
-        const int32_t m[3] = {sd.kseq[3 * e], sd.kseq[3 * e + 1], sd.kseq[3 * e + 2]};
-        const double w = sd.kw ? sd.kw[e] : sd.w_rb;
-        a.ek[r] = 0.5 * w * (re * re + im * im);
-        // amplitude-phase record: phi = arg(rho) / (2 pi), a = w |rho| k
-        const double phi = atan2(im, re) * (1.0 / rmath::kTwoPi);
-        const double mag = hypot(re, im);
-        const double c = w * mag * rmath::kTwoPi;
-        KRec64 h;
-        h.mx = m[0];
-        h.my = m[1];
-        h.mz = m[2];
-        h.phi = phi * rmath::kTurnTab;
-        h.ax = c * h.mx * sd.g.invL[0];
-        h.ay = c * h.my * sd.g.invL[1];
-        h.az = c * h.mz * sd.g.invL[2];
-        h.pad = 0.0;
-        a.kb64[r] = h;
-        // FP32 form: phi in 2^-32 turns, plus 2^9 units: the FP32 phases of
-        // the structure factor and of the far force are each truncated
-        // to 2^-23 turns (half a unit of it low on average), which this
-        // offset takes back
-        KRec32 f;
-        f.mx = m[0];
-        f.my = m[1];
-        f.mz = m[2];
-        f.phi = (uint32_t)(int64_t)rint(phi * 4294967296.0) + 512u;
-        f.ax = (float)h.ax;
-        f.ay = (float)h.ay;
-        f.az = (float)h.az;
-        f.pad = 0.f;
-        a.kb32[r] = f;
+        write_record(a, sd, sys, r, k, re, im);
         __threadfence();
-        if (atomicAdd(&a.sys_done[sys], 1u) == (uint32_t)sd.P - 1u) fin[atomicAdd(&nfin, 1)] = sys;
+        last = atomicAdd(&a.sys_done[sys], 1u) == (uint32_t)sd.P - 1u ? 1 : 0;
     }
     __syncthreads();
-    const int nf = nfin;
+    if (!last) return;
+    // the system's last record: its far energy and the sequence cursor
+    __threadfence();
+    double us = 0.0;
+    for (int64_t e = threadIdx.x; e < sd.P; e += 256) us += a.ek[sd.k0 + e];
+    // the dipole moment from the chunks' partials (zero-frequency modes)
+    double m[3] = {0.0, 0.0, 0.0};
+    if (sd.zmode != 0)
+        for (int32_t ch = threadIdx.x; ch < sd.nch; ch += 256)
+            for (int d = 0; d < 3; ++d) m[d] += a.dip_part[3 * (sd.choff + ch) + d];
     __shared__ double si[4][256];
-    for (int f = 0; f < nf; ++f) {
-        // a system's last record: its far energy and the sequence cursor
-        __threadfence();
-        const int32_t s = fin[f];
-        const SysDev &sf = a.sys[s];
-        double us = 0.0;
-        for (int64_t e = threadIdx.x; e < sf.P; e += 256) us += a.ek[sf.k0 + e];
-        // the dipole moment from the chunks' partials (zero-frequency modes)
-        double m[3] = {0.0, 0.0, 0.0};
-        if (sf.zmode != 0)
-            for (int32_t ch = threadIdx.x; ch < sf.nch; ch += 256)
-                for (int d = 0; d < 3; ++d) m[d] += a.dip_part[3 * (sf.choff + ch) + d];
-        si[0][threadIdx.x] = us;
-        si[1][threadIdx.x] = m[0];
-        si[2][threadIdx.x] = m[1];
-        si[3][threadIdx.x] = m[2];
+    si[0][threadIdx.x] = us;
+    si[1][threadIdx.x] = m[0];
+    si[2][threadIdx.x] = m[1];
+    si[3][threadIdx.x] = m[2];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int j = 0; j < 4; ++j) si[j][threadIdx.x] += si[j][threadIdx.x + o];
         __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if ((int)threadIdx.x < o)
-                for (int j = 0; j < 4; ++j) si[j][threadIdx.x] += si[j][threadIdx.x + o];
-            __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double u0 = 0.0;
+        if (sd.zmode != 0) {
+            const double M[3] = {si[1][0], si[2][0], si[3][0]};
+            for (int d = 0; d < 3; ++d) a.dipole[3 * sys + d] = M[d];
+            u0 = sd.zmode == 1 ? sd.zu * (M[0] * M[0] + M[1] * M[1] + M[2] * M[2]) : sd.zu * M[2] * M[2];
         }
-        if (threadIdx.x == 0) {
-            double u0 = 0.0;
-            if (sf.zmode != 0) {
-                const double M[3] = {si[1][0], si[2][0], si[3][0]};
-                for (int d = 0; d < 3; ++d) a.dipole[3 * s + d] = M[d];
-                u0 = sf.zmode == 1 ? sf.zu * (M[0] * M[0] + M[1] * M[1] + M[2] * M[2]) : sf.zu * M[2] * M[2];
-            }
-            // U* holds the far part with the zero-frequency mode term
-            a.E[4 * s + 1] = si[0][0] + u0;
-            a.E[4 * s + 2] = sf.uself;
-            a.kcur[s] += sf.P;
-            a.sys_done[s] = 0u;
-            if (s == 0 && a.kick && a.thermo) *a.tstep += 1;
-        }
-        __syncthreads();
+        // U* holds the far part with the zero-frequency mode term
+        a.E[4 * sys + 1] = si[0][0] + u0;
+        a.E[4 * sys + 2] = sd.uself;
+        a.kcur[sys] += sd.P;
+        a.sys_done[sys] = 0u;
+        if (sys == 0 && a.kick && a.thermo) *a.tstep += 1;
     }
 }
 
@@ -773,28 +726,41 @@ __global__ __launch_bounds__(256) void k_far_finish(EvalArgs a, const FarItem *_
     }
 }
 
-// Per system, one block: the near energy U_N from the near items' partials
-// of the mode in use and the total U = U_N + U* - U_self (eight loads in
-// flight per thread, fixed order); the kinetic energy after the evaluation
-// from the far items' wave partials (unused slots hold 0), fixed order; for
-// a Nose-Hoover step xi then moves its second half step with it.
+// Per system, gridDim.x blocks: each sums a contiguous share of the far
+// items' wave partials of the kinetic energy and of the near items' energy
+// partials of the mode in use (eight loads in flight per thread, a fixed
+// tree across the block); with one block it finishes alone, else the last
+// block of the system (per-system counter, re-armed) adds the blocks' sums in
+// block order.  The finish: U_N and the total U = U_N + U* - U_self, the
+// kinetic energy after the evaluation, and for a Nose-Hoover step xi's
+// second half step with it.
 __global__ __launch_bounds__(256) void k_kinetic(EvalArgs a) {
     __shared__ double kw[256], ew[256];
-    const int32_t s = blockIdx.x;
+    const int32_t s = blockIdx.y, g = blockIdx.x, G = gridDim.x;
     const SysDev &sp = a.sys[s];
-    double acc = 0.0;
-    for (int64_t j = (int64_t)sp.ft0 * 4 + threadIdx.x; j < (int64_t)sp.ft1 * 4; j += 256) acc += a.kpart[j];
-    double u8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const double *ep = a.always_build ? a.epart_cells : a.epart;
-    const int64_t i0 = a.always_build ? sp.jt0 : sp.it0, i1 = a.always_build ? sp.jt1 : sp.it1;
-    int64_t i = i0 + threadIdx.x;
-    for (; i + 7 * 256 < i1; i += 8 * 256) {
+    // the block's share [lo, hi) of the partials [b0, b1)
+    auto share = [&](int64_t b0, int64_t b1, int64_t &lo, int64_t &hi) {
+        const int64_t per = (b1 - b0 + G - 1) / G;
+        lo = b0 + (int64_t)g * per;
+        hi = lo + per < b1 ? lo + per : b1;
+        if (lo > hi) lo = hi;
+    };
+    auto sum8 = [&](const double *p, int64_t lo, int64_t hi) {
+        double u8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int64_t i = lo + threadIdx.x;
+        for (; i + 7 * 256 < hi; i += 8 * 256) {
 #pragma unroll
-        for (int h = 0; h < 8; ++h) u8[h] += ep[i + h * 256];
-    }
-    for (; i < i1; i += 256) u8[0] += ep[i];
-    kw[threadIdx.x] = acc;
-    ew[threadIdx.x] = ((u8[0] + u8[1]) + (u8[2] + u8[3])) + ((u8[4] + u8[5]) + (u8[6] + u8[7]));
+            for (int h = 0; h < 8; ++h) u8[h] += p[i + h * 256];
+        }
+        for (; i < hi; i += 256) u8[0] += p[i];
+        return ((u8[0] + u8[1]) + (u8[2] + u8[3])) + ((u8[4] + u8[5]) + (u8[6] + u8[7]));
+    };
+    int64_t lo, hi;
+    share((int64_t)sp.ft0 * 4, (int64_t)sp.ft1 * 4, lo, hi);
+    kw[threadIdx.x] = sum8(a.kpart, lo, hi);
+    const double *ep = a.always_build ? a.epart_cells : a.epart;
+    share(a.always_build ? sp.jt0 : sp.it0, a.always_build ? sp.jt1 : sp.it1, lo, hi);
+    ew[threadIdx.x] = sum8(ep, lo, hi);
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) {
@@ -803,20 +769,33 @@ __global__ __launch_bounds__(256) void k_kinetic(EvalArgs a) {
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const double un = ew[0];
-        const double tot = un + a.E[4 * s + 1] - a.E[4 * s + 2];
-        a.E[4 * s] = un;
-        a.E[4 * s + 3] = tot;
-        if (!isfinite(tot)) atomicOr(a.flag, 2);
-        const double K = kw[0];
-        if (a.kick && a.nh) {
-            const double nf = sp.nh_nf, Q = sp.nh_Q;
-            const double xh = a.nh_xi[s] + 0.5 * a.dt * (2.0 * a.kin[s] - nf * a.nh_T) / Q;
-            a.nh_xi[s] = xh + 0.5 * a.dt * (2.0 * K - nf * a.nh_T) / Q;
+    if (threadIdx.x != 0) return;
+    double K = kw[0], un = ew[0];
+    if (G > 1) {
+        double *part = a.kin_part + (int64_t)s * 2 * G;
+        part[2 * g] = K;
+        part[2 * g + 1] = un;
+        __threadfence();
+        if (atomicAdd(&a.sys_done[s], 1u) != (uint32_t)G - 1u) return;
+        __threadfence();
+        K = 0.0;
+        un = 0.0;
+        for (int32_t b = 0; b < G; ++b) {
+            K += part[2 * b];
+            un += part[2 * b + 1];
         }
-        a.kin[s] = K;
+        a.sys_done[s] = 0u;
     }
+    const double tot = un + a.E[4 * s + 1] - a.E[4 * s + 2];
+    a.E[4 * s] = un;
+    a.E[4 * s + 3] = tot;
+    if (!isfinite(tot)) atomicOr(a.flag, 2);
+    if (a.kick && a.nh) {
+        const double nf = sp.nh_nf, Q = sp.nh_Q;
+        const double xh = a.nh_xi[s] + 0.5 * a.dt * (2.0 * a.kin[s] - nf * a.nh_T) / Q;
+        a.nh_xi[s] = xh + 0.5 * a.dt * (2.0 * K - nf * a.nh_T) / Q;
+    }
+    a.kin[s] = K;
 }
 
 
@@ -883,7 +862,7 @@ void launch_far_finish(const EvalArgs &a, const FarItem *items, int32_t nitems, 
 }
 
 void launch_kinetic(const EvalArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_kinetic, dim3((unsigned)a.nsys), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_kinetic, dim3((unsigned)a.kin_blocks, (unsigned)a.nsys), dim3(256), 0, s, a);
 }
 
 }  // namespace rbsog

@@ -245,8 +245,11 @@ struct EvalArgs {
     double hdm, dt;
     double mass;
     // kinetic energy per far item and wave (4 slots per item), and per
-    // system after the evaluation
+    // system after the evaluation; the energy sums' blocks per system
+    // (kin_blocks, at most kKinBlocks) and their sums (2 per block)
     double *kpart, *kin;
+    double *kin_part;
+    int32_t kin_blocks;
     // Nose-Hoover thermostat (nh != 0): xi per system, target temperature
     int32_t nh;
     double nh_T;
@@ -324,6 +327,7 @@ struct SampDev {
     int32_t *out;             // lambda batches of P vectors (3 int32 each)
 };
 constexpr int32_t kMaxChains = 4096;
+constexpr int32_t kKinBlocks = 64;
 // advances every chain of every system by P states and resets the cursors;
 // sets bit 4 of *flag if a chain exceeds its attempt limit
 void launch_refill(const SampDev *samp, int32_t nsys, int32_t lambda, ChainState *chains, int64_t *kcur,
