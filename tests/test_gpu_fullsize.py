@@ -110,6 +110,14 @@ def test_20M_ions_sampled_and_invariants(orc, large, prec, tol):
     say(f"[large prec={prec}] sampled near relrms {e_n:.3e}, rho relrms {e_rho:.3e}, far sum {zsum:.2e}")
     assert e_n < tol and e_rho < tol
     assert zsum < (1e-12 if prec == R.RBSOG_FP64 else 1e-6)
+    # U_N over all 2e7 ions (the oracle's cell-list sum, pinned to brute
+    # force on small systems): the near energies' partials are summed by
+    # several blocks at this size
+    t0 = time.time()
+    _, Un_o = orc.near_cells(c["pos"], c["q"], c["box"], c["rc"], sog)
+    e_un = abs(E[0] - Un_o) / abs(Un_o)
+    say(f"[large prec={prec}] U_N rel {e_un:.3e} (oracle {time.time() - t0:.1f} s)")
+    assert e_un < (1e-10 if prec == R.RBSOG_FP64 else 10 * tol)
     # velocity-Verlet: total momentum stays at its initial zero
     R.rbsog_set_velocities(sysm.ctx, None, T=1.0, seed=8)
     sysm.step(4, 1e-3)
@@ -117,6 +125,12 @@ def test_20M_ions_sampled_and_invariants(orc, large, prec, tol):
     p = float(np.abs(v.sum(0)).max()) / float(np.abs(v).sum(0).max())
     say(f"[large prec={prec}] momentum after 4 steps {p:.2e}")
     assert p < (1e-9 if prec == R.RBSOG_FP64 else 1e-6)
+    # the kinetic energy the library sums (several blocks per system at this
+    # size) against the host's sum of the returned velocities
+    K, _ = R.rbsog_get_kinetic(sysm.ctx)
+    K_h = 0.5 * float(np.sum(v * v))
+    say(f"[large prec={prec}] kinetic rel {abs(K[0] - K_h) / K_h:.3e}")
+    assert abs(K[0] - K_h) < 1e-11 * K_h
     sysm.close()
 
 
