@@ -432,9 +432,10 @@ rbsog_status rbsog_profile_read(rbsog_ctx *ctx, int32_t idx, const char **name, 
  * states, the sequence and its cursor are part of the state): positions,
  * velocities and charges in the current cell order with the caller indices,
  * the fixed-point coordinates and those of the latest near-list build, the
- * cell starts, the near list (its used entries), the near and far forces of
- * the latest evaluation, energies, structure factors and the staged wave
- * vectors, the host chain, sequence and cursor of every system (or the
+ * cell starts (the near list itself is listed again from them on load), the
+ * near and far forces of the latest evaluation, energies, structure factors
+ * and the latest batch's wave-vector records, the host chain, sequence and
+ * cursor of every system (or the
  * device chains and their batches), the Langevin step counter, the
  * Nose-Hoover xi and kinetic energies, the mean-square-displacement origin
  * and displacements, the skin in use with the adaptive-skin counters, the
