@@ -192,11 +192,19 @@ def traffic_table(workload):
 
 
 def traffic_of(tab, key, fp64):
+    """HBM bytes per launch of the kernel the profile steps time for `key`:
+    the first template argument is the precision, and the variant whose
+    remaining flags are all false is the one timed (the far kernel of the
+    single profiled steps does not open the next step; the near list pass
+    records no pairs and sums no energies there)."""
     want = f"{KERNEL_NAMES[key]}<{'true' if fp64 else 'false'}"
-    for k, (rd, wr) in tab.items():
-        if k == want + ">" or k.startswith(want + ","):
-            return rd + wr
-    return None
+    cands = [k for k in tab if k == want + ">" or k.startswith(want + ",")]
+    plain = [k for k in cands if all(x.strip() == "false" for x in k[len(want) + 1:-1].split(",") if x.strip())]
+    pick = plain[0] if plain else (cands[0] if cands else None)
+    if pick is None:
+        return None
+    rd, wr = tab[pick]
+    return rd + wr
 
 
 def rooflines(kernels, n, P, near_pairs, fp64, traffic=None, rates=None):
