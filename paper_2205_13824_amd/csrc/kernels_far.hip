@@ -308,18 +308,14 @@ __device__ __forceinline__ void write_record(const EvalArgs &a, const SysDev &sd
 
 // The structure factor's reduction.  Per k record r: rho = sum over the
 // system's chunks of the partials (fixed order), the per-k energy
-// 1/2 w |rho|^2, and rho written into the records.  The block that reduces
-// the last record of a system (per-system counter) sums that system's far
-// energy in a fixed order (U*, with the zero-mode term and its dipole),
-// writes U_self, advances the sequence cursor by P and re-arms the counter;
-// U_N and U follow in k_kinetic, after the near part.  Nothing here waits
-// for the near part.
+// 1/2 w |rho|^2, and rho written into the records; then k_rho_finish sums
+// each system's far energy.  U_N and U follow in k_kinetic, after the near
+// part.  Nothing here waits for the near part.  (A last-block finish inside
+// the reduction would need a device-scope fence in every block, a writeback
+// of the XCD's L2 each: 0.3 ms for the 6,400 blocks of a 256-system batch.)
 // k_rho_reduce: one wave per record, four records per block (systems of few
 // chunks, many of them in a batch).
 __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
-    __shared__ double si[256];
-    __shared__ int32_t fin[4];
-    __shared__ int32_t nfin;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t r = (int64_t)blockIdx.x * 4 + wave;
     int32_t sys = -1;
@@ -346,58 +342,13 @@ __global__ __launch_bounds__(256) void k_rho_reduce(EvalArgs a) {
         im = wave_sum(im);
         if (lane == 0) write_record(a, sd, sys, r, k, re, im);
     }
-    if (threadIdx.x == 0) nfin = 0;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        for (int w = 0; w < 4; ++w) {
-            const int64_t rw = (int64_t)blockIdx.x * 4 + w;
-            if (rw >= a.K) break;
-            const int32_t s = a.ksys[rw];
-            if (atomicAdd(&a.sys_done[s], 1u) == (uint32_t)a.sys[s].P - 1u) fin[nfin++] = s;
-        }
-    }
-    __syncthreads();
-    const int32_t nf = nfin;
-    for (int f = 0; f < nf; ++f) {
-        __threadfence();
-        const int32_t s = fin[f];
-        const SysDev &sd = a.sys[s];
-        double us = 0.0;
-        for (int64_t k = threadIdx.x; k < sd.P; k += 256) us += a.ek[sd.k0 + k];
-        si[threadIdx.x] = us;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (threadIdx.x < o) si[threadIdx.x] += si[threadIdx.x + o];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            double u0 = 0.0;
-            if (sd.zmode != 0) {
-                double m[3] = {0.0, 0.0, 0.0};
-                for (int32_t ch = 0; ch < sd.nch; ++ch)
-                    for (int d = 0; d < 3; ++d) m[d] += a.dip_part[3 * (sd.choff + ch) + d];
-                for (int d = 0; d < 3; ++d) a.dipole[3 * s + d] = m[d];
-                u0 = sd.zmode == 1 ? sd.zu * (m[0] * m[0] + m[1] * m[1] + m[2] * m[2]) : sd.zu * m[2] * m[2];
-            }
-            // U* holds the far part with the zero-frequency mode term
-            a.E[4 * s + 1] = si[0] + u0;
-            a.E[4 * s + 2] = sd.uself;
-            a.kcur[s] += sd.P;
-            a.sys_done[s] = 0u;
-            if (s == 0 && a.kick && a.thermo) *a.tstep += 1;
-        }
-        __syncthreads();
-    }
 }
 
 // k_rho_reduce_block: one block per record (systems of many chunks): each
 // thread a fixed strided subset of the chunks with eight loads in flight,
-// then a fixed butterfly across each wave and the four waves in order; the
-// finishing block sums the energies and the dipole with all its threads.
+// then a fixed butterfly across each wave and the four waves in order.
 __global__ __launch_bounds__(256) void k_rho_reduce_block(EvalArgs a) {
     __shared__ double2 red[4];
-    __shared__ int32_t last;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t r = blockIdx.x;
     const int32_t sys = a.ksys[r];
@@ -434,21 +385,24 @@ __global__ __launch_bounds__(256) void k_rho_reduce_block(EvalArgs a) {
         re = (red[0].x + red[1].x) + (red[2].x + red[3].x);
         im = (red[0].y + red[1].y) + (red[2].y + red[3].y);
         write_record(a, sd, sys, r, k, re, im);
-        __threadfence();
-        last = atomicAdd(&a.sys_done[sys], 1u) == (uint32_t)sd.P - 1u ? 1 : 0;
     }
-    __syncthreads();
-    if (!last) return;
-    // the system's last record: its far energy and the sequence cursor
-    __threadfence();
+}
+
+// Per system, one block, after the reduction: the far energy U* = sum_e
+// ek_e (strided sums, then a fixed tree) with the zero-frequency mode term
+// and its dipole (the chunks' dipole partials, the same way), U_self, and
+// the sequence cursor moved on by P.  A kernel of its own: the records'
+// writes are visible to it without fences.
+__global__ __launch_bounds__(256) void k_rho_finish(EvalArgs a) {
+    __shared__ double si[4][256];
+    const int32_t s = blockIdx.x;
+    const SysDev &sd = a.sys[s];
     double us = 0.0;
     for (int64_t e = threadIdx.x; e < sd.P; e += 256) us += a.ek[sd.k0 + e];
-    // the dipole moment from the chunks' partials (zero-frequency modes)
     double m[3] = {0.0, 0.0, 0.0};
     if (sd.zmode != 0)
         for (int32_t ch = threadIdx.x; ch < sd.nch; ch += 256)
             for (int d = 0; d < 3; ++d) m[d] += a.dip_part[3 * (sd.choff + ch) + d];
-    __shared__ double si[4][256];
     si[0][threadIdx.x] = us;
     si[1][threadIdx.x] = m[0];
     si[2][threadIdx.x] = m[1];
@@ -463,15 +417,14 @@ __global__ __launch_bounds__(256) void k_rho_reduce_block(EvalArgs a) {
         double u0 = 0.0;
         if (sd.zmode != 0) {
             const double M[3] = {si[1][0], si[2][0], si[3][0]};
-            for (int d = 0; d < 3; ++d) a.dipole[3 * sys + d] = M[d];
+            for (int d = 0; d < 3; ++d) a.dipole[3 * s + d] = M[d];
             u0 = sd.zmode == 1 ? sd.zu * (M[0] * M[0] + M[1] * M[1] + M[2] * M[2]) : sd.zu * M[2] * M[2];
         }
         // U* holds the far part with the zero-frequency mode term
-        a.E[4 * sys + 1] = si[0][0] + u0;
-        a.E[4 * sys + 2] = sd.uself;
-        a.kcur[sys] += sd.P;
-        a.sys_done[sys] = 0u;
-        if (sys == 0 && a.kick && a.thermo) *a.tstep += 1;
+        a.E[4 * s + 1] = si[0][0] + u0;
+        a.E[4 * s + 2] = sd.uself;
+        a.kcur[s] += sd.P;
+        if (s == 0 && a.kick && a.thermo) *a.tstep += 1;
     }
 }
 
@@ -836,6 +789,7 @@ void launch_rho_reduce(const EvalArgs &a, hipStream_t s) {
     if (a.K <= 0) return;
     if (a.red_waves == 4) hipLaunchKernelGGL(k_rho_reduce_block, dim3((unsigned)a.K), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_rho_reduce, dim3((unsigned)((a.K + 3) / 4)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_rho_finish, dim3((unsigned)a.nsys), dim3(256), 0, s, a);
 }
 
 void launch_far(const EvalArgs &a, bool f64, const FarItem *items, int32_t nitems, int32_t block_size,

@@ -238,7 +238,7 @@ struct EvalArgs {
     int32_t *dbg_cnt;
     int32_t dbg_cap;
     int32_t *dbg_kind;
-    uint32_t *sys_done;    // per-system counters of reduced k records
+    uint32_t *sys_done;    // per-system counters of the energy sums' blocks (re-armed to 0)
     uint32_t *bin_done;    // blocks of the bin pass done (its last block scans the counts; re-armed to 0)
     // velocity-Verlet
     int32_t kick;          // nonzero: kick + drift before, kick after
@@ -380,9 +380,8 @@ void launch_neighbor_fill(const EvalArgs &a, int32_t sys, int64_t n, int64_t p0,
 // ---- far part (kernels_far.hip) --------------------------------------------
 void launch_rho(const EvalArgs &a, bool f64, const RhoItem *items, int32_t nitems, hipStream_t s);
 // rho_e per record from the partials (fixed order), its records and per-k
-// energies; the block that completes a system's records also sums that
-// system's far energy (with the zero-mode term) and advances its sequence
-// cursor
+// energies; then per system the far energy (with the zero-mode term) and
+// the sequence cursor moved on
 void launch_rho_reduce(const EvalArgs &a, hipStream_t s);
 // far force; with a.kick the closing half kick v += dt/(2m) (F_N + F*) follows
 // (items of at most block_size particles, block_size in {64, 128, 256})
