@@ -208,10 +208,14 @@ __global__ __launch_bounds__(kBlock) void k_bin(EvalArgs a) {
         run_atomic_add(a.cell_count, cell, valid);
     }
     if constexpr (SCAN) {
+        // one device-scope fence per block (it writes the XCD's L2 back),
+        // after the block's barrier
         __shared__ int32_t last;
-        __threadfence();
         __syncthreads();
-        if (threadIdx.x == 0) last = atomicAdd(a.bin_done, 1u) == gridDim.x - 1 ? 1 : 0;
+        if (threadIdx.x == 0) {
+            __threadfence();
+            last = atomicAdd(a.bin_done, 1u) == gridDim.x - 1 ? 1 : 0;
+        }
         __syncthreads();
         if (!last) return;
         // every block's counts are in: scan them, then re-arm the counter
