@@ -39,6 +39,8 @@ enum ProbeOp : int {
     kRsqF32,
     kSinCosFma2,  // sin + cos + 2 FMA per step, on independent values (structure-factor mix)
     kMul3Add3,    // 3 mul_lo_u32 + add3 per step (fixed-point phase)
+    kRndneF64,    // round to nearest integer, FP64 (the turn index of the FP64 phases)
+    kCvtI32F64,   // FP64 to int32 conversion (the table index)
     kNumProbes
 };
 
@@ -49,7 +51,8 @@ __host__ __device__ constexpr int insts_of(int op) {
 
 const char *const kProbeNames[kNumProbes] = {
     "v_fma_f32", "v_fma_f64", "v_mul_lo_u32", "v_mad_u64_u32", "v_mul_u32_u24", "v_add3_u32",
-    "v_sin_f32", "v_cos_f32", "v_exp_f32", "v_rsq_f32", "sin+cos+2fma", "3mul_lo+add3"};
+    "v_sin_f32", "v_cos_f32", "v_exp_f32", "v_rsq_f32", "sin+cos+2fma", "3mul_lo+add3",
+    "v_rndne_f64", "v_cvt_i32_f64"};
 
 template <int OP>
 __global__ __launch_bounds__(kProbeBlock) void k_probe(uint32_t seed, float *__restrict__ sink) {
@@ -86,6 +89,8 @@ __global__ __launch_bounds__(kProbeBlock) void k_probe(uint32_t seed, float *__r
                 asm volatile("v_mad_u64_u32 %0, %1, %2, %3, %0" : "+v"(w[c]), "=s"(cy) : "v"(u[c]), "s"(ua));
             } else if constexpr (OP == kMulU24) asm volatile("v_mul_u32_u24 %0, %1, %0" : "+v"(u[c]) : "s"(ua));
             else if constexpr (OP == kAdd3U32) asm volatile("v_add3_u32 %0, %0, %1, %2" : "+v"(u[c]) : "v"(v[c]), "s"(ua));
+            else if constexpr (OP == kRndneF64) asm volatile("v_rndne_f64 %0, %0" : "+v"(d[c]));
+            else if constexpr (OP == kCvtI32F64) asm volatile("v_cvt_i32_f64 %0, %1" : "=v"(u[c]) : "v"(d[c]));
             else if constexpr (OP == kSinF32) f[c] = __builtin_amdgcn_sinf(f[c]);
             else if constexpr (OP == kCosF32) f[c] = __builtin_amdgcn_cosf(f[c]);
             else if constexpr (OP == kExpF32) f[c] = __builtin_amdgcn_exp2f(f[c]) - 1.0f;
@@ -122,7 +127,8 @@ typedef void (*ProbeFn)(uint32_t, float *, hipStream_t);
 const ProbeFn kProbeFns[kNumProbes] = {
     launch_probe<kFmaF32>,   launch_probe<kFmaF64>,  launch_probe<kMulLoU32>, launch_probe<kMadU64U32>,
     launch_probe<kMulU24>,   launch_probe<kAdd3U32>, launch_probe<kSinF32>,   launch_probe<kCosF32>,
-    launch_probe<kExpF32>,   launch_probe<kRsqF32>,  launch_probe<kSinCosFma2>, launch_probe<kMul3Add3>};
+    launch_probe<kExpF32>,   launch_probe<kRsqF32>,  launch_probe<kSinCosFma2>, launch_probe<kMul3Add3>,
+    launch_probe<kRndneF64>, launch_probe<kCvtI32F64>};
 
 }  // namespace
 }  // namespace rbsog
