@@ -440,6 +440,9 @@ __device__ __forceinline__ void fill_turns(double2 *turn) {
     __syncthreads();
 }
 
+// Records whose phases a wave stages at once in the FP32C far sum.
+constexpr int kFarStage = 256;
+
 // Far force on particle i (the factor -q_i included) from its system's P
 // amplitude-phase records, streamed as uniform loads: one sine per record,
 // F_i = -q_i sum_e a_e sin(2 pi (phi_e - m_e.s_i)).  Positions and charges
@@ -448,7 +451,7 @@ template <bool F64>
 __device__ __forceinline__ void far_sum(CSys *sp, CRec64 *kb64, CRec32 *kb32, int32_t P, int64_t n, int64_t i,
                                         const uint32_t *__restrict__ u, const float *__restrict__ qf,
                                         const double *__restrict__ x, const double *__restrict__ q,
-                                        const double2 *turn, double &Fx, double &Fy, double &Fz) {
+                                        const double2 *turn, uint64_t *phs, double &Fx, double &Fy, double &Fz) {
     Fx = 0.0; Fy = 0.0; Fz = 0.0;
     // records are consumed in groups so that their uniform loads overlap
     if constexpr (F64) {
@@ -464,7 +467,7 @@ __device__ __forceinline__ void far_sum(CSys *sp, CRec64 *kb64, CRec32 *kb32, in
             for (int h = 0; h < G; ++h) r[h] = ld(kb64 + e + h);
 #pragma unroll
             for (int h = 0; h < G; ++h) {
-                const double t = r[h].phi - (r[h].mx * sx + r[h].my * sy + r[h].mz * sz);
+                const double t = fma(-r[h].mx, sx, fma(-r[h].my, sy, fma(-r[h].mz, sz, r[h].phi)));
                 double v, cv;
                 rmath::sincos2pi_tab(t, turn, &v, &cv);
                 Fx = fma(r[h].ax, v, Fx);
@@ -474,7 +477,7 @@ __device__ __forceinline__ void far_sum(CSys *sp, CRec64 *kb64, CRec32 *kb32, in
         }
         for (; e < P; ++e) {
             const KRec64 r = ld(kb64 + e);
-            const double t = r.phi - (r.mx * sx + r.my * sy + r.mz * sz);
+            const double t = fma(-r.mx, sx, fma(-r.my, sy, fma(-r.mz, sz, r.phi)));
             double v, cv;
             rmath::sincos2pi_tab(t, turn, &v, &cv);
             Fx = fma(r.ax, v, Fx);
@@ -485,39 +488,64 @@ __device__ __forceinline__ void far_sum(CSys *sp, CRec64 *kb64, CRec32 *kb32, in
         Fx *= -qi; Fy *= -qi; Fz *= -qi;
     } else {
         const uint32_t ux = u[i], uy = u[n + i], uz = u[2 * n + i];
+        // per stage of up to 256 records: each lane copies four records'
+        // phases into the wave's LDS slots, from where they are read back
+        // broadcast as the addends of the phase chains (phi + (-m).u = phi -
+        // m.u mod 2^32: the subtraction costs no vector instruction; the
+        // negations of the uniform m are scalar).  The next stage's phases
+        // are loaded while the current one is summed.  FP32 partial sums
+        // over runs of 64 records, accumulated in FP64.
+        const KRec32 *kg = (const KRec32 *)kb32;
+        const int lane = threadIdx.x & 63;
         constexpr int G = 4;
-        int32_t e = 0;
-        // FP32 partial sums over 64 records, then accumulated in FP64
-        for (; e + 16 * G <= P; e += 16 * G) {
-            float fx = 0.f, fy = 0.f, fz = 0.f;
-#pragma unroll
-            for (int h4 = 0; h4 < 16; ++h4) {
-                KRec32 r[G];
-#pragma unroll
-                for (int h = 0; h < G; ++h) r[h] = ld(kb32 + e + h4 * G + h);
-#pragma unroll
-                for (int h = 0; h < G; ++h) {
-                    const uint32_t t = r[h].phi - rmath::dot3_mod32_s((uint32_t)r[h].mx, (uint32_t)r[h].my,
-                                                                      (uint32_t)r[h].mz, ux, uy, uz);
-                    const float v = __builtin_amdgcn_sinf(rmath::phase_rev(t));
-                    fx = fmaf(r[h].ax, v, fx);
-                    fy = fmaf(r[h].ay, v, fy);
-                    fz = fmaf(r[h].az, v, fz);
-                }
-            }
-            Fx += fx; Fy += fy; Fz += fz;
-        }
-        float fx = 0.f, fy = 0.f, fz = 0.f;
-        for (; e < P; ++e) {
-            const KRec32 r = ld(kb32 + e);
-            const uint32_t t = r.phi - rmath::dot3_mod32_s((uint32_t)r.mx, (uint32_t)r.my, (uint32_t)r.mz, ux, uy, uz);
+        auto rec = [&](const KRec32 &r, uint64_t c, float &fx, float &fy, float &fz) {
+            const uint32_t t = rmath::dot3_add_mod32_s(0u - (uint32_t)r.mx, 0u - (uint32_t)r.my, 0u - (uint32_t)r.mz,
+                                                       ux, uy, uz, c);
             const float v = __builtin_amdgcn_sinf(rmath::phase_rev(t));
             fx = fmaf(r.ax, v, fx);
             fy = fmaf(r.ay, v, fy);
             fz = fmaf(r.az, v, fz);
+        };
+        uint32_t nxt[kFarStage / 64];
+        auto fetch = [&](int32_t e0) {
+#pragma unroll
+            for (int h = 0; h < kFarStage / 64; ++h) {
+                const int32_t e = e0 + 64 * h + lane;
+                nxt[h] = kg[e < P ? e : 0].phi;
+            }
+        };
+        fetch(0);
+        for (int32_t e0 = 0; e0 < P; e0 += kFarStage) {
+            wave_sync();  // the previous stage's broadcast reads are done
+#pragma unroll
+            for (int h = 0; h < kFarStage / 64; ++h) phs[64 * h + lane] = (uint64_t)nxt[h];
+            wave_sync();
+            if (e0 + kFarStage < P) fetch(e0 + kFarStage);
+            const int32_t e1 = P - e0 < kFarStage ? P : e0 + kFarStage;
+            for (int32_t e = e0; e < e1; e += 64) {
+                const int cnt = e1 - e < 64 ? e1 - e : 64;
+                const uint64_t *ph = phs + (e - e0);
+                float fx = 0.f, fy = 0.f, fz = 0.f;
+                if (cnt == 64) {
+#pragma unroll
+                    for (int h4 = 0; h4 < 64; h4 += G) {
+                        KRec32 r[G];
+#pragma unroll
+                        for (int h = 0; h < G; ++h) r[h] = ld(kb32 + e + h4 + h);
+                        const ulonglong2 w0 = *(const ulonglong2 *)(ph + h4), w1 = *(const ulonglong2 *)(ph + h4 + 2);
+                        rec(r[0], w0.x, fx, fy, fz);
+                        rec(r[1], w0.y, fx, fy, fz);
+                        rec(r[2], w1.x, fx, fy, fz);
+                        rec(r[3], w1.y, fx, fy, fz);
+                    }
+                } else {
+                    for (int h = 0; h < cnt; ++h) rec(ld(kb32 + e + h), ph[h], fx, fy, fz);
+                }
+                Fx += fx; Fy += fy; Fz += fz;
+            }
         }
         const double qi = -(double)qf[i];
-        Fx = qi * (Fx + fx); Fy = qi * (Fy + fy); Fz = qi * (Fz + fz);
+        Fx *= qi; Fy *= qi; Fz *= qi;
     }
 }
 
@@ -614,6 +642,7 @@ __device__ __forceinline__ void far_finish(const EvalArgs &a, CSys *sp, int32_t 
 template <bool F64, bool FUSE>
 __global__ __launch_bounds__(256) void k_far(EvalArgs a, const FarItem *__restrict__ items, int32_t nitems) {
     __shared__ double2 turn[F64 ? rmath::kTurnTab : 1];
+    __shared__ uint64_t phs[F64 ? 1 : 4 * kFarStage];  // FP32C: record phases, per wave
     if constexpr (F64) fill_turns(turn);
     if (!FUSE && blockIdx.x == 0 && threadIdx.x == 0 && a.rebuild) *a.rebuild = 0;
     for (int32_t itx = blockIdx.x; itx < nitems; itx += gridDim.x) {
@@ -626,7 +655,7 @@ __global__ __launch_bounds__(256) void k_far(EvalArgs a, const FarItem *__restri
         const int64_t i = valid ? i0 : t0;
         double Fx, Fy, Fz;
         far_sum<F64>(sp, (CRec64 *)(a.kb64 + sp->k0), (CRec32 *)(a.kb32 + sp->k0), sp->P, a.N, i, a.u_tmp,
-                     a.cur.qf, a.cur.x, a.cur.q, turn, Fx, Fy, Fz);
+                     a.cur.qf, a.cur.x, a.cur.q, turn, phs + (F64 ? 0 : (threadIdx.x >> 6) * kFarStage), Fx, Fy, Fz);
         far_finish<FUSE>(a, sp, sys, i, valid, Fx, Fy, Fz, itx);
     }
 }
@@ -638,6 +667,7 @@ __global__ __launch_bounds__(256) void k_far(EvalArgs a, const FarItem *__restri
 template <bool F64>
 __global__ __launch_bounds__(256) void k_far_side(EvalArgs a, const FarItem *__restrict__ items, int32_t nitems) {
     __shared__ double2 turn[F64 ? rmath::kTurnTab : 1];
+    __shared__ uint64_t phs[F64 ? 1 : 4 * kFarStage];  // FP32C: record phases, per wave
     if constexpr (F64) fill_turns(turn);
     const int64_t n = a.N;
     for (int32_t itx = blockIdx.x; itx < nitems; itx += gridDim.x) {
@@ -649,7 +679,7 @@ __global__ __launch_bounds__(256) void k_far_side(EvalArgs a, const FarItem *__r
         const int64_t i = valid ? i0 : t0;
         double Fx, Fy, Fz;
         far_sum<F64>(sp, (CRec64 *)(a.kb64 + sp->k0), (CRec32 *)(a.kb32 + sp->k0), sp->P, n, i, a.rs_u, a.rs_qf,
-                     a.rs_x, a.rs_q, turn, Fx, Fy, Fz);
+                     a.rs_x, a.rs_q, turn, phs + (F64 ? 0 : (threadIdx.x >> 6) * kFarStage), Fx, Fy, Fz);
         if (valid) {
             a.Ff_side[i] = Fx;
             a.Ff_side[n + i] = Fy;

@@ -157,12 +157,6 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_bal
 // Values the wave holds in common (loaded or broadcast): keep them scalar.
 __device__ __forceinline__ int32_t rfl(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Broadcast the double held by lane `src` (uniform) to the whole wave.
 __device__ __forceinline__ double bcast64(double v, int src) {
     const long long b = __double_as_longlong(v);

@@ -267,6 +267,14 @@ struct EvalArgs {
     int32_t fuse;
 };
 
+// Orders a wave's LDS accesses before the barrier against those after it,
+// for data exchanged between the lanes of one wave (no block barrier).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Wrap of drifted positions into [0, L) (x_w = frac(x/L) L) and their
 // fixed-point coordinates u = min(2^32-1, floor(frac(x/L) 2^32)), stored for
 // slot t with the copies the structure factor and the near part read (a

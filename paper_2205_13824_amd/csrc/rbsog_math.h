@@ -140,6 +140,19 @@ __device__ __forceinline__ uint32_t dot3_mod32_s(uint32_t ax, uint32_t ay, uint3
     asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(c2) : "s"(ax), "v"(bx), "v"(q));
     return (uint32_t)r;
 }
+// c + a.b mod 2^32 for c the low half of the 64-bit addend `c` (its high half
+// is not read into the low half of any product): the same chain with c in
+// place of the constant 0, so a phase offset costs no instruction.  The
+// first factor from scalar registers, the addend from vector registers (one
+// scalar operand per instruction).
+__device__ __forceinline__ uint32_t dot3_add_mod32_s(uint32_t ax, uint32_t ay, uint32_t az, uint32_t bx, uint32_t by,
+                                                     uint32_t bz, uint64_t c) {
+    uint64_t p, q, r, c0, c1, c2;
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(p), "=s"(c0) : "s"(az), "v"(bz), "v"(c));
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(q), "=s"(c1) : "s"(ay), "v"(by), "v"(p));
+    asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(c2) : "s"(ax), "v"(bx), "v"(q));
+    return (uint32_t)r;
+}
 
 // e^y in FP64 for finite y <= 0 (the narrow Gaussians of the near part),
 // by Cody and Waite's reduction: n = rint(y / ln 2), r = y - n ln 2 with
