@@ -2343,9 +2343,9 @@ rbsog_status rbsog_get_kbatch(rbsog_ctx *c, int32_t sys, int32_t *m_out) {
     HIPCHK(c, hipMemcpyAsync(r.data(), c->kb32 + h.k0, r.size() * sizeof(KRec32), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (int32_t e = 0; e < h.P; ++e) {
-        m_out[3 * e] = r[e].mx;
-        m_out[3 * e + 1] = r[e].my;
-        m_out[3 * e + 2] = r[e].mz;
+        m_out[3 * e] = -r[e].nmx;
+        m_out[3 * e + 1] = -r[e].nmy;
+        m_out[3 * e + 2] = -r[e].nmz;
     }
     return RBSOG_OK;
 }
@@ -2568,7 +2568,7 @@ rbsog_status rbsog_profile_read(rbsog_ctx *c, int32_t idx, const char **name, do
 // serves both the size query (no buffer) and the copy.
 namespace {
 
-constexpr char kStateMagic[8] = {'R', 'B', 'S', 'O', 'G', 'S', 'T', '1'};
+constexpr char kStateMagic[8] = {'R', 'B', 'S', 'O', 'G', 'S', 'T', '2'};
 
 struct StateWriter {
     uint8_t *buf;  // null: count only

@@ -42,15 +42,18 @@ __device__ __forceinline__ KRec64 ld(CRec64 *p) {
     r.pad = p->pad;
     return r;
 }
-__device__ __forceinline__ KRec32 ld(CRec32 *p) {
-    // four 8-byte words, so that the record is one 32-byte load
+// the far sum's part of a record: -m and a (one 24-byte load)
+struct KFar32 {
+    uint32_t nmx, nmy, nmz;
+    float ax, ay, az;
+};
+__device__ __forceinline__ KFar32 ld(CRec32 *p) {
     typedef const unsigned long long __attribute__((address_space(4))) CU64;
-    const unsigned long long w0 = ((CU64 *)p)[0], w1 = ((CU64 *)p)[1], w2 = ((CU64 *)p)[2], w3 = ((CU64 *)p)[3];
-    KRec32 r;
-    r.mx = (int32_t)(uint32_t)w0; r.my = (int32_t)(uint32_t)(w0 >> 32);
-    r.mz = (int32_t)(uint32_t)w1; r.phi = (uint32_t)(w1 >> 32);
-    r.ax = __uint_as_float((uint32_t)w2); r.ay = __uint_as_float((uint32_t)(w2 >> 32));
-    r.az = __uint_as_float((uint32_t)w3); r.pad = __uint_as_float((uint32_t)(w3 >> 32));
+    const unsigned long long w0 = ((CU64 *)p)[0], w1 = ((CU64 *)p)[1], w2 = ((CU64 *)p)[2];
+    KFar32 r;
+    r.nmx = (uint32_t)w0; r.nmy = (uint32_t)(w0 >> 32);
+    r.nmz = (uint32_t)w1; r.ax = __uint_as_float((uint32_t)(w1 >> 32));
+    r.ay = __uint_as_float((uint32_t)w2); r.az = __uint_as_float((uint32_t)(w2 >> 32));
     return r;
 }
 
@@ -295,9 +298,9 @@ __device__ __forceinline__ void write_record(const EvalArgs &a, const SysDev &sd
     // to 2^-23 turns (half a unit of it low on average), which this
     // offset takes back
     KRec32 f;
-    f.mx = m[0];
-    f.my = m[1];
-    f.mz = m[2];
+    f.nmx = -m[0];
+    f.nmy = -m[1];
+    f.nmz = -m[2];
     f.phi = (uint32_t)(int64_t)rint(phi * 4294967296.0) + 512u;
     f.ax = (float)h.ax;
     f.ay = (float)h.ay;
@@ -442,6 +445,8 @@ __device__ __forceinline__ void fill_turns(double2 *turn) {
 
 // Records whose phases a wave stages at once in the FP32C far sum.
 constexpr int kFarStage = 256;
+// s_waitcnt lgkmcnt(0) with the other counters left alone (gfx9 encoding)
+constexpr int kWaitLgkm0 = 0xC07F;
 
 // Far force on particle i (the factor -q_i included) from its system's P
 // amplitude-phase records, streamed as uniform loads: one sine per record,
@@ -491,16 +496,15 @@ __device__ __forceinline__ void far_sum(CSys *sp, CRec64 *kb64, CRec32 *kb32, in
         // per stage of up to 256 records: each lane copies four records'
         // phases into the wave's LDS slots, from where they are read back
         // broadcast as the addends of the phase chains (phi + (-m).u = phi -
-        // m.u mod 2^32: the subtraction costs no vector instruction; the
-        // negations of the uniform m are scalar).  The next stage's phases
-        // are loaded while the current one is summed.  FP32 partial sums
-        // over runs of 64 records, accumulated in FP64.
+        // m.u mod 2^32, the records holding -m: the subtraction costs no
+        // vector instruction).  The next stage's phases are loaded while the
+        // current one is summed.  FP32 partial sums over runs of 64 records,
+        // accumulated in FP64.
         const KRec32 *kg = (const KRec32 *)kb32;
         const int lane = threadIdx.x & 63;
         constexpr int G = 4;
-        auto rec = [&](const KRec32 &r, uint64_t c, float &fx, float &fy, float &fz) {
-            const uint32_t t = rmath::dot3_add_mod32_s(0u - (uint32_t)r.mx, 0u - (uint32_t)r.my, 0u - (uint32_t)r.mz,
-                                                       ux, uy, uz, c);
+        auto rec = [&](const KFar32 &r, uint64_t c, float &fx, float &fy, float &fz) {
+            const uint32_t t = rmath::dot3_add_mod32_s(r.nmx, r.nmy, r.nmz, ux, uy, uz, c);
             const float v = __builtin_amdgcn_sinf(rmath::phase_rev(t));
             fx = fmaf(r.ax, v, fx);
             fy = fmaf(r.ay, v, fy);
@@ -527,16 +531,32 @@ __device__ __forceinline__ void far_sum(CSys *sp, CRec64 *kb64, CRec32 *kb32, in
                 const uint64_t *ph = phs + (e - e0);
                 float fx = 0.f, fy = 0.f, fz = 0.f;
                 if (cnt == 64) {
+                    // scalar loads and LDS reads share one wait counter, and
+                    // a wait on it covers every scalar load in flight: the
+                    // group's phases are read and waited for before the next
+                    // group's records are requested, which then arrive while
+                    // the group is summed
+                    KFar32 r[G];
+#pragma unroll
+                    for (int h = 0; h < G; ++h) r[h] = ld(kb32 + e + h);
 #pragma unroll
                     for (int h4 = 0; h4 < 64; h4 += G) {
-                        KRec32 r[G];
-#pragma unroll
-                        for (int h = 0; h < G; ++h) r[h] = ld(kb32 + e + h4 + h);
                         const ulonglong2 w0 = *(const ulonglong2 *)(ph + h4), w1 = *(const ulonglong2 *)(ph + h4 + 2);
+                        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+                        __builtin_amdgcn_sched_barrier(0);
+                        KFar32 rn[G];
+                        if (h4 + G < 64) {
+#pragma unroll
+                            for (int h = 0; h < G; ++h) rn[h] = ld(kb32 + e + h4 + G + h);
+                        }
                         rec(r[0], w0.x, fx, fy, fz);
                         rec(r[1], w0.y, fx, fy, fz);
                         rec(r[2], w1.x, fx, fy, fz);
                         rec(r[3], w1.y, fx, fy, fz);
+                        if (h4 + G < 64) {
+#pragma unroll
+                            for (int h = 0; h < G; ++h) r[h] = rn[h];
+                        }
                     }
                 } else {
                     for (int h = 0; h < cnt; ++h) rec(ld(kb32 + e + h), ph[h], fx, fy, fz);

@@ -34,12 +34,14 @@ struct KRec64 {
     double ax, ay, az;
     double pad;
 };
-// FP32 form: m as int32, phi as a 32-bit fixed-point fraction of a turn
-// (mod 2^32), a rounded to float.
+// FP32 form: -m as int32 (the far force forms phi + (-m).u), a rounded to
+// float, then phi as a 32-bit fixed-point fraction of a turn (mod 2^32):
+// the far kernel loads the first 24 bytes as scalars and the phases as
+// vectors.
 struct KRec32 {
-    int32_t mx, my, mz;
-    uint32_t phi;
+    int32_t nmx, nmy, nmz;
     float ax, ay, az;
+    uint32_t phi;
     float pad;
 };
 
