@@ -78,10 +78,69 @@ struct Stage64 {
     double sx, sy, sz, q;
 };
 
+// FP32C staging of particles [jb, jb + cnt) of the block's chunk for the
+// structure factor (blocks of 1024 threads, 16 waves): each wave splits its
+// 64 particles by the sign of the charge and pairs consecutive ones of a
+// sign (lane order) whose charges are equal; a pair (u1, u2) is written as
+// two records, h = u1 + ((u2 - u1) >> 1) with 2q and d = u1 - h (so u1 = h +
+// d and u2 = h - d up to one unit of 2^-32 of the box: the pair's phases
+// are m.h +- m.d mod 2^32), the particles left single after all pairs as
+// (u, q).  Returns the block's number of pairs; the records fill
+// st32[0, cnt).  Ends with a barrier.
+__device__ __forceinline__ int stage_pairs(const uint32_t *__restrict__ u, const float *__restrict__ qf, int64_t n,
+                                           int64_t jb, int cnt, uint4 *st32, int2 *wcnt) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool have = (int)threadIdx.x < cnt;
+    uint32_t ux = 0, uy = 0, uz = 0, qb = 0;
+    if (have) {
+        const int64_t j = jb + threadIdx.x;
+        ux = u[j];
+        uy = u[n + j];
+        uz = u[2 * n + j];
+        qb = __float_as_uint(qf[j]);
+    }
+    const bool pos = __uint_as_float(qb) > 0.f;
+    const uint64_t all = __builtin_amdgcn_ballot_w64(have), plus = __builtin_amdgcn_ballot_w64(have && pos);
+    const uint64_t mine = pos ? plus : (all & ~plus);
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const uint64_t below = mine & lt, above = mine & ~(lt | (1ull << lane));
+    const int rank = __builtin_popcountll(below), ncls = __builtin_popcountll(mine);
+    const int nl = above ? __builtin_ctzll(above) : lane;        // next lane of the class
+    const int pl = below ? 63 - __builtin_clzll(below) : lane;   // previous lane of the class
+    const uint32_t nx = __shfl(ux, nl, 64), ny = __shfl(uy, nl, 64), nz = __shfl(uz, nl, 64);
+    const uint32_t nq = __shfl(qb, nl, 64), pq = __shfl(qb, pl, 64);
+    const bool lead = have && (rank & 1) == 0 && rank + 1 < ncls && nq == qb;
+    const bool follow = have && (rank & 1) == 1 && pq == qb;
+    const bool single = have && !lead && !follow;
+    const uint64_t lm = __builtin_amdgcn_ballot_w64(lead), sm = __builtin_amdgcn_ballot_w64(single);
+    if (lane == 0) wcnt[wave] = make_int2(__builtin_popcountll(lm), __builtin_popcountll(sm));
+    __syncthreads();
+    int pofs = 0, sofs = 0, np = 0;
+    for (int w = 0; w < 16; ++w) {
+        const int2 c = wcnt[w];
+        np += c.x;
+        if (w < wave) {
+            pofs += c.x;
+            sofs += c.y;
+        }
+    }
+    if (lead) {
+        const int o = 2 * (pofs + __builtin_popcountll(lm & lt));
+        const uint32_t hx = ux + (uint32_t)((int32_t)(nx - ux) >> 1), hy = uy + (uint32_t)((int32_t)(ny - uy) >> 1),
+                       hz = uz + (uint32_t)((int32_t)(nz - uz) >> 1);
+        st32[o] = make_uint4(hx, hy, hz, __float_as_uint(2.f * __uint_as_float(qb)));
+        st32[o + 1] = make_uint4(ux - hx, uy - hy, uz - hz, 0u);
+    }
+    if (single) st32[2 * np + sofs + __builtin_popcountll(sm & lt)] = make_uint4(ux, uy, uz, qb);
+    __syncthreads();
+    return np;
+}
+
 template <bool F64>
 __global__ __launch_bounds__(1024, F64 ? 1 : 8) void k_rho(EvalArgs a, const RhoItem *__restrict__ items, int32_t nitems) {
     __shared__ double2 red[1024];
     __shared__ uint4 st32[F64 ? 1 : kStage];
+    __shared__ int2 wcnt[F64 ? 1 : 16];
     __shared__ Stage64 st64[F64 ? kStage : 1];
     // FP64: cos and sin of the kTurnTab turns (sincos2pi_tab); the staging
     // loop's first barrier orders the fill before any use
@@ -158,51 +217,68 @@ __global__ __launch_bounds__(1024, F64 ? 1 : 8) void k_rho(EvalArgs a, const Rho
             const uint32_t mx = (uint32_t)mk[0], my = (uint32_t)mk[1], mz = (uint32_t)mk[2];
             for (int64_t jb = j0; jb < j1; jb += kStage) {
                 const int cnt = (int)(j1 - jb < kStage ? j1 - jb : kStage);
-                if ((int)threadIdx.x < cnt) {
-                    const int64_t j = jb + threadIdx.x;
-                    st32[threadIdx.x] = make_uint4(u[j], u[n + j], u[2 * n + j], __float_as_uint(qf[j]));
-                }
-                __syncthreads();
+                const int np = stage_pairs(u, qf, n, jb, cnt, st32, wcnt);
+                const int ns = cnt - 2 * np;
                 if (st < streams) {
-                    // FP32 sums over runs of 32 of the stream's particles, then
-                    // FP64; eight staged particles are read at once, then used
-                    // (one stream: contiguous reads at fixed offsets)
-                    auto runs = [&](auto one) {
+                    // pairs of equal charge q with phases t_m +- t_d: the
+                    // pair adds 2 q cos(t_d) e^{i t_m} (cos a + cos b = 2
+                    // cos((a+b)/2) cos((a-b)/2), sin a + sin b = 2
+                    // sin((a+b)/2) cos((a-b)/2)): three transcendentals
+                    // and three multiply-adds where the two particles take
+                    // four of each.  FP32 sums over runs of 16 pairs (32
+                    // singles), then FP64.
+                    auto pairs = [&](auto one) {
                         constexpr bool ONE = decltype(one)::value;
                         const int sd = ONE ? 1 : streams;
                         int h = st;
-                        for (; h + 32 * sd <= cnt; h += 32 * sd) {
+                        for (; h + 16 * sd <= np; h += 16 * sd) {
                             float rf = 0.f, fi = 0.f;
-                            for (int g0 = 0; g0 < 32; g0 += 8) {
-                                uint4 p[8];
+                            for (int g0 = 0; g0 < 16; g0 += 4) {
+                                uint4 pa[4], pb[4];
 #pragma unroll
-                                for (int g = 0; g < 8; ++g) p[g] = st32[h + (g0 + g) * sd];
+                                for (int g = 0; g < 4; ++g) {
+                                    pa[g] = st32[2 * (h + (g0 + g) * sd)];
+                                    pb[g] = st32[2 * (h + (g0 + g) * sd) + 1];
+                                }
 #pragma unroll
-                                for (int g = 0; g < 8; ++g) {
-                                    const uint32_t t = rmath::dot3_mod32_v(mx, my, mz, p[g].x, p[g].y, p[g].z);
-                                    const float f = rmath::phase_rev(t);
-                                    const float pq = __uint_as_float(p[g].w);
-                                    rf = fmaf(pq, __builtin_amdgcn_cosf(f), rf);
-                                    fi = fmaf(pq, __builtin_amdgcn_sinf(f), fi);
+                                for (int g = 0; g < 4; ++g) {
+                                    const float fm = rmath::phase_rev(rmath::dot3_mod32_v(mx, my, mz, pa[g].x, pa[g].y, pa[g].z));
+                                    const float fd = rmath::phase_rev(rmath::dot3_mod32_v(mx, my, mz, pb[g].x, pb[g].y, pb[g].z));
+                                    const float w = __uint_as_float(pa[g].w) * __builtin_amdgcn_cosf(fd);
+                                    rf = fmaf(w, __builtin_amdgcn_cosf(fm), rf);
+                                    fi = fmaf(w, __builtin_amdgcn_sinf(fm), fi);
                                 }
                             }
                             re += rf;
                             im += fi;
                         }
                         float rf = 0.f, fi = 0.f;
-                        for (; h < cnt; h += sd) {
-                            const uint4 p = st32[h];
-                            const uint32_t t = rmath::dot3_mod32_v(mx, my, mz, p.x, p.y, p.z);
-                            const float f = rmath::phase_rev(t);
-                            const float pq = __uint_as_float(p.w);
-                            rf = fmaf(pq, __builtin_amdgcn_cosf(f), rf);
-                            fi = fmaf(pq, __builtin_amdgcn_sinf(f), fi);
+                        for (; h < np; h += sd) {
+                            const uint4 pa = st32[2 * h], pb = st32[2 * h + 1];
+                            const float fm = rmath::phase_rev(rmath::dot3_mod32_v(mx, my, mz, pa.x, pa.y, pa.z));
+                            const float fd = rmath::phase_rev(rmath::dot3_mod32_v(mx, my, mz, pb.x, pb.y, pb.z));
+                            const float w = __uint_as_float(pa.w) * __builtin_amdgcn_cosf(fd);
+                            rf = fmaf(w, __builtin_amdgcn_cosf(fm), rf);
+                            fi = fmaf(w, __builtin_amdgcn_sinf(fm), fi);
                         }
                         re += rf;
                         im += fi;
                     };
-                    if (streams == 1) runs(std::true_type{});
-                    else runs(std::false_type{});
+                    if (streams == 1) pairs(std::true_type{});
+                    else pairs(std::false_type{});
+                    // the particles left single (at most two per wave of
+                    // the stage, more where charges differ)
+                    const uint4 *sg = st32 + 2 * np;
+                    float rf = 0.f, fi = 0.f;
+                    for (int h = st; h < ns; h += streams) {
+                        const uint4 p = sg[h];
+                        const float f = rmath::phase_rev(rmath::dot3_mod32_v(mx, my, mz, p.x, p.y, p.z));
+                        const float pq = __uint_as_float(p.w);
+                        rf = fmaf(pq, __builtin_amdgcn_cosf(f), rf);
+                        fi = fmaf(pq, __builtin_amdgcn_sinf(f), fi);
+                    }
+                    re += rf;
+                    im += fi;
                 }
                 __syncthreads();
             }
