@@ -281,6 +281,28 @@ def test_c2_full_size_sampled(orc, c2, prec, tol):
     assert np.abs(Ff.sum(0)).max() < (1e-9 if prec == R.RBSOG_FP64 else 1e-3) * np.abs(Ff).max() * math.sqrt(n)
 
 
+@pytest.mark.parametrize("prec,tol", [(R.RBSOG_FP64, F64_TOL), (R.RBSOG_FP32C, F32C_TOL)])
+def test_structure_factor_mixed_charges(orc, prec, tol):
+    """Charges of both signs and several magnitudes, zeros included, in a
+    random order over 30,000 ions: the FP32C structure factor pairs equal
+    charges within each wave of a stage and sums the rest singly (odd
+    counts per sign, unequal neighbours, a ragged last chunk and stage);
+    rho(k) of the batch against the oracle's direct sum."""
+    c = W.c2_electrolyte(30_000)
+    n = len(c["q"])
+    pattern = np.array([1.0, -1.0, 0.4238, 0.4238, -0.8476, 0.3, -0.3, 0.0])
+    q = np.random.default_rng(77).permutation(np.tile(pattern, n // 8))
+    sysm = make(c["pos"], q, c["box"], c["rc"], c["P"], seed=303, prec=prec)
+    m = sysm.sample_k(1)
+    sysm.forces()
+    re, im = R.rbsog_get_rho(sysm.ctx, c["P"])
+    re_o, im_o = orc.structure_factor(c["pos"], q, c["box"], m[: c["P"]])
+    e = math.sqrt(float(np.sum((re - re_o) ** 2 + (im - im_o) ** 2) / np.sum(re_o ** 2 + im_o ** 2)))
+    say(f"[mixed charges prec={prec}] rho relrms {e:.3e}")
+    assert e < tol
+    sysm.close()
+
+
 @pytest.mark.parametrize("prec,nh,skin", [(R.RBSOG_FP64, False, None), (R.RBSOG_FP32C, False, None),
                                           (R.RBSOG_FP32C, True, None), (R.RBSOG_FP64, False, 0.0),
                                           (R.RBSOG_FP32C, True, 0.0)])
